@@ -1,0 +1,241 @@
+"""ctypes wrapper around the plain FP64 C oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and
+``bench.py``'s CPU-baseline leg may import this package.  It shares no code
+with the GPU library; both receive the same seeded input arrays from
+``paper_2504_21784_amd.workloads``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, -O2, single threaded)."""
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"])
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+class Geom(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("xe", _dp), ("ye", _dp),
+                ("nang", C.c_int), ("om", _dp), ("w", _dp), ("G", C.c_int), ("nu", _dp),
+                ("a", C.c_double), ("c", C.c_double)]
+
+
+class Mat(C.Structure):
+    _fields_ = [("region", _ip), ("model", C.c_int), ("sigma0", _dp), ("clip_lo", C.c_double),
+                ("clip_hi", C.c_double), ("cv", _dp)]
+
+
+class BC(C.Structure):
+    _fields_ = [("kind", C.c_int * 4), ("T_bdr", C.c_double * 4), ("inflow_g", _dp * 4)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("eps_outer", C.c_double), ("eps_inner", C.c_double), ("cg_rtol", C.c_double),
+                ("elim_rtol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int),
+                ("max_cg", C.c_int), ("max_elim", C.c_int), ("scheme", C.c_int), ("lo_time_edge", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("outer", C.c_int), ("inner_total", C.c_int), ("cg_total", C.c_int),
+                ("elim_max", C.c_int), ("hit_max", C.c_int), ("energy_residual", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _declare(L):
+    gp, mp, bp, op, sp = C.POINTER(Geom), C.POINTER(Mat), C.POINTER(BC), C.POINTER(Opts), C.POINTER(Stats)
+    L.orc_spectra.argtypes = [C.c_int, _dp, C.c_double, _dp, _dp]
+    L.orc_opacity.argtypes = [gp, mp, _dp, _dp]
+    L.orc_sweep.argtypes = [gp, _dp, _dp, _dp, C.c_double, _dp, _dp]
+    L.orc_sweep.restype = C.c_int
+    L.orc_moments.argtypes = [gp, _dp, _dp, _dp]
+    L.orc_n_moments.argtypes = [C.c_int]
+    L.orc_inflow_from_bc.argtypes = [gp, bp, _dp]
+    L.orc_closures.argtypes = [gp, bp, C.c_int, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_energy_solve.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, _dp]
+    L.orc_energy_solve.restype = C.c_int
+    L.orc_lo_solve.argtypes = [gp, mp, op, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, sp]
+    L.orc_lo_solve.restype = C.c_int
+    L.orc_schur_dense.argtypes = [gp, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_lo_dense.argtypes = [gp, _dp, _dp, _dp]
+    L.orc_step.argtypes = [gp, mp, bp, op, C.c_double, _dp, _dp, _dp, _dp, sp]
+    L.orc_step.restype = C.c_int
+    L.orc_equilibrium_psi.argtypes = [gp, _dp, _dp]
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_opts(**kw) -> dict:
+    """Tolerances and caps of the paper's numerical results section:
+    outer/inner 1e-3, CG 1e-10, elimination 1e-10; caps 100/30/50/40."""
+    o = dict(eps_outer=1e-3, eps_inner=1e-3, cg_rtol=1e-10, elim_rtol=1e-10, max_outer=100,
+             max_inner=30, max_cg=50, max_elim=40, scheme=0, lo_time_edge=0)
+    o.update(kw)
+    return o
+
+
+class Oracle:
+    """Holds ctypes descriptors (and keeps the numpy arrays alive) for one Problem."""
+
+    def __init__(self, p):
+        self.p = p
+        self.L = lib()
+        self._keep = []
+        k = self._keep.append
+        xe = _f64(p.x_edges); k(xe)
+        ye = _f64(p.y_edges) if p.y_edges is not None else None
+        if ye is not None:
+            k(ye)
+        om = _f64(p.omega); k(om)
+        w = _f64(p.w); k(w)
+        nu = _f64(p.nu_edges); k(nu)
+        self.geom = Geom(p.dim, p.nx, p.ny if p.dim == 2 else 1, _p(xe), _p(ye), p.n_angles, _p(om), _p(w),
+                         p.G, _p(nu), p.a, p.c)
+        reg = np.ascontiguousarray(p.region_of_cell, dtype=np.int32); k(reg)
+        s0 = _f64(p.sigma0); k(s0)
+        cv = _f64(p.cv); k(cv)
+        self.mat = Mat(reg.ctypes.data_as(_ip), p.model, _p(s0), p.clip_lo, p.clip_hi, _p(cv))
+        bc = BC()
+        for s in range(2 * p.dim):
+            bc.kind[s] = p.bc_kind[s]
+            bc.T_bdr[s] = p.T_bdr[s]
+            if p.inflow_g[s] is not None:
+                arr = _f64(p.inflow_g[s]); k(arr)
+                bc.inflow_g[s] = _p(arr)
+        self.bc = bc
+        self.nb = 2 if p.dim == 1 else 4 * (p.nx + p.ny)
+
+    # -- pieces -------------------------------------------------------------
+    def spectra(self, T):
+        b = np.zeros(self.p.G)
+        r = np.zeros(self.p.G)
+        self.L.orc_spectra(self.p.G, self.geom.nu, float(T), _p(b), _p(r))
+        return b, r
+
+    def opacity(self, T_nodes):
+        sig = np.zeros((self.p.n_cells, self.p.G))
+        T = _f64(T_nodes)
+        self.L.orc_opacity(C.byref(self.geom), C.byref(self.mat), _p(T), _p(sig))
+        return sig
+
+    def inflow(self):
+        a = np.zeros((self.p.n_angles, self.p.G, self.nb))
+        self.L.orc_inflow_from_bc(C.byref(self.geom), C.byref(self.bc), _p(a))
+        return a
+
+    def sweep(self, sig_t, q_iso, psi_prev, inv_c_dt, inflow):
+        p = self.p
+        out = np.zeros((p.n_angles, p.G, p.n_nodes))
+        st, q = _f64(sig_t), _f64(q_iso)
+        pp = _f64(psi_prev) if psi_prev is not None else None
+        inf = _f64(inflow) if inflow is not None else None
+        r = self.L.orc_sweep(C.byref(self.geom), _p(st), _p(q), _p(pp), float(inv_c_dt), _p(inf), _p(out))
+        assert r == 0
+        return out
+
+    def moments(self, sig, psi):
+        nm = self.L.orc_n_moments(self.p.dim)
+        out = np.zeros((nm, self.p.n_nodes))
+        self.L.orc_moments(C.byref(self.geom), _p(_f64(sig)), _p(_f64(psi)), _p(out))
+        return out
+
+    def closures(self, scheme, dt, sig, T_l, Estar, Fstar, psi, inflow):
+        p, nn = self.p, self.p.n_nodes
+        sigE, sigF, sigP, qE = (np.zeros(nn) for _ in range(4))
+        qF = np.zeros((nn, p.dim))
+        args = [_f64(sig), _f64(T_l), _f64(Estar), _f64(Fstar), _f64(psi), _f64(inflow)]
+        self.L.orc_closures(C.byref(self.geom), C.byref(self.bc), scheme, float(dt), *[_p(a) for a in args],
+                            _p(sigE), _p(sigF), _p(sigP), _p(qE), _p(qF))
+        return dict(sigE=sigE, sigF=sigF, sigP=sigP, qE=qE, qF=qF)
+
+    def energy_solve(self, cv_dt, k4, rhs, T0, rtol=1e-10, maxit=40):
+        T = C.c_double(0.0)
+        it = self.L.orc_energy_solve(cv_dt, k4, rhs, T0, rtol, maxit, C.byref(T))
+        return it, T.value
+
+    def lo_solve(self, opts, dt, Tstar, cl, E, T):
+        p = self.p
+        E = _f64(E).copy()
+        T = _f64(T).copy()
+        F = np.zeros((p.n_nodes, p.dim))
+        st = Stats()
+        o = Opts(**opts)
+        r = self.L.orc_lo_solve(C.byref(self.geom), C.byref(self.mat), C.byref(o), float(dt), _p(_f64(Tstar)),
+                                _p(_f64(cl["sigE"])), _p(_f64(cl["sigF"])), _p(_f64(cl["sigP"])),
+                                _p(_f64(cl["qE"])), _p(_f64(cl["qF"])), _p(E), _p(F), _p(T), C.byref(st))
+        return r, E, F, T, st.as_dict()
+
+    def schur_dense(self, dt, sigE, sigF, sigP, cvn, T0):
+        nn = self.p.n_nodes
+        S = np.zeros((nn, nn))
+        self.L.orc_schur_dense(C.byref(self.geom), float(dt), *[_p(_f64(a)) for a in (sigE, sigF, sigP, cvn, T0)], _p(S))
+        return S
+
+    def lo_dense(self):
+        nn, dim = self.p.n_nodes, self.p.dim
+        D = np.zeros((nn, nn * dim))
+        P = np.zeros((nn, nn))
+        wv = np.zeros(nn)
+        self.L.orc_lo_dense(C.byref(self.geom), _p(D), _p(P), _p(wv))
+        return D, P, wv
+
+    def equilibrium_psi(self, T_nodes):
+        p = self.p
+        out = np.zeros((p.n_angles, p.G, p.n_nodes))
+        self.L.orc_equilibrium_psi(C.byref(self.geom), _p(_f64(T_nodes)), _p(out))
+        return out
+
+    # -- state --------------------------------------------------------------
+    def initial_state(self):
+        p = self.p
+        T = p.initial_T_nodes()
+        psi = self.equilibrium_psi(T)
+        E = np.full(p.n_nodes, p.a * p.T0 ** 4)
+        F = np.zeros((p.n_nodes, p.dim))
+        return dict(psi=psi, T=T, E=E, F=F)
+
+    def step(self, state, opts, dt=None):
+        """One backward-Euler step; returns (status, new_state, stats)."""
+        p = self.p
+        s = {k: _f64(v).copy() for k, v in state.items()}
+        st = Stats()
+        o = Opts(**opts)
+        r = self.L.orc_step(C.byref(self.geom), C.byref(self.mat), C.byref(self.bc), C.byref(o),
+                            float(dt if dt is not None else p.dt), _p(s["psi"]), _p(s["T"]), _p(s["E"]),
+                            _p(s["F"]), C.byref(st))
+        return r, s, st.as_dict()

@@ -1,0 +1,75 @@
+"""Seeded input generators: quadrature sets against the published LQ_n table
+and their moment invariants; workload shapes."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2504_21784_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "level_symmetric_lq.txt")
+
+
+def _table():
+    rows = {}
+    for line in open(GOLD):
+        if line.startswith("#") or not line.strip():
+            continue
+        left, right = line.split("|")
+        toks = left.split()
+        N = int(toks[0])
+        levels = [float(t) for t in toks[1:]]
+        cls = {}
+        for item in right.split():
+            k, v = item.split(":")
+            cls[tuple(int(x) for x in k.split(","))] = float(v)
+        rows[N] = (levels, cls)
+    return rows
+
+
+@pytest.mark.parametrize("N", [4, 8, 12])
+def test_level_symmetric_matches_table(N):
+    levels, cls = _table()[N]
+    om, w = W.level_symmetric_2d(N)
+    got = sorted(set(np.round(np.abs(om[:, 0]), 7)))
+    assert np.allclose(got, levels, atol=1.5e-7)
+    wo = w[:len(w) // 4] / math.pi
+    lev = np.array(levels)
+    for k in range(len(wo)):
+        idx = tuple(sorted(int(np.argmin(np.abs(lev - abs(om[k, a])))) + 1 for a in range(3)))
+        assert abs(wo[k] - cls[idx]) < 1.5e-7
+
+
+@pytest.mark.parametrize("N", [4, 8, 12])
+def test_quadrature_invariants(N):
+    om, w = W.level_symmetric_2d(N)
+    assert len(w) == N * (N + 2) // 2
+    assert abs(w.sum() - 4 * math.pi) < 1e-12 * 4 * math.pi
+    assert np.abs((w[:, None] * om).sum(0)[:2]).max() < 1e-14
+    assert abs((w * om[:, 0] ** 2).sum() - 4 * math.pi / 3) < 1e-13
+    assert abs((w * om[:, 1] ** 2).sum() - 4 * math.pi / 3) < 1e-13
+    assert abs((w * om[:, 0] * om[:, 1]).sum()) < 1e-14
+    assert np.abs(np.linalg.norm(om, axis=1) - 1).max() < 1e-12
+    assert (np.abs(om[:, :2]) > 0).all()
+
+
+def test_gauss_legendre_slab():
+    om, w = W.gauss_legendre_slab(8)
+    assert abs(w.sum() - 4 * math.pi) < 1e-12
+    assert abs((w * om[:, 0]).sum()) < 1e-14
+    assert abs((w * om[:, 0] ** 2).sum() - 4 * math.pi / 3) < 1e-13
+
+
+def test_workload_shapes():
+    p = W.multigroup_2d()
+    assert p.units_per_sweep == 256 * 256 * 40 * 16
+    assert p.n_regions == 256 and p.sigma0.min() >= 1 and p.sigma0.max() <= 100
+    q = W.gray_2d()
+    assert q.units_per_sweep == 128 * 128 * 40
+    assert q.sigma0.min() >= 0.1 and q.sigma0.max() <= 1000
+    b = W.batch_2d()
+    assert len(b) == 32
+    assert all(64 <= x.nx <= 384 and x.G in (4, 8, 16, 32) and x.n_angles in (12, 40, 84) for x in b)
+    a = W.adjoint_2d()
+    assert a.n_regions == 64 and 0.5 <= a.cv.min() and a.cv.max() <= 2.0
