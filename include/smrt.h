@@ -1,0 +1,230 @@
+/*
+ * smrt.h -- C ABI of the MI355X (gfx950) Second Moment thermal radiative
+ * transfer library: the lumped DG S_N transport sweep with fused angular
+ * moments, the SM closures, the FP64 low-order solve and one backward-Euler
+ * step, following Olivier, Warsa & Park, "Efficient, Nonlinear Second
+ * Moment Methods for Multigroup Thermal Radiative Transfer".
+ *
+ * General rules
+ *  - Every call returns an smrt_status and never throws.  On failure the
+ *    message is available from smrt_last_error(ctx) (a thread-local copy
+ *    for calls that fail before a context exists: smrt_last_error(NULL)).
+ *  - Host arrays passed in are copied; the caller may free them after the
+ *    call returns.  Arrays written by the library are caller-owned buffers
+ *    of the documented size.
+ *  - "_dev" entry points take device pointers (e.g. from torch) that the
+ *    library borrows for the duration of the call only; work is ordered on
+ *    the context's HIP stream and the call returns after the stream is
+ *    synchronised unless stated otherwise.
+ *  - The context owns every device buffer it allocates (angular flux ping-
+ *    pong, moments, low-order operators, traces, scratch) and frees them in
+ *    smrt_destroy.
+ *
+ * Discretisation and numbering (Sec. 3 of the paper; all forms lumped with
+ * the trapezoid rule, Sec. 6):
+ *  - rectilinear mesh, nx (x ny) cells; cell c = i + nx*j;
+ *  - bilinear (2D) / linear (1D) DG nodes at the cell vertices; local node
+ *    l = lx + 2*ly; node n = 2^dim * c + l; every nodal array uses n;
+ *  - angular arrays in the ABI ("psi") are laid out [d][g][node];
+ *  - boundary face nodes (general inflow arrays): 1D x-=0, x+=1; 2D: x- side
+ *    2j+ly, x+ side 2ny+2j+ly, y- side 4ny+2i+lx, y+ side 4ny+2nx+2i+lx.
+ *  - moment arrays ([27][node] in 2D, [8][node] in 1D), FP64: 2D quadrant
+ *    q (0:(mu>0,eta>0) 1:(mu<0,eta>0) 2:(mu<0,eta<0) 3:(mu>0,eta<0)) at rows
+ *    6q+k, k = sums over d in q and all g of w*{1,mu,eta,mu^2,mu*eta,eta^2}*I;
+ *    rows 24..26 = sum_g sigma_g sum_d w*{1,mu,eta}*I.  1D: half h (0:mu>0,
+ *    1:mu<0) at rows 3h+k for w*{1,mu,mu^2}*I; rows 6,7 = sigma-weighted
+ *    {1, mu}.
+ */
+#ifndef SMRT_H
+#define SMRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smrt_ctx smrt_ctx;
+typedef struct smrt_batch smrt_batch;
+
+typedef enum {
+    SMRT_OK = 0,
+    SMRT_E_INVALID_ARG = 1,
+    SMRT_E_OUT_OF_MEMORY = 2,
+    SMRT_E_DEVICE = 3,
+    SMRT_E_NOT_CONVERGED = 4,
+    SMRT_E_NONPHYSICAL = 5,
+    SMRT_E_STATE = 6
+} smrt_status;
+
+/* Precision of the sweep and of the stored angular flux.  The low-order
+ * solve, closures and energy balance always run in FP64. */
+typedef enum { SMRT_FP64 = 0, SMRT_FP32 = 1 } smrt_precision;
+
+/* Low-order scheme: consistent LDG SM (Sec. 4), independent LDG SM (Sec. 4),
+ * or the unaccelerated sweep + pointwise elimination iteration (Sec. 6). */
+typedef enum { SMRT_SM_CONSISTENT = 0, SMRT_SM_INDEPENDENT = 1, SMRT_UNACCELERATED = 2 } smrt_scheme;
+
+/* Rectilinear mesh.  dim = 1 or 2; x_edges[nx+1] strictly increasing;
+ * y_edges[ny+1] in 2D (ny = 1 and y_edges = NULL in 1D). */
+typedef struct {
+    int dim, nx, ny;
+    const double *x_edges, *y_edges;
+} smrt_mesh_desc;
+
+/* Discrete ordinates {Omega_d, w_d} (Sec. 2): omega[n][3] unit vectors,
+ * w[n] with sum w = 4*pi (|sum - 4pi| <= 1e-12*4pi); no direction may have
+ * mu = 0, nor eta = 0 in 2D.  1D uses omega[d][0] = mu only. */
+typedef struct {
+    int n_angles;
+    const double *omega;
+    const double *w;
+} smrt_quad_desc;
+
+/* Groups (Sec. 2): nu_edges[G+1] strictly increasing stated group bounds.
+ * The Planck/Rosseland fractions integrate the first group from 0 and the
+ * last group to infinity, so that sum_g b_g = 1.  a = radiation constant,
+ * c = speed of light. */
+typedef struct {
+    int G;
+    const double *nu_edges;
+    double a, c;
+} smrt_groups_desc;
+
+/* Materials.  model 0: sigma_g = sigma0[r*G+g] (constant); model 1:
+ * sigma_g = sigma0[r] / (nubar_g^3 T_cell^3) clipped to [clip_lo, clip_hi],
+ * nubar_g = sqrt(nu_g nu_{g+1}) and T_cell the mean of the cell's nodal
+ * temperatures (Sec. 3: piecewise-constant opacity from the element-average
+ * temperature).  cv[r] = heat capacity of region r. */
+typedef struct {
+    int n_regions;
+    const int32_t *region_of_cell;
+    int model;
+    const double *sigma0;
+    double clip_lo, clip_hi;
+    const double *cv;
+} smrt_material_desc;
+
+/* Boundary, per side (1D: x-, x+; 2D: x-, x+, y-, y+): kind 0 vacuum,
+ * 1 isotropic Planck inflow B_g(T_bdr)/(4 pi), 2 explicit isotropic inflow
+ * inflow_g[side][g] (intensity per group). */
+typedef struct {
+    int kind[4];
+    double T_bdr[4];
+    const double *inflow_g[4];
+} smrt_boundary_desc;
+
+/* Iteration control (Sec. 6 defaults: eps 1e-3, CG and elimination rtol
+ * 1e-10, caps 100/30/50/40).  strict = 1 turns a capped iteration into
+ * SMRT_E_NOT_CONVERGED.  fixed_outer > 0 runs exactly that many outer
+ * iterations (used to replay a reference iteration count). */
+typedef struct {
+    double eps_outer, eps_inner, cg_rtol, elim_rtol;
+    int max_outer, max_inner, max_cg, max_elim;
+    smrt_precision precision;
+    smrt_scheme scheme;
+    int strict;
+    int fixed_outer;
+    int lo_time_edge;   /* 0: E*, F* = HO sums of I^k (default); 1: LO solution */
+} smrt_options;
+
+/* Per-step statistics (the columns of the paper's summary tables). */
+typedef struct {
+    int outer, inner_total, cg_total, elim_max, hit_max;
+    double energy_residual;
+    double t_sweep_ms, t_lo_ms, t_total_ms;
+} smrt_step_stats;
+
+/* Fills *o with the paper's defaults (FP64, consistent SM). */
+void smrt_default_options(smrt_options *o);
+
+/* Creates a problem context.  Validates every descriptor (see the struct
+ * comments; SMRT_E_INVALID_ARG on violation), copies them, allocates all
+ * device memory (SMRT_E_OUT_OF_MEMORY), builds the low-order operators, and
+ * sets the state to the isotropic equilibrium of T = 0 (call
+ * smrt_set_state next).  hip_stream: a hipStream_t to order all work on, or
+ * NULL for a stream owned by the context.  Requires a gfx950 device. */
+smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_desc *quad, const smrt_groups_desc *groups,
+                        const smrt_material_desc *mat, const smrt_boundary_desc *bc, const smrt_options *opt,
+                        void *hip_stream, smrt_ctx **out);
+
+void smrt_destroy(smrt_ctx *ctx);
+
+/* Last error message of ctx (or of the calling thread when ctx is NULL). */
+const char *smrt_last_error(const smrt_ctx *ctx);
+
+/* Replaces iteration options (precision cannot change after create). */
+smrt_status smrt_set_options(smrt_ctx *ctx, const smrt_options *opt);
+
+/* Replaces the boundary description (e.g. per-step T_bdr). */
+smrt_status smrt_set_boundary(smrt_ctx *ctx, const smrt_boundary_desc *bc);
+
+/* Sets the state: T_nodes[n_nodes] (finite, > 0) and psi[d][g][node] (FP64;
+ * rounded to the context precision) or NULL for the isotropic equilibrium
+ * B_g(T)/(4 pi) (problems start in equilibrium).  The low-order E is set to
+ * the HO energy density of psi and F to its flux. */
+smrt_status smrt_set_state(smrt_ctx *ctx, const double *T_nodes, const double *psi);
+
+/* Copies out T[n_nodes], E[n_nodes] (low-order energy density), F[dim*n]
+ * (low-order flux, node-major) and, if psi != NULL, the angular flux
+ * [d][g][node] (FP64).  Any pointer may be NULL. */
+smrt_status smrt_get_state(smrt_ctx *ctx, double *T, double *E, double *F, double *psi);
+
+/* Raw sweep (Eq. dgsn_transport, lumped): for every (d, g) solves
+ *   Omega.grad I + sigt I = q_iso + inv_c_dt * psi_prev
+ * with upwind traces, in downstream order, and accumulates the moments.
+ * sig_t[cell][G] total (incl. time absorption) and sig[cell][G] absorption
+ * opacities (the latter weights rows 24..26 / 6..7 of the moments);
+ * q_iso[node][G]; psi_prev [d][g][node] or NULL (zero); psi_inflow general
+ * inflow [d][g][boundary node] or NULL (use the boundary description).
+ * Host arrays are in FP64; psi_out ([d][g][node], FP64, may be NULL) and
+ * moments_out ([27 or 8][node], FP64, may be NULL) are written.  The sweep
+ * itself runs at the context precision. */
+smrt_status smrt_sweep(smrt_ctx *ctx, const double *sig_t, const double *sig, const double *q_iso,
+                       const double *psi_prev, double inv_c_dt, const double *psi_inflow, double *psi_out,
+                       double *moments_out);
+
+/* Closures and low-order sources (Sec. 2 gray collapse, Sec. 4 consistent /
+ * independent LDG sources) from HO moments (FP64 [27|8][node], as produced by
+ * smrt_sweep), the outer-iterate temperature T_l[n], the time-edge sources
+ * Estar[n], Fstar[dim*n], the absorption opacity sig[cell][G], and dt.
+ * Output closures_out [5+dim... ] laid out as rows [sigE, sigF, sigP, qE,
+ * qF_x(, qF_y)] x n_nodes.  Uses the context's boundary description and
+ * scheme. */
+smrt_status smrt_compute_closures(smrt_ctx *ctx, const double *moments, const double *T_l, const double *Estar,
+                                  const double *Fstar, const double *sig, double dt, double *closures_out);
+
+/* Low-order Newton solve with nonlinear elimination (Sec. 5) for fixed
+ * closures (rows as produced by smrt_compute_closures), time-edge
+ * temperature Tstar[n] and dt: E[n], T[n] in (initial guess) / out, F[dim*n]
+ * out.  Stats: inner_total, cg_total, elim_max, hit_max. */
+smrt_status smrt_lo_solve(smrt_ctx *ctx, const double *closures, const double *Tstar, double dt, double *E,
+                          double *F, double *T, smrt_step_stats *stats);
+
+/* One backward-Euler step of length dt (Algorithm 1) from the context's
+ * current state; all data stays on the device. */
+smrt_status smrt_step(smrt_ctx *ctx, double dt, smrt_step_stats *stats);
+
+/* Sweep-only throughput path: runs the sweep n_times on the context's
+ * resident state (current psi as psi_prev, current emission source and
+ * opacities for dt) and reports the mean time per sweep (ms) measured with
+ * HIP events on the context stream around the sweep kernel launches. */
+smrt_status smrt_sweep_resident(smrt_ctx *ctx, double dt, int n_times, double *ms_per_sweep);
+
+/* Information about the problem and the chosen launch configuration. */
+typedef struct {
+    int dim, nx, ny, n_angles, G, n_nodes, n_cells;
+    int64_t units_per_sweep;
+    int64_t algorithmic_bytes_per_sweep;   /* read I* + write I, at the sweep precision */
+    int band_rows, waves_per_group, pairs_per_lane, pairs_per_chunk, n_chunks, n_workgroups;
+} smrt_info;
+smrt_status smrt_get_info(const smrt_ctx *ctx, smrt_info *info);
+
+/* Sweep launch configuration override (0 = automatic): waves per
+ * workgroup and (angle,group) pairs per lane. */
+smrt_status smrt_set_launch(smrt_ctx *ctx, int waves_per_group, int pairs_per_lane);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,883 @@
+// C ABI and host runtime of the SM-TRT library: context creation and
+// validation, device memory, the launch plan of the sweep, and the
+// backward-Euler step driver (Algorithm 1 of the paper).
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "lo.h"
+#include "tables.h"
+
+using namespace smrt;
+
+static thread_local std::string g_last_error;
+
+struct smrt_ctx {
+    std::string err;
+    // problem description (host copies)
+    int dim = 0, nx = 0, ny = 0, nang = 0, G = 0, nn = 0, ncell = 0, npc = 0, NB = 0, nreg = 0;
+    std::vector<double> xe, ye, om, w, nu;
+    double a = 1, c = 1;
+    std::vector<int> region;
+    int model = 0;
+    std::vector<double> sigma0, cv;
+    double clip_lo = 0, clip_hi = 0;
+    int bc_kind[4] = {0, 0, 0, 0};
+    double bc_T[4] = {0, 0, 0, 0};
+    std::vector<double> bc_explicit;   // [4][G]
+    smrt_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool fp32 = false;
+    size_t rs = 8;
+    // geometry on the device
+    DevBuf<double> d_nu, d_hx64, d_hy64, d_sigma0, d_cvn, d_om, d_w, d_sideval, d_Tb, d_explicit;
+    DevBuf<int> d_region, d_dir_quad, d_kind;
+    DevBuf<unsigned char> d_hx, d_hy, d_dirs, d_mu_w;
+    // sweep plan
+    int NW = 0, K = 1, R = 0, NQC = 0, nbands = 0, NT = 0, n_wg = 0;
+    int user_NW = 0, user_K = 0;
+    std::vector<int> qc_quad;
+    std::vector<int> slot_pair;   // pairs (d, g)
+    DevBuf<int> d_qc_quad, d_slot_pair, d_ctr;
+    DevBuf<unsigned char> d_psi[2], d_part, d_qiso, d_sig2, d_inflow;
+    DevBuf<uint64_t> d_trace;
+    int cur = 0;
+    // FP64 state and work arrays
+    DevBuf<double> d_T, d_E, d_F, d_Eho, d_Fho, d_mom, d_sig, d_sigP, d_sigF, d_clos, d_Tl, d_El, d_Tn, d_En, d_Tstar,
+        d_Estar, d_Fstar, d_sigEho;
+    LoSolver lo;
+    double alpha[2] = {0, 0}, S1[4] = {0, 0, 0, 0}, S2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool have_state = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+template <typename F>
+static smrt_status guard(smrt_ctx *ctx, F &&f) {
+    try {
+        f();
+        return SMRT_OK;
+    } catch (const smrt::Error &e) {
+        if (ctx) ctx->err = e.msg;
+        g_last_error = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->err = "host allocation failed";
+        g_last_error = "host allocation failed";
+        return SMRT_E_OUT_OF_MEMORY;
+    } catch (...) {
+        if (ctx) ctx->err = "unexpected exception";
+        g_last_error = "unexpected exception";
+        return SMRT_E_DEVICE;
+    }
+}
+
+static void require(bool ok, const std::string &msg) {
+    if (!ok) throw smrt::Error(SMRT_E_INVALID_ARG, msg);
+}
+
+static void h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes) SMRT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+}
+static void d2h(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes) SMRT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+}
+
+// Bernoulli coefficients B_2k / ((2k)! (2k+3)) = (-1)^(k+1) 2 zeta(2k) / ((2 pi)^(2k) (2k+3))
+static void upload_series_coefficients() {
+    double coef[NBERN];
+    for (int k = 1; k <= NBERN; ++k) {
+        double z;
+        if (k == 1) z = M_PI * M_PI / 6.0;
+        else {
+            z = 0.0;
+            const int N = 20000;
+            for (int n = N; n >= 1; --n) z += std::pow((double)n, -2.0 * k);
+            z += std::pow((double)N, 1.0 - 2.0 * k) / (2.0 * k - 1.0) - 0.5 * std::pow((double)N, -2.0 * k);
+        }
+        const double sign = (k % 2 == 1) ? 1.0 : -1.0;
+        coef[k - 1] = sign * 2.0 * z / (std::pow(2.0 * M_PI, 2.0 * k) * (2.0 * k + 3.0));
+    }
+    upload_bernoulli(coef);
+}
+
+__global__ void k_zero_int(int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+__global__ void k_init_ctr(int *p) {
+    p[0] = 0;
+    p[1] = 0;
+    p[2] = 1;
+    p[3] = 0;
+}
+// HO energy density and sigma_E from moments (2D rows 0,6,12,18 / 24; 1D rows 0,3 / 6)
+__global__ void k_ho_from_mom(int nn, int dim, double c, const double *mom, const double *sigP, double *E, double *F,
+                              double *sigE) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double phi, fx, fy = 0.0, sp;
+    if (dim == 2) {
+        phi = mom[n] + mom[6 * (int64_t)nn + n] + mom[12 * (int64_t)nn + n] + mom[18 * (int64_t)nn + n];
+        fx = mom[1 * (int64_t)nn + n] + mom[7 * (int64_t)nn + n] + mom[13 * (int64_t)nn + n] + mom[19 * (int64_t)nn + n];
+        fy = mom[2 * (int64_t)nn + n] + mom[8 * (int64_t)nn + n] + mom[14 * (int64_t)nn + n] + mom[20 * (int64_t)nn + n];
+        sp = mom[24 * (int64_t)nn + n];
+    } else {
+        phi = mom[n] + mom[3 * (int64_t)nn + n];
+        fx = mom[1 * (int64_t)nn + n] + mom[4 * (int64_t)nn + n];
+        sp = mom[6 * (int64_t)nn + n];
+    }
+    if (E) E[n] = phi / c;
+    if (F) {
+        F[dim * n] = fx;
+        if (dim == 2) F[dim * n + 1] = fy;
+    }
+    if (sigE) sigE[n] = phi > 0.0 ? sp / phi : sigP[n];
+}
+
+static int nblk(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// launch plan of the 2D sweep
+// ---------------------------------------------------------------------------
+static void plan_sweep(smrt_ctx *x) {
+    if (x->dim != 2) return;
+    std::vector<std::vector<int>> qdirs(4);
+    for (int d = 0; d < x->nang; ++d) {
+        const double mu = x->om[3 * d], eta = x->om[3 * d + 1];
+        const int q = (mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3;
+        qdirs[q].push_back(d);
+    }
+    int maxP = 0;
+    for (int q = 0; q < 4; ++q) maxP = std::max(maxP, (int)qdirs[q].size() * x->G);
+    int K = x->user_K ? x->user_K : 1;
+    if (x->fp32 == false) K = 1;
+    int NW = x->user_NW;
+    if (!NW) NW = std::max(1, std::min(8, (maxP + 4 * K - 1) / (4 * K)));
+    if (!x->fp32 && NW > 8) NW = 8;
+    x->NW = NW;
+    x->K = K;
+    x->R = 4 * NW * K;
+    x->nbands = (x->ny + BAND_ROWS - 1) / BAND_ROWS;
+    x->NT = x->nx + BAND_ROWS - 1;
+    x->qc_quad.clear();
+    x->slot_pair.clear();
+    for (int q = 0; q < 4; ++q) {
+        const int Pq = (int)qdirs[q].size() * x->G;
+        const int chunks = (Pq + x->R - 1) / x->R;
+        for (int ch = 0; ch < chunks; ++ch) {
+            x->qc_quad.push_back(q);
+            for (int s = 0; s < x->R; ++s) {
+                const int p = ch * x->R + s;
+                if (p < Pq) {
+                    const int nd = (int)qdirs[q].size();
+                    const int g = p / nd, dq = p % nd;
+                    x->slot_pair.push_back(qdirs[q][dq]);
+                    x->slot_pair.push_back(g);
+                } else {
+                    x->slot_pair.push_back(-1);
+                    x->slot_pair.push_back(-1);
+                }
+            }
+        }
+    }
+    x->NQC = (int)x->qc_quad.size();
+    x->n_wg = x->NQC * x->nbands;
+    x->d_qc_quad.alloc(x->NQC);
+    x->d_slot_pair.alloc((int64_t)x->slot_pair.size());
+    SMRT_HIP(hipMemcpy(x->d_qc_quad.p, x->qc_quad.data(), sizeof(int) * x->NQC, hipMemcpyHostToDevice));
+    SMRT_HIP(hipMemcpy(x->d_slot_pair.p, x->slot_pair.data(), sizeof(int) * x->slot_pair.size(), hipMemcpyHostToDevice));
+    const int TW = x->fp32 ? 1 : 2;
+    x->d_part.alloc((int64_t)x->NQC * x->nbands * x->NT * BAND_ROWS * PART_PER_CELL * x->rs);
+    x->d_trace.alloc((int64_t)x->NQC * x->nbands * x->R * x->nx * 2 * TW);
+    SMRT_HIP(hipMemset(x->d_trace.p, 0, sizeof(uint64_t) * x->d_trace.n));
+    x->d_ctr.alloc(4);
+    hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, x->stream, x->d_ctr.p);
+    SMRT_HIP(hipStreamSynchronize(x->stream));
+}
+
+static int64_t psi_count(const smrt_ctx *x) {
+    if (x->dim == 2) return (int64_t)x->nang * x->G * psi_slab(x->nx, x->ny);
+    return (int64_t)x->nang * x->G * x->nn;
+}
+
+// ---------------------------------------------------------------------------
+// sweep launch (2D: band kernel + moment finalisation; 1D: pair kernel + moments)
+// ---------------------------------------------------------------------------
+static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const void *sig2, const void *qiso,
+                      const void *inflow, double icdt, const double *sig64, double *mom, bool finalize = true) {
+    if (x->dim == 2) {
+        Sweep2DArgs a{};
+        a.nx = x->nx; a.ny = x->ny; a.G = x->G; a.nbands = x->nbands; a.NT = x->NT;
+        a.NW = x->NW; a.K = x->K; a.R = x->R; a.NQC = x->NQC; a.n_wg = x->n_wg; a.NB = x->NB;
+        a.qc_quad = x->d_qc_quad.p;
+        a.slot_pair = reinterpret_cast<const int2 *>(x->d_slot_pair.p);
+        a.dirs = x->d_dirs.p; a.hx = x->d_hx.p; a.hy = x->d_hy.p;
+        a.sig2 = sig2; a.qiso = qiso; a.psi_prev = psi_prev; a.psi_out = psi_out; a.inflow = inflow;
+        a.inv_c_dt = icdt; a.part = x->d_part.p; a.trace = x->d_trace.p; a.ctr = x->d_ctr.p;
+        if (x->fp32) launch_sweep2d<float>(a, x->stream);
+        else launch_sweep2d<double>(a, x->stream);
+        if (finalize) {
+            if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->NQC, x->d_qc_quad.p, (const float *)x->d_part.p, mom);
+            else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->NQC, x->d_qc_quad.p, (const double *)x->d_part.p, mom);
+        }
+    } else {
+        Sweep1DArgs a{};
+        a.nx = x->nx; a.G = x->G; a.nang = x->nang; a.mu_w = x->d_mu_w.p; a.hx = x->d_hx.p;
+        a.sig2 = sig2; a.qiso = qiso; a.psi_prev = psi_prev; a.psi_out = psi_out; a.inflow = inflow; a.inv_c_dt = icdt;
+        if (x->fp32) {
+            launch_sweep1d<float>(a, x->stream);
+            if (finalize) run_moments1d<float>(x->stream, x->nx, x->G, x->nang, (const float *)x->d_mu_w.p, sig64, (const float *)psi_out, mom);
+        } else {
+            launch_sweep1d<double>(a, x->stream);
+            if (finalize) run_moments1d<double>(x->stream, x->nx, x->G, x->nang, (const double *)x->d_mu_w.p, sig64, (const double *)psi_out, mom);
+        }
+    }
+}
+
+static void check_sweep_flag(smrt_ctx *x) {
+    if (x->dim != 2) return;
+    int ctr[4];
+    SMRT_HIP(hipMemcpyAsync(ctr, x->d_ctr.p, sizeof(ctr), hipMemcpyDeviceToHost, x->stream));
+    SMRT_HIP(hipStreamSynchronize(x->stream));
+    if (ctr[3]) {
+        // reset the protocol state so the context stays usable, then report
+        hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, x->stream, x->d_ctr.p);
+        SMRT_HIP(hipMemsetAsync(x->d_trace.p, 0, sizeof(uint64_t) * x->d_trace.n, x->stream));
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+        throw smrt::Error(SMRT_E_DEVICE, "sweep band-trace wait exceeded its bound");
+    }
+}
+
+// rebuild the per-side inflow tables from the boundary description
+static void build_inflow(smrt_ctx *x) {
+    const int nsides = 2 * x->dim;
+    h2d(x->d_kind.p, x->bc_kind, sizeof(int) * 4, x->stream);
+    h2d(x->d_Tb.p, x->bc_T, sizeof(double) * 4, x->stream);
+    h2d(x->d_explicit.p, x->bc_explicit.data(), sizeof(double) * 4 * x->G, x->stream);
+    run_side_inflow(x->stream, nsides, x->G, x->d_nu.p, x->a, x->c, x->d_kind.p, x->d_Tb.p, x->d_explicit.p, x->d_sideval.p);
+    if (x->fp32) run_fill_inflow<float>(x->stream, x->dim, x->nx, x->ny, x->G, x->nang, x->d_sideval.p, (float *)x->d_inflow.p);
+    else run_fill_inflow<double>(x->stream, x->dim, x->nx, x->ny, x->G, x->nang, x->d_sideval.p, (double *)x->d_inflow.p);
+}
+
+// per-side total isotropic inflow intensity sum_g I_g (Planck: a c T^4 / 4pi since sum_g b_g = 1)
+static void side_totals(const smrt_ctx *x, double Itot[4]) {
+    for (int s = 0; s < 4; ++s) {
+        Itot[s] = 0.0;
+        if (s >= 2 * x->dim) continue;
+        if (x->bc_kind[s] == 1 && x->bc_T[s] > 0) Itot[s] = x->a * x->c * std::pow(x->bc_T[s], 4) / (4.0 * M_PI);
+        else if (x->bc_kind[s] == 2)
+            for (int g = 0; g < x->G; ++g) Itot[s] += x->bc_explicit[s * x->G + g];
+    }
+}
+
+static ClosureArgs closure_args(smrt_ctx *x, int scheme, double dt, const double *mom, const double *sigP,
+                                const double *sigF, const double *Estar, const double *Fstar, double *out) {
+    ClosureArgs a{};
+    a.dim = x->dim; a.nx = x->nx; a.ny = x->ny; a.scheme = scheme; a.c = x->c; a.dt = dt;
+    a.hx = x->d_hx64.p; a.hy = x->d_hy64.p;
+    a.alpha[0] = x->alpha[0]; a.alpha[1] = x->alpha[1];
+    side_totals(x, a.Itot);
+    for (int s = 0; s < 4; ++s) a.S1[s] = x->S1[s];
+    for (int s = 0; s < 8; ++s) a.S2[s] = x->S2[s];
+    a.mom = mom; a.sigP = sigP; a.sigF = sigF; a.Estar = Estar; a.Fstar = Fstar; a.out = out;
+    return a;
+}
+
+static LoInputs lo_inputs(smrt_ctx *x, double dt, const double *clos) {
+    LoInputs in{};
+    in.dt = dt; in.eps_inner = x->opt.eps_inner; in.cg_rtol = x->opt.cg_rtol; in.elim_rtol = x->opt.elim_rtol;
+    in.max_inner = x->opt.max_inner; in.max_cg = x->opt.max_cg; in.max_elim = x->opt.max_elim;
+    const int64_t nn = x->nn;
+    in.sigE = clos; in.sigF = clos + nn; in.sigP = clos + 2 * nn; in.qE = clos + 3 * nn; in.qF = clos + 4 * nn;
+    in.cvn = x->d_cvn.p;
+    return in;
+}
+
+static double diff_norm(smrt_ctx *x, const double *Ta, const double *Tb, const double *Ea, const double *Eb) {
+    x->lo.dot(x->stream, Ta, nullptr, Tb, 6, false);
+    x->lo.dot(x->stream, Ea, nullptr, Eb, 6, true);
+    return std::sqrt(x->lo.fetch(x->stream, 6));
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" void smrt_default_options(smrt_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->eps_outer = 1e-3; o->eps_inner = 1e-3; o->cg_rtol = 1e-10; o->elim_rtol = 1e-10;
+    o->max_outer = 100; o->max_inner = 30; o->max_cg = 50; o->max_elim = 40;
+    o->precision = SMRT_FP64; o->scheme = SMRT_SM_CONSISTENT;
+}
+
+extern "C" const char *smrt_last_error(const smrt_ctx *ctx) { return ctx ? ctx->err.c_str() : g_last_error.c_str(); }
+
+static void set_boundary_impl(smrt_ctx *x, const smrt_boundary_desc *bc) {
+    require(bc != nullptr, "boundary descriptor is NULL");
+    for (int s = 0; s < 2 * x->dim; ++s) {
+        require(bc->kind[s] >= 0 && bc->kind[s] <= 2, "boundary kind must be 0, 1 or 2");
+        require(bc->kind[s] != 1 || bc->T_bdr[s] >= 0.0, "boundary temperature must be >= 0");
+        require(bc->kind[s] != 2 || bc->inflow_g[s] != nullptr, "explicit inflow needs inflow_g");
+        x->bc_kind[s] = bc->kind[s];
+        x->bc_T[s] = bc->T_bdr[s];
+        for (int g = 0; g < x->G; ++g) {
+            const double v = bc->kind[s] == 2 ? bc->inflow_g[s][g] : 0.0;
+            require(v >= 0.0, "explicit inflow must be >= 0");
+            x->bc_explicit[s * x->G + g] = v;
+        }
+    }
+    build_inflow(x);
+}
+
+static void validate_options(const smrt_options *o) {
+    require(o->eps_outer > 0 && o->eps_inner > 0 && o->cg_rtol > 0 && o->elim_rtol > 0, "tolerances must be > 0");
+    require(o->max_outer > 0 && o->max_inner > 0 && o->max_cg > 0 && o->max_elim > 0, "iteration caps must be > 0");
+    require(o->scheme >= 0 && o->scheme <= 2, "unknown scheme");
+    require(o->precision == SMRT_FP64 || o->precision == SMRT_FP32, "unknown precision");
+}
+
+extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_desc *quad, const smrt_groups_desc *groups,
+                                   const smrt_material_desc *mat, const smrt_boundary_desc *bc, const smrt_options *opt,
+                                   void *hip_stream, smrt_ctx **out) {
+    if (!out) { g_last_error = "out is NULL"; return SMRT_E_INVALID_ARG; }
+    *out = nullptr;
+    std::unique_ptr<smrt_ctx> x(new (std::nothrow) smrt_ctx());
+    if (!x) { g_last_error = "host allocation failed"; return SMRT_E_OUT_OF_MEMORY; }
+    smrt_ctx *p = x.get();
+    smrt_status st = guard(p, [&] {
+        require(mesh && quad && groups && mat && bc && opt, "NULL descriptor");
+        require(mesh->dim == 1 || mesh->dim == 2, "dim must be 1 or 2");
+        require(mesh->nx >= 1 && (mesh->dim == 1 || mesh->ny >= 1), "mesh needs at least one cell");
+        require(mesh->x_edges != nullptr && (mesh->dim == 1 || mesh->y_edges != nullptr), "mesh edges are NULL");
+        p->dim = mesh->dim; p->nx = mesh->nx; p->ny = mesh->dim == 2 ? mesh->ny : 1;
+        p->xe.assign(mesh->x_edges, mesh->x_edges + p->nx + 1);
+        for (int i = 0; i < p->nx; ++i) require(p->xe[i + 1] > p->xe[i], "x_edges must increase strictly");
+        if (p->dim == 2) {
+            p->ye.assign(mesh->y_edges, mesh->y_edges + p->ny + 1);
+            for (int j = 0; j < p->ny; ++j) require(p->ye[j + 1] > p->ye[j], "y_edges must increase strictly");
+        }
+        require(quad->n_angles >= 1 && quad->omega && quad->w, "quadrature arrays are NULL");
+        p->nang = quad->n_angles;
+        p->om.assign(quad->omega, quad->omega + 3 * p->nang);
+        p->w.assign(quad->w, quad->w + p->nang);
+        double sw = 0.0;
+        for (int d = 0; d < p->nang; ++d) {
+            sw += p->w[d];
+            require(p->w[d] > 0.0, "quadrature weights must be > 0");
+            require(p->om[3 * d] != 0.0, "a direction has mu = 0");
+            if (p->dim == 2) {
+                require(p->om[3 * d + 1] != 0.0, "a direction has eta = 0");
+                const double nrm = std::sqrt(p->om[3 * d] * p->om[3 * d] + p->om[3 * d + 1] * p->om[3 * d + 1] +
+                                             p->om[3 * d + 2] * p->om[3 * d + 2]);
+                require(std::fabs(nrm - 1.0) <= 1e-12, "directions must be unit vectors");
+            } else {
+                require(std::fabs(p->om[3 * d]) <= 1.0, "|mu| must be <= 1");
+            }
+        }
+        require(std::fabs(sw - 4.0 * M_PI) <= 1e-12 * 4.0 * M_PI, "quadrature weights must sum to 4 pi");
+        require(groups->G >= 1 && groups->G <= MAXG && groups->nu_edges, "G must be in [1, 64]");
+        p->G = groups->G;
+        p->nu.assign(groups->nu_edges, groups->nu_edges + p->G + 1);
+        for (int g = 0; g < p->G; ++g) require(p->nu[g + 1] > p->nu[g] && p->nu[g] >= 0.0, "nu_edges must increase strictly");
+        require(groups->a > 0 && groups->c > 0, "a and c must be > 0");
+        p->a = groups->a; p->c = groups->c;
+        p->npc = p->dim == 2 ? 4 : 2;
+        p->ncell = p->nx * p->ny;
+        p->nn = p->ncell * p->npc;
+        p->NB = p->dim == 1 ? 2 : 4 * (p->nx + p->ny);
+        require(mat->n_regions >= 1 && mat->region_of_cell && mat->sigma0 && mat->cv, "material arrays are NULL");
+        require(mat->model == 0 || mat->model == 1, "material model must be 0 or 1");
+        p->nreg = mat->n_regions;
+        p->region.assign(mat->region_of_cell, mat->region_of_cell + p->ncell);
+        for (int r : p->region) require(r >= 0 && r < p->nreg, "region index out of range");
+        p->model = mat->model;
+        const int ns = p->model == 0 ? p->nreg * p->G : p->nreg;
+        p->sigma0.assign(mat->sigma0, mat->sigma0 + ns);
+        for (double v : p->sigma0) require(v >= 0.0 && std::isfinite(v), "sigma0 must be finite and >= 0");
+        p->cv.assign(mat->cv, mat->cv + p->nreg);
+        for (double v : p->cv) require(v > 0.0, "cv must be > 0");
+        p->clip_lo = mat->clip_lo; p->clip_hi = mat->clip_hi;
+        require(p->model == 0 || (p->clip_lo >= 0 && p->clip_hi >= p->clip_lo), "clip range must satisfy 0 <= lo <= hi");
+        validate_options(opt);
+        p->opt = *opt;
+        p->fp32 = opt->precision == SMRT_FP32;
+        p->rs = p->fp32 ? 4 : 8;
+        int ndev = 0;
+        SMRT_HIP(hipGetDeviceCount(&ndev));
+        require(ndev > 0, "no HIP device");
+        int dev = 0;
+        SMRT_HIP(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        SMRT_HIP(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            throw smrt::Error(SMRT_E_DEVICE, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+        if (hip_stream) p->stream = static_cast<hipStream_t>(hip_stream);
+        else { SMRT_HIP(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking)); p->own_stream = true; }
+        SMRT_HIP(hipEventCreate(&p->ev0));
+        SMRT_HIP(hipEventCreate(&p->ev1));
+        upload_series_coefficients();
+        // quadrature sums used by the closures
+        for (int ax = 0; ax < p->dim; ++ax) {
+            double s = 0.0;
+            for (int d = 0; d < p->nang; ++d) s += p->w[d] * std::fabs(p->om[3 * d + ax]);
+            p->alpha[ax] = s / sw;
+            for (int sd = 0; sd < 2; ++sd) {
+                const int side = 2 * ax + sd;
+                const double sgn = sd ? 1.0 : -1.0;
+                double s1 = 0.0, s2[2] = {0.0, 0.0};
+                for (int d = 0; d < p->nang; ++d) {
+                    const double on = sgn * p->om[3 * d + ax];
+                    if (on < 0) {
+                        s1 += p->w[d] * on;
+                        for (int a = 0; a < p->dim; ++a) s2[a] += p->w[d] * p->om[3 * d + a] * on;
+                    }
+                }
+                p->S1[side] = s1;
+                p->S2[2 * side] = s2[0];
+                p->S2[2 * side + 1] = s2[1];
+            }
+        }
+        // geometry and materials on the device
+        std::vector<double> hx(p->nx), hy(p->ny, 1.0);
+        for (int i = 0; i < p->nx; ++i) hx[i] = p->xe[i + 1] - p->xe[i];
+        if (p->dim == 2)
+            for (int j = 0; j < p->ny; ++j) hy[j] = p->ye[j + 1] - p->ye[j];
+        p->d_hx64.alloc(p->nx); p->d_hy64.alloc(p->ny);
+        h2d(p->d_hx64.p, hx.data(), 8 * p->nx, p->stream);
+        h2d(p->d_hy64.p, hy.data(), 8 * p->ny, p->stream);
+        p->d_hx.alloc(p->nx * p->rs); p->d_hy.alloc(p->ny * p->rs);
+        std::vector<double> dirs((size_t)p->nang * 8), mw((size_t)p->nang * 2);
+        std::vector<int> dq(p->nang);
+        for (int d = 0; d < p->nang; ++d) {
+            const double mu = p->om[3 * d], eta = p->dim == 2 ? p->om[3 * d + 1] : 0.0, ww = p->w[d];
+            const double v[8] = {mu, eta, ww, ww * mu, ww * eta, ww * mu * mu, ww * mu * eta, ww * eta * eta};
+            for (int k = 0; k < 8; ++k) dirs[8 * d + k] = v[k];
+            mw[2 * d] = mu; mw[2 * d + 1] = ww;
+            dq[d] = (mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3;
+        }
+        DevBuf<double> tmp;
+        tmp.alloc(std::max<int64_t>((int64_t)p->nang * 8, std::max(p->nx, p->ny)));
+        auto to_real = [&](const std::vector<double> &src, DevBuf<unsigned char> &dst) {
+            dst.alloc(src.size() * p->rs);
+            SMRT_HIP(hipMemcpy(tmp.p, src.data(), 8 * src.size(), hipMemcpyHostToDevice));
+            if (p->fp32) run_copy_to<float>(p->stream, (int64_t)src.size(), tmp.p, (float *)dst.p);
+            else run_copy_to<double>(p->stream, (int64_t)src.size(), tmp.p, (double *)dst.p);
+            SMRT_HIP(hipStreamSynchronize(p->stream));
+        };
+        to_real(hx, p->d_hx);
+        to_real(hy, p->d_hy);
+        to_real(dirs, p->d_dirs);
+        to_real(mw, p->d_mu_w);
+        p->d_dir_quad.alloc(p->nang);
+        SMRT_HIP(hipMemcpy(p->d_dir_quad.p, dq.data(), sizeof(int) * p->nang, hipMemcpyHostToDevice));
+        p->d_nu.alloc(p->G + 1);
+        SMRT_HIP(hipMemcpy(p->d_nu.p, p->nu.data(), 8 * (p->G + 1), hipMemcpyHostToDevice));
+        p->d_region.alloc(p->ncell);
+        SMRT_HIP(hipMemcpy(p->d_region.p, p->region.data(), sizeof(int) * p->ncell, hipMemcpyHostToDevice));
+        p->d_sigma0.alloc(ns);
+        SMRT_HIP(hipMemcpy(p->d_sigma0.p, p->sigma0.data(), 8 * ns, hipMemcpyHostToDevice));
+        std::vector<double> cvn(p->nn);
+        for (int n = 0; n < p->nn; ++n) cvn[n] = p->cv[p->region[n / p->npc]];
+        p->d_cvn.alloc(p->nn);
+        SMRT_HIP(hipMemcpy(p->d_cvn.p, cvn.data(), 8 * p->nn, hipMemcpyHostToDevice));
+        p->d_om.alloc(3 * p->nang); p->d_w.alloc(p->nang);
+        SMRT_HIP(hipMemcpy(p->d_om.p, p->om.data(), 8 * 3 * p->nang, hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(p->d_w.p, p->w.data(), 8 * p->nang, hipMemcpyHostToDevice));
+        p->d_sideval.alloc(4 * p->G); p->d_Tb.alloc(4); p->d_explicit.alloc(4 * p->G); p->d_kind.alloc(4);
+        p->bc_explicit.assign(4 * p->G, 0.0);
+        // state and work arrays
+        const int NM = p->dim == 2 ? 27 : 8;
+        p->d_psi[0].alloc(psi_count(p) * p->rs);
+        p->d_psi[1].alloc(psi_count(p) * p->rs);
+        p->d_psi[0].zero(p->stream);
+        p->d_psi[1].zero(p->stream);
+        p->d_qiso.alloc((int64_t)p->nn * p->G * p->rs);
+        p->d_sig2.alloc((int64_t)p->ncell * p->G * 2 * p->rs);
+        p->d_inflow.alloc((int64_t)p->nang * p->G * p->NB * p->rs);
+        for (auto *b : {&p->d_T, &p->d_E, &p->d_Eho, &p->d_sigP, &p->d_sigF, &p->d_Tl, &p->d_El, &p->d_Tn, &p->d_En,
+                        &p->d_Tstar, &p->d_Estar, &p->d_sigEho})
+            b->alloc(p->nn);
+        for (auto *b : {&p->d_F, &p->d_Fho, &p->d_Fstar}) b->alloc((int64_t)p->nn * p->dim);
+        p->d_mom.alloc((int64_t)NM * p->nn);
+        p->d_sig.alloc((int64_t)p->ncell * p->G);
+        p->d_clos.alloc((int64_t)(4 + p->dim) * p->nn);
+        p->lo.init(p->dim, p->nx, p->ny, p->xe, p->ye, p->alpha, p->c, p->a);
+        plan_sweep(p);
+        set_boundary_impl(p, bc);
+        SMRT_HIP(hipStreamSynchronize(p->stream));
+    });
+    if (st != SMRT_OK) {
+        g_last_error = p->err;
+        return st;
+    }
+    *out = x.release();
+    return SMRT_OK;
+}
+
+extern "C" void smrt_destroy(smrt_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+extern "C" smrt_status smrt_set_options(smrt_ctx *x, const smrt_options *o) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(o != nullptr, "options are NULL");
+        validate_options(o);
+        require(o->precision == x->opt.precision, "precision cannot change after create");
+        x->opt = *o;
+    });
+}
+
+extern "C" smrt_status smrt_set_boundary(smrt_ctx *x, const smrt_boundary_desc *bc) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        set_boundary_impl(x, bc);
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+    });
+}
+
+extern "C" smrt_status smrt_set_launch(smrt_ctx *x, int waves_per_group, int pairs_per_lane) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(waves_per_group >= 0 && waves_per_group <= MAX_WG_THREADS / 64, "waves per group must be in [0, 8]");
+        require(pairs_per_lane == 0 || pairs_per_lane == 1 || (pairs_per_lane == 2 && x->fp32),
+                "pairs per lane must be 0 (auto), 1, or 2 (FP32 only)");
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+        x->user_NW = waves_per_group;
+        x->user_K = pairs_per_lane;
+        plan_sweep(x);
+    });
+}
+
+extern "C" smrt_status smrt_get_info(const smrt_ctx *x, smrt_info *info) {
+    if (!x || !info) { g_last_error = "NULL argument"; return SMRT_E_INVALID_ARG; }
+    info->dim = x->dim; info->nx = x->nx; info->ny = x->ny; info->n_angles = x->nang; info->G = x->G;
+    info->n_nodes = x->nn; info->n_cells = x->ncell;
+    info->units_per_sweep = (int64_t)x->ncell * x->nang * x->G;
+    info->algorithmic_bytes_per_sweep = info->units_per_sweep * 2 * x->npc * (int64_t)x->rs;
+    info->band_rows = BAND_ROWS; info->waves_per_group = x->NW; info->pairs_per_lane = x->K;
+    info->pairs_per_chunk = x->R; info->n_chunks = x->NQC; info->n_workgroups = x->n_wg;
+    return SMRT_OK;
+}
+
+extern "C" smrt_status smrt_set_state(smrt_ctx *x, const double *T_nodes, const double *psi) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(T_nodes != nullptr, "T is NULL");
+        for (int n = 0; n < x->nn; ++n) require(T_nodes[n] > 0.0 && std::isfinite(T_nodes[n]), "T must be finite and > 0");
+        h2d(x->d_T.p, T_nodes, 8 * x->nn, x->stream);
+        DevBuf<double> abi;
+        const int64_t na = (int64_t)x->nang * x->G * x->nn;
+        abi.alloc(na);
+        if (psi) h2d(abi.p, psi, 8 * na, x->stream);
+        else run_equilibrium(x->stream, x->nn, x->G, x->nang, x->d_T.p, x->d_nu.p, x->a, x->c, abi.p);
+        if (x->dim == 2) {
+            if (x->fp32) run_psi_to_internal<float>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, abi.p, (float *)x->d_psi[x->cur].p);
+            else run_psi_to_internal<double>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, abi.p, (double *)x->d_psi[x->cur].p);
+        } else {
+            if (x->fp32) run_copy_to<float>(x->stream, na, abi.p, (float *)x->d_psi[x->cur].p);
+            else run_copy_to<double>(x->stream, na, abi.p, (double *)x->d_psi[x->cur].p);
+        }
+        run_psi_EF(x->stream, x->nn, x->dim, x->G, x->nang, x->d_om.p, x->d_w.p, x->c, abi.p, x->d_Eho.p, x->d_Fho.p);
+        SMRT_HIP(hipMemcpyAsync(x->d_E.p, x->d_Eho.p, 8 * x->nn, hipMemcpyDeviceToDevice, x->stream));
+        SMRT_HIP(hipMemcpyAsync(x->d_F.p, x->d_Fho.p, 8 * x->nn * x->dim, hipMemcpyDeviceToDevice, x->stream));
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+        x->have_state = true;
+    });
+}
+
+extern "C" smrt_status smrt_get_state(smrt_ctx *x, double *T, double *E, double *F, double *psi) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        if (T) d2h(T, x->d_T.p, 8 * x->nn, x->stream);
+        if (E) d2h(E, x->d_E.p, 8 * x->nn, x->stream);
+        if (F) d2h(F, x->d_F.p, 8 * x->nn * x->dim, x->stream);
+        if (psi) {
+            const int64_t na = (int64_t)x->nang * x->G * x->nn;
+            DevBuf<double> abi;
+            abi.alloc(na);
+            if (x->dim == 2) {
+                if (x->fp32) run_psi_from_internal<float>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const float *)x->d_psi[x->cur].p, abi.p);
+                else run_psi_from_internal<double>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const double *)x->d_psi[x->cur].p, abi.p);
+            } else {
+                // 1D internal layout equals the ABI layout
+                DevBuf<double> t;
+                if (x->fp32) {
+                    std::vector<float> h(na);
+                    d2h(h.data(), x->d_psi[x->cur].p, 4 * na, x->stream);
+                    SMRT_HIP(hipStreamSynchronize(x->stream));
+                    for (int64_t k = 0; k < na; ++k) psi[k] = h[k];
+                    return;
+                }
+                SMRT_HIP(hipMemcpyAsync(abi.p, x->d_psi[x->cur].p, 8 * na, hipMemcpyDeviceToDevice, x->stream));
+            }
+            d2h(psi, abi.p, 8 * na, x->stream);
+            SMRT_HIP(hipStreamSynchronize(x->stream));
+        }
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+    });
+}
+
+extern "C" smrt_status smrt_sweep(smrt_ctx *x, const double *sig_t, const double *sig, const double *q_iso,
+                                  const double *psi_prev, double inv_c_dt, const double *psi_inflow, double *psi_out,
+                                  double *moments_out) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(sig_t && sig && q_iso, "sig_t, sig and q_iso are required");
+        require(std::isfinite(inv_c_dt) && inv_c_dt >= 0.0, "inv_c_dt must be finite and >= 0");
+        const int64_t na = (int64_t)x->nang * x->G * x->nn;
+        const int64_t ng = (int64_t)x->ncell * x->G;
+        for (int64_t k = 0; k < ng; ++k) require(sig_t[k] > 0.0 && sig[k] >= 0.0, "sig_t must be > 0 and sig >= 0");
+        DevBuf<double> t_st, t_s, t_q, t_abi, t_inf;
+        DevBuf<unsigned char> t_sig2, t_qiso, t_in, t_out, t_inflow;
+        t_st.alloc(ng); t_s.alloc(ng); t_q.alloc((int64_t)x->nn * x->G);
+        h2d(t_st.p, sig_t, 8 * ng, x->stream);
+        h2d(t_s.p, sig, 8 * ng, x->stream);
+        h2d(t_q.p, q_iso, 8 * x->nn * x->G, x->stream);
+        t_sig2.alloc(ng * 2 * x->rs);
+        t_qiso.alloc((int64_t)x->nn * x->G * x->rs);
+        t_in.alloc(psi_count(x) * x->rs);
+        t_out.alloc(psi_count(x) * x->rs);
+        t_inflow.alloc((int64_t)x->nang * x->G * x->NB * x->rs);
+        t_abi.alloc(na);
+        if (psi_prev) h2d(t_abi.p, psi_prev, 8 * na, x->stream);
+        if (x->fp32) {
+            run_sig_to_internal<float>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (float *)t_sig2.p);
+            run_qiso_to_internal<float>(x->stream, x->nn, x->G, x->npc, t_q.p, (float *)t_qiso.p);
+            if (psi_prev) {
+                if (x->dim == 2) run_psi_to_internal<float>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, t_abi.p, (float *)t_in.p);
+                else run_copy_to<float>(x->stream, na, t_abi.p, (float *)t_in.p);
+            }
+        } else {
+            run_sig_to_internal<double>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (double *)t_sig2.p);
+            run_qiso_to_internal<double>(x->stream, x->nn, x->G, x->npc, t_q.p, (double *)t_qiso.p);
+            if (psi_prev) {
+                if (x->dim == 2) run_psi_to_internal<double>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, t_abi.p, (double *)t_in.p);
+                else run_copy_to<double>(x->stream, na, t_abi.p, (double *)t_in.p);
+            }
+        }
+        const void *inflow = x->d_inflow.p;
+        if (psi_inflow) {
+            const int64_t ni = (int64_t)x->nang * x->G * x->NB;
+            t_inf.alloc(ni);
+            h2d(t_inf.p, psi_inflow, 8 * ni, x->stream);
+            if (x->fp32) run_copy_to<float>(x->stream, ni, t_inf.p, (float *)t_inflow.p);
+            else run_copy_to<double>(x->stream, ni, t_inf.p, (double *)t_inflow.p);
+            inflow = t_inflow.p;
+        }
+        DevBuf<double> mom;
+        mom.alloc((int64_t)(x->dim == 2 ? 27 : 8) * x->nn);
+        run_sweep(x, psi_prev ? t_in.p : nullptr, t_out.p, t_sig2.p, t_qiso.p, inflow, inv_c_dt, t_s.p, mom.p);
+        check_sweep_flag(x);
+        if (moments_out) d2h(moments_out, mom.p, 8 * mom.n, x->stream);
+        if (psi_out) {
+            if (x->dim == 2) {
+                if (x->fp32) run_psi_from_internal<float>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const float *)t_out.p, t_abi.p);
+                else run_psi_from_internal<double>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const double *)t_out.p, t_abi.p);
+                d2h(psi_out, t_abi.p, 8 * na, x->stream);
+            } else if (x->fp32) {
+                std::vector<float> h(na);
+                d2h(h.data(), t_out.p, 4 * na, x->stream);
+                SMRT_HIP(hipStreamSynchronize(x->stream));
+                for (int64_t k = 0; k < na; ++k) psi_out[k] = h[k];
+            } else {
+                d2h(psi_out, t_out.p, 8 * na, x->stream);
+            }
+        }
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+    });
+}
+
+extern "C" smrt_status smrt_compute_closures(smrt_ctx *x, const double *moments, const double *T_l, const double *Estar,
+                                             const double *Fstar, const double *sig, double dt, double *closures_out) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(moments && T_l && Estar && Fstar && sig && closures_out, "NULL argument");
+        require(dt > 0.0, "dt must be > 0");
+        const int NM = x->dim == 2 ? 27 : 8;
+        DevBuf<double> m, Tl, Es, Fs, sg, sP, sF, out;
+        DevBuf<unsigned char> q;
+        m.alloc((int64_t)NM * x->nn); Tl.alloc(x->nn); Es.alloc(x->nn); Fs.alloc((int64_t)x->nn * x->dim);
+        sg.alloc((int64_t)x->ncell * x->G); sP.alloc(x->nn); sF.alloc(x->nn); out.alloc((int64_t)(4 + x->dim) * x->nn);
+        q.alloc((int64_t)x->nn * x->G * x->rs);
+        h2d(m.p, moments, 8 * m.n, x->stream); h2d(Tl.p, T_l, 8 * x->nn, x->stream); h2d(Es.p, Estar, 8 * x->nn, x->stream);
+        h2d(Fs.p, Fstar, 8 * Fs.n, x->stream); h2d(sg.p, sig, 8 * sg.n, x->stream);
+        if (x->fp32) run_source<float>(x->stream, x->nn, x->npc, x->G, Tl.p, x->d_nu.p, x->a, x->c, sg.p, (float *)q.p, sP.p, sF.p);
+        else run_source<double>(x->stream, x->nn, x->npc, x->G, Tl.p, x->d_nu.p, x->a, x->c, sg.p, (double *)q.p, sP.p, sF.p);
+        run_closures(x->stream, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt, m.p, sP.p, sF.p, Es.p, Fs.p, out.p));
+        d2h(closures_out, out.p, 8 * out.n, x->stream);
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+    });
+}
+
+extern "C" smrt_status smrt_lo_solve(smrt_ctx *x, const double *closures, const double *Tstar, double dt, double *E,
+                                     double *F, double *T, smrt_step_stats *stats) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    smrt_status inner = SMRT_OK;
+    smrt_status st = guard(x, [&] {
+        require(closures && Tstar && E && F && T, "NULL argument");
+        require(dt > 0.0, "dt must be > 0");
+        DevBuf<double> cl, Ts, dE, dF, dT;
+        cl.alloc((int64_t)(4 + x->dim) * x->nn); Ts.alloc(x->nn); dE.alloc(x->nn); dF.alloc((int64_t)x->nn * x->dim); dT.alloc(x->nn);
+        h2d(cl.p, closures, 8 * cl.n, x->stream); h2d(Ts.p, Tstar, 8 * x->nn, x->stream);
+        h2d(dE.p, E, 8 * x->nn, x->stream); h2d(dT.p, T, 8 * x->nn, x->stream);
+        smrt_step_stats s{};
+        LoInputs in = lo_inputs(x, dt, cl.p);
+        in.Tstar = Ts.p;
+        inner = x->lo.solve(x->stream, in, dE.p, dF.p, dT.p, &s, x->err);
+        d2h(E, dE.p, 8 * x->nn, x->stream); d2h(F, dF.p, 8 * dF.n, x->stream); d2h(T, dT.p, 8 * x->nn, x->stream);
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+        if (stats) *stats = s;
+        if (inner == SMRT_OK && x->opt.strict && s.hit_max) {
+            inner = SMRT_E_NOT_CONVERGED;
+            x->err = "low-order iteration cap reached";
+        }
+    });
+    return st != SMRT_OK ? st : inner;
+}
+
+// prepare the per-step opacity table and return 1/(c dt)
+static double prepare_step_tables(smrt_ctx *x, double dt) {
+    const double icdt = 1.0 / (x->c * dt);
+    if (x->fp32) run_opacity<float>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, (float *)x->d_sig2.p);
+    else run_opacity<double>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, (double *)x->d_sig2.p);
+    return icdt;
+}
+
+static void run_source_at(smrt_ctx *x, const double *T) {
+    if (x->fp32) run_source<float>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, (float *)x->d_qiso.p, x->d_sigP.p, x->d_sigF.p);
+    else run_source<double>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, (double *)x->d_qiso.p, x->d_sigP.p, x->d_sigF.p);
+}
+
+extern "C" smrt_status smrt_step(smrt_ctx *x, double dt, smrt_step_stats *stats) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    smrt_status result = SMRT_OK;
+    smrt_status st = guard(x, [&] {
+        require(dt > 0.0 && std::isfinite(dt), "dt must be finite and > 0");
+        require(x->have_state, "smrt_set_state must be called before smrt_step");
+        smrt_step_stats s{};
+        hipStream_t S = x->stream;
+        const int64_t nn = x->nn;
+        SMRT_HIP(hipEventRecord(x->ev0, S));
+        const double icdt = prepare_step_tables(x, dt);
+        SMRT_HIP(hipMemcpyAsync(x->d_Tstar.p, x->d_T.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+        if (x->opt.lo_time_edge) {
+            SMRT_HIP(hipMemcpyAsync(x->d_Estar.p, x->d_E.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+            SMRT_HIP(hipMemcpyAsync(x->d_Fstar.p, x->d_F.p, 8 * nn * x->dim, hipMemcpyDeviceToDevice, S));
+        } else {
+            SMRT_HIP(hipMemcpyAsync(x->d_Estar.p, x->d_Eho.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+            SMRT_HIP(hipMemcpyAsync(x->d_Fstar.p, x->d_Fho.p, 8 * nn * x->dim, hipMemcpyDeviceToDevice, S));
+        }
+        SMRT_HIP(hipMemcpyAsync(x->d_Tl.p, x->d_T.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+        const bool unacc = x->opt.scheme == SMRT_UNACCELERATED;
+        SMRT_HIP(hipMemcpyAsync(x->d_El.p, unacc ? x->d_Estar.p : x->d_E.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+        double first = -1.0;
+        const int maxo = x->opt.fixed_outer > 0 ? x->opt.fixed_outer : x->opt.max_outer;
+        void *pin = x->d_psi[x->cur].p, *pout = x->d_psi[1 - x->cur].p;
+        float t_sweep = 0.f;
+        for (int l = 1; l <= maxo; ++l) {
+            run_source_at(x, x->d_Tl.p);
+            SMRT_HIP(hipEventRecord(x->ev1, S));
+            hipEvent_t e0, e1;
+            SMRT_HIP(hipEventCreate(&e0));
+            SMRT_HIP(hipEventCreate(&e1));
+            SMRT_HIP(hipEventRecord(e0, S));
+            run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p);
+            SMRT_HIP(hipEventRecord(e1, S));
+            s.outer++;
+            SMRT_HIP(hipMemcpyAsync(x->d_Tn.p, x->d_Tl.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+            if (unacc) {
+                // pointwise elimination against sum_g sigma_g phi_g of the sweep
+                hipLaunchKernelGGL(k_ho_from_mom, dim3(nblk(nn)), dim3(256), 0, S, (int)nn, x->dim, x->c, x->d_mom.p,
+                                   x->d_sigP.p, x->d_En.p, (double *)nullptr, x->d_sigEho.p);
+                LoSolver &L = x->lo;
+                hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, S, L.flags.p, 4);
+                run_eliminate(S, (int)nn, x->a, x->c, dt, x->opt.elim_rtol, x->opt.max_elim, x->d_cvn.p, x->d_sigEho.p,
+                              x->d_sigP.p, x->d_En.p, x->d_Tstar.p, x->d_Tn.p, L.flags.p);
+                int fl[4];
+                d2h(fl, L.flags.p, sizeof fl, S);
+                SMRT_HIP(hipStreamSynchronize(S));
+                if (fl[1] > s.elim_max) s.elim_max = fl[1];
+                if (fl[0]) { x->err = "no positive temperature root in the energy balance"; result = SMRT_E_NONPHYSICAL; }
+            } else {
+                SMRT_HIP(hipMemcpyAsync(x->d_En.p, x->d_El.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+                run_closures(S, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt, x->d_mom.p, x->d_sigP.p,
+                                             x->d_sigF.p, x->d_Estar.p, x->d_Fstar.p, x->d_clos.p));
+                LoInputs in = lo_inputs(x, dt, x->d_clos.p);
+                in.Tstar = x->d_Tstar.p;
+                smrt_step_stats ls{};
+                const smrt_status r = x->lo.solve(S, in, x->d_En.p, x->d_F.p, x->d_Tn.p, &ls, x->err);
+                s.inner_total += ls.inner_total;
+                s.cg_total += ls.cg_total;
+                s.elim_max = std::max(s.elim_max, ls.elim_max);
+                s.hit_max |= ls.hit_max;
+                if (r != SMRT_OK) result = r;
+            }
+            float ms = 0.f;
+            SMRT_HIP(hipEventSynchronize(e1));
+            SMRT_HIP(hipEventElapsedTime(&ms, e0, e1));
+            t_sweep += ms;
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            check_sweep_flag(x);
+            const double diff = diff_norm(x, x->d_Tn.p, x->d_Tl.p, x->d_En.p, x->d_El.p);
+            SMRT_HIP(hipMemcpyAsync(x->d_Tl.p, x->d_Tn.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+            SMRT_HIP(hipMemcpyAsync(x->d_El.p, x->d_En.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+            if (result != SMRT_OK) break;
+            if (!std::isfinite(diff)) { x->err = "non-finite outer iterate"; result = SMRT_E_NONPHYSICAL; break; }
+            if (x->opt.fixed_outer > 0) continue;
+            if (l == 1) first = diff;
+            if (diff == 0.0 || (l > 1 && diff < x->opt.eps_outer * first)) break;
+            if (l == maxo) s.hit_max = 1;
+        }
+        // new state: T, E from the last outer iterate; psi and HO moments from the last sweep
+        SMRT_HIP(hipMemcpyAsync(x->d_T.p, x->d_Tl.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+        SMRT_HIP(hipMemcpyAsync(x->d_E.p, x->d_El.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+        hipLaunchKernelGGL(k_ho_from_mom, dim3(nblk(nn)), dim3(256), 0, S, (int)nn, x->dim, x->c, x->d_mom.p, x->d_sigP.p,
+                           x->d_Eho.p, x->d_Fho.p, (double *)nullptr);
+        x->cur = 1 - x->cur;
+        SMRT_HIP(hipEventRecord(x->ev1, S));
+        SMRT_HIP(hipEventSynchronize(x->ev1));
+        float tot = 0.f;
+        SMRT_HIP(hipEventElapsedTime(&tot, x->ev0, x->ev1));
+        s.t_total_ms = tot;
+        s.t_sweep_ms = t_sweep;
+        s.t_lo_ms = tot - t_sweep;
+        if (stats) *stats = s;
+        if (result == SMRT_OK && x->opt.strict && s.hit_max) {
+            result = SMRT_E_NOT_CONVERGED;
+            x->err = "iteration cap reached";
+        }
+    });
+    return st != SMRT_OK ? st : result;
+}
+
+extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, double *ms_per_sweep) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(dt > 0.0 && n_times >= 1 && ms_per_sweep, "invalid argument");
+        require(x->have_state, "smrt_set_state must be called first");
+        const double icdt = prepare_step_tables(x, dt);
+        run_source_at(x, x->d_T.p);
+        void *pin = x->d_psi[x->cur].p, *pout = x->d_psi[1 - x->cur].p;
+        SMRT_HIP(hipEventRecord(x->ev0, x->stream));
+        for (int k = 0; k < n_times; ++k)
+            run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p, false);
+        SMRT_HIP(hipEventRecord(x->ev1, x->stream));
+        SMRT_HIP(hipEventSynchronize(x->ev1));
+        float ms = 0.f;
+        SMRT_HIP(hipEventElapsedTime(&ms, x->ev0, x->ev1));
+        *ms_per_sweep = ms / n_times;
+        check_sweep_flag(x);
+    });
+}

@@ -1,0 +1,112 @@
+// FP64 closure post-pass and low-order solver (lo.hip).
+#pragma once
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "smrt_internal.h"
+
+namespace smrt {
+
+// Owning device buffer.
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    int64_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void alloc(int64_t count) {
+        release();
+        n = count;
+        if (count > 0) {
+            hipError_t e = hipMalloc(&p, sizeof(T) * count);
+            if (e != hipSuccess) {
+                p = nullptr;
+                throw Error(SMRT_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(sizeof(T) * count) + " bytes failed");
+            }
+        }
+    }
+    void zero(hipStream_t s = nullptr) {
+        if (p) SMRT_HIP(hipMemsetAsync(p, 0, sizeof(T) * n, s));
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct Csr {
+    int nrows = 0, ncols = 0;
+    std::vector<int> rowptr, col;
+    std::vector<double> val;
+};
+
+struct DevCsr {
+    DevBuf<int> rp_, col_;
+    DevBuf<double> val_;
+    int *rp = nullptr, *col = nullptr;
+    double *val = nullptr;
+    int nrows = 0;
+    void upload(const Csr &m) {
+        nrows = m.nrows;
+        rp_.alloc(m.rowptr.size());
+        col_.alloc(std::max<size_t>(m.col.size(), 1));
+        val_.alloc(std::max<size_t>(m.val.size(), 1));
+        SMRT_HIP(hipMemcpy(rp_.p, m.rowptr.data(), sizeof(int) * m.rowptr.size(), hipMemcpyHostToDevice));
+        if (!m.col.empty()) {
+            SMRT_HIP(hipMemcpy(col_.p, m.col.data(), sizeof(int) * m.col.size(), hipMemcpyHostToDevice));
+            SMRT_HIP(hipMemcpy(val_.p, m.val.data(), sizeof(double) * m.val.size(), hipMemcpyHostToDevice));
+        }
+        rp = rp_.p;
+        col = col_.p;
+        val = val_.p;
+    }
+};
+
+struct ClosureArgs {
+    int dim, nx, ny, scheme;
+    double c, dt;
+    const double *hx, *hy;        // cell sizes
+    double alpha[2];
+    double Itot[4];               // per side: sum_g inflow intensity (isotropic)
+    double S1[4];                 // per side: sum_{Omega.n<0} w (Omega.n)
+    double S2[8];                 // per side, component: sum_{Omega.n<0} w Omega_a (Omega.n)
+    const double *mom;            // [27|8][nn]
+    const double *sigP, *sigF;    // [nn] at the outer iterate's T
+    const double *Estar, *Fstar;  // [nn], [nn][dim]
+    double *out;                  // [3+1+dim][nn]
+};
+void run_closures(hipStream_t s, const ClosureArgs &a);
+void run_eliminate(hipStream_t s, int nn, double a, double c, double dt, double rtol, int maxit, const double *cvn,
+                   const double *sigE, const double *sigP, const double *E, const double *Tstar, double *T, int *flags);
+
+void assemble_lo_operators(int dim, int nx, int ny, const std::vector<double> &xe, const std::vector<double> &ye,
+                           const double alpha[2], double c, Csr &D, Csr &DT, Csr &P, std::vector<double> &wnode);
+
+struct LoInputs {
+    double dt, eps_inner, cg_rtol, elim_rtol;
+    int max_inner, max_cg, max_elim;
+    const double *sigE, *sigF, *sigP, *qE, *qF;   // closure rows (qF: [dim][nn])
+    const double *cvn, *Tstar;
+};
+
+struct LoSolver {
+    int dim = 0, nn = 0;
+    double c = 1, a = 1;
+    DevCsr dD, dDT, dP;
+    DevBuf<double> wn, MFinv, DqF, jbase, diagE, rhs, Minv, r, z, p, Ap, Eold, Told, tmpF, part, sc;
+    DevBuf<int> flags;
+    void init(int dim, int nx, int ny, const std::vector<double> &xe, const std::vector<double> &ye,
+              const double alpha[2], double c, double a);
+    double dot(hipStream_t s, const double *x, const double *y, const double *cdiff, int slot, bool accumulate);
+    double fetch(hipStream_t s, int slot);
+    void schur(hipStream_t s, const double *x, double *y);
+    int pcg(hipStream_t s, double *x, double rtol, int maxit);
+    smrt_status solve(hipStream_t s, const LoInputs &in, double *E, double *F, double *T, smrt_step_stats *st,
+                      std::string &err);
+};
+
+}  // namespace smrt

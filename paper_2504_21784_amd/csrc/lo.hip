@@ -1,0 +1,576 @@
+// FP64 closure post-pass and low-order (LO) solve of the SM method (gfx950).
+//
+// Closures (Sec. 2 gray collapse; Sec. 4 consistent and independent LDG
+// sources).  Per node, from the HO moments of the last sweep:
+//   sigma_E = sum_g sigma_g phi_g / phi   (sigma_P where phi = 0),
+//   sigma_F, sigma_P from the Rosseland / Planck fractions at the outer
+//   iterate's temperature (computed by the source kernel),
+//   qE = w E*/dt - 2 sum_bfaces fw F_in + R0_cons,
+//   qF = w F*/(c dt) - sum_bfaces fw P_in (consistent) + R1,
+// where, with n = +e_ax from the lower cell K1 to the upper cell K2 and the
+// LDG upwinding s = +1 (upwind vector (1,1)),
+//   R0_cons = fw [u] ( (s/2)[F.n] - [beta]/2 )                  (interior)
+//           - fw ( J+ - c alpha E_HO - F_in )                    (boundary)
+//   R1      = w (sigma_F F - sum_g sigma_g F_g) + sum_m w (T_m grad phi)(x_m)
+//           - fw [v] . {T n}                                     (both schemes)
+//           - fw [v] . ( [(Pi+ - Pi-) n]/2 + (c/6) s n [E] )     (consistent)
+//           + fw ( (c/3) n E_HO - Pi+ n )                         (consistent, boundary)
+// T = Pi - (phi/3) I, beta = sum w (|Omega.n| - alpha) I, Pi = sum w Omega Omega I.
+// Half-range sums come from the quadrant moments of the sweep.
+//
+// Low-order Newton with nonlinear elimination of T (Sec. 5), lumped:
+//   S = (c/3) D M_F^-1 D^T + M_E + P - diag(dB dBt^-1 M_a)  (SPD),
+//   S E = qE + B(T0) - D M_F^-1 qF + dB dBt^-1 (qT - Bt(T0)),
+//   F = M_F^-1 (qF + (c/3) D^T E),
+//   cv T/dt + sigma_P a c T^4 = c sigma_E E + cv T*/dt at every node,
+// with Jacobi-preconditioned CG on S in CSR form; D (divergence) and P
+// (penalty, kappa = alpha/2) are geometric and assembled once on the host.
+#include <cmath>
+
+#include "lo.h"
+
+namespace smrt {
+
+// ---------------------------------------------------------------------------
+// Closure kernels
+// ---------------------------------------------------------------------------
+struct NodeMom2D {
+    double phi, F[2], Pi[2][2];     // full range
+    double Fp[2][2];                // Fp[ax][a]: sum over Omega_ax > 0 of w Omega_a I
+    double Pp[2][2];                // Pp[ax][a]: sum over Omega_ax > 0 of w Omega_a Omega_ax I
+    double sphi, sF[2];
+};
+
+__device__ inline NodeMom2D load_mom2d(const double *mom, int nn, int n) {
+    double m[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) m[k] = mom[(int64_t)k * nn + n];
+    NodeMom2D r;
+    r.phi = m[0] + m[6] + m[12] + m[18];
+    r.F[0] = m[1] + m[7] + m[13] + m[19];
+    r.F[1] = m[2] + m[8] + m[14] + m[20];
+    r.Pi[0][0] = m[3] + m[9] + m[15] + m[21];
+    r.Pi[0][1] = r.Pi[1][0] = m[4] + m[10] + m[16] + m[22];
+    r.Pi[1][1] = m[5] + m[11] + m[17] + m[23];
+    // mu > 0: quadrants 0, 3; eta > 0: quadrants 0, 1
+    r.Fp[0][0] = m[1] + m[19];
+    r.Fp[0][1] = m[2] + m[20];
+    r.Fp[1][0] = m[1] + m[7];
+    r.Fp[1][1] = m[2] + m[8];
+    r.Pp[0][0] = m[3] + m[21];   // Pi_xx over mu > 0
+    r.Pp[0][1] = m[4] + m[22];   // Pi_yx over mu > 0
+    r.Pp[1][0] = m[4] + m[10];   // Pi_xy over eta > 0
+    r.Pp[1][1] = m[5] + m[11];   // Pi_yy over eta > 0
+    r.sphi = m[24];
+    r.sF[0] = m[25];
+    r.sF[1] = m[26];
+    return r;
+}
+
+__device__ inline double Tten(const NodeMom2D &m, int a, int b) { return m.Pi[a][b] - (a == b ? m.phi / 3.0 : 0.0); }
+
+__global__ void k_closures2d(ClosureArgs A) {
+    const int nn = 4 * A.nx * A.ny;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const int cell = n >> 2, l = n & 3, lx = l & 1, ly = l >> 1;
+    const int i = cell % A.nx, j = cell / A.nx;
+    const double hx = A.hx[i], hy = A.hy[j], w = 0.25 * hx * hy, c = A.c;
+    const bool cons = A.scheme == 0;
+    const NodeMom2D me = load_mom2d(A.mom, nn, n);
+    const NodeMom2D px = load_mom2d(A.mom, nn, n ^ 1), py = load_mom2d(A.mom, nn, n ^ 2);
+    const double E = me.phi / c;
+    const double sigP = A.sigP[n], sigF = A.sigF[n];
+    const double sigE = me.phi > 0.0 ? me.sphi / me.phi : sigP;
+    double qE = w * A.Estar[n] / A.dt;
+    double qF[2] = {w * A.Fstar[2 * n] / (c * A.dt), w * A.Fstar[2 * n + 1] / (c * A.dt)};
+    double r0 = 0.0, r1[2];
+    // multigroup additive correction and volume closure sum_m w (T_m grad phi_l)(x_m)
+    const double sx = lx ? 1.0 : -1.0, sy = ly ? 1.0 : -1.0;
+    for (int a = 0; a < 2; ++a) {
+        r1[a] = w * (sigF * me.F[a] - me.sF[a]);
+        r1[a] += w * (sx / hx) * (Tten(me, a, 0) + Tten(px, a, 0)) + w * (sy / hy) * (Tten(me, a, 1) + Tten(py, a, 1));
+    }
+    for (int ax = 0; ax < 2; ++ax) {
+        const int sd = ax == 0 ? lx : ly;
+        const double fw = ax == 0 ? 0.5 * hy : 0.5 * hx;
+        const double sgn = sd ? 1.0 : -1.0;
+        const double alpha = A.alpha[ax];
+        int nbc = -1;
+        if (ax == 0) { const int ii = i + (sd ? 1 : -1); if (ii >= 0 && ii < A.nx) nbc = ii + A.nx * j; }
+        else { const int jj = j + (sd ? 1 : -1); if (jj >= 0 && jj < A.ny) nbc = i + A.nx * jj; }
+        if (nbc >= 0) {
+            const int nbn = 4 * nbc + (l ^ (ax == 0 ? 1 : 2));
+            const NodeMom2D nb = load_mom2d(A.mom, nn, nbn);
+            const NodeMom2D &m1 = sd ? me : nb;   // lower cell K1
+            const NodeMom2D &m2 = sd ? nb : me;   // upper cell K2
+            const double jmp = sgn;
+            const double s = 1.0;
+            if (cons) {
+                const double b1 = (2.0 * m1.Fp[ax][ax] - m1.F[ax]) - alpha * m1.phi;
+                const double b2 = (2.0 * m2.Fp[ax][ax] - m2.F[ax]) - alpha * m2.phi;
+                r0 += fw * jmp * (0.5 * s * (m1.F[ax] - m2.F[ax]) - 0.5 * (b1 - b2));
+            }
+            for (int a = 0; a < 2; ++a) {
+                double v = -0.5 * (Tten(m1, a, ax) + Tten(m2, a, ax));
+                if (cons) {
+                    const double d1 = 2.0 * m1.Pp[ax][a] - m1.Pi[a][ax];
+                    const double d2 = 2.0 * m2.Pp[ax][a] - m2.Pi[a][ax];
+                    v += -0.5 * (d1 - d2) - (c / 6.0) * s * (a == ax ? 1.0 : 0.0) * (m1.phi - m2.phi) / c;
+                }
+                r1[a] += fw * jmp * v;
+            }
+        } else {
+            const int side = 2 * ax + sd;
+            const double Itot = A.Itot[side];
+            const double Fin = Itot * A.S1[side];
+            qE += -2.0 * fw * Fin;
+            if (cons) {
+                const double Jp = sd ? me.Fp[ax][ax] : -(me.F[ax] - me.Fp[ax][ax]);
+                r0 += -fw * (Jp - c * alpha * E - Fin);
+                for (int a = 0; a < 2; ++a) {
+                    const double Pin = Itot * A.S2[2 * side + a];
+                    const double Ppn = sd ? me.Pp[ax][a] : -(me.Pi[a][ax] - me.Pp[ax][a]);
+                    qF[a] += -fw * Pin;
+                    r1[a] += fw * ((c / 3.0) * (a == ax ? sgn : 0.0) * E - Ppn);
+                }
+            }
+        }
+    }
+    A.out[n] = sigE;
+    A.out[(int64_t)nn + n] = sigF;
+    A.out[(int64_t)2 * nn + n] = sigP;
+    A.out[(int64_t)3 * nn + n] = qE + r0;
+    A.out[(int64_t)4 * nn + n] = qF[0] + r1[0];
+    A.out[(int64_t)5 * nn + n] = qF[1] + r1[1];
+}
+
+__global__ void k_closures1d(ClosureArgs A) {
+    const int nn = 2 * A.nx;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const int cell = n >> 1, l = n & 1;
+    const double h = A.hx[cell], w = 0.5 * h, c = A.c;
+    const bool cons = A.scheme == 0;
+    struct M1 { double phi, F, Pi, Fp, Pp, sphi, sF; };
+    auto get = [&](int k) {
+        M1 r;
+        double m[8];
+        for (int q = 0; q < 8; ++q) m[q] = A.mom[(int64_t)q * nn + k];
+        r.phi = m[0] + m[3]; r.F = m[1] + m[4]; r.Pi = m[2] + m[5]; r.Fp = m[1]; r.Pp = m[2];
+        r.sphi = m[6]; r.sF = m[7];
+        return r;
+    };
+    const M1 me = get(n), pr = get(n ^ 1);
+    const double E = me.phi / c;
+    const double sigP = A.sigP[n], sigF = A.sigF[n];
+    const double sigE = me.phi > 0.0 ? me.sphi / me.phi : sigP;
+    double qE = w * A.Estar[n] / A.dt, qF = w * A.Fstar[n] / (c * A.dt);
+    const double s = 1.0, sl = l ? 1.0 : -1.0, alpha = A.alpha[0];
+    double r0 = 0.0;
+    double r1 = w * (sigF * me.F - me.sF) + w * (sl / h) * ((me.Pi - me.phi / 3.0) + (pr.Pi - pr.phi / 3.0));
+    const int cc = cell + (l ? 1 : -1);
+    if (cc >= 0 && cc < A.nx) {
+        const M1 nb = get(2 * cc + (l ^ 1));
+        const M1 &m1 = l ? me : nb;
+        const M1 &m2 = l ? nb : me;
+        if (cons) {
+            const double b1 = (2.0 * m1.Fp - m1.F) - alpha * m1.phi, b2 = (2.0 * m2.Fp - m2.F) - alpha * m2.phi;
+            r0 += sl * (0.5 * s * (m1.F - m2.F) - 0.5 * (b1 - b2));
+        }
+        double v = -0.5 * ((m1.Pi - m1.phi / 3.0) + (m2.Pi - m2.phi / 3.0));
+        if (cons) v += -0.5 * ((2.0 * m1.Pp - m1.Pi) - (2.0 * m2.Pp - m2.Pi)) - (s / 6.0) * (m1.phi - m2.phi);
+        r1 += sl * v;
+    } else {
+        const int side = l;
+        const double Fin = A.Itot[side] * A.S1[side];
+        qE += -2.0 * Fin;
+        if (cons) {
+            const double Jp = l ? me.Fp : -(me.F - me.Fp);
+            r0 += -(Jp - c * alpha * E - Fin);
+            const double Pin = A.Itot[side] * A.S2[2 * side];
+            const double Ppn = l ? me.Pp : -(me.Pi - me.Pp);
+            qF += -Pin;
+            r1 += (c / 3.0) * sl * E - Ppn;
+        }
+    }
+    A.out[n] = sigE;
+    A.out[(int64_t)nn + n] = sigF;
+    A.out[(int64_t)2 * nn + n] = sigP;
+    A.out[(int64_t)3 * nn + n] = qE + r0;
+    A.out[(int64_t)4 * nn + n] = qF + r1;
+}
+
+void run_closures(hipStream_t s, const ClosureArgs &a) {
+    const int nn = a.dim == 2 ? 4 * a.nx * a.ny : 2 * a.nx;
+    if (a.dim == 2) hipLaunchKernelGGL(k_closures2d, dim3((nn + 127) / 128), dim3(128), 0, s, a);
+    else hipLaunchKernelGGL(k_closures1d, dim3((nn + 127) / 128), dim3(128), 0, s, a);
+    SMRT_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// CSR assembly of the lumped LDG divergence D and penalty P (host).
+// D row n, column (m, a) = m*dim + a, such that (D F)_n equals the lumped
+//   - sum_m w grad(phi_n)(x_m) . F_m + interior-face upwinded fluxes.
+// On a rectangle grad(phi_l)(x_m) is nonzero only for m = l and the partner
+// node across the cell in that direction, with value +-1/h.
+// ---------------------------------------------------------------------------
+static void csr_from_rows(const std::vector<std::vector<std::pair<int, double>>> &rows, Csr &m, int ncols) {
+    m.nrows = (int)rows.size();
+    m.ncols = ncols;
+    m.rowptr.assign(m.nrows + 1, 0);
+    m.col.clear();
+    m.val.clear();
+    for (int r = 0; r < m.nrows; ++r) {
+        // merge duplicate columns, keep column order of first appearance sorted
+        std::vector<std::pair<int, double>> e = rows[r];
+        std::sort(e.begin(), e.end(), [](auto &x, auto &y) { return x.first < y.first; });
+        for (size_t k = 0; k < e.size(); ++k) {
+            if (!m.col.empty() && (int)m.col.size() > m.rowptr[r] && m.col.back() == e[k].first) m.val.back() += e[k].second;
+            else { m.col.push_back(e[k].first); m.val.push_back(e[k].second); }
+        }
+        m.rowptr[r + 1] = (int)m.col.size();
+    }
+}
+
+void assemble_lo_operators(int dim, int nx, int ny, const std::vector<double> &xe, const std::vector<double> &ye,
+                           const double alpha[2], double c, Csr &D, Csr &DT, Csr &P, std::vector<double> &wnode) {
+    const int npc = dim == 2 ? 4 : 2;
+    const int nyy = dim == 2 ? ny : 1;
+    const int nn = nx * nyy * npc;
+    std::vector<std::vector<std::pair<int, double>>> Dr(nn), Pr(nn);
+    wnode.assign(nn, 0.0);
+    for (int j = 0; j < nyy; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int cell = i + nx * j;
+            const double hx = xe[i + 1] - xe[i], hy = dim == 2 ? ye[j + 1] - ye[j] : 1.0;
+            const double w = hx * hy / npc;
+            for (int l = 0; l < npc; ++l) {
+                const int n = npc * cell + l;
+                wnode[n] = w;
+                const int lx = l & 1, ly = l >> 1;
+                // volume: x derivative couples l and its x partner (same y level)
+                const double sx = lx ? 1.0 : -1.0;
+                Dr[n].push_back({n * dim + 0, -w * sx / hx});
+                Dr[n].push_back({(npc * cell + (l ^ 1)) * dim + 0, -w * sx / hx});
+                if (dim == 2) {
+                    const double sy = ly ? 1.0 : -1.0;
+                    Dr[n].push_back({n * dim + 1, -w * sy / hy});
+                    Dr[n].push_back({(npc * cell + (l ^ 2)) * dim + 1, -w * sy / hy});
+                }
+                for (int ax = 0; ax < dim; ++ax) {
+                    const int sd = ax == 0 ? lx : ly;
+                    const double fw = dim == 1 ? 1.0 : (ax == 0 ? 0.5 * hy : 0.5 * hx);
+                    int nbc = -1;
+                    if (ax == 0) { const int ii = i + (sd ? 1 : -1); if (ii >= 0 && ii < nx) nbc = ii + nx * j; }
+                    else { const int jj = j + (sd ? 1 : -1); if (jj >= 0 && jj < ny) nbc = i + nx * jj; }
+                    const double cal = c * alpha[ax];
+                    if (nbc < 0) {
+                        Pr[n].push_back({n, fw * cal});
+                        continue;
+                    }
+                    const int nbn = npc * nbc + (l ^ (ax == 0 ? 1 : 2));
+                    // upwinding s = +1: the flux across the face is the lower cell's F.n
+                    const int lower = sd ? n : nbn;
+                    const double jmp = sd ? 1.0 : -1.0;
+                    Dr[n].push_back({lower * dim + ax, fw * jmp});
+                    Pr[n].push_back({n, 0.5 * fw * cal});
+                    Pr[n].push_back({nbn, -0.5 * fw * cal});
+                }
+            }
+        }
+    csr_from_rows(Dr, D, nn * dim);
+    csr_from_rows(Pr, P, nn);
+    std::vector<std::vector<std::pair<int, double>>> Tr(nn * dim);
+    for (int r = 0; r < nn; ++r)
+        for (int k = D.rowptr[r]; k < D.rowptr[r + 1]; ++k) Tr[D.col[k]].push_back({r, D.val[k]});
+    csr_from_rows(Tr, DT, nn);
+}
+
+// ---------------------------------------------------------------------------
+// LO kernels
+// ---------------------------------------------------------------------------
+__global__ void k_lo_outer_setup(int nn, int dim, double icdt, const double *wn, const double *sigF, const double *qF,
+                                 double *MFinv, double *tmpF) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const double mi = 1.0 / (wn[n] * (sigF[n] + icdt));
+    MFinv[n] = mi;
+    for (int a = 0; a < dim; ++a) tmpF[dim * n + a] = qF[(int64_t)a * nn + n] * mi;
+}
+
+// y = A x (CSR), optionally y = alpha A x + beta y
+__global__ void k_spmv(int nrows, const int *rp, const int *col, const double *val, const double *x, double *y) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    double s = 0.0;
+    for (int k = rp[r]; k < rp[r + 1]; ++k) s += val[k] * x[col[k]];
+    y[r] = s;
+}
+
+// dDD_n = (c/3) sum_k D_nk^2 MFinv(col node) + P_nn
+__global__ void k_jacobi_base(int nn, int dim, double c3, const int *drp, const int *dcol, const double *dval,
+                              const int *prp, const int *pcol, const double *pval, const double *MFinv, double *base) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double s = 0.0;
+    for (int k = drp[n]; k < drp[n + 1]; ++k) s += dval[k] * dval[k] * MFinv[dcol[k] / dim];
+    double p = 0.0;
+    for (int k = prp[n]; k < prp[n + 1]; ++k)
+        if (pcol[k] == n) p += pval[k];
+    base[n] = c3 * s + p;
+}
+
+// Newton linearisation at T0: diagE, rhs, Jacobi inverse
+__global__ void k_newton_prep(int nn, double a, double c, double dt, const double *wn, const double *cvn,
+                              const double *T0, const double *Tstar, const double *sigE, const double *sigP,
+                              const double *qE, const double *DqF, const double *jbase, double *diagE, double *rhs,
+                              double *Minv) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const double w = wn[n], t = T0[n];
+    const double dB = w * 4.0 * sigP[n] * a * c * t * t * t;
+    const double dBt = w * cvn[n] / dt + dB;
+    const double B0 = w * sigP[n] * a * c * t * t * t * t;
+    const double Bt0 = w * cvn[n] * t / dt + B0;
+    const double Ma = w * c * sigE[n];
+    const double qT = w * cvn[n] * Tstar[n] / dt;
+    const double de = w * c * (sigE[n] + 1.0 / (c * dt)) - dB * Ma / dBt;
+    diagE[n] = de;
+    rhs[n] = qE[n] + B0 - DqF[n] + dB / dBt * (qT - Bt0);
+    Minv[n] = 1.0 / (jbase[n] + de);
+}
+
+// tmpF = (c/3) MFinv * (D^T x)  (D^T rows are F dofs)
+__global__ void k_dt_scaled(int nrows, int dim, double c3, const int *rp, const int *col, const double *val,
+                            const double *x, const double *MFinv, double *tmpF) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    double s = 0.0;
+    for (int k = rp[r]; k < rp[r + 1]; ++k) s += val[k] * x[col[k]];
+    tmpF[r] = c3 * MFinv[r / dim] * s;
+}
+
+// y = D tmpF + P x + diagE x
+__global__ void k_schur_rows(int nn, const int *drp, const int *dcol, const double *dval, const int *prp, const int *pcol,
+                             const double *pval, const double *tmpF, const double *x, const double *diagE, double *y) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double s = 0.0;
+    for (int k = drp[n]; k < drp[n + 1]; ++k) s += dval[k] * tmpF[dcol[k]];
+    for (int k = prp[n]; k < prp[n + 1]; ++k) s += pval[k] * x[pcol[k]];
+    y[n] = s + diagE[n] * x[n];
+}
+
+// deterministic block reduction of sum_i a_i b_i (b == nullptr: sum a_i^2 of (a - c))
+constexpr int RED_BLOCKS = 256, RED_THREADS = 256;
+__global__ void k_dot_partial(int n, const double *a, const double *b, const double *cdiff, double *part) {
+    __shared__ double sh[RED_THREADS];
+    double s = 0.0;
+    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
+        if (cdiff) { const double d = a[i] - cdiff[i]; s += d * d; }
+        else s += a[i] * (b ? b[i] : a[i]);
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = RED_THREADS / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_dot_finish(const double *part, double *out, int slot, int accumulate) {
+    __shared__ double sh[RED_BLOCKS];
+    sh[threadIdx.x] = part[threadIdx.x];
+    __syncthreads();
+    for (int k = RED_BLOCKS / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[slot] = accumulate ? out[slot] + sh[0] : sh[0];
+}
+
+// CG vector updates with device-side scalars: sc[0]=rz, sc[1]=pAp, sc[2]=rr, sc[3]=rz_new
+__global__ void k_cg_xr(int n, const double *sc, const double *p, const double *Ap, double *x, double *r,
+                        const double *Minv, double *z) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double al = sc[0] / sc[1];
+    x[i] += al * p[i];
+    r[i] -= al * Ap[i];
+    z[i] = Minv[i] * r[i];
+}
+__global__ void k_cg_p(int n, const double *sc, const double *z, double *p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    p[i] = z[i] + (sc[3] / sc[0]) * p[i];
+}
+__global__ void k_cg_init(int n, const double *b, const double *Ax, double *r, const double *Minv, double *z, double *p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    r[i] = b[i] - Ax[i];
+    z[i] = Minv[i] * r[i];
+    p[i] = z[i];
+}
+__global__ void k_shift(double *sc) { sc[0] = sc[3]; }
+
+// F = MFinv (qF + (c/3) D^T E)  (qF rows [a][n], F node-major [n][a])
+__global__ void k_backsub(int nn, int dim, double c3, const int *rp, const int *col, const double *val, const double *E,
+                          const double *qF, const double *MFinv, double *F) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nn * dim) return;
+    double s = 0.0;
+    for (int k = rp[r]; k < rp[r + 1]; ++k) s += val[k] * E[col[k]];
+    const int n = r / dim, a = r % dim;
+    F[r] = MFinv[n] * (qF[(int64_t)a * nn + n] + c3 * s);
+}
+
+// pointwise energy balance: cv T/dt + sigP a c T^4 = c sigE E + cv T*/dt
+// (Newton safeguarded by bisection on [0, rhs dt/cv]; stop at |f| <= rtol |rhs|)
+__global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, int maxit, const double *cvn,
+                            const double *sigE, const double *sigP, const double *E, const double *Tstar, double *T,
+                            int *flags) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const double cv_dt = cvn[n] / dt, k4 = sigP[n] * a * c;
+    const double rhs = c * sigE[n] * E[n] + cv_dt * Tstar[n];
+    if (!(rhs > 0.0)) { atomicOr(&flags[0], 1); return; }
+    double lo = 0.0, hi = rhs / cv_dt, t = T[n];
+    if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
+    int it = 0;
+    for (; it < maxit; ++it) {
+        const double f = cv_dt * t + k4 * t * t * t * t - rhs;
+        if (fabs(f) <= rtol * fabs(rhs)) break;
+        if (f > 0) hi = t; else lo = t;
+        double tn = t - f / (cv_dt + 4.0 * k4 * t * t * t);
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        t = tn;
+    }
+    T[n] = t;
+    atomicMax(&flags[1], it);
+    if (it == maxit) atomicOr(&flags[2], 1);
+}
+
+__global__ void k_zero4(int *p) { p[threadIdx.x] = 0; }
+
+void run_eliminate(hipStream_t s, int nn, double a, double c, double dt, double rtol, int maxit, const double *cvn,
+                   const double *sigE, const double *sigP, const double *E, const double *Tstar, double *T, int *flags) {
+    hipLaunchKernelGGL(k_eliminate, dim3((nn + 255) / 256), dim3(256), 0, s, nn, a, c, dt, rtol, maxit, cvn, sigE, sigP,
+                       E, Tstar, T, flags);
+}
+
+// ---------------------------------------------------------------------------
+// host driver of the LO solve
+// ---------------------------------------------------------------------------
+static inline int nb(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
+
+void LoSolver::init(int dim_, int nx, int ny, const std::vector<double> &xe, const std::vector<double> &ye,
+                    const double alpha[2], double c_, double a_) {
+    dim = dim_;
+    c = c_;
+    a = a_;
+    Csr D, DT, P;
+    std::vector<double> wv;
+    assemble_lo_operators(dim, nx, ny, xe, ye, alpha, c, D, DT, P, wv);
+    nn = D.nrows;
+    dD.upload(D);
+    dDT.upload(DT);
+    dP.upload(P);
+    wn.alloc(nn);
+    SMRT_HIP(hipMemcpy(wn.p, wv.data(), sizeof(double) * nn, hipMemcpyHostToDevice));
+    for (auto *v : {&MFinv, &DqF, &jbase, &diagE, &rhs, &Minv, &r, &z, &p, &Ap, &Eold, &Told}) v->alloc(nn);
+    tmpF.alloc((int64_t)nn * dim);
+    part.alloc(RED_BLOCKS);
+    sc.alloc(8);
+    flags.alloc(4);
+}
+
+double LoSolver::dot(hipStream_t s, const double *x, const double *y, const double *cdiff, int slot, bool accumulate) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, nn, x, y, cdiff, part.p);
+    hipLaunchKernelGGL(k_dot_finish, dim3(1), dim3(RED_BLOCKS), 0, s, part.p, sc.p, slot, accumulate ? 1 : 0);
+    return 0.0;
+}
+
+double LoSolver::fetch(hipStream_t s, int slot) {
+    double v;
+    SMRT_HIP(hipMemcpyAsync(&v, sc.p + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+    SMRT_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+void LoSolver::schur(hipStream_t s, const double *x, double *y) {
+    hipLaunchKernelGGL(k_dt_scaled, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn * dim, dim, c / 3.0, dDT.rp, dDT.col,
+                       dDT.val, x, MFinv.p, tmpF.p);
+    hipLaunchKernelGGL(k_schur_rows, dim3(nb(nn)), dim3(256), 0, s, nn, dD.rp, dD.col, dD.val, dP.rp, dP.col, dP.val,
+                       tmpF.p, x, diagE.p, y);
+}
+
+int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
+    schur(s, x, Ap.p);
+    hipLaunchKernelGGL(k_cg_init, dim3(nb(nn)), dim3(256), 0, s, nn, rhs.p, Ap.p, r.p, Minv.p, z.p, p.p);
+    dot(s, rhs.p, nullptr, nullptr, 4, false);     // |b|^2
+    dot(s, r.p, z.p, nullptr, 0, false);           // rz
+    dot(s, r.p, nullptr, nullptr, 2, false);       // rr
+    double bb = fetch(s, 4);
+    const double tol2 = rtol * rtol * (bb > 0 ? bb : 1.0);
+    double rr = fetch(s, 2);
+    int it = 0;
+    while (it < maxit && rr > tol2) {
+        schur(s, p.p, Ap.p);
+        dot(s, p.p, Ap.p, nullptr, 1, false);
+        hipLaunchKernelGGL(k_cg_xr, dim3(nb(nn)), dim3(256), 0, s, nn, sc.p, p.p, Ap.p, x, r.p, Minv.p, z.p);
+        dot(s, r.p, z.p, nullptr, 3, false);
+        hipLaunchKernelGGL(k_cg_p, dim3(nb(nn)), dim3(256), 0, s, nn, sc.p, z.p, p.p);
+        hipLaunchKernelGGL(k_shift, dim3(1), dim3(1), 0, s, sc.p);
+        dot(s, r.p, nullptr, nullptr, 2, false);
+        rr = fetch(s, 2);
+        ++it;
+    }
+    return it;
+}
+
+smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double *F, double *T, smrt_step_stats *st,
+                            std::string &err) {
+    const double icdt = 1.0 / (c * in.dt);
+    hipLaunchKernelGGL(k_lo_outer_setup, dim3(nb(nn)), dim3(256), 0, s, nn, dim, icdt, wn.p, in.sigF, in.qF, MFinv.p, tmpF.p);
+    hipLaunchKernelGGL(k_spmv, dim3(nb(nn)), dim3(256), 0, s, nn, dD.rp, dD.col, dD.val, tmpF.p, DqF.p);
+    hipLaunchKernelGGL(k_jacobi_base, dim3(nb(nn)), dim3(256), 0, s, nn, dim, c / 3.0, dD.rp, dD.col, dD.val, dP.rp,
+                       dP.col, dP.val, MFinv.p, jbase.p);
+    double first = -1.0;
+    smrt_status status = SMRT_OK;
+    for (int m = 1; m <= in.max_inner; ++m) {
+        SMRT_HIP(hipMemcpyAsync(Eold.p, E, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+        SMRT_HIP(hipMemcpyAsync(Told.p, T, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_newton_prep, dim3(nb(nn)), dim3(256), 0, s, nn, a, c, in.dt, wn.p, in.cvn, T, in.Tstar,
+                           in.sigE, in.sigP, in.qE, DqF.p, jbase.p, diagE.p, rhs.p, Minv.p);
+        st->cg_total += pcg(s, E, in.cg_rtol, in.max_cg);
+        hipLaunchKernelGGL(k_backsub, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn, dim, c / 3.0, dDT.rp, dDT.col,
+                           dDT.val, E, in.qF, MFinv.p, F);
+        hipLaunchKernelGGL(k_zero4, dim3(1), dim3(4), 0, s, flags.p);
+        hipLaunchKernelGGL(k_eliminate, dim3(nb(nn)), dim3(256), 0, s, nn, a, c, in.dt, in.elim_rtol, in.max_elim,
+                           in.cvn, in.sigE, in.sigP, E, in.Tstar, T, flags.p);
+        int fl[4];
+        SMRT_HIP(hipMemcpyAsync(fl, flags.p, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+        dot(s, T, nullptr, Told.p, 5, false);
+        dot(s, E, nullptr, Eold.p, 5, true);
+        const double diff = std::sqrt(fetch(s, 5));
+        st->inner_total++;
+        if (fl[1] > st->elim_max) st->elim_max = fl[1];
+        if (fl[0]) {
+            err = "no positive temperature root in the energy balance";
+            status = SMRT_E_NONPHYSICAL;
+            break;
+        }
+        if (!std::isfinite(diff)) {
+            err = "non-finite low-order iterate";
+            status = SMRT_E_NONPHYSICAL;
+            break;
+        }
+        if (m == 1) first = diff;
+        if (diff == 0.0 || (m > 1 && diff < in.eps_inner * first)) break;
+        if (m == in.max_inner) st->hit_max = 1;
+    }
+    return status;
+}
+
+}  // namespace smrt

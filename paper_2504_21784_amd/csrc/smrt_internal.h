@@ -1,0 +1,76 @@
+// Internal declarations of the MI355X SM-TRT library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/smrt.h"
+
+namespace smrt {
+
+constexpr int BAND_ROWS = 16;       // rows of cells per band (lanes per channel)
+constexpr int CHANNELS = 4;         // (angle, group) channels per wave (64 / BAND_ROWS)
+constexpr int NMOM2D = 9;           // per node per quadrant: 6 quadrant sums + 3 sigma-weighted
+constexpr int PART_PER_CELL = 4 * NMOM2D;   // partial moments per cell per chunk
+constexpr int SPIN_LIMIT = 1 << 20;          // bounded wait on a band trace
+constexpr int MAX_WG_THREADS = 512;          // sweep workgroups: at most 8 waves (256 VGPRs each)
+
+#define SMRT_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) throw smrt::Error(SMRT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Error {
+    smrt_status st;
+    std::string msg;
+    Error(smrt_status s, std::string m) : st(s), msg(std::move(m)) {}
+};
+
+// Device-side description of one 2D sweep (one problem).
+struct Sweep2DArgs {
+    int nx, ny, G, nbands, NT;       // NT = nx + BAND_ROWS - 1 steps per band
+    int NW, K, R, NQC;               // waves/WG, pairs/lane, pairs/chunk, (quadrant,chunk) count
+    int n_wg;                        // workgroups of this launch (NQC * nbands)
+    int NB;                          // boundary face nodes
+    const int *qc_quad;              // [NQC] quadrant of each chunk
+    const int2 *slot_pair;           // [NQC*R] (direction, group) or (-1,-1)
+    const void *dirs;                // per direction: real[8] = mu, eta, w, w*mu, w*eta, w*mu^2, w*mu*eta, w*eta^2
+    const void *hx, *hy;             // real[nx], real[ny]
+    const void *sig2;                // real2 [G][cell] = (sigma_t, sigma)
+    const void *qiso;                // real [G][cell][4] natural node order
+    const void *psi_prev;            // internal layout or nullptr
+    void *psi_out;                   // internal layout
+    const void *inflow;              // real [d][G][NB]
+    double inv_c_dt;
+    void *part;                      // real [NQC][nbands][NT][16][36]
+    uint64_t *trace;                 // [NQC][nbands][R][nx][2 * words]
+    int *ctr;                        // [4]: ticket, done, epoch, error flag
+};
+
+// Internal angular-flux layout (both precisions): [d][g][band][t][r][4 canonical nodes].
+__host__ __device__ inline int64_t psi_slab(int nx, int ny) {
+    int nb = (ny + BAND_ROWS - 1) / BAND_ROWS;
+    return (int64_t)nb * (nx + BAND_ROWS - 1) * BAND_ROWS * 4;
+}
+
+template <typename real>
+void launch_sweep2d(const Sweep2DArgs &a, hipStream_t s);
+
+struct Sweep1DArgs {
+    int nx, G, nang;
+    const void *mu_w;       // real[2*nang]: mu, w
+    const void *hx;
+    const void *sig2;       // real2 [G][cell]
+    const void *qiso;       // real [G][cell][2]
+    const void *psi_prev;   // [d][g][node]
+    void *psi_out;
+    const void *inflow;     // [d][G][2]
+    double inv_c_dt;
+};
+template <typename real>
+void launch_sweep1d(const Sweep1DArgs &a, hipStream_t s);
+
+}  // namespace smrt

@@ -1,0 +1,40 @@
+// Host launchers of the table, conversion and 1D kernels (tables.hip).
+#pragma once
+#include "smrt_internal.h"
+
+namespace smrt {
+
+constexpr int NBERN = 24;   // Bernoulli terms of the small-argument Planck series
+constexpr int MAXG = 64;    // largest group count
+
+void upload_bernoulli(const double *coef);
+template <typename real>
+void run_opacity(hipStream_t s, int ncell, int npc, int G, const double *T, const int *region, int model,
+                 const double *sigma0, double lo, double hi, const double *nu, double icdt, double *sig, real *sig2);
+template <typename real>
+void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const double *nu, double a, double c,
+                const double *sig, real *qiso, double *sigP, double *sigF);
+void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
+                     double *psi);
+void run_side_inflow(hipStream_t s, int nsides, int G, const double *nu, double a, double c, const int *kind,
+                     const double *Tb, const double *explicit_g, double *val);
+template <typename real>
+void run_fill_inflow(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *val, real *inflow);
+template <typename real>
+void run_copy_to(hipStream_t s, int64_t n, const double *src, real *dst);
+template <typename real>
+void run_qiso_to_internal(hipStream_t s, int nn, int G, int npc, const double *q, real *qi);
+template <typename real>
+void run_sig_to_internal(hipStream_t s, int ncell, int G, const double *st, const double *sg, real *sig2);
+template <typename real>
+void run_psi_to_internal(hipStream_t s, int nx, int ny, int G, int nang, const int *dq, const double *abi, real *in);
+template <typename real>
+void run_psi_from_internal(hipStream_t s, int nx, int ny, int G, int nang, const int *dq, const real *in, double *abi);
+template <typename real>
+void run_moments_finalize(hipStream_t s, int nx, int ny, int NQC, const int *qcq, const real *part, double *mom);
+template <typename real>
+void run_moments1d(hipStream_t s, int nx, int G, int nang, const real *mw, const double *sig, const real *psi, double *mom);
+void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *om, const double *w, double c,
+                const double *psi, double *E, double *F);
+
+}  // namespace smrt

@@ -1,0 +1,453 @@
+// Per-step and per-outer-iteration tables of the SM-TRT step (gfx950):
+//  * opacity table: sigma_g per cell from the cell-average temperature of
+//    the previous step (Sec. 3), and sigma_t = sigma + 1/(c dt) (Sec. 2);
+//  * emission source: q_iso = sigma_g a c T^4 b_g(T) / (4 pi) at every node
+//    (Eq. planck / black_body), plus the Planck- and Rosseland-collapsed
+//    gray opacities sigma_P and sigma_F at the node (Sec. 2, Eq. sigmaF);
+//  * boundary inflow table B_g(T_bdr)/(4 pi) or explicit values;
+//  * layout conversions between the ABI and the sweep's internal layout;
+//  * the 2D moment finalisation (sum of per-workgroup partials, FP64);
+//  * the 1D sweep (lanes = (angle, group) pairs) and its moments.
+//
+// The group fractions use the cumulative Planck function
+//   P(x) = 15/pi^4 int_0^x t^3/(e^t - 1) dt
+// evaluated with the Bernoulli-number series for x < 2 and the exponential
+// series 1 - 15/pi^4 sum_k e^{-kx}(x^3/k + 3x^2/k^2 + 6x/k^3 + 6/k^4) for
+// x >= 2 (both follow from expanding the integrand), and the Rosseland
+// cumulative R(x) = P(x) - 15/(4 pi^4) x^4/(e^x - 1) (integration by parts
+// of x^4 e^x/(e^x-1)^2).  b_g = P(x_{g+1}) - P(x_g), r_g likewise, with the
+// first lower bound at 0 and the last upper bound at infinity.
+#include "smrt_internal.h"
+#include "tables.h"
+
+namespace smrt {
+
+__constant__ double c_bern[NBERN];   // B_{2k} / ((2k)! (2k+3)), k = 1..NBERN
+
+__device__ double planck_cum(double x) {
+    constexpr double c15 = 15.0 / (M_PI * M_PI * M_PI * M_PI);
+    if (!(x > 0.0)) return 0.0;
+    if (x >= 1e300) return 1.0;
+    if (x < 2.0) {
+        // int_0^x t^3/(e^t-1) dt = x^3/3 - x^4/8 + sum_k B_2k x^(2k+3) / ((2k)! (2k+3))
+        const double x2 = x * x, x3 = x2 * x;
+        double s = 0.0, p = x3 * x2;   // x^(2k+3) for k = 1
+        for (int k = 0; k < NBERN; ++k) {
+            s += c_bern[k] * p;
+            p *= x2;
+        }
+        return c15 * (x3 / 3.0 - x3 * x / 8.0 + s);
+    }
+    double s = 0.0;
+    const double e = exp(-x);
+    double ek = e;
+    for (int k = 1; k <= 200; ++k) {
+        const double ik = 1.0 / k;
+        const double term = ek * (x * x * x * ik + 3.0 * x * x * ik * ik + 6.0 * x * ik * ik * ik + 6.0 * ik * ik * ik * ik);
+        s += term;
+        if (term < 1e-18 * s) break;
+        ek *= e;
+        if (ek == 0.0) break;
+    }
+    return 1.0 - c15 * s;
+}
+
+__device__ double rosseland_cum(double x) {
+    constexpr double c15_4 = 15.0 / (4.0 * M_PI * M_PI * M_PI * M_PI);
+    if (!(x > 0.0)) return 0.0;
+    if (x >= 1e300 || x > 700.0) return 1.0;
+    const double em = -expm1(-x);                  // 1 - e^{-x}
+    return planck_cum(x) - c15_4 * x * x * x * x * exp(-x) / em;
+}
+
+// group fractions at temperature T for all G groups
+__device__ void group_fractions(int G, const double *nu, double T, double *b, double *r) {
+    if (G == 1) {
+        b[0] = 1.0;
+        r[0] = 1.0;
+        return;
+    }
+    double Pl = 0.0, Rl = 0.0;
+    for (int g = 0; g < G; ++g) {
+        double Pu = 1.0, Ru = 1.0;
+        if (g < G - 1) {
+            const double x = nu[g + 1] / T;
+            Pu = planck_cum(x);
+            Ru = rosseland_cum(x);
+        }
+        b[g] = Pu - Pl;
+        r[g] = Ru - Rl;
+        Pl = Pu;
+        Rl = Ru;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Opacity table (once per step)
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void k_opacity(int ncell, int npc, int G, const double *T, const int *region, int model,
+                          const double *sigma0, double clip_lo, double clip_hi, const double *nu,
+                          double inv_c_dt, double *sig, real *sig2) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    double Tc = 0.0;
+    for (int l = 0; l < npc; ++l) Tc += T[npc * c + l];
+    Tc /= npc;
+    const int r = region[c];
+    for (int g = 0; g < G; ++g) {
+        double s;
+        if (model == 0) {
+            s = sigma0[r * G + g];
+        } else {
+            const double nb = sqrt(nu[g] * nu[g + 1]);
+            s = sigma0[r] / (nb * nb * nb * Tc * Tc * Tc);
+            s = fmin(fmax(s, clip_lo), clip_hi);
+        }
+        sig[(int64_t)c * G + g] = s;
+        sig2[2 * ((int64_t)g * ncell + c)] = (real)(s + inv_c_dt);
+        sig2[2 * ((int64_t)g * ncell + c) + 1] = (real)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Emission source and gray collapse (once per outer iteration)
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void k_source(int nn, int npc, int G, const double *T, const double *nu, double a, double c,
+                         const double *sig, real *qiso, double *sigP, double *sigF) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double b[MAXG], r[MAXG];
+    const double Tn = T[n];
+    group_fractions(G, nu, Tn, b, r);
+    const int cell = n / npc, l = n - cell * npc;
+    const int ncell = nn / npc;
+    const double B = a * c * Tn * Tn * Tn * Tn / (4.0 * M_PI);
+    double sb = 0, sbs = 0, sr = 0, srs = 0;
+    for (int g = 0; g < G; ++g) {
+        const double s = sig[(int64_t)cell * G + g];
+        qiso[((int64_t)g * ncell + cell) * npc + l] = (real)(s * B * b[g]);
+        sb += b[g];
+        sbs += b[g] * s;
+        sr += r[g];
+        srs += r[g] * s;
+    }
+    sigP[n] = sbs / sb;
+    sigF[n] = srs / sr;
+}
+
+// Isotropic equilibrium intensity B_g(T_n)/(4 pi) in the ABI layout [d][g][node]
+// (FP64) -- used to initialise a state.
+__global__ void k_equilibrium(int nn, int G, int nang, const double *T, const double *nu, double a, double c,
+                              double *psi) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double b[MAXG], r[MAXG];
+    group_fractions(G, nu, T[n], b, r);
+    const double B = a * c * pow(T[n], 4) / (4.0 * M_PI);
+    for (int d = 0; d < nang; ++d)
+        for (int g = 0; g < G; ++g) psi[((int64_t)d * G + g) * nn + n] = B * b[g];
+}
+
+// Side values of the isotropic inflow: val[side][g]
+__global__ void k_side_inflow(int G, const double *nu, double a, double c, const int *kind, const double *Tb,
+                              const double *explicit_g, double *val) {
+    const int side = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    double b[MAXG], r[MAXG];
+    for (int g = 0; g < G; ++g) val[side * G + g] = 0.0;
+    if (kind[side] == 1 && Tb[side] > 0.0) {
+        group_fractions(G, nu, Tb[side], b, r);
+        const double B = a * c * pow(Tb[side], 4) / (4.0 * M_PI);
+        for (int g = 0; g < G; ++g) val[side * G + g] = B * b[g];
+    } else if (kind[side] == 2) {
+        for (int g = 0; g < G; ++g) val[side * G + g] = explicit_g[side * G + g];
+    }
+}
+
+// General inflow table [d][g][NB] from the side values
+template <typename real>
+__global__ void k_fill_inflow(int dim, int nx, int ny, int G, int nang, const double *val, real *inflow) {
+    const int NB = dim == 1 ? 2 : 4 * (nx + ny);
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nang * G * NB) return;
+    const int b = (int)(i % NB);
+    const int g = (int)((i / NB) % G);
+    int side;
+    if (dim == 1) side = b;
+    else side = b < 2 * ny ? 0 : b < 4 * ny ? 1 : b < 4 * ny + 2 * nx ? 2 : 3;
+    inflow[i] = (real)val[side * G + g];
+}
+
+template <typename real>
+__global__ void k_copy_to(int64_t n, const double *src, real *dst) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (real)src[i];
+}
+
+// q_iso ABI [node][G] -> internal [G][cell][npc]
+template <typename real>
+__global__ void k_qiso_to_internal(int nn, int G, const double *q, real *qi, int npc) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nn * G) return;
+    const int n = (int)(i / G), g = (int)(i % G);
+    const int cell = n / npc, l = n % npc;
+    qi[((int64_t)g * (nn / npc) + cell) * npc + l] = (real)q[i];
+}
+
+// sig_t, sig ABI [cell][G] -> internal (sigma_t, sigma) pairs [G][cell]
+template <typename real>
+__global__ void k_sig_to_internal(int ncell, int G, const double *st, const double *s, real *sig2) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)ncell * G) return;
+    const int c = (int)(i / G), g = (int)(i % G);
+    sig2[2 * ((int64_t)g * ncell + c)] = (real)st[i];
+    sig2[2 * ((int64_t)g * ncell + c) + 1] = (real)s[i];
+}
+
+// ---------------------------------------------------------------------------
+// Angular flux layout conversion (2D): ABI [d][g][node] <-> internal
+// [d][g][band][t][r][canonical node].  dir_quad[d] gives the quadrant.
+// ---------------------------------------------------------------------------
+__device__ inline int64_t internal_index(int nx, int ny, int q, int i, int j, int l, int64_t slab_base) {
+    const bool fx = (q == 1 || q == 2), fy = (q == 2 || q == 3);
+    const int ic = fx ? nx - 1 - i : i, jc = fy ? ny - 1 - j : j;
+    const int lc = l ^ ((fx ? 1 : 0) | (fy ? 2 : 0));
+    const int band = jc / BAND_ROWS, r = jc % BAND_ROWS, t = ic + r;
+    const int NT = nx + BAND_ROWS - 1;
+    return slab_base + (((int64_t)band * NT + t) * BAND_ROWS + r) * 4 + lc;
+}
+
+template <typename real, typename src_t, bool TO_INTERNAL>
+__global__ void k_psi_convert(int nx, int ny, int G, int nang, const int *dir_quad, const src_t *in, real *out_or_in_real,
+                              double *out_abi) {
+    const int nn = nx * ny * 4;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nang * G * nn) return;
+    const int n = (int)(i % nn);
+    const int dg = (int)(i / nn);
+    const int d = dg / G;
+    const int cell = n >> 2, l = n & 3;
+    const int ii = cell % nx, jj = cell / nx;
+    const int64_t slab = (int64_t)dg * psi_slab(nx, ny);
+    const int64_t k = internal_index(nx, ny, dir_quad[d], ii, jj, l, slab);
+    if (TO_INTERNAL) out_or_in_real[k] = (real)in[i];
+    else out_abi[i] = (double)out_or_in_real[k];
+}
+
+// ---------------------------------------------------------------------------
+// Moment finalisation (2D): mom[27][node] (FP64) = sum over (quadrant,chunk)
+// partials in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void k_moments_finalize(int nx, int ny, int NQC, const int *qc_quad, const real *part, double *mom) {
+    const int i = blockIdx.x * 16 + threadIdx.x;
+    const int j = blockIdx.y * 16 + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const int nb = (ny + BAND_ROWS - 1) / BAND_ROWS, NT = nx + BAND_ROWS - 1;
+    const int nn = nx * ny * 4;
+    const int cell = i + nx * j;
+    double acc[4][27];
+    for (int l = 0; l < 4; ++l)
+        for (int m = 0; m < 27; ++m) acc[l][m] = 0.0;
+    for (int qc = 0; qc < NQC; ++qc) {
+        const int q = qc_quad[qc];
+        const bool fx = (q == 1 || q == 2), fy = (q == 2 || q == 3);
+        const int ic = fx ? nx - 1 - i : i, jc = fy ? ny - 1 - j : j;
+        const int band = jc / BAND_ROWS, r = jc % BAND_ROWS, t = ic + r;
+        const real *p = part + ((((int64_t)qc * nb + band) * NT + t) * BAND_ROWS + r) * PART_PER_CELL;
+        const int flip = (fx ? 1 : 0) | (fy ? 2 : 0);
+        for (int lc = 0; lc < 4; ++lc) {
+            const int l = lc ^ flip;
+            for (int k = 0; k < 6; ++k) acc[l][6 * q + k] += (double)p[lc * NMOM2D + k];
+            for (int k = 0; k < 3; ++k) acc[l][24 + k] += (double)p[lc * NMOM2D + 6 + k];
+        }
+    }
+    for (int l = 0; l < 4; ++l)
+        for (int m = 0; m < 27; ++m) mom[(int64_t)m * nn + 4 * cell + l] = acc[l][m];
+}
+
+// ---------------------------------------------------------------------------
+// 1D sweep: one thread per (direction, group); cells in upwind order.
+// Lumped linear DG, nodes (L, R); for mu > 0 (canonical):
+//   [[d, m/2], [-m/2, d]] [I_L, I_R] = [w q_L + m I_up, w q_R],
+//   d = m/2 + sigt h/2, w = h/2, m = |mu|  ->  inverse (dI - (m/2)J)/(d^2 + m^2/4)
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ void k_sweep1d(Sweep1DArgs A) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.nang * A.G) return;
+    const int d = i / A.G, g = i % A.G;
+    const real *mw = static_cast<const real *>(A.mu_w);
+    const real *hx = static_cast<const real *>(A.hx);
+    const real *sig2 = static_cast<const real *>(A.sig2);
+    const real *qi = static_cast<const real *>(A.qiso);
+    const real *pp = static_cast<const real *>(A.psi_prev);
+    real *po = static_cast<real *>(A.psi_out);
+    const real *inf = static_cast<const real *>(A.inflow);
+    const real mu = mw[2 * d];
+    const bool fwd = mu > 0;
+    const real m = fabs(mu);
+    const int nn = 2 * A.nx;
+    const int64_t base = ((int64_t)d * A.G + g) * nn;
+    real up = inf[((int64_t)d * A.G + g) * 2 + (fwd ? 0 : 1)];
+    const real icdt = (real)A.inv_c_dt;
+    for (int s = 0; s < A.nx; ++s) {
+        const int c = fwd ? s : A.nx - 1 - s;
+        const real h = hx[c];
+        const real w = real(0.5) * h;
+        const real st = sig2[2 * ((int64_t)g * A.nx + c)];
+        const int nu_ = fwd ? 0 : 1, nd_ = fwd ? 1 : 0;     // upwind / downwind node
+        real qu = qi[((int64_t)g * A.nx + c) * 2 + nu_], qd = qi[((int64_t)g * A.nx + c) * 2 + nd_];
+        if (pp) {
+            qu += icdt * pp[base + 2 * c + nu_];
+            qd += icdt * pp[base + 2 * c + nd_];
+        }
+        const real r0 = w * qu + m * up, r1 = w * qd;
+        const real dg = real(0.5) * m + st * w, hm = real(0.5) * m;
+        const real inv = real(1) / (dg * dg + hm * hm);
+        const real Iu = (dg * r0 - hm * r1) * inv;
+        const real Id = (dg * r1 + hm * r0) * inv;
+        po[base + 2 * c + nu_] = Iu;
+        po[base + 2 * c + nd_] = Id;
+        up = Id;
+    }
+}
+
+// 1D moments [8][node] from psi [d][g][node] (sum over d, g in a fixed order)
+template <typename real>
+__global__ void k_moments1d(int nx, int G, int nang, const real *mu_w, const double *sig, const real *psi, double *mom) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nn = 2 * nx;
+    if (n >= nn) return;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int c = n >> 1;
+    for (int d = 0; d < nang; ++d) {
+        const double mu = mu_w[2 * d], w = mu_w[2 * d + 1];
+        const int h = mu > 0 ? 0 : 1;
+        for (int g = 0; g < G; ++g) {
+            const double v = psi[((int64_t)d * G + g) * nn + n];
+            acc[3 * h] += w * v;
+            acc[3 * h + 1] += w * mu * v;
+            acc[3 * h + 2] += w * mu * mu * v;
+            const double s = sig[(int64_t)c * G + g];
+            acc[6] += s * w * v;
+            acc[7] += s * w * mu * v;
+        }
+    }
+    for (int m = 0; m < 8; ++m) mom[(int64_t)m * nn + n] = acc[m];
+}
+
+// HO energy density and flux of an ABI-layout psi (FP64): E = (1/c) sum w I,
+// F = sum w Omega I  (used at set_state)
+__global__ void k_psi_EF(int nn, int dim, int G, int nang, const double *om, const double *w, double c,
+                         const double *psi, double *E, double *F) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double e = 0, fx = 0, fy = 0;
+    for (int d = 0; d < nang; ++d)
+        for (int g = 0; g < G; ++g) {
+            const double v = w[d] * psi[((int64_t)d * G + g) * nn + n];
+            e += v;
+            fx += om[3 * d] * v;
+            fy += om[3 * d + 1] * v;
+        }
+    E[n] = e / c;
+    F[dim * n] = fx;
+    if (dim == 2) F[dim * n + 1] = fy;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+void upload_bernoulli(const double *coef) { SMRT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_bern), coef, sizeof(double) * NBERN)); }
+
+template <typename real>
+void run_opacity(hipStream_t s, int ncell, int npc, int G, const double *T, const int *region, int model,
+                 const double *sigma0, double lo, double hi, const double *nu, double icdt, double *sig, real *sig2) {
+    hipLaunchKernelGGL(k_opacity<real>, dim3(nblk(ncell, 256)), dim3(256), 0, s, ncell, npc, G, T, region, model,
+                       sigma0, lo, hi, nu, icdt, sig, sig2);
+}
+template <typename real>
+void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const double *nu, double a, double c,
+                const double *sig, real *qiso, double *sigP, double *sigF) {
+    hipLaunchKernelGGL(k_source<real>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, npc, G, T, nu, a, c, sig, qiso, sigP, sigF);
+}
+void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
+                     double *psi) {
+    hipLaunchKernelGGL(k_equilibrium, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, G, nang, T, nu, a, c, psi);
+}
+void run_side_inflow(hipStream_t s, int nsides, int G, const double *nu, double a, double c, const int *kind,
+                     const double *Tb, const double *explicit_g, double *val) {
+    hipLaunchKernelGGL(k_side_inflow, dim3(nsides), dim3(64), 0, s, G, nu, a, c, kind, Tb, explicit_g, val);
+}
+template <typename real>
+void run_fill_inflow(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *val, real *inflow) {
+    const int NB = dim == 1 ? 2 : 4 * (nx + ny);
+    hipLaunchKernelGGL(k_fill_inflow<real>, dim3(nblk((int64_t)nang * G * NB, 256)), dim3(256), 0, s, dim, nx, ny, G,
+                       nang, val, inflow);
+}
+template <typename real>
+void run_copy_to(hipStream_t s, int64_t n, const double *src, real *dst) {
+    hipLaunchKernelGGL(k_copy_to<real>, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
+}
+template <typename real>
+void run_qiso_to_internal(hipStream_t s, int nn, int G, int npc, const double *q, real *qi) {
+    hipLaunchKernelGGL(k_qiso_to_internal<real>, dim3(nblk((int64_t)nn * G, 256)), dim3(256), 0, s, nn, G, q, qi, npc);
+}
+template <typename real>
+void run_sig_to_internal(hipStream_t s, int ncell, int G, const double *st, const double *sg, real *sig2) {
+    hipLaunchKernelGGL(k_sig_to_internal<real>, dim3(nblk((int64_t)ncell * G, 256)), dim3(256), 0, s, ncell, G, st, sg, sig2);
+}
+template <typename real>
+void run_psi_to_internal(hipStream_t s, int nx, int ny, int G, int nang, const int *dq, const double *abi, real *in) {
+    const int64_t n = (int64_t)nang * G * nx * ny * 4;
+    hipLaunchKernelGGL((k_psi_convert<real, double, true>), dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, nang, dq, abi,
+                       in, (double *)nullptr);
+}
+template <typename real>
+void run_psi_from_internal(hipStream_t s, int nx, int ny, int G, int nang, const int *dq, const real *in, double *abi) {
+    const int64_t n = (int64_t)nang * G * nx * ny * 4;
+    hipLaunchKernelGGL((k_psi_convert<real, double, false>), dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, nang, dq,
+                       (const double *)nullptr, const_cast<real *>(in), abi);
+}
+template <typename real>
+void run_moments_finalize(hipStream_t s, int nx, int ny, int NQC, const int *qcq, const real *part, double *mom) {
+    hipLaunchKernelGGL(k_moments_finalize<real>, dim3(nblk(nx, 16), nblk(ny, 16)), dim3(16, 16), 0, s, nx, ny, NQC, qcq,
+                       part, mom);
+}
+template <typename real>
+void launch_sweep1d(const Sweep1DArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep1d<real>, dim3(nblk(a.nang * a.G, 64)), dim3(64), 0, s, a);
+    SMRT_HIP(hipGetLastError());
+}
+template <typename real>
+void run_moments1d(hipStream_t s, int nx, int G, int nang, const real *mw, const double *sig, const real *psi, double *mom) {
+    hipLaunchKernelGGL(k_moments1d<real>, dim3(nblk(2 * nx, 128)), dim3(128), 0, s, nx, G, nang, mw, sig, psi, mom);
+}
+void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *om, const double *w, double c,
+                const double *psi, double *E, double *F) {
+    hipLaunchKernelGGL(k_psi_EF, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, dim, G, nang, om, w, c, psi, E, F);
+}
+
+#define INST(real)                                                                                                  \
+    template void run_opacity<real>(hipStream_t, int, int, int, const double *, const int *, int, const double *,  \
+                                    double, double, const double *, double, double *, real *);                      \
+    template void run_source<real>(hipStream_t, int, int, int, const double *, const double *, double, double,      \
+                                   const double *, real *, double *, double *);                                     \
+    template void run_fill_inflow<real>(hipStream_t, int, int, int, int, int, const double *, real *);              \
+    template void run_copy_to<real>(hipStream_t, int64_t, const double *, real *);                                  \
+    template void run_qiso_to_internal<real>(hipStream_t, int, int, int, const double *, real *);                   \
+    template void run_sig_to_internal<real>(hipStream_t, int, int, const double *, const double *, real *);         \
+    template void run_psi_to_internal<real>(hipStream_t, int, int, int, int, const int *, const double *, real *);  \
+    template void run_psi_from_internal<real>(hipStream_t, int, int, int, int, const int *, const real *, double *); \
+    template void run_moments_finalize<real>(hipStream_t, int, int, int, const int *, const real *, double *);      \
+    template void launch_sweep1d<real>(const Sweep1DArgs &, hipStream_t);                                           \
+    template void run_moments1d<real>(hipStream_t, int, int, int, const real *, const double *, const real *, double *);
+INST(float)
+INST(double)
+
+}  // namespace smrt

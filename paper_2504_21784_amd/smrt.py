@@ -1,0 +1,262 @@
+"""Thin ctypes binding of the gfx950 SM-TRT library (``libsmrt.so``).
+
+Argument marshalling only: every step of the transport sweep, moments,
+closures, low-order solve and time step runs in the HIP library.  The
+binding raises if the compiled library is missing -- there is no CPU
+fallback.  Names follow the C ABI in ``include/smrt.h``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmrt.so")
+
+SMRT_FP64, SMRT_FP32 = 0, 1
+SMRT_SM_CONSISTENT, SMRT_SM_INDEPENDENT, SMRT_UNACCELERATED = 0, 1, 2
+STATUS = {0: "SMRT_OK", 1: "SMRT_E_INVALID_ARG", 2: "SMRT_E_OUT_OF_MEMORY", 3: "SMRT_E_DEVICE",
+          4: "SMRT_E_NOT_CONVERGED", 5: "SMRT_E_NONPHYSICAL", 6: "SMRT_E_STATE"}
+
+_dp = C.POINTER(C.c_double)
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("x_edges", _dp), ("y_edges", _dp)]
+
+
+class QuadDesc(C.Structure):
+    _fields_ = [("n_angles", C.c_int), ("omega", _dp), ("w", _dp)]
+
+
+class GroupsDesc(C.Structure):
+    _fields_ = [("G", C.c_int), ("nu_edges", _dp), ("a", C.c_double), ("c", C.c_double)]
+
+
+class MaterialDesc(C.Structure):
+    _fields_ = [("n_regions", C.c_int), ("region_of_cell", C.POINTER(C.c_int32)), ("model", C.c_int),
+                ("sigma0", _dp), ("clip_lo", C.c_double), ("clip_hi", C.c_double), ("cv", _dp)]
+
+
+class BoundaryDesc(C.Structure):
+    _fields_ = [("kind", C.c_int * 4), ("T_bdr", C.c_double * 4), ("inflow_g", _dp * 4)]
+
+
+class Options(C.Structure):
+    _fields_ = [("eps_outer", C.c_double), ("eps_inner", C.c_double), ("cg_rtol", C.c_double),
+                ("elim_rtol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int), ("max_cg", C.c_int),
+                ("max_elim", C.c_int), ("precision", C.c_int), ("scheme", C.c_int), ("strict", C.c_int),
+                ("fixed_outer", C.c_int), ("lo_time_edge", C.c_int)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("outer", C.c_int), ("inner_total", C.c_int), ("cg_total", C.c_int), ("elim_max", C.c_int),
+                ("hit_max", C.c_int), ("energy_residual", C.c_double), ("t_sweep_ms", C.c_double),
+                ("t_lo_ms", C.c_double), ("t_total_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Info(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("n_angles", C.c_int), ("G", C.c_int),
+                ("n_nodes", C.c_int), ("n_cells", C.c_int), ("units_per_sweep", C.c_int64),
+                ("algorithmic_bytes_per_sweep", C.c_int64), ("band_rows", C.c_int), ("waves_per_group", C.c_int),
+                ("pairs_per_lane", C.c_int), ("pairs_per_chunk", C.c_int), ("n_chunks", C.c_int),
+                ("n_workgroups", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+# exported names and ctypes signatures (argtypes, restype)
+_SIGS = {
+    "smrt_default_options": ([C.POINTER(Options)], None),
+    "smrt_create": ([C.POINTER(MeshDesc), C.POINTER(QuadDesc), C.POINTER(GroupsDesc), C.POINTER(MaterialDesc),
+                     C.POINTER(BoundaryDesc), C.POINTER(Options), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "smrt_destroy": ([C.c_void_p], None),
+    "smrt_last_error": ([C.c_void_p], C.c_char_p),
+    "smrt_set_options": ([C.c_void_p, C.POINTER(Options)], C.c_int),
+    "smrt_set_boundary": ([C.c_void_p, C.POINTER(BoundaryDesc)], C.c_int),
+    "smrt_set_state": ([C.c_void_p, _dp, _dp], C.c_int),
+    "smrt_get_state": ([C.c_void_p, _dp, _dp, _dp, _dp], C.c_int),
+    "smrt_sweep": ([C.c_void_p, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp], C.c_int),
+    "smrt_compute_closures": ([C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp], C.c_int),
+    "smrt_lo_solve": ([C.c_void_p, _dp, _dp, C.c_double, _dp, _dp, _dp, C.POINTER(StepStats)], C.c_int),
+    "smrt_step": ([C.c_void_p, C.c_double, C.POINTER(StepStats)], C.c_int),
+    "smrt_sweep_resident": ([C.c_void_p, C.c_double, C.c_int, _dp], C.c_int),
+    "smrt_get_info": ([C.c_void_p, C.POINTER(Info)], C.c_int),
+    "smrt_set_launch": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
+}
+
+
+def load():
+    """Load libsmrt.so (no fallback: raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2504_21784_amd.build.build()")
+        lib = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+class SmrtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load().smrt_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """One problem on the GPU.  ``problem`` is a workloads.Problem."""
+
+    def __init__(self, problem, precision=SMRT_FP64, scheme=SMRT_SM_CONSISTENT, stream=None, **opts):
+        L = load()
+        self.L = L
+        self.p = p = problem
+        keep = self._keep = []
+
+        def arr(a, dt=np.float64):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a
+
+        xe = arr(p.x_edges)
+        ye = arr(p.y_edges) if p.y_edges is not None else None
+        self.mesh = MeshDesc(p.dim, p.nx, p.ny if p.dim == 2 else 1, _p(xe), _p(ye))
+        om, w = arr(p.omega), arr(p.w)
+        self.quad = QuadDesc(p.n_angles, _p(om), _p(w))
+        nu = arr(p.nu_edges)
+        self.groups = GroupsDesc(p.G, _p(nu), p.a, p.c)
+        reg = arr(p.region_of_cell, np.int32)
+        s0, cv = arr(p.sigma0), arr(p.cv)
+        self.mat = MaterialDesc(p.n_regions, reg.ctypes.data_as(C.POINTER(C.c_int32)), p.model, _p(s0), p.clip_lo,
+                                p.clip_hi, _p(cv))
+        self.bc = self._bc(p)
+        self.opts = default_options(precision=precision, scheme=scheme, **opts)
+        h = C.c_void_p()
+        st = L.smrt_create(C.byref(self.mesh), C.byref(self.quad), C.byref(self.groups), C.byref(self.mat),
+                           C.byref(self.bc), C.byref(self.opts), stream, C.byref(h))
+        if st != 0:
+            raise SmrtError(st, L.smrt_last_error(None).decode())
+        self.h = h
+
+    def _bc(self, p):
+        bc = BoundaryDesc()
+        for s in range(2 * p.dim):
+            bc.kind[s] = p.bc_kind[s]
+            bc.T_bdr[s] = p.T_bdr[s]
+            if p.inflow_g[s] is not None:
+                a = _f64(p.inflow_g[s])
+                self._keep.append(a)
+                bc.inflow_g[s] = _p(a)
+        return bc
+
+    def _check(self, st):
+        if st != 0:
+            raise SmrtError(st, self.L.smrt_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.smrt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- ABI wrappers ------------------------------------------------------
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opts, k, v)
+        self._check(self.L.smrt_set_options(self.h, C.byref(self.opts)))
+
+    def set_boundary(self, problem=None):
+        self.bc = self._bc(problem or self.p)
+        self._check(self.L.smrt_set_boundary(self.h, C.byref(self.bc)))
+
+    def set_launch(self, waves_per_group=0, pairs_per_lane=0):
+        self._check(self.L.smrt_set_launch(self.h, waves_per_group, pairs_per_lane))
+
+    def info(self) -> dict:
+        i = Info()
+        self._check(self.L.smrt_get_info(self.h, C.byref(i)))
+        return i.as_dict()
+
+    def set_state(self, T, psi=None):
+        T = _f64(T)
+        ps = _f64(psi) if psi is not None else None
+        self._check(self.L.smrt_set_state(self.h, _p(T), _p(ps)))
+
+    def get_state(self, with_psi=True):
+        p = self.p
+        T, E = np.zeros(p.n_nodes), np.zeros(p.n_nodes)
+        F = np.zeros((p.n_nodes, p.dim))
+        psi = np.zeros((p.n_angles, p.G, p.n_nodes)) if with_psi else None
+        self._check(self.L.smrt_get_state(self.h, _p(T), _p(E), _p(F), _p(psi)))
+        return dict(T=T, E=E, F=F, psi=psi)
+
+    def sweep(self, sig_t, sig, q_iso, psi_prev, inv_c_dt, inflow=None):
+        p = self.p
+        psi = np.zeros((p.n_angles, p.G, p.n_nodes))
+        mom = np.zeros((27 if p.dim == 2 else 8, p.n_nodes))
+        args = [_f64(sig_t), _f64(sig), _f64(q_iso)]
+        pp = _f64(psi_prev) if psi_prev is not None else None
+        inf = _f64(inflow) if inflow is not None else None
+        self._check(self.L.smrt_sweep(self.h, *[_p(a) for a in args], _p(pp), float(inv_c_dt), _p(inf), _p(psi),
+                                      _p(mom)))
+        return psi, mom
+
+    def compute_closures(self, moments, T_l, Estar, Fstar, sig, dt):
+        p = self.p
+        out = np.zeros((4 + p.dim, p.n_nodes))
+        args = [_f64(moments), _f64(T_l), _f64(Estar), _f64(Fstar), _f64(sig)]
+        self._check(self.L.smrt_compute_closures(self.h, *[_p(a) for a in args], float(dt), _p(out)))
+        return out
+
+    def lo_solve(self, closures, Tstar, dt, E, T):
+        p = self.p
+        E, T = _f64(E).copy(), _f64(T).copy()
+        F = np.zeros((p.n_nodes, p.dim))
+        st = StepStats()
+        self._check(self.L.smrt_lo_solve(self.h, _p(_f64(closures)), _p(_f64(Tstar)), float(dt), _p(E), _p(F), _p(T),
+                                         C.byref(st)))
+        return E, F, T, st.as_dict()
+
+    def step(self, dt=None) -> dict:
+        st = StepStats()
+        self._check(self.L.smrt_step(self.h, float(dt if dt is not None else self.p.dt), C.byref(st)))
+        return st.as_dict()
+
+    def sweep_resident(self, dt=None, n_times=1) -> float:
+        ms = C.c_double(0.0)
+        self._check(self.L.smrt_sweep_resident(self.h, float(dt if dt is not None else self.p.dt), int(n_times),
+                                               C.byref(ms)))
+        return ms.value

@@ -18,3 +18,10 @@ def oracle_mod():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def smrt_mod():
+    from paper_2504_21784_amd import smrt
+    smrt.load()
+    return smrt

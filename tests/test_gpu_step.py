@@ -1,0 +1,165 @@
+"""GPU parity of the closure post-pass, the FP64 low-order solve and full
+backward-Euler SM steps against the FP64 oracle (through the C ABI).
+
+FP64 results agree to 1e-10 relative when both sides iterate to tight
+tolerances; with the paper's tolerances the outer iteration count matches
+within +-1.  The FP32 sweep keeps flux within 1e-5 and temperature within
+1e-6 of the FP64 oracle over several steps.
+"""
+import numpy as np
+import pytest
+
+from paper_2504_21784_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = dict(eps_outer=1e-11, eps_inner=1e-12, cg_rtol=1e-13, elim_rtol=1e-15, max_outer=200, max_inner=60,
+             max_cg=3000)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _mg_small(n=20, G=4, sn=4, seed=3, T0=0.05):
+    p = W.multigroup_2d(n=n, G=G, sn=sn, region=5, seed=seed)
+    p.T0 = T0
+    return p
+
+
+def _state_after_sweep(oracle_mod, p):
+    o = oracle_mod.Oracle(p)
+    st = o.initial_state()
+    T = st["T"] * (1.0 + 0.3 * np.random.default_rng(1).uniform(size=p.n_nodes))
+    sig = o.opacity(T)
+    sigt = sig + 1.0 / (p.c * p.dt)
+    q = np.zeros((p.n_nodes, p.G))
+    for n in range(p.n_nodes):
+        b, _ = o.spectra(T[n])
+        q[n] = sig[n // 4] * p.a * p.c * T[n] ** 4 * b / (4 * np.pi)
+    psi = o.sweep(sigt, q, st["psi"], 1.0 / (p.c * p.dt), o.inflow())
+    Estar = np.einsum("d,dgn->n", p.w, st["psi"]) / p.c
+    Fstar = np.einsum("d,da,dgn->na", p.w, p.omega[:, :2], st["psi"])
+    return o, T, sig, psi, Estar, Fstar
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_closures_match_oracle(smrt_mod, oracle_mod, scheme):
+    p = _mg_small()
+    o, T, sig, psi, Estar, Fstar = _state_after_sweep(oracle_mod, p)
+    ref = o.closures(scheme, p.dt, sig, T, Estar, Fstar, psi, o.inflow())
+    mom = o.moments(sig, psi)
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, scheme=scheme)
+    out = ctx.compute_closures(mom, T, Estar, Fstar, sig, p.dt)
+    names = ["sigE", "sigF", "sigP", "qE"]
+    for k, nm in enumerate(names):
+        assert _rel(out[k], ref[nm]) < 1e-11, nm
+    for a in range(2):
+        assert _rel(out[4 + a], ref["qF"][:, a]) < 1e-10, ("qF", a)
+    ctx.close()
+
+
+def test_closures_1d_match_oracle(smrt_mod, oracle_mod):
+    p = W.slab_1d(n_cells=17, n_angles=8)
+    o = oracle_mod.Oracle(p)
+    st = o.initial_state()
+    sig = o.opacity(st["T"])
+    psi = o.sweep(sig + 100.0, np.full((p.n_nodes, 1), 0.01), st["psi"], 100.0, o.inflow())
+    Estar = np.einsum("d,dgn->n", p.w, st["psi"]) / p.c
+    Fstar = np.einsum("d,dgn->n", p.w * p.omega[:, 0], st["psi"])[:, None]
+    T = st["T"] * 1.5
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64)
+    ref = o.closures(0, p.dt, sig, T, Estar, Fstar, psi, o.inflow())
+    out = ctx.compute_closures(o.moments(sig, psi), T, Estar, Fstar, sig, p.dt)
+    for k, nm in enumerate(["sigE", "sigF", "sigP", "qE"]):
+        assert _rel(out[k], ref[nm]) < 1e-11, nm
+    assert _rel(out[4], ref["qF"][:, 0]) < 1e-10
+    ctx.close()
+
+
+def test_lo_solve_matches_oracle(smrt_mod, oracle_mod):
+    p = _mg_small(n=16)
+    o, T, sig, psi, Estar, Fstar = _state_after_sweep(oracle_mod, p)
+    cl = o.closures(0, p.dt, sig, T, Estar, Fstar, psi, o.inflow())
+    E0 = Estar.copy()
+    opts = oracle_mod.default_opts(**TIGHT)
+    r, E_ref, F_ref, T_ref, st = o.lo_solve(opts, p.dt, p.initial_T_nodes(), cl, E0, T)
+    assert r == 0
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **TIGHT)
+    rows = np.vstack([cl["sigE"], cl["sigF"], cl["sigP"], cl["qE"], cl["qF"].T])
+    E, F, Tg, gst = ctx.lo_solve(rows, p.initial_T_nodes(), p.dt, E0, T)
+    assert _rel(Tg, T_ref) < 1e-10
+    assert _rel(E, E_ref) < 1e-10
+    assert _rel(F, F_ref) < 1e-9
+    assert abs(gst["inner_total"] - st["inner_total"]) <= 1
+    ctx.close()
+
+
+def _run_steps(smrt_mod, oracle_mod, p, n_steps, scheme, prec, opts):
+    o = oracle_mod.Oracle(p)
+    st = o.initial_state()
+    ctx = smrt_mod.Context(p, precision=prec, scheme=scheme, **opts)
+    ctx.set_state(st["T"])
+    out = []
+    for k in range(n_steps):
+        print(f"step {k}", flush=True)
+        r, st, ost = o.step(st, oracle_mod.default_opts(scheme=scheme, **opts))
+        assert r == 0
+        gst = ctx.step()
+        got = ctx.get_state()
+        out.append((st, ost, got, gst))
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_step_fp64_matches_oracle_2d(smrt_mod, oracle_mod, scheme):
+    p = _mg_small(n=18, G=3, sn=4, seed=11, T0=0.2)
+    opts = dict(TIGHT)
+    if scheme == 2:
+        opts["max_outer"] = 2000
+    for ref, ost, got, gst in _run_steps(smrt_mod, oracle_mod, p, 2, scheme, 0, opts):
+        assert _rel(got["T"], ref["T"]) < 1e-10
+        assert _rel(got["E"], ref["E"]) < 1e-10
+        assert _rel(got["psi"], ref["psi"]) < 1e-10
+        assert abs(gst["outer"] - ost["outer"]) <= 1
+
+
+def test_step_fp64_slab_paper_tolerances(smrt_mod, oracle_mod):
+    """1D gray slab (sigma=10, c_v=1, T0=0.01, left inflow at T=1), SM to 1e-8:
+    outer iteration counts within +-1 of the oracle per step."""
+    p = W.slab_1d(n_cells=64, n_angles=8)
+    opts = dict(eps_outer=1e-8, eps_inner=1e-8, cg_rtol=1e-12, elim_rtol=1e-12, max_outer=100, max_inner=30,
+                max_cg=500)
+    res = _run_steps(smrt_mod, oracle_mod, p, 10, 0, 0, opts)
+    for ref, ost, got, gst in res:
+        assert abs(gst["outer"] - ost["outer"]) <= 1
+        assert _rel(got["T"], ref["T"]) < 1e-7
+
+
+def test_step_fp32_error_budget(smrt_mod, oracle_mod):
+    """FP32 sweep, FP64 low-order: phi within 1e-5 and T within 1e-6 (relative
+    L2) of the FP64 oracle over several steps."""
+    p = W.gray_2d(n=32, sn=8, block=8, seed=2)
+    opts = dict(TIGHT)
+    for ref, ost, got, gst in _run_steps(smrt_mod, oracle_mod, p, 4, 0, 1, opts):
+        phi_ref = np.einsum("d,dgn->n", p.w, ref["psi"])
+        phi = np.einsum("d,dgn->n", p.w, got["psi"])
+        assert np.linalg.norm(phi - phi_ref) / np.linalg.norm(phi_ref) < 1e-5
+        assert np.linalg.norm(got["T"] - ref["T"]) / np.linalg.norm(ref["T"]) < 1e-6
+
+
+def test_step_rejects_bad_dt(smrt_mod):
+    p = W.gray_2d(n=8, sn=4, block=4)
+    ctx = smrt_mod.Context(p)
+    ctx.set_state(p.initial_T_nodes())
+    with pytest.raises(smrt_mod.SmrtError):
+        ctx.step(dt=-1.0)
+    ctx.close()
+
+
+def test_create_rejects_bad_quadrature(smrt_mod):
+    p = W.gray_2d(n=8, sn=4, block=4)
+    p.w = p.w * 1.01
+    with pytest.raises(smrt_mod.SmrtError):
+        smrt_mod.Context(p)
