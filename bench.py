@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the SM-TRT high-order path on one MI355X.
+
+Workload: 2D 256x256 bilinear DG, level-symmetric S8 (40 angles), 16 groups
+log-spaced on [1e-3, 10], power-law opacities with per-region coefficients
+(synthetic, seeded), Planck emission at T0 = 0.01, left inflow at T = 1,
+dt = 1e-3 -- the multigroup throughput configuration.
+
+One bench step = one resident high-order pass: opacity table, emission and
+gray-collapse tables, the FP32 sweep over all 640 (angle, group) pairs with
+fused moments, the moment finalisation and the SM closure post-pass, with
+every input already in HBM.  value = swept cell*angle*group units per
+second of that pass.  The JSON line also carries the sweep kernel's
+HBM roofline (algorithmic bytes: read I* + write I), the FP64 sweep for
+the FP32-vs-FP64 ratio, and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(p, sample_groups=8):
+    """FP64 oracle sweep + moments on the same mesh, angles and opacities,
+    restricted to the first `sample_groups` groups; single thread."""
+    import numpy as np
+    import oracle
+    from paper_2504_21784_amd import workloads as W
+
+    T = p.initial_T_nodes()
+    sig = oracle.Oracle(p).opacity(T)
+    q = W.multigroup_2d()
+    q.G = sample_groups
+    q.nu_edges = p.nu_edges[:sample_groups + 1]
+    o = oracle.Oracle(q)
+    sigt = sig[:, :sample_groups] + 1.0 / (p.c * p.dt)
+    full = oracle.Oracle(p)
+    b = np.array([full.spectra(t)[0][:sample_groups] for t in T[:1]])[0]
+    B = p.a * p.c * T ** 4 / (4 * np.pi)
+    qiso = sig[np.arange(p.n_nodes) // 4, :sample_groups] * (B[:, None] * b[None, :])
+    psi0 = np.broadcast_to((B[None, None, :] * b[None, :, None]), (p.n_angles, sample_groups, p.n_nodes)).copy()
+    inflow = full.inflow()[:, :sample_groups, :]
+    t0 = time.perf_counter()
+    psi = o.sweep(sigt, qiso, psi0, 1.0 / (p.c * p.dt), inflow)
+    o.moments(sig[:, :sample_groups], psi)
+    dt = time.perf_counter() - t0
+    units = p.n_cells * p.n_angles * sample_groups
+    return {"value": units / dt, "unit": "units/s", "cores": 1, "kind": "oracle",
+            "sample": f"same 256x256 S8 workload, groups 1-{sample_groups} of {p.G} "
+                      f"({units / 1e6:.2f} M units): FP64 sweep + moments, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--waves", type=int, default=0, help="sweep waves per workgroup (0 = automatic)")
+    ap.add_argument("--pairs", type=int, default=0, help="(angle,group) pairs per lane (0 = automatic)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one MI355X: this build runs on a single GPU (the multi-GPU sharding "
+              "of the sweep is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2504_21784_amd import smrt, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    p = W.multigroup_2d()
+    T0 = p.initial_T_nodes()
+
+    def make(prec):
+        ctx = smrt.Context(p, precision=prec, stream=stream)
+        if args.waves or args.pairs:
+            ctx.set_launch(args.waves, args.pairs if prec == smrt.SMRT_FP32 else min(args.pairs, 1))
+        ctx.set_state(T0)
+        return ctx
+
+    ctx = make(smrt.SMRT_FP32)
+    info = ctx.info()
+    units = info["units_per_sweep"]
+    for _ in range(args.warmup):
+        ctx.sweep_resident(n_times=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = []
+    for _ in range(args.steps):
+        _, k = ctx.sweep_resident(n_times=1)
+        kms.append(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    k_ms = float(np.mean(kms))
+    mom32 = ctx.get_moments()
+    alg_bytes = info["algorithmic_bytes_per_sweep"]
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    ctx.close()
+
+    # FP64 sweep on the same inputs: throughput ratio and FP32 error
+    c64 = make(smrt.SMRT_FP64)
+    c64.sweep_resident(n_times=1)
+    _, k64 = c64.sweep_resident(n_times=max(3, args.steps // 4))
+    mom64 = c64.get_moments()
+    c64.close()
+    phi32 = sum(mom32[6 * q] for q in range(4))
+    phi64 = sum(mom64[6 * q] for q in range(4))
+    phi_err = float(np.linalg.norm(phi32 - phi64) / np.linalg.norm(phi64))
+
+    out = {
+        "metric": "swept cell*angle*group unknowns/s (FP32 sweep with fused moments and closures, 1 GPU)",
+        "value": units / (ms_per_step * 1e-3),
+        "unit": "units/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "multigroup_2d: 256x256 bilinear DG, level-symmetric S8 (40 angles), 16 groups, "
+                               "power-law region opacities (seed 3), dt=1e-3; step = opacity + sources + FP32 sweep "
+                               "with fused moments + moment finalisation + SM closures",
+                   "units_per_sweep": units, "launch": {k: info[k] for k in ("band_rows", "waves_per_group",
+                                                                             "pairs_per_lane", "pairs_per_chunk",
+                                                                             "n_chunks", "n_workgroups")}},
+        "sweep_kernel_ms": k_ms,
+        "sweep_units_per_s": units / (k_ms * 1e-3),
+        "fp64_sweep_kernel_ms": k64,
+        "fp64_sweep_units_per_s": units / (k64 * 1e-3),
+        "fp32_vs_fp64_sweep_speedup": k64 / k_ms,
+        "fp32_phi_rel_l2_vs_fp64": phi_err,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sweep2d_kernel<float,K,2>",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

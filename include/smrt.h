@@ -205,11 +205,20 @@ smrt_status smrt_lo_solve(smrt_ctx *ctx, const double *closures, const double *T
  * current state; all data stays on the device. */
 smrt_status smrt_step(smrt_ctx *ctx, double dt, smrt_step_stats *stats);
 
-/* Sweep-only throughput path: runs the sweep n_times on the context's
- * resident state (current psi as psi_prev, current emission source and
- * opacities for dt) and reports the mean time per sweep (ms) measured with
- * HIP events on the context stream around the sweep kernel launches. */
-smrt_status smrt_sweep_resident(smrt_ctx *ctx, double dt, int n_times, double *ms_per_sweep);
+/* Resident high-order pass, for throughput measurement: n_times times, on
+ * the context's current state (T, psi as psi_prev) with time step dt, runs
+ * the opacity table, the emission source and gray-collapse tables, the
+ * sweep with fused moments, the moment finalisation and the closure
+ * post-pass, all on the context stream with no host transfer.  Writes the
+ * mean wall time per pass (ms) and the mean duration of the sweep kernel
+ * alone (ms), both measured with HIP events on the context stream.  The
+ * state (T, psi) is not advanced. */
+smrt_status smrt_sweep_resident(smrt_ctx *ctx, double dt, int n_times, double *ms_per_pass, double *ms_sweep_kernel);
+
+/* Copies the HO moments of the most recent sweep of the context (the last
+ * outer iteration of smrt_step, or smrt_sweep_resident) into moments
+ * ([27|8][n_nodes], FP64, layout as in the header comment). */
+smrt_status smrt_get_moments(smrt_ctx *ctx, double *moments);
 
 /* Information about the problem and the chosen launch configuration. */
 typedef struct {

@@ -862,22 +862,53 @@ extern "C" smrt_status smrt_step(smrt_ctx *x, double dt, smrt_step_stats *stats)
     return st != SMRT_OK ? st : result;
 }
 
-extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, double *ms_per_sweep) {
+extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, double *ms_per_pass,
+                                           double *ms_sweep_kernel) {
     if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
     return guard(x, [&] {
-        require(dt > 0.0 && n_times >= 1 && ms_per_sweep, "invalid argument");
+        require(dt > 0.0 && n_times >= 1 && ms_per_pass && ms_sweep_kernel, "invalid argument");
         require(x->have_state, "smrt_set_state must be called first");
-        const double icdt = prepare_step_tables(x, dt);
-        run_source_at(x, x->d_T.p);
         void *pin = x->d_psi[x->cur].p, *pout = x->d_psi[1 - x->cur].p;
+        std::vector<hipEvent_t> ev(2 * n_times);
+        for (auto &e : ev) SMRT_HIP(hipEventCreate(&e));
         SMRT_HIP(hipEventRecord(x->ev0, x->stream));
-        for (int k = 0; k < n_times; ++k)
+        for (int k = 0; k < n_times; ++k) {
+            const double icdt = prepare_step_tables(x, dt);
+            run_source_at(x, x->d_T.p);
+            SMRT_HIP(hipEventRecord(ev[2 * k], x->stream));
             run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p, false);
+            SMRT_HIP(hipEventRecord(ev[2 * k + 1], x->stream));
+            if (x->dim == 2) {
+                if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->NQC, x->d_qc_quad.p, (const float *)x->d_part.p, x->d_mom.p);
+                else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->NQC, x->d_qc_quad.p, (const double *)x->d_part.p, x->d_mom.p);
+            } else {
+                if (x->fp32) run_moments1d<float>(x->stream, x->nx, x->G, x->nang, (const float *)x->d_mu_w.p, x->d_sig.p, (const float *)pout, x->d_mom.p);
+                else run_moments1d<double>(x->stream, x->nx, x->G, x->nang, (const double *)x->d_mu_w.p, x->d_sig.p, (const double *)pout, x->d_mom.p);
+            }
+            run_closures(x->stream, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt, x->d_mom.p,
+                                                 x->d_sigP.p, x->d_sigF.p, x->d_Eho.p, x->d_Fho.p, x->d_clos.p));
+        }
         SMRT_HIP(hipEventRecord(x->ev1, x->stream));
         SMRT_HIP(hipEventSynchronize(x->ev1));
-        float ms = 0.f;
+        float ms = 0.f, ks = 0.f;
         SMRT_HIP(hipEventElapsedTime(&ms, x->ev0, x->ev1));
-        *ms_per_sweep = ms / n_times;
+        for (int k = 0; k < n_times; ++k) {
+            float t = 0.f;
+            SMRT_HIP(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
+            ks += t;
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        *ms_per_pass = ms / n_times;
+        *ms_sweep_kernel = ks / n_times;
         check_sweep_flag(x);
+    });
+}
+
+extern "C" smrt_status smrt_get_moments(smrt_ctx *x, double *moments) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(moments != nullptr, "moments is NULL");
+        d2h(moments, x->d_mom.p, 8 * x->d_mom.n, x->stream);
+        SMRT_HIP(hipStreamSynchronize(x->stream));
     });
 }

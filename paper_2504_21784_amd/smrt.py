@@ -89,8 +89,9 @@ _SIGS = {
     "smrt_compute_closures": ([C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp], C.c_int),
     "smrt_lo_solve": ([C.c_void_p, _dp, _dp, C.c_double, _dp, _dp, _dp, C.POINTER(StepStats)], C.c_int),
     "smrt_step": ([C.c_void_p, C.c_double, C.POINTER(StepStats)], C.c_int),
-    "smrt_sweep_resident": ([C.c_void_p, C.c_double, C.c_int, _dp], C.c_int),
+    "smrt_sweep_resident": ([C.c_void_p, C.c_double, C.c_int, _dp, _dp], C.c_int),
     "smrt_get_info": ([C.c_void_p, C.POINTER(Info)], C.c_int),
+    "smrt_get_moments": ([C.c_void_p, _dp], C.c_int),
     "smrt_set_launch": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
 }
 
@@ -250,13 +251,19 @@ class Context:
                                          C.byref(st)))
         return E, F, T, st.as_dict()
 
+    def get_moments(self):
+        m = np.zeros((27 if self.p.dim == 2 else 8, self.p.n_nodes))
+        self._check(self.L.smrt_get_moments(self.h, _p(m)))
+        return m
+
     def step(self, dt=None) -> dict:
         st = StepStats()
         self._check(self.L.smrt_step(self.h, float(dt if dt is not None else self.p.dt), C.byref(st)))
         return st.as_dict()
 
-    def sweep_resident(self, dt=None, n_times=1) -> float:
-        ms = C.c_double(0.0)
+    def sweep_resident(self, dt=None, n_times=1):
+        """Returns (ms per high-order pass, ms of the sweep kernel alone)."""
+        ms, ks = C.c_double(0.0), C.c_double(0.0)
         self._check(self.L.smrt_sweep_resident(self.h, float(dt if dt is not None else self.p.dt), int(n_times),
-                                               C.byref(ms)))
-        return ms.value
+                                               C.byref(ms), C.byref(ks)))
+        return ms.value, ks.value
