@@ -45,6 +45,7 @@ struct smrt_ctx {
     DevBuf<uint64_t> d_trace;
     int cur = 0;
     // FP64 state and work arrays
+    DevBuf<double> d_qnat;   // q_iso [node][G] FP64 (2D: gathered into the skewed tables)
     DevBuf<double> d_T, d_E, d_F, d_Eho, d_Fho, d_mom, d_sig, d_sigP, d_sigF, d_clos, d_Tl, d_El, d_Tn, d_En, d_Tstar,
         d_Estar, d_Fstar, d_sigEho;
     LoSolver lo;
@@ -496,8 +497,11 @@ extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_d
         p->d_psi[1].alloc(psi_count(p) * p->rs);
         p->d_psi[0].zero(p->stream);
         p->d_psi[1].zero(p->stream);
-        p->d_qiso.alloc((int64_t)p->nn * p->G * p->rs);
-        p->d_sig2.alloc((int64_t)p->ncell * p->G * 2 * p->rs);
+        // sweep tables: 2D per-quadrant skewed layout, 1D natural layout
+        const int64_t tab_cells = p->dim == 2 ? 4 * cell_slab(p->nx, p->ny) : p->ncell;
+        p->d_qiso.alloc(tab_cells * p->G * p->npc * p->rs);
+        p->d_sig2.alloc(tab_cells * p->G * 2 * p->rs);
+        if (p->dim == 2) p->d_qnat.alloc((int64_t)p->nn * p->G);
         p->d_inflow.alloc((int64_t)p->nang * p->G * p->NB * p->rs);
         for (auto *b : {&p->d_T, &p->d_E, &p->d_Eho, &p->d_sigP, &p->d_sigF, &p->d_Tl, &p->d_El, &p->d_Tn, &p->d_En,
                         &p->d_Tstar, &p->d_Estar, &p->d_sigEho})
@@ -644,23 +648,34 @@ extern "C" smrt_status smrt_sweep(smrt_ctx *x, const double *sig_t, const double
         h2d(t_st.p, sig_t, 8 * ng, x->stream);
         h2d(t_s.p, sig, 8 * ng, x->stream);
         h2d(t_q.p, q_iso, 8 * x->nn * x->G, x->stream);
-        t_sig2.alloc(ng * 2 * x->rs);
-        t_qiso.alloc((int64_t)x->nn * x->G * x->rs);
+        const int64_t tab_cells = x->dim == 2 ? 4 * cell_slab(x->nx, x->ny) : x->ncell;
+        t_sig2.alloc(tab_cells * x->G * 2 * x->rs);
+        t_qiso.alloc(tab_cells * x->G * x->npc * x->rs);
         t_in.alloc(psi_count(x) * x->rs);
         t_out.alloc(psi_count(x) * x->rs);
         t_inflow.alloc((int64_t)x->nang * x->G * x->NB * x->rs);
         t_abi.alloc(na);
         if (psi_prev) h2d(t_abi.p, psi_prev, 8 * na, x->stream);
         if (x->fp32) {
-            run_sig_to_internal<float>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (float *)t_sig2.p);
-            run_qiso_to_internal<float>(x->stream, x->nn, x->G, x->npc, t_q.p, (float *)t_qiso.p);
+            if (x->dim == 2) {
+                run_stab2d<float>(x->stream, x->nx, x->ny, x->G, t_s.p, t_st.p, 0.0, (float *)t_sig2.p);
+                run_qtab2d<float>(x->stream, x->nx, x->ny, x->G, nullptr, nullptr, 0.0, 0.0, nullptr, t_q.p, (float *)t_qiso.p);
+            } else {
+                run_sig_to_internal<float>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (float *)t_sig2.p);
+                run_qiso_to_internal<float>(x->stream, x->nn, x->G, x->npc, t_q.p, (float *)t_qiso.p);
+            }
             if (psi_prev) {
                 if (x->dim == 2) run_psi_to_internal<float>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, t_abi.p, (float *)t_in.p);
                 else run_copy_to<float>(x->stream, na, t_abi.p, (float *)t_in.p);
             }
         } else {
-            run_sig_to_internal<double>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (double *)t_sig2.p);
-            run_qiso_to_internal<double>(x->stream, x->nn, x->G, x->npc, t_q.p, (double *)t_qiso.p);
+            if (x->dim == 2) {
+                run_stab2d<double>(x->stream, x->nx, x->ny, x->G, t_s.p, t_st.p, 0.0, (double *)t_sig2.p);
+                run_qtab2d<double>(x->stream, x->nx, x->ny, x->G, nullptr, nullptr, 0.0, 0.0, nullptr, t_q.p, (double *)t_qiso.p);
+            } else {
+                run_sig_to_internal<double>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (double *)t_sig2.p);
+                run_qiso_to_internal<double>(x->stream, x->nn, x->G, x->npc, t_q.p, (double *)t_qiso.p);
+            }
             if (psi_prev) {
                 if (x->dim == 2) run_psi_to_internal<double>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, t_abi.p, (double *)t_in.p);
                 else run_copy_to<double>(x->stream, na, t_abi.p, (double *)t_in.p);
@@ -712,8 +727,8 @@ extern "C" smrt_status smrt_compute_closures(smrt_ctx *x, const double *moments,
         q.alloc((int64_t)x->nn * x->G * x->rs);
         h2d(m.p, moments, 8 * m.n, x->stream); h2d(Tl.p, T_l, 8 * x->nn, x->stream); h2d(Es.p, Estar, 8 * x->nn, x->stream);
         h2d(Fs.p, Fstar, 8 * Fs.n, x->stream); h2d(sg.p, sig, 8 * sg.n, x->stream);
-        if (x->fp32) run_source<float>(x->stream, x->nn, x->npc, x->G, Tl.p, x->d_nu.p, x->a, x->c, sg.p, (float *)q.p, sP.p, sF.p);
-        else run_source<double>(x->stream, x->nn, x->npc, x->G, Tl.p, x->d_nu.p, x->a, x->c, sg.p, (double *)q.p, sP.p, sF.p);
+        if (x->fp32) run_source<float>(x->stream, x->nn, x->npc, x->G, Tl.p, x->d_nu.p, x->a, x->c, sg.p, (float *)q.p, nullptr, sP.p, sF.p);
+        else run_source<double>(x->stream, x->nn, x->npc, x->G, Tl.p, x->d_nu.p, x->a, x->c, sg.p, (double *)q.p, nullptr, sP.p, sF.p);
         run_closures(x->stream, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt, m.p, sP.p, sF.p, Es.p, Fs.p, out.p));
         d2h(closures_out, out.p, 8 * out.n, x->stream);
         SMRT_HIP(hipStreamSynchronize(x->stream));
@@ -749,14 +764,26 @@ extern "C" smrt_status smrt_lo_solve(smrt_ctx *x, const double *closures, const 
 // prepare the per-step opacity table and return 1/(c dt)
 static double prepare_step_tables(smrt_ctx *x, double dt) {
     const double icdt = 1.0 / (x->c * dt);
-    if (x->fp32) run_opacity<float>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, (float *)x->d_sig2.p);
-    else run_opacity<double>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, (double *)x->d_sig2.p);
+    const bool d2 = x->dim == 2;
+    if (x->fp32) {
+        run_opacity<float>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, d2 ? nullptr : (float *)x->d_sig2.p);
+        if (d2) run_stab2d<float>(x->stream, x->nx, x->ny, x->G, x->d_sig.p, nullptr, icdt, (float *)x->d_sig2.p);
+    } else {
+        run_opacity<double>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, d2 ? nullptr : (double *)x->d_sig2.p);
+        if (d2) run_stab2d<double>(x->stream, x->nx, x->ny, x->G, x->d_sig.p, nullptr, icdt, (double *)x->d_sig2.p);
+    }
     return icdt;
 }
 
 static void run_source_at(smrt_ctx *x, const double *T) {
-    if (x->fp32) run_source<float>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, (float *)x->d_qiso.p, x->d_sigP.p, x->d_sigF.p);
-    else run_source<double>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, (double *)x->d_qiso.p, x->d_sigP.p, x->d_sigF.p);
+    const bool d2 = x->dim == 2;
+    if (x->fp32) {
+        run_source<float>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (float *)x->d_qiso.p, d2 ? x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p);
+        if (d2) run_qtab2d<float>(x->stream, x->nx, x->ny, x->G, nullptr, nullptr, 0.0, 0.0, nullptr, x->d_qnat.p, (float *)x->d_qiso.p);
+    } else {
+        run_source<double>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (double *)x->d_qiso.p, d2 ? x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p);
+        if (d2) run_qtab2d<double>(x->stream, x->nx, x->ny, x->G, nullptr, nullptr, 0.0, 0.0, nullptr, x->d_qnat.p, (double *)x->d_qiso.p);
+    }
 }
 
 extern "C" smrt_status smrt_step(smrt_ctx *x, double dt, smrt_step_stats *stats) {

@@ -15,6 +15,7 @@ constexpr int CHANNELS = 4;         // (angle, group) channels per wave (64 / BA
 constexpr int NMOM2D = 9;           // per node per quadrant: 6 quadrant sums + 3 sigma-weighted
 constexpr int PART_PER_CELL = 4 * NMOM2D;   // partial moments per cell per chunk
 constexpr int SPIN_LIMIT = 1 << 20;          // bounded wait on a band trace
+constexpr int TRACE_LAG = 8;                 // columns a band stays behind the band below
 constexpr int MAX_WG_THREADS = 512;          // sweep workgroups: at most 8 waves (256 VGPRs each)
 
 #define SMRT_HIP(call)                                                                   \
@@ -39,8 +40,8 @@ struct Sweep2DArgs {
     const int2 *slot_pair;           // [NQC*R] (direction, group) or (-1,-1)
     const void *dirs;                // per direction: real[8] = mu, eta, w, w*mu, w*eta, w*mu^2, w*mu*eta, w*eta^2
     const void *hx, *hy;             // real[nx], real[ny]
-    const void *sig2;                // real2 [G][cell] = (sigma_t, sigma)
-    const void *qiso;                // real [G][cell][4] natural node order
+    const void *sig2;                // real2 [4 quad][G][band][t][r] = (sigma_t, sigma), skewed canonical
+    const void *qiso;                // real4 [4 quad][G][band][t][r], canonical node order
     const void *psi_prev;            // internal layout or nullptr
     void *psi_out;                   // internal layout
     const void *inflow;              // real [d][G][NB]
@@ -54,6 +55,13 @@ struct Sweep2DArgs {
 __host__ __device__ inline int64_t psi_slab(int nx, int ny) {
     int nb = (ny + BAND_ROWS - 1) / BAND_ROWS;
     return (int64_t)nb * (nx + BAND_ROWS - 1) * BAND_ROWS * 4;
+}
+
+// Per-(quadrant, group) cell tables use the same skewed band layout as the
+// angular flux so that a wave's diagonal of cells is contiguous in memory.
+__host__ __device__ inline int64_t cell_slab(int nx, int ny) {
+    int nb = (ny + BAND_ROWS - 1) / BAND_ROWS;
+    return (int64_t)nb * (nx + BAND_ROWS - 1) * BAND_ROWS;
 }
 
 template <typename real>

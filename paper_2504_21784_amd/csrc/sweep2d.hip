@@ -63,12 +63,6 @@ __device__ __forceinline__ void put_trace(uint64_t *p, double v, uint32_t ep) {
     __hip_atomic_store(p, pack_word(ep, (uint32_t)b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(p + 1, pack_word(ep, (uint32_t)(b >> 32)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void pack_valid(uint64_t *w, float v, uint32_t ep) { w[0] = pack_word(ep, __float_as_uint(v)); }
-__device__ __forceinline__ void pack_valid(uint64_t *w, double v, uint32_t ep) {
-    uint64_t b = __double_as_longlong(v);
-    w[0] = pack_word(ep, (uint32_t)b);
-    w[1] = pack_word(ep, (uint32_t)(b >> 32));
-}
 __device__ __forceinline__ uint64_t poll_word(const uint64_t *p) {
     return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -95,12 +89,13 @@ __device__ __forceinline__ double shift_up_one_row<double>(double v) {
 
 template <typename real, int K>
 struct StepIn {
+    // raw loaded values only: any reordering happens at use, so the loads of
+    // several steps can stay in flight
     real psi[K][4];     // I* (canonical node order)
-    real q[K][4];       // q_iso (canonical node order)
+    real qn[K][4];      // q_iso (canonical node order)
     real st[K], sg[K];  // sigma_t, sigma
-    // y-upwind words for row 0: band trace words (band > 0) or the boundary
-    // inflow packed as already-valid words (band 0)
-    uint64_t tw[K][2 * trace_words<real>::n];
+    real bot[K][2];     // y- boundary inflow for canonical nodes 0, 1 (band 0)
+    uint64_t tw[K][2 * trace_words<real>::n];   // band trace words (band > 0)
     real hx;
 };
 
@@ -136,7 +131,6 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
     const int jc = band * BAND_ROWS + r;
     const bool row_ok = jc < ny;
     const int jn = fy ? ny - 1 - jc : jc;
-    const int lflip = (fx ? 1 : 0) | (fy ? 2 : 0);   // canonical <-> natural local node
 
     const real *dirs = static_cast<const real *>(A.dirs);
     const real *hxa = static_cast<const real *>(A.hx);
@@ -156,7 +150,7 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
     for (int k = 0; k < K; ++k) {
         const int slot = (wv * CHANNELS + ch) * K + k;
         const int2 pg = A.slot_pair[qc * A.R + slot];
-        dd[k] = pg.x;
+        dd[k] = pg.x < 0 ? 0 : pg.x;      // inactive slots (-1) address direction 0
         gg[k] = pg.y < 0 ? 0 : pg.y;
         act[k] = pg.x >= 0 && row_ok;
         const int d = pg.x < 0 ? 0 : pg.x;
@@ -168,6 +162,7 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
         slab[k] = (((int64_t)d * G + gg[k]) * nbands + band) * NT * BAND_ROWS;
     }
     const real hy = row_ok ? hya[jn] : real(1);
+    const int64_t tslab = (int64_t)nbands * NT * BAND_ROWS;   // cells per (quadrant, group) table slab
     const real icdt = (real)A.inv_c_dt;
 
     // boundary side bases in the general inflow array [d][g][NB]
@@ -179,64 +174,97 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
     const bool produce = (r == BAND_ROWS - 1) && (band + 1 < nbands);
     const bool consume = (r == 0) && (band > 0);
 
+    // All prefetch loads are issued unconditionally from clamped (always
+    // valid) addresses into raw registers, so several steps of loads stay in
+    // flight: a load under a branch, or a reordering of its result, makes the
+    // compiler wait for every outstanding memory operation.
+    // psi_prev may be absent (raw sweep without a time-edge source): loads then
+    // read psi_out (valid memory) and the values are discarded at use.
+    const bool has_prev = pprev != nullptr;
+    const r4 *pp_eff = has_prev ? pprev : pout;
     auto load_step = [&](int t, StepIn<real, K> &S) {
         const int ic = t - r;
         const bool col_ok = ic >= 0 && ic < nx;
-        const int in = fx ? nx - 1 - ic : ic;
-        S.hx = (col_ok) ? hxa[in] : real(1);
-        const int cell = in + nx * jn;
+        const int icc = col_ok ? ic : 0;
+        const int in = fx ? nx - 1 - icc : icc;
+        S.hx = hxa[in];
+        // band trace words first (band > 0, row 0): issued before the other loads.
+        // Every lane of a channel reads the word its row-0 lane needs (column t),
+        // so a wave touches one address per channel and no word is contended.
+        const int tcol = t < nx ? t : nx - 1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t *src = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + tcol) * 2 * TW;
+#pragma unroll
+            for (int u = 0; u < 2 * TW; ++u) S.tw[k][u] = poll_word(src + u);
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const bool ok = act[k] && col_ok;
-            if (ok) {
-                const r2 s = sig2[(int64_t)gg[k] * nx * ny + cell];
-                S.st[k] = s.x;
-                S.sg[k] = s.y;
-                const r4 qn = qiso[(int64_t)gg[k] * nx * ny + cell];
-                const real qa[4] = {qn.x, qn.y, qn.z, qn.w};
-#pragma unroll
-                for (int l = 0; l < 4; ++l) S.q[k][l] = qa[l ^ lflip];
-                if (pprev) {
-                    const r4 p = pprev[slab[k] + (int64_t)t * BAND_ROWS + r];
-                    S.psi[k][0] = p.x; S.psi[k][1] = p.y; S.psi[k][2] = p.z; S.psi[k][3] = p.w;
-                } else {
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) S.psi[k][l] = 0;
-                }
-                if (r == 0 && band == 0) {
-                    const int64_t ib = ((int64_t)dd[k] * G + gg[k]) * A.NB;
-                    const int lx0 = fx ? 1 : 0;
-                    pack_valid(S.tw[k], inflow[ib + yside + 2 * in + lx0], epoch);
-                    pack_valid(S.tw[k] + TW, inflow[ib + yside + 2 * in + (1 - lx0)], epoch);
-                }
-                if (consume) {
-                    const uint64_t *src = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + ic) * 2 * TW;
-#pragma unroll
-                    for (int u = 0; u < 2 * TW; ++u) S.tw[k][u] = poll_word(src + u);
-                }
-            }
+            // (quadrant, group) tables in the skewed layout: contiguous per channel
+            const int64_t ti = ((int64_t)quad * G + gg[k]) * tslab + ((int64_t)band * NT + t) * BAND_ROWS + r;
+            const r2 s = sig2[ti];
+            S.st[k] = s.x;
+            S.sg[k] = s.y;
+            const r4 qn = qiso[ti];
+            S.qn[k][0] = qn.x; S.qn[k][1] = qn.y; S.qn[k][2] = qn.z; S.qn[k][3] = qn.w;
+            const r4 p = pp_eff[ok ? slab[k] + (int64_t)t * BAND_ROWS + r : 0];
+            S.psi[k][0] = p.x; S.psi[k][1] = p.y; S.psi[k][2] = p.z; S.psi[k][3] = p.w;
+            // y- boundary inflow (band 0, row 0) -- other lanes read one shared valid word
+            const int64_t ib = ((int64_t)dd[k] * G + gg[k]) * A.NB;
+            const int bnd = (band == 0 && r == 0 && ok) ? 1 : 0;
+            const int lx0 = fx ? 1 : 0;
+            const int64_t bbase = ib + yside + bnd * (2 * in);   // always a valid index
+            S.bot[k][0] = inflow[bbase + bnd * lx0];
+            S.bot[k][1] = inflow[bbase + bnd * (1 - lx0)];
         }
     };
-
-    StepIn<real, K> buf[PF + 1];
-#pragma unroll
-    for (int u = 0; u <= PF; ++u)
-        if (u < NT) load_step(u, buf[u]);
 
     real xl[K][2], yb[K][2];   // x-upwind (nodes 1,3 of the left cell), y-upwind (nodes 2,3 of the cell below)
     real left[K][2];           // canonical x- boundary inflow of this row (nodes 0, 2)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         xl[k][0] = xl[k][1] = yb[k][0] = yb[k][1] = 0;
-        left[k][0] = left[k][1] = 0;
-        if (act[k]) {
-            const int64_t ib = ((int64_t)dd[k] * G + gg[k]) * A.NB;
-            const int ly0 = fy ? 1 : 0;
-            left[k][0] = inflow[ib + xside + 2 * jn + ly0];
-            left[k][1] = inflow[ib + xside + 2 * jn + (1 - ly0)];
+        const int64_t ib = ((int64_t)dd[k] * G + gg[k]) * A.NB;
+        const int ly0 = fy ? 1 : 0;
+        const int jv = row_ok ? jn : 0;
+        left[k][0] = inflow[ib + xside + 2 * jv + ly0];
+        left[k][1] = inflow[ib + xside + 2 * jv + (1 - ly0)];
+    }
+    StepIn<real, K> buf[PF + 1];
+#pragma unroll
+    for (int u = 0; u <= PF; ++u)
+        if (u < NT) load_step(u, buf[u]);
+    // One full wait after the prologue: the loop then starts from a state with
+    // no pending loads, so the per-step waits only cover the slot being used.
+    __builtin_amdgcn_s_waitcnt(0);
+    int err = 0;
+
+    // Start gate: a band begins only once the band below has published the
+    // trace of column TRACE_LAG, so that in steady state each prefetched
+    // trace word was written several steps before it is needed.
+    if (band > 0) {
+        const int gcol = TRACE_LAG < nx - 1 ? TRACE_LAG : nx - 1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint64_t *g = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + gcol) * 2 * TW;
+            bool waiting = (r == 0) && act[k];
+            int spins = 0;
+            while (waiting) {
+                bool rd = true;
+#pragma unroll
+                for (int u2 = 0; u2 < 2 * TW; ++u2) rd &= (uint32_t)(poll_word(g + u2) >> 32) == epoch;
+                if (rd) break;
+                if (++spins > SPIN_LIMIT ||
+                    __hip_atomic_load(&A.ctr[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    err = 1;
+                    atomicOr(&A.ctr[3], 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
         }
     }
-    int err = 0;
 
     for (int t0 = 0; t0 < NT; t0 += PF + 1) {
 #pragma unroll
@@ -257,31 +285,39 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
                     // y-upwind values: from the lane below (already shifted), the band
                     // below (trace words) or the boundary.
                     real yin0 = yb[k][0], yin1 = yb[k][1];
-                    if (r == 0 && ok) {
-                        {
-                            uint64_t *tw = S.tw[k];
-                            const uint64_t *src = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + ic) * 2 * TW;
-                            int spins = 0;
-                            bool ready = true;
+                    if (r == 0 && band == 0) {
+                        yin0 = S.bot[k][0];
+                        yin1 = S.bot[k][1];
+                    } else if (r == 0) {
+                        uint64_t *tw = S.tw[k];
+                        bool ready = true;
 #pragma unroll
-                            for (int u2 = 0; u2 < 2 * TW; ++u2) ready &= (uint32_t)(tw[u2] >> 32) == epoch;
-                            while (!ready && !err) {
-                                // bounded wait; any timed-out wave raises ctr[3] and every
-                                // other waiter gives up at once
+                        for (int u2 = 0; u2 < 2 * TW; ++u2) ready &= (uint32_t)(tw[u2] >> 32) == epoch;
+                        const bool wait_here = ok && !ready && !err;
+                        if (__builtin_amdgcn_ballot_w64(wait_here) != 0) {   // rare: trace not yet valid
+                            const uint64_t *src = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + (ok ? ic : 0)) * 2 * TW;
+                            int spins = 0;
+                            bool waiting = wait_here;
+                            while (waiting) {
+                                // bounded wait; a timed-out wave raises ctr[3] and every other
+                                // waiter gives up at once
                                 if (++spins > SPIN_LIMIT ||
                                     __hip_atomic_load(&A.ctr[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                                     err = 1;
+                                    atomicOr(&A.ctr[3], 1);
                                     break;
                                 }
                                 __builtin_amdgcn_s_sleep(1);
-                                ready = true;
+                                bool rd = true;
 #pragma unroll
                                 for (int u2 = 0; u2 < 2 * TW; ++u2) {
                                     tw[u2] = poll_word(src + u2);
-                                    ready &= (uint32_t)(tw[u2] >> 32) == epoch;
+                                    rd &= (uint32_t)(tw[u2] >> 32) == epoch;
                                 }
+                                waiting = !rd;
                             }
-                            if (!ready && err) atomicOr(&A.ctr[3], 1);
+                        }
+                        if (ok) {
                             yin0 = word_value(tw, real(0));
                             yin1 = word_value(tw + TW, real(0));
                         }
@@ -290,10 +326,13 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
                     const real xin2 = (ic == 0) ? left[k][1] : xl[k][1];
                     const real a = am[k] * hy * real(0.5);
                     const real b = bm[k] * hx * real(0.5);
-                    real rh0 = wgt * (S.q[k][0] + icdt * S.psi[k][0]) + a * xin0 + b * yin0;
-                    real rh1 = wgt * (S.q[k][1] + icdt * S.psi[k][1]) + b * yin1;
-                    real rh2 = wgt * (S.q[k][2] + icdt * S.psi[k][2]) + a * xin2;
-                    real rh3 = wgt * (S.q[k][3] + icdt * S.psi[k][3]);
+                    const real q0 = S.qn[k][0], q1 = S.qn[k][1], q2 = S.qn[k][2], q3 = S.qn[k][3];
+                    const real ps0 = has_prev ? S.psi[k][0] : real(0), ps1 = has_prev ? S.psi[k][1] : real(0);
+                    const real ps2 = has_prev ? S.psi[k][2] : real(0), ps3 = has_prev ? S.psi[k][3] : real(0);
+                    real rh0 = wgt * (q0 + icdt * ps0) + a * xin0 + b * yin0;
+                    real rh1 = wgt * (q1 + icdt * ps1) + b * yin1;
+                    real rh2 = wgt * (q2 + icdt * ps2) + a * xin2;
+                    real rh3 = wgt * (q3 + icdt * ps3);
                     const real dg = real(0.5) * (a + b) + S.st[k] * wgt;
                     const real ha = real(0.5) * a, hb = real(0.5) * b;
                     const real y0 = dg * rh0 - ha * rh1 - hb * rh2;

@@ -105,8 +105,10 @@ __global__ void k_opacity(int ncell, int npc, int G, const double *T, const int 
             s = fmin(fmax(s, clip_lo), clip_hi);
         }
         sig[(int64_t)c * G + g] = s;
-        sig2[2 * ((int64_t)g * ncell + c)] = (real)(s + inv_c_dt);
-        sig2[2 * ((int64_t)g * ncell + c) + 1] = (real)s;
+        if (sig2) {
+            sig2[2 * ((int64_t)g * ncell + c)] = (real)(s + inv_c_dt);
+            sig2[2 * ((int64_t)g * ncell + c) + 1] = (real)s;
+        }
     }
 }
 
@@ -115,7 +117,7 @@ __global__ void k_opacity(int ncell, int npc, int G, const double *T, const int 
 // ---------------------------------------------------------------------------
 template <typename real>
 __global__ void k_source(int nn, int npc, int G, const double *T, const double *nu, double a, double c,
-                         const double *sig, real *qiso, double *sigP, double *sigF) {
+                         const double *sig, real *qiso, double *qnat, double *sigP, double *sigF) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
     double b[MAXG], r[MAXG];
@@ -127,7 +129,8 @@ __global__ void k_source(int nn, int npc, int G, const double *T, const double *
     double sb = 0, sbs = 0, sr = 0, srs = 0;
     for (int g = 0; g < G; ++g) {
         const double s = sig[(int64_t)cell * G + g];
-        qiso[((int64_t)g * ncell + cell) * npc + l] = (real)(s * B * b[g]);
+        if (qiso) qiso[((int64_t)g * ncell + cell) * npc + l] = (real)(s * B * b[g]);
+        if (qnat) qnat[(int64_t)n * G + g] = s * B * b[g];
         sb += b[g];
         sbs += b[g] * s;
         sr += r[g];
@@ -135,6 +138,77 @@ __global__ void k_source(int nn, int npc, int G, const double *T, const double *
     }
     sigP[n] = sbs / sb;
     sigF[n] = srs / sr;
+}
+
+// ---------------------------------------------------------------------------
+// 2D sweep tables in the skewed band layout of the sweep, one copy per
+// quadrant: slot (band, t, r) of quadrant q holds the canonical cell
+// (t - r, 16 band + r); entries outside the mesh are padding.
+// ---------------------------------------------------------------------------
+__device__ inline bool skew_to_cell(int nx, int ny, int q, int64_t slot, int &cell, int &flip) {
+    const int NT = nx + BAND_ROWS - 1;
+    const int r = (int)(slot % BAND_ROWS);
+    const int64_t bt = slot / BAND_ROWS;
+    const int t = (int)(bt % NT), band = (int)(bt / NT);
+    const int ic = t - r, jc = band * BAND_ROWS + r;
+    if (ic < 0 || ic >= nx || jc >= ny) return false;
+    const bool fx = (q == 1 || q == 2), fy = (q == 2 || q == 3);
+    cell = (fx ? nx - 1 - ic : ic) + nx * (fy ? ny - 1 - jc : jc);
+    flip = (fx ? 1 : 0) | (fy ? 2 : 0);
+    return true;
+}
+
+// (sigma_t, sigma) per (quadrant, group, skewed cell) from sigma [cell][G] (and sigma_t if given)
+template <typename real>
+__global__ void k_stab2d(int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab) {
+    const int64_t cs = cell_slab(nx, ny);
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 4 * (int64_t)G * cs) return;
+    const int64_t slot = i % cs;
+    const int qg = (int)(i / cs), g = qg % G, q = qg / G;
+    int cell, flip;
+    if (!skew_to_cell(nx, ny, q, slot, cell, flip)) {
+        stab[2 * i] = real(1);
+        stab[2 * i + 1] = real(0);
+        return;
+    }
+    const double s = sig[(int64_t)cell * G + g];
+    stab[2 * i] = (real)(sigt ? sigt[(int64_t)cell * G + g] : s + icdt);
+    stab[2 * i + 1] = (real)s;
+}
+
+// q_iso per (quadrant, group, skewed cell), canonical node order:
+// from T (emission sigma_g a c T^4 b_g(T)/4pi) or from an ABI array q[node][G]
+template <typename real>
+__global__ void k_qtab2d(int nx, int ny, int G, const double *T, const double *nu, double a, double c,
+                         const double *sig, const double *qabi, real *qtab) {
+    const int64_t cs = cell_slab(nx, ny);
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 4 * (int64_t)G * cs) return;
+    const int64_t slot = i % cs;
+    const int qg = (int)(i / cs), g = qg % G, q = qg / G;
+    int cell, flip;
+    if (!skew_to_cell(nx, ny, q, slot, cell, flip)) {
+        for (int lc = 0; lc < 4; ++lc) qtab[4 * i + lc] = real(0);
+        return;
+    }
+    for (int lc = 0; lc < 4; ++lc) {
+        const int n = 4 * cell + (lc ^ flip);
+        double v;
+        if (qabi) {
+            v = qabi[(int64_t)n * G + g];
+        } else {
+            const double Tn = T[n];
+            double bg = 1.0;
+            if (G > 1) {
+                const double lo = g == 0 ? 0.0 : planck_cum(nu[g] / Tn);
+                const double hi = g == G - 1 ? 1.0 : planck_cum(nu[g + 1] / Tn);
+                bg = hi - lo;
+            }
+            v = sig[(int64_t)cell * G + g] * a * c * Tn * Tn * Tn * Tn / (4.0 * M_PI) * bg;
+        }
+        qtab[4 * i + lc] = (real)v;
+    }
 }
 
 // Isotropic equilibrium intensity B_g(T_n)/(4 pi) in the ABI layout [d][g][node]
@@ -373,8 +447,19 @@ void run_opacity(hipStream_t s, int ncell, int npc, int G, const double *T, cons
 }
 template <typename real>
 void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const double *nu, double a, double c,
-                const double *sig, real *qiso, double *sigP, double *sigF) {
-    hipLaunchKernelGGL(k_source<real>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, npc, G, T, nu, a, c, sig, qiso, sigP, sigF);
+                const double *sig, real *qiso, double *qnat, double *sigP, double *sigF) {
+    hipLaunchKernelGGL(k_source<real>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, npc, G, T, nu, a, c, sig, qiso, qnat, sigP, sigF);
+}
+template <typename real>
+void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab) {
+    const int64_t n = 4 * (int64_t)G * cell_slab(nx, ny);
+    hipLaunchKernelGGL(k_stab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, sig, sigt, icdt, stab);
+}
+template <typename real>
+void run_qtab2d(hipStream_t s, int nx, int ny, int G, const double *T, const double *nu, double a, double c,
+                const double *sig, const double *qabi, real *qtab) {
+    const int64_t n = 4 * (int64_t)G * cell_slab(nx, ny);
+    hipLaunchKernelGGL(k_qtab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, T, nu, a, c, sig, qabi, qtab);
 }
 void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
                      double *psi) {
@@ -437,8 +522,11 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
     template void run_opacity<real>(hipStream_t, int, int, int, const double *, const int *, int, const double *,  \
                                     double, double, const double *, double, double *, real *);                      \
     template void run_source<real>(hipStream_t, int, int, int, const double *, const double *, double, double,      \
-                                   const double *, real *, double *, double *);                                     \
+                                   const double *, real *, double *, double *, double *);                           \
     template void run_fill_inflow<real>(hipStream_t, int, int, int, int, int, const double *, real *);              \
+    template void run_stab2d<real>(hipStream_t, int, int, int, const double *, const double *, double, real *);     \
+    template void run_qtab2d<real>(hipStream_t, int, int, int, const double *, const double *, double, double,      \
+                                   const double *, const double *, real *);                                        \
     template void run_copy_to<real>(hipStream_t, int64_t, const double *, real *);                                  \
     template void run_qiso_to_internal<real>(hipStream_t, int, int, int, const double *, real *);                   \
     template void run_sig_to_internal<real>(hipStream_t, int, int, const double *, const double *, real *);         \

@@ -58,7 +58,7 @@ def test_sweep2d_fp64_matches_oracle(smrt_mod, oracle_mod, nx, ny, sn, G):
 
 
 @pytest.mark.parametrize("nx,ny,sn,G", [(37, 35, 4, 3), (20, 33, 8, 4), (64, 48, 8, 2)])
-@pytest.mark.parametrize("launch", [(0, 1), (0, 2), (2, 1)])
+@pytest.mark.parametrize("launch", [(0, 1), (0, 2), (2, 1), (8, 2)])
 def test_sweep2d_fp32_matches_oracle(smrt_mod, oracle_mod, nx, ny, sn, G, launch):
     p = _prob2d(nx, ny, sn, G, seed=3)
     print(f"shape nx={nx} ny={ny} S{sn} G={G} launch={launch}", flush=True)
@@ -76,6 +76,20 @@ def test_sweep2d_fp32_matches_oracle(smrt_mod, oracle_mod, nx, ny, sn, G, launch
     assert np.linalg.norm(phi - phi_ref) / np.linalg.norm(phi_ref) < 1e-5
     for m in range(27):
         assert _rel(mom[m], ref_mom[m]) < 1e-5, m
+    ctx.close()
+
+
+def test_sweep2d_inactive_slots_large(smrt_mod, oracle_mod):
+    """Regression: chunks with inactive (angle, group) slots (8 waves x 2 pairs
+    = 64 slots for 40 pairs per quadrant) at a size where a negative slot
+    index would leave the inflow buffer."""
+    p = _prob2d(96, 80, 8, 4, seed=8)
+    sigt, q, pp, inf = W.random_sweep_inputs(p, seed=21)
+    ref = oracle_mod.Oracle(p).sweep(sigt, q, pp, 0.5, inf)
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP32)
+    ctx.set_launch(8, 2)
+    psi, _ = ctx.sweep(sigt, 0.5 * sigt, q, pp, 0.5, inf)
+    assert _rel(psi, ref) < 1e-5
     ctx.close()
 
 
