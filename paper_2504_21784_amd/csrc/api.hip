@@ -40,12 +40,13 @@ struct smrt_ctx {
     int user_NW = 0, user_K = 0;
     std::vector<int> qc_quad;
     std::vector<int> slot_pair;   // pairs (d, g)
+    ChunkRanges chunks{};         // chunk range of each quadrant
     DevBuf<int> d_qc_quad, d_slot_pair, d_ctr;
     DevBuf<unsigned char> d_psi[2], d_part, d_qiso, d_sig2, d_inflow;
     DevBuf<uint64_t> d_trace;
     int cur = 0;
     // FP64 state and work arrays
-    DevBuf<double> d_qnat;   // q_iso [node][G] FP64 (2D: gathered into the skewed tables)
+    DevBuf<double> d_qnat;   // q_iso [G][node] FP64 (2D: gathered into the skewed tables)
     DevBuf<double> d_T, d_E, d_F, d_Eho, d_Fho, d_mom, d_sig, d_sigP, d_sigF, d_clos, d_Tl, d_El, d_Tn, d_En, d_Tstar,
         d_Estar, d_Fstar, d_sigEho;
     LoSolver lo;
@@ -153,13 +154,19 @@ static void plan_sweep(smrt_ctx *x) {
         const int q = (mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3;
         qdirs[q].push_back(d);
     }
-    int maxP = 0;
-    for (int q = 0; q < 4; ++q) maxP = std::max(maxP, (int)qdirs[q].size() * x->G);
+    // A chunk = (quadrant, block of NW directions, block of 4K groups): wave w
+    // of a workgroup sweeps direction w of the block, its channel c the groups
+    // 4k + c of the group block.  Slots past the quadrant's directions or past
+    // G are inactive (-1, -1).
+    int maxD = 0;
+    for (int q = 0; q < 4; ++q) maxD = std::max(maxD, (int)qdirs[q].size());
     int K = x->user_K ? x->user_K : 1;
     if (x->fp32 == false) K = 1;
     int NW = x->user_NW;
-    if (!NW) NW = std::max(1, std::min(8, (maxP + 4 * K - 1) / (4 * K)));
-    if (!x->fp32 && NW > 8) NW = 8;
+    if (!NW) {
+        const int nblk = (maxD + 7) / 8;
+        NW = std::max(1, (maxD + nblk - 1) / nblk);
+    }
     x->NW = NW;
     x->K = K;
     x->R = 4 * NW * K;
@@ -167,26 +174,28 @@ static void plan_sweep(smrt_ctx *x) {
     x->NT = x->nx + BAND_ROWS - 1;
     x->qc_quad.clear();
     x->slot_pair.clear();
+    const int GB = 4 * K;
+    const int ngb = (x->G + GB - 1) / GB;
     for (int q = 0; q < 4; ++q) {
-        const int Pq = (int)qdirs[q].size() * x->G;
-        const int chunks = (Pq + x->R - 1) / x->R;
-        for (int ch = 0; ch < chunks; ++ch) {
-            x->qc_quad.push_back(q);
-            for (int s = 0; s < x->R; ++s) {
-                const int p = ch * x->R + s;
-                if (p < Pq) {
-                    const int nd = (int)qdirs[q].size();
-                    const int g = p / nd, dq = p % nd;
-                    x->slot_pair.push_back(qdirs[q][dq]);
-                    x->slot_pair.push_back(g);
-                } else {
-                    x->slot_pair.push_back(-1);
-                    x->slot_pair.push_back(-1);
-                }
+        const int nd = (int)qdirs[q].size();
+        const int ndb = (nd + NW - 1) / NW;
+        for (int db = 0; db < ndb; ++db)
+            for (int gb = 0; gb < ngb; ++gb) {
+                x->qc_quad.push_back(q);
+                for (int w = 0; w < NW; ++w)
+                    for (int c = 0; c < CHANNELS; ++c)
+                        for (int k = 0; k < K; ++k) {
+                            const int dq = db * NW + w, g = gb * GB + CHANNELS * k + c;
+                            const bool on = dq < nd && g < x->G;
+                            x->slot_pair.push_back(on ? qdirs[q][dq] : -1);
+                            x->slot_pair.push_back(on ? g : -1);
+                        }
             }
-        }
     }
     x->NQC = (int)x->qc_quad.size();
+    for (int q = 0; q <= 4; ++q) x->chunks.start[q] = 0;
+    for (int qc = 0; qc < x->NQC; ++qc) x->chunks.start[x->qc_quad[qc] + 1] = qc + 1;
+    for (int q = 1; q <= 4; ++q) x->chunks.start[q] = std::max(x->chunks.start[q], x->chunks.start[q - 1]);
     x->n_wg = x->NQC * x->nbands;
     x->d_qc_quad.alloc(x->NQC);
     x->d_slot_pair.alloc((int64_t)x->slot_pair.size());
@@ -223,8 +232,8 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
         if (x->fp32) launch_sweep2d<float>(a, x->stream);
         else launch_sweep2d<double>(a, x->stream);
         if (finalize) {
-            if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->NQC, x->d_qc_quad.p, (const float *)x->d_part.p, mom);
-            else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->NQC, x->d_qc_quad.p, (const double *)x->d_part.p, mom);
+            if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, mom);
+            else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, mom);
         }
     } else {
         Sweep1DArgs a{};
@@ -659,7 +668,7 @@ extern "C" smrt_status smrt_sweep(smrt_ctx *x, const double *sig_t, const double
         if (x->fp32) {
             if (x->dim == 2) {
                 run_stab2d<float>(x->stream, x->nx, x->ny, x->G, t_s.p, t_st.p, 0.0, (float *)t_sig2.p);
-                run_qtab2d<float>(x->stream, x->nx, x->ny, x->G, nullptr, nullptr, 0.0, 0.0, nullptr, t_q.p, (float *)t_qiso.p);
+                run_qtab2d<float>(x->stream, x->nx, x->ny, x->G, t_q.p, x->G, 1, (float *)t_qiso.p);
             } else {
                 run_sig_to_internal<float>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (float *)t_sig2.p);
                 run_qiso_to_internal<float>(x->stream, x->nn, x->G, x->npc, t_q.p, (float *)t_qiso.p);
@@ -671,7 +680,7 @@ extern "C" smrt_status smrt_sweep(smrt_ctx *x, const double *sig_t, const double
         } else {
             if (x->dim == 2) {
                 run_stab2d<double>(x->stream, x->nx, x->ny, x->G, t_s.p, t_st.p, 0.0, (double *)t_sig2.p);
-                run_qtab2d<double>(x->stream, x->nx, x->ny, x->G, nullptr, nullptr, 0.0, 0.0, nullptr, t_q.p, (double *)t_qiso.p);
+                run_qtab2d<double>(x->stream, x->nx, x->ny, x->G, t_q.p, x->G, 1, (double *)t_qiso.p);
             } else {
                 run_sig_to_internal<double>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (double *)t_sig2.p);
                 run_qiso_to_internal<double>(x->stream, x->nn, x->G, x->npc, t_q.p, (double *)t_qiso.p);
@@ -779,10 +788,10 @@ static void run_source_at(smrt_ctx *x, const double *T) {
     const bool d2 = x->dim == 2;
     if (x->fp32) {
         run_source<float>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (float *)x->d_qiso.p, d2 ? x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p);
-        if (d2) run_qtab2d<float>(x->stream, x->nx, x->ny, x->G, nullptr, nullptr, 0.0, 0.0, nullptr, x->d_qnat.p, (float *)x->d_qiso.p);
+        if (d2) run_qtab2d<float>(x->stream, x->nx, x->ny, x->G, x->d_qnat.p, 1, x->nn, (float *)x->d_qiso.p);
     } else {
         run_source<double>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (double *)x->d_qiso.p, d2 ? x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p);
-        if (d2) run_qtab2d<double>(x->stream, x->nx, x->ny, x->G, nullptr, nullptr, 0.0, 0.0, nullptr, x->d_qnat.p, (double *)x->d_qiso.p);
+        if (d2) run_qtab2d<double>(x->stream, x->nx, x->ny, x->G, x->d_qnat.p, 1, x->nn, (double *)x->d_qiso.p);
     }
 }
 
@@ -906,8 +915,8 @@ extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, 
             run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p, false);
             SMRT_HIP(hipEventRecord(ev[2 * k + 1], x->stream));
             if (x->dim == 2) {
-                if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->NQC, x->d_qc_quad.p, (const float *)x->d_part.p, x->d_mom.p);
-                else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->NQC, x->d_qc_quad.p, (const double *)x->d_part.p, x->d_mom.p);
+                if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, x->d_mom.p);
+                else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, x->d_mom.p);
             } else {
                 if (x->fp32) run_moments1d<float>(x->stream, x->nx, x->G, x->nang, (const float *)x->d_mu_w.p, x->d_sig.p, (const float *)pout, x->d_mom.p);
                 else run_moments1d<double>(x->stream, x->nx, x->G, x->nang, (const double *)x->d_mu_w.p, x->d_sig.p, (const double *)pout, x->d_mom.p);

@@ -30,6 +30,12 @@ struct Error {
     Error(smrt_status s, std::string m) : st(s), msg(std::move(m)) {}
 };
 
+// Chunks of a 2D sweep are ordered by quadrant: quadrant q owns chunks
+// [start[q], start[q+1]).
+struct ChunkRanges {
+    int start[5];
+};
+
 // Device-side description of one 2D sweep (one problem).
 struct Sweep2DArgs {
     int nx, ny, G, nbands, NT;       // NT = nx + BAND_ROWS - 1 steps per band

@@ -16,16 +16,22 @@
 // Work decomposition (CDNA4, wave64):
 //  * The mesh is viewed per quadrant in canonical coordinates (flipped so
 //    the sweep runs +x,+y) and cut into bands of 16 rows.
-//  * A wave = 4 channels x 16 rows: lane = channel*16 + row.  Each channel
-//    is one (direction, group) pair (times K pairs handled in sequence by
-//    the lane).  At step t the lane of row r handles column t - r, so a
-//    band is a diagonal wavefront inside the wave: the x-upwind trace stays
-//    in the lane's registers and the y-upwind trace moves one lane up with
-//    a DPP row shift.
-//  * A workgroup = NW waves on the same band of the same quadrant with
-//    disjoint (direction, group) pairs; their moment contributions are
-//    reduced through LDS every step (summed in FP64 in a fixed order) and
-//    one partial per cell and workgroup is written.
+//  * A wave = one direction and 4 channels x 16 rows: lane = channel*16 +
+//    row; channel c handles groups c, c+4, .. (K groups per lane, in
+//    sequence).  At step t the lane of row r handles column t - r, so a band
+//    is a diagonal wavefront inside the wave: the x-upwind trace stays in the
+//    lane's registers and the y-upwind trace moves one lane up with a DPP
+//    row shift.
+//  * Moments: because the direction is uniform across the wave, its
+//    contribution to every moment of a node is (wave-uniform coefficient) x
+//    (sum over the wave's groups of I) or x (sum of sigma_g I).  Each lane
+//    accumulates these two sums (4 nodes each), the 4 channels are summed
+//    with two gfx950 permlane swaps, and channel c forms the 9 moments of
+//    canonical node c.  A workgroup = NW waves = NW directions of one
+//    quadrant on the same band and the same 4K groups; their 9-value
+//    contributions are reduced through double-buffered LDS every step
+//    (summed in FP64 in a fixed order, one barrier per step) into one
+//    partial per cell and workgroup.
 //  * Bands hand their top-row outflow to the band above through a trace
 //    buffer of 64-bit words that carry (sweep epoch, value bits), written
 //    and polled with relaxed device-scope atomics: a word is valid when
@@ -87,6 +93,12 @@ __device__ __forceinline__ double shift_up_one_row<double>(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
+// entries per node block of the moment-reduction buffer (9 moments x NW waves
+// x 16 rows, padded to 16 mod 64)
+constexpr int red_node_block(int nw) {
+    return NMOM2D * nw * BAND_ROWS + (((BAND_ROWS - NMOM2D * nw * BAND_ROWS) % 64) + 64) % 64;
+}
+
 template <typename real, int K>
 struct StepIn {
     // raw loaded values only: any reordering happens at use, so the loads of
@@ -99,11 +111,40 @@ struct StepIn {
     real hx;
 };
 
-template <typename real, int K, int PF>
-__global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) {
+// reciprocal: the hardware's 1-ulp v_rcp_f32 in FP32, a correctly rounded
+// division in FP64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// sum of v over the 4 channel rows of the wave (every lane gets the total)
+__device__ __forceinline__ float channel_sum(float v) {
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+__device__ __forceinline__ double channel_sum(double v) {
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    const auto al = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto ah = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double s = __longlong_as_double(((uint64_t)ah[0] << 32) | al[0]) + __longlong_as_double(((uint64_t)ah[1] << 32) | al[1]);
+    const uint64_t w = __double_as_longlong(s);
+    const uint32_t wl = (uint32_t)w, wh = (uint32_t)(w >> 32);
+    const auto bl = __builtin_amdgcn_permlane32_swap(wl, wl, false, false);
+    const auto bh = __builtin_amdgcn_permlane32_swap(wh, wh, false, false);
+    return __longlong_as_double(((uint64_t)bh[0] << 32) | bl[0]) + __longlong_as_double(((uint64_t)bh[1] << 32) | bl[1]);
+}
+
+template <typename real, int K, int PF, int NW>
+__global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
     using r2 = typename vec2<real>::type;
     using r4 = typename vec4<real>::type;
     constexpr int TW = trace_words<real>::n;
+    // LDS reduction buffer: [buffer][node c][moment j][wave][row]; node blocks
+    // padded to 16 (mod 64) entries so the 4 channels of a wave hit disjoint banks
+    constexpr int CB = red_node_block(NW);
+    constexpr int BUF = 4 * CB;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *red = reinterpret_cast<real *>(smem_raw);
     __shared__ int s_task, s_epoch;
@@ -112,8 +153,6 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
     const int wv = threadIdx.x >> 6;
     const int ch = lane >> 4;
     const int r = lane & 15;
-    const int nthr = A.NW * 64;
-    const int red_stride = nthr + 1;
 
     if (threadIdx.x == 0) {
         s_task = atomicAdd(&A.ctr[0], 1);
@@ -141,24 +180,25 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
     r4 *pout = static_cast<r4 *>(A.psi_out);
     const real *inflow = static_cast<const real *>(A.inflow);
 
-    int dd[K], gg[K];
+    // the wave's direction (uniform); slot (wv, ch, k) -> group
+    const int2 pg0 = A.slot_pair[qc * A.R + wv * CHANNELS * K];
+    const int dw = __builtin_amdgcn_readfirstlane(pg0.x);
+    const bool wave_on = dw >= 0;
+    const int d = wave_on ? dw : 0;
+    const real *dr = dirs + 8 * d;
+    const real am = fabs(dr[0]), bm = fabs(dr[1]);
+    real cw[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) cw[m] = dr[2 + m];
+    int gg[K];
     bool act[K];
-    real am[K], bm[K];            // |mu|, |eta|
-    real cw[K][6];                // w*{1, mu, eta, mu^2, mu eta, eta^2}
     int64_t slab[K];              // offset of this (d,g) band slab in units of cells
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int slot = (wv * CHANNELS + ch) * K + k;
         const int2 pg = A.slot_pair[qc * A.R + slot];
-        dd[k] = pg.x < 0 ? 0 : pg.x;      // inactive slots (-1) address direction 0
         gg[k] = pg.y < 0 ? 0 : pg.y;
         act[k] = pg.x >= 0 && row_ok;
-        const int d = pg.x < 0 ? 0 : pg.x;
-        const real *dr = dirs + 8 * d;
-        am[k] = fabs(dr[0]);
-        bm[k] = fabs(dr[1]);
-#pragma unroll
-        for (int m = 0; m < 6; ++m) cw[k][m] = dr[2 + m];
         slab[k] = (((int64_t)d * G + gg[k]) * nbands + band) * NT * BAND_ROWS;
     }
     const real hy = row_ok ? hya[jn] : real(1);
@@ -172,7 +212,6 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
     uint64_t *trace_in = A.trace + ((int64_t)qc * nbands + (band > 0 ? band - 1 : 0)) * traces_per_band;
     uint64_t *trace_out = A.trace + ((int64_t)qc * nbands + band) * traces_per_band;
     const bool produce = (r == BAND_ROWS - 1) && (band + 1 < nbands);
-    const bool consume = (r == 0) && (band > 0);
 
     // All prefetch loads are issued unconditionally from clamped (always
     // valid) addresses into raw registers, so several steps of loads stay in
@@ -183,6 +222,9 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
     const bool has_prev = pprev != nullptr;
     const r4 *pp_eff = has_prev ? pprev : pout;
     auto load_step = [&](int t, StepIn<real, K> &S) {
+        // steps past NT (padding of the last group of PF+1 steps) touch no cell
+        // and read the tables of step NT-1
+        const int tt = t < NT ? t : NT - 1;
         const int ic = t - r;
         const bool col_ok = ic >= 0 && ic < nx;
         const int icc = col_ok ? ic : 0;
@@ -202,7 +244,7 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
         for (int k = 0; k < K; ++k) {
             const bool ok = act[k] && col_ok;
             // (quadrant, group) tables in the skewed layout: contiguous per channel
-            const int64_t ti = ((int64_t)quad * G + gg[k]) * tslab + ((int64_t)band * NT + t) * BAND_ROWS + r;
+            const int64_t ti = ((int64_t)quad * G + gg[k]) * tslab + ((int64_t)band * NT + tt) * BAND_ROWS + r;
             const r2 s = sig2[ti];
             S.st[k] = s.x;
             S.sg[k] = s.y;
@@ -211,7 +253,7 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
             const r4 p = pp_eff[ok ? slab[k] + (int64_t)t * BAND_ROWS + r : 0];
             S.psi[k][0] = p.x; S.psi[k][1] = p.y; S.psi[k][2] = p.z; S.psi[k][3] = p.w;
             // y- boundary inflow (band 0, row 0) -- other lanes read one shared valid word
-            const int64_t ib = ((int64_t)dd[k] * G + gg[k]) * A.NB;
+            const int64_t ib = ((int64_t)d * G + gg[k]) * A.NB;
             const int bnd = (band == 0 && r == 0 && ok) ? 1 : 0;
             const int lx0 = fx ? 1 : 0;
             const int64_t bbase = ib + yside + bnd * (2 * in);   // always a valid index
@@ -225,7 +267,7 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         xl[k][0] = xl[k][1] = yb[k][0] = yb[k][1] = 0;
-        const int64_t ib = ((int64_t)dd[k] * G + gg[k]) * A.NB;
+        const int64_t ib = ((int64_t)d * G + gg[k]) * A.NB;
         const int ly0 = fy ? 1 : 0;
         const int jv = row_ok ? jn : 0;
         left[k][0] = inflow[ib + xside + 2 * jv + ly0];
@@ -233,8 +275,7 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
     }
     StepIn<real, K> buf[PF + 1];
 #pragma unroll
-    for (int u = 0; u <= PF; ++u)
-        if (u < NT) load_step(u, buf[u]);
+    for (int u = 0; u <= PF; ++u) load_step(u, buf[u]);
     // One full wait after the prologue: the loop then starts from a state with
     // no pending loads, so the per-step waits only cover the slot being used.
     __builtin_amdgcn_s_waitcnt(0);
@@ -266,19 +307,24 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
         }
     }
 
+    real *part_base = static_cast<real *>(A.part) + ((int64_t)qc * nbands + band) * NT * (BAND_ROWS * PART_PER_CELL);
+    // The step loop runs in whole groups of PF+1 steps with no per-step
+    // condition (a conditional step or prefetch would merge register values
+    // and force a wait on every outstanding load); padding steps t >= NT have
+    // no valid column, so they store nothing and write no partial.
     for (int t0 = 0; t0 < NT; t0 += PF + 1) {
 #pragma unroll
         for (int u = 0; u <= PF; ++u) {
             const int t = t0 + u;
-            if (t < NT) {
+            {
                 StepIn<real, K> &S = buf[u];
                 const int ic = t - r;
                 const bool col_ok = ic >= 0 && ic < nx;
                 const real hx = S.hx;
                 const real wgt = hx * hy * real(0.25);
-                real acc[PART_PER_CELL];
-#pragma unroll
-                for (int m = 0; m < PART_PER_CELL; ++m) acc[m] = 0;
+                const real a = am * hy * real(0.5);
+                const real b = bm * hx * real(0.5);
+                real sumI[4] = {0, 0, 0, 0}, sumS[4] = {0, 0, 0, 0};   // sum_k I, sum_k sigma I
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const bool ok = act[k] && col_ok;
@@ -324,15 +370,12 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
                     }
                     const real xin0 = (ic == 0) ? left[k][0] : xl[k][0];
                     const real xin2 = (ic == 0) ? left[k][1] : xl[k][1];
-                    const real a = am[k] * hy * real(0.5);
-                    const real b = bm[k] * hx * real(0.5);
-                    const real q0 = S.qn[k][0], q1 = S.qn[k][1], q2 = S.qn[k][2], q3 = S.qn[k][3];
                     const real ps0 = has_prev ? S.psi[k][0] : real(0), ps1 = has_prev ? S.psi[k][1] : real(0);
                     const real ps2 = has_prev ? S.psi[k][2] : real(0), ps3 = has_prev ? S.psi[k][3] : real(0);
-                    real rh0 = wgt * (q0 + icdt * ps0) + a * xin0 + b * yin0;
-                    real rh1 = wgt * (q1 + icdt * ps1) + b * yin1;
-                    real rh2 = wgt * (q2 + icdt * ps2) + a * xin2;
-                    real rh3 = wgt * (q3 + icdt * ps3);
+                    real rh0 = wgt * (S.qn[k][0] + icdt * ps0) + a * xin0 + b * yin0;
+                    real rh1 = wgt * (S.qn[k][1] + icdt * ps1) + b * yin1;
+                    real rh2 = wgt * (S.qn[k][2] + icdt * ps2) + a * xin2;
+                    real rh3 = wgt * (S.qn[k][3] + icdt * ps3);
                     const real dg = real(0.5) * (a + b) + S.st[k] * wgt;
                     const real ha = real(0.5) * a, hb = real(0.5) * b;
                     const real y0 = dg * rh0 - ha * rh1 - hb * rh2;
@@ -341,7 +384,7 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
                     const real y3 = dg * rh3 + ha * rh2 + hb * rh1;
                     const real al = dg * dg + ha * ha + hb * hb;
                     const real be = real(2) * ha * hb;
-                    const real inv = real(1) / (al * al - be * be);
+                    const real inv = recip(al * al - be * be);
                     const real ai = al * inv, bi = be * inv;
                     const real I0 = ai * y0 + bi * y3;
                     const real I1 = ai * y1 - bi * y2;
@@ -356,46 +399,53 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
                             put_trace(dst, I2, epoch);
                             put_trace(dst + TW, I3, epoch);
                         }
-                        const real Iv[4] = {I0, I1, I2, I3};
-#pragma unroll
-                        for (int l = 0; l < 4; ++l) {
-                            const real v = Iv[l];
-                            real *m = acc + l * NMOM2D;
-#pragma unroll
-                            for (int j = 0; j < 6; ++j) m[j] += cw[k][j] * v;
-                            const real sv = S.sg[k] * v;
-                            m[6] += cw[k][0] * sv;
-                            m[7] += cw[k][1] * sv;
-                            m[8] += cw[k][2] * sv;
-                        }
                     }
+                    const real i0 = ok ? I0 : real(0), i1 = ok ? I1 : real(0);
+                    const real i2 = ok ? I2 : real(0), i3 = ok ? I3 : real(0);
+                    const real sg = S.sg[k];
+                    sumI[0] += i0; sumI[1] += i1; sumI[2] += i2; sumI[3] += i3;
+                    sumS[0] += sg * i0; sumS[1] += sg * i1; sumS[2] += sg * i2; sumS[3] += sg * i3;
                     xl[k][0] = I1;
                     xl[k][1] = I3;
                     yb[k][0] = shift_up_one_row<real>(I2);
                     yb[k][1] = shift_up_one_row<real>(I3);
                 }
                 // prefetch the step PF+1 ahead into the slot just consumed
-                if (t + PF + 1 < NT) load_step(t + PF + 1, buf[u]);
+                load_step(t + PF + 1, buf[u]);
 
-                // workgroup reduction of the moment contributions of this step
+                // channel sums; channel c then forms the 9 moments of canonical node c
+                real nI = 0, nS = 0;
 #pragma unroll
-                for (int m = 0; m < PART_PER_CELL; ++m) red[m * red_stride + threadIdx.x] = acc[m];
+                for (int l = 0; l < 4; ++l) {
+                    const real vI = channel_sum(sumI[l]);
+                    const real vS = channel_sum(sumS[l]);
+                    nI = (ch == l) ? vI : nI;
+                    nS = (ch == l) ? vS : nS;
+                }
+                real *rb = red + (t & 1) * BUF + ch * CB + wv * BAND_ROWS + r;
+#pragma unroll
+                for (int j = 0; j < 6; ++j) rb[j * NW * BAND_ROWS] = wave_on ? cw[j] * nI : real(0);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) rb[(6 + j) * NW * BAND_ROWS] = wave_on ? cw[j] * nS : real(0);
                 __syncthreads();
-                real *part = static_cast<real *>(A.part) + (((int64_t)qc * nbands + band) * NT + t) * (BAND_ROWS * PART_PER_CELL);
-                for (int o = threadIdx.x; o < BAND_ROWS * PART_PER_CELL; o += nthr) {
-                    const int rr = o / PART_PER_CELL;
-                    const int m = o - rr * PART_PER_CELL;
-                    const int icc = t - rr;
-                    if (icc >= 0 && icc < nx && band * BAND_ROWS + rr < ny) {
-                        double s = 0.0;
-                        const real *src = red + m * red_stride + rr;
-                        for (int w2 = 0; w2 < A.NW; ++w2)
+                // one partial per cell of this step: [t][node*9 + moment][row]
+                const real *rr_base = red + (t & 1) * BUF;
+                real *part = part_base + (int64_t)t * (BAND_ROWS * PART_PER_CELL);
 #pragma unroll
-                            for (int c2 = 0; c2 < CHANNELS; ++c2) s += (double)src[w2 * 64 + c2 * BAND_ROWS];
-                        part[o] = (real)s;
+                for (int o0 = 0; o0 < BAND_ROWS * PART_PER_CELL; o0 += NW * 64) {
+                    const int o = o0 + threadIdx.x;
+                    if (o < BAND_ROWS * PART_PER_CELL) {
+                        const int rr = o & (BAND_ROWS - 1);
+                        const int lm = o >> 4;                  // node*9 + moment
+                        const int l = lm / NMOM2D, j = lm - l * NMOM2D;
+                        const int icc = t - rr;
+                        const real *src = rr_base + l * CB + j * NW * BAND_ROWS + rr;
+                        double s = 0.0;
+#pragma unroll
+                        for (int w2 = 0; w2 < NW; ++w2) s += (double)src[w2 * BAND_ROWS];
+                        if (icc >= 0 && icc < nx && band * BAND_ROWS + rr < ny) part[o] = (real)s;
                     }
                 }
-                __syncthreads();
             }
         }
     }
@@ -412,13 +462,29 @@ __global__ void __launch_bounds__(MAX_WG_THREADS) sweep2d_kernel(Sweep2DArgs A) 
     }
 }
 
+template <typename real, int K, int NW>
+static void launch_knw(const Sweep2DArgs &a, hipStream_t s) {
+    constexpr int PF = sizeof(real) == 4 ? 2 : 1;
+    constexpr int CB = red_node_block(NW);
+    const size_t lds = (size_t)2 * 4 * CB * sizeof(real);
+    SMRT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep2d_kernel<real, K, PF, NW>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((sweep2d_kernel<real, K, PF, NW>), dim3(a.n_wg), dim3(NW * 64), lds, s, a);
+}
+
 template <typename real, int K>
 static void launch_k(const Sweep2DArgs &a, hipStream_t s) {
-    constexpr int PF = sizeof(real) == 4 ? 2 : 1;
-    const size_t lds = (size_t)PART_PER_CELL * (a.NW * 64 + 1) * sizeof(real);
-    SMRT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep2d_kernel<real, K, PF>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((sweep2d_kernel<real, K, PF>), dim3(a.n_wg), dim3(a.NW * 64), lds, s, a);
+    switch (a.NW) {
+        case 1: launch_knw<real, K, 1>(a, s); break;
+        case 2: launch_knw<real, K, 2>(a, s); break;
+        case 3: launch_knw<real, K, 3>(a, s); break;
+        case 4: launch_knw<real, K, 4>(a, s); break;
+        case 5: launch_knw<real, K, 5>(a, s); break;
+        case 6: launch_knw<real, K, 6>(a, s); break;
+        case 7: launch_knw<real, K, 7>(a, s); break;
+        case 8: launch_knw<real, K, 8>(a, s); break;
+        default: throw Error(SMRT_E_INVALID_ARG, "waves per workgroup must be in [1, 8]");
+    }
 }
 
 template <typename real>

@@ -17,8 +17,7 @@ void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const do
 template <typename real>
 void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab);
 template <typename real>
-void run_qtab2d(hipStream_t s, int nx, int ny, int G, const double *T, const double *nu, double a, double c,
-                const double *sig, const double *qabi, real *qtab);
+void run_qtab2d(hipStream_t s, int nx, int ny, int G, const double *q, int64_t sn, int64_t sg, real *qtab);
 void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
                      double *psi);
 void run_side_inflow(hipStream_t s, int nsides, int G, const double *nu, double a, double c, const int *kind,
@@ -36,7 +35,7 @@ void run_psi_to_internal(hipStream_t s, int nx, int ny, int G, int nang, const i
 template <typename real>
 void run_psi_from_internal(hipStream_t s, int nx, int ny, int G, int nang, const int *dq, const real *in, double *abi);
 template <typename real>
-void run_moments_finalize(hipStream_t s, int nx, int ny, int NQC, const int *qcq, const real *part, double *mom);
+void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const real *part, double *mom);
 template <typename real>
 void run_moments1d(hipStream_t s, int nx, int G, int nang, const real *mw, const double *sig, const real *psi, double *mom);
 void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *om, const double *w, double c,

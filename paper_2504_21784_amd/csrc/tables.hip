@@ -130,7 +130,7 @@ __global__ void k_source(int nn, int npc, int G, const double *T, const double *
     for (int g = 0; g < G; ++g) {
         const double s = sig[(int64_t)cell * G + g];
         if (qiso) qiso[((int64_t)g * ncell + cell) * npc + l] = (real)(s * B * b[g]);
-        if (qnat) qnat[(int64_t)n * G + g] = s * B * b[g];
+        if (qnat) qnat[(int64_t)g * nn + n] = s * B * b[g];
         sb += b[g];
         sbs += b[g] * s;
         sr += r[g];
@@ -177,38 +177,24 @@ __global__ void k_stab2d(int nx, int ny, int G, const double *sig, const double 
     stab[2 * i + 1] = (real)s;
 }
 
-// q_iso per (quadrant, group, skewed cell), canonical node order:
-// from T (emission sigma_g a c T^4 b_g(T)/4pi) or from an ABI array q[node][G]
+// Emission table in the skewed per-quadrant layout (canonical node order) from
+// a natural-order FP64 field q[n * sn + g * sg].
 template <typename real>
-__global__ void k_qtab2d(int nx, int ny, int G, const double *T, const double *nu, double a, double c,
-                         const double *sig, const double *qabi, real *qtab) {
+__global__ void k_qtab2d(int nx, int ny, int G, const double *q, int64_t sn, int64_t sg, real *qtab) {
     const int64_t cs = cell_slab(nx, ny);
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= 4 * (int64_t)G * cs) return;
     const int64_t slot = i % cs;
-    const int qg = (int)(i / cs), g = qg % G, q = qg / G;
+    const int qg = (int)(i / cs), g = qg % G, qd = qg / G;
     int cell, flip;
-    if (!skew_to_cell(nx, ny, q, slot, cell, flip)) {
+    if (!skew_to_cell(nx, ny, qd, slot, cell, flip)) {
         for (int lc = 0; lc < 4; ++lc) qtab[4 * i + lc] = real(0);
         return;
     }
-    for (int lc = 0; lc < 4; ++lc) {
-        const int n = 4 * cell + (lc ^ flip);
-        double v;
-        if (qabi) {
-            v = qabi[(int64_t)n * G + g];
-        } else {
-            const double Tn = T[n];
-            double bg = 1.0;
-            if (G > 1) {
-                const double lo = g == 0 ? 0.0 : planck_cum(nu[g] / Tn);
-                const double hi = g == G - 1 ? 1.0 : planck_cum(nu[g + 1] / Tn);
-                bg = hi - lo;
-            }
-            v = sig[(int64_t)cell * G + g] * a * c * Tn * Tn * Tn * Tn / (4.0 * M_PI) * bg;
-        }
-        qtab[4 * i + lc] = (real)v;
-    }
+    const double *src = q + (int64_t)g * sg + (int64_t)4 * cell * sn;
+    double v[4];
+    for (int l = 0; l < 4; ++l) v[l] = src[l * sn];
+    for (int lc = 0; lc < 4; ++lc) qtab[4 * i + lc] = (real)v[lc ^ flip];
 }
 
 // Isotropic equilibrium intensity B_g(T_n)/(4 pi) in the ABI layout [d][g][node]
@@ -311,35 +297,51 @@ __global__ void k_psi_convert(int nx, int ny, int G, int nang, const int *dir_qu
 }
 
 // ---------------------------------------------------------------------------
-// Moment finalisation (2D): mom[27][node] (FP64) = sum over (quadrant,chunk)
-// partials in a fixed order.
+// Moment finalisation (2D): mom[27][node] (FP64) = sum over the chunks of each
+// quadrant of the sweep partials, in a fixed order (deterministic).
+// Partials: [chunk][band][step t][canonical node lc * 9 + moment][row], the
+// cell of (t, row) being canonical column t - row.  A block owns a 16x16 tile
+// of natural cells (thread = cell) and loops over the 4 nodes; for one chunk
+// the tile's partials form a skewed strip of ~31 steps that stays in L1.
+// Tiles are numbered so that each XCD takes a contiguous run of neighbouring
+// tiles, which share the partial lines at their common edges in its L2.
 // ---------------------------------------------------------------------------
 template <typename real>
-__global__ void k_moments_finalize(int nx, int ny, int NQC, const int *qc_quad, const real *part, double *mom) {
-    const int i = blockIdx.x * 16 + threadIdx.x;
-    const int j = blockIdx.y * 16 + threadIdx.y;
+__global__ void __launch_bounds__(256) k_moments_finalize(int nx, int ny, ChunkRanges cr, const real *part,
+                                                          double *mom) {
+    const int ntx = (nx + 15) / 16;
+    const int nblocks = gridDim.x;
+    const int b = blockIdx.x;
+    const int per = nblocks / 8, rem = nblocks % 8, xcd = b % 8, idx = b / 8;
+    const int tile = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+    const int i = (tile % ntx) * 16 + (threadIdx.x & 15);
+    const int j = (tile / ntx) * 16 + (threadIdx.x >> 4);
     if (i >= nx || j >= ny) return;
     const int nb = (ny + BAND_ROWS - 1) / BAND_ROWS, NT = nx + BAND_ROWS - 1;
-    const int nn = nx * ny * 4;
-    const int cell = i + nx * j;
-    double acc[4][27];
-    for (int l = 0; l < 4; ++l)
-        for (int m = 0; m < 27; ++m) acc[l][m] = 0.0;
-    for (int qc = 0; qc < NQC; ++qc) {
-        const int q = qc_quad[qc];
-        const bool fx = (q == 1 || q == 2), fy = (q == 2 || q == 3);
-        const int ic = fx ? nx - 1 - i : i, jc = fy ? ny - 1 - j : j;
-        const int band = jc / BAND_ROWS, r = jc % BAND_ROWS, t = ic + r;
-        const real *p = part + ((((int64_t)qc * nb + band) * NT + t) * BAND_ROWS + r) * PART_PER_CELL;
-        const int flip = (fx ? 1 : 0) | (fy ? 2 : 0);
-        for (int lc = 0; lc < 4; ++lc) {
-            const int l = lc ^ flip;
-            for (int k = 0; k < 6; ++k) acc[l][6 * q + k] += (double)p[lc * NMOM2D + k];
-            for (int k = 0; k < 3; ++k) acc[l][24 + k] += (double)p[lc * NMOM2D + 6 + k];
+    const int64_t nn = (int64_t)nx * ny * 4;
+    const int64_t cell = i + (int64_t)nx * j;
+    constexpr int PB = BAND_ROWS * PART_PER_CELL;   // partial entries per step
+    for (int l = 0; l < 4; ++l) {
+        double acc[27];
+#pragma unroll
+        for (int m = 0; m < 27; ++m) acc[m] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool fx = (q == 1 || q == 2), fy = (q == 2 || q == 3);
+            const int ic = fx ? nx - 1 - i : i, jc = fy ? ny - 1 - j : j;
+            const int band = jc / BAND_ROWS, rc = jc % BAND_ROWS, t = ic + rc;
+            const int lc = l ^ ((fx ? 1 : 0) | (fy ? 2 : 0));
+            for (int qc = cr.start[q]; qc < cr.start[q + 1]; ++qc) {
+                const real *p = part + (((int64_t)qc * nb + band) * NT + t) * PB + lc * NMOM2D * BAND_ROWS + rc;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) acc[6 * q + k] += (double)p[k * BAND_ROWS];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) acc[24 + k] += (double)p[(6 + k) * BAND_ROWS];
+            }
         }
+#pragma unroll
+        for (int m = 0; m < 27; ++m) mom[m * nn + 4 * cell + l] = acc[m];
     }
-    for (int l = 0; l < 4; ++l)
-        for (int m = 0; m < 27; ++m) mom[(int64_t)m * nn + 4 * cell + l] = acc[l][m];
 }
 
 // ---------------------------------------------------------------------------
@@ -456,10 +458,9 @@ void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const d
     hipLaunchKernelGGL(k_stab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, sig, sigt, icdt, stab);
 }
 template <typename real>
-void run_qtab2d(hipStream_t s, int nx, int ny, int G, const double *T, const double *nu, double a, double c,
-                const double *sig, const double *qabi, real *qtab) {
+void run_qtab2d(hipStream_t s, int nx, int ny, int G, const double *q, int64_t sn, int64_t sg, real *qtab) {
     const int64_t n = 4 * (int64_t)G * cell_slab(nx, ny);
-    hipLaunchKernelGGL(k_qtab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, T, nu, a, c, sig, qabi, qtab);
+    hipLaunchKernelGGL(k_qtab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, q, sn, sg, qtab);
 }
 void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
                      double *psi) {
@@ -500,9 +501,9 @@ void run_psi_from_internal(hipStream_t s, int nx, int ny, int G, int nang, const
                        (const double *)nullptr, const_cast<real *>(in), abi);
 }
 template <typename real>
-void run_moments_finalize(hipStream_t s, int nx, int ny, int NQC, const int *qcq, const real *part, double *mom) {
-    hipLaunchKernelGGL(k_moments_finalize<real>, dim3(nblk(nx, 16), nblk(ny, 16)), dim3(16, 16), 0, s, nx, ny, NQC, qcq,
-                       part, mom);
+void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const real *part, double *mom) {
+    hipLaunchKernelGGL(k_moments_finalize<real>, dim3(nblk(nx, 16) * nblk(ny, 16)), dim3(256), 0, s, nx, ny, cr, part,
+                       mom);
 }
 template <typename real>
 void launch_sweep1d(const Sweep1DArgs &a, hipStream_t s) {
@@ -525,14 +526,13 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
                                    const double *, real *, double *, double *, double *);                           \
     template void run_fill_inflow<real>(hipStream_t, int, int, int, int, int, const double *, real *);              \
     template void run_stab2d<real>(hipStream_t, int, int, int, const double *, const double *, double, real *);     \
-    template void run_qtab2d<real>(hipStream_t, int, int, int, const double *, const double *, double, double,      \
-                                   const double *, const double *, real *);                                        \
+    template void run_qtab2d<real>(hipStream_t, int, int, int, const double *, int64_t, int64_t, real *);          \
     template void run_copy_to<real>(hipStream_t, int64_t, const double *, real *);                                  \
     template void run_qiso_to_internal<real>(hipStream_t, int, int, int, const double *, real *);                   \
     template void run_sig_to_internal<real>(hipStream_t, int, int, const double *, const double *, real *);         \
     template void run_psi_to_internal<real>(hipStream_t, int, int, int, int, const int *, const double *, real *);  \
     template void run_psi_from_internal<real>(hipStream_t, int, int, int, int, const int *, const real *, double *); \
-    template void run_moments_finalize<real>(hipStream_t, int, int, int, const int *, const real *, double *);      \
+    template void run_moments_finalize<real>(hipStream_t, int, int, const ChunkRanges &, const real *, double *);  \
     template void launch_sweep1d<real>(const Sweep1DArgs &, hipStream_t);                                           \
     template void run_moments1d<real>(hipStream_t, int, int, int, const real *, const double *, const real *, double *);
 INST(float)
