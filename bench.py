@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--waves", type=int, default=0, help="sweep waves per workgroup (0 = automatic)")
     ap.add_argument("--pairs", type=int, default=0, help="(angle,group) pairs per lane (0 = automatic)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (reference point for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X: this build runs on a single GPU (the multi-GPU sharding "
@@ -87,6 +89,15 @@ def main():
             ctx.set_launch(args.waves, args.pairs if prec == smrt.SMRT_FP32 else min(args.pairs, 1))
         ctx.set_state(T0)
         return ctx
+
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx = make(smrt.SMRT_FP32)
     info = ctx.info()

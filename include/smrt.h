@@ -230,7 +230,9 @@ typedef struct {
 smrt_status smrt_get_info(const smrt_ctx *ctx, smrt_info *info);
 
 /* Sweep launch configuration override (0 = automatic): waves per
- * workgroup and (angle,group) pairs per lane. */
+ * workgroup in [0, 12] (each wave sweeps one direction of a quadrant) and
+ * groups per lane in {0, 1, 2} (2: FP32 only, with at most 8 waves).
+ * Returns SMRT_E_INVALID_ARG outside these ranges. */
 smrt_status smrt_set_launch(smrt_ctx *ctx, int waves_per_group, int pairs_per_lane);
 
 #ifdef __cplusplus

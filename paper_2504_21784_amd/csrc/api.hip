@@ -47,6 +47,7 @@ struct smrt_ctx {
     int cur = 0;
     // FP64 state and work arrays
     DevBuf<double> d_qnat;   // q_iso [G][node] FP64 (2D: gathered into the skewed tables)
+    DevBuf<double> d_sigq;   // per-quadrant sigma-weighted moments [4][3][node] (2D finalisation)
     DevBuf<double> d_T, d_E, d_F, d_Eho, d_Fho, d_mom, d_sig, d_sigP, d_sigF, d_clos, d_Tl, d_El, d_Tn, d_En, d_Tstar,
         d_Estar, d_Fstar, d_sigEho;
     LoSolver lo;
@@ -164,7 +165,10 @@ static void plan_sweep(smrt_ctx *x) {
     if (x->fp32 == false) K = 1;
     int NW = x->user_NW;
     if (!NW) {
-        const int nblk = (maxD + 7) / 8;
+        // fewest direction blocks of at most 8 waves, balanced (more waves per
+        // workgroup share its CU's SIMDs and slow every step of the band)
+        const int cap = 8;
+        const int nblk = (maxD + cap - 1) / cap;
         NW = std::max(1, (maxD + nblk - 1) / nblk);
     }
     x->NW = NW;
@@ -172,6 +176,9 @@ static void plan_sweep(smrt_ctx *x) {
     x->R = 4 * NW * K;
     x->nbands = (x->ny + BAND_ROWS - 1) / BAND_ROWS;
     x->NT = x->nx + BAND_ROWS - 1;
+    // a sweep wave addresses its 4K group slabs through 32-bit byte offsets
+    require((int64_t)CHANNELS * K * x->nbands * x->NT * BAND_ROWS * 4 * x->rs < (int64_t(1) << 32),
+            "mesh too large for the sweep's 32-bit per-wave offsets");
     x->qc_quad.clear();
     x->slot_pair.clear();
     const int GB = 4 * K;
@@ -232,8 +239,8 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
         if (x->fp32) launch_sweep2d<float>(a, x->stream);
         else launch_sweep2d<double>(a, x->stream);
         if (finalize) {
-            if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, mom);
-            else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, mom);
+            if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, x->d_sigq.p, mom);
+            else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, x->d_sigq.p, mom);
         }
     } else {
         Sweep1DArgs a{};
@@ -511,6 +518,7 @@ extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_d
         p->d_qiso.alloc(tab_cells * p->G * p->npc * p->rs);
         p->d_sig2.alloc(tab_cells * p->G * 2 * p->rs);
         if (p->dim == 2) p->d_qnat.alloc((int64_t)p->nn * p->G);
+        if (p->dim == 2) p->d_sigq.alloc((int64_t)12 * p->nn);
         p->d_inflow.alloc((int64_t)p->nang * p->G * p->NB * p->rs);
         for (auto *b : {&p->d_T, &p->d_E, &p->d_Eho, &p->d_sigP, &p->d_sigF, &p->d_Tl, &p->d_El, &p->d_Tn, &p->d_En,
                         &p->d_Tstar, &p->d_Estar, &p->d_sigEho})
@@ -562,9 +570,10 @@ extern "C" smrt_status smrt_set_boundary(smrt_ctx *x, const smrt_boundary_desc *
 extern "C" smrt_status smrt_set_launch(smrt_ctx *x, int waves_per_group, int pairs_per_lane) {
     if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
     return guard(x, [&] {
-        require(waves_per_group >= 0 && waves_per_group <= MAX_WG_THREADS / 64, "waves per group must be in [0, 8]");
+        require(waves_per_group >= 0 && waves_per_group <= MAX_SWEEP_WAVES, "waves per group must be in [0, 12]");
         require(pairs_per_lane == 0 || pairs_per_lane == 1 || (pairs_per_lane == 2 && x->fp32),
                 "pairs per lane must be 0 (auto), 1, or 2 (FP32 only)");
+        require(!(pairs_per_lane == 2 && waves_per_group > 8), "2 groups per lane allow at most 8 waves per group");
         SMRT_HIP(hipStreamSynchronize(x->stream));
         x->user_NW = waves_per_group;
         x->user_K = pairs_per_lane;
@@ -915,8 +924,8 @@ extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, 
             run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p, false);
             SMRT_HIP(hipEventRecord(ev[2 * k + 1], x->stream));
             if (x->dim == 2) {
-                if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, x->d_mom.p);
-                else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, x->d_mom.p);
+                if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, x->d_sigq.p, x->d_mom.p);
+                else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, x->d_sigq.p, x->d_mom.p);
             } else {
                 if (x->fp32) run_moments1d<float>(x->stream, x->nx, x->G, x->nang, (const float *)x->d_mu_w.p, x->d_sig.p, (const float *)pout, x->d_mom.p);
                 else run_moments1d<double>(x->stream, x->nx, x->G, x->nang, (const double *)x->d_mu_w.p, x->d_sig.p, (const double *)pout, x->d_mom.p);

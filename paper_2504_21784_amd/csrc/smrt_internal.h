@@ -16,7 +16,7 @@ constexpr int NMOM2D = 9;           // per node per quadrant: 6 quadrant sums + 
 constexpr int PART_PER_CELL = 4 * NMOM2D;   // partial moments per cell per chunk
 constexpr int SPIN_LIMIT = 1 << 20;          // bounded wait on a band trace
 constexpr int TRACE_LAG = 8;                 // columns a band stays behind the band below
-constexpr int MAX_WG_THREADS = 512;          // sweep workgroups: at most 8 waves (256 VGPRs each)
+constexpr int MAX_SWEEP_WAVES = 12;         // sweep workgroups: at most 12 waves (one direction each)
 
 #define SMRT_HIP(call)                                                                   \
     do {                                                                                 \

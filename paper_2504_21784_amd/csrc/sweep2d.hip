@@ -25,9 +25,9 @@
 //  * Moments: because the direction is uniform across the wave, its
 //    contribution to every moment of a node is (wave-uniform coefficient) x
 //    (sum over the wave's groups of I) or x (sum of sigma_g I).  Each lane
-//    accumulates these two sums (4 nodes each), the 4 channels are summed
-//    with two gfx950 permlane swaps, and channel c forms the 9 moments of
-//    canonical node c.  A workgroup = NW waves = NW directions of one
+//    accumulates these two sums (4 nodes each), three gfx950 permlane swaps
+//    reduce-scatter them over the 4 channels so that channel c holds node c's
+//    totals, and channel c forms the 9 moments of canonical node c.  A workgroup = NW waves = NW directions of one
 //    quadrant on the same band and the same 4K groups; their 9-value
 //    contributions are reduced through double-buffered LDS every step
 //    (summed in FP64 in a fixed order, one barrier per step) into one
@@ -93,6 +93,65 @@ __device__ __forceinline__ double shift_up_one_row<double>(double v) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
+// Buffer-resource access: a wave-uniform base (SGPRs) + a per-lane 32-bit
+// byte offset fixed for the whole band + a wave-uniform per-step byte offset,
+// so a step's loads and stores need no per-lane address arithmetic.  Every
+// access stays inside the resource (the kernel never relies on range checks).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int RSRC_DWORD3 = 0x00020000;   // gfx9-family raw buffer, 32-bit data format
+constexpr int CPOL_SC1 = 16;              // coherent at device scope (trace words)
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0,
+                                             (int)(bytes < 0xffffffffull ? bytes : 0xffffffffull), RSRC_DWORD3);
+}
+__device__ __forceinline__ void bload(float2 &v, rsrc_t r, uint32_t vo, uint32_t so) {
+    v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ __forceinline__ void bload(float4 &v, rsrc_t r, uint32_t vo, uint32_t so) {
+    v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+}
+__device__ __forceinline__ void bload(double2 &v, rsrc_t r, uint32_t vo, uint32_t so) {
+    v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+}
+__device__ __forceinline__ void bload(double4 &v, rsrc_t r, uint32_t vo, uint32_t so) {
+    const double2 a = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+    const double2 b = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so + 16, 0));
+    v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+}
+__device__ __forceinline__ void bstore(const float4 &v, rsrc_t r, uint32_t vo, uint32_t so) {
+    using u4 = __attribute__((ext_vector_type(4))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, vo, so, 0);
+}
+__device__ __forceinline__ void bstore(const double4 &v, rsrc_t r, uint32_t vo, uint32_t so) {
+    using u4 = __attribute__((ext_vector_type(4))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, make_double2(v.x, v.y)), r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, make_double2(v.z, v.w)), r, vo, so + 16, 0);
+}
+// trace words (device-coherent loads; the bounded spin path re-polls atomically)
+__device__ __forceinline__ void bload_words(uint64_t *w, int n, rsrc_t r, uint32_t vo, uint32_t so) {
+    if (n == 2) {
+        const auto a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, CPOL_SC1);
+        w[0] = ((uint64_t)a[1] << 32) | a[0];
+        w[1] = ((uint64_t)a[3] << 32) | a[2];
+    } else {
+        const auto a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, CPOL_SC1);
+        const auto b = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so + 16, CPOL_SC1);
+        w[0] = ((uint64_t)a[1] << 32) | a[0];
+        w[1] = ((uint64_t)a[3] << 32) | a[2];
+        w[2] = ((uint64_t)b[1] << 32) | b[0];
+        w[3] = ((uint64_t)b[3] << 32) | b[2];
+    }
+}
+// two adjacent boundary values
+__device__ __forceinline__ void bload_pair(float &a, float &b, rsrc_t r, uint32_t vo, uint32_t so) {
+    const float2 v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    a = v.x; b = v.y;
+}
+__device__ __forceinline__ void bload_pair(double &a, double &b, rsrc_t r, uint32_t vo, uint32_t so) {
+    const double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+    a = v.x; b = v.y;
+}
+
 // entries per node block of the moment-reduction buffer (9 moments x NW waves
 // x 16 rows, padded to 16 mod 64)
 constexpr int red_node_block(int nw) {
@@ -106,9 +165,9 @@ struct StepIn {
     real psi[K][4];     // I* (canonical node order)
     real qn[K][4];      // q_iso (canonical node order)
     real st[K], sg[K];  // sigma_t, sigma
-    real bot[K][2];     // y- boundary inflow for canonical nodes 0, 1 (band 0)
+    real bot[K][2];     // y- boundary inflow at natural nodes (2 in, 2 in + 1) of row 0's column (band 0)
     uint64_t tw[K][2 * trace_words<real>::n];   // band trace words (band > 0)
-    real hx;
+    real hx0;           // width of row 0's column (other rows take it from the row above)
 };
 
 // reciprocal: the hardware's 1-ulp v_rcp_f32 in FP32, a correctly rounded
@@ -116,24 +175,45 @@ struct StepIn {
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-// sum of v over the 4 channel rows of the wave (every lane gets the total)
-__device__ __forceinline__ float channel_sum(float v) {
-    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
-    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
-    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+// Reduce-scatter over the 4 channels (rows of 16 lanes) of a wave: given each
+// lane's values v[0..3] (one per canonical node), every lane of channel c gets
+// the sum over the 4 channels of v[c].  gfx950 permlane swaps: the 32-lane swap
+// exchanges the upper half of its first operand with the lower half of its
+// second, the 16-lane swap the odd rows of its first operand with the even rows
+// of its second; in both cases the two results sum to the wanted partial.
+__device__ __forceinline__ uint2 swap32(uint32_t a, uint32_t b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    return make_uint2(r[0], r[1]);
 }
-__device__ __forceinline__ double channel_sum(double v) {
-    const uint64_t u = __double_as_longlong(v);
-    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
-    const auto al = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto ah = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    const double s = __longlong_as_double(((uint64_t)ah[0] << 32) | al[0]) + __longlong_as_double(((uint64_t)ah[1] << 32) | al[1]);
-    const uint64_t w = __double_as_longlong(s);
-    const uint32_t wl = (uint32_t)w, wh = (uint32_t)(w >> 32);
-    const auto bl = __builtin_amdgcn_permlane32_swap(wl, wl, false, false);
-    const auto bh = __builtin_amdgcn_permlane32_swap(wh, wh, false, false);
-    return __longlong_as_double(((uint64_t)bh[0] << 32) | bl[0]) + __longlong_as_double(((uint64_t)bh[1] << 32) | bl[1]);
+__device__ __forceinline__ uint2 swap16(uint32_t a, uint32_t b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    return make_uint2(r[0], r[1]);
+}
+__device__ __forceinline__ float sum_swapped32(float a, float b) {
+    const uint2 r = swap32(__float_as_uint(a), __float_as_uint(b));
+    return __uint_as_float(r.x) + __uint_as_float(r.y);
+}
+__device__ __forceinline__ float sum_swapped16(float a, float b) {
+    const uint2 r = swap16(__float_as_uint(a), __float_as_uint(b));
+    return __uint_as_float(r.x) + __uint_as_float(r.y);
+}
+__device__ __forceinline__ double sum_swapped32(double a, double b) {
+    const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    const uint2 lo = swap32((uint32_t)ua, (uint32_t)ub), hi = swap32((uint32_t)(ua >> 32), (uint32_t)(ub >> 32));
+    return __longlong_as_double(((uint64_t)hi.x << 32) | lo.x) + __longlong_as_double(((uint64_t)hi.y << 32) | lo.y);
+}
+__device__ __forceinline__ double sum_swapped16(double a, double b) {
+    const uint64_t ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    const uint2 lo = swap16((uint32_t)ua, (uint32_t)ub), hi = swap16((uint32_t)(ua >> 32), (uint32_t)(ub >> 32));
+    return __longlong_as_double(((uint64_t)hi.x << 32) | lo.x) + __longlong_as_double(((uint64_t)hi.y << 32) | lo.y);
+}
+template <typename real>
+__device__ __forceinline__ real channel_scatter_sum(const real (&v)[4]) {
+    // lower half keeps nodes 0,1 and upper half nodes 2,3 ...
+    const real h0 = sum_swapped32(v[0], v[2]);
+    const real h1 = sum_swapped32(v[1], v[3]);
+    // ... then even channels keep their even node, odd channels their odd node
+    return sum_swapped16(h0, h1);
 }
 
 template <typename real, int K, int PF, int NW>
@@ -189,20 +269,20 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
     const real am = fabs(dr[0]), bm = fabs(dr[1]);
     real cw[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) cw[m] = dr[2 + m];
-    int gg[K];
+    for (int m = 0; m < 6; ++m) cw[m] = wave_on ? dr[2 + m] : real(0);   // an idle wave adds zeros
+    // the workgroup's group block starts at gb0; lane group = gb0 + gl[k]
+    const int gb0 = wave_on ? __builtin_amdgcn_readfirstlane(pg0.y) : 0;
     bool act[K];
-    int64_t slab[K];              // offset of this (d,g) band slab in units of cells
+    int gl[K];                    // group within the block (0 for an inactive slot)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int slot = (wv * CHANNELS + ch) * K + k;
         const int2 pg = A.slot_pair[qc * A.R + slot];
-        gg[k] = pg.y < 0 ? 0 : pg.y;
         act[k] = pg.x >= 0 && row_ok;
-        slab[k] = (((int64_t)d * G + gg[k]) * nbands + band) * NT * BAND_ROWS;
+        gl[k] = pg.y >= 0 ? pg.y - gb0 : 0;
     }
     const real hy = row_ok ? hya[jn] : real(1);
-    const int64_t tslab = (int64_t)nbands * NT * BAND_ROWS;   // cells per (quadrant, group) table slab
+    const int64_t gslab = (int64_t)nbands * NT * BAND_ROWS;   // cells per (direction or quadrant, group) slab
     const real icdt = (real)A.inv_c_dt;
 
     // boundary side bases in the general inflow array [d][g][NB]
@@ -213,61 +293,68 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
     uint64_t *trace_out = A.trace + ((int64_t)qc * nbands + band) * traces_per_band;
     const bool produce = (r == BAND_ROWS - 1) && (band + 1 < nbands);
 
-    // All prefetch loads are issued unconditionally from clamped (always
-    // valid) addresses into raw registers, so several steps of loads stay in
-    // flight: a load under a branch, or a reordering of its result, makes the
-    // compiler wait for every outstanding memory operation.
+    // buffer resources (wave-uniform bases) and per-lane byte offsets
+    const bool has_prev = pprev != nullptr;
+    const int64_t pbase = (((int64_t)d * G + gb0) * nbands + band) * NT * BAND_ROWS;
+    const int64_t tbase = ((int64_t)quad * G + gb0) * gslab + (int64_t)band * NT * BAND_ROWS;
+    const uint64_t span = (uint64_t)CHANNELS * K * gslab;           // cells covered from a base
     // psi_prev may be absent (raw sweep without a time-edge source): loads then
     // read psi_out (valid memory) and the values are discarded at use.
-    const bool has_prev = pprev != nullptr;
-    const r4 *pp_eff = has_prev ? pprev : pout;
+    const rsrc_t rs_prev = make_rsrc((has_prev ? pprev : pout) + pbase, span * sizeof(r4));
+    const rsrc_t rs_out = make_rsrc(pout + pbase, span * sizeof(r4));
+    const rsrc_t rs_sig = make_rsrc(sig2 + tbase, span * sizeof(r2));
+    const rsrc_t rs_q = make_rsrc(qiso + tbase, span * sizeof(r4));
+    const rsrc_t rs_inf = make_rsrc(inflow + ((int64_t)d * G + gb0) * A.NB, (uint64_t)CHANNELS * K * A.NB * sizeof(real));
+    const rsrc_t rs_tr = make_rsrc(trace_in + (int64_t)wv * CHANNELS * K * nx * 2 * TW,
+                                   (uint64_t)CHANNELS * K * nx * 2 * TW * sizeof(uint64_t));
+    uint32_t vo_cell[K];   // lane's cell offset (entries) in a slab: gl * gslab + r
+    uint32_t vo_inf[K], vo_tr[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        vo_cell[k] = (uint32_t)(gl[k] * gslab + r);
+        vo_inf[k] = (uint32_t)((gl[k] * A.NB + yside) * sizeof(real));
+        vo_tr[k] = (uint32_t)((ch * K + k) * nx * 2 * TW * sizeof(uint64_t));
+    }
+
+    // All prefetch loads are issued unconditionally (always in bounds) into raw
+    // registers, so several steps of loads stay in flight: a load under a
+    // branch, or a reordering of its result, makes the compiler wait for every
+    // outstanding memory operation.
     auto load_step = [&](int t, StepIn<real, K> &S) {
         // steps past NT (padding of the last group of PF+1 steps) touch no cell
         // and read the tables of step NT-1
         const int tt = t < NT ? t : NT - 1;
-        const int ic = t - r;
-        const bool col_ok = ic >= 0 && ic < nx;
-        const int icc = col_ok ? ic : 0;
-        const int in = fx ? nx - 1 - icc : icc;
-        S.hx = hxa[in];
-        // band trace words first (band > 0, row 0): issued before the other loads.
-        // Every lane of a channel reads the word its row-0 lane needs (column t),
-        // so a wave touches one address per channel and no word is contended.
-        const int tcol = t < nx ? t : nx - 1;
+        const int c0 = t < nx ? t : nx - 1;               // row 0's column (clamped)
+        const int in0 = fx ? nx - 1 - c0 : c0;            // ... in natural order
+        // band trace words first (band > 0, row 0): every lane of a channel reads
+        // the words its row-0 lane needs, so a wave touches one address per channel
+#pragma unroll
+        for (int k = 0; k < K; ++k) bload_words(S.tw[k], 2 * TW, rs_tr, vo_tr[k], (uint32_t)(c0 * 2 * TW * sizeof(uint64_t)));
+        S.hx0 = hxa[in0];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const uint64_t *src = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + tcol) * 2 * TW;
-#pragma unroll
-            for (int u = 0; u < 2 * TW; ++u) S.tw[k][u] = poll_word(src + u);
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const bool ok = act[k] && col_ok;
-            // (quadrant, group) tables in the skewed layout: contiguous per channel
-            const int64_t ti = ((int64_t)quad * G + gg[k]) * tslab + ((int64_t)band * NT + tt) * BAND_ROWS + r;
-            const r2 s = sig2[ti];
-            S.st[k] = s.x;
-            S.sg[k] = s.y;
-            const r4 qn = qiso[ti];
+            r2 sv;
+            bload(sv, rs_sig, vo_cell[k] * (uint32_t)sizeof(r2), (uint32_t)(tt * BAND_ROWS * sizeof(r2)));
+            S.st[k] = sv.x;
+            S.sg[k] = sv.y;
+            r4 qn;
+            bload(qn, rs_q, vo_cell[k] * (uint32_t)sizeof(r4), (uint32_t)(tt * BAND_ROWS * sizeof(r4)));
             S.qn[k][0] = qn.x; S.qn[k][1] = qn.y; S.qn[k][2] = qn.z; S.qn[k][3] = qn.w;
-            const r4 p = pp_eff[ok ? slab[k] + (int64_t)t * BAND_ROWS + r : 0];
+            r4 p;
+            bload(p, rs_prev, vo_cell[k] * (uint32_t)sizeof(r4), (uint32_t)(tt * BAND_ROWS * sizeof(r4)));
             S.psi[k][0] = p.x; S.psi[k][1] = p.y; S.psi[k][2] = p.z; S.psi[k][3] = p.w;
-            // y- boundary inflow (band 0, row 0) -- other lanes read one shared valid word
-            const int64_t ib = ((int64_t)d * G + gg[k]) * A.NB;
-            const int bnd = (band == 0 && r == 0 && ok) ? 1 : 0;
-            const int lx0 = fx ? 1 : 0;
-            const int64_t bbase = ib + yside + bnd * (2 * in);   // always a valid index
-            S.bot[k][0] = inflow[bbase + bnd * lx0];
-            S.bot[k][1] = inflow[bbase + bnd * (1 - lx0)];
+            // y- boundary inflow at row 0's column (used by band 0, row 0 only)
+            bload_pair(S.bot[k][0], S.bot[k][1], rs_inf, vo_inf[k], (uint32_t)(2 * in0 * sizeof(real)));
         }
     };
 
     real xl[K][2], yb[K][2];   // x-upwind (nodes 1,3 of the left cell), y-upwind (nodes 2,3 of the cell below)
     real left[K][2];           // canonical x- boundary inflow of this row (nodes 0, 2)
+    real hx_sh = 0;            // width of the column of the row above at the previous step
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         xl[k][0] = xl[k][1] = yb[k][0] = yb[k][1] = 0;
-        const int64_t ib = ((int64_t)d * G + gg[k]) * A.NB;
+        const int64_t ib = ((int64_t)d * G + gb0 + gl[k]) * A.NB;
         const int ly0 = fy ? 1 : 0;
         const int jv = row_ok ? jn : 0;
         left[k][0] = inflow[ib + xside + 2 * jv + ly0];
@@ -320,11 +407,11 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
                 StepIn<real, K> &S = buf[u];
                 const int ic = t - r;
                 const bool col_ok = ic >= 0 && ic < nx;
-                const real hx = S.hx;
+                const real hx = (r == 0) ? S.hx0 : hx_sh;
                 const real wgt = hx * hy * real(0.25);
                 const real a = am * hy * real(0.5);
                 const real b = bm * hx * real(0.5);
-                real sumI[4] = {0, 0, 0, 0}, sumS[4] = {0, 0, 0, 0};   // sum_k I, sum_k sigma I
+                real sumI[4], sumS[4];   // sum_k I, sum_k sigma I
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const bool ok = act[k] && col_ok;
@@ -332,8 +419,8 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
                     // below (trace words) or the boundary.
                     real yin0 = yb[k][0], yin1 = yb[k][1];
                     if (r == 0 && band == 0) {
-                        yin0 = S.bot[k][0];
-                        yin1 = S.bot[k][1];
+                        yin0 = fx ? S.bot[k][1] : S.bot[k][0];   // canonical node 0 is natural lx = fx
+                        yin1 = fx ? S.bot[k][0] : S.bot[k][1];
                     } else if (r == 0) {
                         uint64_t *tw = S.tw[k];
                         bool ready = true;
@@ -393,7 +480,7 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
                     if (ok) {
                         r4 o;
                         o.x = I0; o.y = I1; o.z = I2; o.w = I3;
-                        pout[slab[k] + (int64_t)t * BAND_ROWS + r] = o;
+                        bstore(o, rs_out, vo_cell[k] * (uint32_t)sizeof(r4), (uint32_t)(t * BAND_ROWS * sizeof(r4)));
                         if (produce) {
                             uint64_t *dst = trace_out + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + ic) * 2 * TW;
                             put_trace(dst, I2, epoch);
@@ -403,30 +490,30 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
                     const real i0 = ok ? I0 : real(0), i1 = ok ? I1 : real(0);
                     const real i2 = ok ? I2 : real(0), i3 = ok ? I3 : real(0);
                     const real sg = S.sg[k];
-                    sumI[0] += i0; sumI[1] += i1; sumI[2] += i2; sumI[3] += i3;
-                    sumS[0] += sg * i0; sumS[1] += sg * i1; sumS[2] += sg * i2; sumS[3] += sg * i3;
+                    if (k == 0) {
+                        sumI[0] = i0; sumI[1] = i1; sumI[2] = i2; sumI[3] = i3;
+                        sumS[0] = sg * i0; sumS[1] = sg * i1; sumS[2] = sg * i2; sumS[3] = sg * i3;
+                    } else {
+                        sumI[0] += i0; sumI[1] += i1; sumI[2] += i2; sumI[3] += i3;
+                        sumS[0] += sg * i0; sumS[1] += sg * i1; sumS[2] += sg * i2; sumS[3] += sg * i3;
+                    }
                     xl[k][0] = I1;
                     xl[k][1] = I3;
                     yb[k][0] = shift_up_one_row<real>(I2);
                     yb[k][1] = shift_up_one_row<real>(I3);
                 }
+                hx_sh = shift_up_one_row<real>(hx);
                 // prefetch the step PF+1 ahead into the slot just consumed
                 load_step(t + PF + 1, buf[u]);
 
                 // channel sums; channel c then forms the 9 moments of canonical node c
-                real nI = 0, nS = 0;
-#pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                    const real vI = channel_sum(sumI[l]);
-                    const real vS = channel_sum(sumS[l]);
-                    nI = (ch == l) ? vI : nI;
-                    nS = (ch == l) ? vS : nS;
-                }
+                const real nI = channel_scatter_sum<real>(sumI);
+                const real nS = channel_scatter_sum<real>(sumS);
                 real *rb = red + (t & 1) * BUF + ch * CB + wv * BAND_ROWS + r;
 #pragma unroll
-                for (int j = 0; j < 6; ++j) rb[j * NW * BAND_ROWS] = wave_on ? cw[j] * nI : real(0);
+                for (int j = 0; j < 6; ++j) rb[j * NW * BAND_ROWS] = cw[j] * nI;
 #pragma unroll
-                for (int j = 0; j < 3; ++j) rb[(6 + j) * NW * BAND_ROWS] = wave_on ? cw[j] * nS : real(0);
+                for (int j = 0; j < 3; ++j) rb[(6 + j) * NW * BAND_ROWS] = cw[j] * nS;
                 __syncthreads();
                 // one partial per cell of this step: [t][node*9 + moment][row]
                 const real *rr_base = red + (t & 1) * BUF;
@@ -440,10 +527,10 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
                         const int l = lm / NMOM2D, j = lm - l * NMOM2D;
                         const int icc = t - rr;
                         const real *src = rr_base + l * CB + j * NW * BAND_ROWS + rr;
-                        double s = 0.0;
+                        real s = 0;   // fixed order over the waves
 #pragma unroll
-                        for (int w2 = 0; w2 < NW; ++w2) s += (double)src[w2 * BAND_ROWS];
-                        if (icc >= 0 && icc < nx && band * BAND_ROWS + rr < ny) part[o] = (real)s;
+                        for (int w2 = 0; w2 < NW; ++w2) s += src[w2 * BAND_ROWS];
+                        if (icc >= 0 && icc < nx && band * BAND_ROWS + rr < ny) part[o] = s;
                     }
                 }
             }
@@ -464,7 +551,8 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
 
 template <typename real, int K, int NW>
 static void launch_knw(const Sweep2DArgs &a, hipStream_t s) {
-    constexpr int PF = sizeof(real) == 4 ? 2 : 1;
+    // prefetch depth (steps in flight beyond the current one), bounded by registers
+    constexpr int PF = sizeof(real) == 4 ? (K == 1 ? 4 : 2) : 1;
     constexpr int CB = red_node_block(NW);
     const size_t lds = (size_t)2 * 4 * CB * sizeof(real);
     SMRT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep2d_kernel<real, K, PF, NW>),
@@ -483,7 +571,18 @@ static void launch_k(const Sweep2DArgs &a, hipStream_t s) {
         case 6: launch_knw<real, K, 6>(a, s); break;
         case 7: launch_knw<real, K, 7>(a, s); break;
         case 8: launch_knw<real, K, 8>(a, s); break;
-        default: throw Error(SMRT_E_INVALID_ARG, "waves per workgroup must be in [1, 8]");
+        default:
+            // more than 8 waves only with one group per lane (two would spill)
+            if constexpr (K == 1) {
+                switch (a.NW) {
+                    case 9: launch_knw<real, K, 9>(a, s); return;
+                    case 10: launch_knw<real, K, 10>(a, s); return;
+                    case 11: launch_knw<real, K, 11>(a, s); return;
+                    case 12: launch_knw<real, K, 12>(a, s); return;
+                    default: break;
+                }
+            }
+            throw Error(SMRT_E_INVALID_ARG, "waves per workgroup must be in [1, 12] (in [1, 8] with 2 groups per lane)");
     }
 }
 

@@ -158,43 +158,55 @@ __device__ inline bool skew_to_cell(int nx, int ny, int q, int64_t slot, int &ce
     return true;
 }
 
-// (sigma_t, sigma) per (quadrant, group, skewed cell) from sigma [cell][G] (and sigma_t if given)
+// (sigma_t, sigma) per (quadrant, group, skewed cell) from sigma [cell][G]
+// (and sigma_t if given).  One thread per (quadrant, skewed slot) walks the
+// groups: its reads are the cell's contiguous [G] row, its writes for each
+// group are coalesced across the slots.
 template <typename real>
 __global__ void k_stab2d(int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab) {
     const int64_t cs = cell_slab(nx, ny);
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= 4 * (int64_t)G * cs) return;
+    if (i >= 4 * cs) return;
     const int64_t slot = i % cs;
-    const int qg = (int)(i / cs), g = qg % G, q = qg / G;
+    const int q = (int)(i / cs);
     int cell, flip;
-    if (!skew_to_cell(nx, ny, q, slot, cell, flip)) {
-        stab[2 * i] = real(1);
-        stab[2 * i + 1] = real(0);
-        return;
+    const bool on = skew_to_cell(nx, ny, q, slot, cell, flip);
+    for (int g = 0; g < G; ++g) {
+        const int64_t o = ((int64_t)q * G + g) * cs + slot;
+        if (!on) {
+            stab[2 * o] = real(1);
+            stab[2 * o + 1] = real(0);
+            continue;
+        }
+        const double sg = sig[(int64_t)cell * G + g];
+        stab[2 * o] = (real)(sigt ? sigt[(int64_t)cell * G + g] : sg + icdt);
+        stab[2 * o + 1] = (real)sg;
     }
-    const double s = sig[(int64_t)cell * G + g];
-    stab[2 * i] = (real)(sigt ? sigt[(int64_t)cell * G + g] : s + icdt);
-    stab[2 * i + 1] = (real)s;
 }
 
 // Emission table in the skewed per-quadrant layout (canonical node order) from
-// a natural-order FP64 field q[n * sn + g * sg].
+// a natural-order FP64 field q[n * sn + g * sg]; one thread per (quadrant,
+// skewed slot) walks the groups.
 template <typename real>
 __global__ void k_qtab2d(int nx, int ny, int G, const double *q, int64_t sn, int64_t sg, real *qtab) {
     const int64_t cs = cell_slab(nx, ny);
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= 4 * (int64_t)G * cs) return;
+    if (i >= 4 * cs) return;
     const int64_t slot = i % cs;
-    const int qg = (int)(i / cs), g = qg % G, qd = qg / G;
+    const int qd = (int)(i / cs);
     int cell, flip;
-    if (!skew_to_cell(nx, ny, qd, slot, cell, flip)) {
-        for (int lc = 0; lc < 4; ++lc) qtab[4 * i + lc] = real(0);
-        return;
+    const bool on = skew_to_cell(nx, ny, qd, slot, cell, flip);
+    for (int g = 0; g < G; ++g) {
+        const int64_t o = ((int64_t)qd * G + g) * cs + slot;
+        if (!on) {
+            for (int lc = 0; lc < 4; ++lc) qtab[4 * o + lc] = real(0);
+            continue;
+        }
+        const double *src = q + (int64_t)g * sg + (int64_t)4 * cell * sn;
+        double v[4];
+        for (int l = 0; l < 4; ++l) v[l] = src[l * sn];
+        for (int lc = 0; lc < 4; ++lc) qtab[4 * o + lc] = (real)v[lc ^ flip];
     }
-    const double *src = q + (int64_t)g * sg + (int64_t)4 * cell * sn;
-    double v[4];
-    for (int l = 0; l < 4; ++l) v[l] = src[l * sn];
-    for (int lc = 0; lc < 4; ++lc) qtab[4 * i + lc] = (real)v[lc ^ flip];
 }
 
 // Isotropic equilibrium intensity B_g(T_n)/(4 pi) in the ABI layout [d][g][node]
@@ -297,51 +309,55 @@ __global__ void k_psi_convert(int nx, int ny, int G, int nang, const int *dir_qu
 }
 
 // ---------------------------------------------------------------------------
-// Moment finalisation (2D): mom[27][node] (FP64) = sum over the chunks of each
-// quadrant of the sweep partials, in a fixed order (deterministic).
+// Moment finalisation (2D), deterministic (fixed summation order).
 // Partials: [chunk][band][step t][canonical node lc * 9 + moment][row], the
-// cell of (t, row) being canonical column t - row.  A block owns a 16x16 tile
-// of natural cells (thread = cell) and loops over the 4 nodes; for one chunk
-// the tile's partials form a skewed strip of ~31 steps that stays in L1.
-// Tiles are numbered so that each XCD takes a contiguous run of neighbouring
-// tiles, which share the partial lines at their common edges in its L2.
+// cell of (t, row) being canonical column t - row; chunks are grouped by
+// quadrant.  Pass 1 works in each quadrant's own skewed coordinates (thread =
+// (quadrant, band, step, canonical node, row), so the 16 rows of a wave read
+// contiguous partials), sums the quadrant's chunks in FP64 and writes the 6
+// angular moments of that quadrant into mom and the 3 sigma-weighted ones into
+// a per-quadrant buffer; pass 2 sums those over the 4 quadrants.
 // ---------------------------------------------------------------------------
 template <typename real>
-__global__ void __launch_bounds__(256) k_moments_finalize(int nx, int ny, ChunkRanges cr, const real *part,
-                                                          double *mom) {
-    const int ntx = (nx + 15) / 16;
-    const int nblocks = gridDim.x;
-    const int b = blockIdx.x;
-    const int per = nblocks / 8, rem = nblocks % 8, xcd = b % 8, idx = b / 8;
-    const int tile = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-    const int i = (tile % ntx) * 16 + (threadIdx.x & 15);
-    const int j = (tile / ntx) * 16 + (threadIdx.x >> 4);
-    if (i >= nx || j >= ny) return;
+__global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkRanges cr, const real *part,
+                                                          double *mom, double *sigq) {
     const int nb = (ny + BAND_ROWS - 1) / BAND_ROWS, NT = nx + BAND_ROWS - 1;
-    const int64_t nn = (int64_t)nx * ny * 4;
-    const int64_t cell = i + (int64_t)nx * j;
+    const int ntb = (NT + 3) / 4;
+    int b = blockIdx.x;
+    const int tb = b % ntb;
+    b /= ntb;
+    const int band = b % nb, q = b / nb;
+    const int rc = threadIdx.x & 15, lc = (threadIdx.x >> 4) & 3;
+    const int t = tb * 4 + (threadIdx.x >> 6);
+    const int ic = t - rc, jc = band * BAND_ROWS + rc;
+    if (t >= NT || ic < 0 || ic >= nx || jc >= ny) return;
     constexpr int PB = BAND_ROWS * PART_PER_CELL;   // partial entries per step
-    for (int l = 0; l < 4; ++l) {
-        double acc[27];
+    double acc[NMOM2D];
 #pragma unroll
-        for (int m = 0; m < 27; ++m) acc[m] = 0.0;
+    for (int k = 0; k < NMOM2D; ++k) acc[k] = 0.0;
+    for (int qc = cr.start[q]; qc < cr.start[q + 1]; ++qc) {
+        const real *p = part + (((int64_t)qc * nb + band) * NT + t) * PB + lc * NMOM2D * BAND_ROWS + rc;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const bool fx = (q == 1 || q == 2), fy = (q == 2 || q == 3);
-            const int ic = fx ? nx - 1 - i : i, jc = fy ? ny - 1 - j : j;
-            const int band = jc / BAND_ROWS, rc = jc % BAND_ROWS, t = ic + rc;
-            const int lc = l ^ ((fx ? 1 : 0) | (fy ? 2 : 0));
-            for (int qc = cr.start[q]; qc < cr.start[q + 1]; ++qc) {
-                const real *p = part + (((int64_t)qc * nb + band) * NT + t) * PB + lc * NMOM2D * BAND_ROWS + rc;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) acc[6 * q + k] += (double)p[k * BAND_ROWS];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) acc[24 + k] += (double)p[(6 + k) * BAND_ROWS];
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < 27; ++m) mom[m * nn + 4 * cell + l] = acc[m];
+        for (int k = 0; k < NMOM2D; ++k) acc[k] += (double)p[k * BAND_ROWS];
     }
+    const bool fx = (q == 1 || q == 2), fy = (q == 2 || q == 3);
+    const int i = fx ? nx - 1 - ic : ic, j = fy ? ny - 1 - jc : jc;
+    const int l = lc ^ ((fx ? 1 : 0) | (fy ? 2 : 0));
+    const int64_t nn = (int64_t)nx * ny * 4;
+    const int64_t n = 4 * (i + (int64_t)nx * j) + l;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) mom[(6 * q + k) * nn + n] = acc[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sigq[(3 * q + k) * nn + n] = acc[6 + k];
+}
+
+__global__ void k_moments_sigma(int64_t nn, const double *sigq, double *mom) {
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        mom[(24 + k) * nn + n] = ((sigq[k * nn + n] + sigq[(3 + k) * nn + n]) + sigq[(6 + k) * nn + n]) +
+                                 sigq[(9 + k) * nn + n];
 }
 
 // ---------------------------------------------------------------------------
@@ -454,12 +470,12 @@ void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const do
 }
 template <typename real>
 void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab) {
-    const int64_t n = 4 * (int64_t)G * cell_slab(nx, ny);
+    const int64_t n = 4 * cell_slab(nx, ny);
     hipLaunchKernelGGL(k_stab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, sig, sigt, icdt, stab);
 }
 template <typename real>
 void run_qtab2d(hipStream_t s, int nx, int ny, int G, const double *q, int64_t sn, int64_t sg, real *qtab) {
-    const int64_t n = 4 * (int64_t)G * cell_slab(nx, ny);
+    const int64_t n = 4 * cell_slab(nx, ny);
     hipLaunchKernelGGL(k_qtab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, q, sn, sg, qtab);
 }
 void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
@@ -501,9 +517,13 @@ void run_psi_from_internal(hipStream_t s, int nx, int ny, int G, int nang, const
                        (const double *)nullptr, const_cast<real *>(in), abi);
 }
 template <typename real>
-void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const real *part, double *mom) {
-    hipLaunchKernelGGL(k_moments_finalize<real>, dim3(nblk(nx, 16) * nblk(ny, 16)), dim3(256), 0, s, nx, ny, cr, part,
-                       mom);
+void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const real *part, double *sigq,
+                          double *mom) {
+    const int nb = (ny + BAND_ROWS - 1) / BAND_ROWS, NT = nx + BAND_ROWS - 1;
+    hipLaunchKernelGGL(k_moments_quadrant<real>, dim3(4 * nb * ((NT + 3) / 4)), dim3(256), 0, s, nx, ny, cr, part, mom,
+                       sigq);
+    const int64_t nn = (int64_t)nx * ny * 4;
+    hipLaunchKernelGGL(k_moments_sigma, dim3(nblk(nn, 256)), dim3(256), 0, s, nn, (const double *)sigq, mom);
 }
 template <typename real>
 void launch_sweep1d(const Sweep1DArgs &a, hipStream_t s) {
@@ -532,7 +552,8 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
     template void run_sig_to_internal<real>(hipStream_t, int, int, const double *, const double *, real *);         \
     template void run_psi_to_internal<real>(hipStream_t, int, int, int, int, const int *, const double *, real *);  \
     template void run_psi_from_internal<real>(hipStream_t, int, int, int, int, const int *, const real *, double *); \
-    template void run_moments_finalize<real>(hipStream_t, int, int, const ChunkRanges &, const real *, double *);  \
+    template void run_moments_finalize<real>(hipStream_t, int, int, const ChunkRanges &, const real *, double *,   \
+                                              double *);                                                        \
     template void launch_sweep1d<real>(const Sweep1DArgs &, hipStream_t);                                           \
     template void run_moments1d<real>(hipStream_t, int, int, int, const real *, const double *, const real *, double *);
 INST(float)
