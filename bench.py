@@ -25,11 +25,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep2d_fp32_256x256_S8_G16_hbm_bytes.md")
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2504_21784_amd", "csrc", f) for f in ("sweep2d.hip", "smrt_internal.h")]
 
 
-def cpu_baseline(p, sample_groups=8):
-    """FP64 oracle sweep + moments on the same mesh, angles and opacities,
-    restricted to the first `sample_groups` groups; single thread."""
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the sweep source has changed since those counters."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        h = hashlib.sha256(b"".join(open(f, "rb").read() for f in SWEEP_SOURCES)).hexdigest()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+    if vals.get("source_sha256", "").strip() != h:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def cpu_baseline(p, sample_groups=16):
+    """FP64 oracle sweep + moments on the same mesh, angles and opacities
+    (the first `sample_groups` groups; all 16 by default: one full sweep),
+    single thread."""
     import numpy as np
     import oracle
     from paper_2504_21784_amd import workloads as W
@@ -117,6 +135,8 @@ def main():
     mom32 = ctx.get_moments()
     alg_bytes = info["algorithmic_bytes_per_sweep"]
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    sweep_kernel = f"sweep2d_kernel<float, {info['pairs_per_lane']}, {4 if info['pairs_per_lane'] == 1 else 2}, " \
+                   f"{info['waves_per_group']}>"
     ctx.close()
 
     # FP64 sweep on the same inputs: throughput ratio and FP32 error
@@ -155,8 +175,8 @@ def main():
         "fp32_vs_fp64_sweep_speedup": k64 / k_ms,
         "fp32_phi_rel_l2_vs_fp64": phi_err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep2d_kernel<float,K,2>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": sweep_kernel,
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu_baseline:
