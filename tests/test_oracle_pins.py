@@ -433,3 +433,64 @@ def test_P10_consistent_equals_unaccelerated(oracle_mod, dim):
         Eho = np.einsum("d,dgn->n", p.w, sm["psi"]) / p.c
         assert np.linalg.norm(sm["E"] - Eho) < 1e-8 * np.linalg.norm(Eho)
         assert s1["outer"] <= s2["outer"]
+
+
+# ---------------------------------------------------------------------------
+# Opacity model (Sec. 2 multigroup opacities; the power-law synthetic model
+# sigma0_r / (nubar_g^3 T^3) clipped): invariants that a wrong exponent, a
+# wrong group mean or a wrong cell temperature average would break.
+# ---------------------------------------------------------------------------
+def test_opacity_power_law_invariants(oracle_mod):
+    p = W.multigroup_2d(n=16, G=8)
+    o = oracle_mod.Oracle(p)
+    lo, hi = p.clip_lo, p.clip_hi
+    T1 = np.full(p.n_nodes, 0.4)
+    s1 = o.opacity(T1)
+    s2 = o.opacity(2 * T1)
+    free = (s1 > lo * 1.01) & (s1 < hi / 1.01) & (s2 > lo * 1.01) & (s2 < hi / 1.01)
+    assert free.sum() > 10
+    # sigma scales as T^-3 away from the clip bounds
+    assert np.abs(s2[free] * 8 / s1[free] - 1).max() < 1e-13
+    # group dependence: nubar_g^-3 with nubar the geometric mean of the bounds
+    nub = np.sqrt(p.nu_edges[:-1] * p.nu_edges[1:])
+    ratio = s1[:, 1:] / s1[:, :-1]
+    ok = free[:, 1:] & free[:, :-1]
+    expect = np.broadcast_to((nub[:-1] / nub[1:]) ** 3, ratio.shape)
+    assert ok.sum() > 10
+    assert np.abs(ratio[ok] / expect[ok] - 1).max() < 1e-12
+    # clipping at both ends
+    assert np.all(o.opacity(np.full(p.n_nodes, 1e-4)) == hi)
+    assert np.all(o.opacity(np.full(p.n_nodes, 1e4)) == lo)
+    # the cell temperature is the arithmetic mean of its 4 nodal values
+    Tn = np.repeat(np.array([0.2, 0.3, 0.5, 0.6]), p.n_cells).reshape(4, -1).T.ravel().copy()
+    sm = o.opacity(Tn)
+    su = o.opacity(np.full(p.n_nodes, 0.4))
+    assert np.abs(sm / su - 1).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Moments (Sec. 3 angular moments, quadrant-split in 2D): a single nonzero
+# direction lands in its own quadrant's slots with the weights w, w mu, w eta,
+# w mu^2, w mu eta, w eta^2, and the sigma-weighted slots get sigma w (1, mu, eta).
+# ---------------------------------------------------------------------------
+def test_moments_single_direction_2d(oracle_mod):
+    p = _geom2d(3, 2, sn=4, G=2)
+    o = oracle_mod.Oracle(p)
+    rng = np.random.default_rng(7)
+    sig = rng.uniform(0.5, 2.0, (p.n_cells, p.G))
+    for d in range(p.n_angles):
+        mu, eta = p.omega[d, 0], p.omega[d, 1]
+        q = 0 if (mu > 0 and eta > 0) else 1 if (mu < 0 and eta > 0) else 2 if (mu < 0 and eta < 0) else 3
+        psi = np.zeros((p.n_angles, p.G, p.n_nodes))
+        v = rng.uniform(0.1, 1.0, (p.G, p.n_nodes))
+        psi[d] = v
+        m = o.moments(sig, psi)
+        w = p.w[d]
+        vs = v.sum(0)
+        sv = (sig[np.arange(p.n_nodes) // 4, :].T * v).sum(0)
+        expect = np.zeros_like(m)
+        for k, f in enumerate((1.0, mu, eta, mu * mu, mu * eta, eta * eta)):
+            expect[6 * q + k] = w * f * vs
+        for k, f in enumerate((1.0, mu, eta)):
+            expect[24 + k] = w * f * sv
+        assert np.abs(m - expect).max() < 1e-14 * max(1.0, np.abs(expect).max())
