@@ -235,6 +235,53 @@ smrt_status smrt_get_info(const smrt_ctx *ctx, smrt_info *info);
  * Returns SMRT_E_INVALID_ARG outside these ranges. */
 smrt_status smrt_set_launch(smrt_ctx *ctx, int waves_per_group, int pairs_per_lane);
 
+/* Launch-shape autotuner (2D): on the context's current state with time step
+ * dt, times one sweep for every candidate (waves per workgroup, groups per
+ * lane) that leaves no workgroup with an idle wave in every direction block,
+ * applies the fastest and returns it with its sweep time in ms (any output
+ * pointer may be NULL).  The state is not advanced.  Errors:
+ * SMRT_E_INVALID_ARG before smrt_set_state, for 1D, or for dt <= 0. */
+smrt_status smrt_autotune(smrt_ctx *ctx, double dt, int *waves_per_group, int *pairs_per_lane, double *ms_best);
+
+/* ---- Batches: many independent 2D problems swept in one launch ---------
+ * A batch borrows n contexts (all 2D, one precision, each with a state) and
+ * sweeps every (problem, quadrant, direction block, group block,
+ * band) task of all of them in one persistent launch, in an order where
+ * every band follows the band below it of the same problem (no deadlock at
+ * any residency) and the longest bands start first.  The contexts stay
+ * owned by the caller and must outlive the batch; the batch re-plans their
+ * sweep launch shape (one shape for the whole batch).  A batch call drains
+ * every problem's stream, works on the batch's own stream and drains it
+ * before returning.  The LO of each
+ * problem stays per problem, in FP64 (Sec. 5). */
+typedef struct smrt_batch smrt_batch;
+smrt_status smrt_batch_create(int n, smrt_ctx *const *problems, smrt_batch **out);
+void smrt_batch_destroy(smrt_batch *batch);
+const char *smrt_batch_last_error(const smrt_batch *batch);
+/* Launch shape shared by the batch (waves in [1, 12]; groups per lane 1, or
+ * 2 in FP32 with at most 8 waves). */
+smrt_status smrt_batch_set_launch(smrt_batch *batch, int waves_per_group, int pairs_per_lane);
+/* Total units per batched sweep, workgroup tasks, and the launch shape. */
+smrt_status smrt_batch_info(const smrt_batch *batch, int64_t *units_per_sweep, int *n_tasks, int *waves_per_group,
+                            int *pairs_per_lane);
+/* Batch autotuner: times the batched sweep for every candidate launch shape
+ * on the problems' current states with time step dt, applies and returns the
+ * fastest (ms of one batched sweep). */
+smrt_status smrt_batch_autotune(smrt_batch *batch, double dt, int *waves_per_group, int *pairs_per_lane,
+                                double *ms_best);
+/* Resident high-order pass of every problem (as smrt_sweep_resident, with
+ * all sweeps in one batched launch), n_times.  capture_graph != 0 records
+ * the pass once as a HIP graph (kernels only) and replays it n_times.
+ * Writes the mean time per pass and the time of one batched sweep launch
+ * (ms).  States are not advanced. */
+smrt_status smrt_batch_sweep_resident(smrt_batch *batch, double dt, int n_times, int capture_graph,
+                                      double *ms_per_pass, double *ms_sweep_kernel);
+/* One backward-Euler step (Algorithm 1) of every problem, dt[n] per problem:
+ * the outer iterations run in lock-step, each with one batched sweep over
+ * the problems still iterating; stats[n] (may be NULL) per problem.  Returns
+ * the first problem's failure status (message in smrt_batch_last_error). */
+smrt_status smrt_batch_step(smrt_batch *batch, const double *dt, smrt_step_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <algorithm>
 
 #include "lo.h"
 #include "tables.h"
@@ -41,7 +42,8 @@ struct smrt_ctx {
     std::vector<int> qc_quad;
     std::vector<int> slot_pair;   // pairs (d, g)
     ChunkRanges chunks{};         // chunk range of each quadrant
-    DevBuf<int> d_qc_quad, d_slot_pair, d_ctr;
+    DevBuf<int> d_qc_quad, d_slot_pair, d_ctr, d_lctr;
+    DevBuf<int2> d_tasks;         // single-problem task list (0, band * NQC + chunk)
     DevBuf<unsigned char> d_psi[2], d_part, d_qiso, d_sig2, d_inflow;
     DevBuf<uint64_t> d_trace;
     int cur = 0;
@@ -214,6 +216,12 @@ static void plan_sweep(smrt_ctx *x) {
     SMRT_HIP(hipMemset(x->d_trace.p, 0, sizeof(uint64_t) * x->d_trace.n));
     x->d_ctr.alloc(4);
     hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, x->stream, x->d_ctr.p);
+    std::vector<int2> tasks(x->n_wg);
+    for (int t = 0; t < x->n_wg; ++t) tasks[t] = make_int2(0, t);
+    x->d_tasks.alloc(x->n_wg);
+    SMRT_HIP(hipMemcpy(x->d_tasks.p, tasks.data(), sizeof(int2) * x->n_wg, hipMemcpyHostToDevice));
+    x->d_lctr.alloc(2);
+    SMRT_HIP(hipMemset(x->d_lctr.p, 0, 2 * sizeof(int)));
     SMRT_HIP(hipStreamSynchronize(x->stream));
 }
 
@@ -225,23 +233,39 @@ static int64_t psi_count(const smrt_ctx *x) {
 // ---------------------------------------------------------------------------
 // sweep launch (2D: band kernel + moment finalisation; 1D: pair kernel + moments)
 // ---------------------------------------------------------------------------
+static Sweep2DArgs sweep_args(const smrt_ctx *x, const void *psi_prev, void *psi_out, const void *sig2,
+                              const void *qiso, const void *inflow, double icdt) {
+    Sweep2DArgs a{};
+    a.nx = x->nx; a.ny = x->ny; a.G = x->G; a.nbands = x->nbands; a.NT = x->NT;
+    a.NW = x->NW; a.K = x->K; a.R = x->R; a.NQC = x->NQC; a.n_wg = x->n_wg; a.NB = x->NB;
+    a.qc_quad = x->d_qc_quad.p;
+    a.slot_pair = reinterpret_cast<const int2 *>(x->d_slot_pair.p);
+    a.dirs = x->d_dirs.p; a.hx = x->d_hx.p; a.hy = x->d_hy.p;
+    a.sig2 = sig2; a.qiso = qiso; a.psi_prev = psi_prev; a.psi_out = psi_out; a.inflow = inflow;
+    a.inv_c_dt = icdt; a.part = x->d_part.p; a.trace = x->d_trace.p; a.ctr = x->d_ctr.p;
+    return a;
+}
+
+static void finalize_moments(smrt_ctx *x, double *mom) {
+    if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, x->d_sigq.p, mom);
+    else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, x->d_sigq.p, mom);
+}
+
 static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const void *sig2, const void *qiso,
                       const void *inflow, double icdt, const double *sig64, double *mom, bool finalize = true) {
     if (x->dim == 2) {
-        Sweep2DArgs a{};
-        a.nx = x->nx; a.ny = x->ny; a.G = x->G; a.nbands = x->nbands; a.NT = x->NT;
-        a.NW = x->NW; a.K = x->K; a.R = x->R; a.NQC = x->NQC; a.n_wg = x->n_wg; a.NB = x->NB;
-        a.qc_quad = x->d_qc_quad.p;
-        a.slot_pair = reinterpret_cast<const int2 *>(x->d_slot_pair.p);
-        a.dirs = x->d_dirs.p; a.hx = x->d_hx.p; a.hy = x->d_hy.p;
-        a.sig2 = sig2; a.qiso = qiso; a.psi_prev = psi_prev; a.psi_out = psi_out; a.inflow = inflow;
-        a.inv_c_dt = icdt; a.part = x->d_part.p; a.trace = x->d_trace.p; a.ctr = x->d_ctr.p;
-        if (x->fp32) launch_sweep2d<float>(a, x->stream);
-        else launch_sweep2d<double>(a, x->stream);
-        if (finalize) {
-            if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, x->d_sigq.p, mom);
-            else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, x->d_sigq.p, mom);
-        }
+        const Sweep2DArgs a = sweep_args(x, psi_prev, psi_out, sig2, qiso, inflow, icdt);
+        SweepLaunch L{};
+        L.single = a;
+        L.probs = nullptr;
+        L.tasks = x->d_tasks.p;
+        L.n_tasks = x->n_wg;
+        L.NW = x->NW;
+        L.K = x->K;
+        L.lctr = x->d_lctr.p;
+        if (x->fp32) launch_sweep2d<float>(L, x->stream);
+        else launch_sweep2d<double>(L, x->stream);
+        if (finalize) finalize_moments(x, mom);
     } else {
         Sweep1DArgs a{};
         a.nx = x->nx; a.G = x->G; a.nang = x->nang; a.mu_w = x->d_mu_w.p; a.hx = x->d_hx.p;
@@ -804,17 +828,28 @@ static void run_source_at(smrt_ctx *x, const double *T) {
     }
 }
 
-extern "C" smrt_status smrt_step(smrt_ctx *x, double dt, smrt_step_stats *stats) {
-    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+// One backward-Euler step (Algorithm 1) split into phases, so that a batch
+// can run the outer iterations of many problems in lock-step with one
+// batched sweep per outer iteration.
+struct StepRun {
+    smrt_ctx *x = nullptr;
+    double dt = 0, icdt = 0, first = -1.0;
+    int l = 0, maxo = 0;
+    bool unacc = false, done = false;
     smrt_status result = SMRT_OK;
-    smrt_status st = guard(x, [&] {
+    smrt_step_stats s{};
+    void *pin = nullptr, *pout = nullptr;
+    float t_sweep = 0.f;
+
+    void begin(smrt_ctx *ctx, double step_dt) {
+        x = ctx;
+        dt = step_dt;
         require(dt > 0.0 && std::isfinite(dt), "dt must be finite and > 0");
         require(x->have_state, "smrt_set_state must be called before smrt_step");
-        smrt_step_stats s{};
         hipStream_t S = x->stream;
         const int64_t nn = x->nn;
         SMRT_HIP(hipEventRecord(x->ev0, S));
-        const double icdt = prepare_step_tables(x, dt);
+        icdt = prepare_step_tables(x, dt);
         SMRT_HIP(hipMemcpyAsync(x->d_Tstar.p, x->d_T.p, 8 * nn, hipMemcpyDeviceToDevice, S));
         if (x->opt.lo_time_edge) {
             SMRT_HIP(hipMemcpyAsync(x->d_Estar.p, x->d_E.p, 8 * nn, hipMemcpyDeviceToDevice, S));
@@ -824,67 +859,66 @@ extern "C" smrt_status smrt_step(smrt_ctx *x, double dt, smrt_step_stats *stats)
             SMRT_HIP(hipMemcpyAsync(x->d_Fstar.p, x->d_Fho.p, 8 * nn * x->dim, hipMemcpyDeviceToDevice, S));
         }
         SMRT_HIP(hipMemcpyAsync(x->d_Tl.p, x->d_T.p, 8 * nn, hipMemcpyDeviceToDevice, S));
-        const bool unacc = x->opt.scheme == SMRT_UNACCELERATED;
+        unacc = x->opt.scheme == SMRT_UNACCELERATED;
         SMRT_HIP(hipMemcpyAsync(x->d_El.p, unacc ? x->d_Estar.p : x->d_E.p, 8 * nn, hipMemcpyDeviceToDevice, S));
-        double first = -1.0;
-        const int maxo = x->opt.fixed_outer > 0 ? x->opt.fixed_outer : x->opt.max_outer;
-        void *pin = x->d_psi[x->cur].p, *pout = x->d_psi[1 - x->cur].p;
-        float t_sweep = 0.f;
-        for (int l = 1; l <= maxo; ++l) {
-            run_source_at(x, x->d_Tl.p);
-            SMRT_HIP(hipEventRecord(x->ev1, S));
-            hipEvent_t e0, e1;
-            SMRT_HIP(hipEventCreate(&e0));
-            SMRT_HIP(hipEventCreate(&e1));
-            SMRT_HIP(hipEventRecord(e0, S));
-            run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p);
-            SMRT_HIP(hipEventRecord(e1, S));
-            s.outer++;
-            SMRT_HIP(hipMemcpyAsync(x->d_Tn.p, x->d_Tl.p, 8 * nn, hipMemcpyDeviceToDevice, S));
-            if (unacc) {
-                // pointwise elimination against sum_g sigma_g phi_g of the sweep
-                hipLaunchKernelGGL(k_ho_from_mom, dim3(nblk(nn)), dim3(256), 0, S, (int)nn, x->dim, x->c, x->d_mom.p,
-                                   x->d_sigP.p, x->d_En.p, (double *)nullptr, x->d_sigEho.p);
-                LoSolver &L = x->lo;
-                hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, S, L.flags.p, 4);
-                run_eliminate(S, (int)nn, x->a, x->c, dt, x->opt.elim_rtol, x->opt.max_elim, x->d_cvn.p, x->d_sigEho.p,
-                              x->d_sigP.p, x->d_En.p, x->d_Tstar.p, x->d_Tn.p, L.flags.p);
-                int fl[4];
-                d2h(fl, L.flags.p, sizeof fl, S);
-                SMRT_HIP(hipStreamSynchronize(S));
-                if (fl[1] > s.elim_max) s.elim_max = fl[1];
-                if (fl[0]) { x->err = "no positive temperature root in the energy balance"; result = SMRT_E_NONPHYSICAL; }
-            } else {
-                SMRT_HIP(hipMemcpyAsync(x->d_En.p, x->d_El.p, 8 * nn, hipMemcpyDeviceToDevice, S));
-                run_closures(S, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt, x->d_mom.p, x->d_sigP.p,
-                                             x->d_sigF.p, x->d_Estar.p, x->d_Fstar.p, x->d_clos.p));
-                LoInputs in = lo_inputs(x, dt, x->d_clos.p);
-                in.Tstar = x->d_Tstar.p;
-                smrt_step_stats ls{};
-                const smrt_status r = x->lo.solve(S, in, x->d_En.p, x->d_F.p, x->d_Tn.p, &ls, x->err);
-                s.inner_total += ls.inner_total;
-                s.cg_total += ls.cg_total;
-                s.elim_max = std::max(s.elim_max, ls.elim_max);
-                s.hit_max |= ls.hit_max;
-                if (r != SMRT_OK) result = r;
-            }
-            float ms = 0.f;
-            SMRT_HIP(hipEventSynchronize(e1));
-            SMRT_HIP(hipEventElapsedTime(&ms, e0, e1));
-            t_sweep += ms;
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            check_sweep_flag(x);
-            const double diff = diff_norm(x, x->d_Tn.p, x->d_Tl.p, x->d_En.p, x->d_El.p);
-            SMRT_HIP(hipMemcpyAsync(x->d_Tl.p, x->d_Tn.p, 8 * nn, hipMemcpyDeviceToDevice, S));
-            SMRT_HIP(hipMemcpyAsync(x->d_El.p, x->d_En.p, 8 * nn, hipMemcpyDeviceToDevice, S));
-            if (result != SMRT_OK) break;
-            if (!std::isfinite(diff)) { x->err = "non-finite outer iterate"; result = SMRT_E_NONPHYSICAL; break; }
-            if (x->opt.fixed_outer > 0) continue;
-            if (l == 1) first = diff;
-            if (diff == 0.0 || (l > 1 && diff < x->opt.eps_outer * first)) break;
-            if (l == maxo) s.hit_max = 1;
+        maxo = x->opt.fixed_outer > 0 ? x->opt.fixed_outer : x->opt.max_outer;
+        pin = x->d_psi[x->cur].p;
+        pout = x->d_psi[1 - x->cur].p;
+    }
+    // emission tables at the current outer temperature
+    void pre_sweep() {
+        ++l;
+        run_source_at(x, x->d_Tl.p);
+    }
+    // LO (or pointwise elimination) after the sweep; returns true once the
+    // outer iteration of this step is finished
+    bool post_sweep() {
+        hipStream_t S = x->stream;
+        const int64_t nn = x->nn;
+        s.outer++;
+        SMRT_HIP(hipMemcpyAsync(x->d_Tn.p, x->d_Tl.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+        if (unacc) {
+            // pointwise elimination against sum_g sigma_g phi_g of the sweep
+            hipLaunchKernelGGL(k_ho_from_mom, dim3(nblk(nn)), dim3(256), 0, S, (int)nn, x->dim, x->c, x->d_mom.p,
+                               x->d_sigP.p, x->d_En.p, (double *)nullptr, x->d_sigEho.p);
+            LoSolver &L = x->lo;
+            hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, S, L.flags.p, 4);
+            run_eliminate(S, (int)nn, x->a, x->c, dt, x->opt.elim_rtol, x->opt.max_elim, x->d_cvn.p, x->d_sigEho.p,
+                          x->d_sigP.p, x->d_En.p, x->d_Tstar.p, x->d_Tn.p, L.flags.p);
+            int fl[4];
+            d2h(fl, L.flags.p, sizeof fl, S);
+            SMRT_HIP(hipStreamSynchronize(S));
+            if (fl[1] > s.elim_max) s.elim_max = fl[1];
+            if (fl[0]) { x->err = "no positive temperature root in the energy balance"; result = SMRT_E_NONPHYSICAL; }
+        } else {
+            SMRT_HIP(hipMemcpyAsync(x->d_En.p, x->d_El.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+            run_closures(S, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt, x->d_mom.p, x->d_sigP.p,
+                                         x->d_sigF.p, x->d_Estar.p, x->d_Fstar.p, x->d_clos.p));
+            LoInputs in = lo_inputs(x, dt, x->d_clos.p);
+            in.Tstar = x->d_Tstar.p;
+            smrt_step_stats ls{};
+            const smrt_status r = x->lo.solve(S, in, x->d_En.p, x->d_F.p, x->d_Tn.p, &ls, x->err);
+            s.inner_total += ls.inner_total;
+            s.cg_total += ls.cg_total;
+            s.elim_max = std::max(s.elim_max, ls.elim_max);
+            s.hit_max |= ls.hit_max;
+            if (r != SMRT_OK) result = r;
         }
+        check_sweep_flag(x);
+        const double diff = diff_norm(x, x->d_Tn.p, x->d_Tl.p, x->d_En.p, x->d_El.p);
+        SMRT_HIP(hipMemcpyAsync(x->d_Tl.p, x->d_Tn.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+        SMRT_HIP(hipMemcpyAsync(x->d_El.p, x->d_En.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+        if (result != SMRT_OK) return done = true;
+        if (!std::isfinite(diff)) { x->err = "non-finite outer iterate"; result = SMRT_E_NONPHYSICAL; return done = true; }
+        if (x->opt.fixed_outer > 0) return done = (l >= maxo);
+        if (l == 1) first = diff;
+        if (diff == 0.0 || (l > 1 && diff < x->opt.eps_outer * first)) return done = true;
+        if (l == maxo) { s.hit_max = 1; return done = true; }
+        return false;
+    }
+    smrt_status end(smrt_step_stats *stats) {
+        hipStream_t S = x->stream;
+        const int64_t nn = x->nn;
         // new state: T, E from the last outer iterate; psi and HO moments from the last sweep
         SMRT_HIP(hipMemcpyAsync(x->d_T.p, x->d_Tl.p, 8 * nn, hipMemcpyDeviceToDevice, S));
         SMRT_HIP(hipMemcpyAsync(x->d_E.p, x->d_El.p, 8 * nn, hipMemcpyDeviceToDevice, S));
@@ -903,8 +937,42 @@ extern "C" smrt_status smrt_step(smrt_ctx *x, double dt, smrt_step_stats *stats)
             result = SMRT_E_NOT_CONVERGED;
             x->err = "iteration cap reached";
         }
+        return result;
+    }
+};
+
+// time one stream-ordered section (ms)
+template <typename F>
+static float timed(hipStream_t S, F &&f) {
+    hipEvent_t e0, e1;
+    SMRT_HIP(hipEventCreate(&e0));
+    SMRT_HIP(hipEventCreate(&e1));
+    SMRT_HIP(hipEventRecord(e0, S));
+    f();
+    SMRT_HIP(hipEventRecord(e1, S));
+    SMRT_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    SMRT_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
+
+extern "C" smrt_status smrt_step(smrt_ctx *x, double dt, smrt_step_stats *stats) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    StepRun run;
+    smrt_status st = guard(x, [&] {
+        run.begin(x, dt);
+        for (;;) {
+            run.pre_sweep();
+            run.t_sweep += timed(x->stream, [&] {
+                run_sweep(x, run.pin, run.pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, run.icdt, x->d_sig.p, x->d_mom.p);
+            });
+            if (run.post_sweep()) break;
+        }
+        run.end(stats);
     });
-    return st != SMRT_OK ? st : result;
+    return st != SMRT_OK ? st : run.result;
 }
 
 extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, double *ms_per_pass,
@@ -956,4 +1024,408 @@ extern "C" smrt_status smrt_get_moments(smrt_ctx *x, double *moments) {
         d2h(moments, x->d_mom.p, 8 * x->d_mom.n, x->stream);
         SMRT_HIP(hipStreamSynchronize(x->stream));
     });
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape autotuner (one problem): time one sweep per candidate
+// (waves per workgroup, groups per lane) on the context's current state and
+// keep the fastest.
+// ---------------------------------------------------------------------------
+static std::vector<std::pair<int, int>> launch_candidates(bool fp32, int max_dirs_per_quadrant) {
+    std::vector<std::pair<int, int>> c;
+    for (int k = 1; k <= (fp32 ? 2 : 1); ++k)
+        for (int nw = 1; nw <= (k == 1 ? MAX_SWEEP_WAVES : 8); ++nw) {
+            if (nw > max_dirs_per_quadrant) break;          // only idle waves beyond this
+            const int blocks = (max_dirs_per_quadrant + nw - 1) / nw;
+            if (blocks * nw - max_dirs_per_quadrant >= blocks) continue;   // an idle wave in every block
+            c.emplace_back(nw, k);
+        }
+    return c;
+}
+
+static int max_dirs_per_quadrant(const smrt_ctx *x) {
+    int cnt[4] = {0, 0, 0, 0};
+    for (int d = 0; d < x->nang; ++d) {
+        const double mu = x->om[3 * d], eta = x->om[3 * d + 1];
+        cnt[(mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3]++;
+    }
+    return *std::max_element(cnt, cnt + 4);
+}
+
+extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_group, int *pairs_per_lane, double *ms_best) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(x->dim == 2, "the launch shape applies to 2D sweeps");
+        require(x->have_state, "smrt_set_state must be called first");
+        require(dt > 0.0, "dt must be > 0");
+        const double icdt = prepare_step_tables(x, dt);
+        run_source_at(x, x->d_T.p);
+        void *pin = x->d_psi[x->cur].p, *pout = x->d_psi[1 - x->cur].p;
+        float best = 1e30f;
+        int bnw = 0, bk = 0;
+        for (auto [nw, k] : launch_candidates(x->fp32, max_dirs_per_quadrant(x))) {
+            SMRT_HIP(hipStreamSynchronize(x->stream));
+            x->user_NW = nw;
+            x->user_K = k;
+            plan_sweep(x);
+            auto once = [&] { run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p, false); };
+            once();   // warm-up
+            const float ms = std::min(timed(x->stream, once), timed(x->stream, once));
+            check_sweep_flag(x);
+            if (ms < best) { best = ms; bnw = nw; bk = k; }
+        }
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+        x->user_NW = bnw;
+        x->user_K = bk;
+        plan_sweep(x);
+        if (waves_per_group) *waves_per_group = bnw;
+        if (pairs_per_lane) *pairs_per_lane = bk;
+        if (ms_best) *ms_best = best;
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Batches: every sweep task of many 2D problems in one persistent launch.
+// ---------------------------------------------------------------------------
+struct smrt_batch {
+    std::string err;
+    std::vector<smrt_ctx *> P;
+    hipStream_t stream = nullptr;   // the batch's own stream (default priority)
+    bool fp32 = false;
+    int NW = 0, K = 1;
+    DevBuf<Sweep2DArgs> d_args;
+    DevBuf<int2> d_tasks;
+    DevBuf<int> d_lctr;
+    std::vector<Sweep2DArgs> h_args;
+    std::vector<int> task_set;    // active set the uploaded task list was built for
+    int n_tasks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    ~smrt_batch() {
+        drop_graph();
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+    void drop_graph() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+// For the duration of a batch call every problem works on the batch stream:
+// each problem's own stream is drained first and the batch stream is drained
+// before the problems get their streams back.
+struct BatchStreams {
+    smrt_batch *b;
+    std::vector<hipStream_t> saved;
+    explicit BatchStreams(smrt_batch *bb) : b(bb) {
+        for (smrt_ctx *x : b->P) {
+            SMRT_HIP(hipStreamSynchronize(x->stream));
+            saved.push_back(x->stream);
+            x->stream = b->stream;
+        }
+    }
+    ~BatchStreams() {
+        (void)hipStreamSynchronize(b->stream);
+        for (size_t i = 0; i < saved.size(); ++i) b->P[i]->stream = saved[i];
+    }
+};
+
+template <typename F>
+static smrt_status bguard(smrt_batch *b, F &&f) {
+    try {
+        f();
+        return SMRT_OK;
+    } catch (const smrt::Error &e) {
+        if (b) b->err = e.msg;
+        g_last_error = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return SMRT_E_OUT_OF_MEMORY;
+    } catch (...) {
+        g_last_error = "unexpected exception";
+        return SMRT_E_DEVICE;
+    }
+}
+
+// re-plan every problem with the batch's launch shape
+static void batch_plan(smrt_batch *b, int nw, int k) {
+    SMRT_HIP(hipStreamSynchronize(b->stream));
+    b->drop_graph();
+    b->task_set.clear();
+    for (smrt_ctx *x : b->P) {
+        x->user_NW = nw;
+        x->user_K = k;
+        plan_sweep(x);
+    }
+    b->NW = b->P[0]->NW;
+    b->K = b->P[0]->K;
+    for (smrt_ctx *x : b->P) require(x->NW == b->NW && x->K == b->K, "problems of a batch need one launch shape: set it explicitly");
+}
+
+// Task list over the given problems: band level by band level (so every band
+// follows the band below it), and within a level the problems with the
+// longest bands first (their pipelines are the critical paths).
+static void batch_upload_tasks(smrt_batch *b, const std::vector<int> &active) {
+    if (active == b->task_set) return;
+    std::vector<int> order(active.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return b->P[active[i]]->NT > b->P[active[j]]->NT; });
+    int maxb = 0;
+    for (int p : active) maxb = std::max(maxb, b->P[p]->nbands);
+    std::vector<int2> tasks;
+    for (int band = 0; band < maxb; ++band)
+        for (int i : order) {
+            const smrt_ctx *x = b->P[active[i]];
+            if (band >= x->nbands) continue;
+            for (int qc = 0; qc < x->NQC; ++qc) tasks.push_back(make_int2(i, band * x->NQC + qc));
+        }
+    b->n_tasks = (int)tasks.size();
+    b->d_tasks.alloc(std::max<int64_t>(1, b->n_tasks));
+    SMRT_HIP(hipMemcpyAsync(b->d_tasks.p, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice, b->stream));
+    SMRT_HIP(hipStreamSynchronize(b->stream));
+    b->task_set = active;
+}
+
+// argument blocks of the active problems (position i in the launch = active[i])
+static void batch_upload_args(smrt_batch *b, const std::vector<int> &active, const std::vector<double> &icdt) {
+    b->h_args.resize(active.size());
+    for (size_t i = 0; i < active.size(); ++i) {
+        smrt_ctx *x = b->P[active[i]];
+        b->h_args[i] = sweep_args(x, x->d_psi[x->cur].p, x->d_psi[1 - x->cur].p, x->d_sig2.p, x->d_qiso.p,
+                                  x->d_inflow.p, icdt[active[i]]);
+    }
+    if (b->d_args.n < (int64_t)active.size()) b->d_args.alloc((int64_t)b->P.size());
+    SMRT_HIP(hipMemcpyAsync(b->d_args.p, b->h_args.data(), sizeof(Sweep2DArgs) * active.size(), hipMemcpyHostToDevice,
+                            b->stream));
+    SMRT_HIP(hipStreamSynchronize(b->stream));
+}
+
+static void batch_launch(smrt_batch *b) {
+    SweepLaunch L{};
+    L.probs = b->d_args.p;
+    L.tasks = b->d_tasks.p;
+    L.n_tasks = b->n_tasks;
+    L.NW = b->NW;
+    L.K = b->K;
+    L.lctr = b->d_lctr.p;
+    if (b->fp32) launch_sweep2d<float>(L, b->stream);
+    else launch_sweep2d<double>(L, b->stream);
+}
+
+static std::vector<int> all_problems(const smrt_batch *b) {
+    std::vector<int> a(b->P.size());
+    std::iota(a.begin(), a.end(), 0);
+    return a;
+}
+
+extern "C" smrt_status smrt_batch_create(int n, smrt_ctx *const *problems, smrt_batch **out) {
+    if (!out || !problems || n < 1) { g_last_error = "invalid argument"; return SMRT_E_INVALID_ARG; }
+    *out = nullptr;
+    auto b = std::make_unique<smrt_batch>();
+    smrt_status st = bguard(b.get(), [&] {
+        for (int i = 0; i < n; ++i) {
+            smrt_ctx *x = problems[i];
+            require(x != nullptr, "NULL problem");
+            require(x->dim == 2, "batched sweeps are 2D");
+            require(x->have_state, "every problem needs a state (smrt_set_state) before batching");
+            require(x->fp32 == problems[0]->fp32, "problems of a batch share one precision");
+            for (int j = 0; j < i; ++j) require(problems[j] != x, "a problem appears twice in the batch");
+            b->P.push_back(x);
+        }
+        SMRT_HIP(hipStreamCreate(&b->stream));
+        b->fp32 = problems[0]->fp32;
+        BatchStreams on(b.get());
+        b->d_lctr.alloc(2);
+        SMRT_HIP(hipMemsetAsync(b->d_lctr.p, 0, 2 * sizeof(int), b->stream));
+        // default shape: the largest problem's automatic one, shared by all
+        int big = 0;
+        for (int i = 1; i < n; ++i)
+            if ((int64_t)b->P[i]->ncell * b->P[i]->nang * b->P[i]->G > (int64_t)b->P[big]->ncell * b->P[big]->nang * b->P[big]->G) big = i;
+        smrt_ctx *xb = b->P[big];
+        xb->user_NW = 0;
+        xb->user_K = 0;
+        plan_sweep(xb);
+        batch_plan(b.get(), xb->NW, xb->K);
+    });
+    if (st != SMRT_OK) return st;
+    *out = b.release();
+    return SMRT_OK;
+}
+
+extern "C" void smrt_batch_destroy(smrt_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+extern "C" const char *smrt_batch_last_error(const smrt_batch *b) { return b ? b->err.c_str() : g_last_error.c_str(); }
+
+extern "C" smrt_status smrt_batch_set_launch(smrt_batch *b, int waves_per_group, int pairs_per_lane) {
+    if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
+    return bguard(b, [&] {
+        BatchStreams on(b);
+        require(waves_per_group >= 1 && waves_per_group <= MAX_SWEEP_WAVES, "waves per group must be in [1, 12]");
+        require(pairs_per_lane == 1 || (pairs_per_lane == 2 && b->fp32 && waves_per_group <= 8),
+                "pairs per lane must be 1, or 2 (FP32, at most 8 waves)");
+        batch_plan(b, waves_per_group, pairs_per_lane);
+    });
+}
+
+extern "C" smrt_status smrt_batch_info(const smrt_batch *b, int64_t *units_per_sweep, int *n_tasks,
+                                       int *waves_per_group, int *pairs_per_lane) {
+    if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
+    int64_t u = 0, t = 0;
+    for (const smrt_ctx *x : b->P) {
+        u += (int64_t)x->ncell * x->nang * x->G;
+        t += x->n_wg;
+    }
+    if (units_per_sweep) *units_per_sweep = u;
+    if (n_tasks) *n_tasks = (int)t;
+    if (waves_per_group) *waves_per_group = b->NW;
+    if (pairs_per_lane) *pairs_per_lane = b->K;
+    return SMRT_OK;
+}
+
+// tables, sources and one batched sweep of every problem (+ finalisation and closures)
+static void batch_tables(smrt_batch *b, double dt, std::vector<double> &icdt) {
+    icdt.assign(b->P.size(), 0.0);
+    for (size_t i = 0; i < b->P.size(); ++i) {
+        smrt_ctx *x = b->P[i];
+        icdt[i] = prepare_step_tables(x, dt);
+        run_source_at(x, x->d_T.p);
+    }
+}
+static void batch_post(smrt_batch *b, double dt) {
+    for (smrt_ctx *x : b->P) {
+        finalize_moments(x, x->d_mom.p);
+        run_closures(x->stream, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt, x->d_mom.p,
+                                             x->d_sigP.p, x->d_sigF.p, x->d_Eho.p, x->d_Fho.p, x->d_clos.p));
+    }
+}
+
+extern "C" smrt_status smrt_batch_sweep_resident(smrt_batch *b, double dt, int n_times, int capture_graph,
+                                                 double *ms_per_pass, double *ms_sweep_kernel) {
+    if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
+    return bguard(b, [&] {
+        BatchStreams on(b);
+        require(dt > 0.0 && n_times >= 1 && ms_per_pass && ms_sweep_kernel, "invalid argument");
+        const std::vector<int> all = all_problems(b);
+        std::vector<double> icdt(b->P.size());
+        for (size_t i = 0; i < b->P.size(); ++i) icdt[i] = 1.0 / (b->P[i]->c * dt);
+        batch_upload_tasks(b, all);
+        batch_upload_args(b, all, icdt);
+        // the batched sweep alone (eager), for the kernel time
+        batch_tables(b, dt, icdt);
+        batch_launch(b);
+        SMRT_HIP(hipStreamSynchronize(b->stream));
+        float ks = 1e30f;
+        for (int r = 0; r < 2; ++r) ks = std::min(ks, timed(b->stream, [&] { batch_launch(b); }));
+        for (smrt_ctx *x : b->P) check_sweep_flag(x);
+        auto pass = [&] {
+            std::vector<double> ic;
+            batch_tables(b, dt, ic);
+            batch_launch(b);
+            batch_post(b, dt);
+        };
+        float ms = 0.f;
+        if (capture_graph) {
+            b->drop_graph();
+            SMRT_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            try {
+                pass();
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(b->stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            SMRT_HIP(hipStreamEndCapture(b->stream, &b->graph));
+            SMRT_HIP(hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0));
+            SMRT_HIP(hipGraphLaunch(b->graph_exec, b->stream));   // warm-up replay
+            SMRT_HIP(hipStreamSynchronize(b->stream));
+            ms = timed(b->stream, [&] {
+                for (int k = 0; k < n_times; ++k) SMRT_HIP(hipGraphLaunch(b->graph_exec, b->stream));
+            });
+        } else {
+            ms = timed(b->stream, [&] {
+                for (int k = 0; k < n_times; ++k) pass();
+            });
+        }
+        for (smrt_ctx *x : b->P) check_sweep_flag(x);
+        *ms_per_pass = ms / n_times;
+        *ms_sweep_kernel = ks;
+    });
+}
+
+extern "C" smrt_status smrt_batch_autotune(smrt_batch *b, double dt, int *waves_per_group, int *pairs_per_lane,
+                                           double *ms_best) {
+    if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
+    return bguard(b, [&] {
+        BatchStreams on(b);
+        require(dt > 0.0, "dt must be > 0");
+        int maxd = 0;
+        for (const smrt_ctx *x : b->P) maxd = std::max(maxd, max_dirs_per_quadrant(x));
+        float best = 1e30f;
+        int bnw = b->NW, bk = b->K;
+        const std::vector<int> all = all_problems(b);
+        for (auto [nw, k] : launch_candidates(b->fp32, maxd)) {
+            batch_plan(b, nw, k);
+            std::vector<double> icdt;
+            batch_tables(b, dt, icdt);
+            batch_upload_tasks(b, all);
+            batch_upload_args(b, all, icdt);
+            batch_launch(b);   // warm-up
+            const float ms = std::min(timed(b->stream, [&] { batch_launch(b); }), timed(b->stream, [&] { batch_launch(b); }));
+            for (smrt_ctx *x : b->P) check_sweep_flag(x);
+            if (ms < best) { best = ms; bnw = nw; bk = k; }
+        }
+        batch_plan(b, bnw, bk);
+        if (waves_per_group) *waves_per_group = bnw;
+        if (pairs_per_lane) *pairs_per_lane = bk;
+        if (ms_best) *ms_best = best;
+    });
+}
+
+extern "C" smrt_status smrt_batch_step(smrt_batch *b, const double *dt, smrt_step_stats *stats) {
+    if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
+    const size_t n = b->P.size();
+    std::vector<StepRun> runs(n);
+    smrt_status result = SMRT_OK;
+    smrt_status st = bguard(b, [&] {
+        BatchStreams on(b);
+        require(dt != nullptr, "dt is NULL");
+        for (size_t i = 0; i < n; ++i) runs[i].begin(b->P[i], dt[i]);
+        std::vector<int> active = all_problems(b);
+        while (!active.empty()) {
+            std::vector<double> icdt(n, 0.0);
+            for (int p : active) {
+                runs[p].pre_sweep();
+                icdt[p] = runs[p].icdt;
+            }
+            batch_upload_tasks(b, active);
+            batch_upload_args(b, active, icdt);
+            const float ms = timed(b->stream, [&] {
+                batch_launch(b);
+                for (int p : active) finalize_moments(b->P[p], b->P[p]->d_mom.p);
+            });
+            std::vector<int> next;
+            for (int p : active) {
+                runs[p].t_sweep += ms;
+                if (!runs[p].post_sweep()) next.push_back(p);
+            }
+            active.swap(next);
+        }
+        for (size_t i = 0; i < n; ++i) {
+            const smrt_status r = runs[i].end(stats ? stats + i : nullptr);
+            if (r != SMRT_OK && result == SMRT_OK) {
+                result = r;
+                b->err = "problem " + std::to_string(i) + ": " + b->P[i]->err;
+            }
+        }
+    });
+    if (st == SMRT_OK && result != SMRT_OK) g_last_error = b->err;
+    return st != SMRT_OK ? st : result;
 }

@@ -54,7 +54,20 @@ struct Sweep2DArgs {
     double inv_c_dt;
     void *part;                      // real [NQC][nbands][NT][16][36]
     uint64_t *trace;                 // [NQC][nbands][R][nx][2 * words]
-    int *ctr;                        // [4]: ticket, done, epoch, error flag
+    int *ctr;                        // [4]: (unused), workgroups done, epoch, error flag
+};
+
+// One sweep launch: one problem (args by value) or a batch of problems
+// (device array), and the launch's task list.  A task is (problem, band *
+// NQC + chunk); the list is ordered so that every band comes after the band
+// below it of the same problem and chunk (deadlock-free at any residency).
+struct SweepLaunch {
+    Sweep2DArgs single;              // used when probs == nullptr
+    const Sweep2DArgs *probs;        // [n_probs] device array (batch) or nullptr
+    const int2 *tasks;               // [n_tasks]
+    int n_tasks;
+    int NW, K;                       // launch shape shared by every problem
+    int *lctr;                       // [2]: ticket, tasks done (reset by the last workgroup)
 };
 
 // Internal angular-flux layout (both precisions): [d][g][band][t][r][4 canonical nodes].
@@ -71,7 +84,7 @@ __host__ __device__ inline int64_t cell_slab(int nx, int ny) {
 }
 
 template <typename real>
-void launch_sweep2d(const Sweep2DArgs &a, hipStream_t s);
+void launch_sweep2d(const SweepLaunch &L, hipStream_t s);
 
 struct Sweep1DArgs {
     int nx, G, nang;

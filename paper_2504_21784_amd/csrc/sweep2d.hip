@@ -30,16 +30,19 @@
 //    totals, and channel c forms the 9 moments of canonical node c.  A workgroup = NW waves = NW directions of one
 //    quadrant on the same band and the same 4K groups; their 9-value
 //    contributions are reduced through double-buffered LDS every step
-//    (summed in FP64 in a fixed order, one barrier per step) into one
-//    partial per cell and workgroup.
+//    (summed at the sweep precision in a fixed order, one barrier per step)
+//    into one partial per cell and workgroup; partials are summed in FP64
+//    by the finalisation kernels.
 //  * Bands hand their top-row outflow to the band above through a trace
 //    buffer of 64-bit words that carry (sweep epoch, value bits), written
 //    and polled with relaxed device-scope atomics: a word is valid when
 //    its epoch matches, so no cache flushes are needed.  Workgroups take
-//    tasks from a ticket counter in band-major order, so a workgroup only
-//    ever waits on a band whose workgroup started earlier: no deadlock,
-//    whatever the residency.  Every wait is bounded (SPIN_LIMIT) and sets an
-//    error flag instead of hanging.
+//    tasks (problem, band, chunk) from a ticket counter over a task list in
+//    which every band follows the band below it, so a workgroup only ever
+//    waits on a band whose workgroup started earlier: no deadlock, whatever
+//    the residency.  One launch may sweep many problems (a batch): each
+//    problem keeps its own epoch, done counter and error flag.  Every wait
+//    is bounded (SPIN_LIMIT) and sets an error flag instead of hanging.
 //  * Angular-flux layout [d][g][band][t][r][node]: at step t a channel's 16
 //    lanes read and write 16 consecutive 4-node cells (256 B in FP32).
 #include "smrt_internal.h"
@@ -152,6 +155,20 @@ __device__ __forceinline__ void bload_pair(double &a, double &b, rsrc_t r, uint3
     a = v.x; b = v.y;
 }
 
+// A batch problem's arguments, read from the device array and made
+// wave-uniform dword by dword so they live in scalar registers.
+__device__ __forceinline__ Sweep2DArgs load_uniform_args(const Sweep2DArgs *p) {
+    constexpr int N = sizeof(Sweep2DArgs) / 4;
+    static_assert(sizeof(Sweep2DArgs) % 4 == 0, "argument block must be dword-sized");
+    int w[N];
+    __builtin_memcpy(w, p, sizeof(Sweep2DArgs));
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    Sweep2DArgs a;
+    __builtin_memcpy(&a, w, sizeof(Sweep2DArgs));
+    return a;
+}
+
 // entries per node block of the moment-reduction buffer (9 moments x NW waves
 // x 16 rows, padded to 16 mod 64)
 constexpr int red_node_block(int nw) {
@@ -216,8 +233,8 @@ __device__ __forceinline__ real channel_scatter_sum(const real (&v)[4]) {
     return sum_swapped16(h0, h1);
 }
 
-template <typename real, int K, int PF, int NW>
-__global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
+template <typename real, int K, int PF, int NW, bool BATCH>
+__global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     using r2 = typename vec2<real>::type;
     using r4 = typename vec4<real>::type;
     constexpr int TW = trace_words<real>::n;
@@ -227,7 +244,7 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
     constexpr int BUF = 4 * CB;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *red = reinterpret_cast<real *>(smem_raw);
-    __shared__ int s_task, s_epoch;
+    __shared__ int s_prob, s_task, s_epoch;
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -235,11 +252,18 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
     const int r = lane & 15;
 
     if (threadIdx.x == 0) {
-        s_task = atomicAdd(&A.ctr[0], 1);
-        s_epoch = __hip_atomic_load(&A.ctr[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int2 tk = L.tasks[atomicAdd(&L.lctr[0], 1)];
+        s_prob = tk.x;
+        s_task = tk.y;
+        int *pc = BATCH ? L.probs[tk.x].ctr : L.single.ctr;
+        s_epoch = __hip_atomic_load(&pc[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    const int task = s_task;
+    const int prob = __builtin_amdgcn_readfirstlane(s_prob);
+    // problem arguments: kernel arguments (one problem) or the batch's device
+    // array (uniform index, so they live in scalar registers either way)
+    const Sweep2DArgs A = BATCH ? load_uniform_args(L.probs + prob) : L.single;
+    const int task = __builtin_amdgcn_readfirstlane(s_task);
     const uint32_t epoch = (uint32_t)s_epoch;
     const int band = task / A.NQC;
     const int qc = task - band * A.NQC;
@@ -537,48 +561,63 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(Sweep2DArgs A) {
         }
     }
 
-    // the last workgroup to finish resets the ticket counters and advances the epoch
+    // completion: per-problem epoch, per-launch ticket
     __syncthreads();
     if (threadIdx.x == 0) {
+        // the problem's last workgroup advances its epoch (every workgroup of the
+        // problem read the epoch before this point)
         const int done = atomicAdd(&A.ctr[1], 1);
         if (done == A.n_wg - 1) {
-            __hip_atomic_store(&A.ctr[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&A.ctr[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&A.ctr[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // the launch's last workgroup resets the ticket
+        const int ldone = atomicAdd(&L.lctr[1], 1);
+        if (ldone == L.n_tasks - 1) {
+            __hip_atomic_store(&L.lctr[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&L.lctr[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
 
-template <typename real, int K, int NW>
-static void launch_knw(const Sweep2DArgs &a, hipStream_t s) {
-    // prefetch depth (steps in flight beyond the current one), bounded by registers
+template <typename real, int K, int NW, bool BATCH>
+static void launch_knwb(const SweepLaunch &L, hipStream_t s) {
     constexpr int PF = sizeof(real) == 4 ? (K == 1 ? 4 : 2) : 1;
     constexpr int CB = red_node_block(NW);
     const size_t lds = (size_t)2 * 4 * CB * sizeof(real);
-    SMRT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep2d_kernel<real, K, PF, NW>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((sweep2d_kernel<real, K, PF, NW>), dim3(a.n_wg), dim3(NW * 64), lds, s, a);
+    static bool lds_attr_set = false;   // once per instantiation (so a launch can be graph-captured)
+    if (!lds_attr_set) {
+        SMRT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep2d_kernel<real, K, PF, NW, BATCH>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        lds_attr_set = true;
+    }
+    hipLaunchKernelGGL((sweep2d_kernel<real, K, PF, NW, BATCH>), dim3(L.n_tasks), dim3(NW * 64), lds, s, L);
+}
+template <typename real, int K, int NW>
+static void launch_knw(const SweepLaunch &L, hipStream_t s) {
+    if (L.probs) launch_knwb<real, K, NW, true>(L, s);
+    else launch_knwb<real, K, NW, false>(L, s);
 }
 
 template <typename real, int K>
-static void launch_k(const Sweep2DArgs &a, hipStream_t s) {
-    switch (a.NW) {
-        case 1: launch_knw<real, K, 1>(a, s); break;
-        case 2: launch_knw<real, K, 2>(a, s); break;
-        case 3: launch_knw<real, K, 3>(a, s); break;
-        case 4: launch_knw<real, K, 4>(a, s); break;
-        case 5: launch_knw<real, K, 5>(a, s); break;
-        case 6: launch_knw<real, K, 6>(a, s); break;
-        case 7: launch_knw<real, K, 7>(a, s); break;
-        case 8: launch_knw<real, K, 8>(a, s); break;
+static void launch_k(const SweepLaunch &L, hipStream_t s) {
+    switch (L.NW) {
+        case 1: launch_knw<real, K, 1>(L, s); break;
+        case 2: launch_knw<real, K, 2>(L, s); break;
+        case 3: launch_knw<real, K, 3>(L, s); break;
+        case 4: launch_knw<real, K, 4>(L, s); break;
+        case 5: launch_knw<real, K, 5>(L, s); break;
+        case 6: launch_knw<real, K, 6>(L, s); break;
+        case 7: launch_knw<real, K, 7>(L, s); break;
+        case 8: launch_knw<real, K, 8>(L, s); break;
         default:
             // more than 8 waves only with one group per lane (two would spill)
             if constexpr (K == 1) {
-                switch (a.NW) {
-                    case 9: launch_knw<real, K, 9>(a, s); return;
-                    case 10: launch_knw<real, K, 10>(a, s); return;
-                    case 11: launch_knw<real, K, 11>(a, s); return;
-                    case 12: launch_knw<real, K, 12>(a, s); return;
+                switch (L.NW) {
+                    case 9: launch_knw<real, K, 9>(L, s); return;
+                    case 10: launch_knw<real, K, 10>(L, s); return;
+                    case 11: launch_knw<real, K, 11>(L, s); return;
+                    case 12: launch_knw<real, K, 12>(L, s); return;
                     default: break;
                 }
             }
@@ -587,15 +626,16 @@ static void launch_k(const Sweep2DArgs &a, hipStream_t s) {
 }
 
 template <typename real>
-void launch_sweep2d(const Sweep2DArgs &a, hipStream_t s) {
-    if (a.K == 1) { launch_k<real, 1>(a, s); SMRT_HIP(hipGetLastError()); return; }
+void launch_sweep2d(const SweepLaunch &L, hipStream_t s) {
+    if (L.n_tasks <= 0) return;
+    if (L.K == 1) { launch_k<real, 1>(L, s); SMRT_HIP(hipGetLastError()); return; }
     if constexpr (sizeof(real) == 4) {
-        if (a.K == 2) { launch_k<real, 2>(a, s); SMRT_HIP(hipGetLastError()); return; }
+        if (L.K == 2) { launch_k<real, 2>(L, s); SMRT_HIP(hipGetLastError()); return; }
     }
     throw Error(SMRT_E_INVALID_ARG, "pairs per lane must be 1 (FP64) or 1, 2 (FP32)");
 }
 
-template void launch_sweep2d<float>(const Sweep2DArgs &, hipStream_t);
-template void launch_sweep2d<double>(const Sweep2DArgs &, hipStream_t);
+template void launch_sweep2d<float>(const SweepLaunch &, hipStream_t);
+template void launch_sweep2d<double>(const SweepLaunch &, hipStream_t);
 
 }  // namespace smrt

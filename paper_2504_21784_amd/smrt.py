@@ -22,6 +22,7 @@ STATUS = {0: "SMRT_OK", 1: "SMRT_E_INVALID_ARG", 2: "SMRT_E_OUT_OF_MEMORY", 3: "
           4: "SMRT_E_NOT_CONVERGED", 5: "SMRT_E_NONPHYSICAL", 6: "SMRT_E_STATE"}
 
 _dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
 
 
 class MeshDesc(C.Structure):
@@ -93,6 +94,15 @@ _SIGS = {
     "smrt_get_info": ([C.c_void_p, C.POINTER(Info)], C.c_int),
     "smrt_get_moments": ([C.c_void_p, _dp], C.c_int),
     "smrt_set_launch": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
+    "smrt_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _dp], C.c_int),
+    "smrt_batch_create": ([C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)], C.c_int),
+    "smrt_batch_destroy": ([C.c_void_p], None),
+    "smrt_batch_last_error": ([C.c_void_p], C.c_char_p),
+    "smrt_batch_set_launch": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
+    "smrt_batch_info": ([C.c_void_p, C.POINTER(C.c_int64), _ip, _ip, _ip], C.c_int),
+    "smrt_batch_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _dp], C.c_int),
+    "smrt_batch_sweep_resident": ([C.c_void_p, C.c_double, C.c_int, C.c_int, _dp, _dp], C.c_int),
+    "smrt_batch_step": ([C.c_void_p, _dp, C.POINTER(StepStats)], C.c_int),
 }
 
 
@@ -267,3 +277,68 @@ class Context:
         self._check(self.L.smrt_sweep_resident(self.h, float(dt if dt is not None else self.p.dt), int(n_times),
                                                C.byref(ms), C.byref(ks)))
         return ms.value, ks.value
+
+    def autotune(self, dt=None):
+        """Pick the fastest sweep launch shape; returns (waves, groups per lane, ms)."""
+        nw, k, ms = C.c_int(0), C.c_int(0), C.c_double(0.0)
+        self._check(self.L.smrt_autotune(self.h, float(dt if dt is not None else self.p.dt), C.byref(nw), C.byref(k),
+                                         C.byref(ms)))
+        return nw.value, k.value, ms.value
+
+
+class Batch:
+    """Many 2D contexts swept together (one launch per sweep).  The contexts
+    stay owned by the caller and must outlive the batch."""
+
+    def __init__(self, contexts):
+        self.L = load()
+        self.contexts = list(contexts)
+        arr = (C.c_void_p * len(self.contexts))(*[c.h for c in self.contexts])
+        h = C.c_void_p()
+        st = self.L.smrt_batch_create(len(self.contexts), arr, C.byref(h))
+        if st != 0:
+            raise SmrtError(st, self.L.smrt_batch_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != 0:
+            raise SmrtError(st, self.L.smrt_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.smrt_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        u, t, nw, k = C.c_int64(0), C.c_int(0), C.c_int(0), C.c_int(0)
+        self._check(self.L.smrt_batch_info(self.h, C.byref(u), C.byref(t), C.byref(nw), C.byref(k)))
+        return {"units_per_sweep": u.value, "n_tasks": t.value, "waves_per_group": nw.value, "pairs_per_lane": k.value}
+
+    def set_launch(self, waves_per_group, pairs_per_lane=1):
+        self._check(self.L.smrt_batch_set_launch(self.h, int(waves_per_group), int(pairs_per_lane)))
+
+    def autotune(self, dt):
+        nw, k, ms = C.c_int(0), C.c_int(0), C.c_double(0.0)
+        self._check(self.L.smrt_batch_autotune(self.h, float(dt), C.byref(nw), C.byref(k), C.byref(ms)))
+        return nw.value, k.value, ms.value
+
+    def sweep_resident(self, dt, n_times=1, capture_graph=False):
+        """Returns (ms per batched high-order pass, ms of one batched sweep launch)."""
+        ms, ks = C.c_double(0.0), C.c_double(0.0)
+        self._check(self.L.smrt_batch_sweep_resident(self.h, float(dt), int(n_times), int(bool(capture_graph)),
+                                                     C.byref(ms), C.byref(ks)))
+        return ms.value, ks.value
+
+    def step(self, dt):
+        """One time step of every problem; dt scalar or per problem. Returns per-problem stats."""
+        n = len(self.contexts)
+        d = _f64(np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,)))
+        st = (StepStats * n)()
+        self._check(self.L.smrt_batch_step(self.h, _p(d), st))
+        return [s.as_dict() for s in st]

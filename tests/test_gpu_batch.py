@@ -1,0 +1,161 @@
+"""GPU tests of the batched persistent sweep (many uneven problems in one
+launch), its HIP-graph replay, the lock-stepped batched time step and the
+launch-shape autotuners, through the C ABI.
+
+Each batched result is compared with the same problem run on its own
+context (the single-problem launch) and, for one problem, with the FP64
+oracle on identical inputs.
+"""
+import numpy as np
+import pytest
+
+from paper_2504_21784_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _problems():
+    # uneven sizes, group counts and quadratures from the batch recipe
+    ps = W.batch_2d(n_problems=4, seed=11, sizes=[16, 24, 40])
+    return ps
+
+
+def _contexts(smrt_mod, problems, prec):
+    cs = []
+    for p in problems:
+        c = smrt_mod.Context(p, precision=prec)
+        c.set_state(p.initial_T_nodes())
+        cs.append(c)
+    return cs
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6)])
+def test_batched_pass_matches_single_problem_launches(smrt_mod, prec, tol):
+    ps = _problems()
+    print("batch:", [p.name for p in ps], flush=True)
+    single = _contexts(smrt_mod, ps, prec)
+    batched = _contexts(smrt_mod, ps, prec)
+    b = smrt_mod.Batch(batched)
+    info = b.info()
+    for c in single:
+        c.set_launch(info["waves_per_group"], info["pairs_per_lane"])
+        c.sweep_resident(n_times=1)
+    b.sweep_resident(ps[0].dt, n_times=1)
+    for c1, c2 in zip(single, batched):
+        m1, m2 = c1.get_moments(), c2.get_moments()
+        assert _rel(m2, m1) < tol
+    b.close()
+    for c in single + batched:
+        c.close()
+
+
+def test_batched_pass_fp64_matches_oracle(smrt_mod, oracle_mod):
+    ps = _problems()
+    cs = _contexts(smrt_mod, ps, 0)
+    b = smrt_mod.Batch(cs)
+    b.sweep_resident(ps[0].dt, n_times=1)
+    p = ps[0]
+    o = oracle_mod.Oracle(p)
+    T = p.initial_T_nodes()
+    sig = o.opacity(T)
+    icdt = 1.0 / (p.c * p.dt)
+    st = o.initial_state()
+    B = p.a * p.c * T ** 4 / (4 * np.pi)
+    frac = np.array([o.spectra(t)[0] for t in T])
+    q = sig[np.arange(p.n_nodes) // 4, :] * B[:, None] * frac
+    ref = o.sweep(sig + icdt, q, st["psi"], icdt, o.inflow())
+    ref_m = o.moments(sig, ref)
+    m = cs[0].get_moments()
+    for k in range(27):
+        assert _rel(m[k], ref_m[k]) < 1e-10, k
+    b.close()
+    for c in cs:
+        c.close()
+
+
+def test_batched_graph_replay_matches_eager(smrt_mod):
+    ps = _problems()
+    cs = _contexts(smrt_mod, ps, 1)
+    b = smrt_mod.Batch(cs)
+    b.sweep_resident(ps[0].dt, n_times=1, capture_graph=False)
+    eager = [c.get_moments() for c in cs]
+    for rep in range(3):
+        # replays with eager work and synchronisation in between
+        b.sweep_resident(ps[0].dt, n_times=2, capture_graph=True)
+        for c, e in zip(cs, eager):
+            assert np.array_equal(c.get_moments(), e), rep
+        b.sweep_resident(ps[0].dt, n_times=1, capture_graph=False)
+    b.close()
+    for c in cs:
+        c.close()
+
+
+def test_batched_steps_match_single_problem_steps(smrt_mod):
+    ps = _problems()[:3]
+    single = _contexts(smrt_mod, ps, 0)
+    batched = _contexts(smrt_mod, ps, 0)
+    b = smrt_mod.Batch(batched)
+    info = b.info()
+    for c in single:
+        c.set_launch(info["waves_per_group"], info["pairs_per_lane"])
+    for step in range(2):
+        print("step", step, flush=True)
+        s1 = [c.step(p.dt) for c, p in zip(single, ps)]
+        s2 = b.step([p.dt for p in ps])
+        for a, c in zip(s1, s2):
+            assert a["outer"] == c["outer"] and a["cg_total"] == c["cg_total"]
+    for c1, c2 in zip(single, batched):
+        g1, g2 = c1.get_state(), c2.get_state()
+        for k in ("T", "E", "F", "psi"):
+            assert _rel(g2[k], g1[k]) < 1e-12, k
+    b.close()
+    for c in single + batched:
+        c.close()
+
+
+def test_batch_autotune_keeps_results(smrt_mod):
+    ps = _problems()
+    cs = _contexts(smrt_mod, ps, 1)
+    b = smrt_mod.Batch(cs)
+    b.sweep_resident(ps[0].dt, n_times=1)
+    before = [c.get_moments() for c in cs]
+    nw, k, ms = b.autotune(ps[0].dt)
+    print("batch autotune:", nw, k, ms, flush=True)
+    assert 1 <= nw <= 12 and k in (1, 2) and ms > 0
+    assert b.info()["waves_per_group"] == nw
+    b.sweep_resident(ps[0].dt, n_times=1)
+    for c, m in zip(cs, before):
+        assert _rel(c.get_moments(), m) < 1e-6
+    b.close()
+    for c in cs:
+        c.close()
+
+
+def test_single_autotune(smrt_mod):
+    p = W.multigroup_2d(n=48, G=8)
+    c = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP32)
+    c.set_state(p.initial_T_nodes())
+    c.sweep_resident(n_times=1)
+    before = c.get_moments()
+    nw, k, ms = c.autotune()
+    print("autotune:", nw, k, ms, flush=True)
+    assert c.info()["waves_per_group"] == nw and c.info()["pairs_per_lane"] == k
+    c.sweep_resident(n_times=1)
+    assert _rel(c.get_moments(), before) < 1e-6
+    c.close()
+
+
+def test_batch_rejects_mixed_precision(smrt_mod):
+    ps = _problems()[:2]
+    a = smrt_mod.Context(ps[0], precision=0)
+    c = smrt_mod.Context(ps[1], precision=1)
+    a.set_state(ps[0].initial_T_nodes())
+    c.set_state(ps[1].initial_T_nodes())
+    with pytest.raises(smrt_mod.SmrtError):
+        smrt_mod.Batch([a, c])
+    a.close()
+    c.close()
