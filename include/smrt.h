@@ -184,6 +184,26 @@ smrt_status smrt_sweep(smrt_ctx *ctx, const double *sig_t, const double *sig, co
                        const double *psi_prev, double inv_c_dt, const double *psi_inflow, double *psi_out,
                        double *moments_out);
 
+/* Adjoint sweep: the transpose of the lumped upwind DG transport operator
+ * of smrt_sweep (Sec. 3, eq. dgsn_transport), the building block of the
+ * adjoint of a time step.  For every (d, g):
+ *   lambda_d = L_d^{-T} (w . src_d),
+ * L_d the sweep operator of direction d for total cross section
+ * sig_t[cell][G] (> 0) with zero inflow (the adjoint boundary condition is
+ * homogeneous), w the lumped nodal weights |cell| / 2^dim.  src and
+ * lambda_out are [d][g][node] FP64.  If dsig_out ([cell][G], may be NULL)
+ * is given, emis ([node][G], emission per unit opacity B_g/4pi) and psi_fwd
+ * ([d][g][node], the forward intensity) are required and
+ *   dsig_out[c][g] = sum_d sum_{l in c} w_l lambda_{d,g,l} (emis_{l,g} - psi_fwd_{d,g,l}),
+ * the derivative of <lambda, transport residual> with respect to sigma_g of
+ * the cell through the emission and removal terms (with the sign of a
+ * gradient of J when lambda solves the adjoint of dJ/dI).  Needs a quadrature
+ * closed under Omega -> -Omega (level-symmetric, Gauss-Legendre); runs at
+ * the context precision.  Errors: SMRT_E_INVALID_ARG for NULL inputs,
+ * sig_t <= 0 or a quadrature without opposite directions. */
+smrt_status smrt_adjoint_sweep(smrt_ctx *ctx, const double *sig_t, const double *src, const double *emis,
+                               const double *psi_fwd, double *lambda_out, double *dsig_out);
+
 /* Closures and low-order sources (Sec. 2 gray collapse, Sec. 4 consistent /
  * independent LDG sources) from HO moments (FP64 [27|8][node], as produced by
  * smrt_sweep), the outer-iterate temperature T_l[n], the time-edge sources

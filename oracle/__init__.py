@@ -77,6 +77,8 @@ def _declare(L):
     L.orc_opacity.argtypes = [gp, mp, _dp, _dp]
     L.orc_sweep.argtypes = [gp, _dp, _dp, _dp, C.c_double, _dp, _dp]
     L.orc_sweep.restype = C.c_int
+    L.orc_adjoint_sweep.argtypes = [gp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_adjoint_sweep.restype = C.c_int
     L.orc_moments.argtypes = [gp, _dp, _dp, _dp]
     L.orc_n_moments.argtypes = [C.c_int]
     L.orc_inflow_from_bc.argtypes = [gp, bp, _dp]
@@ -167,6 +169,19 @@ class Oracle:
         r = self.L.orc_sweep(C.byref(self.geom), _p(st), _p(q), _p(pp), float(inv_c_dt), _p(inf), _p(out))
         assert r == 0
         return out
+
+    def adjoint_sweep(self, sig_t, src, emis=None, psi_fwd=None):
+        """lambda = L^{-T} (w . src) per (d, g) (zero inflow); with emis and
+        psi_fwd also dsig[cell][G]."""
+        p = self.p
+        lam = np.zeros((p.n_angles, p.G, p.n_nodes))
+        want = emis is not None and psi_fwd is not None
+        dsig = np.zeros((p.n_cells, p.G)) if want else None
+        r = self.L.orc_adjoint_sweep(C.byref(self.geom), _p(_f64(sig_t)), _p(_f64(src)),
+                                     _p(_f64(emis)) if want else None, _p(_f64(psi_fwd)) if want else None,
+                                     _p(lam), _p(dsig))
+        assert r == 0
+        return (lam, dsig) if want else lam
 
     def moments(self, sig, psi):
         nm = self.L.orc_n_moments(self.p.dim)

@@ -340,6 +340,89 @@ int orc_sweep(const orc_geom *g, const double *sig_t, const double *q_iso, const
 }
 
 /* ------------------------------------------------------------------------ */
+/* Adjoint sweep: solves L^T lambda = b for each (d,g), L the operator of    */
+/* orc_sweep (zero inflow), b_l = w_l src_l.  L is block lower-triangular   */
+/* in upwind order: row (c,l) holds the local block A^c and, for every      */
+/* inflow face f of l, the coupling (Omega.n_f) fw to the upwind neighbour's */
+/* coincident node.  So L^T is block upper-triangular: row (c,m) holds      */
+/* (A^c)^T and, for every outflow face f of m, the coupling                 */
+/* (-Omega.n_f) fw to the downwind neighbour's coincident node.  The cells  */
+/* are visited in reverse (downwind first); each transposed local system is */
+/* assembled from the same terms as orc_sweep and solved by Gaussian        */
+/* elimination.  Optionally                                                  */
+/*   dsig[c][g] = sum_d sum_{l in c} w_l lambda_l (emis_{l,g} - psi_fwd_l).   */
+/* ------------------------------------------------------------------------ */
+
+int orc_adjoint_sweep(const orc_geom *g, const double *sig_t, const double *src, const double *emis,
+                      const double *psi_fwd, double *lambda, double *dsig)
+{
+    int nx = g->nx, ny = g->dim == 2 ? g->ny : 1, np = npc(g), G = g->G, nn = nnode(g);
+    for (int d = 0; d < g->nang; ++d) {
+        int fwdx = om_ax(g, d, 0) > 0.0, fwdy = g->dim == 2 ? om_ax(g, d, 1) > 0.0 : 1;
+        for (int k = 0; k < G; ++k) {
+            const double *s = src + ((size_t)d * G + k) * nn;
+            double *out = lambda + ((size_t)d * G + k) * nn;
+            for (int jj = ny - 1; jj >= 0; --jj) {
+                int j = fwdy ? jj : ny - 1 - jj;
+                for (int ii = nx - 1; ii >= 0; --ii) {
+                    int i = fwdx ? ii : nx - 1 - ii;
+                    int c = i + nx * j;
+                    double A[16], At[16], b[4], x[4];
+                    double wv = vol_weight(g, i, j), st = sig_t[(size_t)c * G + k];
+                    for (int l = 0; l < np; ++l) {
+                        for (int m = 0; m < np; ++m) {
+                            double og = 0.0;
+                            for (int ax = 0; ax < g->dim; ++ax) og += om_ax(g, d, ax) * dbasis(g, i, j, l, m, ax);
+                            A[l * np + m] = (l == m ? st * wv : 0.0) - wv * og;
+                        }
+                        for (int ax = 0; ax < g->dim; ++ax)
+                            for (int sd = 0; sd < 2; ++sd) {
+                                if (!node_on_face(l, ax, sd)) continue;
+                                double on = om_ax(g, d, ax) * (sd ? 1.0 : -1.0);
+                                if (on > 0.0) A[l * np + l] += on * face_weight(g, i, j, ax);
+                            }
+                    }
+                    for (int l = 0; l < np; ++l)
+                        for (int m = 0; m < np; ++m) At[m * np + l] = A[l * np + m];
+                    for (int m = 0; m < np; ++m) {
+                        b[m] = wv * s[np * c + m];
+                        for (int ax = 0; ax < g->dim; ++ax)
+                            for (int sd = 0; sd < 2; ++sd) {
+                                if (!node_on_face(m, ax, sd)) continue;
+                                double on = om_ax(g, d, ax) * (sd ? 1.0 : -1.0);
+                                if (on <= 0.0) continue;            /* only outflow faces of m */
+                                int nb = neighbour(g, i, j, ax, sd);
+                                if (nb < 0) continue;               /* homogeneous adjoint boundary */
+                                b[m] -= -on * face_weight(g, i, j, ax) * out[np * nb + mirror(m, ax)];
+                            }
+                    }
+                    if (lu_solve(np, At, b, x)) return -1;
+                    for (int l = 0; l < np; ++l) out[np * c + l] = x[l];
+                }
+            }
+        }
+    }
+    if (dsig) {
+        int nc = ncell(g);
+        for (int c = 0; c < nc; ++c) {
+            int i = c % nx, j = c / nx;
+            double wv = vol_weight(g, i, j);
+            for (int k = 0; k < G; ++k) {
+                double acc = 0.0;
+                for (int d = 0; d < g->nang; ++d) {
+                    const double *L = lambda + ((size_t)d * G + k) * nn;
+                    const double *I = psi_fwd + ((size_t)d * G + k) * nn;
+                    for (int l = 0; l < np; ++l)
+                        acc += wv * L[np * c + l] * (emis[(size_t)(np * c + l) * G + k] - I[np * c + l]);
+                }
+                dsig[(size_t)c * G + k] = acc;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Moments in the comparison format (sums over directions by definition).  */
 /* 2D, per node: for quadrant q (0:(+,+) 1:(-,+) 2:(-,-) 3:(+,-)) the six  */
 /* sums of w*{1, mu, eta, mu^2, mu*eta, eta^2}*I over d in q and all g, at */

@@ -35,6 +35,8 @@ struct smrt_ctx {
     // geometry on the device
     DevBuf<double> d_nu, d_hx64, d_hy64, d_sigma0, d_cvn, d_om, d_w, d_sideval, d_Tb, d_explicit;
     DevBuf<int> d_region, d_dir_quad, d_kind;
+    DevBuf<int> d_opposite;       // direction with -Omega (adjoint sweeps)
+    bool have_opposite = false;
     DevBuf<unsigned char> d_hx, d_hy, d_dirs, d_mu_w;
     // sweep plan
     int NW = 0, K = 1, R = 0, NQC = 0, nbands = 0, NT = 0, n_wg = 0;
@@ -516,6 +518,19 @@ extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_d
         to_real(mw, p->d_mu_w);
         p->d_dir_quad.alloc(p->nang);
         SMRT_HIP(hipMemcpy(p->d_dir_quad.p, dq.data(), sizeof(int) * p->nang, hipMemcpyHostToDevice));
+        // opposite directions (-mu, -eta): the adjoint sweep of d is the sweep of its opposite
+        std::vector<int> opp(p->nang, -1);
+        for (int d = 0; d < p->nang; ++d)
+            for (int e = 0; e < p->nang; ++e) {
+                const double dm = p->om[3 * e] + p->om[3 * d];
+                const double de = p->dim == 2 ? p->om[3 * e + 1] + p->om[3 * d + 1] : 0.0;
+                if (std::fabs(dm) < 1e-12 && std::fabs(de) < 1e-12) { opp[d] = e; break; }
+            }
+        p->have_opposite = std::all_of(opp.begin(), opp.end(), [](int e) { return e >= 0; });
+        if (p->have_opposite) {
+            p->d_opposite.alloc(p->nang);
+            SMRT_HIP(hipMemcpy(p->d_opposite.p, opp.data(), sizeof(int) * p->nang, hipMemcpyHostToDevice));
+        }
         p->d_nu.alloc(p->G + 1);
         SMRT_HIP(hipMemcpy(p->d_nu.p, p->nu.data(), 8 * (p->G + 1), hipMemcpyHostToDevice));
         p->d_region.alloc(p->ncell);
@@ -674,6 +689,55 @@ extern "C" smrt_status smrt_get_state(smrt_ctx *x, double *T, double *E, double 
     });
 }
 
+// One sweep from device-resident FP64 arrays in the ABI layouts: sig_t, sig
+// [cell][G]; q [node][G]; prev (psi_prev, or nullptr) [d][g][node]; inflow
+// (nullptr: the context's boundary inflow) [d][g][NB]; out [d][g][node];
+// mom (or nullptr) [27|8][node].
+static void raw_sweep(smrt_ctx *x, const double *sig_t, const double *sig, const double *q, const double *prev,
+                      double inv_c_dt, const double *inflow64, double *out, double *mom) {
+    const int64_t na = (int64_t)x->nang * x->G * x->nn;
+    const int64_t tab_cells = x->dim == 2 ? 4 * cell_slab(x->nx, x->ny) : x->ncell;
+    DevBuf<unsigned char> t_sig2, t_qiso, t_in, t_out, t_inflow;
+    t_sig2.alloc(tab_cells * x->G * 2 * x->rs);
+    t_qiso.alloc(tab_cells * x->G * x->npc * x->rs);
+    t_in.alloc(psi_count(x) * x->rs);
+    t_out.alloc(psi_count(x) * x->rs);
+    t_inflow.alloc((int64_t)x->nang * x->G * x->NB * x->rs);
+    auto tables = [&](auto zero) {
+        using real = decltype(zero);
+        if (x->dim == 2) {
+            run_stab2d<real>(x->stream, x->nx, x->ny, x->G, sig, sig_t, 0.0, (real *)t_sig2.p);
+            run_qtab2d<real>(x->stream, x->nx, x->ny, x->G, q, x->G, 1, (real *)t_qiso.p);
+        } else {
+            run_sig_to_internal<real>(x->stream, x->ncell, x->G, sig_t, sig, (real *)t_sig2.p);
+            run_qiso_to_internal<real>(x->stream, x->nn, x->G, x->npc, q, (real *)t_qiso.p);
+        }
+        if (prev) {
+            if (x->dim == 2) run_psi_to_internal<real>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, prev, (real *)t_in.p);
+            else run_copy_to<real>(x->stream, na, prev, (real *)t_in.p);
+        }
+        if (inflow64) run_copy_to<real>(x->stream, (int64_t)x->nang * x->G * x->NB, inflow64, (real *)t_inflow.p);
+    };
+    if (x->fp32) tables(0.0f);
+    else tables(0.0);
+    DevBuf<double> m;
+    if (!mom) {
+        m.alloc((int64_t)(x->dim == 2 ? 27 : 8) * x->nn);
+        mom = m.p;
+    }
+    run_sweep(x, prev ? t_in.p : nullptr, t_out.p, t_sig2.p, t_qiso.p, inflow64 ? t_inflow.p : x->d_inflow.p, inv_c_dt,
+              sig, mom);
+    check_sweep_flag(x);
+    auto back = [&](auto zero) {
+        using real = decltype(zero);
+        if (x->dim == 2) run_psi_from_internal<real>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const real *)t_out.p, out);
+        else run_copy_from<real>(x->stream, na, (const real *)t_out.p, out);
+    };
+    if (x->fp32) back(0.0f);
+    else back(0.0);
+    SMRT_HIP(hipStreamSynchronize(x->stream));
+}
+
 extern "C" smrt_status smrt_sweep(smrt_ctx *x, const double *sig_t, const double *sig, const double *q_iso,
                                   const double *psi_prev, double inv_c_dt, const double *psi_inflow, double *psi_out,
                                   double *moments_out) {
@@ -684,72 +748,64 @@ extern "C" smrt_status smrt_sweep(smrt_ctx *x, const double *sig_t, const double
         const int64_t na = (int64_t)x->nang * x->G * x->nn;
         const int64_t ng = (int64_t)x->ncell * x->G;
         for (int64_t k = 0; k < ng; ++k) require(sig_t[k] > 0.0 && sig[k] >= 0.0, "sig_t must be > 0 and sig >= 0");
-        DevBuf<double> t_st, t_s, t_q, t_abi, t_inf;
-        DevBuf<unsigned char> t_sig2, t_qiso, t_in, t_out, t_inflow;
-        t_st.alloc(ng); t_s.alloc(ng); t_q.alloc((int64_t)x->nn * x->G);
+        DevBuf<double> t_st, t_s, t_q, t_prev, t_inf, t_out, mom;
+        t_st.alloc(ng); t_s.alloc(ng); t_q.alloc((int64_t)x->nn * x->G); t_out.alloc(na);
         h2d(t_st.p, sig_t, 8 * ng, x->stream);
         h2d(t_s.p, sig, 8 * ng, x->stream);
         h2d(t_q.p, q_iso, 8 * x->nn * x->G, x->stream);
-        const int64_t tab_cells = x->dim == 2 ? 4 * cell_slab(x->nx, x->ny) : x->ncell;
-        t_sig2.alloc(tab_cells * x->G * 2 * x->rs);
-        t_qiso.alloc(tab_cells * x->G * x->npc * x->rs);
-        t_in.alloc(psi_count(x) * x->rs);
-        t_out.alloc(psi_count(x) * x->rs);
-        t_inflow.alloc((int64_t)x->nang * x->G * x->NB * x->rs);
-        t_abi.alloc(na);
-        if (psi_prev) h2d(t_abi.p, psi_prev, 8 * na, x->stream);
-        if (x->fp32) {
-            if (x->dim == 2) {
-                run_stab2d<float>(x->stream, x->nx, x->ny, x->G, t_s.p, t_st.p, 0.0, (float *)t_sig2.p);
-                run_qtab2d<float>(x->stream, x->nx, x->ny, x->G, t_q.p, x->G, 1, (float *)t_qiso.p);
-            } else {
-                run_sig_to_internal<float>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (float *)t_sig2.p);
-                run_qiso_to_internal<float>(x->stream, x->nn, x->G, x->npc, t_q.p, (float *)t_qiso.p);
-            }
-            if (psi_prev) {
-                if (x->dim == 2) run_psi_to_internal<float>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, t_abi.p, (float *)t_in.p);
-                else run_copy_to<float>(x->stream, na, t_abi.p, (float *)t_in.p);
-            }
-        } else {
-            if (x->dim == 2) {
-                run_stab2d<double>(x->stream, x->nx, x->ny, x->G, t_s.p, t_st.p, 0.0, (double *)t_sig2.p);
-                run_qtab2d<double>(x->stream, x->nx, x->ny, x->G, t_q.p, x->G, 1, (double *)t_qiso.p);
-            } else {
-                run_sig_to_internal<double>(x->stream, x->ncell, x->G, t_st.p, t_s.p, (double *)t_sig2.p);
-                run_qiso_to_internal<double>(x->stream, x->nn, x->G, x->npc, t_q.p, (double *)t_qiso.p);
-            }
-            if (psi_prev) {
-                if (x->dim == 2) run_psi_to_internal<double>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, t_abi.p, (double *)t_in.p);
-                else run_copy_to<double>(x->stream, na, t_abi.p, (double *)t_in.p);
-            }
+        if (psi_prev) {
+            t_prev.alloc(na);
+            h2d(t_prev.p, psi_prev, 8 * na, x->stream);
         }
-        const void *inflow = x->d_inflow.p;
         if (psi_inflow) {
-            const int64_t ni = (int64_t)x->nang * x->G * x->NB;
-            t_inf.alloc(ni);
-            h2d(t_inf.p, psi_inflow, 8 * ni, x->stream);
-            if (x->fp32) run_copy_to<float>(x->stream, ni, t_inf.p, (float *)t_inflow.p);
-            else run_copy_to<double>(x->stream, ni, t_inf.p, (double *)t_inflow.p);
-            inflow = t_inflow.p;
+            t_inf.alloc((int64_t)x->nang * x->G * x->NB);
+            h2d(t_inf.p, psi_inflow, 8 * t_inf.n, x->stream);
         }
-        DevBuf<double> mom;
         mom.alloc((int64_t)(x->dim == 2 ? 27 : 8) * x->nn);
-        run_sweep(x, psi_prev ? t_in.p : nullptr, t_out.p, t_sig2.p, t_qiso.p, inflow, inv_c_dt, t_s.p, mom.p);
-        check_sweep_flag(x);
+        raw_sweep(x, t_st.p, t_s.p, t_q.p, t_prev.p, inv_c_dt, t_inf.p, t_out.p, mom.p);
         if (moments_out) d2h(moments_out, mom.p, 8 * mom.n, x->stream);
-        if (psi_out) {
-            if (x->dim == 2) {
-                if (x->fp32) run_psi_from_internal<float>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const float *)t_out.p, t_abi.p);
-                else run_psi_from_internal<double>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const double *)t_out.p, t_abi.p);
-                d2h(psi_out, t_abi.p, 8 * na, x->stream);
-            } else if (x->fp32) {
-                std::vector<float> h(na);
-                d2h(h.data(), t_out.p, 4 * na, x->stream);
-                SMRT_HIP(hipStreamSynchronize(x->stream));
-                for (int64_t k = 0; k < na; ++k) psi_out[k] = h[k];
-            } else {
-                d2h(psi_out, t_out.p, 8 * na, x->stream);
-            }
+        if (psi_out) d2h(psi_out, t_out.p, 8 * na, x->stream);
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+    });
+}
+
+// Adjoint sweep (transpose of the lumped upwind DG operator).  With every
+// form lumped on a rectilinear mesh the transpose of the operator of
+// direction Omega is the operator of -Omega (the local matrices are
+// dI + (a/2)Kx + (b/2)Ky with antisymmetric Kx, Ky, and the upwind
+// couplings swap sides), so lambda_d = L_{-Omega_d}^{-1} (w . src_d) is one
+// forward sweep of the opposite direction with zero inflow, its source
+// carried in the time-edge slot (inv_c_dt = 1, q = 0).
+extern "C" smrt_status smrt_adjoint_sweep(smrt_ctx *x, const double *sig_t, const double *src, const double *emis,
+                                          const double *psi_fwd, double *lambda_out, double *dsig_out) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(sig_t && src && lambda_out, "sig_t, src and lambda_out are required");
+        require(!dsig_out || (emis && psi_fwd), "dsig_out needs emis and psi_fwd");
+        require(x->have_opposite, "the quadrature has a direction without its opposite: no adjoint sweep");
+        const int64_t na = (int64_t)x->nang * x->G * x->nn;
+        const int64_t ng = (int64_t)x->ncell * x->G;
+        for (int64_t k = 0; k < ng; ++k) require(sig_t[k] > 0.0, "sig_t must be > 0");
+        DevBuf<double> t_st, t_q, t_src, t_prev, t_inf, t_out, t_lam;
+        t_st.alloc(ng); t_q.alloc((int64_t)x->nn * x->G); t_src.alloc(na); t_prev.alloc(na);
+        t_inf.alloc((int64_t)x->nang * x->G * x->NB); t_out.alloc(na); t_lam.alloc(na);
+        h2d(t_st.p, sig_t, 8 * ng, x->stream);
+        h2d(t_src.p, src, 8 * na, x->stream);
+        t_q.zero(x->stream);
+        t_inf.zero(x->stream);
+        const int64_t per = (int64_t)x->G * x->nn;
+        run_permute_dirs(x->stream, x->nang, per, x->d_opposite.p, t_src.p, t_prev.p);
+        raw_sweep(x, t_st.p, t_st.p, t_q.p, t_prev.p, 1.0, t_inf.p, t_out.p, nullptr);
+        run_permute_dirs(x->stream, x->nang, per, x->d_opposite.p, t_out.p, t_lam.p);
+        d2h(lambda_out, t_lam.p, 8 * na, x->stream);
+        if (dsig_out) {
+            DevBuf<double> t_e, t_f, t_d;
+            t_e.alloc((int64_t)x->nn * x->G); t_f.alloc(na); t_d.alloc(ng);
+            h2d(t_e.p, emis, 8 * t_e.n, x->stream);
+            h2d(t_f.p, psi_fwd, 8 * na, x->stream);
+            run_adjoint_dsig(x->stream, x->dim, x->nx, x->dim == 2 ? x->ny : 1, x->G, x->nang, x->d_hx64.p,
+                             x->dim == 2 ? x->d_hy64.p : nullptr, t_lam.p, t_e.p, t_f.p, t_d.p);
+            d2h(dsig_out, t_d.p, 8 * ng, x->stream);
         }
         SMRT_HIP(hipStreamSynchronize(x->stream));
     });

@@ -27,6 +27,11 @@ void run_fill_inflow(hipStream_t s, int dim, int nx, int ny, int G, int nang, co
 template <typename real>
 void run_copy_to(hipStream_t s, int64_t n, const double *src, real *dst);
 template <typename real>
+void run_copy_from(hipStream_t s, int64_t n, const real *src, double *dst);
+void run_permute_dirs(hipStream_t s, int nang, int64_t per, const int *map, const double *in, double *out);
+void run_adjoint_dsig(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy,
+                      const double *lam, const double *emis, const double *psi, double *dsig);
+template <typename real>
 void run_qiso_to_internal(hipStream_t s, int nn, int G, int npc, const double *q, real *qi);
 template <typename real>
 void run_sig_to_internal(hipStream_t s, int ncell, int G, const double *st, const double *sg, real *sig2);

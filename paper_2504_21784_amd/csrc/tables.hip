@@ -257,6 +257,11 @@ __global__ void k_copy_to(int64_t n, const double *src, real *dst) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) dst[i] = (real)src[i];
 }
+template <typename real>
+__global__ void k_copy_from(int64_t n, const real *src, double *dst) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (double)src[i];
+}
 
 // q_iso ABI [node][G] -> internal [G][cell][npc]
 template <typename real>
@@ -306,6 +311,37 @@ __global__ void k_psi_convert(int nx, int ny, int G, int nang, const int *dir_qu
     const int64_t k = internal_index(nx, ny, dir_quad[d], ii, jj, l, slab);
     if (TO_INTERNAL) out_or_in_real[k] = (real)in[i];
     else out_abi[i] = (double)out_or_in_real[k];
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint helpers: direction permutation (out[d] = in[map[d]]) of [d][per]
+// arrays, and the opacity sensitivity of a sweep,
+//   dsig[c][g] = sum_d sum_{l in c} w_l lambda_{d,g,l} (emis_{l,g} - I_{d,g,l}),
+// w_l the lumped nodal weight |cell| / 2^dim (one thread per (cell, group),
+// directions summed in index order).
+// ---------------------------------------------------------------------------
+__global__ void k_permute_dirs(int nang, int64_t per, const int *map, const double *in, double *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nang * per) return;
+    const int d = (int)(i / per);
+    out[i] = in[(int64_t)map[d] * per + (i - d * per)];
+}
+
+__global__ void k_adjoint_dsig(int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy,
+                               const double *lam, const double *emis, const double *psi, double *dsig) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int ncell = nx * ny, npc = dim == 2 ? 4 : 2;
+    if (i >= (int64_t)ncell * G) return;
+    const int c = (int)(i / G), g = (int)(i % G);
+    const double wl = dim == 2 ? hx[c % nx] * hy[c / nx] * 0.25 : hx[c] * 0.5;
+    const int64_t nn = (int64_t)ncell * npc;
+    double s = 0.0;
+    for (int d = 0; d < nang; ++d) {
+        const double *L = lam + ((int64_t)d * G + g) * nn + (int64_t)npc * c;
+        const double *I = psi + ((int64_t)d * G + g) * nn + (int64_t)npc * c;
+        for (int l = 0; l < npc; ++l) s += L[l] * (emis[((int64_t)npc * c + l) * G + g] - I[l]);
+    }
+    dsig[i] = wl * s;
 }
 
 // ---------------------------------------------------------------------------
@@ -516,6 +552,18 @@ void run_psi_from_internal(hipStream_t s, int nx, int ny, int G, int nang, const
     hipLaunchKernelGGL((k_psi_convert<real, double, false>), dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, nang, dq,
                        (const double *)nullptr, const_cast<real *>(in), abi);
 }
+void run_permute_dirs(hipStream_t s, int nang, int64_t per, const int *map, const double *in, double *out) {
+    hipLaunchKernelGGL(k_permute_dirs, dim3(nblk(nang * per, 256)), dim3(256), 0, s, nang, per, map, in, out);
+}
+void run_adjoint_dsig(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy,
+                      const double *lam, const double *emis, const double *psi, double *dsig) {
+    hipLaunchKernelGGL(k_adjoint_dsig, dim3(nblk((int64_t)nx * ny * G, 128)), dim3(128), 0, s, dim, nx, ny, G, nang, hx,
+                       hy, lam, emis, psi, dsig);
+}
+template <typename real>
+void run_copy_from(hipStream_t s, int64_t n, const real *src, double *dst) {
+    hipLaunchKernelGGL(k_copy_from<real>, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
+}
 template <typename real>
 void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const real *part, double *sigq,
                           double *mom) {
@@ -548,6 +596,7 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
     template void run_stab2d<real>(hipStream_t, int, int, int, const double *, const double *, double, real *);     \
     template void run_qtab2d<real>(hipStream_t, int, int, int, const double *, int64_t, int64_t, real *);          \
     template void run_copy_to<real>(hipStream_t, int64_t, const double *, real *);                                  \
+    template void run_copy_from<real>(hipStream_t, int64_t, const real *, double *);                                \
     template void run_qiso_to_internal<real>(hipStream_t, int, int, int, const double *, real *);                   \
     template void run_sig_to_internal<real>(hipStream_t, int, int, const double *, const double *, real *);         \
     template void run_psi_to_internal<real>(hipStream_t, int, int, int, int, const int *, const double *, real *);  \

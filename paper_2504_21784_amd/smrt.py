@@ -95,6 +95,7 @@ _SIGS = {
     "smrt_get_moments": ([C.c_void_p, _dp], C.c_int),
     "smrt_set_launch": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
     "smrt_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _dp], C.c_int),
+    "smrt_adjoint_sweep": ([C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp], C.c_int),
     "smrt_batch_create": ([C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)], C.c_int),
     "smrt_batch_destroy": ([C.c_void_p], None),
     "smrt_batch_last_error": ([C.c_void_p], C.c_char_p),
@@ -244,6 +245,18 @@ class Context:
         self._check(self.L.smrt_sweep(self.h, *[_p(a) for a in args], _p(pp), float(inv_c_dt), _p(inf), _p(psi),
                                       _p(mom)))
         return psi, mom
+
+    def adjoint_sweep(self, sig_t, src, emis=None, psi_fwd=None, want_dsig=False):
+        """lambda = L^{-T}(w . src) per (d, g); with want_dsig also the opacity
+        sensitivity dsig[cell][G] (needs emis[node][G] and psi_fwd)."""
+        p = self.p
+        lam = np.zeros((p.n_angles, p.G, p.n_nodes))
+        dsig = np.zeros((p.n_cells, p.G)) if want_dsig else None
+        st, s = _f64(sig_t), _f64(src)
+        e = _f64(emis) if emis is not None else None
+        f = _f64(psi_fwd) if psi_fwd is not None else None
+        self._check(self.L.smrt_adjoint_sweep(self.h, _p(st), _p(s), _p(e), _p(f), _p(lam), _p(dsig)))
+        return (lam, dsig) if want_dsig else lam
 
     def compute_closures(self, moments, T_l, Estar, Fstar, sig, dt):
         p = self.p
