@@ -204,6 +204,33 @@ smrt_status smrt_sweep(smrt_ctx *ctx, const double *sig_t, const double *sig, co
 smrt_status smrt_adjoint_sweep(smrt_ctx *ctx, const double *sig_t, const double *src, const double *emis,
                                const double *psi_fwd, double *lambda_out, double *dsig_out);
 
+/* Replace the per-region material parameters (Sec. 2 opacity and heat
+ * capacity): sigma0 as given to smrt_create ([n_regions] for the power-law
+ * model, [n_regions][G] for constant opacities) and cv[n_regions]; either
+ * may be NULL to keep it.  Copied.  Errors: SMRT_E_INVALID_ARG for negative
+ * sigma0, non-positive cv or both NULL. */
+smrt_status smrt_set_materials(smrt_ctx *ctx, const double *sigma0, const double *cv);
+
+/* Adjoint gradient (the differentiable form of the time step).  From the
+ * context's current state, runs n_steps backward-Euler steps of length dt
+ * (smrt_step with the context options; use tight tolerances so each step is
+ * at its fixed point), keeping per-step checkpoints of I, T and sigma, and
+ * returns the time-integrated outflow through the x+ boundary
+ *   J = sum_k dt sum_g sum_{mu_d > 0} w_d mu_d sum_{n on x+} fw_n I^k_{d,g,n}
+ * (objective 0, the only one implemented) with its gradient with respect to
+ * log sigma0_r and log c_v,r (grad arrays [n_regions]).  The gradient is
+ * that of the converged discrete solution of every step (transport with
+ * emission, Sec. 3, plus the lumped energy balance, Sec. 2), obtained
+ * backwards by adjoint source iteration: adjoint sweeps (smrt_adjoint_sweep)
+ * alternating with the pointwise temperature adjoint.  Clipped opacities
+ * contribute no sigma0 sensitivity.  adjoint_iterations (may be NULL)
+ * receives the total number of adjoint source iterations.  The context
+ * state is advanced by n_steps.  Errors: SMRT_E_INVALID_ARG (objective,
+ * n_steps < 1, dt <= 0, constant-opacity model, quadrature without
+ * opposite directions, no state), or the failure of a forward step. */
+smrt_status smrt_adjoint(smrt_ctx *ctx, int objective, int n_steps, double dt, double *J, double *grad_log_sigma0,
+                         double *grad_log_cv, int *adjoint_iterations);
+
 /* Closures and low-order sources (Sec. 2 gray collapse, Sec. 4 consistent /
  * independent LDG sources) from HO moments (FP64 [27|8][node], as produced by
  * smrt_sweep), the outer-iterate temperature T_l[n], the time-edge sources

@@ -79,6 +79,11 @@ def _declare(L):
     L.orc_sweep.restype = C.c_int
     L.orc_adjoint_sweep.argtypes = [gp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_adjoint_sweep.restype = C.c_int
+    L.orc_adjoint_gradient.argtypes = [gp, mp, bp, C.POINTER(Opts), C.c_double, C.c_int, _dp, _dp, _dp, _dp, _dp,
+                                       C.c_int, C.POINTER(C.c_int)]
+    L.orc_adjoint_gradient.restype = C.c_int
+    L.orc_leakage.argtypes = [gp, mp, bp, C.POINTER(Opts), C.c_double, C.c_int, _dp, _dp, _dp]
+    L.orc_leakage.restype = C.c_int
     L.orc_moments.argtypes = [gp, _dp, _dp, _dp]
     L.orc_n_moments.argtypes = [C.c_int]
     L.orc_inflow_from_bc.argtypes = [gp, bp, _dp]
@@ -182,6 +187,31 @@ class Oracle:
                                      _p(lam), _p(dsig))
         assert r == 0
         return (lam, dsig) if want else lam
+
+    def leakage(self, opts, n_steps, dt=None):
+        """Time-integrated right-boundary outflow over n_steps from the initial state."""
+        st = self.initial_state()
+        J = C.c_double(0.0)
+        o = Opts(**opts)
+        r = self.L.orc_leakage(C.byref(self.geom), C.byref(self.mat), C.byref(self.bc), C.byref(o),
+                               float(dt if dt is not None else self.p.dt), int(n_steps), _p(st["psi"]), _p(st["T"]),
+                               C.byref(J))
+        assert r == 0, r
+        return J.value
+
+    def adjoint_gradient(self, opts, n_steps, dt=None):
+        """(J, dJ/dlog sigma0 [n_regions], dJ/dlog c_v [n_regions], adjoint iterations)."""
+        st = self.initial_state()
+        nr = self.p.n_regions
+        J = C.c_double(0.0)
+        gs, gc = np.zeros(nr), np.zeros(nr)
+        it = C.c_int(0)
+        o = Opts(**opts)
+        r = self.L.orc_adjoint_gradient(C.byref(self.geom), C.byref(self.mat), C.byref(self.bc), C.byref(o),
+                                        float(dt if dt is not None else self.p.dt), int(n_steps), _p(st["psi"]),
+                                        _p(st["T"]), C.byref(J), _p(gs), _p(gc), nr, C.byref(it))
+        assert r == 0, r
+        return J.value, gs, gc, it.value
 
     def moments(self, sig, psi):
         nm = self.L.orc_n_moments(self.p.dim)

@@ -1092,3 +1092,219 @@ void orc_equilibrium_psi(const orc_geom *g, const double *T, double *psi)
     }
     free(b); free(r);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint gradient of the time-integrated right-boundary outflow            */
+/*   J = sum_k dt sum_g sum_{d: mu_d > 0} w_d mu_d sum_{n on x+} fw_n I^k_n  */
+/* with respect to log sigma0_r and log c_v,r, taken at the converged fixed  */
+/* point of every step (implicit function theorem).  The fixed point of a   */
+/* step solves the lumped DG transport with emission sigma_g B_g(T)/4pi and */
+/* time-edge source I^{k-1}/(c dt) (Sec. 3) together with the lumped nodal  */
+/* energy balance c_v (T - T^{k-1})/dt = sum_g sigma_g (phi_g - 4 pi E_g(T)),*/
+/* E_g = a c T^4 b_g / 4pi (Sec. 2), with sigma_g from the start-of-step     */
+/* cell temperature.  Forward: orc_step with the options given (tight       */
+/* tolerances), keeping I^k, T^k, sigma^k.  Reverse, k = N..1: the adjoint  */
+/* of the step solves                                                        */
+/*   L^T lam_{d,g} = S^I_{d,g} + sigma_g w_d tau                              */
+/*   D tau - w sum_g sigma_g E'_g(T) sum_d lam_{d,g} = S^T,                   */
+/*   D = c_v/dt + sum_g sigma_g 4 pi E'_g(T),  4 pi E'_g = 4 a c T^3 r_g      */
+/* by source iteration (adjoint sweep, then pointwise tau), with            */
+/*   S^I = dJ/dI^k + (w/(c dt)) lam^{k+1},                                    */
+/*   S^T = (c_v/dt) tau^{k+1} - sum_g dsigma^{k+1}_g/dT^k G^{k+1}_g,          */
+/*   G_{c,g} = lam^T dR/dsigma_{c,g}                                          */
+/*          = sum_d sum_{l in c} w_l lam (I - E_g)                             */
+/*            - sum_{l in c} tau_l (phi_g - 4 pi E_g),                         */
+/* and dJ/dlog sigma0_r = -sum_k sum_{c in r, g unclipped} sigma G,          */
+/*     dJ/dlog c_v,r    = -sum_k sum_{n in r} tau_n c_v (T^k - T^{k-1})/dt.  */
+/* ------------------------------------------------------------------------ */
+
+int orc_adjoint_gradient(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_opts *op, double dt,
+                         int n_steps, const double *psi0, const double *T0, double *J_out, double *grad_s0,
+                         double *grad_cv, int n_regions, int *adj_iters)
+{
+    int nn = nnode(g), np = npc(g), G = g->G, nc = ncell(g), nd = g->nang, dim = g->dim;
+    int nx = g->nx;
+    size_t npsi = (size_t)nd * G * nn;
+    double a = g->a, c = g->c;
+    int N = n_steps;
+    double *ck_psi = malloc(sizeof(double) * npsi * (N + 1));
+    double *ck_T = malloc(sizeof(double) * (size_t)nn * (N + 1));
+    double *ck_sig = malloc(sizeof(double) * (size_t)nc * G * (N + 1));
+    double *E = malloc(sizeof(double) * nn), *F = calloc((size_t)nn * dim, sizeof(double));
+    double *cvn = malloc(sizeof(double) * nn), *wsp = malloc(sizeof(double) * nn);
+    double *dJdI = calloc(npsi, sizeof(double));
+    int rc = ORC_OK;
+    nodal_cv(g, mt, cvn);
+    for (int cc = 0; cc < nc; ++cc)
+        for (int l = 0; l < np; ++l) wsp[np * cc + l] = vol_weight(g, cc % nx, cc / nx);
+    /* objective weights: outflow through x+ */
+    for (int d = 0; d < nd; ++d) {
+        double mu = om_ax(g, d, 0);
+        if (mu <= 0.0) continue;
+        for (int k = 0; k < G; ++k)
+            for (int cc = 0; cc < nc; ++cc) {
+                int i = cc % nx, j = cc / nx;
+                if (i != nx - 1) continue;
+                for (int l = 0; l < np; ++l)
+                    if (node_on_face(l, 0, 1))
+                        dJdI[((size_t)d * G + k) * nn + np * cc + l] = dt * g->w[d] * mu * face_weight(g, i, j, 0);
+            }
+    }
+    /* forward with checkpoints */
+    memcpy(ck_psi, psi0, sizeof(double) * npsi);
+    memcpy(ck_T, T0, sizeof(double) * nn);
+    for (int n = 0; n < nn; ++n) E[n] = a * pow(T0[n], 4);
+    double J = 0.0;
+    for (int k = 1; k <= N && rc == ORC_OK; ++k) {
+        double *psi = ck_psi + npsi * k, *T = ck_T + (size_t)nn * k;
+        memcpy(psi, ck_psi + npsi * (k - 1), sizeof(double) * npsi);
+        memcpy(T, ck_T + (size_t)nn * (k - 1), sizeof(double) * nn);
+        orc_opacity(g, mt, T, ck_sig + (size_t)nc * G * k);    /* start-of-step temperature */
+        orc_stats st;
+        rc = orc_step(g, mt, bc, op, dt, psi, T, E, F, &st);
+        for (size_t t = 0; t < npsi; ++t) J += dJdI[t] * psi[t];
+    }
+    *J_out = J;
+    if (rc != ORC_OK) goto done;
+    {
+        for (int r = 0; r < n_regions; ++r) { grad_s0[r] = 0.0; grad_cv[r] = 0.0; }
+        double *lam = calloc(npsi, sizeof(double)), *lam_next = calloc(npsi, sizeof(double));
+        double *src = malloc(sizeof(double) * npsi), *sigt = malloc(sizeof(double) * (size_t)nc * G);
+        double *tau = calloc(nn, sizeof(double)), *ST = calloc(nn, sizeof(double)), *ST_prev = calloc(nn, sizeof(double));
+        double *emis = malloc(sizeof(double) * (size_t)nn * G), *dE = malloc(sizeof(double) * (size_t)nn * G);
+        double *phi = malloc(sizeof(double) * (size_t)nn * G), *D = malloc(sizeof(double) * nn);
+        double *Gs = malloc(sizeof(double) * (size_t)nc * G), *dsig = malloc(sizeof(double) * (size_t)nc * G);
+        double *bg = malloc(sizeof(double) * G), *rg = malloc(sizeof(double) * G), *tau_new = malloc(sizeof(double) * nn);
+        int iters = 0;
+        for (int k = N; k >= 1; --k) {
+            const double *psi = ck_psi + npsi * k, *T = ck_T + (size_t)nn * k, *Tp = ck_T + (size_t)nn * (k - 1);
+            const double *sig = ck_sig + (size_t)nc * G * k;
+            for (size_t t = 0; t < (size_t)nc * G; ++t) sigt[t] = sig[t] + 1.0 / (c * dt);
+            for (int n = 0; n < nn; ++n) {
+                orc_spectra(G, g->nu, T[n], bg, rg);
+                double T3 = pow(T[n], 3), T4 = T3 * T[n];
+                D[n] = cvn[n] / dt;
+                for (int q = 0; q < G; ++q) {
+                    emis[(size_t)n * G + q] = a * c * T4 * bg[q] / (4.0 * M_PI);
+                    dE[(size_t)n * G + q] = 4.0 * a * c * T3 * rg[q] / (4.0 * M_PI);
+                    D[n] += sig[(size_t)(n / np) * G + q] * 4.0 * M_PI * dE[(size_t)n * G + q];
+                    double s = 0.0;
+                    for (int d = 0; d < nd; ++d) s += g->w[d] * psi[((size_t)d * G + q) * nn + n];
+                    phi[(size_t)n * G + q] = s;
+                }
+            }
+            /* adjoint source iteration */
+            for (int n = 0; n < nn; ++n) tau[n] = 0.0;
+            for (int it = 0; it < 500; ++it) {
+                for (int d = 0; d < nd; ++d)
+                    for (int q = 0; q < G; ++q)
+                        for (int n = 0; n < nn; ++n) {
+                            size_t t = ((size_t)d * G + q) * nn + n;
+                            double SI = dJdI[t] + wsp[n] / (c * dt) * lam_next[t];
+                            src[t] = (SI + sig[(size_t)(n / np) * G + q] * g->w[d] * tau[n]) / wsp[n];
+                        }
+                if (orc_adjoint_sweep(g, sigt, src, NULL, NULL, lam, NULL)) { rc = -1; break; }
+                double num = 0.0, den = 0.0;
+                for (int n = 0; n < nn; ++n) {
+                    double s = ST[n];
+                    for (int q = 0; q < G; ++q) {
+                        double ls = 0.0;
+                        for (int d = 0; d < nd; ++d) ls += lam[((size_t)d * G + q) * nn + n];
+                        s += wsp[n] * sig[(size_t)(n / np) * G + q] * dE[(size_t)n * G + q] * ls;
+                    }
+                    tau_new[n] = s / D[n];
+                    num += (tau_new[n] - tau[n]) * (tau_new[n] - tau[n]);
+                    den += tau_new[n] * tau_new[n];
+                }
+                memcpy(tau, tau_new, sizeof(double) * nn);
+                ++iters;
+                if (num <= 1e-30 * den || den == 0.0) break;
+            }
+            if (rc) break;
+            /* lam consistent with the final tau */
+            for (int d = 0; d < nd; ++d)
+                for (int q = 0; q < G; ++q)
+                    for (int n = 0; n < nn; ++n) {
+                        size_t t = ((size_t)d * G + q) * nn + n;
+                        double SI = dJdI[t] + wsp[n] / (c * dt) * lam_next[t];
+                        src[t] = (SI + sig[(size_t)(n / np) * G + q] * g->w[d] * tau[n]) / wsp[n];
+                    }
+            if (orc_adjoint_sweep(g, sigt, src, emis, psi, lam, dsig)) { rc = -1; break; }
+            /* G = lam^T dR/dsigma, gradient contributions, S^T for step k-1 */
+            for (int cc = 0; cc < nc; ++cc)
+                for (int q = 0; q < G; ++q) {
+                    double v = -dsig[(size_t)cc * G + q];
+                    for (int l = 0; l < np; ++l) {
+                        int n = np * cc + l;
+                        v -= tau[n] * (phi[(size_t)n * G + q] - 4.0 * M_PI * emis[(size_t)n * G + q]);
+                    }
+                    Gs[(size_t)cc * G + q] = v;
+                }
+            for (int cc = 0; cc < nc; ++cc) {
+                int r = mt->region[cc];
+                double Tc = 0.0;
+                for (int l = 0; l < np; ++l) Tc += Tp[np * cc + l];
+                Tc /= np;
+                for (int q = 0; q < G; ++q) {
+                    double s = sig[(size_t)cc * G + q];
+                    int free_ = mt->model == 0 || (s > mt->clip_lo && s < mt->clip_hi);
+                    if (free_) grad_s0[r] -= s * Gs[(size_t)cc * G + q];
+                }
+                for (int l = 0; l < np; ++l) {
+                    int n = np * cc + l;
+                    grad_cv[r] -= tau[n] * cvn[n] * (T[n] - Tp[n]) / dt;
+                    double sT = cvn[n] / dt * tau[n];
+                    if (mt->model == 1)
+                        for (int q = 0; q < G; ++q) {
+                            double s = sig[(size_t)cc * G + q];
+                            if (s > mt->clip_lo && s < mt->clip_hi)
+                                sT -= (-3.0 * s / (np * Tc)) * Gs[(size_t)cc * G + q];
+                        }
+                    ST_prev[n] = sT;
+                }
+            }
+            memcpy(ST, ST_prev, sizeof(double) * nn);
+            memcpy(lam_next, lam, sizeof(double) * npsi);
+        }
+        if (adj_iters) *adj_iters = iters;
+        free(lam); free(lam_next); free(src); free(sigt); free(tau); free(ST); free(ST_prev); free(emis); free(dE);
+        free(phi); free(D); free(Gs); free(dsig); free(bg); free(rg); free(tau_new);
+    }
+done:
+    free(ck_psi); free(ck_T); free(ck_sig); free(E); free(F); free(cvn); free(wsp); free(dJdI);
+    return rc;
+}
+
+/* J alone (forward only), for finite differences */
+int orc_leakage(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_opts *op, double dt, int n_steps,
+                const double *psi0, const double *T0, double *J_out)
+{
+    int nn = nnode(g), np = npc(g), G = g->G, nc = ncell(g), nd = g->nang, dim = g->dim, nx = g->nx;
+    size_t npsi = (size_t)nd * G * nn;
+    double *psi = malloc(sizeof(double) * npsi), *T = malloc(sizeof(double) * nn);
+    double *E = malloc(sizeof(double) * nn), *F = calloc((size_t)nn * dim, sizeof(double));
+    memcpy(psi, psi0, sizeof(double) * npsi);
+    memcpy(T, T0, sizeof(double) * nn);
+    for (int n = 0; n < nn; ++n) E[n] = g->a * pow(T0[n], 4);
+    double J = 0.0;
+    int rc = ORC_OK;
+    for (int k = 1; k <= n_steps && rc == ORC_OK; ++k) {
+        orc_stats st;
+        rc = orc_step(g, mt, bc, op, dt, psi, T, E, F, &st);
+        for (int d = 0; d < nd; ++d) {
+            double mu = om_ax(g, d, 0);
+            if (mu <= 0.0) continue;
+            for (int q = 0; q < G; ++q)
+                for (int cc = 0; cc < nc; ++cc) {
+                    int i = cc % nx, j = cc / nx;
+                    if (i != nx - 1) continue;
+                    for (int l = 0; l < np; ++l)
+                        if (node_on_face(l, 0, 1))
+                            J += dt * g->w[d] * mu * face_weight(g, i, j, 0) * psi[((size_t)d * G + q) * nn + np * cc + l];
+                }
+        }
+    }
+    *J_out = J;
+    free(psi); free(T); free(E); free(F);
+    return rc;
+}

@@ -1485,3 +1485,152 @@ extern "C" smrt_status smrt_batch_step(smrt_batch *b, const double *dt, smrt_ste
     if (st == SMRT_OK && result != SMRT_OK) g_last_error = b->err;
     return st != SMRT_OK ? st : result;
 }
+
+// ---------------------------------------------------------------------------
+// Materials update (per-region sigma0 and c_v), e.g. between gradient steps
+// ---------------------------------------------------------------------------
+extern "C" smrt_status smrt_set_materials(smrt_ctx *x, const double *sigma0, const double *cv) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(sigma0 != nullptr || cv != nullptr, "nothing to set");
+        if (sigma0) {
+            const size_t ns = x->sigma0.size();
+            for (size_t k = 0; k < ns; ++k) require(std::isfinite(sigma0[k]) && sigma0[k] >= 0.0, "sigma0 must be >= 0");
+            std::copy(sigma0, sigma0 + ns, x->sigma0.begin());
+            SMRT_HIP(hipMemcpy(x->d_sigma0.p, x->sigma0.data(), 8 * ns, hipMemcpyHostToDevice));
+        }
+        if (cv) {
+            for (int r = 0; r < x->nreg; ++r) require(std::isfinite(cv[r]) && cv[r] > 0.0, "c_v must be > 0");
+            std::copy(cv, cv + x->nreg, x->cv.begin());
+            std::vector<double> cvn(x->nn);
+            for (int n = 0; n < x->nn; ++n) cvn[n] = x->cv[x->region[n / x->npc]];
+            SMRT_HIP(hipMemcpy(x->d_cvn.p, cvn.data(), 8 * x->nn, hipMemcpyHostToDevice));
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint gradient of the time-integrated right-boundary outflow
+//   J = sum_k dt sum_g sum_{mu_d > 0} w_d mu_d sum_{n on x+} fw_n I^k_n
+// with respect to log sigma0_r and log c_v,r, at the converged fixed point of
+// every step (implicit function theorem): forward steps with checkpoints of
+// (I^k, T^k, sigma^k), then, backwards, the adjoint of each step by source
+// iteration (adjoint sweep + pointwise temperature adjoint) and the
+// sensitivities of the opacity and heat-capacity terms.
+// ---------------------------------------------------------------------------
+static void adjoint_sweep_dev(smrt_ctx *x, const double *sigt, const double *src, double *lam, double *prev_tmp,
+                              double *out_tmp, const double *zq, const double *zinf) {
+    const int64_t per = (int64_t)x->G * x->nn;
+    run_permute_dirs(x->stream, x->nang, per, x->d_opposite.p, src, prev_tmp);
+    raw_sweep(x, sigt, sigt, zq, prev_tmp, 1.0, zinf, out_tmp, nullptr);
+    run_permute_dirs(x->stream, x->nang, per, x->d_opposite.p, out_tmp, lam);
+}
+
+static void psi_state_to_abi(smrt_ctx *x, double *out) {
+    const int64_t na = (int64_t)x->nang * x->G * x->nn;
+    if (x->dim == 2) {
+        if (x->fp32) run_psi_from_internal<float>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const float *)x->d_psi[x->cur].p, out);
+        else run_psi_from_internal<double>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const double *)x->d_psi[x->cur].p, out);
+    } else {
+        if (x->fp32) run_copy_from<float>(x->stream, na, (const float *)x->d_psi[x->cur].p, out);
+        else run_copy_from<double>(x->stream, na, (const double *)x->d_psi[x->cur].p, out);
+    }
+}
+
+extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, double dt, double *J_out,
+                                    double *grad_log_sigma0, double *grad_log_cv, int *adjoint_iterations) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(objective == 0, "objective 0 (right-boundary outflow) is the one implemented");
+        require(n_steps >= 1 && dt > 0.0 && std::isfinite(dt), "n_steps >= 1 and dt > 0 required");
+        require(J_out && grad_log_sigma0 && grad_log_cv, "NULL output");
+        require(x->have_state, "smrt_set_state must be called first");
+        require(x->have_opposite, "the quadrature has a direction without its opposite: no adjoint sweep");
+        require(x->model == 1, "the gradient is defined for the power-law opacity model (one sigma0 per region)");
+        hipStream_t S = x->stream;
+        const int N = n_steps, nn = x->nn, nc = x->ncell, G = x->G, npc = x->npc, nreg = x->nreg;
+        const int64_t npsi = (int64_t)x->nang * G * nn, ncg = (int64_t)nc * G;
+        const int ny1 = x->dim == 2 ? x->ny : 1;
+        const double *hy = x->dim == 2 ? x->d_hy64.p : nullptr;
+        DevBuf<double> ck_psi, ck_T, ck_sig, dJdI, part, scal;
+        ck_psi.alloc(npsi * (N + 1));
+        ck_T.alloc((int64_t)nn * (N + 1));
+        ck_sig.alloc(ncg * (N + 1));
+        dJdI.alloc(npsi);
+        part.alloc(std::max<int64_t>(256, 2 * ((nn + 255) / 256)));
+        scal.alloc(4);
+        run_adj_dJdI(S, x->dim, x->nx, ny1, G, x->nang, x->d_om.p, x->d_w.p, hy, dt, dJdI.p);
+        // forward with checkpoints
+        psi_state_to_abi(x, ck_psi.p);
+        SMRT_HIP(hipMemcpyAsync(ck_T.p, x->d_T.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+        double J = 0.0;
+        for (int k = 1; k <= N; ++k) {
+            StepRun run;
+            run.begin(x, dt);
+            SMRT_HIP(hipMemcpyAsync(ck_sig.p + ncg * k, x->d_sig.p, 8 * ncg, hipMemcpyDeviceToDevice, S));
+            for (;;) {
+                run.pre_sweep();
+                run.t_sweep += timed(S, [&] {
+                    run_sweep(x, run.pin, run.pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, run.icdt, x->d_sig.p, x->d_mom.p);
+                });
+                if (run.post_sweep()) break;
+            }
+            const smrt_status r = run.end(nullptr);
+            if (r != SMRT_OK) throw smrt::Error(r, "forward step " + std::to_string(k) + ": " + x->err);
+            psi_state_to_abi(x, ck_psi.p + npsi * k);
+            SMRT_HIP(hipMemcpyAsync(ck_T.p + (int64_t)nn * k, x->d_T.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+            run_dot(S, npsi, dJdI.p, ck_psi.p + npsi * k, part.p, scal.p);
+            double jk = 0.0;
+            d2h(&jk, scal.p, 8, S);
+            SMRT_HIP(hipStreamSynchronize(S));
+            J += jk;
+        }
+        // reverse
+        DevBuf<double> lam, lam_next, src, prev_tmp, out_tmp, zq, zinf, sigt, tau, tau_new, ST, ST_prev, emis, dE, phi, D,
+            dsig, gs_cell, gcv_node, gs, gc;
+        lam.alloc(npsi); lam_next.alloc(npsi); src.alloc(npsi); prev_tmp.alloc(npsi); out_tmp.alloc(npsi);
+        zq.alloc((int64_t)nn * G); zinf.alloc((int64_t)x->nang * G * x->NB);
+        sigt.alloc(ncg); tau.alloc(nn); tau_new.alloc(nn); ST.alloc(nn); ST_prev.alloc(nn);
+        emis.alloc((int64_t)nn * G); dE.alloc((int64_t)nn * G); phi.alloc((int64_t)nn * G); D.alloc(nn);
+        dsig.alloc(ncg); gs_cell.alloc(nc); gcv_node.alloc(nn); gs.alloc(nreg); gc.alloc(nreg);
+        lam_next.zero(S); zq.zero(S); zinf.zero(S); ST.zero(S); gs.zero(S); gc.zero(S);
+        const double icdt = 1.0 / (x->c * dt);
+        int iters = 0;
+        for (int k = N; k >= 1; --k) {
+            const double *psi = ck_psi.p + npsi * k, *T = ck_T.p + (int64_t)nn * k, *Tp = ck_T.p + (int64_t)nn * (k - 1);
+            const double *sig = ck_sig.p + ncg * k;
+            run_add_scalar(S, ncg, sig, icdt, sigt.p);
+            run_adj_prep(S, nn, npc, G, x->nang, x->d_nu.p, x->a, x->c, dt, T, sig, x->d_cvn.p, x->d_w.p, psi, emis.p,
+                         dE.p, D.p, phi.p);
+            tau.zero(S);
+            for (int it = 0; it < 500; ++it) {
+                run_adj_src(S, x->dim, x->nx, ny1, G, x->nang, x->d_hx64.p, hy, x->d_w.p, dJdI.p, lam_next.p, icdt, sig,
+                            tau.p, src.p);
+                adjoint_sweep_dev(x, sigt.p, src.p, lam.p, prev_tmp.p, out_tmp.p, zq.p, zinf.p);
+                run_adj_tau(S, x->dim, x->nx, ny1, G, x->nang, x->d_hx64.p, hy, sig, dE.p, ST.p, D.p, lam.p, tau.p,
+                            tau_new.p, part.p, scal.p);
+                double nd[2];
+                d2h(nd, scal.p, 16, S);
+                SMRT_HIP(hipStreamSynchronize(S));
+                std::swap(tau.p, tau_new.p);
+                ++iters;
+                if (!(nd[0] > 1e-30 * nd[1]) || nd[1] == 0.0) break;
+            }
+            // lam consistent with the final tau, then the sensitivities of this step
+            run_adj_src(S, x->dim, x->nx, ny1, G, x->nang, x->d_hx64.p, hy, x->d_w.p, dJdI.p, lam_next.p, icdt, sig,
+                        tau.p, src.p);
+            adjoint_sweep_dev(x, sigt.p, src.p, lam.p, prev_tmp.p, out_tmp.p, zq.p, zinf.p);
+            run_adjoint_dsig(S, x->dim, x->nx, ny1, G, x->nang, x->d_hx64.p, hy, lam.p, emis.p, psi, dsig.p);
+            run_adj_cell(S, npc, nc, G, x->model, x->clip_lo, x->clip_hi, dt, dsig.p, tau.p, phi.p, emis.p, sig,
+                         x->d_cvn.p, T, Tp, gs_cell.p, gcv_node.p, ST_prev.p);
+            run_region_sums(S, nreg, nc, npc, x->d_region.p, gs_cell.p, gcv_node.p, gs.p, gc.p);
+            std::swap(ST.p, ST_prev.p);
+            std::swap(lam_next.p, lam.p);
+        }
+        d2h(grad_log_sigma0, gs.p, 8 * nreg, S);
+        d2h(grad_log_cv, gc.p, 8 * nreg, S);
+        SMRT_HIP(hipStreamSynchronize(S));
+        *J_out = J;
+        if (adjoint_iterations) *adjoint_iterations = iters;
+    });
+}

@@ -28,6 +28,27 @@ template <typename real>
 void run_copy_to(hipStream_t s, int64_t n, const double *src, real *dst);
 template <typename real>
 void run_copy_from(hipStream_t s, int64_t n, const real *src, double *dst);
+void run_adj_prep(hipStream_t s, int nn, int npc, int G, int nang, const double *nu, double a, double c, double dt,
+                  const double *T, const double *sig, const double *cvn, const double *w, const double *psi, double *emis,
+                  double *dE, double *D, double *phi);
+void run_adj_dJdI(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *om, const double *w,
+                  const double *hy, double dt, double *out);
+void run_adj_src(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy,
+                 const double *wang, const double *dJdI, const double *lam_next, double icdt, const double *sig,
+                 const double *tau, double *src);
+// part: scratch of 2 * ceil(nodes / 256) doubles; out2: [|tau_new - tau|^2, |tau_new|^2]
+void run_adj_tau(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy,
+                 const double *sig, const double *dE, const double *ST, const double *D, const double *lam,
+                 const double *tau, double *tau_new, double *part, double *out2);
+void run_adj_cell(hipStream_t s, int npc, int ncell, int G, int model, double clip_lo, double clip_hi, double dt,
+                  const double *dsig, const double *tau, const double *phi, const double *emis, const double *sig,
+                  const double *cvn, const double *T, const double *Tp, double *gs_cell, double *gcv_node,
+                  double *ST_prev);
+void run_region_sums(hipStream_t s, int nreg, int ncell, int npc, const int *region, const double *gs_cell,
+                     const double *gcv_node, double *grad_s0, double *grad_cv);
+// part256: scratch of 256 doubles
+void run_dot(hipStream_t s, int64_t n, const double *a, const double *b, double *part256, double *out);
+void run_add_scalar(hipStream_t s, int64_t n, const double *a, double v, double *out);
 void run_permute_dirs(hipStream_t s, int nang, int64_t per, const int *map, const double *in, double *out);
 void run_adjoint_dsig(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy,
                       const double *lam, const double *emis, const double *psi, double *dsig);

@@ -345,6 +345,188 @@ __global__ void k_adjoint_dsig(int dim, int nx, int ny, int G, int nang, const d
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of a time step (implicit function theorem at the converged step):
+// per-node quantities of the step, adjoint source assembly, the pointwise
+// temperature adjoint, sigma-sensitivities and per-region gradient sums.
+// Nodal weights: 2D |cell|/4 = hx hy / 4, 1D hx / 2.
+// ---------------------------------------------------------------------------
+__device__ inline double nodal_weight(int dim, int nx, const double *hx, const double *hy, int cell) {
+    return dim == 2 ? hx[cell % nx] * hy[cell / nx] * 0.25 : hx[cell] * 0.5;
+}
+
+// emis = a c T^4 b_g / 4pi, dE = 4 a c T^3 r_g / 4pi, D = c_v/dt + sum_g sigma_g 4pi dE,
+// phi_g = sum_d w_d I_{d,g}
+__global__ void k_adj_prep(int nn, int npc, int G, int nang, const double *nu, double a, double c, double dt,
+                           const double *T, const double *sig, const double *cvn, const double *w, const double *psi,
+                           double *emis, double *dE, double *D, double *phi) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double b[MAXG], r[MAXG];
+    const double Tn = T[n];
+    group_fractions(G, nu, Tn, b, r);
+    const double T3 = Tn * Tn * Tn, T4 = T3 * Tn;
+    double dsum = cvn[n] / dt;
+    for (int g = 0; g < G; ++g) {
+        const double e = a * c * T4 * b[g] / (4.0 * M_PI), de = 4.0 * a * c * T3 * r[g] / (4.0 * M_PI);
+        emis[(int64_t)n * G + g] = e;
+        dE[(int64_t)n * G + g] = de;
+        dsum += sig[(int64_t)(n / npc) * G + g] * 4.0 * M_PI * de;
+        double ph = 0.0;
+        for (int d = 0; d < nang; ++d) ph += w[d] * psi[((int64_t)d * G + g) * nn + n];
+        phi[(int64_t)n * G + g] = ph;
+    }
+    D[n] = dsum;
+}
+
+// right-boundary outflow weights dJ/dI = dt w_d mu_d fw_n (mu_d > 0, n on x+)
+__global__ void k_adj_dJdI(int dim, int nx, int ny, int G, int nang, const double *om, const double *w, const double *hy,
+                           double dt, double *out) {
+    const int npc = dim == 2 ? 4 : 2, nn = nx * ny * npc;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nang * G * nn) return;
+    const int n = (int)(i % nn), d = (int)(i / ((int64_t)G * nn));
+    const int cell = n / npc, l = n % npc;
+    const double mu = om[3 * d];
+    double v = 0.0;
+    if (mu > 0.0 && cell % nx == nx - 1 && (l & 1)) v = dt * w[d] * mu * (dim == 2 ? 0.5 * hy[cell / nx] : 1.0);
+    out[i] = v;
+}
+
+// src = (dJ/dI + w/(c dt) lam_next + sigma_g w_d tau) / w
+__global__ void k_adj_src(int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy, const double *wang,
+                          const double *dJdI, const double *lam_next, double icdt, const double *sig, const double *tau,
+                          double *src) {
+    const int npc = dim == 2 ? 4 : 2, nn = nx * ny * npc;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nang * G * nn) return;
+    const int n = (int)(i % nn);
+    const int64_t dg = i / nn;
+    const int d = (int)(dg / G), g = (int)(dg % G);
+    const int cell = n / npc;
+    const double wl = nodal_weight(dim, nx, hx, hy, cell);
+    src[i] = (dJdI[i] + wl * icdt * lam_next[i] + sig[(int64_t)cell * G + g] * wang[d] * tau[n]) / wl;
+}
+
+// tau_new = (ST + w sum_g sigma_g dE_g sum_d lam) / D; block partials of |tau_new - tau|^2 and |tau_new|^2
+__global__ void k_adj_tau(int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy,
+                          const double *sig, const double *dE, const double *ST, const double *D, const double *lam,
+                          const double *tau, double *tau_new, double *part) {
+    __shared__ double sh[2][256];
+    const int npc = dim == 2 ? 4 : 2, nn = nx * ny * npc;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    double e1 = 0.0, e2 = 0.0;
+    if (n < nn) {
+        const int cell = n / npc;
+        double s = ST[n];
+        for (int g = 0; g < G; ++g) {
+            double ls = 0.0;
+            for (int d = 0; d < nang; ++d) ls += lam[((int64_t)d * G + g) * nn + n];
+            s += nodal_weight(dim, nx, hx, hy, cell) * sig[(int64_t)cell * G + g] * dE[(int64_t)n * G + g] * ls;
+        }
+        const double t = s / D[n];
+        tau_new[n] = t;
+        e1 = (t - tau[n]) * (t - tau[n]);
+        e2 = t * t;
+    }
+    sh[0][threadIdx.x] = e1;
+    sh[1][threadIdx.x] = e2;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0];
+        part[2 * blockIdx.x + 1] = sh[1][0];
+    }
+}
+
+// sum of nb pairs of block partials in a fixed order (one thread)
+__global__ void k_sum_pairs(int nb, const double *part, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < nb; ++k) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    out[0] = a;
+    out[1] = b;
+}
+
+// G_{c,g} = lam^T dR/dsigma_{c,g} = -dsig - sum_{l in c} tau_l (phi_g - 4pi emis_g); then per cell the
+// log-sigma0 sensitivity, per node the log-c_v sensitivity and the temperature source of the step before
+__global__ void k_adj_cell(int npc, int ncell, int G, int model, double clip_lo, double clip_hi, double dt,
+                           const double *dsig, const double *tau, const double *phi, const double *emis,
+                           const double *sig, const double *cvn, const double *T, const double *Tp, double *gs_cell,
+                           double *gcv_node, double *ST_prev) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    double Tc = 0.0;
+    for (int l = 0; l < npc; ++l) Tc += Tp[npc * c + l];
+    Tc /= npc;
+    double gsum = 0.0, dTsum = 0.0;   // sum_g free sigma G ; sum_g free dsigma/dT G
+    for (int g = 0; g < G; ++g) {
+        double Gv = -dsig[(int64_t)c * G + g];
+        for (int l = 0; l < npc; ++l) {
+            const int n = npc * c + l;
+            Gv -= tau[n] * (phi[(int64_t)n * G + g] - 4.0 * M_PI * emis[(int64_t)n * G + g]);
+        }
+        const double s = sig[(int64_t)c * G + g];
+        const bool free_ = model == 0 || (s > clip_lo && s < clip_hi);
+        if (free_) gsum += s * Gv;
+        if (model == 1 && s > clip_lo && s < clip_hi) dTsum += (-3.0 * s / (npc * Tc)) * Gv;
+    }
+    gs_cell[c] = -gsum;
+    for (int l = 0; l < npc; ++l) {
+        const int n = npc * c + l;
+        gcv_node[n] = -tau[n] * cvn[n] * (T[n] - Tp[n]) / dt;
+        ST_prev[n] = cvn[n] / dt * tau[n] - dTsum;
+    }
+}
+
+// per-region sums in cell order (one thread per region); accumulated into grad_s0, grad_cv
+__global__ void k_region_sums(int nreg, int ncell, int npc, const int *region, const double *gs_cell,
+                              const double *gcv_node, double *grad_s0, double *grad_cv) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nreg) return;
+    double a = 0.0, b = 0.0;
+    for (int c = 0; c < ncell; ++c) {
+        if (region[c] != r) continue;
+        a += gs_cell[c];
+        for (int l = 0; l < npc; ++l) b += gcv_node[npc * c + l];
+    }
+    grad_s0[r] += a;
+    grad_cv[r] += b;
+}
+
+// deterministic dot product of two long arrays (block partials, fixed-order sum)
+__global__ void k_dot_blocks(int64_t n, const double *a, const double *b, double *part) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += a[i] * b[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_sum_blocks(int nb, const double *part, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += part[k];
+    out[0] = s;
+}
+__global__ void k_add_scalar(int64_t n, const double *a, double v, double *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] + v;
+}
+
+// ---------------------------------------------------------------------------
 // Moment finalisation (2D), deterministic (fixed summation order).
 // Partials: [chunk][band][step t][canonical node lc * 9 + moment][row], the
 // cell of (t, row) being canonical column t - row; chunks are grouped by
@@ -559,6 +741,51 @@ void run_adjoint_dsig(hipStream_t s, int dim, int nx, int ny, int G, int nang, c
                       const double *lam, const double *emis, const double *psi, double *dsig) {
     hipLaunchKernelGGL(k_adjoint_dsig, dim3(nblk((int64_t)nx * ny * G, 128)), dim3(128), 0, s, dim, nx, ny, G, nang, hx,
                        hy, lam, emis, psi, dsig);
+}
+void run_adj_prep(hipStream_t s, int nn, int npc, int G, int nang, const double *nu, double a, double c, double dt,
+                  const double *T, const double *sig, const double *cvn, const double *w, const double *psi, double *emis,
+                  double *dE, double *D, double *phi) {
+    hipLaunchKernelGGL(k_adj_prep, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, npc, G, nang, nu, a, c, dt, T, sig, cvn, w,
+                       psi, emis, dE, D, phi);
+}
+void run_adj_dJdI(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *om, const double *w,
+                  const double *hy, double dt, double *out) {
+    const int64_t n = (int64_t)nang * G * nx * ny * (dim == 2 ? 4 : 2);
+    hipLaunchKernelGGL(k_adj_dJdI, dim3(nblk(n, 256)), dim3(256), 0, s, dim, nx, ny, G, nang, om, w, hy, dt, out);
+}
+void run_adj_src(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy,
+                 const double *wang, const double *dJdI, const double *lam_next, double icdt, const double *sig,
+                 const double *tau, double *src) {
+    const int64_t n = (int64_t)nang * G * nx * ny * (dim == 2 ? 4 : 2);
+    hipLaunchKernelGGL(k_adj_src, dim3(nblk(n, 256)), dim3(256), 0, s, dim, nx, ny, G, nang, hx, hy, wang, dJdI,
+                       lam_next, icdt, sig, tau, src);
+}
+void run_adj_tau(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *hx, const double *hy,
+                 const double *sig, const double *dE, const double *ST, const double *D, const double *lam,
+                 const double *tau, double *tau_new, double *part, double *out2) {
+    const int nn = nx * ny * (dim == 2 ? 4 : 2), nb = nblk(nn, 256);
+    hipLaunchKernelGGL(k_adj_tau, dim3(nb), dim3(256), 0, s, dim, nx, ny, G, nang, hx, hy, sig, dE, ST, D, lam, tau,
+                       tau_new, part);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(64), 0, s, nb, part, out2);
+}
+void run_adj_cell(hipStream_t s, int npc, int ncell, int G, int model, double clip_lo, double clip_hi, double dt,
+                  const double *dsig, const double *tau, const double *phi, const double *emis, const double *sig,
+                  const double *cvn, const double *T, const double *Tp, double *gs_cell, double *gcv_node,
+                  double *ST_prev) {
+    hipLaunchKernelGGL(k_adj_cell, dim3(nblk(ncell, 128)), dim3(128), 0, s, npc, ncell, G, model, clip_lo, clip_hi, dt,
+                       dsig, tau, phi, emis, sig, cvn, T, Tp, gs_cell, gcv_node, ST_prev);
+}
+void run_region_sums(hipStream_t s, int nreg, int ncell, int npc, const int *region, const double *gs_cell,
+                     const double *gcv_node, double *grad_s0, double *grad_cv) {
+    hipLaunchKernelGGL(k_region_sums, dim3(nblk(nreg, 64)), dim3(64), 0, s, nreg, ncell, npc, region, gs_cell, gcv_node,
+                       grad_s0, grad_cv);
+}
+void run_dot(hipStream_t s, int64_t n, const double *a, const double *b, double *part256, double *out) {
+    hipLaunchKernelGGL(k_dot_blocks, dim3(256), dim3(256), 0, s, n, a, b, part256);
+    hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(64), 0, s, 256, part256, out);
+}
+void run_add_scalar(hipStream_t s, int64_t n, const double *a, double v, double *out) {
+    hipLaunchKernelGGL(k_add_scalar, dim3(nblk(n, 256)), dim3(256), 0, s, n, a, v, out);
 }
 template <typename real>
 void run_copy_from(hipStream_t s, int64_t n, const real *src, double *dst) {

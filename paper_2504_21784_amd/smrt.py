@@ -96,6 +96,8 @@ _SIGS = {
     "smrt_set_launch": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
     "smrt_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _dp], C.c_int),
     "smrt_adjoint_sweep": ([C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp], C.c_int),
+    "smrt_set_materials": ([C.c_void_p, _dp, _dp], C.c_int),
+    "smrt_adjoint": ([C.c_void_p, C.c_int, C.c_int, C.c_double, _dp, _dp, _dp, _ip], C.c_int),
     "smrt_batch_create": ([C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)], C.c_int),
     "smrt_batch_destroy": ([C.c_void_p], None),
     "smrt_batch_last_error": ([C.c_void_p], C.c_char_p),
@@ -257,6 +259,21 @@ class Context:
         f = _f64(psi_fwd) if psi_fwd is not None else None
         self._check(self.L.smrt_adjoint_sweep(self.h, _p(st), _p(s), _p(e), _p(f), _p(lam), _p(dsig)))
         return (lam, dsig) if want_dsig else lam
+
+    def set_materials(self, sigma0=None, cv=None):
+        s0 = _f64(sigma0) if sigma0 is not None else None
+        c = _f64(cv) if cv is not None else None
+        self._check(self.L.smrt_set_materials(self.h, _p(s0), _p(c)))
+
+    def adjoint(self, n_steps, dt=None):
+        """Runs n_steps from the current state; returns (J, dJ/dlog sigma0, dJ/dlog c_v, adjoint iterations)."""
+        nr = self.p.n_regions
+        J = C.c_double(0.0)
+        gs, gc = np.zeros(nr), np.zeros(nr)
+        it = C.c_int(0)
+        self._check(self.L.smrt_adjoint(self.h, 0, int(n_steps), float(dt if dt is not None else self.p.dt),
+                                        C.byref(J), _p(gs), _p(gc), C.byref(it)))
+        return J.value, gs, gc, it.value
 
     def compute_closures(self, moments, T_l, Estar, Fstar, sig, dt):
         p = self.p

@@ -3,6 +3,14 @@ import sys
 
 import pytest
 
+# Load torch's HIP runtime before the library (the benchmark does the same):
+# both provide libamdhip64.so.7, and the process must use one of them for the
+# library and for torch (the autograd wrapper) alike.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

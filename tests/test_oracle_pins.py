@@ -575,3 +575,41 @@ def test_P11_adjoint_dsig_definition(oracle_mod):
         t = (w[None, :] * lam[:, g, :] * (emis[None, :, g] - I[:, g, :])).sum(0)
         ref[:, g] = t.reshape(p.n_cells, 4).sum(1)
     assert np.abs(dsig - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# P11 (gradient): the oracle's adjoint gradient of the time-integrated
+# right-boundary outflow with respect to log sigma0_r and log c_v,r against
+# central finite differences of the oracle's own forward run (h = 1e-4).
+# ---------------------------------------------------------------------------
+TIGHT = dict(eps_outer=1e-13, eps_inner=1e-13, cg_rtol=1e-14, elim_rtol=1e-15, max_outer=200, max_inner=100,
+             max_cg=500, max_elim=100, scheme=0, lo_time_edge=0)
+
+
+def _adjoint_problem():
+    p = W.multigroup_2d(n=6, G=2, sn=4, region=3, seed=41, n_steps=3, cv_range=(0.5, 2.0))
+    p.T0 = 0.3
+    return p
+
+
+def test_P11_adjoint_gradient_matches_finite_differences(oracle_mod):
+    p = _adjoint_problem()
+    o = oracle_mod.Oracle(p)
+    J, gs, gc, its = o.adjoint_gradient(TIGHT, n_steps=3)
+    assert abs(J - o.leakage(TIGHT, n_steps=3)) <= 1e-14 * abs(J)
+    h = 1e-4
+    fd_s, fd_c = np.zeros_like(gs), np.zeros_like(gc)
+    for r in range(p.n_regions):
+        for arr, fd in ((p.sigma0, fd_s), (p.cv, fd_c)):
+            base = arr.copy()
+            vals = []
+            for sgn in (1, -1):
+                arr[...] = base
+                arr[r] = base[r] * math.exp(sgn * h)
+                vals.append(oracle_mod.Oracle(p).leakage(TIGHT, n_steps=3))
+            arr[...] = base
+            fd[r] = (vals[0] - vals[1]) / (2 * h)
+    scale = max(np.abs(fd_s).max(), np.abs(fd_c).max())
+    assert scale > 0
+    assert np.abs(gs - fd_s).max() <= 1e-5 * scale, (gs, fd_s)
+    assert np.abs(gc - fd_c).max() <= 1e-5 * scale, (gc, fd_c)
