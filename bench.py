@@ -111,6 +111,48 @@ def batched(args):
     return res
 
 
+def adjoint():
+    """Adjoint workload: 128x128, S8, 8 groups, 64 regions (seed 4), 10 steps of
+    dt = 1e-3, FP64: time of the gradient of the time-integrated x+ outflow
+    with respect to the 128 region parameters (forward with checkpoints +
+    reverse), and its agreement with central finite differences (h = 1e-4)
+    on the two largest components of each kind."""
+    import time as _t
+    import numpy as np
+    from paper_2504_21784_amd import smrt, workloads as W
+
+    p = W.adjoint_2d()
+    tight = dict(eps_outer=1e-10, eps_inner=1e-11, cg_rtol=1e-13, elim_rtol=1e-15, max_outer=200, max_inner=60,
+                 max_cg=500, max_elim=100)
+    ctx = smrt.Context(p, precision=smrt.SMRT_FP64, **tight)
+    T0 = p.initial_T_nodes()
+    ctx.set_state(T0)
+    t0 = _t.perf_counter()
+    J, gs, gc, its = ctx.adjoint(p.n_steps)
+    t_adj = _t.perf_counter() - t0
+
+    def J_at(s0, cv):
+        ctx.set_materials(s0, cv)
+        ctx.set_state(T0)
+        return ctx.adjoint(p.n_steps)[0]
+
+    h = 1e-4
+    errs = []
+    for g, which in ((gs, 0), (gc, 1)):
+        for r in np.argsort(-np.abs(g))[:2]:
+            e = np.zeros(p.n_regions)
+            e[r] = h
+            args_p = (p.sigma0 * np.exp(e), p.cv) if which == 0 else (p.sigma0, p.cv * np.exp(e))
+            args_m = (p.sigma0 * np.exp(-e), p.cv) if which == 0 else (p.sigma0, p.cv * np.exp(-e))
+            fd = (J_at(*args_p) - J_at(*args_m)) / (2 * h)
+            errs.append(abs(g[r] - fd) / max(abs(fd), 1e-300))
+    ctx.close()
+    return {"workload": "128x128 bilinear DG, S8, 8 groups, 64 regions of sigma0 and c_v (seed 4), 10 steps "
+                        "dt=1e-3, FP64; J = time-integrated x+ outflow",
+            "J": J, "n_parameters": 2 * p.n_regions, "adjoint_iterations": its, "gradient_s": t_adj,
+            "fd_max_rel_err_top4": max(errs), "fd_h": h}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +162,7 @@ def main():
     ap.add_argument("--waves", type=int, default=0, help="sweep waves per workgroup (0 = automatic)")
     ap.add_argument("--pairs", type=int, default=0, help="(angle,group) pairs per lane (0 = automatic)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-problem batched-sweep measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient measurement")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference point for HBM byte counters)")
     args = ap.parse_args()
@@ -218,6 +261,8 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched(args)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
