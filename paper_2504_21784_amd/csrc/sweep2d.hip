@@ -104,8 +104,12 @@ using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int RSRC_DWORD3 = 0x00020000;   // gfx9-family raw buffer, 32-bit data format
 constexpr int CPOL_SC1 = 16;              // coherent at device scope (trace words)
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint64_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0,
-                                             (int)(bytes < 0xffffffffull ? bytes : 0xffffffffull), RSRC_DWORD3);
+    // base and size are wave-uniform by construction; say so, so the resource
+    // lives in scalar registers (a divergent resource would need a waterfall loop)
+    const uint64_t b = (uint64_t)base;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b), hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    const int n = __builtin_amdgcn_readfirstlane((int)(bytes < 0xffffffffull ? bytes : 0xffffffffull));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), 0, n, RSRC_DWORD3);
 }
 __device__ __forceinline__ void bload(float2 &v, rsrc_t r, uint32_t vo, uint32_t so) {
     v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
@@ -248,6 +252,7 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);   // the same value, known wave-uniform
     const int ch = lane >> 4;
     const int r = lane & 15;
 
@@ -329,7 +334,7 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     const rsrc_t rs_sig = make_rsrc(sig2 + tbase, span * sizeof(r2));
     const rsrc_t rs_q = make_rsrc(qiso + tbase, span * sizeof(r4));
     const rsrc_t rs_inf = make_rsrc(inflow + ((int64_t)d * G + gb0) * A.NB, (uint64_t)CHANNELS * K * A.NB * sizeof(real));
-    const rsrc_t rs_tr = make_rsrc(trace_in + (int64_t)wv * CHANNELS * K * nx * 2 * TW,
+    const rsrc_t rs_tr = make_rsrc(trace_in + (int64_t)wvu * CHANNELS * K * nx * 2 * TW,
                                    (uint64_t)CHANNELS * K * nx * 2 * TW * sizeof(uint64_t));
     uint32_t vo_cell[K];   // lane's cell offset (entries) in a slab: gl * gslab + r
     uint32_t vo_inf[K], vo_tr[K];
@@ -441,17 +446,16 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                     const bool ok = act[k] && col_ok;
                     // y-upwind values: from the lane below (already shifted), the band
                     // below (trace words) or the boundary.
-                    real yin0 = yb[k][0], yin1 = yb[k][1];
-                    if (r == 0 && band == 0) {
-                        yin0 = fx ? S.bot[k][1] : S.bot[k][0];   // canonical node 0 is natural lx = fx
-                        yin1 = fx ? S.bot[k][0] : S.bot[k][1];
-                    } else if (r == 0) {
-                        uint64_t *tw = S.tw[k];
+                    // y-upwind values: the lane below (already shifted) or, in row 0, the
+                    // band below (trace words) or the y- boundary (band 0); branch-free
+                    // except for the rare wait on a trace word that is not yet valid.
+                    uint64_t *tw = S.tw[k];
+                    if (band > 0) {
                         bool ready = true;
 #pragma unroll
                         for (int u2 = 0; u2 < 2 * TW; ++u2) ready &= (uint32_t)(tw[u2] >> 32) == epoch;
-                        const bool wait_here = ok && !ready && !err;
-                        if (__builtin_amdgcn_ballot_w64(wait_here) != 0) {   // rare: trace not yet valid
+                        const bool wait_here = (r == 0) && ok && !ready && !err;
+                        if (__builtin_amdgcn_ballot_w64(wait_here) != 0) {
                             const uint64_t *src = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + (ok ? ic : 0)) * 2 * TW;
                             int spins = 0;
                             bool waiting = wait_here;
@@ -474,11 +478,13 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                                 waiting = !rd;
                             }
                         }
-                        if (ok) {
-                            yin0 = word_value(tw, real(0));
-                            yin1 = word_value(tw + TW, real(0));
-                        }
                     }
+                    const real bv0 = fx ? S.bot[k][1] : S.bot[k][0];   // canonical node 0 is natural lx = fx
+                    const real bv1 = fx ? S.bot[k][0] : S.bot[k][1];
+                    const real e0 = band == 0 ? bv0 : word_value(tw, real(0));
+                    const real e1 = band == 0 ? bv1 : word_value(tw + TW, real(0));
+                    const real yin0 = (r == 0) ? e0 : yb[k][0];
+                    const real yin1 = (r == 0) ? e1 : yb[k][1];
                     const real xin0 = (ic == 0) ? left[k][0] : xl[k][0];
                     const real xin2 = (ic == 0) ? left[k][1] : xl[k][1];
                     const real ps0 = has_prev ? S.psi[k][0] : real(0), ps1 = has_prev ? S.psi[k][1] : real(0);
@@ -545,16 +551,17 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
 #pragma unroll
                 for (int o0 = 0; o0 < BAND_ROWS * PART_PER_CELL; o0 += NW * 64) {
                     const int o = o0 + threadIdx.x;
-                    if (o < BAND_ROWS * PART_PER_CELL) {
+                    // 576 outputs = 9 whole waves: the test is uniform per wave
+                    if (o0 + wvu * 64 < BAND_ROWS * PART_PER_CELL) {
                         const int rr = o & (BAND_ROWS - 1);
                         const int lm = o >> 4;                  // node*9 + moment
                         const int l = lm / NMOM2D, j = lm - l * NMOM2D;
-                        const int icc = t - rr;
                         const real *src = rr_base + l * CB + j * NW * BAND_ROWS + rr;
                         real s = 0;   // fixed order over the waves
 #pragma unroll
                         for (int w2 = 0; w2 < NW; ++w2) s += src[w2 * BAND_ROWS];
-                        if (icc >= 0 && icc < nx && band * BAND_ROWS + rr < ny) part[o] = s;
+                        // cells outside the mesh reduce to exact zeros: no per-lane test
+                        if (t < NT) part[o] = s;
                     }
                 }
             }
