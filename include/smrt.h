@@ -282,11 +282,17 @@ smrt_status smrt_get_info(const smrt_ctx *ctx, smrt_info *info);
  * Returns SMRT_E_INVALID_ARG outside these ranges. */
 smrt_status smrt_set_launch(smrt_ctx *ctx, int waves_per_group, int pairs_per_lane);
 
+/* Sweep occupancy (2D): at most workgroups_per_cu sweep workgroups share a
+ * compute unit (the launch pads its LDS request accordingly); 0 = as many as
+ * the registers allow (default).  Errors: SMRT_E_INVALID_ARG outside [0, 8]. */
+smrt_status smrt_set_occupancy(smrt_ctx *ctx, int workgroups_per_cu);
+
 /* Launch-shape autotuner (2D): on the context's current state with time step
  * dt, times one sweep for every candidate (waves per workgroup, groups per
  * lane) that leaves no workgroup with an idle wave in every direction block,
- * applies the fastest and returns it with its sweep time in ms (any output
- * pointer may be NULL).  The state is not advanced.  Errors:
+ * each at occupancy 0, 1 and 2 workgroups per CU, applies the fastest and
+ * returns its shape with its sweep time in ms (any output pointer may be
+ * NULL).  The state is not advanced.  Errors:
  * SMRT_E_INVALID_ARG before smrt_set_state, for 1D, or for dt <= 0. */
 smrt_status smrt_autotune(smrt_ctx *ctx, double dt, int *waves_per_group, int *pairs_per_lane, double *ms_best);
 
@@ -308,6 +314,8 @@ const char *smrt_batch_last_error(const smrt_batch *batch);
 /* Launch shape shared by the batch (waves in [1, 12]; groups per lane 1, or
  * 2 in FP32 with at most 8 waves). */
 smrt_status smrt_batch_set_launch(smrt_batch *batch, int waves_per_group, int pairs_per_lane);
+/* Occupancy of the batched sweep (as smrt_set_occupancy). */
+smrt_status smrt_batch_set_occupancy(smrt_batch *batch, int workgroups_per_cu);
 /* Total units per batched sweep, workgroup tasks, and the launch shape. */
 smrt_status smrt_batch_info(const smrt_batch *batch, int64_t *units_per_sweep, int *n_tasks, int *waves_per_group,
                             int *pairs_per_lane);

@@ -40,7 +40,7 @@ struct smrt_ctx {
     DevBuf<unsigned char> d_hx, d_hy, d_dirs, d_mu_w;
     // sweep plan
     int NW = 0, K = 1, R = 0, NQC = 0, nbands = 0, NT = 0, n_wg = 0;
-    int user_NW = 0, user_K = 0;
+    int user_NW = 0, user_K = 0, wg_per_cu = 0;
     std::vector<int> qc_quad;
     std::vector<int> slot_pair;   // pairs (d, g)
     ChunkRanges chunks{};         // chunk range of each quadrant
@@ -264,6 +264,7 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
         L.n_tasks = x->n_wg;
         L.NW = x->NW;
         L.K = x->K;
+        L.wg_per_cu = x->wg_per_cu;
         L.lctr = x->d_lctr.p;
         if (x->fp32) launch_sweep2d<float>(L, x->stream);
         else launch_sweep2d<double>(L, x->stream);
@@ -617,6 +618,14 @@ extern "C" smrt_status smrt_set_launch(smrt_ctx *x, int waves_per_group, int pai
         x->user_NW = waves_per_group;
         x->user_K = pairs_per_lane;
         plan_sweep(x);
+    });
+}
+
+extern "C" smrt_status smrt_set_occupancy(smrt_ctx *x, int workgroups_per_cu) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(workgroups_per_cu >= 0 && workgroups_per_cu <= 8, "workgroups per CU must be in [0, 8]");
+        x->wg_per_cu = workgroups_per_cu;
     });
 }
 
@@ -1119,20 +1128,25 @@ extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_grou
         void *pin = x->d_psi[x->cur].p, *pout = x->d_psi[1 - x->cur].p;
         float best = 1e30f;
         int bnw = 0, bk = 0;
+        int bo = 0;
         for (auto [nw, k] : launch_candidates(x->fp32, max_dirs_per_quadrant(x))) {
             SMRT_HIP(hipStreamSynchronize(x->stream));
             x->user_NW = nw;
             x->user_K = k;
             plan_sweep(x);
-            auto once = [&] { run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p, false); };
-            once();   // warm-up
-            const float ms = std::min(timed(x->stream, once), timed(x->stream, once));
-            check_sweep_flag(x);
-            if (ms < best) { best = ms; bnw = nw; bk = k; }
+            for (int occ : {0, 1, 2}) {
+                x->wg_per_cu = occ;
+                auto once = [&] { run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p, false); };
+                once();   // warm-up
+                const float ms = std::min(timed(x->stream, once), timed(x->stream, once));
+                check_sweep_flag(x);
+                if (ms < best) { best = ms; bnw = nw; bk = k; bo = occ; }
+            }
         }
         SMRT_HIP(hipStreamSynchronize(x->stream));
         x->user_NW = bnw;
         x->user_K = bk;
+        x->wg_per_cu = bo;
         plan_sweep(x);
         if (waves_per_group) *waves_per_group = bnw;
         if (pairs_per_lane) *pairs_per_lane = bk;
@@ -1148,7 +1162,7 @@ struct smrt_batch {
     std::vector<smrt_ctx *> P;
     hipStream_t stream = nullptr;   // the batch's own stream (default priority)
     bool fp32 = false;
-    int NW = 0, K = 1;
+    int NW = 0, K = 1, wg_per_cu = 0;
     DevBuf<Sweep2DArgs> d_args;
     DevBuf<int2> d_tasks;
     DevBuf<int> d_lctr;
@@ -1266,6 +1280,7 @@ static void batch_launch(smrt_batch *b) {
     L.n_tasks = b->n_tasks;
     L.NW = b->NW;
     L.K = b->K;
+    L.wg_per_cu = b->wg_per_cu;
     L.lctr = b->d_lctr.p;
     if (b->fp32) launch_sweep2d<float>(L, b->stream);
     else launch_sweep2d<double>(L, b->stream);
@@ -1327,6 +1342,15 @@ extern "C" smrt_status smrt_batch_set_launch(smrt_batch *b, int waves_per_group,
         require(pairs_per_lane == 1 || (pairs_per_lane == 2 && b->fp32 && waves_per_group <= 8),
                 "pairs per lane must be 1, or 2 (FP32, at most 8 waves)");
         batch_plan(b, waves_per_group, pairs_per_lane);
+    });
+}
+
+extern "C" smrt_status smrt_batch_set_occupancy(smrt_batch *b, int workgroups_per_cu) {
+    if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
+    return bguard(b, [&] {
+        require(workgroups_per_cu >= 0 && workgroups_per_cu <= 8, "workgroups per CU must be in [0, 8]");
+        b->drop_graph();
+        b->wg_per_cu = workgroups_per_cu;
     });
 }
 
@@ -1427,18 +1451,23 @@ extern "C" smrt_status smrt_batch_autotune(smrt_batch *b, double dt, int *waves_
         float best = 1e30f;
         int bnw = b->NW, bk = b->K;
         const std::vector<int> all = all_problems(b);
+        int bo = 0;
         for (auto [nw, k] : launch_candidates(b->fp32, maxd)) {
             batch_plan(b, nw, k);
             std::vector<double> icdt;
             batch_tables(b, dt, icdt);
             batch_upload_tasks(b, all);
             batch_upload_args(b, all, icdt);
-            batch_launch(b);   // warm-up
-            const float ms = std::min(timed(b->stream, [&] { batch_launch(b); }), timed(b->stream, [&] { batch_launch(b); }));
-            for (smrt_ctx *x : b->P) check_sweep_flag(x);
-            if (ms < best) { best = ms; bnw = nw; bk = k; }
+            for (int occ : {0, 1, 2}) {
+                b->wg_per_cu = occ;
+                batch_launch(b);   // warm-up
+                const float ms = std::min(timed(b->stream, [&] { batch_launch(b); }), timed(b->stream, [&] { batch_launch(b); }));
+                for (smrt_ctx *x : b->P) check_sweep_flag(x);
+                if (ms < best) { best = ms; bnw = nw; bk = k; bo = occ; }
+            }
         }
         batch_plan(b, bnw, bk);
+        b->wg_per_cu = bo;
         if (waves_per_group) *waves_per_group = bnw;
         if (pairs_per_lane) *pairs_per_lane = bk;
         if (ms_best) *ms_best = best;

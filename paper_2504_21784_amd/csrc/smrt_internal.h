@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,7 @@ constexpr int NMOM2D = 9;           // per node per quadrant: 6 quadrant sums + 
 constexpr int PART_PER_CELL = 4 * NMOM2D;   // partial moments per cell per chunk
 constexpr int SPIN_LIMIT = 1 << 20;          // bounded wait on a band trace
 constexpr int TRACE_LAG = 8;                 // columns a band stays behind the band below
+constexpr int LDS_PER_CU = 160 * 1024;       // gfx950 LDS per compute unit (bytes)
 constexpr int MAX_SWEEP_WAVES = 12;         // sweep workgroups: at most 12 waves (one direction each)
 
 #define SMRT_HIP(call)                                                                   \
@@ -67,6 +69,7 @@ struct SweepLaunch {
     const int2 *tasks;               // [n_tasks]
     int n_tasks;
     int NW, K;                       // launch shape shared by every problem
+    int wg_per_cu;                   // 0: as many as fit; n: pad LDS so at most n workgroups share a CU
     int *lctr;                       // [2]: ticket, tasks done (reset by the last workgroup)
 };
 

@@ -591,11 +591,14 @@ template <typename real, int K, int NW, bool BATCH>
 static void launch_knwb(const SweepLaunch &L, hipStream_t s) {
     constexpr int PF = sizeof(real) == 4 ? (K == 1 ? 4 : 2) : 1;
     constexpr int CB = red_node_block(NW);
-    const size_t lds = (size_t)2 * 4 * CB * sizeof(real);
+    // LDS: the reduction buffer, or more when the launch asks for fewer
+    // workgroups per CU (a workgroup alone on a CU runs each step faster)
+    size_t lds = (size_t)2 * 4 * CB * sizeof(real);
+    if (L.wg_per_cu > 0) lds = std::max(lds, (size_t)(LDS_PER_CU / L.wg_per_cu - 1024));
     static bool lds_attr_set = false;   // once per instantiation (so a launch can be graph-captured)
     if (!lds_attr_set) {
         SMRT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep2d_kernel<real, K, PF, NW, BATCH>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, LDS_PER_CU - 1024));
         lds_attr_set = true;
     }
     hipLaunchKernelGGL((sweep2d_kernel<real, K, PF, NW, BATCH>), dim3(L.n_tasks), dim3(NW * 64), lds, s, L);

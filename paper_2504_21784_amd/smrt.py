@@ -95,6 +95,8 @@ _SIGS = {
     "smrt_get_moments": ([C.c_void_p, _dp], C.c_int),
     "smrt_set_launch": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
     "smrt_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _dp], C.c_int),
+    "smrt_set_occupancy": ([C.c_void_p, C.c_int], C.c_int),
+    "smrt_batch_set_occupancy": ([C.c_void_p, C.c_int], C.c_int),
     "smrt_adjoint_sweep": ([C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp], C.c_int),
     "smrt_set_materials": ([C.c_void_p, _dp, _dp], C.c_int),
     "smrt_adjoint": ([C.c_void_p, C.c_int, C.c_int, C.c_double, _dp, _dp, _dp, _ip], C.c_int),
@@ -215,6 +217,9 @@ class Context:
     def set_boundary(self, problem=None):
         self.bc = self._bc(problem or self.p)
         self._check(self.L.smrt_set_boundary(self.h, C.byref(self.bc)))
+
+    def set_occupancy(self, workgroups_per_cu=0):
+        self._check(self.L.smrt_set_occupancy(self.h, int(workgroups_per_cu)))
 
     def set_launch(self, waves_per_group=0, pairs_per_lane=0):
         self._check(self.L.smrt_set_launch(self.h, waves_per_group, pairs_per_lane))
@@ -352,6 +357,9 @@ class Batch:
 
     def set_launch(self, waves_per_group, pairs_per_lane=1):
         self._check(self.L.smrt_batch_set_launch(self.h, int(waves_per_group), int(pairs_per_lane)))
+
+    def set_occupancy(self, workgroups_per_cu=0):
+        self._check(self.L.smrt_batch_set_occupancy(self.h, int(workgroups_per_cu)))
 
     def autotune(self, dt):
         nw, k, ms = C.c_int(0), C.c_int(0), C.c_double(0.0)
