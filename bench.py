@@ -29,17 +29,22 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep2d_fp32_256x256_S8_G16_hb
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2504_21784_amd", "csrc", f) for f in ("sweep2d.hip", "smrt_internal.h")]
 
 
-def measured_traffic():
+def measured_traffic(info):
     """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when the sweep source has changed since those counters."""
+    summary, or None when the sweep source or the launch shape differs from the
+    one those counters were taken on."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
         h = hashlib.sha256(b"".join(open(f, "rb").read() for f in SWEEP_SOURCES)).hexdigest()
     except OSError:
         return None
-    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+    vals = dict(l.split(": ", 1) for l in text.splitlines()
+                if l.startswith(("traffic_bytes_per_launch:", "source_sha256:", "launch:")))
     if vals.get("source_sha256", "").strip() != h:
+        return None
+    shape = f"waves_per_group={info['waves_per_group']} pairs_per_lane={info['pairs_per_lane']}"
+    if vals.get("launch", "").strip() != shape:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -255,7 +260,7 @@ def main():
         "fp32_vs_fp64_sweep_speedup": k64 / k_ms,
         "fp32_phi_rel_l2_vs_fp64": phi_err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(info),
                      "kernel": sweep_kernel,
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
