@@ -17,6 +17,8 @@
 // cumulative R(x) = P(x) - 15/(4 pi^4) x^4/(e^x - 1) (integration by parts
 // of x^4 e^x/(e^x-1)^2).  b_g = P(x_{g+1}) - P(x_g), r_g likewise, with the
 // first lower bound at 0 and the last upper bound at infinity.
+#include <type_traits>
+
 #include "smrt_internal.h"
 #include "tables.h"
 
@@ -24,10 +26,30 @@ namespace smrt {
 
 __constant__ double c_bern[NBERN];   // B_{2k} / ((2k)! (2k+3)), k = 1..NBERN
 
-__device__ double planck_cum(double x) {
+// 1/k for the exponential series (no division in the loop)
+struct InvTable {
+    double v[201];
+    constexpr InvTable() : v() {
+        for (int k = 1; k <= 200; ++k) v[k] = 1.0 / k;
+    }
+};
+__constant__ InvTable c_inv = InvTable();
+
+// Cumulative normalised Planck and Rosseland spectra at x = nu/T, from one
+// evaluation of the Planck integral:
+//   P(x) = 15/pi^4 int_0^x t^3/(e^t-1) dt,
+//   R(x) = 15/(4 pi^4) int_0^x t^4 e^t/(e^t-1)^2 dt = P(x) - 15/(4 pi^4) x^4 e^{-x}/(1-e^{-x})
+// (integration by parts).  P by the Bernoulli series for x < 2 and by the
+// exponential series sum_k e^{-kx} (x^3/k + 3x^2/k^2 + 6x/k^3 + 6/k^4) above.
+struct PR {
+    double P, R;
+};
+__device__ PR planck_rosseland_cum(double x) {
     constexpr double c15 = 15.0 / (M_PI * M_PI * M_PI * M_PI);
-    if (!(x > 0.0)) return 0.0;
-    if (x >= 1e300) return 1.0;
+    constexpr double c15_4 = 15.0 / (4.0 * M_PI * M_PI * M_PI * M_PI);
+    if (!(x > 0.0)) return {0.0, 0.0};
+    if (x >= 1e300) return {1.0, 1.0};
+    double P, e, em;
     if (x < 2.0) {
         // int_0^x t^3/(e^t-1) dt = x^3/3 - x^4/8 + sum_k B_2k x^(2k+3) / ((2k)! (2k+3))
         const double x2 = x * x, x3 = x2 * x;
@@ -36,28 +58,27 @@ __device__ double planck_cum(double x) {
             s += c_bern[k] * p;
             p *= x2;
         }
-        return c15 * (x3 / 3.0 - x3 * x / 8.0 + s);
+        P = c15 * (x3 / 3.0 - x3 * x / 8.0 + s);
+        e = exp(-x);
+        em = -expm1(-x);
+    } else {
+        double s = 0.0;
+        e = exp(-x);
+        em = 1.0 - e;
+        const double x2 = x * x, x3 = x2 * x;
+        double ek = e;
+        for (int k = 1; k <= 200; ++k) {
+            const double ik = c_inv.v[k];
+            const double term = ek * (ik * (x3 + ik * (3.0 * x2 + ik * (6.0 * x + 6.0 * ik))));
+            s += term;
+            if (term < 1e-18 * s) break;
+            ek *= e;
+            if (ek == 0.0) break;
+        }
+        P = 1.0 - c15 * s;
     }
-    double s = 0.0;
-    const double e = exp(-x);
-    double ek = e;
-    for (int k = 1; k <= 200; ++k) {
-        const double ik = 1.0 / k;
-        const double term = ek * (x * x * x * ik + 3.0 * x * x * ik * ik + 6.0 * x * ik * ik * ik + 6.0 * ik * ik * ik * ik);
-        s += term;
-        if (term < 1e-18 * s) break;
-        ek *= e;
-        if (ek == 0.0) break;
-    }
-    return 1.0 - c15 * s;
-}
-
-__device__ double rosseland_cum(double x) {
-    constexpr double c15_4 = 15.0 / (4.0 * M_PI * M_PI * M_PI * M_PI);
-    if (!(x > 0.0)) return 0.0;
-    if (x >= 1e300 || x > 700.0) return 1.0;
-    const double em = -expm1(-x);                  // 1 - e^{-x}
-    return planck_cum(x) - c15_4 * x * x * x * x * exp(-x) / em;
+    const double R = x > 700.0 ? 1.0 : P - c15_4 * x * x * x * x * e / em;
+    return {P, R};
 }
 
 // group fractions at temperature T for all G groups
@@ -71,9 +92,9 @@ __device__ void group_fractions(int G, const double *nu, double T, double *b, do
     for (int g = 0; g < G; ++g) {
         double Pu = 1.0, Ru = 1.0;
         if (g < G - 1) {
-            const double x = nu[g + 1] / T;
-            Pu = planck_cum(x);
-            Ru = rosseland_cum(x);
+            const PR pr = planck_rosseland_cum(nu[g + 1] / T);
+            Pu = pr.P;
+            Ru = pr.R;
         }
         b[g] = Pu - Pl;
         r[g] = Ru - Rl;
@@ -171,16 +192,20 @@ __global__ void k_stab2d(int nx, int ny, int G, const double *sig, const double 
     const int q = (int)(i / cs);
     int cell, flip;
     const bool on = skew_to_cell(nx, ny, q, slot, cell, flip);
+    using r2 = typename std::conditional<sizeof(real) == 4, float2, double2>::type;
+    r2 *out = reinterpret_cast<r2 *>(stab);
     for (int g = 0; g < G; ++g) {
         const int64_t o = ((int64_t)q * G + g) * cs + slot;
+        r2 v;
         if (!on) {
-            stab[2 * o] = real(1);
-            stab[2 * o + 1] = real(0);
-            continue;
+            v.x = real(1);
+            v.y = real(0);
+        } else {
+            const double sg = sig[(int64_t)cell * G + g];
+            v.x = (real)(sigt ? sigt[(int64_t)cell * G + g] : sg + icdt);
+            v.y = (real)sg;
         }
-        const double sg = sig[(int64_t)cell * G + g];
-        stab[2 * o] = (real)(sigt ? sigt[(int64_t)cell * G + g] : sg + icdt);
-        stab[2 * o + 1] = (real)sg;
+        out[o] = v;
     }
 }
 
@@ -196,16 +221,23 @@ __global__ void k_qtab2d(int nx, int ny, int G, const double *q, int64_t sn, int
     const int qd = (int)(i / cs);
     int cell, flip;
     const bool on = skew_to_cell(nx, ny, qd, slot, cell, flip);
+    using r4 = typename std::conditional<sizeof(real) == 4, float4, double4>::type;
+    r4 *out = reinterpret_cast<r4 *>(qtab);
     for (int g = 0; g < G; ++g) {
         const int64_t o = ((int64_t)qd * G + g) * cs + slot;
+        r4 w;
         if (!on) {
-            for (int lc = 0; lc < 4; ++lc) qtab[4 * o + lc] = real(0);
-            continue;
+            w.x = w.y = w.z = w.w = real(0);
+        } else {
+            const double *src = q + (int64_t)g * sg + (int64_t)4 * cell * sn;
+            double v[4];
+            for (int l = 0; l < 4; ++l) v[l] = src[l * sn];
+            w.x = (real)v[0 ^ flip];
+            w.y = (real)v[1 ^ flip];
+            w.z = (real)v[2 ^ flip];
+            w.w = (real)v[3 ^ flip];
         }
-        const double *src = q + (int64_t)g * sg + (int64_t)4 * cell * sn;
-        double v[4];
-        for (int l = 0; l < 4; ++l) v[l] = src[l * sn];
-        for (int lc = 0; lc < 4; ++lc) qtab[4 * o + lc] = (real)v[lc ^ flip];
+        out[o] = w;
     }
 }
 
@@ -553,6 +585,7 @@ __global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkR
     double acc[NMOM2D];
 #pragma unroll
     for (int k = 0; k < NMOM2D; ++k) acc[k] = 0.0;
+#pragma unroll 4
     for (int qc = cr.start[q]; qc < cr.start[q + 1]; ++qc) {
         const real *p = part + (((int64_t)qc * nb + band) * NT + t) * PB + lc * NMOM2D * BAND_ROWS + rc;
 #pragma unroll
