@@ -116,6 +116,29 @@ def batched(args):
     return res
 
 
+def time_steps(p, T0, n=3):
+    """Full backward-Euler steps (Algorithm 1: consistent SM, FP32 sweep, FP64
+    LO, the paper's tolerances 1e-3) on the benchmark workload: wall time per
+    step and the iteration counts."""
+    import time as _t
+    import numpy as np
+    from paper_2504_21784_amd import smrt
+
+    ctx = smrt.Context(p, precision=smrt.SMRT_FP32)
+    ctx.set_state(T0)
+    ctx.step(p.dt)   # warm-up step
+    t0 = _t.perf_counter()
+    stats = [ctx.step(p.dt) for _ in range(n)]
+    wall = (_t.perf_counter() - t0) / n
+    ctx.close()
+    return {"workload": "same 256x256 S8 G16 workload, consistent SM, FP32 sweep + FP64 LO, eps 1e-3",
+            "ms_per_step": 1e3 * wall,
+            "outer_per_step": float(np.mean([s["outer"] for s in stats])),
+            "inner_per_step": float(np.mean([s["inner_total"] for s in stats])),
+            "cg_per_step": float(np.mean([s["cg_total"] for s in stats])),
+            "sweep_ms_per_step": float(np.mean([s["t_sweep_ms"] for s in stats]))}
+
+
 def adjoint():
     """Adjoint workload: 128x128, S8, 8 groups, 64 regions (seed 4), 10 steps of
     dt = 1e-3, FP64: time of the gradient of the time-integrated x+ outflow
@@ -168,6 +191,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=0, help="(angle,group) pairs per lane (0 = automatic)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-problem batched-sweep measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient measurement")
+    ap.add_argument("--no-step", action="store_true", help="skip the full time-step measurement")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference point for HBM byte counters)")
     args = ap.parse_args()
@@ -264,6 +288,8 @@ def main():
                      "kernel": sweep_kernel,
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if not args.no_step:
+        out["time_step"] = time_steps(p, T0)
     if not args.no_batch:
         out["batched"] = batched(args)
     if not args.no_adjoint:

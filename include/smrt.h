@@ -126,6 +126,8 @@ typedef struct {
     int strict;
     int fixed_outer;
     int lo_time_edge;   /* 0: E*, F* = HO sums of I^k (default); 1: LO solution */
+    int lo_graphs;      /* 1 (default): the LO conjugate-gradient iterations replay a captured HIP
+                           graph of 4 iterations; 0: launched one kernel at a time */
 } smrt_options;
 
 /* Per-step statistics (the columns of the paper's summary tables). */

@@ -333,6 +333,7 @@ static ClosureArgs closure_args(smrt_ctx *x, int scheme, double dt, const double
 }
 
 static LoInputs lo_inputs(smrt_ctx *x, double dt, const double *clos) {
+    x->lo.use_graphs = x->opt.lo_graphs != 0;
     LoInputs in{};
     in.dt = dt; in.eps_inner = x->opt.eps_inner; in.cg_rtol = x->opt.cg_rtol; in.elim_rtol = x->opt.elim_rtol;
     in.max_inner = x->opt.max_inner; in.max_cg = x->opt.max_cg; in.max_elim = x->opt.max_elim;
@@ -355,6 +356,7 @@ extern "C" void smrt_default_options(smrt_options *o) {
     if (!o) return;
     std::memset(o, 0, sizeof *o);
     o->eps_outer = 1e-3; o->eps_inner = 1e-3; o->cg_rtol = 1e-10; o->elim_rtol = 1e-10;
+    o->lo_graphs = 1;
     o->max_outer = 100; o->max_inner = 30; o->max_cg = 50; o->max_elim = 40;
     o->precision = SMRT_FP64; o->scheme = SMRT_SM_CONSISTENT;
 }
@@ -383,6 +385,7 @@ static void validate_options(const smrt_options *o) {
     require(o->max_outer > 0 && o->max_inner > 0 && o->max_cg > 0 && o->max_elim > 0, "iteration caps must be > 0");
     require(o->scheme >= 0 && o->scheme <= 2, "unknown scheme");
     require(o->precision == SMRT_FP64 || o->precision == SMRT_FP32, "unknown precision");
+    require(o->lo_graphs == 0 || o->lo_graphs == 1, "lo_graphs must be 0 or 1");
 }
 
 extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_desc *quad, const smrt_groups_desc *groups,

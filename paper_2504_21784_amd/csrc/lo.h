@@ -99,6 +99,15 @@ struct LoSolver {
     DevCsr dD, dDT, dP;
     DevBuf<double> wn, MFinv, DqF, jbase, diagE, rhs, Minv, r, z, p, Ap, Eold, Told, tmpF, part, sc;
     DevBuf<int> flags;
+    // captured HIP graph of a block of CG iterations (kernels only), per (stream, x)
+    hipGraph_t cg_graph = nullptr;
+    hipGraphExec_t cg_exec = nullptr;
+    hipStream_t cg_stream = nullptr;
+    const double *cg_x = nullptr;
+    bool use_graphs = true, graph_failed = false;
+    ~LoSolver();
+    void drop_graph();
+    void cg_block(hipStream_t s, double *x, int iters);
     void init(int dim, int nx, int ny, const std::vector<double> &xe, const std::vector<double> &ye,
               const double alpha[2], double c, double a);
     double dot(hipStream_t s, const double *x, const double *y, const double *cdiff, int slot, bool accumulate);

@@ -391,10 +391,14 @@ __global__ void k_dot_finish(const double *part, double *out, int slot, int accu
 }
 
 // CG vector updates with device-side scalars: sc[0]=rz, sc[1]=pAp, sc[2]=rr, sc[3]=rz_new
+// CG scalar slots: 0 rz, 1 pAp, 2 rr, 3 rz_new, 4 |b|^2, 8 stop flag (1: converged,
+// 2: iteration cap), 9 iterations done, 10 tolerance on rr, 11 iteration cap.
+// Once the stop flag is set the update kernels leave x, r, z, p unchanged, so
+// the host checks convergence only every few iterations.
 __global__ void k_cg_xr(int n, const double *sc, const double *p, const double *Ap, double *x, double *r,
                         const double *Minv, double *z) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || sc[8] != 0.0) return;
     const double al = sc[0] / sc[1];
     x[i] += al * p[i];
     r[i] -= al * Ap[i];
@@ -402,7 +406,7 @@ __global__ void k_cg_xr(int n, const double *sc, const double *p, const double *
 }
 __global__ void k_cg_p(int n, const double *sc, const double *z, double *p) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || sc[8] != 0.0) return;
     p[i] = z[i] + (sc[3] / sc[0]) * p[i];
 }
 __global__ void k_cg_init(int n, const double *b, const double *Ax, double *r, const double *Minv, double *z, double *p) {
@@ -412,7 +416,19 @@ __global__ void k_cg_init(int n, const double *b, const double *Ax, double *r, c
     z[i] = Minv[i] * r[i];
     p[i] = z[i];
 }
-__global__ void k_shift(double *sc) { sc[0] = sc[3]; }
+__global__ void k_cg_step_end(double *sc) {
+    if (sc[8] != 0.0) return;
+    sc[0] = sc[3];
+    sc[9] += 1.0;
+    if (sc[2] <= sc[10]) sc[8] = 1.0;
+    else if (sc[9] >= sc[11]) sc[8] = 2.0;
+}
+__global__ void k_cg_start(double *sc, double tol2, int maxit) {
+    sc[8] = 0.0;
+    sc[9] = 0.0;
+    sc[10] = tol2;
+    sc[11] = (double)maxit;
+}
 
 // F = MFinv (qF + (c/3) D^T E)  (qF rows [a][n], F node-major [n][a])
 __global__ void k_backsub(int nn, int dim, double c3, const int *rp, const int *col, const double *val, const double *E,
@@ -481,7 +497,7 @@ void LoSolver::init(int dim_, int nx, int ny, const std::vector<double> &xe, con
     for (auto *v : {&MFinv, &DqF, &jbase, &diagE, &rhs, &Minv, &r, &z, &p, &Ap, &Eold, &Told}) v->alloc(nn);
     tmpF.alloc((int64_t)nn * dim);
     part.alloc(RED_BLOCKS);
-    sc.alloc(8);
+    sc.alloc(12);
     flags.alloc(4);
 }
 
@@ -514,20 +530,63 @@ int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
     double bb = fetch(s, 4);
     const double tol2 = rtol * rtol * (bb > 0 ? bb : 1.0);
     double rr = fetch(s, 2);
-    int it = 0;
-    while (it < maxit && rr > tol2) {
+    if (!(rr > tol2) || maxit <= 0) return 0;
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1), 0, s, sc.p, tol2, maxit);
+    constexpr int CHECK = 4;   // iterations queued between host checks
+    if (use_graphs && !graph_failed && (cg_exec == nullptr || cg_stream != s || cg_x != x)) {
+        // record CHECK iterations once (kernels only) and replay them; streams
+        // that cannot capture fall back to direct launches
+        drop_graph();
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            cg_block(s, x, CHECK);
+            hipGraph_t g = nullptr;
+            if (hipStreamEndCapture(s, &g) == hipSuccess && g &&
+                hipGraphInstantiate(&cg_exec, g, nullptr, nullptr, 0) == hipSuccess) {
+                cg_graph = g;
+                cg_stream = s;
+                cg_x = x;
+            } else {
+                if (g) (void)hipGraphDestroy(g);
+                cg_exec = nullptr;
+                graph_failed = true;
+            }
+        } else {
+            (void)hipGetLastError();
+            graph_failed = true;
+        }
+    }
+    for (;;) {
+        if (use_graphs && cg_exec) SMRT_HIP(hipGraphLaunch(cg_exec, s));
+        else cg_block(s, x, CHECK);
+        double st[2];
+        SMRT_HIP(hipMemcpyAsync(st, sc.p + 8, sizeof(st), hipMemcpyDeviceToHost, s));
+        SMRT_HIP(hipStreamSynchronize(s));
+        if (st[0] != 0.0) return (int)st[1];
+    }
+}
+
+void LoSolver::cg_block(hipStream_t s, double *x, int iters) {
+    for (int k = 0; k < iters; ++k) {
         schur(s, p.p, Ap.p);
         dot(s, p.p, Ap.p, nullptr, 1, false);
         hipLaunchKernelGGL(k_cg_xr, dim3(nb(nn)), dim3(256), 0, s, nn, sc.p, p.p, Ap.p, x, r.p, Minv.p, z.p);
         dot(s, r.p, z.p, nullptr, 3, false);
-        hipLaunchKernelGGL(k_cg_p, dim3(nb(nn)), dim3(256), 0, s, nn, sc.p, z.p, p.p);
-        hipLaunchKernelGGL(k_shift, dim3(1), dim3(1), 0, s, sc.p);
         dot(s, r.p, nullptr, nullptr, 2, false);
-        rr = fetch(s, 2);
-        ++it;
+        hipLaunchKernelGGL(k_cg_p, dim3(nb(nn)), dim3(256), 0, s, nn, sc.p, z.p, p.p);
+        hipLaunchKernelGGL(k_cg_step_end, dim3(1), dim3(1), 0, s, sc.p);
     }
-    return it;
 }
+
+void LoSolver::drop_graph() {
+    if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
+    if (cg_graph) (void)hipGraphDestroy(cg_graph);
+    cg_exec = nullptr;
+    cg_graph = nullptr;
+    cg_stream = nullptr;
+    cg_x = nullptr;
+}
+
+LoSolver::~LoSolver() { drop_graph(); }
 
 smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double *F, double *T, smrt_step_stats *st,
                             std::string &err) {

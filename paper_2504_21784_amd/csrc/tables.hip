@@ -585,7 +585,6 @@ __global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkR
     double acc[NMOM2D];
 #pragma unroll
     for (int k = 0; k < NMOM2D; ++k) acc[k] = 0.0;
-#pragma unroll 4
     for (int qc = cr.start[q]; qc < cr.start[q + 1]; ++qc) {
         const real *p = part + (((int64_t)qc * nb + band) * NT + t) * PB + lc * NMOM2D * BAND_ROWS + rc;
 #pragma unroll
