@@ -362,6 +362,95 @@ __global__ void k_schur_rows(int nn, const int *drp, const int *dcol, const doub
     y[n] = s + diagE[n] * x[n];
 }
 
+// S x fused with the block partials of x . (S x) (one partial per 256-row block)
+__global__ void __launch_bounds__(256) k_schur_rows_dot(int nn, const int *drp, const int *dcol, const double *dval,
+                                                        const int *prp, const int *pcol, const double *pval,
+                                                        const double *tmpF, const double *x, const double *diagE,
+                                                        double *y, double *part) {
+    __shared__ double sh[256];
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (n < nn) {
+        double s = 0.0;
+        for (int k = drp[n]; k < drp[n + 1]; ++k) s += dval[k] * tmpF[dcol[k]];
+        for (int k = prp[n]; k < prp[n + 1]; ++k) s += pval[k] * x[pcol[k]];
+        s += diagE[n] * x[n];
+        y[n] = s;
+        v = x[n] * s;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// CG scalar slots: 0 rz, 1 pAp, 2 rr, 3 rz_new, 4 |b|^2, 8 stop flag (1: converged,
+// 2: iteration cap), 9 iterations done, 10 tolerance on rr, 11 iteration cap.
+// Once the stop flag is set the update kernels leave x, r, z, p unchanged, so
+// the host checks convergence only every few iterations.
+// CG update x += al p, r -= al Ap, z = M^-1 r fused with the block partials of r.z and r.r
+__global__ void __launch_bounds__(256) k_cg_xr_dot(int n, const double *sc, const double *p, const double *Ap,
+                                                   double *x, double *r, const double *Minv, double *z, double *part) {
+    __shared__ double sh[2][256];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const bool frozen = sc[8] != 0.0;
+    double rz = 0.0, rr = 0.0;
+    if (i < n) {
+        double ri = r[i];
+        if (!frozen) {
+            const double al = sc[0] / sc[1];
+            x[i] += al * p[i];
+            ri -= al * Ap[i];
+            r[i] = ri;
+            z[i] = Minv[i] * ri;
+        }
+        rz = ri * z[i];
+        rr = ri * ri;
+    }
+    sh[0][threadIdx.x] = rz;
+    sh[1][threadIdx.x] = rr;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0];
+        part[2 * blockIdx.x + 1] = sh[1][0];
+    }
+}
+
+// fixed-order sums of nb block partials with the given stride into up to two scalar slots
+__global__ void __launch_bounds__(256) k_partials_finish(int nb, int stride, const double *part, double *sc, int slot0,
+                                                         int slot1) {
+    __shared__ double sh[2][256];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nb; k += 256) {
+        a += part[stride * k];
+        if (slot1 >= 0) b += part[stride * k + 1];
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sc[slot0] = sh[0][0];
+        if (slot1 >= 0) sc[slot1] = sh[1][0];
+    }
+}
+
 // deterministic block reduction of sum_i a_i b_i (b == nullptr: sum a_i^2 of (a - c))
 constexpr int RED_BLOCKS = 256, RED_THREADS = 256;
 __global__ void k_dot_partial(int n, const double *a, const double *b, const double *cdiff, double *part) {
@@ -391,19 +480,6 @@ __global__ void k_dot_finish(const double *part, double *out, int slot, int accu
 }
 
 // CG vector updates with device-side scalars: sc[0]=rz, sc[1]=pAp, sc[2]=rr, sc[3]=rz_new
-// CG scalar slots: 0 rz, 1 pAp, 2 rr, 3 rz_new, 4 |b|^2, 8 stop flag (1: converged,
-// 2: iteration cap), 9 iterations done, 10 tolerance on rr, 11 iteration cap.
-// Once the stop flag is set the update kernels leave x, r, z, p unchanged, so
-// the host checks convergence only every few iterations.
-__global__ void k_cg_xr(int n, const double *sc, const double *p, const double *Ap, double *x, double *r,
-                        const double *Minv, double *z) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || sc[8] != 0.0) return;
-    const double al = sc[0] / sc[1];
-    x[i] += al * p[i];
-    r[i] -= al * Ap[i];
-    z[i] = Minv[i] * r[i];
-}
 __global__ void k_cg_p(int n, const double *sc, const double *z, double *p) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || sc[8] != 0.0) return;
@@ -498,6 +574,7 @@ void LoSolver::init(int dim_, int nx, int ny, const std::vector<double> &xe, con
     tmpF.alloc((int64_t)nn * dim);
     part.alloc(RED_BLOCKS);
     sc.alloc(12);
+    bpart.alloc(2 * (int64_t)((nn + 255) / 256));
     flags.alloc(4);
 }
 
@@ -565,14 +642,19 @@ int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
     }
 }
 
+// One CG iteration = 7 launches: D^T p, S p with p.Sp partials, pAp, the x/r/z
+// update with r.z and r.r partials, (rz, rr), the new direction, the scalars.
 void LoSolver::cg_block(hipStream_t s, double *x, int iters) {
+    const int nbk = nb(nn);
     for (int k = 0; k < iters; ++k) {
-        schur(s, p.p, Ap.p);
-        dot(s, p.p, Ap.p, nullptr, 1, false);
-        hipLaunchKernelGGL(k_cg_xr, dim3(nb(nn)), dim3(256), 0, s, nn, sc.p, p.p, Ap.p, x, r.p, Minv.p, z.p);
-        dot(s, r.p, z.p, nullptr, 3, false);
-        dot(s, r.p, nullptr, nullptr, 2, false);
-        hipLaunchKernelGGL(k_cg_p, dim3(nb(nn)), dim3(256), 0, s, nn, sc.p, z.p, p.p);
+        hipLaunchKernelGGL(k_dt_scaled, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn * dim, dim, c / 3.0, dDT.rp,
+                           dDT.col, dDT.val, p.p, MFinv.p, tmpF.p);
+        hipLaunchKernelGGL(k_schur_rows_dot, dim3(nbk), dim3(256), 0, s, nn, dD.rp, dD.col, dD.val, dP.rp, dP.col,
+                           dP.val, tmpF.p, p.p, diagE.p, Ap.p, bpart.p);
+        hipLaunchKernelGGL(k_partials_finish, dim3(1), dim3(256), 0, s, nbk, 1, bpart.p, sc.p, 1, -1);
+        hipLaunchKernelGGL(k_cg_xr_dot, dim3(nbk), dim3(256), 0, s, nn, sc.p, p.p, Ap.p, x, r.p, Minv.p, z.p, bpart.p);
+        hipLaunchKernelGGL(k_partials_finish, dim3(1), dim3(256), 0, s, nbk, 2, bpart.p, sc.p, 3, 2);
+        hipLaunchKernelGGL(k_cg_p, dim3(nbk), dim3(256), 0, s, nn, sc.p, z.p, p.p);
         hipLaunchKernelGGL(k_cg_step_end, dim3(1), dim3(1), 0, s, sc.p);
     }
 }
