@@ -50,7 +50,7 @@ struct smrt_ctx {
     DevBuf<uint64_t> d_trace;
     int cur = 0;
     // FP64 state and work arrays
-    DevBuf<double> d_qnat;   // q_iso [G][node] FP64 (2D: gathered into the skewed tables)
+    DevBuf<double> d_qnat;   // q_iso [G][node] at the sweep precision (2D: gathered into the skewed tables)
     DevBuf<double> d_sigq;   // per-quadrant sigma-weighted moments [4][3][node] (2D finalisation)
     DevBuf<double> d_T, d_E, d_F, d_Eho, d_Fho, d_mom, d_sig, d_sigP, d_sigF, d_clos, d_Tl, d_El, d_Tn, d_En, d_Tstar,
         d_Estar, d_Fstar, d_sigEho;
@@ -181,8 +181,9 @@ static void plan_sweep(smrt_ctx *x) {
     x->nbands = (x->ny + BAND_ROWS - 1) / BAND_ROWS;
     x->NT = x->nx + BAND_ROWS - 1;
     // a sweep wave addresses its 4K group slabs through 32-bit byte offsets
-    require((int64_t)CHANNELS * K * x->nbands * x->NT * BAND_ROWS * 4 * x->rs < (int64_t(1) << 32),
-            "mesh too large for the sweep's 32-bit per-wave offsets");
+    // below 2^31 (offsets from 2^31 up mark lanes with no work)
+    require((int64_t)CHANNELS * K * x->nbands * x->NT * BAND_ROWS * 4 * x->rs < (int64_t(1) << 31),
+            "mesh too large for the sweep's 31-bit per-wave offsets");
     x->qc_quad.clear();
     x->slot_pair.clear();
     const int GB = 4 * K;
@@ -719,7 +720,7 @@ static void raw_sweep(smrt_ctx *x, const double *sig_t, const double *sig, const
         using real = decltype(zero);
         if (x->dim == 2) {
             run_stab2d<real>(x->stream, x->nx, x->ny, x->G, sig, sig_t, 0.0, (real *)t_sig2.p);
-            run_qtab2d<real>(x->stream, x->nx, x->ny, x->G, q, x->G, 1, (real *)t_qiso.p);
+            run_qtab2d<real, double>(x->stream, x->nx, x->ny, x->G, q, x->G, 1, (real *)t_qiso.p);
         } else {
             run_sig_to_internal<real>(x->stream, x->ncell, x->G, sig_t, sig, (real *)t_sig2.p);
             run_qiso_to_internal<real>(x->stream, x->nn, x->G, x->npc, q, (real *)t_qiso.p);
@@ -888,11 +889,11 @@ static double prepare_step_tables(smrt_ctx *x, double dt) {
 static void run_source_at(smrt_ctx *x, const double *T) {
     const bool d2 = x->dim == 2;
     if (x->fp32) {
-        run_source<float>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (float *)x->d_qiso.p, d2 ? x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p);
-        if (d2) run_qtab2d<float>(x->stream, x->nx, x->ny, x->G, x->d_qnat.p, 1, x->nn, (float *)x->d_qiso.p);
+        run_source<float>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (float *)x->d_qiso.p, d2 ? (float *)x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p);
+        if (d2) run_qtab2d<float, float>(x->stream, x->nx, x->ny, x->G, (const float *)x->d_qnat.p, 1, x->nn, (float *)x->d_qiso.p);
     } else {
         run_source<double>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (double *)x->d_qiso.p, d2 ? x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p);
-        if (d2) run_qtab2d<double>(x->stream, x->nx, x->ny, x->G, x->d_qnat.p, 1, x->nn, (double *)x->d_qiso.p);
+        if (d2) run_qtab2d<double, double>(x->stream, x->nx, x->ny, x->G, x->d_qnat.p, 1, x->nn, (double *)x->d_qiso.p);
     }
 }
 

@@ -64,14 +64,6 @@ __device__ __forceinline__ uint64_t pack_word(uint32_t epoch, uint32_t bits) {
     return ((uint64_t)epoch << 32) | bits;
 }
 
-__device__ __forceinline__ void put_trace(uint64_t *p, float v, uint32_t ep) {
-    __hip_atomic_store(p, pack_word(ep, __float_as_uint(v)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void put_trace(uint64_t *p, double v, uint32_t ep) {
-    uint64_t b = __double_as_longlong(v);
-    __hip_atomic_store(p, pack_word(ep, (uint32_t)b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(p + 1, pack_word(ep, (uint32_t)(b >> 32)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ uint64_t poll_word(const uint64_t *p) {
     return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -98,11 +90,16 @@ __device__ __forceinline__ double shift_up_one_row<double>(double v) {
 
 // Buffer-resource access: a wave-uniform base (SGPRs) + a per-lane 32-bit
 // byte offset fixed for the whole band + a wave-uniform per-step byte offset,
-// so a step's loads and stores need no per-lane address arithmetic.  Every
-// access stays inside the resource (the kernel never relies on range checks).
+// so a step's loads and stores need no per-lane address arithmetic.  A lane
+// with no work (a slot past the group or direction count, a row past the
+// mesh) gets the per-lane offset OOB, at or past every resource's size: the
+// hardware's range check for raw buffers then returns zeros to its loads and
+// drops its stores, so the step needs no per-lane masking.  Every other
+// access stays inside its resource.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int RSRC_DWORD3 = 0x00020000;   // gfx9-family raw buffer, 32-bit data format
 constexpr int CPOL_SC1 = 16;              // coherent at device scope (trace words)
+constexpr uint32_t OOB = 0x80000000u;     // resources are smaller than 2^31 bytes (checked by the host)
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint64_t bytes) {
     // base and size are wave-uniform by construction; say so, so the resource
     // lives in scalar registers (a divergent resource would need a waterfall loop)
@@ -135,6 +132,20 @@ __device__ __forceinline__ void bstore(const double4 &v, rsrc_t r, uint32_t vo, 
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, make_double2(v.z, v.w)), r, vo, so + 16, 0);
 }
 // trace words (device-coherent loads; the bounded spin path re-polls atomically)
+// A trace word holds (epoch, value bits) and is written with one 64-bit
+// device-coherent store, the form a relaxed device-scope atomic store takes.
+__device__ __forceinline__ void bstore_word(uint64_t w, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, w), r, vo,
+                                          so, CPOL_SC1);
+}
+__device__ __forceinline__ void put_trace_words(float v, uint32_t ep, rsrc_t r, uint32_t vo, uint32_t so) {
+    bstore_word(pack_word(ep, __float_as_uint(v)), r, vo, so);
+}
+__device__ __forceinline__ void put_trace_words(double v, uint32_t ep, rsrc_t r, uint32_t vo, uint32_t so) {
+    const uint64_t b = __double_as_longlong(v);
+    bstore_word(pack_word(ep, (uint32_t)b), r, vo, so);
+    bstore_word(pack_word(ep, (uint32_t)(b >> 32)), r, vo, so + 8);
+}
 __device__ __forceinline__ void bload_words(uint64_t *w, int n, rsrc_t r, uint32_t vo, uint32_t so) {
     if (n == 2) {
         const auto a = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, CPOL_SC1);
@@ -327,22 +338,28 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     const int64_t pbase = (((int64_t)d * G + gb0) * nbands + band) * NT * BAND_ROWS;
     const int64_t tbase = ((int64_t)quad * G + gb0) * gslab + (int64_t)band * NT * BAND_ROWS;
     const uint64_t span = (uint64_t)CHANNELS * K * gslab;           // cells covered from a base
-    // psi_prev may be absent (raw sweep without a time-edge source): loads then
-    // read psi_out (valid memory) and the values are discarded at use.
-    const rsrc_t rs_prev = make_rsrc((has_prev ? pprev : pout) + pbase, span * sizeof(r4));
+    // psi_prev may be absent (raw sweep without a time-edge source): an empty
+    // resource then makes every load of it return zeros.
+    const rsrc_t rs_prev = make_rsrc((has_prev ? pprev : pout) + pbase, has_prev ? span * sizeof(r4) : 0);
     const rsrc_t rs_out = make_rsrc(pout + pbase, span * sizeof(r4));
     const rsrc_t rs_sig = make_rsrc(sig2 + tbase, span * sizeof(r2));
     const rsrc_t rs_q = make_rsrc(qiso + tbase, span * sizeof(r4));
     const rsrc_t rs_inf = make_rsrc(inflow + ((int64_t)d * G + gb0) * A.NB, (uint64_t)CHANNELS * K * A.NB * sizeof(real));
-    const rsrc_t rs_tr = make_rsrc(trace_in + (int64_t)wvu * CHANNELS * K * nx * 2 * TW,
-                                   (uint64_t)CHANNELS * K * nx * 2 * TW * sizeof(uint64_t));
-    uint32_t vo_cell[K];   // lane's cell offset (entries) in a slab: gl * gslab + r
-    uint32_t vo_inf[K], vo_tr[K];
+    const uint64_t wave_trace_bytes = (uint64_t)CHANNELS * K * nx * 2 * TW * sizeof(uint64_t);
+    const rsrc_t rs_tr = make_rsrc(trace_in + (int64_t)wvu * CHANNELS * K * nx * 2 * TW, wave_trace_bytes);
+    const rsrc_t rs_tw = make_rsrc(trace_out + (int64_t)wvu * CHANNELS * K * nx * 2 * TW, wave_trace_bytes);
+    // lane byte offsets, OOB for a lane with no work (see make_rsrc)
+    uint32_t vo4[K], vo2[K];   // cell gl * gslab + r in the 4-value and 2-value slabs
+    uint32_t vo_inf[K], vo_tr[K], vo_tw[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        vo_cell[k] = (uint32_t)(gl[k] * gslab + r);
-        vo_inf[k] = (uint32_t)((gl[k] * A.NB + yside) * sizeof(real));
-        vo_tr[k] = (uint32_t)((ch * K + k) * nx * 2 * TW * sizeof(uint64_t));
+        const uint32_t cell = (uint32_t)(gl[k] * gslab + r);
+        const uint32_t slot_words = (uint32_t)((ch * K + k) * nx * 2 * TW * sizeof(uint64_t));
+        vo4[k] = act[k] ? cell * (uint32_t)sizeof(r4) : OOB;
+        vo2[k] = act[k] ? cell * (uint32_t)sizeof(r2) : OOB;
+        vo_inf[k] = act[k] ? (uint32_t)((gl[k] * A.NB + yside) * sizeof(real)) : OOB;
+        vo_tr[k] = act[k] ? slot_words : OOB;
+        vo_tw[k] = act[k] && produce ? slot_words : OOB;
     }
 
     // All prefetch loads are issued unconditionally (always in bounds) into raw
@@ -363,14 +380,14 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             r2 sv;
-            bload(sv, rs_sig, vo_cell[k] * (uint32_t)sizeof(r2), (uint32_t)(tt * BAND_ROWS * sizeof(r2)));
+            bload(sv, rs_sig, vo2[k], (uint32_t)(tt * BAND_ROWS * sizeof(r2)));
             S.st[k] = sv.x;
             S.sg[k] = sv.y;
             r4 qn;
-            bload(qn, rs_q, vo_cell[k] * (uint32_t)sizeof(r4), (uint32_t)(tt * BAND_ROWS * sizeof(r4)));
+            bload(qn, rs_q, vo4[k], (uint32_t)(tt * BAND_ROWS * sizeof(r4)));
             S.qn[k][0] = qn.x; S.qn[k][1] = qn.y; S.qn[k][2] = qn.z; S.qn[k][3] = qn.w;
             r4 p;
-            bload(p, rs_prev, vo_cell[k] * (uint32_t)sizeof(r4), (uint32_t)(tt * BAND_ROWS * sizeof(r4)));
+            bload(p, rs_prev, vo4[k], (uint32_t)(tt * BAND_ROWS * sizeof(r4)));
             S.psi[k][0] = p.x; S.psi[k][1] = p.y; S.psi[k][2] = p.z; S.psi[k][3] = p.w;
             // y- boundary inflow at row 0's column (used by band 0, row 0 only)
             bload_pair(S.bot[k][0], S.bot[k][1], rs_inf, vo_inf[k], (uint32_t)(2 * in0 * sizeof(real)));
@@ -386,8 +403,8 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
         const int64_t ib = ((int64_t)d * G + gb0 + gl[k]) * A.NB;
         const int ly0 = fy ? 1 : 0;
         const int jv = row_ok ? jn : 0;
-        left[k][0] = inflow[ib + xside + 2 * jv + ly0];
-        left[k][1] = inflow[ib + xside + 2 * jv + (1 - ly0)];
+        left[k][0] = act[k] ? inflow[ib + xside + 2 * jv + ly0] : real(0);
+        left[k][1] = act[k] ? inflow[ib + xside + 2 * jv + (1 - ly0)] : real(0);
     }
     StepIn<real, K> buf[PF + 1];
 #pragma unroll
@@ -424,6 +441,10 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     }
 
     real *part_base = static_cast<real *>(A.part) + ((int64_t)qc * nbands + band) * NT * (BAND_ROWS * PART_PER_CELL);
+    // rows 0 of active slots: the lanes that read the band below's trace
+    uint64_t row0_mask[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) row0_mask[k] = __builtin_amdgcn_ballot_w64(r == 0 && act[k]);
     // The step loop runs in whole groups of PF+1 steps with no per-step
     // condition (a conditional step or prefetch would merge register values
     // and force a wait on every outstanding load); padding steps t >= NT have
@@ -435,7 +456,6 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
             {
                 StepIn<real, K> &S = buf[u];
                 const int ic = t - r;
-                const bool col_ok = ic >= 0 && ic < nx;
                 const real hx = (r == 0) ? S.hx0 : hx_sh;
                 const real wgt = hx * hy * real(0.25);
                 const real a = am * hy * real(0.5);
@@ -443,22 +463,20 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                 real sumI[4], sumS[4];   // sum_k I, sum_k sigma I
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const bool ok = act[k] && col_ok;
-                    // y-upwind values: from the lane below (already shifted), the band
-                    // below (trace words) or the boundary.
                     // y-upwind values: the lane below (already shifted) or, in row 0, the
                     // band below (trace words) or the y- boundary (band 0); branch-free
                     // except for the rare wait on a trace word that is not yet valid.
                     uint64_t *tw = S.tw[k];
-                    if (band > 0) {
+                    // row 0 has a column at this step exactly when t < nx (ic = t)
+                    if (band > 0 && t < nx) {
                         bool ready = true;
 #pragma unroll
                         for (int u2 = 0; u2 < 2 * TW; ++u2) ready &= (uint32_t)(tw[u2] >> 32) == epoch;
-                        const bool wait_here = (r == 0) && ok && !ready && !err;
-                        if (__builtin_amdgcn_ballot_w64(wait_here) != 0) {
-                            const uint64_t *src = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + (ok ? ic : 0)) * 2 * TW;
+                        const uint64_t need = __builtin_amdgcn_ballot_w64(!ready) & row0_mask[k];
+                        if (need != 0) {
+                            const uint64_t *src = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + t) * 2 * TW;
                             int spins = 0;
-                            bool waiting = wait_here;
+                            bool waiting = ((need >> lane) & 1) && !err;
                             while (waiting) {
                                 // bounded wait; a timed-out wave raises ctr[3] and every other
                                 // waiter gives up at once
@@ -487,8 +505,7 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                     const real yin1 = (r == 0) ? e1 : yb[k][1];
                     const real xin0 = (ic == 0) ? left[k][0] : xl[k][0];
                     const real xin2 = (ic == 0) ? left[k][1] : xl[k][1];
-                    const real ps0 = has_prev ? S.psi[k][0] : real(0), ps1 = has_prev ? S.psi[k][1] : real(0);
-                    const real ps2 = has_prev ? S.psi[k][2] : real(0), ps3 = has_prev ? S.psi[k][3] : real(0);
+                    const real ps0 = S.psi[k][0], ps1 = S.psi[k][1], ps2 = S.psi[k][2], ps3 = S.psi[k][3];
                     real rh0 = wgt * (S.qn[k][0] + icdt * ps0) + a * xin0 + b * yin0;
                     real rh1 = wgt * (S.qn[k][1] + icdt * ps1) + b * yin1;
                     real rh2 = wgt * (S.qn[k][2] + icdt * ps2) + a * xin2;
@@ -507,18 +524,22 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                     const real I1 = ai * y1 - bi * y2;
                     const real I2 = ai * y2 - bi * y1;
                     const real I3 = ai * y3 + bi * y0;
-                    if (ok) {
+                    // A cell outside the mesh (ic < 0 or ic >= nx, or a row past ny)
+                    // is a padding slot of the skewed layout: its store lands
+                    // there and its moments are never read, so neither needs a
+                    // per-lane test.  Padding steps (t >= NT) store nothing.
+                    if (t < NT) {
                         r4 o;
                         o.x = I0; o.y = I1; o.z = I2; o.w = I3;
-                        bstore(o, rs_out, vo_cell[k] * (uint32_t)sizeof(r4), (uint32_t)(t * BAND_ROWS * sizeof(r4)));
-                        if (produce) {
-                            uint64_t *dst = trace_out + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + ic) * 2 * TW;
-                            put_trace(dst, I2, epoch);
-                            put_trace(dst + TW, I3, epoch);
-                        }
+                        bstore(o, rs_out, vo4[k], (uint32_t)(t * BAND_ROWS * sizeof(r4)));
                     }
-                    const real i0 = ok ? I0 : real(0), i1 = ok ? I1 : real(0);
-                    const real i2 = ok ? I2 : real(0), i3 = ok ? I3 : real(0);
+                    // the top row publishes its column ic = t - 15 while it lies in the mesh
+                    if (t >= BAND_ROWS - 1 && t < NT) {
+                        const uint32_t so = (uint32_t)((t - (BAND_ROWS - 1)) * 2 * TW * sizeof(uint64_t));
+                        put_trace_words(I2, epoch, rs_tw, vo_tw[k], so);
+                        put_trace_words(I3, epoch, rs_tw, vo_tw[k], so + TW * (uint32_t)sizeof(uint64_t));
+                    }
+                    const real i0 = I0, i1 = I1, i2 = I2, i3 = I3;
                     const real sg = S.sg[k];
                     if (k == 0) {
                         sumI[0] = i0; sumI[1] = i1; sumI[2] = i2; sumI[3] = i3;

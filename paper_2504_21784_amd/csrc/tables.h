@@ -13,11 +13,11 @@ void run_opacity(hipStream_t s, int ncell, int npc, int G, const double *T, cons
                  const double *sigma0, double lo, double hi, const double *nu, double icdt, double *sig, real *sig2);
 template <typename real>
 void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const double *nu, double a, double c,
-                const double *sig, real *qiso, double *qnat, double *sigP, double *sigF);
+                const double *sig, real *qiso, real *qnat, double *sigP, double *sigF);
 template <typename real>
 void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab);
-template <typename real>
-void run_qtab2d(hipStream_t s, int nx, int ny, int G, const double *q, int64_t sn, int64_t sg, real *qtab);
+template <typename real, typename src_t>
+void run_qtab2d(hipStream_t s, int nx, int ny, int G, const src_t *q, int64_t sn, int64_t sg, real *qtab);
 void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
                      double *psi);
 void run_side_inflow(hipStream_t s, int nsides, int G, const double *nu, double a, double c, const int *kind,

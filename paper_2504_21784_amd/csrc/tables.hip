@@ -81,27 +81,29 @@ __device__ PR planck_rosseland_cum(double x) {
     return {P, R};
 }
 
-// group fractions at temperature T for all G groups
-__device__ void group_fractions(int G, const double *nu, double T, double *b, double *r) {
-    if (G == 1) {
-        b[0] = 1.0;
-        r[0] = 1.0;
-        return;
-    }
-    double Pl = 0.0, Rl = 0.0;
-    for (int g = 0; g < G; ++g) {
+// Group fractions at temperature T, produced one group at a time in group
+// order (no per-thread arrays, which would live in scratch memory):
+// b_g = P(x_{g+1}) - P(x_g), r_g likewise, with x_0 = 0 and x_G = infinity
+// (so a single group gets b = r = 1).
+struct GroupFractions {
+    const double *nu;
+    double T, Pl = 0.0, Rl = 0.0;
+    int G, g = 0;
+    __device__ GroupFractions(int G_, const double *nu_, double T_) : nu(nu_), T(T_), G(G_) {}
+    __device__ void next(double &b, double &r) {
         double Pu = 1.0, Ru = 1.0;
         if (g < G - 1) {
             const PR pr = planck_rosseland_cum(nu[g + 1] / T);
             Pu = pr.P;
             Ru = pr.R;
         }
-        b[g] = Pu - Pl;
-        r[g] = Ru - Rl;
+        b = Pu - Pl;
+        r = Ru - Rl;
         Pl = Pu;
         Rl = Ru;
+        ++g;
     }
-}
+};
 
 // ---------------------------------------------------------------------------
 // Opacity table (once per step)
@@ -138,24 +140,25 @@ __global__ void k_opacity(int ncell, int npc, int G, const double *T, const int 
 // ---------------------------------------------------------------------------
 template <typename real>
 __global__ void k_source(int nn, int npc, int G, const double *T, const double *nu, double a, double c,
-                         const double *sig, real *qiso, double *qnat, double *sigP, double *sigF) {
+                         const double *sig, real *qiso, real *qnat, double *sigP, double *sigF) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
-    double b[MAXG], r[MAXG];
     const double Tn = T[n];
-    group_fractions(G, nu, Tn, b, r);
+    GroupFractions fr(G, nu, Tn);
     const int cell = n / npc, l = n - cell * npc;
     const int ncell = nn / npc;
     const double B = a * c * Tn * Tn * Tn * Tn / (4.0 * M_PI);
     double sb = 0, sbs = 0, sr = 0, srs = 0;
     for (int g = 0; g < G; ++g) {
+        double bg, rg;
+        fr.next(bg, rg);
         const double s = sig[(int64_t)cell * G + g];
-        if (qiso) qiso[((int64_t)g * ncell + cell) * npc + l] = (real)(s * B * b[g]);
-        if (qnat) qnat[(int64_t)g * nn + n] = s * B * b[g];
-        sb += b[g];
-        sbs += b[g] * s;
-        sr += r[g];
-        srs += r[g] * s;
+        if (qiso) qiso[((int64_t)g * ncell + cell) * npc + l] = (real)(s * B * bg);
+        if (qnat) qnat[(int64_t)g * nn + n] = (real)(s * B * bg);
+        sb += bg;
+        sbs += bg * s;
+        sr += rg;
+        srs += rg * s;
     }
     sigP[n] = sbs / sb;
     sigF[n] = srs / sr;
@@ -181,63 +184,89 @@ __device__ inline bool skew_to_cell(int nx, int ny, int q, int64_t slot, int &ce
 
 // (sigma_t, sigma) per (quadrant, group, skewed cell) from sigma [cell][G]
 // (and sigma_t if given).  One thread per (quadrant, skewed slot) walks the
-// groups: its reads are the cell's contiguous [G] row, its writes for each
-// group are coalesced across the slots.
+// groups in blocks of GB, issuing a block's gathers before its stores; its
+// writes for each group are coalesced across the slots.  A padding slot
+// reads cell 0 and stores (1, 0).
+constexpr int TAB_GB = 4;
 template <typename real>
-__global__ void k_stab2d(int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab) {
+__global__ void k_stab2d(int nx, int ny, int G, const double *__restrict__ sig, const double *__restrict__ sigt,
+                         double icdt, real *__restrict__ stab) {
     const int64_t cs = cell_slab(nx, ny);
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= 4 * cs) return;
     const int64_t slot = i % cs;
     const int q = (int)(i / cs);
-    int cell, flip;
+    int cell = 0, flip;
     const bool on = skew_to_cell(nx, ny, q, slot, cell, flip);
+    if (!on) cell = 0;
     using r2 = typename std::conditional<sizeof(real) == 4, float2, double2>::type;
-    r2 *out = reinterpret_cast<r2 *>(stab);
-    for (int g = 0; g < G; ++g) {
-        const int64_t o = ((int64_t)q * G + g) * cs + slot;
-        r2 v;
-        if (!on) {
-            v.x = real(1);
-            v.y = real(0);
-        } else {
-            const double sg = sig[(int64_t)cell * G + g];
-            v.x = (real)(sigt ? sigt[(int64_t)cell * G + g] : sg + icdt);
-            v.y = (real)sg;
+    r2 *__restrict__ out = reinterpret_cast<r2 *>(stab);
+    const double *__restrict__ st_src = sigt ? sigt : sig;   // sigma_t given, or sigma + 1/(c dt)
+    const double add = sigt ? 0.0 : icdt;
+    const double *row = sig + (int64_t)cell * G, *strow = st_src + (int64_t)cell * G;
+    for (int g0 = 0; g0 < G; g0 += TAB_GB) {
+        double sg[TAB_GB], st[TAB_GB];
+#pragma unroll
+        for (int k = 0; k < TAB_GB; ++k) {
+            const int g = g0 + k < G ? g0 + k : G - 1;
+            sg[k] = row[g];
+            st[k] = strow[g];
         }
-        out[o] = v;
+#pragma unroll
+        for (int k = 0; k < TAB_GB; ++k) {
+            if (g0 + k < G) {   // uniform across the grid
+                r2 v;
+                v.x = on ? (real)(st[k] + add) : real(1);
+                v.y = on ? (real)sg[k] : real(0);
+                out[((int64_t)q * G + g0 + k) * cs + slot] = v;
+            }
+        }
     }
 }
 
 // Emission table in the skewed per-quadrant layout (canonical node order) from
-// a natural-order FP64 field q[n * sn + g * sg]; one thread per (quadrant,
-// skewed slot) walks the groups.
-template <typename real>
-__global__ void k_qtab2d(int nx, int ny, int G, const double *q, int64_t sn, int64_t sg, real *qtab) {
+// a natural-order field q[n * sn + g * sg] (FP64, or already at the sweep
+// precision); one thread per (quadrant, skewed slot) walks the groups in
+// blocks of TAB_GB (gathers first, then stores).  A padding slot stores zeros.
+template <typename real, typename src_t>
+__global__ void k_qtab2d(int nx, int ny, int G, const src_t *__restrict__ q, int64_t sn, int64_t sg,
+                         real *__restrict__ qtab) {
     const int64_t cs = cell_slab(nx, ny);
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= 4 * cs) return;
     const int64_t slot = i % cs;
     const int qd = (int)(i / cs);
-    int cell, flip;
+    int cell = 0, flip = 0;
     const bool on = skew_to_cell(nx, ny, qd, slot, cell, flip);
+    if (!on) cell = 0;
     using r4 = typename std::conditional<sizeof(real) == 4, float4, double4>::type;
-    r4 *out = reinterpret_cast<r4 *>(qtab);
-    for (int g = 0; g < G; ++g) {
-        const int64_t o = ((int64_t)qd * G + g) * cs + slot;
-        r4 w;
-        if (!on) {
-            w.x = w.y = w.z = w.w = real(0);
-        } else {
-            const double *src = q + (int64_t)g * sg + (int64_t)4 * cell * sn;
-            double v[4];
-            for (int l = 0; l < 4; ++l) v[l] = src[l * sn];
-            w.x = (real)v[0 ^ flip];
-            w.y = (real)v[1 ^ flip];
-            w.z = (real)v[2 ^ flip];
-            w.w = (real)v[3 ^ flip];
+    r4 *__restrict__ out = reinterpret_cast<r4 *>(qtab);
+    const src_t *base = q + (int64_t)4 * cell * sn;
+    for (int g0 = 0; g0 < G; g0 += TAB_GB) {
+        src_t v[TAB_GB][4];
+        using s4 = typename std::conditional<sizeof(src_t) == 4, float4, double4>::type;
+#pragma unroll
+        for (int k = 0; k < TAB_GB; ++k) {
+            const int g = g0 + k < G ? g0 + k : G - 1;
+            if (sn == 1) {   // a cell's 4 nodes are contiguous (and 4-value aligned)
+                const s4 t4 = *reinterpret_cast<const s4 *>(base + (int64_t)g * sg);
+                v[k][0] = t4.x; v[k][1] = t4.y; v[k][2] = t4.z; v[k][3] = t4.w;
+            } else {
+#pragma unroll
+                for (int l = 0; l < 4; ++l) v[k][l] = base[(int64_t)g * sg + l * sn];
+            }
         }
-        out[o] = w;
+#pragma unroll
+        for (int k = 0; k < TAB_GB; ++k) {
+            if (g0 + k < G) {   // uniform across the grid
+                r4 w;
+                w.x = on ? (real)v[k][0 ^ flip] : real(0);
+                w.y = on ? (real)v[k][1 ^ flip] : real(0);
+                w.z = on ? (real)v[k][2 ^ flip] : real(0);
+                w.w = on ? (real)v[k][3 ^ flip] : real(0);
+                out[((int64_t)qd * G + g0 + k) * cs + slot] = w;
+            }
+        }
     }
 }
 
@@ -247,11 +276,13 @@ __global__ void k_equilibrium(int nn, int G, int nang, const double *T, const do
                               double *psi) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
-    double b[MAXG], r[MAXG];
-    group_fractions(G, nu, T[n], b, r);
+    GroupFractions fr(G, nu, T[n]);
     const double B = a * c * pow(T[n], 4) / (4.0 * M_PI);
-    for (int d = 0; d < nang; ++d)
-        for (int g = 0; g < G; ++g) psi[((int64_t)d * G + g) * nn + n] = B * b[g];
+    for (int g = 0; g < G; ++g) {
+        double bg, rg;
+        fr.next(bg, rg);
+        for (int d = 0; d < nang; ++d) psi[((int64_t)d * G + g) * nn + n] = B * bg;
+    }
 }
 
 // Side values of the isotropic inflow: val[side][g]
@@ -259,12 +290,15 @@ __global__ void k_side_inflow(int G, const double *nu, double a, double c, const
                               const double *explicit_g, double *val) {
     const int side = blockIdx.x;
     if (threadIdx.x != 0) return;
-    double b[MAXG], r[MAXG];
     for (int g = 0; g < G; ++g) val[side * G + g] = 0.0;
     if (kind[side] == 1 && Tb[side] > 0.0) {
-        group_fractions(G, nu, Tb[side], b, r);
+        GroupFractions fr(G, nu, Tb[side]);
         const double B = a * c * pow(Tb[side], 4) / (4.0 * M_PI);
-        for (int g = 0; g < G; ++g) val[side * G + g] = B * b[g];
+        for (int g = 0; g < G; ++g) {
+            double bg, rg;
+            fr.next(bg, rg);
+            val[side * G + g] = B * bg;
+        }
     } else if (kind[side] == 2) {
         for (int g = 0; g < G; ++g) val[side * G + g] = explicit_g[side * G + g];
     }
@@ -393,13 +427,14 @@ __global__ void k_adj_prep(int nn, int npc, int G, int nang, const double *nu, d
                            double *emis, double *dE, double *D, double *phi) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
-    double b[MAXG], r[MAXG];
     const double Tn = T[n];
-    group_fractions(G, nu, Tn, b, r);
+    GroupFractions fr(G, nu, Tn);
     const double T3 = Tn * Tn * Tn, T4 = T3 * Tn;
     double dsum = cvn[n] / dt;
     for (int g = 0; g < G; ++g) {
-        const double e = a * c * T4 * b[g] / (4.0 * M_PI), de = 4.0 * a * c * T3 * r[g] / (4.0 * M_PI);
+        double bg, rg;
+        fr.next(bg, rg);
+        const double e = a * c * T4 * bg / (4.0 * M_PI), de = 4.0 * a * c * T3 * rg / (4.0 * M_PI);
         emis[(int64_t)n * G + g] = e;
         dE[(int64_t)n * G + g] = de;
         dsum += sig[(int64_t)(n / npc) * G + g] * 4.0 * M_PI * de;
@@ -715,7 +750,7 @@ void run_opacity(hipStream_t s, int ncell, int npc, int G, const double *T, cons
 }
 template <typename real>
 void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const double *nu, double a, double c,
-                const double *sig, real *qiso, double *qnat, double *sigP, double *sigF) {
+                const double *sig, real *qiso, real *qnat, double *sigP, double *sigF) {
     hipLaunchKernelGGL(k_source<real>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, npc, G, T, nu, a, c, sig, qiso, qnat, sigP, sigF);
 }
 template <typename real>
@@ -723,10 +758,10 @@ void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const d
     const int64_t n = 4 * cell_slab(nx, ny);
     hipLaunchKernelGGL(k_stab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, sig, sigt, icdt, stab);
 }
-template <typename real>
-void run_qtab2d(hipStream_t s, int nx, int ny, int G, const double *q, int64_t sn, int64_t sg, real *qtab) {
+template <typename real, typename src_t>
+void run_qtab2d(hipStream_t s, int nx, int ny, int G, const src_t *q, int64_t sn, int64_t sg, real *qtab) {
     const int64_t n = 4 * cell_slab(nx, ny);
-    hipLaunchKernelGGL(k_qtab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, q, sn, sg, qtab);
+    hipLaunchKernelGGL((k_qtab2d<real, src_t>), dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, q, sn, sg, qtab);
 }
 void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
                      double *psi) {
@@ -850,10 +885,10 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
     template void run_opacity<real>(hipStream_t, int, int, int, const double *, const int *, int, const double *,  \
                                     double, double, const double *, double, double *, real *);                      \
     template void run_source<real>(hipStream_t, int, int, int, const double *, const double *, double, double,      \
-                                   const double *, real *, double *, double *, double *);                           \
+                                   const double *, real *, real *, double *, double *);                             \
     template void run_fill_inflow<real>(hipStream_t, int, int, int, int, int, const double *, real *);              \
     template void run_stab2d<real>(hipStream_t, int, int, int, const double *, const double *, double, real *);     \
-    template void run_qtab2d<real>(hipStream_t, int, int, int, const double *, int64_t, int64_t, real *);          \
+    template void run_qtab2d<real, double>(hipStream_t, int, int, int, const double *, int64_t, int64_t, real *);  \
     template void run_copy_to<real>(hipStream_t, int64_t, const double *, real *);                                  \
     template void run_copy_from<real>(hipStream_t, int64_t, const real *, double *);                                \
     template void run_qiso_to_internal<real>(hipStream_t, int, int, int, const double *, real *);                   \
@@ -865,6 +900,7 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
     template void launch_sweep1d<real>(const Sweep1DArgs &, hipStream_t);                                           \
     template void run_moments1d<real>(hipStream_t, int, int, int, const real *, const double *, const real *, double *);
 INST(float)
+template void run_qtab2d<float, float>(hipStream_t, int, int, int, const float *, int64_t, int64_t, float *);
 INST(double)
 
 }  // namespace smrt

@@ -93,6 +93,24 @@ def test_sweep2d_inactive_slots_large(smrt_mod, oracle_mod):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5)])
+def test_sweep2d_without_time_edge_source(smrt_mod, oracle_mod, prec, tol):
+    """No psi_prev (the raw-sweep form the adjoint uses): the time-edge term
+    drops out, including on lanes with no (angle, group) pair (G = 3)."""
+    p = _prob2d(27, 21, 4, 3, seed=12)
+    sigt, q, pp, inf = W.random_sweep_inputs(p, seed=13)
+    sig = 0.7 * sigt
+    o = oracle_mod.Oracle(p)
+    ref = o.sweep(sigt, q, np.zeros_like(pp), 0.9, inf)
+    ref_mom = o.moments(sig, ref)
+    ctx = smrt_mod.Context(p, precision=prec)
+    psi, mom = ctx.sweep(sigt, sig, q, None, 0.9, inf)
+    assert _rel(psi, ref) < tol
+    for m in range(27):
+        assert _rel(mom[m], ref_mom[m]) < tol, m
+    ctx.close()
+
+
 def test_sweep2d_launch_shapes_agree_fp64(smrt_mod, oracle_mod):
     p = _prob2d(45, 40, 8, 3, seed=1)
     sigt, q, pp, inf = W.random_sweep_inputs(p, seed=9)
