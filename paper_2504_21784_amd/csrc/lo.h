@@ -97,7 +97,7 @@ struct LoSolver {
     int dim = 0, nn = 0;
     double c = 1, a = 1;
     DevCsr dD, dDT, dP;
-    DevBuf<double> wn, MFinv, DqF, jbase, diagE, rhs, Minv, r, z, p, Ap, Eold, Told, tmpF, part, sc, bpart;
+    DevBuf<double> wn, MFinv, DqF, jbase, diagE, rhs, Minv, r, z, p, Ap, Eold, Told, tmpF, part, sc, bpart, apart;
     DevBuf<int> flags;
     // captured HIP graph of a block of CG iterations (kernels only), per (stream, x)
     hipGraph_t cg_graph = nullptr;

@@ -325,10 +325,12 @@ __global__ void k_jacobi_base(int nn, int dim, double c3, const int *drp, const 
 __global__ void k_newton_prep(int nn, double a, double c, double dt, const double *wn, const double *cvn,
                               const double *T0, const double *Tstar, const double *sigE, const double *sigP,
                               const double *qE, const double *DqF, const double *jbase, double *diagE, double *rhs,
-                              double *Minv) {
+                              double *Minv, const double *E, double *Eold, double *Told) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
     const double w = wn[n], t = T0[n];
+    Told[n] = t;      // the iterate this Newton step starts from (for the stopping test)
+    Eold[n] = E[n];
     const double dB = w * 4.0 * sigP[n] * a * c * t * t * t;
     const double dBt = w * cvn[n] / dt + dB;
     const double B0 = w * sigP[n] * a * c * t * t * t * t;
@@ -387,21 +389,51 @@ __global__ void __launch_bounds__(256) k_schur_rows_dot(int nn, const int *drp, 
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// CG scalar slots: 0 rz, 1 pAp, 2 rr, 3 rz_new, 4 |b|^2, 8 stop flag (1: converged,
-// 2: iteration cap), 9 iterations done, 10 tolerance on rr, 11 iteration cap.
+// Fixed-order sum of nb block partials (stride apart; a second sequence at +1
+// when two) by a 256-thread block: thread k sums k, k+256, .., then a tree.
+// Every block that calls it on the same partials gets the same bits.
+__device__ void block_sum_partials(int nb, int stride, bool two, const double *part, double (*sh)[256], double &a,
+                                   double &b) {
+    double x = 0.0, y = 0.0;
+    for (int k = threadIdx.x; k < nb; k += 256) {
+        x += part[stride * k];
+        if (two) y += part[stride * k + 1];
+    }
+    sh[0][threadIdx.x] = x;
+    sh[1][threadIdx.x] = y;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    a = sh[0][0];
+    b = sh[1][0];
+    __syncthreads();   // sh may be reused by the caller
+}
+
+// CG scalar slots: 0 rz, 2 rr, 3 rz_new, 4 |b|^2, 8 stop flag (1: converged,
+// 2: iteration cap, 3: converged or capped before the first iteration),
+// 9 iterations done, 10 tolerance on rr, 11 iteration cap.
 // Once the stop flag is set the update kernels leave x, r, z, p unchanged, so
 // the host checks convergence only every few iterations.
-// CG update x += al p, r -= al Ap, z = M^-1 r fused with the block partials of r.z and r.r
-__global__ void __launch_bounds__(256) k_cg_xr_dot(int n, const double *sc, const double *p, const double *Ap,
-                                                   double *x, double *r, const double *Minv, double *z, double *part) {
+// CG update x += al p, r -= al Ap, z = M^-1 r (al = rz / pAp, pAp summed here from
+// the block partials apart of p.Ap) fused with the block partials of r.z and r.r
+__global__ void __launch_bounds__(256) k_cg_xr_dot(int n, int nbk, const double *sc, const double *apart,
+                                                   const double *p, const double *Ap, double *x, double *r,
+                                                   const double *Minv, double *z, double *part) {
     __shared__ double sh[2][256];
     const int i = blockIdx.x * 256 + threadIdx.x;
     const bool frozen = sc[8] != 0.0;
+    double pAp = 0.0, unused;
+    block_sum_partials(nbk, 1, false, apart, sh, pAp, unused);
     double rz = 0.0, rr = 0.0;
     if (i < n) {
         double ri = r[i];
         if (!frozen) {
-            const double al = sc[0] / sc[1];
+            const double al = sc[0] / pAp;
             x[i] += al * p[i];
             ri -= al * Ap[i];
             r[i] = ri;
@@ -423,31 +455,6 @@ __global__ void __launch_bounds__(256) k_cg_xr_dot(int n, const double *sc, cons
     if (threadIdx.x == 0) {
         part[2 * blockIdx.x] = sh[0][0];
         part[2 * blockIdx.x + 1] = sh[1][0];
-    }
-}
-
-// fixed-order sums of nb block partials with the given stride into up to two scalar slots
-__global__ void __launch_bounds__(256) k_partials_finish(int nb, int stride, const double *part, double *sc, int slot0,
-                                                         int slot1) {
-    __shared__ double sh[2][256];
-    double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < nb; k += 256) {
-        a += part[stride * k];
-        if (slot1 >= 0) b += part[stride * k + 1];
-    }
-    sh[0][threadIdx.x] = a;
-    sh[1][threadIdx.x] = b;
-    __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
-        if (threadIdx.x < k) {
-            sh[0][threadIdx.x] += sh[0][threadIdx.x + k];
-            sh[1][threadIdx.x] += sh[1][threadIdx.x + k];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        sc[slot0] = sh[0][0];
-        if (slot1 >= 0) sc[slot1] = sh[1][0];
     }
 }
 
@@ -480,10 +487,15 @@ __global__ void k_dot_finish(const double *part, double *out, int slot, int accu
 }
 
 // CG vector updates with device-side scalars: sc[0]=rz, sc[1]=pAp, sc[2]=rr, sc[3]=rz_new
-__global__ void k_cg_p(int n, const double *sc, const double *z, double *p) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || sc[8] != 0.0) return;
-    p[i] = z[i] + (sc[3] / sc[0]) * p[i];
+// p = z + (rz_new / rz) p, rz_new summed here from the r.z block partials
+__global__ void __launch_bounds__(256) k_cg_p(int n, int nbk, const double *sc, const double *part, const double *z,
+                                              double *p) {
+    __shared__ double sh[2][256];
+    if (sc[8] != 0.0) return;   // uniform over the grid
+    double rzn, unused;
+    block_sum_partials(nbk, 2, false, part, sh, rzn, unused);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = z[i] + (rzn / sc[0]) * p[i];
 }
 __global__ void k_cg_init(int n, const double *b, const double *Ax, double *r, const double *Minv, double *z, double *p) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -492,15 +504,26 @@ __global__ void k_cg_init(int n, const double *b, const double *Ax, double *r, c
     z[i] = Minv[i] * r[i];
     p[i] = z[i];
 }
-__global__ void k_cg_step_end(double *sc) {
-    if (sc[8] != 0.0) return;
+// one 256-thread block: (rz_new, rr) from the block partials, then the scalars
+__global__ void __launch_bounds__(256) k_cg_step_end(int nbk, const double *part, double *sc) {
+    __shared__ double sh[2][256];
+    if (sc[8] != 0.0) return;   // uniform over the block
+    double rzn, rr;
+    block_sum_partials(nbk, 2, true, part, sh, rzn, rr);
+    if (threadIdx.x != 0) return;
+    sc[3] = rzn;
+    sc[2] = rr;
     sc[0] = sc[3];
     sc[9] += 1.0;
     if (sc[2] <= sc[10]) sc[8] = 1.0;
     else if (sc[9] >= sc[11]) sc[8] = 2.0;
 }
-__global__ void k_cg_start(double *sc, double tol2, int maxit) {
-    sc[8] = 0.0;
+// stopping threshold rtol^2 |b|^2 (|b|^2 in sc[4], 1 if b = 0) and the stop
+// flag before the first iteration (already converged, or no iterations allowed)
+__global__ void k_cg_start(double *sc, double rtol, int maxit) {
+    const double bb = sc[4];
+    const double tol2 = rtol * rtol * (bb > 0 ? bb : 1.0);
+    sc[8] = (!(sc[2] > tol2) || maxit <= 0) ? 3.0 : 0.0;
     sc[9] = 0.0;
     sc[10] = tol2;
     sc[11] = (double)maxit;
@@ -518,29 +541,47 @@ __global__ void k_backsub(int nn, int dim, double c3, const int *rp, const int *
 }
 
 // pointwise energy balance: cv T/dt + sigP a c T^4 = c sigE E + cv T*/dt
-// (Newton safeguarded by bisection on [0, rhs dt/cv]; stop at |f| <= rtol |rhs|)
+// (Newton safeguarded by bisection on [0, rhs dt/cv]; stop at |f| <= rtol |rhs|).
+// flags: [0] a node without a positive root, [1] the largest iteration count,
+// [2] a node that hit maxit; the count is reduced over the wave first, so the
+// flags see one atomic per wave.
 __global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, int maxit, const double *cvn,
                             const double *sigE, const double *sigP, const double *E, const double *Tstar, double *T,
                             int *flags) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
-    const double cv_dt = cvn[n] / dt, k4 = sigP[n] * a * c;
-    const double rhs = c * sigE[n] * E[n] + cv_dt * Tstar[n];
-    if (!(rhs > 0.0)) { atomicOr(&flags[0], 1); return; }
-    double lo = 0.0, hi = rhs / cv_dt, t = T[n];
-    if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
     int it = 0;
-    for (; it < maxit; ++it) {
-        const double f = cv_dt * t + k4 * t * t * t * t - rhs;
-        if (fabs(f) <= rtol * fabs(rhs)) break;
-        if (f > 0) hi = t; else lo = t;
-        double tn = t - f / (cv_dt + 4.0 * k4 * t * t * t);
-        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-        t = tn;
+    bool bad = false, capped = false;
+    if (n < nn) {
+        const double cv_dt = cvn[n] / dt, k4 = sigP[n] * a * c;
+        const double rhs = c * sigE[n] * E[n] + cv_dt * Tstar[n];
+        if (!(rhs > 0.0)) {
+            bad = true;
+        } else {
+            double lo = 0.0, hi = rhs / cv_dt, t = T[n];
+            if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
+            for (; it < maxit; ++it) {
+                const double f = cv_dt * t + k4 * t * t * t * t - rhs;
+                if (fabs(f) <= rtol * fabs(rhs)) break;
+                if (f > 0) hi = t; else lo = t;
+                double tn = t - f / (cv_dt + 4.0 * k4 * t * t * t);
+                if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+                t = tn;
+            }
+            T[n] = t;
+            capped = it == maxit;
+        }
     }
-    T[n] = t;
-    atomicMax(&flags[1], it);
-    if (it == maxit) atomicOr(&flags[2], 1);
+    // wave maximum of the iteration count (every lane of the wave takes part)
+    int m = it;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+    const bool any_bad = __builtin_amdgcn_ballot_w64(bad) != 0;
+    const bool any_capped = __builtin_amdgcn_ballot_w64(capped) != 0;
+    if ((threadIdx.x & 63) == 0) {
+        if (any_bad) atomicOr(&flags[0], 1);
+        if (m > 0) atomicMax(&flags[1], m);
+        if (any_capped) atomicOr(&flags[2], 1);
+    }
 }
 
 __global__ void k_zero4(int *p) { p[threadIdx.x] = 0; }
@@ -575,6 +616,7 @@ void LoSolver::init(int dim_, int nx, int ny, const std::vector<double> &xe, con
     part.alloc(RED_BLOCKS);
     sc.alloc(12);
     bpart.alloc(2 * (int64_t)((nn + 255) / 256));
+    apart.alloc((int64_t)((nn + 255) / 256));
     flags.alloc(4);
 }
 
@@ -604,11 +646,9 @@ int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
     dot(s, rhs.p, nullptr, nullptr, 4, false);     // |b|^2
     dot(s, r.p, z.p, nullptr, 0, false);           // rz
     dot(s, r.p, nullptr, nullptr, 2, false);       // rr
-    double bb = fetch(s, 4);
-    const double tol2 = rtol * rtol * (bb > 0 ? bb : 1.0);
-    double rr = fetch(s, 2);
-    if (!(rr > tol2) || maxit <= 0) return 0;
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1), 0, s, sc.p, tol2, maxit);
+    // the threshold and the initial convergence test stay on the device: a
+    // solve that starts converged runs one frozen block and reports 0 iterations
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1), 0, s, sc.p, rtol, maxit);
     constexpr int CHECK = 4;   // iterations queued between host checks
     if (use_graphs && !graph_failed && (cg_exec == nullptr || cg_stream != s || cg_x != x)) {
         // record CHECK iterations once (kernels only) and replay them; streams
@@ -642,20 +682,20 @@ int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
     }
 }
 
-// One CG iteration = 7 launches: D^T p, S p with p.Sp partials, pAp, the x/r/z
-// update with r.z and r.r partials, (rz, rr), the new direction, the scalars.
+// One CG iteration = 5 launches: D^T p; S p with the p.Sp block partials; the
+// x/r/z update (each block sums the p.Sp partials itself) with the r.z and r.r
+// partials; the new direction (each block sums r.z); the scalars and the stop test.
 void LoSolver::cg_block(hipStream_t s, double *x, int iters) {
     const int nbk = nb(nn);
     for (int k = 0; k < iters; ++k) {
         hipLaunchKernelGGL(k_dt_scaled, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn * dim, dim, c / 3.0, dDT.rp,
                            dDT.col, dDT.val, p.p, MFinv.p, tmpF.p);
         hipLaunchKernelGGL(k_schur_rows_dot, dim3(nbk), dim3(256), 0, s, nn, dD.rp, dD.col, dD.val, dP.rp, dP.col,
-                           dP.val, tmpF.p, p.p, diagE.p, Ap.p, bpart.p);
-        hipLaunchKernelGGL(k_partials_finish, dim3(1), dim3(256), 0, s, nbk, 1, bpart.p, sc.p, 1, -1);
-        hipLaunchKernelGGL(k_cg_xr_dot, dim3(nbk), dim3(256), 0, s, nn, sc.p, p.p, Ap.p, x, r.p, Minv.p, z.p, bpart.p);
-        hipLaunchKernelGGL(k_partials_finish, dim3(1), dim3(256), 0, s, nbk, 2, bpart.p, sc.p, 3, 2);
-        hipLaunchKernelGGL(k_cg_p, dim3(nbk), dim3(256), 0, s, nn, sc.p, z.p, p.p);
-        hipLaunchKernelGGL(k_cg_step_end, dim3(1), dim3(1), 0, s, sc.p);
+                           dP.val, tmpF.p, p.p, diagE.p, Ap.p, apart.p);
+        hipLaunchKernelGGL(k_cg_xr_dot, dim3(nbk), dim3(256), 0, s, nn, nbk, sc.p, apart.p, p.p, Ap.p, x, r.p, Minv.p,
+                           z.p, bpart.p);
+        hipLaunchKernelGGL(k_cg_p, dim3(nbk), dim3(256), 0, s, nn, nbk, sc.p, bpart.p, z.p, p.p);
+        hipLaunchKernelGGL(k_cg_step_end, dim3(1), dim3(256), 0, s, nbk, bpart.p, sc.p);
     }
 }
 
@@ -680,10 +720,8 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
     double first = -1.0;
     smrt_status status = SMRT_OK;
     for (int m = 1; m <= in.max_inner; ++m) {
-        SMRT_HIP(hipMemcpyAsync(Eold.p, E, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
-        SMRT_HIP(hipMemcpyAsync(Told.p, T, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_newton_prep, dim3(nb(nn)), dim3(256), 0, s, nn, a, c, in.dt, wn.p, in.cvn, T, in.Tstar,
-                           in.sigE, in.sigP, in.qE, DqF.p, jbase.p, diagE.p, rhs.p, Minv.p);
+                           in.sigE, in.sigP, in.qE, DqF.p, jbase.p, diagE.p, rhs.p, Minv.p, E, Eold.p, Told.p);
         st->cg_total += pcg(s, E, in.cg_rtol, in.max_cg);
         hipLaunchKernelGGL(k_backsub, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn, dim, c / 3.0, dDT.rp, dDT.col,
                            dDT.val, E, in.qF, MFinv.p, F);
