@@ -1,0 +1,76 @@
+"""GPU parity at the benchmark's full size and launch: the 256x256 bilinear-DG
+mesh, level-symmetric S8 (40 angles), 16 groups, with the 5-wave,
+1-group-per-lane launch that bench.py times (FP32, the timed form, and FP64),
+on seeded random inputs of the workload's shapes.
+
+* Sampled outputs: three whole groups (every angle and node) are swept by the
+  FP64 oracle and compared element by element (1e-5 of the field's maximum
+  in FP32, 1e-10 in FP64).
+* A property at any size: the fused moments the sweep returns equal the
+  moments recomputed in FP64 from the sweep's own angular flux (quadrant
+  phi, F, Pi and the sigma-weighted full-range phi, F), so the partial
+  reduction and finalisation are checked on every node of the full mesh.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from paper_2504_21784_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SAMPLED_GROUPS = [0, 7, 15]
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _quadrant(mu, eta):
+    # quadrant order of the moment rows: (+,+), (-,+), (-,-), (+,-)
+    if mu > 0:
+        return 0 if eta > 0 else 3
+    return 1 if eta > 0 else 2
+
+
+@pytest.mark.parametrize("prec,tol,mtol", [(1, 1e-5, 1e-5), (0, 1e-10, 1e-12)])
+def test_full_size_sweep_sampled_groups_and_moments(smrt_mod, oracle_mod, prec, tol, mtol):
+    p = W.multigroup_2d()
+    assert (p.nx, p.ny, p.n_angles, p.G) == (256, 256, 40, 16)
+    print(f"full size: 256x256 S8 G16, precision {prec}, launch (5 waves, 1 group per lane)", flush=True)
+    sigt, q, pp, inf = W.random_sweep_inputs(p, seed=2024)
+    sig = 0.8 * sigt
+    icdt = 1.0 / (p.c * p.dt)
+    ctx = smrt_mod.Context(p, precision=prec)
+    ctx.set_launch(5, 1)
+    psi, mom = ctx.sweep(sigt, sig, q, pp, icdt, inf)
+    ctx.close()
+
+    # sampled groups against the FP64 oracle (the same inputs, those groups only)
+    sub = copy.copy(p)
+    sub.G = len(SAMPLED_GROUPS)
+    sub.nu_edges = np.logspace(-3.0, 1.0, sub.G + 1)
+    o = oracle_mod.Oracle(sub)
+    S = SAMPLED_GROUPS
+    ref = o.sweep(np.ascontiguousarray(sigt[:, S]), np.ascontiguousarray(q[:, S]),
+                  np.ascontiguousarray(pp[:, S, :]), icdt, np.ascontiguousarray(inf[:, S, :]))
+    for i, g in enumerate(S):
+        assert _rel(psi[:, g, :], ref[:, i, :]) < tol, g
+
+    # fused moments against moments recomputed from the returned flux
+    nn = p.n_nodes
+    sig_node = np.repeat(sig, 4, axis=0)                # [node][G]
+    want = np.zeros((27, nn))
+    for d in range(p.n_angles):
+        mu, eta = p.omega[d, 0], p.omega[d, 1]
+        w = p.w[d]
+        qd = _quadrant(mu, eta)
+        s = psi[d].sum(axis=0)                          # sum over groups
+        ss = (psi[d] * sig_node.T).sum(axis=0)          # sigma-weighted
+        for k, c in enumerate((1.0, mu, eta, mu * mu, mu * eta, eta * eta)):
+            want[6 * qd + k] += w * c * s
+        for k, c in enumerate((1.0, mu, eta)):
+            want[24 + k] += w * c * ss
+    for m in range(27):
+        assert _rel(mom[m], want[m]) < mtol, m
