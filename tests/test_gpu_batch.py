@@ -159,3 +159,31 @@ def test_batch_rejects_mixed_precision(smrt_mod):
         smrt_mod.Batch([a, c])
     a.close()
     c.close()
+
+
+def test_full_batch_matches_single_problem_launches(smrt_mod):
+    """The benchmark's batch at full size (32 problems, n in {64..384}, G in
+    {4..32}, S4/S8/S12, FP32) in one launch with the launch shape the
+    benchmark reports (4 waves x 2 groups per lane): the largest, the
+    smallest and one middle problem match the same problem launched alone
+    with the same shape (which the full-size sweep test checks against the
+    oracle)."""
+    ps = W.batch_2d()
+    print("full batch:", len(ps), "problems", flush=True)
+    cs = _contexts(smrt_mod, ps, 1)
+    b = smrt_mod.Batch(cs)
+    b.set_launch(4, 2)
+    b.sweep_resident(ps[0].dt, n_times=1)
+    sizes = [p.nx * p.ny * p.n_angles * p.G for p in ps]
+    picks = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), len(ps) // 2})
+    for i in picks:
+        print("problem", ps[i].name, flush=True)
+        single = smrt_mod.Context(ps[i], precision=1)
+        single.set_state(ps[i].initial_T_nodes())
+        single.set_launch(4, 2)
+        single.sweep_resident(ps[i].dt, n_times=1)
+        assert _rel(cs[i].get_moments(), single.get_moments()) < 1e-6, ps[i].name
+        single.close()
+    b.close()
+    for c in cs:
+        c.close()
