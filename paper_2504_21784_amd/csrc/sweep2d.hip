@@ -27,16 +27,18 @@
 //    (sum over the wave's groups of I) or x (sum of sigma_g I).  Each lane
 //    accumulates these two sums (4 nodes each), three gfx950 permlane swaps
 //    reduce-scatter them over the 4 channels so that channel c holds node c's
-//    totals, and channel c forms the 9 moments of canonical node c.  A workgroup = NW waves = NW directions of one
-//    quadrant on the same band and the same 4K groups; their 9-value
+//    totals, and channel c forms the 9 moments of canonical node c.  A
+//    workgroup = NW waves = NW directions of one quadrant on the same band
+//    and the same 4K groups; their 9-value
 //    contributions are reduced through double-buffered LDS every step
 //    (summed at the sweep precision in a fixed order, one barrier per step)
 //    into one partial per cell and workgroup; partials are summed in FP64
 //    by the finalisation kernels.
 //  * Bands hand their top-row outflow to the band above through a trace
 //    buffer of 64-bit words that carry (sweep epoch, value bits), written
-//    and polled with relaxed device-scope atomics: a word is valid when
-//    its epoch matches, so no cache flushes are needed.  Workgroups take
+//    with single 64-bit device-coherent stores (the form a relaxed
+//    device-scope atomic store takes) and read with device-coherent loads:
+//    a word is valid when its epoch matches, so no cache flushes are needed.  Workgroups take
 //    tasks (problem, band, chunk) from a ticket counter over a task list in
 //    which every band follows the band below it, so a workgroup only ever
 //    waits on a band whose workgroup started earlier: no deadlock, whatever
@@ -362,7 +364,8 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
         vo_tw[k] = act[k] && produce ? slot_words : OOB;
     }
 
-    // All prefetch loads are issued unconditionally (always in bounds) into raw
+    // All prefetch loads are issued unconditionally (in bounds, or at the
+    // out-of-range offset of a lane with no work, which reads zeros) into raw
     // registers, so several steps of loads stay in flight: a load under a
     // branch, or a reordering of its result, makes the compiler wait for every
     // outstanding memory operation.
