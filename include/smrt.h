@@ -217,17 +217,22 @@ smrt_status smrt_set_materials(smrt_ctx *ctx, const double *sigma0, const double
  * context's current state, runs n_steps backward-Euler steps of length dt
  * (smrt_step with the context options; use tight tolerances so each step is
  * at its fixed point), keeping per-step checkpoints of I, T and sigma, and
- * returns the time-integrated outflow through the x+ boundary
- *   J = sum_k dt sum_g sum_{mu_d > 0} w_d mu_d sum_{n on x+} fw_n I^k_{d,g,n}
- * (objective 0, the only one implemented) with its gradient with respect to
- * log sigma0_r and log c_v,r (grad arrays [n_regions]).  The gradient is
+ * returns the objective
+ *   0: the time-integrated outflow through the x+ boundary,
+ *      J = sum_k dt sum_g sum_{mu_d > 0} w_d mu_d sum_{n on x+} fw_n I^k_{d,g,n};
+ *   1: the material energy at the last step, J = sum_n w_n c_v,n T^N_n
+ *      (w_n the lumped nodal weight),
+ * with its gradient with respect to log sigma0_r and log c_v,r (grad arrays
+ * [n_regions]; for objective 1 the c_v gradient includes J's direct
+ * dependence on c_v).  The gradient is
  * that of the converged discrete solution of every step (transport with
  * emission, Sec. 3, plus the lumped energy balance, Sec. 2), obtained
  * backwards by adjoint source iteration: adjoint sweeps (smrt_adjoint_sweep)
  * alternating with the pointwise temperature adjoint.  Clipped opacities
  * contribute no sigma0 sensitivity.  adjoint_iterations (may be NULL)
  * receives the total number of adjoint source iterations.  The context
- * state is advanced by n_steps.  Errors: SMRT_E_INVALID_ARG (objective,
+ * state is advanced by n_steps.  Errors: SMRT_E_INVALID_ARG (objective not
+ * 0 or 1,
  * n_steps < 1, dt <= 0, constant-opacity model, quadrature without
  * opposite directions, no state), or the failure of a forward step. */
 smrt_status smrt_adjoint(smrt_ctx *ctx, int objective, int n_steps, double dt, double *J, double *grad_log_sigma0,

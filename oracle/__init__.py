@@ -79,11 +79,11 @@ def _declare(L):
     L.orc_sweep.restype = C.c_int
     L.orc_adjoint_sweep.argtypes = [gp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_adjoint_sweep.restype = C.c_int
-    L.orc_adjoint_gradient.argtypes = [gp, mp, bp, C.POINTER(Opts), C.c_double, C.c_int, _dp, _dp, _dp, _dp, _dp,
+    L.orc_adjoint_gradient.argtypes = [gp, mp, bp, C.POINTER(Opts), C.c_double, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp,
                                        C.c_int, C.POINTER(C.c_int)]
     L.orc_adjoint_gradient.restype = C.c_int
-    L.orc_leakage.argtypes = [gp, mp, bp, C.POINTER(Opts), C.c_double, C.c_int, _dp, _dp, _dp]
-    L.orc_leakage.restype = C.c_int
+    L.orc_objective.argtypes = [gp, mp, bp, C.POINTER(Opts), C.c_double, C.c_int, C.c_int, _dp, _dp, _dp]
+    L.orc_objective.restype = C.c_int
     L.orc_moments.argtypes = [gp, _dp, _dp, _dp]
     L.orc_n_moments.argtypes = [C.c_int]
     L.orc_inflow_from_bc.argtypes = [gp, bp, _dp]
@@ -188,18 +188,23 @@ class Oracle:
         assert r == 0
         return (lam, dsig) if want else lam
 
-    def leakage(self, opts, n_steps, dt=None):
-        """Time-integrated right-boundary outflow over n_steps from the initial state."""
+    def objective(self, opts, n_steps, objective=0, dt=None):
+        """J over n_steps from the initial state: objective 0 the time-integrated
+        right-boundary outflow, 1 the material energy sum_n w_n c_v T_n at the end."""
         st = self.initial_state()
         J = C.c_double(0.0)
         o = Opts(**opts)
-        r = self.L.orc_leakage(C.byref(self.geom), C.byref(self.mat), C.byref(self.bc), C.byref(o),
-                               float(dt if dt is not None else self.p.dt), int(n_steps), _p(st["psi"]), _p(st["T"]),
-                               C.byref(J))
+        r = self.L.orc_objective(C.byref(self.geom), C.byref(self.mat), C.byref(self.bc), C.byref(o),
+                                 float(dt if dt is not None else self.p.dt), int(n_steps), int(objective),
+                                 _p(st["psi"]), _p(st["T"]), C.byref(J))
         assert r == 0, r
         return J.value
 
-    def adjoint_gradient(self, opts, n_steps, dt=None):
+    def leakage(self, opts, n_steps, dt=None):
+        """Time-integrated right-boundary outflow over n_steps from the initial state."""
+        return self.objective(opts, n_steps, 0, dt)
+
+    def adjoint_gradient(self, opts, n_steps, dt=None, objective=0):
         """(J, dJ/dlog sigma0 [n_regions], dJ/dlog c_v [n_regions], adjoint iterations)."""
         st = self.initial_state()
         nr = self.p.n_regions
@@ -208,8 +213,8 @@ class Oracle:
         it = C.c_int(0)
         o = Opts(**opts)
         r = self.L.orc_adjoint_gradient(C.byref(self.geom), C.byref(self.mat), C.byref(self.bc), C.byref(o),
-                                        float(dt if dt is not None else self.p.dt), int(n_steps), _p(st["psi"]),
-                                        _p(st["T"]), C.byref(J), _p(gs), _p(gc), nr, C.byref(it))
+                                        float(dt if dt is not None else self.p.dt), int(n_steps), int(objective),
+                                        _p(st["psi"]), _p(st["T"]), C.byref(J), _p(gs), _p(gc), nr, C.byref(it))
         assert r == 0, r
         return J.value, gs, gc, it.value
 

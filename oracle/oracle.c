@@ -1116,12 +1116,19 @@ void orc_equilibrium_psi(const orc_geom *g, const double *T, double *psi)
 /*            - sum_{l in c} tau_l (phi_g - 4 pi E_g),                         */
 /* and dJ/dlog sigma0_r = -sum_k sum_{c in r, g unclipped} sigma G,          */
 /*     dJ/dlog c_v,r    = -sum_k sum_{n in r} tau_n c_v (T^k - T^{k-1})/dt.  */
+/* Objectives: 0, the time-integrated outflow through x+,                    */
+/*   J = sum_k dt sum_{d: mu>0} w_d mu_d sum_g sum_{n on x+} fw_n I^k        */
+/*   (dJ/dI^k the outflow weights, no direct T dependence);                   */
+/* 1, the material energy at the final step, J = sum_n w_n c_v,n T^N_n       */
+/*   (dJ/dI = 0; S^T at step N gains w c_v; dJ/dlog c_v,r gains the direct  */
+/*   term sum_{n in r} w c_v T^N).                                             */
 /* ------------------------------------------------------------------------ */
 
 int orc_adjoint_gradient(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_opts *op, double dt,
-                         int n_steps, const double *psi0, const double *T0, double *J_out, double *grad_s0,
-                         double *grad_cv, int n_regions, int *adj_iters)
+                         int n_steps, int objective, const double *psi0, const double *T0, double *J_out,
+                         double *grad_s0, double *grad_cv, int n_regions, int *adj_iters)
 {
+    if (objective != 0 && objective != 1) return -2;
     int nn = nnode(g), np = npc(g), G = g->G, nc = ncell(g), nd = g->nang, dim = g->dim;
     int nx = g->nx;
     size_t npsi = (size_t)nd * G * nn;
@@ -1137,8 +1144,8 @@ int orc_adjoint_gradient(const orc_geom *g, const orc_mat *mt, const orc_bc *bc,
     nodal_cv(g, mt, cvn);
     for (int cc = 0; cc < nc; ++cc)
         for (int l = 0; l < np; ++l) wsp[np * cc + l] = vol_weight(g, cc % nx, cc / nx);
-    /* objective weights: outflow through x+ */
-    for (int d = 0; d < nd; ++d) {
+    /* objective 0 weights: outflow through x+ (objective 1 leaves dJ/dI = 0) */
+    for (int d = 0; d < nd && objective == 0; ++d) {
         double mu = om_ax(g, d, 0);
         if (mu <= 0.0) continue;
         for (int k = 0; k < G; ++k)
@@ -1164,6 +1171,10 @@ int orc_adjoint_gradient(const orc_geom *g, const orc_mat *mt, const orc_bc *bc,
         rc = orc_step(g, mt, bc, op, dt, psi, T, E, F, &st);
         for (size_t t = 0; t < npsi; ++t) J += dJdI[t] * psi[t];
     }
+    if (objective == 1) {
+        const double *TN = ck_T + (size_t)nn * N;
+        for (int n = 0; n < nn; ++n) J += wsp[n] * cvn[n] * TN[n];
+    }
     *J_out = J;
     if (rc != ORC_OK) goto done;
     {
@@ -1176,6 +1187,8 @@ int orc_adjoint_gradient(const orc_geom *g, const orc_mat *mt, const orc_bc *bc,
         double *Gs = malloc(sizeof(double) * (size_t)nc * G), *dsig = malloc(sizeof(double) * (size_t)nc * G);
         double *bg = malloc(sizeof(double) * G), *rg = malloc(sizeof(double) * G), *tau_new = malloc(sizeof(double) * nn);
         int iters = 0;
+        if (objective == 1)   /* dJ/dT^N enters the energy-balance adjoint of the last step */
+            for (int n = 0; n < nn; ++n) ST[n] = wsp[n] * cvn[n];
         for (int k = N; k >= 1; --k) {
             const double *psi = ck_psi + npsi * k, *T = ck_T + (size_t)nn * k, *Tp = ck_T + (size_t)nn * (k - 1);
             const double *sig = ck_sig + (size_t)nc * G * k;
@@ -1266,6 +1279,14 @@ int orc_adjoint_gradient(const orc_geom *g, const orc_mat *mt, const orc_bc *bc,
             memcpy(ST, ST_prev, sizeof(double) * nn);
             memcpy(lam_next, lam, sizeof(double) * npsi);
         }
+        if (objective == 1 && rc == ORC_OK) {   /* direct dependence of J on c_v */
+            const double *TN = ck_T + (size_t)nn * N;
+            for (int cc = 0; cc < nc; ++cc)
+                for (int l = 0; l < np; ++l) {
+                    int n = np * cc + l;
+                    grad_cv[mt->region[cc]] += wsp[n] * cvn[n] * TN[n];
+                }
+        }
         if (adj_iters) *adj_iters = iters;
         free(lam); free(lam_next); free(src); free(sigt); free(tau); free(ST); free(ST_prev); free(emis); free(dE);
         free(phi); free(D); free(Gs); free(dsig); free(bg); free(rg); free(tau_new);
@@ -1275,12 +1296,14 @@ done:
     return rc;
 }
 
-/* J alone (forward only), for finite differences */
-int orc_leakage(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_opts *op, double dt, int n_steps,
-                const double *psi0, const double *T0, double *J_out)
+/* J alone (forward only), for finite differences: objective 0 the
+   time-integrated outflow through x+, 1 the final material energy */
+int orc_objective(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_opts *op, double dt, int n_steps,
+                  int objective, const double *psi0, const double *T0, double *J_out)
 {
     int nn = nnode(g), np = npc(g), G = g->G, nc = ncell(g), nd = g->nang, dim = g->dim, nx = g->nx;
     size_t npsi = (size_t)nd * G * nn;
+    if (objective != 0 && objective != 1) return -2;
     double *psi = malloc(sizeof(double) * npsi), *T = malloc(sizeof(double) * nn);
     double *E = malloc(sizeof(double) * nn), *F = calloc((size_t)nn * dim, sizeof(double));
     memcpy(psi, psi0, sizeof(double) * npsi);
@@ -1291,7 +1314,7 @@ int orc_leakage(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const or
     for (int k = 1; k <= n_steps && rc == ORC_OK; ++k) {
         orc_stats st;
         rc = orc_step(g, mt, bc, op, dt, psi, T, E, F, &st);
-        for (int d = 0; d < nd; ++d) {
+        for (int d = 0; d < nd && objective == 0; ++d) {
             double mu = om_ax(g, d, 0);
             if (mu <= 0.0) continue;
             for (int q = 0; q < G; ++q)
@@ -1303,6 +1326,13 @@ int orc_leakage(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const or
                             J += dt * g->w[d] * mu * face_weight(g, i, j, 0) * psi[((size_t)d * G + q) * nn + np * cc + l];
                 }
         }
+    }
+    if (objective == 1) {
+        double *cvn = malloc(sizeof(double) * nn);
+        nodal_cv(g, mt, cvn);
+        for (int cc = 0; cc < nc; ++cc)
+            for (int l = 0; l < np; ++l) J += vol_weight(g, cc % nx, cc / nx) * cvn[np * cc + l] * T[np * cc + l];
+        free(cvn);
     }
     *J_out = J;
     free(psi); free(T); free(E); free(F);

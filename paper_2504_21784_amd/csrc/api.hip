@@ -1574,7 +1574,8 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
                                     double *grad_log_sigma0, double *grad_log_cv, int *adjoint_iterations) {
     if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
     return guard(x, [&] {
-        require(objective == 0, "objective 0 (right-boundary outflow) is the one implemented");
+        require(objective == 0 || objective == 1,
+                "objective must be 0 (time-integrated right-boundary outflow) or 1 (final material energy)");
         require(n_steps >= 1 && dt > 0.0 && std::isfinite(dt), "n_steps >= 1 and dt > 0 required");
         require(J_out && grad_log_sigma0 && grad_log_cv, "NULL output");
         require(x->have_state, "smrt_set_state must be called first");
@@ -1585,14 +1586,21 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
         const int64_t npsi = (int64_t)x->nang * G * nn, ncg = (int64_t)nc * G;
         const int ny1 = x->dim == 2 ? x->ny : 1;
         const double *hy = x->dim == 2 ? x->d_hy64.p : nullptr;
-        DevBuf<double> ck_psi, ck_T, ck_sig, dJdI, part, scal;
+        DevBuf<double> ck_psi, ck_T, ck_sig, dJdI, part, scal, wc;
         ck_psi.alloc(npsi * (N + 1));
         ck_T.alloc((int64_t)nn * (N + 1));
         ck_sig.alloc(ncg * (N + 1));
         dJdI.alloc(npsi);
         part.alloc(std::max<int64_t>(256, 2 * ((nn + 255) / 256)));
         scal.alloc(4);
-        run_adj_dJdI(S, x->dim, x->nx, ny1, G, x->nang, x->d_om.p, x->d_w.p, hy, dt, dJdI.p);
+        wc.alloc(nn);
+        if (objective == 0) {
+            run_adj_dJdI(S, x->dim, x->nx, ny1, G, x->nang, x->d_om.p, x->d_w.p, hy, dt, dJdI.p);
+        } else {
+            // J = sum_n w_n c_v,n T^N_n: no direct dependence on I
+            dJdI.zero(S);
+            run_adj_energy_weights(S, x->dim, x->nx, npc, nn, x->d_hx64.p, hy, x->d_cvn.p, wc.p);
+        }
         // forward with checkpoints
         psi_state_to_abi(x, ck_psi.p);
         SMRT_HIP(hipMemcpyAsync(ck_T.p, x->d_T.p, 8 * nn, hipMemcpyDeviceToDevice, S));
@@ -1612,11 +1620,19 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
             if (r != SMRT_OK) throw smrt::Error(r, "forward step " + std::to_string(k) + ": " + x->err);
             psi_state_to_abi(x, ck_psi.p + npsi * k);
             SMRT_HIP(hipMemcpyAsync(ck_T.p + (int64_t)nn * k, x->d_T.p, 8 * nn, hipMemcpyDeviceToDevice, S));
-            run_dot(S, npsi, dJdI.p, ck_psi.p + npsi * k, part.p, scal.p);
-            double jk = 0.0;
-            d2h(&jk, scal.p, 8, S);
+            if (objective == 0) {
+                run_dot(S, npsi, dJdI.p, ck_psi.p + npsi * k, part.p, scal.p);
+                double jk = 0.0;
+                d2h(&jk, scal.p, 8, S);
+                SMRT_HIP(hipStreamSynchronize(S));
+                J += jk;
+            }
+        }
+        const double *TN = ck_T.p + (int64_t)nn * N;
+        if (objective == 1) {
+            run_dot(S, nn, wc.p, TN, part.p, scal.p);
+            d2h(&J, scal.p, 8, S);
             SMRT_HIP(hipStreamSynchronize(S));
-            J += jk;
         }
         // reverse
         DevBuf<double> lam, lam_next, src, prev_tmp, out_tmp, zq, zinf, sigt, tau, tau_new, ST, ST_prev, emis, dE, phi, D,
@@ -1627,6 +1643,8 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
         emis.alloc((int64_t)nn * G); dE.alloc((int64_t)nn * G); phi.alloc((int64_t)nn * G); D.alloc(nn);
         dsig.alloc(ncg); gs_cell.alloc(nc); gcv_node.alloc(nn); gs.alloc(nreg); gc.alloc(nreg);
         lam_next.zero(S); zq.zero(S); zinf.zero(S); ST.zero(S); gs.zero(S); gc.zero(S);
+        // objective 1: dJ/dT^N = w c_v enters the energy-balance adjoint of the last step
+        if (objective == 1) run_add_scalar(S, nn, wc.p, 0.0, ST.p);
         const double icdt = 1.0 / (x->c * dt);
         int iters = 0;
         for (int k = N; k >= 1; --k) {
@@ -1659,6 +1677,12 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
             run_region_sums(S, nreg, nc, npc, x->d_region.p, gs_cell.p, gcv_node.p, gs.p, gc.p);
             std::swap(ST.p, ST_prev.p);
             std::swap(lam_next.p, lam.p);
+        }
+        if (objective == 1) {
+            // direct dependence of J on c_v: sum over the region of w c_v T^N
+            gs_cell.zero(S);
+            run_mul(S, nn, wc.p, TN, gcv_node.p);
+            run_region_sums(S, nreg, nc, npc, x->d_region.p, gs_cell.p, gcv_node.p, gs.p, gc.p);
         }
         d2h(grad_log_sigma0, gs.p, 8 * nreg, S);
         d2h(grad_log_cv, gc.p, 8 * nreg, S);

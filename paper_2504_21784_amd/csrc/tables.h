@@ -46,6 +46,10 @@ void run_adj_cell(hipStream_t s, int npc, int ncell, int G, int model, double cl
                   double *ST_prev);
 void run_region_sums(hipStream_t s, int nreg, int ncell, int npc, const int *region, const double *gs_cell,
                      const double *gcv_node, double *grad_s0, double *grad_cv);
+// wc[n] = (lumped nodal weight) c_v,n; out = a * b elementwise
+void run_adj_energy_weights(hipStream_t s, int dim, int nx, int npc, int nn, const double *hx, const double *hy,
+                            const double *cvn, double *wc);
+void run_mul(hipStream_t s, int64_t n, const double *a, const double *b, double *out);
 // part256: scratch of 256 doubles
 void run_dot(hipStream_t s, int64_t n, const double *a, const double *b, double *part256, double *out);
 void run_add_scalar(hipStream_t s, int64_t n, const double *a, double v, double *out);

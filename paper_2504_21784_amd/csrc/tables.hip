@@ -445,6 +445,18 @@ __global__ void k_adj_prep(int nn, int npc, int G, int nang, const double *nu, d
     D[n] = dsum;
 }
 
+// final-material-energy weights w_n c_v,n (dJ/dT^N of J = sum_n w_n c_v,n T^N_n)
+__global__ void k_adj_energy_weights(int dim, int nx, int npc, int nn, const double *hx, const double *hy,
+                                     const double *cvn, double *wc) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    wc[n] = nodal_weight(dim, nx, hx, hy, n / npc) * cvn[n];
+}
+__global__ void k_mul(int64_t n, const double *a, const double *b, double *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] * b[i];
+}
+
 // right-boundary outflow weights dJ/dI = dt w_d mu_d fw_n (mu_d > 0, n on x+)
 __global__ void k_adj_dJdI(int dim, int nx, int ny, int G, int nang, const double *om, const double *w, const double *hy,
                            double dt, double *out) {
@@ -846,6 +858,13 @@ void run_region_sums(hipStream_t s, int nreg, int ncell, int npc, const int *reg
                      const double *gcv_node, double *grad_s0, double *grad_cv) {
     hipLaunchKernelGGL(k_region_sums, dim3(nblk(nreg, 64)), dim3(64), 0, s, nreg, ncell, npc, region, gs_cell, gcv_node,
                        grad_s0, grad_cv);
+}
+void run_adj_energy_weights(hipStream_t s, int dim, int nx, int npc, int nn, const double *hx, const double *hy,
+                            const double *cvn, double *wc) {
+    hipLaunchKernelGGL(k_adj_energy_weights, dim3(nblk(nn, 256)), dim3(256), 0, s, dim, nx, npc, nn, hx, hy, cvn, wc);
+}
+void run_mul(hipStream_t s, int64_t n, const double *a, const double *b, double *out) {
+    hipLaunchKernelGGL(k_mul, dim3(nblk(n, 256)), dim3(256), 0, s, n, a, b, out);
 }
 void run_dot(hipStream_t s, int64_t n, const double *a, const double *b, double *part256, double *out) {
     hipLaunchKernelGGL(k_dot_blocks, dim3(256), dim3(256), 0, s, n, a, b, part256);

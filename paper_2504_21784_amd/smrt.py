@@ -270,13 +270,14 @@ class Context:
         c = _f64(cv) if cv is not None else None
         self._check(self.L.smrt_set_materials(self.h, _p(s0), _p(c)))
 
-    def adjoint(self, n_steps, dt=None):
-        """Runs n_steps from the current state; returns (J, dJ/dlog sigma0, dJ/dlog c_v, adjoint iterations)."""
+    def adjoint(self, n_steps, dt=None, objective=0):
+        """Runs n_steps from the current state; returns (J, dJ/dlog sigma0, dJ/dlog c_v, adjoint iterations).
+        objective 0: time-integrated x+ outflow; 1: material energy at the last step."""
         nr = self.p.n_regions
         J = C.c_double(0.0)
         gs, gc = np.zeros(nr), np.zeros(nr)
         it = C.c_int(0)
-        self._check(self.L.smrt_adjoint(self.h, 0, int(n_steps), float(dt if dt is not None else self.p.dt),
+        self._check(self.L.smrt_adjoint(self.h, int(objective), int(n_steps), float(dt if dt is not None else self.p.dt),
                                         C.byref(J), _p(gs), _p(gc), C.byref(it)))
         return J.value, gs, gc, it.value
 

@@ -88,13 +88,16 @@ def _adjoint_problem():
     return p
 
 
-def test_adjoint_gradient_matches_oracle(smrt_mod, oracle_mod):
+@pytest.mark.parametrize("objective", [0, 1])
+def test_adjoint_gradient_matches_oracle(smrt_mod, oracle_mod, objective):
+    """Objective 0: time-integrated x+ outflow; 1: final material energy."""
     p = _adjoint_problem()
-    ref_J, ref_s, ref_c, _ = oracle_mod.Oracle(p).adjoint_gradient(dict(oracle_mod.default_opts(), **TIGHT), 3)
+    ref_J, ref_s, ref_c, _ = oracle_mod.Oracle(p).adjoint_gradient(dict(oracle_mod.default_opts(), **TIGHT), 3,
+                                                                   objective=objective)
     ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **TIGHT)
     ctx.set_state(p.initial_T_nodes())
-    J, gs, gc, its = ctx.adjoint(3)
-    print("adjoint J", J, "iterations", its, flush=True)
+    J, gs, gc, its = ctx.adjoint(3, objective=objective)
+    print("objective", objective, "adjoint J", J, "iterations", its, flush=True)
     scale = max(np.abs(ref_s).max(), np.abs(ref_c).max())
     assert abs(J - ref_J) <= 1e-10 * abs(ref_J)
     assert np.abs(gs - ref_s).max() <= 1e-8 * scale
@@ -102,19 +105,20 @@ def test_adjoint_gradient_matches_oracle(smrt_mod, oracle_mod):
     ctx.close()
 
 
-def test_adjoint_gradient_matches_finite_differences_on_gpu(smrt_mod):
+@pytest.mark.parametrize("objective", [0, 1])
+def test_adjoint_gradient_matches_finite_differences_on_gpu(smrt_mod, objective):
     p = _adjoint_problem()
     ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **TIGHT)
     T0 = p.initial_T_nodes()
     ctx.set_state(T0)
-    J, gs, gc, _ = ctx.adjoint(3)
+    J, gs, gc, _ = ctx.adjoint(3, objective=objective)
     h = 1e-4
     s0, cv = p.sigma0.copy(), p.cv.copy()
 
     def J_at(s, c):
         ctx.set_materials(s, c)
         ctx.set_state(T0)
-        return ctx.adjoint(3)[0]
+        return ctx.adjoint(3, objective=objective)[0]
 
     scale = max(np.abs(gs).max(), np.abs(gc).max())
     for r in (int(np.argmax(np.abs(gs))), int(np.argmax(np.abs(gc)))):
@@ -127,22 +131,32 @@ def test_adjoint_gradient_matches_finite_differences_on_gpu(smrt_mod):
     ctx.close()
 
 
-def test_autograd_function(smrt_mod):
+@pytest.mark.parametrize("kind", [0, 1])
+def test_autograd_function(smrt_mod, kind):
     import torch
-    from paper_2504_21784_amd.autograd import outflow
+    from paper_2504_21784_amd.autograd import material_energy, outflow
     p = _adjoint_problem()
     ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **TIGHT)
     T0 = p.initial_T_nodes()
     ls = torch.tensor(np.log(p.sigma0), dtype=torch.float64, requires_grad=True)
     lc = torch.tensor(np.log(p.cv), dtype=torch.float64, requires_grad=True)
-    J = outflow(ls, lc, ctx, T0, 3, p.dt)
+    J = (outflow if kind == 0 else material_energy)(ls, lc, ctx, T0, 3, p.dt)
     J.backward()
     ctx.set_materials(p.sigma0, p.cv)
     ctx.set_state(T0)
-    J2, gs, gc, _ = ctx.adjoint(3)
+    J2, gs, gc, _ = ctx.adjoint(3, objective=kind)
     # exp(log(sigma0)) differs from sigma0 in the last bit: agreement to rounding of the solves
     scale = max(np.abs(gs).max(), np.abs(gc).max())
     assert abs(J.item() - J2) <= 1e-10 * abs(J2)
     assert np.abs(ls.grad.numpy() - gs).max() <= 1e-9 * scale
     assert np.abs(lc.grad.numpy() - gc).max() <= 1e-9 * scale
+    ctx.close()
+
+
+def test_adjoint_rejects_unknown_objective(smrt_mod):
+    p = _adjoint_problem()
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **TIGHT)
+    ctx.set_state(p.initial_T_nodes())
+    with pytest.raises(smrt_mod.SmrtError):
+        ctx.adjoint(1, objective=2)
     ctx.close()

@@ -592,11 +592,13 @@ def _adjoint_problem():
     return p
 
 
-def test_P11_adjoint_gradient_matches_finite_differences(oracle_mod):
+@pytest.mark.parametrize("objective", [0, 1])
+def test_P11_adjoint_gradient_matches_finite_differences(oracle_mod, objective):
+    """Objective 0: time-integrated x+ outflow; 1: final material energy."""
     p = _adjoint_problem()
     o = oracle_mod.Oracle(p)
-    J, gs, gc, its = o.adjoint_gradient(TIGHT, n_steps=3)
-    assert abs(J - o.leakage(TIGHT, n_steps=3)) <= 1e-14 * abs(J)
+    J, gs, gc, its = o.adjoint_gradient(TIGHT, n_steps=3, objective=objective)
+    assert abs(J - o.objective(TIGHT, 3, objective)) <= 1e-14 * abs(J)
     h = 1e-4
     fd_s, fd_c = np.zeros_like(gs), np.zeros_like(gc)
     for r in range(p.n_regions):
@@ -606,7 +608,7 @@ def test_P11_adjoint_gradient_matches_finite_differences(oracle_mod):
             for sgn in (1, -1):
                 arr[...] = base
                 arr[r] = base[r] * math.exp(sgn * h)
-                vals.append(oracle_mod.Oracle(p).leakage(TIGHT, n_steps=3))
+                vals.append(oracle_mod.Oracle(p).objective(TIGHT, 3, objective))
             arr[...] = base
             fd[r] = (vals[0] - vals[1]) / (2 * h)
     scale = max(np.abs(fd_s).max(), np.abs(fd_c).max())
