@@ -186,6 +186,21 @@ smrt_status smrt_sweep(smrt_ctx *ctx, const double *sig_t, const double *sig, co
                        const double *psi_prev, double inv_c_dt, const double *psi_inflow, double *psi_out,
                        double *moments_out);
 
+/* smrt_sweep on device arrays (e.g. torch tensors): the same operation
+ * (Sec. 3, eq. dgsn_transport, lumped) and the same layouts, all FP64 and
+ * contiguous, but every pointer is a device address on the context's GPU.
+ * The arrays are borrowed for the duration of the call and never freed;
+ * the work is ordered on the context stream (the caller makes the inputs
+ * ready on it, e.g. by creating the context on its own stream or
+ * synchronizing first) and the call returns once the outputs are written.
+ * psi_out ([d][g][node]) is required; psi_prev, psi_inflow and moments_out
+ * may be NULL as in smrt_sweep.  Errors: SMRT_E_INVALID_ARG for a NULL
+ * required array, inv_c_dt < 0 or not finite, or (checked on the device)
+ * sig_t <= 0 or sig < 0 anywhere. */
+smrt_status smrt_sweep_dev(smrt_ctx *ctx, const double *sig_t, const double *sig, const double *q_iso,
+                           const double *psi_prev, double inv_c_dt, const double *psi_inflow, double *psi_out,
+                           double *moments_out);
+
 /* Adjoint sweep: the transpose of the lumped upwind DG transport operator
  * of smrt_sweep (Sec. 3, eq. dgsn_transport), the building block of the
  * adjoint of a time step.  For every (d, g):

@@ -782,6 +782,34 @@ extern "C" smrt_status smrt_sweep(smrt_ctx *x, const double *sig_t, const double
     });
 }
 
+// 1 in *bad if some sig_t <= 0 or sig < 0 (device-side input check)
+__global__ void k_check_opacities(int64_t n, const double *sig_t, const double *sig, int *bad) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool b = i < n && !(sig_t[i] > 0.0 && sig[i] >= 0.0);
+    if (__builtin_amdgcn_ballot_w64(b) != 0 && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+}
+
+extern "C" smrt_status smrt_sweep_dev(smrt_ctx *x, const double *sig_t, const double *sig, const double *q_iso,
+                                      const double *psi_prev, double inv_c_dt, const double *psi_inflow,
+                                      double *psi_out, double *moments_out) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(sig_t && sig && q_iso && psi_out, "sig_t, sig, q_iso and psi_out are required");
+        require(std::isfinite(inv_c_dt) && inv_c_dt >= 0.0, "inv_c_dt must be finite and >= 0");
+        const int64_t ng = (int64_t)x->ncell * x->G;
+        DevBuf<int> bad;
+        bad.alloc(1);
+        bad.zero(x->stream);
+        hipLaunchKernelGGL(k_check_opacities, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, x->stream, ng, sig_t,
+                           sig, bad.p);
+        int hb = 0;
+        d2h(&hb, bad.p, sizeof(int), x->stream);
+        SMRT_HIP(hipStreamSynchronize(x->stream));
+        require(hb == 0, "sig_t must be > 0 and sig >= 0");
+        raw_sweep(x, sig_t, sig, q_iso, psi_prev, inv_c_dt, psi_inflow, psi_out, moments_out);
+    });
+}
+
 // Adjoint sweep (transpose of the lumped upwind DG operator).  With every
 // form lumped on a rectilinear mesh the transpose of the operator of
 // direction Omega is the operator of -Omega (the local matrices are

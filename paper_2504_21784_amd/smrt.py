@@ -87,6 +87,8 @@ _SIGS = {
     "smrt_set_state": ([C.c_void_p, _dp, _dp], C.c_int),
     "smrt_get_state": ([C.c_void_p, _dp, _dp, _dp, _dp], C.c_int),
     "smrt_sweep": ([C.c_void_p, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp], C.c_int),
+    "smrt_sweep_dev": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                        C.c_void_p, C.c_void_p], C.c_int),
     "smrt_compute_closures": ([C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp], C.c_int),
     "smrt_lo_solve": ([C.c_void_p, _dp, _dp, C.c_double, _dp, _dp, _dp, C.POINTER(StepStats)], C.c_int),
     "smrt_step": ([C.c_void_p, C.c_double, C.POINTER(StepStats)], C.c_int),
@@ -252,6 +254,29 @@ class Context:
         self._check(self.L.smrt_sweep(self.h, *[_p(a) for a in args], _p(pp), float(inv_c_dt), _p(inf), _p(psi),
                                       _p(mom)))
         return psi, mom
+
+    def sweep_dev(self, sig_t, sig, q_iso, psi_prev, inv_c_dt, inflow=None, psi_out=None, moments_out=None):
+        """smrt_sweep on device tensors (float64, contiguous, on the context's GPU), no host round trip.
+        Returns (psi_out, moments_out or None); psi_out is allocated if not given."""
+        import torch
+        p = self.p
+        want = {"sig_t": (p.n_cells, p.G), "sig": (p.n_cells, p.G), "q_iso": (p.n_nodes, p.G),
+                "psi_prev": (p.n_angles, p.G, p.n_nodes), "inflow": (p.n_angles, p.G, 2 if p.dim == 1 else 4 * (p.nx + p.ny)),
+                "psi_out": (p.n_angles, p.G, p.n_nodes), "moments_out": (27 if p.dim == 2 else 8, p.n_nodes)}
+        if psi_out is None:
+            psi_out = torch.empty(want["psi_out"], dtype=torch.float64, device=sig_t.device)
+        args = dict(sig_t=sig_t, sig=sig, q_iso=q_iso, psi_prev=psi_prev, inflow=inflow, psi_out=psi_out,
+                    moments_out=moments_out)
+        for name, t in args.items():
+            if t is None:
+                continue
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == want[name]):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {want[name]}")
+        ptr = {k: (v.data_ptr() if v is not None else None) for k, v in args.items()}
+        torch.cuda.current_stream(sig_t.device).synchronize()   # inputs ready before the context stream reads them
+        self._check(self.L.smrt_sweep_dev(self.h, ptr["sig_t"], ptr["sig"], ptr["q_iso"], ptr["psi_prev"],
+                                          float(inv_c_dt), ptr["inflow"], ptr["psi_out"], ptr["moments_out"]))
+        return psi_out, moments_out
 
     def adjoint_sweep(self, sig_t, src, emis=None, psi_fwd=None, want_dsig=False):
         """lambda = L^{-T}(w . src) per (d, g); with want_dsig also the opacity

@@ -182,3 +182,30 @@ def test_sweep_rejects_bad_input(smrt_mod):
     with pytest.raises(smrt_mod.SmrtError):
         ctx.sweep(sigt, sigt, np.zeros((p.n_nodes, 1)), None, 0.0)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sweep_dev_matches_host_sweep(smrt_mod, prec):
+    """The device-array entry point runs the same kernels on torch tensors:
+    bitwise equal to the host-array sweep; bad opacities are caught on the
+    device, bad tensors by the binding."""
+    import torch
+    p = _prob2d(29, 23, 4, 3, seed=17)
+    sigt, q, pp, inf = W.random_sweep_inputs(p, seed=18)
+    sig = 0.6 * sigt
+    ctx = smrt_mod.Context(p, precision=prec)
+    psi_h, mom_h = ctx.sweep(sigt, sig, q, pp, 0.4, inf)
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in
+         dict(sigt=sigt, sig=sig, q=q, pp=pp, inf=inf).items()}
+    mom_d = torch.zeros((27, p.n_nodes), dtype=torch.float64, device=dev)
+    psi_d, _ = ctx.sweep_dev(t["sigt"], t["sig"], t["q"], t["pp"], 0.4, t["inf"], moments_out=mom_d)
+    assert np.array_equal(psi_d.cpu().numpy(), psi_h)
+    assert np.array_equal(mom_d.cpu().numpy(), mom_h)
+    bad = t["sigt"].clone()
+    bad[3, 1] = -1.0
+    with pytest.raises(smrt_mod.SmrtError):
+        ctx.sweep_dev(bad, t["sig"], t["q"], t["pp"], 0.4, t["inf"])
+    with pytest.raises(ValueError):
+        ctx.sweep_dev(t["sigt"].float(), t["sig"], t["q"], t["pp"], 0.4, t["inf"])
+    ctx.close()
