@@ -706,16 +706,29 @@ extern "C" smrt_status smrt_get_state(smrt_ctx *x, double *T, double *E, double 
 // [cell][G]; q [node][G]; prev (psi_prev, or nullptr) [d][g][node]; inflow
 // (nullptr: the context's boundary inflow) [d][g][NB]; out [d][g][node];
 // mom (or nullptr) [27|8][node].
+// Device scratch of a raw sweep (tables, internal-layout intensities, inflow,
+// moments); a caller that sweeps many times keeps one and passes it in.
+struct RawScratch {
+    DevBuf<unsigned char> sig2, qiso, in, out, inflow;
+    DevBuf<double> mom;
+};
+template <typename T>
+static void ensure(DevBuf<T> &b, int64_t n) {
+    if (b.n != n) b.alloc(n);
+}
+
 static void raw_sweep(smrt_ctx *x, const double *sig_t, const double *sig, const double *q, const double *prev,
-                      double inv_c_dt, const double *inflow64, double *out, double *mom) {
+                      double inv_c_dt, const double *inflow64, double *out, double *mom, RawScratch *scratch = nullptr) {
     const int64_t na = (int64_t)x->nang * x->G * x->nn;
     const int64_t tab_cells = x->dim == 2 ? 4 * cell_slab(x->nx, x->ny) : x->ncell;
-    DevBuf<unsigned char> t_sig2, t_qiso, t_in, t_out, t_inflow;
-    t_sig2.alloc(tab_cells * x->G * 2 * x->rs);
-    t_qiso.alloc(tab_cells * x->G * x->npc * x->rs);
-    t_in.alloc(psi_count(x) * x->rs);
-    t_out.alloc(psi_count(x) * x->rs);
-    t_inflow.alloc((int64_t)x->nang * x->G * x->NB * x->rs);
+    RawScratch local;
+    RawScratch &R = scratch ? *scratch : local;
+    ensure(R.sig2, tab_cells * x->G * 2 * x->rs);
+    ensure(R.qiso, tab_cells * x->G * x->npc * x->rs);
+    ensure(R.in, psi_count(x) * x->rs);
+    ensure(R.out, psi_count(x) * x->rs);
+    ensure(R.inflow, (int64_t)x->nang * x->G * x->NB * x->rs);
+    DevBuf<unsigned char> &t_sig2 = R.sig2, &t_qiso = R.qiso, &t_in = R.in, &t_out = R.out, &t_inflow = R.inflow;
     auto tables = [&](auto zero) {
         using real = decltype(zero);
         if (x->dim == 2) {
@@ -733,10 +746,9 @@ static void raw_sweep(smrt_ctx *x, const double *sig_t, const double *sig, const
     };
     if (x->fp32) tables(0.0f);
     else tables(0.0);
-    DevBuf<double> m;
     if (!mom) {
-        m.alloc((int64_t)(x->dim == 2 ? 27 : 8) * x->nn);
-        mom = m.p;
+        ensure(R.mom, (int64_t)(x->dim == 2 ? 27 : 8) * x->nn);
+        mom = R.mom.p;
     }
     run_sweep(x, prev ? t_in.p : nullptr, t_out.p, t_sig2.p, t_qiso.p, inflow64 ? t_inflow.p : x->d_inflow.p, inv_c_dt,
               sig, mom);
@@ -1580,10 +1592,10 @@ extern "C" smrt_status smrt_set_materials(smrt_ctx *x, const double *sigma0, con
 // sensitivities of the opacity and heat-capacity terms.
 // ---------------------------------------------------------------------------
 static void adjoint_sweep_dev(smrt_ctx *x, const double *sigt, const double *src, double *lam, double *prev_tmp,
-                              double *out_tmp, const double *zq, const double *zinf) {
+                              double *out_tmp, const double *zq, const double *zinf, RawScratch *scratch = nullptr) {
     const int64_t per = (int64_t)x->G * x->nn;
     run_permute_dirs(x->stream, x->nang, per, x->d_opposite.p, src, prev_tmp);
-    raw_sweep(x, sigt, sigt, zq, prev_tmp, 1.0, zinf, out_tmp, nullptr);
+    raw_sweep(x, sigt, sigt, zq, prev_tmp, 1.0, zinf, out_tmp, nullptr, scratch);
     run_permute_dirs(x->stream, x->nang, per, x->d_opposite.p, out_tmp, lam);
 }
 
@@ -1671,6 +1683,13 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
         emis.alloc((int64_t)nn * G); dE.alloc((int64_t)nn * G); phi.alloc((int64_t)nn * G); D.alloc(nn);
         dsig.alloc(ncg); gs_cell.alloc(nc); gcv_node.alloc(nn); gs.alloc(nreg); gc.alloc(nreg);
         lam_next.zero(S); zq.zero(S); zinf.zero(S); ST.zero(S); gs.zero(S); gc.zero(S);
+        // Anderson acceleration of each step's temperature iteration (window AA_M)
+        constexpr int AA_M = 5;
+        static_assert(AA_M <= AA_MAX, "Anderson window too large");
+        DevBuf<double> dFr, dGr, fprev, gprev, aapart, aaout;
+        dFr.alloc((int64_t)AA_M * nn); dGr.alloc((int64_t)AA_M * nn); fprev.alloc(nn); gprev.alloc(nn);
+        aapart.alloc((int64_t)2 * AA_M * ((nn + 255) / 256)); aaout.alloc(2 * AA_M);
+        RawScratch rsc;   // the adjoint sweeps' scratch, allocated once
         // objective 1: dJ/dT^N = w c_v enters the energy-balance adjoint of the last step
         if (objective == 1) run_add_scalar(S, nn, wc.p, 0.0, ST.p);
         const double icdt = 1.0 / (x->c * dt);
@@ -1681,24 +1700,90 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
             run_add_scalar(S, ncg, sig, icdt, sigt.p);
             run_adj_prep(S, nn, npc, G, x->nang, x->d_nu.p, x->a, x->c, dt, T, sig, x->d_cvn.p, x->d_w.p, psi, emis.p,
                          dE.p, D.p, phi.p);
+            // tau <- g(tau) = (pointwise temperature adjoint)(adjoint sweep(tau)), a linear
+            // fixed point, solved by Anderson acceleration: tau_{k+1} = g_k - dG gamma with
+            // gamma = argmin |f_k - dF gamma| over the last AA_M differences of f = g - tau
+            // and g (normal equations, Cholesky); a failed solve restarts the window.
             tau.zero(S);
+            int win[AA_M], nwin = 0, next_slot = 0;
+            double Mg[AA_M][AA_M] = {};
             for (int it = 0; it < 500; ++it) {
                 run_adj_src(S, x->dim, x->nx, ny1, G, x->nang, x->d_hx64.p, hy, x->d_w.p, dJdI.p, lam_next.p, icdt, sig,
                             tau.p, src.p);
-                adjoint_sweep_dev(x, sigt.p, src.p, lam.p, prev_tmp.p, out_tmp.p, zq.p, zinf.p);
+                adjoint_sweep_dev(x, sigt.p, src.p, lam.p, prev_tmp.p, out_tmp.p, zq.p, zinf.p, &rsc);
                 run_adj_tau(S, x->dim, x->nx, ny1, G, x->nang, x->d_hx64.p, hy, sig, dE.p, ST.p, D.p, lam.p, tau.p,
                             tau_new.p, part.p, scal.p);
                 double nd[2];
                 d2h(nd, scal.p, 16, S);
                 SMRT_HIP(hipStreamSynchronize(S));
-                std::swap(tau.p, tau_new.p);
                 ++iters;
-                if (!(nd[0] > 1e-30 * nd[1]) || nd[1] == 0.0) break;
+                if (!(nd[0] > 1e-30 * nd[1]) || nd[1] == 0.0) {   // |g - tau| small: keep g
+                    std::swap(tau.p, tau_new.p);
+                    break;
+                }
+                const int slot = next_slot;
+                run_aa_columns(S, nn, tau.p, tau_new.p, fprev.p, gprev.p, dFr.p + (int64_t)slot * nn,
+                               dGr.p + (int64_t)slot * nn, it == 0);
+                if (it == 0) {   // no history yet: a plain step
+                    std::swap(tau.p, tau_new.p);
+                    continue;
+                }
+                if (nwin == AA_M) {
+                    for (int c = 0; c + 1 < AA_M; ++c) win[c] = win[c + 1];
+                    --nwin;
+                }
+                win[nwin++] = slot;
+                next_slot = (slot + 1) % AA_M;
+                AASlots sl{};
+                for (int c = 0; c < nwin; ++c) sl.s[c] = win[c];
+                run_aa_dots(S, nn, nwin, sl, dFr.p, dFr.p + (int64_t)slot * nn, fprev.p, aapart.p, aaout.p);
+                double dots[2 * AA_M];
+                d2h(dots, aaout.p, sizeof(double) * 2 * nwin, S);
+                SMRT_HIP(hipStreamSynchronize(S));
+                double b[AA_M], A[AA_M][AA_M], L[AA_M][AA_M] = {};
+                for (int c = 0; c < nwin; ++c) {
+                    Mg[win[c]][slot] = Mg[slot][win[c]] = dots[2 * c];
+                    b[c] = dots[2 * c + 1];
+                }
+                double dmax = 0.0;
+                for (int i = 0; i < nwin; ++i) dmax = std::max(dmax, Mg[win[i]][win[i]]);
+                for (int i = 0; i < nwin; ++i)
+                    for (int j = 0; j < nwin; ++j) A[i][j] = Mg[win[i]][win[j]] + (i == j ? 1e-13 * dmax : 0.0);
+                bool ok = dmax > 0.0;
+                for (int i = 0; i < nwin && ok; ++i)   // Cholesky A = L L^T
+                    for (int j = 0; j <= i; ++j) {
+                        double v = A[i][j];
+                        for (int k2 = 0; k2 < j; ++k2) v -= L[i][k2] * L[j][k2];
+                        if (i == j) {
+                            if (!(v > 0.0)) { ok = false; break; }
+                            L[i][i] = std::sqrt(v);
+                        } else {
+                            L[i][j] = v / L[j][j];
+                        }
+                    }
+                if (!ok) {   // restart the history with a plain step
+                    nwin = 0;
+                    std::swap(tau.p, tau_new.p);
+                    continue;
+                }
+                double y[AA_M];
+                for (int i = 0; i < nwin; ++i) {
+                    double v = b[i];
+                    for (int k2 = 0; k2 < i; ++k2) v -= L[i][k2] * y[k2];
+                    y[i] = v / L[i][i];
+                }
+                AACoef gm{};
+                for (int i = nwin - 1; i >= 0; --i) {
+                    double v = y[i];
+                    for (int k2 = i + 1; k2 < nwin; ++k2) v -= L[k2][i] * gm.v[k2];
+                    gm.v[i] = v / L[i][i];
+                }
+                run_aa_update(S, nn, nwin, sl, gm, dGr.p, tau_new.p, tau.p);
             }
             // lam consistent with the final tau, then the sensitivities of this step
             run_adj_src(S, x->dim, x->nx, ny1, G, x->nang, x->d_hx64.p, hy, x->d_w.p, dJdI.p, lam_next.p, icdt, sig,
                         tau.p, src.p);
-            adjoint_sweep_dev(x, sigt.p, src.p, lam.p, prev_tmp.p, out_tmp.p, zq.p, zinf.p);
+            adjoint_sweep_dev(x, sigt.p, src.p, lam.p, prev_tmp.p, out_tmp.p, zq.p, zinf.p, &rsc);
             run_adjoint_dsig(S, x->dim, x->nx, ny1, G, x->nang, x->d_hx64.p, hy, lam.p, emis.p, psi, dsig.p);
             run_adj_cell(S, npc, nc, G, x->model, x->clip_lo, x->clip_hi, dt, dsig.p, tau.p, phi.p, emis.p, sig,
                          x->d_cvn.p, T, Tp, gs_cell.p, gcv_node.p, ST_prev.p);

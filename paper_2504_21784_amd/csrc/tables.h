@@ -50,6 +50,18 @@ void run_region_sums(hipStream_t s, int nreg, int ncell, int npc, const int *reg
 void run_adj_energy_weights(hipStream_t s, int dim, int nx, int npc, int nn, const double *hx, const double *hy,
                             const double *cvn, double *wc);
 void run_mul(hipStream_t s, int64_t n, const double *a, const double *b, double *out);
+// Anderson acceleration of the adjoint temperature iteration: history columns
+// (ring of AA_MAX slots of nn doubles), their dot products, the update.
+constexpr int AA_MAX = 8;
+struct AASlots { int s[AA_MAX]; };
+struct AACoef { double v[AA_MAX]; };
+void run_aa_columns(hipStream_t s, int nn, const double *tau, const double *g, double *fprev, double *gprev,
+                    double *dF, double *dG, bool first);
+// out[2c] = <col_c, a>, out[2c+1] = <col_c, b>; part: scratch of 2 * ncols * ceil(nn / 256) doubles
+void run_aa_dots(hipStream_t s, int nn, int ncols, const AASlots &sl, const double *cols, const double *a,
+                 const double *b, double *part, double *out);
+void run_aa_update(hipStream_t s, int nn, int ncols, const AASlots &sl, const AACoef &gm, const double *dG,
+                   const double *g, double *tau);
 // part256: scratch of 256 doubles
 void run_dot(hipStream_t s, int64_t n, const double *a, const double *b, double *part256, double *out);
 void run_add_scalar(hipStream_t s, int64_t n, const double *a, double v, double *out);

@@ -523,6 +523,57 @@ __global__ void k_adj_tau(int dim, int nx, int ny, int G, int nang, const double
     }
 }
 
+// Anderson acceleration of the adjoint temperature iteration tau <- g(tau):
+// f = g - tau; unless first, dF = f - f_prev and dG = g - g_prev (a new
+// history column); then f_prev = f, g_prev = g.
+__global__ void k_aa_columns(int nn, const double *tau, const double *g, double *fprev, double *gprev, double *dF,
+                             double *dG, int first) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const double gn = g[n], f = gn - tau[n];
+    if (!first) {
+        dF[n] = f - fprev[n];
+        dG[n] = gn - gprev[n];
+    }
+    fprev[n] = f;
+    gprev[n] = gn;
+}
+// block partials of <col_c, a> and <col_c, b> for the ncols history columns
+// col_c = cols + slot[c] * nn: part[(2 c + j) * nblocks + block]
+__global__ void __launch_bounds__(256) k_aa_dots(int nn, int ncols, AASlots sl, const double *cols, const double *a,
+                                                 const double *b, double *part) {
+    __shared__ double sh[256];
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    for (int q = 0; q < 2 * ncols; ++q) {
+        const double *col = cols + (int64_t)sl.s[q >> 1] * nn;
+        const double *v = (q & 1) ? b : a;
+        sh[threadIdx.x] = n < nn ? col[n] * v[n] : 0.0;
+        __syncthreads();
+        for (int k = 128; k > 0; k >>= 1) {
+            if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)q * gridDim.x + blockIdx.x] = sh[0];
+        __syncthreads();
+    }
+}
+// out[q] = sum over blocks of part[q * nb + block] (fixed order), q < nq
+__global__ void k_aa_dots_finish(int nb, int nq, const double *part, double *out) {
+    const int q = threadIdx.x;
+    if (q >= nq) return;
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += part[(int64_t)q * nb + k];
+    out[q] = s;
+}
+// tau = g - sum_c gamma_c dG[slot c]
+__global__ void k_aa_update(int nn, int ncols, AASlots sl, AACoef gm, const double *dG, const double *g, double *tau) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double t = g[n];
+    for (int c = 0; c < ncols; ++c) t -= gm.v[c] * dG[(int64_t)sl.s[c] * nn + n];
+    tau[n] = t;
+}
+
 // sum of nb pairs of block partials in a fixed order (one thread)
 __global__ void k_sum_pairs(int nb, const double *part, double *out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -846,6 +897,21 @@ void run_adj_tau(hipStream_t s, int dim, int nx, int ny, int G, int nang, const 
     hipLaunchKernelGGL(k_adj_tau, dim3(nb), dim3(256), 0, s, dim, nx, ny, G, nang, hx, hy, sig, dE, ST, D, lam, tau,
                        tau_new, part);
     hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(64), 0, s, nb, part, out2);
+}
+void run_aa_columns(hipStream_t s, int nn, const double *tau, const double *g, double *fprev, double *gprev,
+                    double *dF, double *dG, bool first) {
+    hipLaunchKernelGGL(k_aa_columns, dim3(nblk(nn, 256)), dim3(256), 0, s, nn, tau, g, fprev, gprev, dF, dG,
+                       first ? 1 : 0);
+}
+void run_aa_dots(hipStream_t s, int nn, int ncols, const AASlots &sl, const double *cols, const double *a,
+                 const double *b, double *part, double *out) {
+    const int nb = nblk(nn, 256);
+    hipLaunchKernelGGL(k_aa_dots, dim3(nb), dim3(256), 0, s, nn, ncols, sl, cols, a, b, part);
+    hipLaunchKernelGGL(k_aa_dots_finish, dim3(1), dim3(64), 0, s, nb, 2 * ncols, part, out);
+}
+void run_aa_update(hipStream_t s, int nn, int ncols, const AASlots &sl, const AACoef &gm, const double *dG,
+                   const double *g, double *tau) {
+    hipLaunchKernelGGL(k_aa_update, dim3(nblk(nn, 256)), dim3(256), 0, s, nn, ncols, sl, gm, dG, g, tau);
 }
 void run_adj_cell(hipStream_t s, int npc, int ncell, int G, int model, double clip_lo, double clip_hi, double dt,
                   const double *dsig, const double *tau, const double *phi, const double *emis, const double *sig,

@@ -160,3 +160,35 @@ def test_adjoint_rejects_unknown_objective(smrt_mod):
     with pytest.raises(smrt_mod.SmrtError):
         ctx.adjoint(1, objective=2)
     ctx.close()
+
+
+@pytest.mark.parametrize("objective", [0, 1])
+def test_adjoint_full_size_finite_differences(smrt_mod, objective):
+    """The adjoint configuration at full size (128x128, S8, 8 groups, 64 regions
+    of sigma0 and c_v, 10 steps of dt = 1e-3, FP64): the two largest gradient
+    components of each kind against central finite differences (h = 1e-4)."""
+    p = W.adjoint_2d()
+    print(f"adjoint 128x128 S8 G8, 10 steps, objective {objective}", flush=True)
+    tight = dict(eps_outer=1e-10, eps_inner=1e-11, cg_rtol=1e-13, elim_rtol=1e-15, max_outer=200, max_inner=60,
+                 max_cg=500, max_elim=100)
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **tight)
+    T0 = p.initial_T_nodes()
+    ctx.set_state(T0)
+    J, gs, gc, _ = ctx.adjoint(p.n_steps, objective=objective)
+
+    def J_at(s0, cv):
+        ctx.set_materials(s0, cv)
+        ctx.set_state(T0)
+        return ctx.adjoint(p.n_steps, objective=objective)[0]
+
+    h = 1e-4
+    for g, which in ((gs, 0), (gc, 1)):
+        for r in np.argsort(-np.abs(g))[:2]:
+            e = np.zeros(p.n_regions)
+            e[r] = h
+            if which == 0:
+                fd = (J_at(p.sigma0 * np.exp(e), p.cv) - J_at(p.sigma0 * np.exp(-e), p.cv)) / (2 * h)
+            else:
+                fd = (J_at(p.sigma0, p.cv * np.exp(e)) - J_at(p.sigma0, p.cv * np.exp(-e))) / (2 * h)
+            assert abs(g[r] - fd) <= 1e-4 * abs(fd), (which, r, g[r], fd)
+    ctx.close()

@@ -149,6 +149,27 @@ def test_step_fp32_error_budget(smrt_mod, oracle_mod):
         assert np.linalg.norm(got["T"] - ref["T"]) / np.linalg.norm(ref["T"]) < 1e-6
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gray_2d_full_size_steps(smrt_mod, oracle_mod, prec):
+    """The gray 2D configuration at full size (128x128, S8, 1 group, sigma per
+    8x8-cell block log-uniform in [0.1, 1000], left inflow at T = 1, dt = 1e-3),
+    three steps against the oracle: FP64 to 1e-10 in T, E and I; the FP32 sweep
+    within the FP32 budget (phi 1e-5, T 1e-6 relative L2)."""
+    p = W.gray_2d(n=128, sn=8, block=8, seed=2)
+    print(f"gray 2D 128x128 S8, precision {prec}", flush=True)
+    for ref, ost, got, gst in _run_steps(smrt_mod, oracle_mod, p, 3, 0, prec, dict(TIGHT)):
+        if prec == 0:
+            assert _rel(got["T"], ref["T"]) < 1e-10
+            assert _rel(got["E"], ref["E"]) < 1e-10
+            assert _rel(got["psi"], ref["psi"]) < 1e-10
+            assert abs(gst["outer"] - ost["outer"]) <= 1
+        else:
+            phi_ref = np.einsum("d,dgn->n", p.w, ref["psi"])
+            phi = np.einsum("d,dgn->n", p.w, got["psi"])
+            assert np.linalg.norm(phi - phi_ref) / np.linalg.norm(phi_ref) < 1e-5
+            assert np.linalg.norm(got["T"] - ref["T"]) / np.linalg.norm(ref["T"]) < 1e-6
+
+
 def test_step_rejects_bad_dt(smrt_mod):
     p = W.gray_2d(n=8, sn=4, block=4)
     ctx = smrt_mod.Context(p)
