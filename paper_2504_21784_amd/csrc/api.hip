@@ -1051,19 +1051,33 @@ struct StepRun {
 };
 
 // time one stream-ordered section (ms)
+// a pair of events released on every exit path
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    EventPair() {
+        SMRT_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            throw Error(SMRT_E_DEVICE, "hipEventCreate failed");
+        }
+    }
+    ~EventPair() {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+};
+
 template <typename F>
 static float timed(hipStream_t S, F &&f) {
-    hipEvent_t e0, e1;
-    SMRT_HIP(hipEventCreate(&e0));
-    SMRT_HIP(hipEventCreate(&e1));
-    SMRT_HIP(hipEventRecord(e0, S));
+    EventPair ev;
+    SMRT_HIP(hipEventRecord(ev.e0, S));
     f();
-    SMRT_HIP(hipEventRecord(e1, S));
-    SMRT_HIP(hipEventSynchronize(e1));
+    SMRT_HIP(hipEventRecord(ev.e1, S));
+    SMRT_HIP(hipEventSynchronize(ev.e1));
     float ms = 0.f;
-    SMRT_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    SMRT_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
     return ms;
 }
 
@@ -1091,15 +1105,14 @@ extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, 
         require(dt > 0.0 && n_times >= 1 && ms_per_pass && ms_sweep_kernel, "invalid argument");
         require(x->have_state, "smrt_set_state must be called first");
         void *pin = x->d_psi[x->cur].p, *pout = x->d_psi[1 - x->cur].p;
-        std::vector<hipEvent_t> ev(2 * n_times);
-        for (auto &e : ev) SMRT_HIP(hipEventCreate(&e));
+        std::vector<EventPair> evp(n_times);   // released on every exit path
         SMRT_HIP(hipEventRecord(x->ev0, x->stream));
         for (int k = 0; k < n_times; ++k) {
             const double icdt = prepare_step_tables(x, dt);
             run_source_at(x, x->d_T.p);
-            SMRT_HIP(hipEventRecord(ev[2 * k], x->stream));
+            SMRT_HIP(hipEventRecord(evp[k].e0, x->stream));
             run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p, false);
-            SMRT_HIP(hipEventRecord(ev[2 * k + 1], x->stream));
+            SMRT_HIP(hipEventRecord(evp[k].e1, x->stream));
             if (x->dim == 2) {
                 if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, x->d_sigq.p, x->d_mom.p);
                 else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, x->d_sigq.p, x->d_mom.p);
@@ -1116,10 +1129,9 @@ extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, 
         SMRT_HIP(hipEventElapsedTime(&ms, x->ev0, x->ev1));
         for (int k = 0; k < n_times; ++k) {
             float t = 0.f;
-            SMRT_HIP(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
+            SMRT_HIP(hipEventElapsedTime(&t, evp[k].e0, evp[k].e1));
             ks += t;
         }
-        for (auto &e : ev) (void)hipEventDestroy(e);
         *ms_per_pass = ms / n_times;
         *ms_sweep_kernel = ks / n_times;
         check_sweep_flag(x);
