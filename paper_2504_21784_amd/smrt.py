@@ -20,6 +20,8 @@ SMRT_FP64, SMRT_FP32 = 0, 1
 SMRT_SM_CONSISTENT, SMRT_SM_INDEPENDENT, SMRT_UNACCELERATED = 0, 1, 2
 STATUS = {0: "SMRT_OK", 1: "SMRT_E_INVALID_ARG", 2: "SMRT_E_OUT_OF_MEMORY", 3: "SMRT_E_DEVICE",
           4: "SMRT_E_NOT_CONVERGED", 5: "SMRT_E_NONPHYSICAL", 6: "SMRT_E_STATE"}
+(SMRT_OK, SMRT_E_INVALID_ARG, SMRT_E_OUT_OF_MEMORY, SMRT_E_DEVICE, SMRT_E_NOT_CONVERGED, SMRT_E_NONPHYSICAL,
+ SMRT_E_STATE) = range(7)
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)

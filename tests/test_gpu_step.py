@@ -202,3 +202,37 @@ def test_lo_graph_replay_matches_direct_launches(smrt_mod):
     assert ca == cb and sum(ca) > 0
     for k in ("T", "E", "F"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_step_iteration_cap_strict_and_relaxed(smrt_mod):
+    """A capped outer iteration: strict = 1 returns SMRT_E_NOT_CONVERGED;
+    strict = 0 returns OK with hit_max set (the paper continues past capped
+    steps)."""
+    p = W.gray_2d(n=16, sn=4, block=4, seed=2)
+    opts = dict(TIGHT, max_outer=1)
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **opts)
+    ctx.set_state(p.initial_T_nodes())
+    st = ctx.step()
+    assert st["hit_max"] == 1 and st["outer"] == 1
+    ctx.close()
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, strict=1, **opts)
+    ctx.set_state(p.initial_T_nodes())
+    with pytest.raises(smrt_mod.SmrtError) as e:
+        ctx.step()
+    assert e.value.status == smrt_mod.SMRT_E_NOT_CONVERGED
+    ctx.close()
+
+
+def test_lo_nonphysical_energy_balance(smrt_mod):
+    """A strongly negative energy source drives the LO radiation energy below
+    zero: the pointwise energy balance has no positive temperature root and
+    the solve reports SMRT_E_NONPHYSICAL (no floor, no fixup)."""
+    p = W.gray_2d(n=8, sn=4, block=4, seed=2)
+    nn = p.n_nodes
+    T = p.initial_T_nodes()
+    rows = np.vstack([np.ones(nn), np.ones(nn), np.ones(nn), np.full(nn, -1.0e6), np.zeros((p.dim, nn))])
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **TIGHT)
+    with pytest.raises(smrt_mod.SmrtError) as e:
+        ctx.lo_solve(rows, T, p.dt, p.a * T ** 4, T)
+    assert e.value.status == smrt_mod.SMRT_E_NONPHYSICAL
+    ctx.close()
