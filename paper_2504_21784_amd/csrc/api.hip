@@ -917,11 +917,11 @@ static double prepare_step_tables(smrt_ctx *x, double dt) {
     const double icdt = 1.0 / (x->c * dt);
     const bool d2 = x->dim == 2;
     if (x->fp32) {
-        run_opacity<float>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, d2 ? nullptr : (float *)x->d_sig2.p);
-        if (d2) run_stab2d<float>(x->stream, x->nx, x->ny, x->G, x->d_sig.p, nullptr, icdt, (float *)x->d_sig2.p);
+        if (d2) run_opacity_tab2d<float>(x->stream, x->nx, x->ny, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, (float *)x->d_sig2.p);
+        else run_opacity<float>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, (float *)x->d_sig2.p);
     } else {
-        run_opacity<double>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, d2 ? nullptr : (double *)x->d_sig2.p);
-        if (d2) run_stab2d<double>(x->stream, x->nx, x->ny, x->G, x->d_sig.p, nullptr, icdt, (double *)x->d_sig2.p);
+        if (d2) run_opacity_tab2d<double>(x->stream, x->nx, x->ny, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, (double *)x->d_sig2.p);
+        else run_opacity<double>(x->stream, x->ncell, x->npc, x->G, x->d_T.p, x->d_region.p, x->model, x->d_sigma0.p, x->clip_lo, x->clip_hi, x->d_nu.p, icdt, x->d_sig.p, (double *)x->d_sig2.p);
     }
     return icdt;
 }

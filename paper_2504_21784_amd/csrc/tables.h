@@ -16,6 +16,11 @@ void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const do
                 const double *sig, real *qiso, real *qnat, double *sigP, double *sigF);
 template <typename real>
 void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab);
+// 2D: opacity sigma[cell][G] and its skewed per-quadrant (sigma_t, sigma) tables in one pass
+template <typename real>
+void run_opacity_tab2d(hipStream_t s, int nx, int ny, int G, const double *T, const int *region, int model,
+                       const double *sigma0, double lo, double hi, const double *nu, double icdt, double *sig,
+                       real *stab);
 template <typename real, typename src_t>
 void run_qtab2d(hipStream_t s, int nx, int ny, int G, const src_t *q, int64_t sn, int64_t sg, real *qtab);
 void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,

@@ -108,25 +108,33 @@ struct GroupFractions {
 // ---------------------------------------------------------------------------
 // Opacity table (once per step)
 // ---------------------------------------------------------------------------
+// cell-average temperature (arithmetic mean of the nodal values) and the
+// group opacity of a cell at it: model 0 sigma0[r][g], model 1
+// sigma0[r] / (nu_g^3 T^3) with nu_g the geometric mean of the group bounds,
+// clipped to [clip_lo, clip_hi]
+__device__ inline double cell_mean_T(int npc, const double *T, int c) {
+    double Tc = 0.0;
+    for (int l = 0; l < npc; ++l) Tc += T[npc * c + l];
+    return Tc / npc;
+}
+__device__ inline double group_opacity(int model, int G, int r, int g, const double *sigma0, const double *nu,
+                                       double Tc, double clip_lo, double clip_hi) {
+    if (model == 0) return sigma0[r * G + g];
+    const double nb = sqrt(nu[g] * nu[g + 1]);
+    const double s = sigma0[r] / (nb * nb * nb * Tc * Tc * Tc);
+    return fmin(fmax(s, clip_lo), clip_hi);
+}
+
 template <typename real>
 __global__ void k_opacity(int ncell, int npc, int G, const double *T, const int *region, int model,
                           const double *sigma0, double clip_lo, double clip_hi, const double *nu,
                           double inv_c_dt, double *sig, real *sig2) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    double Tc = 0.0;
-    for (int l = 0; l < npc; ++l) Tc += T[npc * c + l];
-    Tc /= npc;
+    const double Tc = cell_mean_T(npc, T, c);
     const int r = region[c];
     for (int g = 0; g < G; ++g) {
-        double s;
-        if (model == 0) {
-            s = sigma0[r * G + g];
-        } else {
-            const double nb = sqrt(nu[g] * nu[g + 1]);
-            s = sigma0[r] / (nb * nb * nb * Tc * Tc * Tc);
-            s = fmin(fmax(s, clip_lo), clip_hi);
-        }
+        const double s = group_opacity(model, G, r, g, sigma0, nu, Tc, clip_lo, clip_hi);
         sig[(int64_t)c * G + g] = s;
         if (sig2) {
             sig2[2 * ((int64_t)g * ncell + c)] = (real)(s + inv_c_dt);
@@ -221,6 +229,47 @@ __global__ void k_stab2d(int nx, int ny, int G, const double *__restrict__ sig, 
                 out[((int64_t)q * G + g0 + k) * cs + slot] = v;
             }
         }
+    }
+}
+
+// 2D opacity and its skewed per-quadrant tables in one pass: one thread per
+// (quadrant, skewed slot) evaluates its cell's opacities from the nodal
+// temperatures (four quadrants recompute a cell's values, cheaper than
+// reading them back), writes (sigma + 1/(c dt), sigma) for every group, and
+// the quadrant-0 thread of the cell also writes sigma[cell][G].  A padding
+// slot stores (1, 0).
+template <typename real>
+__global__ void k_opacity_tab2d(int nx, int ny, int G, const double *__restrict__ T, const int *__restrict__ region,
+                                int model, const double *__restrict__ sigma0, double clip_lo, double clip_hi,
+                                const double *__restrict__ nu, double icdt, double *__restrict__ sig,
+                                real *__restrict__ stab) {
+    const int64_t cs = cell_slab(nx, ny);
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 4 * cs) return;
+    const int64_t slot = i % cs;
+    const int q = (int)(i / cs);
+    int cell = 0, flip;
+    const bool on = skew_to_cell(nx, ny, q, slot, cell, flip);
+    using r2 = typename std::conditional<sizeof(real) == 4, float2, double2>::type;
+    r2 *__restrict__ out = reinterpret_cast<r2 *>(stab);
+    if (!on) {
+        for (int g = 0; g < G; ++g) {
+            r2 v;
+            v.x = real(1);
+            v.y = real(0);
+            out[((int64_t)q * G + g) * cs + slot] = v;
+        }
+        return;
+    }
+    const double Tc = cell_mean_T(4, T, cell);
+    const int r = region[cell];
+    for (int g = 0; g < G; ++g) {
+        const double s = group_opacity(model, G, r, g, sigma0, nu, Tc, clip_lo, clip_hi);
+        r2 v;
+        v.x = (real)(s + icdt);
+        v.y = (real)s;
+        out[((int64_t)q * G + g) * cs + slot] = v;
+        if (q == 0) sig[(int64_t)cell * G + g] = s;
     }
 }
 
@@ -817,6 +866,14 @@ void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const do
     hipLaunchKernelGGL(k_source<real>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, npc, G, T, nu, a, c, sig, qiso, qnat, sigP, sigF);
 }
 template <typename real>
+void run_opacity_tab2d(hipStream_t s, int nx, int ny, int G, const double *T, const int *region, int model,
+                       const double *sigma0, double lo, double hi, const double *nu, double icdt, double *sig,
+                       real *stab) {
+    const int64_t n = 4 * cell_slab(nx, ny);
+    hipLaunchKernelGGL(k_opacity_tab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, T, region, model, sigma0,
+                       lo, hi, nu, icdt, sig, stab);
+}
+template <typename real>
 void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab) {
     const int64_t n = 4 * cell_slab(nx, ny);
     hipLaunchKernelGGL(k_stab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, sig, sigt, icdt, stab);
@@ -973,6 +1030,8 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
                                    const double *, real *, real *, double *, double *);                             \
     template void run_fill_inflow<real>(hipStream_t, int, int, int, int, int, const double *, real *);              \
     template void run_stab2d<real>(hipStream_t, int, int, int, const double *, const double *, double, real *);     \
+    template void run_opacity_tab2d<real>(hipStream_t, int, int, int, const double *, const int *, int,            \
+                                          const double *, double, double, const double *, double, double *, real *); \
     template void run_qtab2d<real, double>(hipStream_t, int, int, int, const double *, int64_t, int64_t, real *);  \
     template void run_copy_to<real>(hipStream_t, int64_t, const double *, real *);                                  \
     template void run_copy_from<real>(hipStream_t, int64_t, const real *, double *);                                \
