@@ -209,3 +209,24 @@ def test_sweep_dev_matches_host_sweep(smrt_mod, prec):
     with pytest.raises(ValueError):
         ctx.sweep_dev(t["sigt"].float(), t["sig"], t["q"], t["pp"], 0.4, t["inf"])
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5)])
+def test_sweep2d_s12_max_groups(smrt_mod, oracle_mod, prec, tol):
+    """The top of the supported ranges: level-symmetric S12 (84 angles, 21 per
+    quadrant: three direction blocks) and 64 groups (the maximum: 16 group
+    blocks), ragged mesh, against the oracle element by element."""
+    p = _prob2d(21, 18, 12, 64, seed=31, nonuniform=True)
+    assert p.n_angles == 84 and p.G == 64
+    print(f"S12 G64 21x18 precision {prec}", flush=True)
+    sigt, q, pp, inf = W.random_sweep_inputs(p, seed=32)
+    sig = 0.4 * sigt
+    o = oracle_mod.Oracle(p)
+    ref = o.sweep(sigt, q, pp, 0.6, inf)
+    ref_mom = o.moments(sig, ref)
+    ctx = smrt_mod.Context(p, precision=prec)
+    psi, mom = ctx.sweep(sigt, sig, q, pp, 0.6, inf)
+    assert _rel(psi, ref) < tol
+    for m in range(27):
+        assert _rel(mom[m], ref_mom[m]) < tol, m
+    ctx.close()
