@@ -9,11 +9,15 @@ dt = 1e-3 -- the multigroup throughput configuration.
 One bench step = one resident high-order pass: opacity table, emission and
 gray-collapse tables, the FP32 sweep over all 640 (angle, group) pairs with
 fused moments, the moment finalisation and the SM closure post-pass, with
-every input already in HBM.  value = swept cell*angle*group units per
-second of that pass.  The JSON line also carries the sweep kernel's
-HBM roofline (algorithmic bytes: read I* + write I), the FP64 sweep for
-the FP32-vs-FP64 ratio, and the FP64 CPU oracle timed on a bounded sample
-of the same workload.
+every input already in HBM, on fixed inputs from a mid-run state (two FP64
+time steps from the initial state).  value = swept cell*angle*group units
+per second of that pass.  The JSON line also carries the sweep kernel's
+HBM roofline (algorithmic bytes: read I* + write I; measured bytes from the
+committed counters; the measured device-to-device copy rate as a practical
+ceiling), the FP64 sweep for the FP32-vs-FP64 ratio and errors (one sweep
+and one full step from the same state), full time steps, the batched and
+adjoint workloads, and the FP64 CPU oracle timed on a bounded sample of the
+same workload.
 """
 import argparse
 import json
@@ -210,12 +214,20 @@ def main():
     p = W.multigroup_2d()
     T0 = p.initial_T_nodes()
 
-    def make(prec):
+    def make(prec, T=T0, psi=None):
         ctx = smrt.Context(p, precision=prec, stream=stream)
         if args.waves or args.pairs:
             ctx.set_launch(args.waves, args.pairs if prec == smrt.SMRT_FP32 else min(args.pairs, 1))
-        ctx.set_state(T0)
+        ctx.set_state(T, psi)
         return ctx
+
+    # a mid-run state (two FP64 steps from the initial state): the fixed inputs
+    # of the timed passes and of the FP32-vs-FP64 comparisons
+    c = make(smrt.SMRT_FP64)
+    for _ in range(2):
+        c.step()
+    mid = c.get_state()
+    c.close()
 
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -226,7 +238,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    ctx = make(smrt.SMRT_FP32)
+    ctx = make(smrt.SMRT_FP32, mid["T"], mid["psi"])
     info = ctx.info()
     units = info["units_per_sweep"]
     for _ in range(args.warmup):
@@ -242,6 +254,8 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     k_ms = float(np.mean(kms))
     mom32 = ctx.get_moments()
+    ctx.step()                                  # one full FP32 step from the mid-run state
+    step32 = (ctx.get_moments(), ctx.get_state(with_psi=False)["T"])
     alg_bytes = info["algorithmic_bytes_per_sweep"]
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     sweep_kernel = f"sweep2d_kernel<float, {info['pairs_per_lane']}, {4 if info['pairs_per_lane'] == 1 else 2}, " \
@@ -249,14 +263,41 @@ def main():
     ctx.close()
 
     # FP64 sweep on the same inputs: throughput ratio and FP32 error
-    c64 = make(smrt.SMRT_FP64)
+    c64 = make(smrt.SMRT_FP64, mid["T"], mid["psi"])
     c64.sweep_resident(n_times=1)
     _, k64 = c64.sweep_resident(n_times=max(3, args.steps // 4))
     mom64 = c64.get_moments()
+    c64.step()
+    step64 = (c64.get_moments(), c64.get_state(with_psi=False)["T"])
     c64.close()
-    phi32 = sum(mom32[6 * q] for q in range(4))
-    phi64 = sum(mom64[6 * q] for q in range(4))
-    phi_err = float(np.linalg.norm(phi32 - phi64) / np.linalg.norm(phi64))
+    del mid
+
+    def rel_l2(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def phi(m):
+        return sum(m[6 * q] for q in range(4))
+
+    phi_err = rel_l2(phi(mom32), phi(mom64))
+    step_err = {"phi_rel_l2": rel_l2(phi(step32[0]), phi(step64[0])), "T_rel_l2": rel_l2(step32[1], step64[1])}
+
+    # measured device-to-device copy rate (read + write bytes), the practical
+    # ceiling for mixed traffic, timed with events on torch's stream
+    nc = (1 << 30) // 4
+    a = torch.ones(nc, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rates = []
+    for _ in range(5):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        rates.append(2.0 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    copy_gbs = float(np.median(rates))
+    del a, b
+    traffic = measured_traffic(info)
 
     out = {
         "metric": "swept cell*angle*group unknowns/s (FP32 sweep with fused moments and closures, 1 GPU)",
@@ -283,10 +324,14 @@ def main():
         "fp64_sweep_units_per_s": units / (k64 * 1e-3),
         "fp32_vs_fp64_sweep_speedup": k64 / k_ms,
         "fp32_phi_rel_l2_vs_fp64": phi_err,
+        "fp32_step_vs_fp64_step": step_err,
+        "inputs": "mid-run state: two FP64 steps from the initial state",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(info),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": sweep_kernel,
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs,
+                     "traffic_GBs": (traffic / (k_ms * 1e-3) / 1e9) if traffic else None},
     }
     if not args.no_step:
         out["time_step"] = time_steps(p, T0)
