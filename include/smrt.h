@@ -128,6 +128,16 @@ typedef struct {
     int lo_time_edge;   /* 0: E*, F* = HO sums of I^k (default); 1: LO solution */
     int lo_graphs;      /* 1 (default): the LO conjugate-gradient iterations replay a captured HIP
                            graph of 4 iterations; 0: launched one kernel at a time */
+    int fixup;          /* 1: zero-and-scale negative-flux fixup inside every sweep (Sec. 6, after
+                           Hamilton et al.): a cell whose solution has a negative entry gets those
+                           entries set to 0 and the others scaled by one factor that keeps the
+                           cell's particle balance (the sum of the rows of its local system); a
+                           cell whose balance has a non-positive right side is set to 0.
+                           0 (default): the plain linear sweep */
+    double T_floor;     /* > 0: temperature floor (Sec. 6): the pointwise energy balance returns
+                           max(root, T_floor), and T_floor where it has no positive root, instead
+                           of failing with SMRT_E_NONPHYSICAL.  0 (default): no floor.  In the
+                           problem's temperature units. */
 } smrt_options;
 
 /* Per-step statistics (the columns of the paper's summary tables). */
@@ -247,9 +257,10 @@ smrt_status smrt_set_materials(smrt_ctx *ctx, const double *sigma0, const double
  * contribute no sigma0 sensitivity.  adjoint_iterations (may be NULL)
  * receives the total number of adjoint source iterations.  The context
  * state is advanced by n_steps.  Errors: SMRT_E_INVALID_ARG (objective not
- * 0 or 1,
- * n_steps < 1, dt <= 0, constant-opacity model, quadrature without
- * opposite directions, no state), or the failure of a forward step. */
+ * 0 or 1, n_steps < 1, dt <= 0, constant-opacity model, quadrature without
+ * opposite directions, no state, fixup or T_floor switched on: the adjoint is
+ * that of the linear sweep and the unfloored balance), or the failure of a
+ * forward step. */
 smrt_status smrt_adjoint(smrt_ctx *ctx, int objective, int n_steps, double dt, double *J, double *grad_log_sigma0,
                          double *grad_log_cv, int *adjoint_iterations);
 

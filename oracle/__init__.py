@@ -60,7 +60,8 @@ class BC(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("eps_outer", C.c_double), ("eps_inner", C.c_double), ("cg_rtol", C.c_double),
                 ("elim_rtol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int),
-                ("max_cg", C.c_int), ("max_elim", C.c_int), ("scheme", C.c_int), ("lo_time_edge", C.c_int)]
+                ("max_cg", C.c_int), ("max_elim", C.c_int), ("scheme", C.c_int), ("lo_time_edge", C.c_int),
+                ("fixup", C.c_int), ("T_floor", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -75,7 +76,7 @@ def _declare(L):
     gp, mp, bp, op, sp = C.POINTER(Geom), C.POINTER(Mat), C.POINTER(BC), C.POINTER(Opts), C.POINTER(Stats)
     L.orc_spectra.argtypes = [C.c_int, _dp, C.c_double, _dp, _dp]
     L.orc_opacity.argtypes = [gp, mp, _dp, _dp]
-    L.orc_sweep.argtypes = [gp, _dp, _dp, _dp, C.c_double, _dp, _dp]
+    L.orc_sweep.argtypes = [gp, _dp, _dp, _dp, C.c_double, _dp, C.c_int, _dp]
     L.orc_sweep.restype = C.c_int
     L.orc_adjoint_sweep.argtypes = [gp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_adjoint_sweep.restype = C.c_int
@@ -111,7 +112,7 @@ def default_opts(**kw) -> dict:
     """Tolerances and caps of the paper's numerical results section:
     outer/inner 1e-3, CG 1e-10, elimination 1e-10; caps 100/30/50/40."""
     o = dict(eps_outer=1e-3, eps_inner=1e-3, cg_rtol=1e-10, elim_rtol=1e-10, max_outer=100,
-             max_inner=30, max_cg=50, max_elim=40, scheme=0, lo_time_edge=0)
+             max_inner=30, max_cg=50, max_elim=40, scheme=0, lo_time_edge=0, fixup=0, T_floor=0.0)
     o.update(kw)
     return o
 
@@ -165,13 +166,16 @@ class Oracle:
         self.L.orc_inflow_from_bc(C.byref(self.geom), C.byref(self.bc), _p(a))
         return a
 
-    def sweep(self, sig_t, q_iso, psi_prev, inv_c_dt, inflow):
+    def sweep(self, sig_t, q_iso, psi_prev, inv_c_dt, inflow, fixup=False):
+        """Lumped DG sweep of every (d, g); fixup=True applies the
+        zero-and-scale negative-flux fixup in every cell."""
         p = self.p
         out = np.zeros((p.n_angles, p.G, p.n_nodes))
         st, q = _f64(sig_t), _f64(q_iso)
         pp = _f64(psi_prev) if psi_prev is not None else None
         inf = _f64(inflow) if inflow is not None else None
-        r = self.L.orc_sweep(C.byref(self.geom), _p(st), _p(q), _p(pp), float(inv_c_dt), _p(inf), _p(out))
+        r = self.L.orc_sweep(C.byref(self.geom), _p(st), _p(q), _p(pp), float(inv_c_dt), _p(inf), int(bool(fixup)),
+                             _p(out))
         assert r == 0
         return out
 

@@ -67,6 +67,8 @@ typedef struct {
     int max_outer, max_inner, max_cg, max_elim;
     int scheme;            /* 0 consistent SM, 1 independent SM, 2 unaccelerated */
     int lo_time_edge;      /* 0: E*,F* from HO sums (default), 1: from LO solution */
+    int fixup;             /* 1: zero-and-scale negative-flux fixup in the sweep */
+    double T_floor;        /* > 0: temperature floor of the energy balance */
 } orc_opts;
 
 typedef struct {
@@ -277,18 +279,40 @@ void orc_opacity(const orc_geom *g, const orc_mat *m, const double *T_nodes, dou
 }
 
 /* ------------------------------------------------------------------------ */
+/* Zero-and-scale negative-flux fixup (Sec. 6, after Hamilton, Benzi and   */
+/* Warsa).  The particle balance of a cell is the sum of the rows of its    */
+/* local system A x = b:  sum_m colsum_m x_m = sum_l b_l  (absorption plus  */
+/* outflow equals source plus inflow).  When x has a negative entry, every  */
+/* negative entry is set to zero and the rest multiplied by the one factor  */
+/* that restores that sum; if no factor can (the source side or the scaled  */
+/* sum is not positive) the whole cell is set to zero.                      */
+/* ------------------------------------------------------------------------ */
+
+static void zero_and_scale(int np, const double *colsum, double src, double *x)
+{
+    int neg = 0;
+    for (int l = 0; l < np; ++l) if (x[l] < 0.0) neg = 1;
+    if (!neg) return;
+    double den = 0.0;
+    for (int m = 0; m < np; ++m) den += colsum[m] * (x[m] > 0.0 ? x[m] : 0.0);
+    double f = (src > 0.0 && den > 0.0) ? src / den : 0.0;
+    for (int m = 0; m < np; ++m) x[m] = x[m] > 0.0 ? f * x[m] : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sweep: lumped upwind DG S_N (Eq. dgsn_transport with every form lumped  */
 /* by the trapezoid rule).  For each (d,g) the cells are visited in upwind  */
 /* order and the local system                                              */
 /*   A_lm = sigt w_l delta_lm - w_m Omega.grad(phi_l)(x_m)                 */
 /*        + delta_lm sum_{outflow faces f of l} (Omega.n_f) fw_f            */
 /*   b_l  = w_l q_l - sum_{inflow faces f of l} (Omega.n_f) fw_f I_up       */
-/* is assembled and solved by Gaussian elimination.                         */
+/* is assembled and solved by Gaussian elimination; with fixup != 0 the   */
+/* solution then goes through zero_and_scale.                               */
 /*   q_l = q_iso[l][g] + inv_c_dt * psi_prev[d][g][l]                       */
 /* ------------------------------------------------------------------------ */
 
 int orc_sweep(const orc_geom *g, const double *sig_t, const double *q_iso, const double *psi_prev,
-              double inv_c_dt, const double *inflow, double *psi)
+              double inv_c_dt, const double *inflow, int fixup, double *psi)
 {
     int nx = g->nx, ny = g->dim == 2 ? g->ny : 1, np = npc(g), G = g->G, nn = nnode(g), NB = nbnode(g);
     for (int d = 0; d < g->nang; ++d) {
@@ -330,7 +354,14 @@ int orc_sweep(const orc_geom *g, const double *sig_t, const double *q_iso, const
                             }
                         }
                     }
+                    double colsum[4], src = 0.0;
+                    for (int m = 0; m < np; ++m) {
+                        colsum[m] = 0.0;
+                        for (int l = 0; l < np; ++l) colsum[m] += A[l * np + m];
+                        src += b[m];
+                    }
                     if (lu_solve(np, A, b, x)) return -1;
+                    if (fixup) zero_and_scale(np, colsum, src, x);
                     for (int l = 0; l < np; ++l) out[np * c + l] = x[l];
                 }
             }
@@ -771,6 +802,20 @@ int orc_energy_solve(double cv_dt, double k4, double rhs, double T0, double rtol
     return maxit;
 }
 
+/* Temperature floor (Sec. 6): with T_floor > 0 the balance's temperature  */
+/* is max(root, T_floor), and T_floor when it has no positive root (it < 0  */
+/* from orc_energy_solve).  Returns 1 for a missing root without a floor.   */
+static int floor_temperature(double T_floor, int it, double *T)
+{
+    if (it < 0) {
+        if (!(T_floor > 0.0)) return 1;
+        *T = T_floor;
+        return 0;
+    }
+    if (T_floor > 0.0 && *T < T_floor) *T = T_floor;
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Low-order Newton with nonlinear elimination of T (Sec. 5):              */
 /*   S = (c/3) D M_F^-1 D^T + M_E + P - dB dBt^-1 M_a                       */
@@ -881,7 +926,7 @@ static int lo_solve_ops(const orc_geom *g, const orc_lo_ops *ops, const orc_opts
         for (int n = 0; n < nn; ++n) {
             double r = c * sigE[n] * E[n] + cvn[n] * Tstar[n] / dt;
             int it = orc_energy_solve(cvn[n] / dt, sigP[n] * a * c, r, T[n], op->elim_rtol, op->max_elim, &T[n]);
-            if (it < 0) { status = ORC_E_NONPHYSICAL; break; }
+            if (floor_temperature(op->T_floor, it, &T[n])) { status = ORC_E_NONPHYSICAL; break; }
             if (it > st->elim_max) st->elim_max = it;
         }
         st->inner_total++;
@@ -1020,7 +1065,7 @@ int orc_step(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_o
             double B = a * c * pow(Tl[n], 4);
             for (int k = 0; k < G; ++k) q[(size_t)n * G + k] = sig[(size_t)(n / np) * G + k] * B * bg[k] / (4.0 * M_PI);
         }
-        orc_sweep(g, sigt, q, psi_prev, 1.0 / (c * dt), inflow, psi);
+        orc_sweep(g, sigt, q, psi_prev, 1.0 / (c * dt), inflow, op->fixup, psi);
         st->outer++;
         double *Tn = malloc(sizeof(double) * nn), *En = malloc(sizeof(double) * nn);
         if (op->scheme == 2) {
@@ -1040,7 +1085,7 @@ int orc_step(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_o
                 double r = sphi[n] + cvn[n] * Tstar[n] / dt;
                 Tn[n] = Tl[n];
                 int it = orc_energy_solve(cvn[n] / dt, (sbs / sb) * a * c, r, Tl[n], op->elim_rtol, op->max_elim, &Tn[n]);
-                if (it < 0) { status = ORC_E_NONPHYSICAL; break; }
+                if (floor_temperature(op->T_floor, it, &Tn[n])) { status = ORC_E_NONPHYSICAL; break; }
                 if (it > st->elim_max) st->elim_max = it;
             }
             memcpy(E_lo, En, sizeof(double) * nn);
@@ -1129,6 +1174,7 @@ int orc_adjoint_gradient(const orc_geom *g, const orc_mat *mt, const orc_bc *bc,
                          double *grad_s0, double *grad_cv, int n_regions, int *adj_iters)
 {
     if (objective != 0 && objective != 1) return -2;
+    if (op->fixup || op->T_floor != 0.0) return -2;   /* the adjoint of the linear, unfloored step */
     int nn = nnode(g), np = npc(g), G = g->G, nc = ncell(g), nd = g->nang, dim = g->dim;
     int nx = g->nx;
     size_t npsi = (size_t)nd * G * nn;

@@ -267,6 +267,7 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
         L.K = x->K;
         L.wg_per_cu = x->wg_per_cu;
         L.lctr = x->d_lctr.p;
+        L.fixup = x->opt.fixup;
         if (x->fp32) launch_sweep2d<float>(L, x->stream);
         else launch_sweep2d<double>(L, x->stream);
         if (finalize) finalize_moments(x, mom);
@@ -274,6 +275,7 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
         Sweep1DArgs a{};
         a.nx = x->nx; a.G = x->G; a.nang = x->nang; a.mu_w = x->d_mu_w.p; a.hx = x->d_hx.p;
         a.sig2 = sig2; a.qiso = qiso; a.psi_prev = psi_prev; a.psi_out = psi_out; a.inflow = inflow; a.inv_c_dt = icdt;
+        a.fixup = x->opt.fixup;
         if (x->fp32) {
             launch_sweep1d<float>(a, x->stream);
             if (finalize) run_moments1d<float>(x->stream, x->nx, x->G, x->nang, (const float *)x->d_mu_w.p, sig64, (const float *)psi_out, mom);
@@ -338,6 +340,7 @@ static LoInputs lo_inputs(smrt_ctx *x, double dt, const double *clos) {
     LoInputs in{};
     in.dt = dt; in.eps_inner = x->opt.eps_inner; in.cg_rtol = x->opt.cg_rtol; in.elim_rtol = x->opt.elim_rtol;
     in.max_inner = x->opt.max_inner; in.max_cg = x->opt.max_cg; in.max_elim = x->opt.max_elim;
+    in.T_floor = x->opt.T_floor;
     const int64_t nn = x->nn;
     in.sigE = clos; in.sigF = clos + nn; in.sigP = clos + 2 * nn; in.qE = clos + 3 * nn; in.qF = clos + 4 * nn;
     in.cvn = x->d_cvn.p;
@@ -387,6 +390,8 @@ static void validate_options(const smrt_options *o) {
     require(o->scheme >= 0 && o->scheme <= 2, "unknown scheme");
     require(o->precision == SMRT_FP64 || o->precision == SMRT_FP32, "unknown precision");
     require(o->lo_graphs == 0 || o->lo_graphs == 1, "lo_graphs must be 0 or 1");
+    require(o->fixup == 0 || o->fixup == 1, "fixup must be 0 or 1");
+    require(std::isfinite(o->T_floor) && o->T_floor >= 0.0, "T_floor must be finite and >= 0");
 }
 
 extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_desc *quad, const smrt_groups_desc *groups,
@@ -992,7 +997,8 @@ struct StepRun {
                                x->d_sigP.p, x->d_En.p, (double *)nullptr, x->d_sigEho.p);
             LoSolver &L = x->lo;
             hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, S, L.flags.p, 4);
-            run_eliminate(S, (int)nn, x->a, x->c, dt, x->opt.elim_rtol, x->opt.max_elim, x->d_cvn.p, x->d_sigEho.p,
+            run_eliminate(S, (int)nn, x->a, x->c, dt, x->opt.elim_rtol, x->opt.max_elim, x->opt.T_floor, x->d_cvn.p,
+                          x->d_sigEho.p,
                           x->d_sigP.p, x->d_En.p, x->d_Tstar.p, x->d_Tn.p, L.flags.p);
             int fl[4];
             d2h(fl, L.flags.p, sizeof fl, S);
@@ -1338,6 +1344,9 @@ static void batch_launch(smrt_batch *b) {
     L.K = b->K;
     L.wg_per_cu = b->wg_per_cu;
     L.lctr = b->d_lctr.p;
+    // one kernel serves the whole batch, so its problems share the fixup setting
+    L.fixup = b->P[0]->opt.fixup;
+    for (const smrt_ctx *x : b->P) require(x->opt.fixup == L.fixup, "problems of a batch share one fixup setting");
     if (b->fp32) launch_sweep2d<float>(L, b->stream);
     else launch_sweep2d<double>(L, b->stream);
 }
@@ -1633,6 +1642,8 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
         require(x->have_state, "smrt_set_state must be called first");
         require(x->have_opposite, "the quadrature has a direction without its opposite: no adjoint sweep");
         require(x->model == 1, "the gradient is defined for the power-law opacity model (one sigma0 per region)");
+        require(x->opt.fixup == 0 && x->opt.T_floor == 0.0,
+                "the adjoint differentiates the linear sweep and the unfloored energy balance: fixup and T_floor must be off");
         hipStream_t S = x->stream;
         const int N = n_steps, nn = x->nn, nc = x->ncell, G = x->G, npc = x->npc, nreg = x->nreg;
         const int64_t npsi = (int64_t)x->nang * G * nn, ncg = (int64_t)nc * G;

@@ -80,14 +80,16 @@ struct ClosureArgs {
     double *out;                  // [3+1+dim][nn]
 };
 void run_closures(hipStream_t s, const ClosureArgs &a);
-void run_eliminate(hipStream_t s, int nn, double a, double c, double dt, double rtol, int maxit, const double *cvn,
-                   const double *sigE, const double *sigP, const double *E, const double *Tstar, double *T, int *flags);
+void run_eliminate(hipStream_t s, int nn, double a, double c, double dt, double rtol, int maxit, double T_floor,
+                   const double *cvn, const double *sigE, const double *sigP, const double *E, const double *Tstar,
+                   double *T, int *flags);
 
 void assemble_lo_operators(int dim, int nx, int ny, const std::vector<double> &xe, const std::vector<double> &ye,
                            const double alpha[2], double c, Csr &D, Csr &DT, Csr &P, std::vector<double> &wnode);
 
 struct LoInputs {
     double dt, eps_inner, cg_rtol, elim_rtol;
+    double T_floor;                               // > 0: temperature floor of the elimination
     int max_inner, max_cg, max_elim;
     const double *sigE, *sigF, *sigP, *qE, *qF;   // closure rows (qF: [dim][nn])
     const double *cvn, *Tstar;

@@ -542,12 +542,15 @@ __global__ void k_backsub(int nn, int dim, double c3, const int *rp, const int *
 
 // pointwise energy balance: cv T/dt + sigP a c T^4 = c sigE E + cv T*/dt
 // (Newton safeguarded by bisection on [0, rhs dt/cv]; stop at |f| <= rtol |rhs|).
-// flags: [0] a node without a positive root, [1] the largest iteration count,
-// [2] a node that hit maxit; the count is reduced over the wave first, so the
-// flags see one atomic per wave.
-__global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, int maxit, const double *cvn,
-                            const double *sigE, const double *sigP, const double *E, const double *Tstar, double *T,
-                            int *flags) {
+// T_floor > 0 floors the temperature (Sec. 6): T = max(root, T_floor), and
+// T_floor where the balance has no positive root; T_floor = 0 leaves the root
+// as it is and flags a node without one.
+// flags: [0] a node without a positive root (no floor), [1] the largest
+// iteration count, [2] a node that hit maxit; the count is reduced over the
+// wave first, so the flags see one atomic per wave.
+__global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, int maxit, double T_floor,
+                            const double *cvn, const double *sigE, const double *sigP, const double *E,
+                            const double *Tstar, double *T, int *flags) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     int it = 0;
     bool bad = false, capped = false;
@@ -555,7 +558,8 @@ __global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, 
         const double cv_dt = cvn[n] / dt, k4 = sigP[n] * a * c;
         const double rhs = c * sigE[n] * E[n] + cv_dt * Tstar[n];
         if (!(rhs > 0.0)) {
-            bad = true;
+            if (T_floor > 0.0) T[n] = T_floor;
+            else bad = true;
         } else {
             double lo = 0.0, hi = rhs / cv_dt, t = T[n];
             if (!(t > lo && t < hi)) t = 0.5 * (lo + hi);
@@ -567,7 +571,7 @@ __global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, 
                 if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
                 t = tn;
             }
-            T[n] = t;
+            T[n] = T_floor > 0.0 ? fmax(t, T_floor) : t;
             capped = it == maxit;
         }
     }
@@ -586,10 +590,11 @@ __global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, 
 
 __global__ void k_zero4(int *p) { p[threadIdx.x] = 0; }
 
-void run_eliminate(hipStream_t s, int nn, double a, double c, double dt, double rtol, int maxit, const double *cvn,
-                   const double *sigE, const double *sigP, const double *E, const double *Tstar, double *T, int *flags) {
-    hipLaunchKernelGGL(k_eliminate, dim3((nn + 255) / 256), dim3(256), 0, s, nn, a, c, dt, rtol, maxit, cvn, sigE, sigP,
-                       E, Tstar, T, flags);
+void run_eliminate(hipStream_t s, int nn, double a, double c, double dt, double rtol, int maxit, double T_floor,
+                   const double *cvn, const double *sigE, const double *sigP, const double *E, const double *Tstar,
+                   double *T, int *flags) {
+    hipLaunchKernelGGL(k_eliminate, dim3((nn + 255) / 256), dim3(256), 0, s, nn, a, c, dt, rtol, maxit, T_floor, cvn,
+                       sigE, sigP, E, Tstar, T, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -727,7 +732,7 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
                            dDT.val, E, in.qF, MFinv.p, F);
         hipLaunchKernelGGL(k_zero4, dim3(1), dim3(4), 0, s, flags.p);
         hipLaunchKernelGGL(k_eliminate, dim3(nb(nn)), dim3(256), 0, s, nn, a, c, in.dt, in.elim_rtol, in.max_elim,
-                           in.cvn, in.sigE, in.sigP, E, in.Tstar, T, flags.p);
+                           in.T_floor, in.cvn, in.sigE, in.sigP, E, in.Tstar, T, flags.p);
         int fl[4];
         SMRT_HIP(hipMemcpyAsync(fl, flags.p, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
         dot(s, T, nullptr, Told.p, 5, false);

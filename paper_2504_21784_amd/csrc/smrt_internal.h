@@ -71,6 +71,7 @@ struct SweepLaunch {
     int NW, K;                       // launch shape shared by every problem
     int wg_per_cu;                   // 0: as many as fit; n: pad LDS so at most n workgroups share a CU
     int *lctr;                       // [2]: ticket, tasks done (reset by the last workgroup)
+    int fixup;                       // 1: zero-and-scale negative-flux fixup in every cell
 };
 
 // Internal angular-flux layout (both precisions): [d][g][band][t][r][4 canonical nodes].
@@ -99,6 +100,7 @@ struct Sweep1DArgs {
     void *psi_out;
     const void *inflow;     // [d][G][2]
     double inv_c_dt;
+    int fixup;              // 1: zero-and-scale negative-flux fixup in every cell
 };
 template <typename real>
 void launch_sweep1d(const Sweep1DArgs &a, hipStream_t s);

@@ -47,6 +47,9 @@
 //    is bounded (SPIN_LIMIT) and sets an error flag instead of hanging.
 //  * Angular-flux layout [d][g][band][t][r][node]: at step t a channel's 16
 //    lanes read and write 16 consecutive 4-node cells (256 B in FP32).
+//  * Optional zero-and-scale negative-flux fixup (Sec. 6, after Hamilton et
+//    al.), compiled in only when asked for: a cell solution with a negative
+//    entry is replaced before it is stored, traced or summed into moments.
 #include "smrt_internal.h"
 
 namespace smrt {
@@ -250,7 +253,27 @@ __device__ __forceinline__ real channel_scatter_sum(const real (&v)[4]) {
     return sum_swapped16(h0, h1);
 }
 
-template <typename real, int K, int PF, int NW, bool BATCH>
+// Zero-and-scale fixup of one cell (Sec. 6, Hamilton et al.): when the cell
+// solution has a negative entry, the negative entries become zero and the
+// others are scaled by one factor chosen so that the cell's particle balance,
+// the sum of the rows of its local system, still holds.  In canonical node
+// order the columns of A sum to (sw, sw + a, sw + b, sw + a + b) with
+// sw = sigma_t hx hy/4, so the balance reads
+//     sw (I0 + I1 + I2 + I3) + a (I1 + I3) + b (I2 + I3) = src,
+// src the sum of the right-hand sides.  When no non-negative solution keeps
+// it (src <= 0), the cell is set to zero.
+template <typename real>
+__device__ __forceinline__ void zero_and_scale(real &I0, real &I1, real &I2, real &I3, real sw, real a, real b,
+                                               real src) {
+    if (fmin(fmin(I0, I1), fmin(I2, I3)) < real(0)) {
+        const real p0 = fmax(I0, real(0)), p1 = fmax(I1, real(0)), p2 = fmax(I2, real(0)), p3 = fmax(I3, real(0));
+        const real den = sw * (p0 + p1 + p2 + p3) + a * (p1 + p3) + b * (p2 + p3);
+        const real f = (src > real(0) && den > real(0)) ? src * recip(den) : real(0);
+        I0 = f * p0; I1 = f * p1; I2 = f * p2; I3 = f * p3;
+    }
+}
+
+template <typename real, int K, int PF, int NW, bool BATCH, bool FIX>
 __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     using r2 = typename vec2<real>::type;
     using r4 = typename vec4<real>::type;
@@ -523,10 +546,11 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                     const real be = real(2) * ha * hb;
                     const real inv = recip(al * al - be * be);
                     const real ai = al * inv, bi = be * inv;
-                    const real I0 = ai * y0 + bi * y3;
-                    const real I1 = ai * y1 - bi * y2;
-                    const real I2 = ai * y2 - bi * y1;
-                    const real I3 = ai * y3 + bi * y0;
+                    real I0 = ai * y0 + bi * y3;
+                    real I1 = ai * y1 - bi * y2;
+                    real I2 = ai * y2 - bi * y1;
+                    real I3 = ai * y3 + bi * y0;
+                    if constexpr (FIX) zero_and_scale(I0, I1, I2, I3, S.st[k] * wgt, a, b, (rh0 + rh1) + (rh2 + rh3));
                     // A cell outside the mesh (ic < 0 or ic >= nx, or a row past ny)
                     // is a padding slot of the skewed layout: its store lands
                     // there and its moments are never read, so neither needs a
@@ -611,8 +635,8 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     }
 }
 
-template <typename real, int K, int NW, bool BATCH>
-static void launch_knwb(const SweepLaunch &L, hipStream_t s) {
+template <typename real, int K, int NW, bool BATCH, bool FIX>
+static void launch_knwbf(const SweepLaunch &L, hipStream_t s) {
     constexpr int PF = sizeof(real) == 4 ? (K == 1 ? 4 : 2) : 1;
     constexpr int CB = red_node_block(NW);
     // LDS: the reduction buffer, or more when the launch asks for fewer
@@ -621,11 +645,16 @@ static void launch_knwb(const SweepLaunch &L, hipStream_t s) {
     if (L.wg_per_cu > 0) lds = std::max(lds, (size_t)(LDS_PER_CU / L.wg_per_cu - 1024));
     static bool lds_attr_set = false;   // once per instantiation (so a launch can be graph-captured)
     if (!lds_attr_set) {
-        SMRT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep2d_kernel<real, K, PF, NW, BATCH>),
+        SMRT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep2d_kernel<real, K, PF, NW, BATCH, FIX>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, LDS_PER_CU - 1024));
         lds_attr_set = true;
     }
-    hipLaunchKernelGGL((sweep2d_kernel<real, K, PF, NW, BATCH>), dim3(L.n_tasks), dim3(NW * 64), lds, s, L);
+    hipLaunchKernelGGL((sweep2d_kernel<real, K, PF, NW, BATCH, FIX>), dim3(L.n_tasks), dim3(NW * 64), lds, s, L);
+}
+template <typename real, int K, int NW, bool BATCH>
+static void launch_knwb(const SweepLaunch &L, hipStream_t s) {
+    if (L.fixup) launch_knwbf<real, K, NW, BATCH, true>(L, s);
+    else launch_knwbf<real, K, NW, BATCH, false>(L, s);
 }
 template <typename real, int K, int NW>
 static void launch_knw(const SweepLaunch &L, hipStream_t s) {

@@ -762,6 +762,11 @@ __global__ void k_moments_sigma(int64_t nn, const double *sigq, double *mom) {
 // Lumped linear DG, nodes (L, R); for mu > 0 (canonical):
 //   [[d, m/2], [-m/2, d]] [I_L, I_R] = [w q_L + m I_up, w q_R],
 //   d = m/2 + sigt h/2, w = h/2, m = |mu|  ->  inverse (dI - (m/2)J)/(d^2 + m^2/4)
+// Optional zero-and-scale fixup (Sec. 6, Hamilton et al.): the columns sum to
+// (sigt w, sigt w + m), so a cell with a negative entry keeps its balance
+//   sigt w (I_u + I_d) + m I_d = r0 + r1
+// when its negative entry is zeroed and the other scaled to match (zero if the
+// right side is not positive).
 // ---------------------------------------------------------------------------
 template <typename real>
 __global__ void k_sweep1d(Sweep1DArgs A) {
@@ -796,8 +801,15 @@ __global__ void k_sweep1d(Sweep1DArgs A) {
         const real r0 = w * qu + m * up, r1 = w * qd;
         const real dg = real(0.5) * m + st * w, hm = real(0.5) * m;
         const real inv = real(1) / (dg * dg + hm * hm);
-        const real Iu = (dg * r0 - hm * r1) * inv;
-        const real Id = (dg * r1 + hm * r0) * inv;
+        real Iu = (dg * r0 - hm * r1) * inv;
+        real Id = (dg * r1 + hm * r0) * inv;
+        if (A.fixup && fmin(Iu, Id) < real(0)) {
+            const real pu = fmax(Iu, real(0)), pd = fmax(Id, real(0));
+            const real src = r0 + r1, den = st * w * (pu + pd) + m * pd;
+            const real f = (src > real(0) && den > real(0)) ? src / den : real(0);
+            Iu = f * pu;
+            Id = f * pd;
+        }
         po[base + 2 * c + nu_] = Iu;
         po[base + 2 * c + nd_] = Id;
         up = Id;
