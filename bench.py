@@ -15,7 +15,8 @@ per second of that pass.  The JSON line also carries the sweep kernel's
 HBM roofline (algorithmic bytes: read I* + write I; measured bytes from the
 committed counters; the measured device-to-device copy rate as a practical
 ceiling), the FP64 sweep for the FP32-vs-FP64 ratio and errors (one sweep
-and one full step from the same state), full time steps, the batched and
+and one full step from the same state), the sweep with the negative-flux
+fixup switched on (its cost), full time steps, the batched and
 adjoint workloads, and the FP64 CPU oracle timed on a bounded sample of the
 same workload.
 """
@@ -259,8 +260,16 @@ def main():
     alg_bytes = info["algorithmic_bytes_per_sweep"]
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     sweep_kernel = f"sweep2d_kernel<float, {info['pairs_per_lane']}, {4 if info['pairs_per_lane'] == 1 else 2}, " \
-                   f"{info['waves_per_group']}>"
+                   f"{info['waves_per_group']}, false, false>"
     ctx.close()
+
+    # the same sweep with the zero-and-scale negative-flux fixup compiled in
+    # (same inputs, same launch): the cost of the fixup
+    cf = make(smrt.SMRT_FP32, mid["T"], mid["psi"])
+    cf.set_options(fixup=1)
+    cf.sweep_resident(n_times=1)
+    _, k_fix = cf.sweep_resident(n_times=max(3, args.steps // 4))
+    cf.close()
 
     # FP64 sweep on the same inputs: throughput ratio and FP32 error
     c64 = make(smrt.SMRT_FP64, mid["T"], mid["psi"])
@@ -323,6 +332,8 @@ def main():
         "fp64_sweep_kernel_ms": k64,
         "fp64_sweep_units_per_s": units / (k64 * 1e-3),
         "fp32_vs_fp64_sweep_speedup": k64 / k_ms,
+        "fixup_sweep_kernel_ms": k_fix,
+        "fixup_sweep_cost": k_fix / k_ms - 1.0,
         "fp32_phi_rel_l2_vs_fp64": phi_err,
         "fp32_step_vs_fp64_step": step_err,
         "inputs": "mid-run state: two FP64 steps from the initial state",
