@@ -88,6 +88,8 @@ def _declare(L):
     L.orc_moments.argtypes = [gp, _dp, _dp, _dp]
     L.orc_n_moments.argtypes = [C.c_int]
     L.orc_inflow_from_bc.argtypes = [gp, bp, _dp]
+    L.orc_reflect_inflow.argtypes = [gp, bp, _dp, _dp]
+    L.orc_reflect_inflow.restype = C.c_int
     L.orc_closures.argtypes = [gp, bp, C.c_int, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_energy_solve.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, _dp]
     L.orc_energy_solve.restype = C.c_int
@@ -161,9 +163,14 @@ class Oracle:
         self.L.orc_opacity(C.byref(self.geom), C.byref(self.mat), _p(T), _p(sig))
         return sig
 
-    def inflow(self):
+    def inflow(self, psi=None):
+        """Boundary inflow [d][g][NB] from the boundary description; with psi
+        the reflective sides carry the mirrored intensities of psi."""
         a = np.zeros((self.p.n_angles, self.p.G, self.nb))
         self.L.orc_inflow_from_bc(C.byref(self.geom), C.byref(self.bc), _p(a))
+        if psi is not None:
+            r = self.L.orc_reflect_inflow(C.byref(self.geom), C.byref(self.bc), _p(_f64(psi)), _p(a))
+            assert r == 0, "a reflective side needs the mirrored direction of every direction"
         return a
 
     def sweep(self, sig_t, q_iso, psi_prev, inv_c_dt, inflow, fixup=False):

@@ -57,7 +57,7 @@ typedef struct {
 } orc_mat;
 
 typedef struct {
-    int kind[4];           /* 0 vacuum, 1 Planck at T_bdr, 2 explicit isotropic per group */
+    int kind[4];           /* 0 vacuum, 1 Planck at T_bdr, 2 explicit isotropic per group, 3 reflective */
     double T_bdr[4];
     const double *inflow_g[4];
 } orc_bc;
@@ -522,6 +522,58 @@ void orc_inflow_from_bc(const orc_geom *g, const orc_bc *bc, double *inflow)
             for (int t = 0; t < 2 * g->nx; ++t) { o[4 * g->ny + t] = val[2 * G + k]; o[4 * g->ny + 2 * g->nx + t] = val[3 * G + k]; }
         }
     free(val); free(b); free(r);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reflective sides (specular reflection, the symmetry planes of Sec. 6):  */
+/* at a boundary node of a reflective side, the inflow of a direction      */
+/* entering through that side is the intensity, at the same node, of the   */
+/* mirrored direction (mu -> -mu on the x sides, eta -> -eta on the y     */
+/* sides), taken from psi [d][g][node].  Entries of other sides and of     */
+/* leaving directions are not touched.  Returns -1 if a mirrored direction */
+/* is missing from the quadrature.                                          */
+/* ------------------------------------------------------------------------ */
+
+static int mirror_direction(const orc_geom *g, int d, int ax)
+{
+    for (int e = 0; e < g->nang; ++e) {
+        int same = 1;
+        for (int k = 0; k < g->dim; ++k) {
+            double want = k == ax ? -om_ax(g, d, k) : om_ax(g, d, k);
+            if (fabs(om_ax(g, e, k) - want) > 1e-12) same = 0;
+        }
+        if (same && fabs(g->w[e] - g->w[d]) <= 1e-12 * g->w[d]) return e;
+    }
+    return -1;
+}
+
+int orc_reflect_inflow(const orc_geom *g, const orc_bc *bc, const double *psi, double *inflow)
+{
+    int nx = g->nx, ny = g->dim == 2 ? g->ny : 1, np = npc(g), G = g->G, nn = nnode(g), NB = nbnode(g);
+    for (int s = 0; s < 2 * g->dim; ++s) {
+        if (bc->kind[s] != 3) continue;
+        int ax = s / 2, sd = s % 2;
+        for (int d = 0; d < g->nang; ++d) {
+            double on = (sd ? 1.0 : -1.0) * om_ax(g, d, ax);
+            if (on >= 0.0) continue;                 /* leaves through this side */
+            int e = mirror_direction(g, d, ax);
+            if (e < 0) return -1;
+            for (int k = 0; k < G; ++k) {
+                const double *I = psi + ((size_t)e * G + k) * nn;
+                double *o = inflow + ((size_t)d * G + k) * NB;
+                /* every node of every cell on this side */
+                int ncs = ax == 0 ? ny : nx;
+                for (int t = 0; t < ncs; ++t) {
+                    int i = ax == 0 ? (sd ? nx - 1 : 0) : t, j = ax == 0 ? t : (sd ? ny - 1 : 0);
+                    for (int l = 0; l < np; ++l) {
+                        if (!node_on_face(l, ax, sd)) continue;
+                        o[bnode_index(g, i, j, ax, sd, l)] = I[np * (i + nx * j) + l];
+                    }
+                }
+            }
+        }
+    }
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1039,6 +1091,7 @@ int orc_step(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_o
     orc_opacity(g, mt, T, sig);
     for (size_t k = 0; k < (size_t)nc * G; ++k) sigt[k] = sig[k] + 1.0 / (c * dt);
     orc_inflow_from_bc(g, bc, inflow);
+    int refl_bad = orc_reflect_inflow(g, bc, psi_prev, inflow);
     /* time-edge sources: HO sums of I^k (default) or the LO solution */
     if (op->lo_time_edge) {
         memcpy(Estar, E_lo, sizeof(double) * nn);
@@ -1056,8 +1109,8 @@ int orc_step(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_o
     if (op->scheme == 2) memcpy(El, Estar, sizeof(double) * nn);
     else memcpy(El, E_lo, sizeof(double) * nn);
     double first = -1.0;
-    int status = ORC_OK;
-    int maxo = op->max_outer;
+    int status = refl_bad ? -2 : ORC_OK;
+    int maxo = refl_bad ? 0 : op->max_outer;
     for (int l = 1; l <= maxo; ++l) {
         /* emission source at the current temperature iterate */
         for (int n = 0; n < nn; ++n) {
@@ -1066,6 +1119,9 @@ int orc_step(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_o
             for (int k = 0; k < G; ++k) q[(size_t)n * G + k] = sig[(size_t)(n / np) * G + k] * B * bg[k] / (4.0 * M_PI);
         }
         orc_sweep(g, sigt, q, psi_prev, 1.0 / (c * dt), inflow, op->fixup, psi);
+        /* reflective sides: the inflow now mirrors this sweep's intensity (the
+           closures below and the next sweep use it) */
+        orc_reflect_inflow(g, bc, psi, inflow);
         st->outer++;
         double *Tn = malloc(sizeof(double) * nn), *En = malloc(sizeof(double) * nn);
         if (op->scheme == 2) {
@@ -1175,6 +1231,8 @@ int orc_adjoint_gradient(const orc_geom *g, const orc_mat *mt, const orc_bc *bc,
 {
     if (objective != 0 && objective != 1) return -2;
     if (op->fixup || op->T_floor != 0.0) return -2;   /* the adjoint of the linear, unfloored step */
+    for (int s = 0; s < 2 * g->dim; ++s)
+        if (bc->kind[s] == 3) return -2;               /* vacuum and given inflow only */
     int nn = nnode(g), np = npc(g), G = g->G, nc = ncell(g), nd = g->nang, dim = g->dim;
     int nx = g->nx;
     size_t npsi = (size_t)nd * G * nn;

@@ -100,7 +100,7 @@ def level_symmetric_2d(N: int):
 # Problem description
 # ----------------------------------------------------------------------------
 
-BC_VACUUM, BC_PLANCK, BC_EXPLICIT = 0, 1, 2
+BC_VACUUM, BC_PLANCK, BC_EXPLICIT, BC_REFLECT = 0, 1, 2, 3
 MODEL_CONST, MODEL_POWERLAW = 0, 1
 
 
@@ -182,6 +182,31 @@ def slab_1d(n_cells: int = 64, n_angles: int = 8, sigma: float = 10.0, n_steps: 
         sigma0=np.array([[sigma]]), clip_lo=0.0, clip_hi=1e300, cv=np.array([1.0]),
         bc_kind=[BC_PLANCK, BC_VACUUM], T_bdr=[1.0, 0.0], inflow_g=[None, None],
         T0=0.01, dt=0.01, n_steps=n_steps)
+
+
+# Physical constants of the Marshak wave (T in eV, lengths in cm, time in s):
+# the radiation constant 7.5657e-15 erg cm^-3 K^-4 with 1 eV = 11604.518 K.
+RAD_CONST_EV = 7.5657e-15 * 11604.518 ** 4      # 137.20 erg cm^-3 eV^-4
+LIGHT_SPEED_CM_S = 2.99792458e10
+
+
+def marshak_1d(n_cells: int = 128, dt_ns: float = 8e-3, t_end_ns: float = 2.5) -> Problem:
+    """Marshak wave (Sec. 6): gray slab [0, 0.05] cm, sigma(T) = 1e12/T^3 per cm
+    (T in eV), c_v = 3e12 erg/(cm^3 eV), initial equilibrium at 1 eV, a 1 keV
+    Planck source on the left, Gauss-Legendre S6.  The paper leaves the right
+    boundary and c unstated: vacuum and c = 2.99792458e10 cm/s.  The power law
+    is the library's model 1 with one group whose bounds have geometric mean
+    1, so sigma = sigma0/T^3 with sigma0 = 1e12 (no clipping)."""
+    om, w = gauss_legendre_slab(6)
+    dt = dt_ns * 1e-9
+    return Problem(
+        name=f"marshak_1d_{n_cells}", dim=1, nx=n_cells, ny=1,
+        x_edges=np.linspace(0.0, 0.05, n_cells + 1), y_edges=None,
+        omega=om, w=w, G=1, nu_edges=np.array([0.5, 2.0]), a=RAD_CONST_EV, c=LIGHT_SPEED_CM_S,
+        region_of_cell=np.zeros(n_cells, np.int32), model=MODEL_POWERLAW,
+        sigma0=np.array([1e12]), clip_lo=0.0, clip_hi=1e300, cv=np.array([3e12]),
+        bc_kind=[BC_PLANCK, BC_VACUUM], T_bdr=[1000.0, 0.0], inflow_g=[None, None],
+        T0=1.0, dt=dt, n_steps=int(round(t_end_ns / dt_ns)))
 
 
 def gray_2d(n: int = 128, sn: int = 8, block: int = 8, seed: int = 2, n_steps: int = 20) -> Problem:
