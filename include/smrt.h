@@ -107,7 +107,15 @@ typedef struct {
 
 /* Boundary, per side (1D: x-, x+; 2D: x-, x+, y-, y+): kind 0 vacuum,
  * 1 isotropic Planck inflow B_g(T_bdr)/(4 pi), 2 explicit isotropic inflow
- * inflow_g[side][g] (intensity per group). */
+ * inflow_g[side][g] (intensity per group), 3 reflective (specular: the
+ * symmetry planes of Sec. 6).  On a reflective side a direction entering
+ * the domain takes, at each boundary node, the intensity of its mirror
+ * image (mu -> -mu on x sides, eta -> -eta on y sides) at that node: the
+ * context refreshes it from the newest intensity (smrt_set_state, after
+ * every sweep of a step or resident pass), and the closures take that
+ * inflow's incoming moments node by node.  Kind 3 needs the mirror image of
+ * every direction, with the same weight, in the quadrature
+ * (SMRT_E_INVALID_ARG otherwise). */
 typedef struct {
     int kind[4];
     double T_bdr[4];
@@ -188,7 +196,9 @@ smrt_status smrt_get_state(smrt_ctx *ctx, double *T, double *E, double *F, doubl
  * sig_t[cell][G] total (incl. time absorption) and sig[cell][G] absorption
  * opacities (the latter weights rows 24..26 / 6..7 of the moments);
  * q_iso[node][G]; psi_prev [d][g][node] or NULL (zero); psi_inflow general
- * inflow [d][g][boundary node] or NULL (use the boundary description).
+ * inflow [d][g][boundary node] or NULL (use the boundary description; a
+ * reflective side then carries the mirror of the context's last intensity:
+ * this call sweeps once and does not iterate the reflection).
  * Host arrays are in FP64; psi_out ([d][g][node], FP64, may be NULL) and
  * moments_out ([27 or 8][node], FP64, may be NULL) are written.  The sweep
  * itself runs at the context precision. */
@@ -259,8 +269,8 @@ smrt_status smrt_set_materials(smrt_ctx *ctx, const double *sigma0, const double
  * state is advanced by n_steps.  Errors: SMRT_E_INVALID_ARG (objective not
  * 0 or 1, n_steps < 1, dt <= 0, constant-opacity model, quadrature without
  * opposite directions, no state, fixup or T_floor switched on: the adjoint is
- * that of the linear sweep and the unfloored balance), or the failure of a
- * forward step. */
+ * that of the linear sweep and the unfloored balance, a reflective side), or
+ * the failure of a forward step. */
 smrt_status smrt_adjoint(smrt_ctx *ctx, int objective, int n_steps, double dt, double *J, double *grad_log_sigma0,
                          double *grad_log_cv, int *adjoint_iterations);
 
@@ -270,7 +280,8 @@ smrt_status smrt_adjoint(smrt_ctx *ctx, int objective, int n_steps, double dt, d
  * Estar[n], Fstar[dim*n], the absorption opacity sig[cell][G], and dt.
  * Output closures_out [5+dim... ] laid out as rows [sigE, sigF, sigP, qE,
  * qF_x(, qF_y)] x n_nodes.  Uses the context's boundary description and
- * scheme. */
+ * scheme; a reflective side takes the context's current reflected inflow
+ * (the mirror of the last intensity the context swept or was given). */
 smrt_status smrt_compute_closures(smrt_ctx *ctx, const double *moments, const double *T_l, const double *Estar,
                                   const double *Fstar, const double *sig, double dt, double *closures_out);
 

@@ -37,6 +37,10 @@ struct smrt_ctx {
     DevBuf<int> d_region, d_dir_quad, d_kind;
     DevBuf<int> d_opposite;       // direction with -Omega (adjoint sweeps)
     bool have_opposite = false;
+    DevBuf<int> d_mirror;         // [2][nang]: direction with mu -> -mu (x sides), eta -> -eta (y sides); -1 if none
+    bool have_mirror[2] = {false, false};
+    int refl = 0;                 // bit s: side s is reflective
+    DevBuf<double> d_bmom;        // [NB][3] incoming moments of the reflective sides' inflow
     DevBuf<unsigned char> d_hx, d_hy, d_dirs, d_mu_w;
     // sweep plan
     int NW = 0, K = 1, R = 0, NQC = 0, nbands = 0, NT = 0, n_wg = 0;
@@ -301,6 +305,19 @@ static void check_sweep_flag(smrt_ctx *x) {
 }
 
 // rebuild the per-side inflow tables from the boundary description
+// Reflective sides: the inflow of the directions entering through them is
+// set from the mirrored directions of psi (the newest intensity), with the
+// incoming moments the closures need.  Nothing when no side reflects.
+static void reflect_update(smrt_ctx *x, const void *psi) {
+    if (!x->refl) return;
+    if (x->fp32)
+        run_reflect<float>(x->stream, x->dim, x->nx, x->ny, x->G, x->nang, x->refl, x->d_mirror.p, x->d_om.p, x->d_w.p,
+                           x->d_dir_quad.p, (const float *)psi, (float *)x->d_inflow.p, x->d_bmom.p);
+    else
+        run_reflect<double>(x->stream, x->dim, x->nx, x->ny, x->G, x->nang, x->refl, x->d_mirror.p, x->d_om.p,
+                            x->d_w.p, x->d_dir_quad.p, (const double *)psi, (double *)x->d_inflow.p, x->d_bmom.p);
+}
+
 static void build_inflow(smrt_ctx *x) {
     const int nsides = 2 * x->dim;
     h2d(x->d_kind.p, x->bc_kind, sizeof(int) * 4, x->stream);
@@ -309,6 +326,7 @@ static void build_inflow(smrt_ctx *x) {
     run_side_inflow(x->stream, nsides, x->G, x->d_nu.p, x->a, x->c, x->d_kind.p, x->d_Tb.p, x->d_explicit.p, x->d_sideval.p);
     if (x->fp32) run_fill_inflow<float>(x->stream, x->dim, x->nx, x->ny, x->G, x->nang, x->d_sideval.p, (float *)x->d_inflow.p);
     else run_fill_inflow<double>(x->stream, x->dim, x->nx, x->ny, x->G, x->nang, x->d_sideval.p, (double *)x->d_inflow.p);
+    if (x->have_state) reflect_update(x, x->d_psi[x->cur].p);
 }
 
 // per-side total isotropic inflow intensity sum_g I_g (Planck: a c T^4 / 4pi since sum_g b_g = 1)
@@ -328,6 +346,8 @@ static ClosureArgs closure_args(smrt_ctx *x, int scheme, double dt, const double
     a.dim = x->dim; a.nx = x->nx; a.ny = x->ny; a.scheme = scheme; a.c = x->c; a.dt = dt;
     a.hx = x->d_hx64.p; a.hy = x->d_hy64.p;
     a.alpha[0] = x->alpha[0]; a.alpha[1] = x->alpha[1];
+    a.refl = x->refl;
+    a.bmom = x->d_bmom.p;
     side_totals(x, a.Itot);
     for (int s = 0; s < 4; ++s) a.S1[s] = x->S1[s];
     for (int s = 0; s < 8; ++s) a.S2[s] = x->S2[s];
@@ -369,18 +389,24 @@ extern "C" const char *smrt_last_error(const smrt_ctx *ctx) { return ctx ? ctx->
 
 static void set_boundary_impl(smrt_ctx *x, const smrt_boundary_desc *bc) {
     require(bc != nullptr, "boundary descriptor is NULL");
+    // validate every side before changing any
+    int refl = 0;
     for (int s = 0; s < 2 * x->dim; ++s) {
-        require(bc->kind[s] >= 0 && bc->kind[s] <= 2, "boundary kind must be 0, 1 or 2");
+        require(bc->kind[s] >= 0 && bc->kind[s] <= 3, "boundary kind must be 0, 1, 2 or 3");
+        require(bc->kind[s] != 3 || x->have_mirror[s / 2],
+                "a reflective side needs the mirror image of every direction in the quadrature");
         require(bc->kind[s] != 1 || bc->T_bdr[s] >= 0.0, "boundary temperature must be >= 0");
         require(bc->kind[s] != 2 || bc->inflow_g[s] != nullptr, "explicit inflow needs inflow_g");
+        for (int g = 0; g < x->G && bc->kind[s] == 2; ++g)
+            require(bc->inflow_g[s][g] >= 0.0, "explicit inflow must be >= 0");
+        if (bc->kind[s] == 3) refl |= 1 << s;
+    }
+    for (int s = 0; s < 2 * x->dim; ++s) {
         x->bc_kind[s] = bc->kind[s];
         x->bc_T[s] = bc->T_bdr[s];
-        for (int g = 0; g < x->G; ++g) {
-            const double v = bc->kind[s] == 2 ? bc->inflow_g[s][g] : 0.0;
-            require(v >= 0.0, "explicit inflow must be >= 0");
-            x->bc_explicit[s * x->G + g] = v;
-        }
+        for (int g = 0; g < x->G; ++g) x->bc_explicit[s * x->G + g] = bc->kind[s] == 2 ? bc->inflow_g[s][g] : 0.0;
     }
+    x->refl = refl;
     build_inflow(x);
 }
 
@@ -541,6 +567,25 @@ extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_d
             p->d_opposite.alloc(p->nang);
             SMRT_HIP(hipMemcpy(p->d_opposite.p, opp.data(), sizeof(int) * p->nang, hipMemcpyHostToDevice));
         }
+        // mirror images for reflective sides: (-mu, eta) for the x sides, (mu, -eta) for the y sides,
+        // with the same weight
+        std::vector<int> mir(2 * (size_t)p->nang, -1);
+        for (int ax = 0; ax < p->dim; ++ax) {
+            for (int d = 0; d < p->nang; ++d)
+                for (int e = 0; e < p->nang; ++e) {
+                    bool same = std::fabs(p->w[e] - p->w[d]) <= 1e-12 * p->w[d];
+                    for (int k = 0; k < p->dim; ++k) {
+                        const double want = k == ax ? -p->om[3 * d + k] : p->om[3 * d + k];
+                        same = same && std::fabs(p->om[3 * e + k] - want) <= 1e-12;
+                    }
+                    if (same) { mir[(size_t)ax * p->nang + d] = e; break; }
+                }
+            p->have_mirror[ax] = std::all_of(mir.begin() + (size_t)ax * p->nang, mir.begin() + (size_t)(ax + 1) * p->nang,
+                                             [](int e) { return e >= 0; });
+        }
+        p->d_mirror.alloc(2 * (int64_t)p->nang);
+        SMRT_HIP(hipMemcpy(p->d_mirror.p, mir.data(), sizeof(int) * mir.size(), hipMemcpyHostToDevice));
+        p->d_bmom.alloc(3 * (int64_t)(p->dim == 1 ? 2 : 4 * (p->nx + p->ny)));
         p->d_nu.alloc(p->G + 1);
         SMRT_HIP(hipMemcpy(p->d_nu.p, p->nu.data(), 8 * (p->G + 1), hipMemcpyHostToDevice));
         p->d_region.alloc(p->ncell);
@@ -670,6 +715,7 @@ extern "C" smrt_status smrt_set_state(smrt_ctx *x, const double *T_nodes, const 
         run_psi_EF(x->stream, x->nn, x->dim, x->G, x->nang, x->d_om.p, x->d_w.p, x->c, abi.p, x->d_Eho.p, x->d_Fho.p);
         SMRT_HIP(hipMemcpyAsync(x->d_E.p, x->d_Eho.p, 8 * x->nn, hipMemcpyDeviceToDevice, x->stream));
         SMRT_HIP(hipMemcpyAsync(x->d_F.p, x->d_Fho.p, 8 * x->nn * x->dim, hipMemcpyDeviceToDevice, x->stream));
+        reflect_update(x, x->d_psi[x->cur].p);
         SMRT_HIP(hipStreamSynchronize(x->stream));
         x->have_state = true;
     });
@@ -990,6 +1036,7 @@ struct StepRun {
         hipStream_t S = x->stream;
         const int64_t nn = x->nn;
         s.outer++;
+        reflect_update(x, pout);   // reflective sides mirror this sweep's intensity from here on
         SMRT_HIP(hipMemcpyAsync(x->d_Tn.p, x->d_Tl.p, 8 * nn, hipMemcpyDeviceToDevice, S));
         if (unacc) {
             // pointwise elimination against sum_g sigma_g phi_g of the sweep
@@ -1126,6 +1173,7 @@ extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, 
                 if (x->fp32) run_moments1d<float>(x->stream, x->nx, x->G, x->nang, (const float *)x->d_mu_w.p, x->d_sig.p, (const float *)pout, x->d_mom.p);
                 else run_moments1d<double>(x->stream, x->nx, x->G, x->nang, (const double *)x->d_mu_w.p, x->d_sig.p, (const double *)pout, x->d_mom.p);
             }
+            reflect_update(x, pout);
             run_closures(x->stream, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt, x->d_mom.p,
                                                  x->d_sigP.p, x->d_sigF.p, x->d_Eho.p, x->d_Fho.p, x->d_clos.p));
         }
@@ -1446,6 +1494,7 @@ static void batch_tables(smrt_batch *b, double dt, std::vector<double> &icdt) {
 static void batch_post(smrt_batch *b, double dt) {
     for (smrt_ctx *x : b->P) {
         finalize_moments(x, x->d_mom.p);
+        reflect_update(x, x->d_psi[1 - x->cur].p);
         run_closures(x->stream, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt, x->d_mom.p,
                                              x->d_sigP.p, x->d_sigF.p, x->d_Eho.p, x->d_Fho.p, x->d_clos.p));
     }
@@ -1644,6 +1693,7 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
         require(x->model == 1, "the gradient is defined for the power-law opacity model (one sigma0 per region)");
         require(x->opt.fixup == 0 && x->opt.T_floor == 0.0,
                 "the adjoint differentiates the linear sweep and the unfloored energy balance: fixup and T_floor must be off");
+        require(x->refl == 0, "the adjoint takes vacuum or given inflow on every side (no reflective side)");
         hipStream_t S = x->stream;
         const int N = n_steps, nn = x->nn, nc = x->ncell, G = x->G, npc = x->npc, nreg = x->nreg;
         const int64_t npsi = (int64_t)x->nang * G * nn, ncg = (int64_t)nc * G;

@@ -74,6 +74,8 @@ struct ClosureArgs {
     double Itot[4];               // per side: sum_g inflow intensity (isotropic)
     double S1[4];                 // per side: sum_{Omega.n<0} w (Omega.n)
     double S2[8];                 // per side, component: sum_{Omega.n<0} w Omega_a (Omega.n)
+    int refl;                     // bit s: side s is reflective; its F_in, P_in come from bmom
+    const double *bmom;           // [NB][3] incoming moments (F_in, P_in,x, P_in,y) per boundary node
     const double *mom;            // [27|8][nn]
     const double *sigP, *sigF;    // [nn] at the outer iterate's T
     const double *Estar, *Fstar;  // [nn], [nn][dim]

@@ -122,14 +122,27 @@ __global__ void k_closures2d(ClosureArgs A) {
             }
         } else {
             const int side = 2 * ax + sd;
-            const double Itot = A.Itot[side];
-            const double Fin = Itot * A.S1[side];
+            // incoming moments: isotropic side inflow, or per node (reflective side)
+            double Fin, Pin2[2];
+            if ((A.refl >> side) & 1) {
+                const int b = side == 0 ? 2 * j + ly
+                            : side == 1 ? 2 * A.ny + 2 * j + ly
+                            : side == 2 ? 4 * A.ny + 2 * i + lx
+                                        : 4 * A.ny + 2 * A.nx + 2 * i + lx;
+                Fin = A.bmom[3 * b];
+                Pin2[0] = A.bmom[3 * b + 1];
+                Pin2[1] = A.bmom[3 * b + 2];
+            } else {
+                Fin = A.Itot[side] * A.S1[side];
+                Pin2[0] = A.Itot[side] * A.S2[2 * side];
+                Pin2[1] = A.Itot[side] * A.S2[2 * side + 1];
+            }
             qE += -2.0 * fw * Fin;
             if (cons) {
                 const double Jp = sd ? me.Fp[ax][ax] : -(me.F[ax] - me.Fp[ax][ax]);
                 r0 += -fw * (Jp - c * alpha * E - Fin);
                 for (int a = 0; a < 2; ++a) {
-                    const double Pin = Itot * A.S2[2 * side + a];
+                    const double Pin = Pin2[a];
                     const double Ppn = sd ? me.Pp[ax][a] : -(me.Pi[a][ax] - me.Pp[ax][a]);
                     qF[a] += -fw * Pin;
                     r1[a] += fw * ((c / 3.0) * (a == ax ? sgn : 0.0) * E - Ppn);
@@ -183,12 +196,13 @@ __global__ void k_closures1d(ClosureArgs A) {
         r1 += sl * v;
     } else {
         const int side = l;
-        const double Fin = A.Itot[side] * A.S1[side];
+        const bool rf = (A.refl >> side) & 1;
+        const double Fin = rf ? A.bmom[3 * side] : A.Itot[side] * A.S1[side];
         qE += -2.0 * Fin;
         if (cons) {
             const double Jp = l ? me.Fp : -(me.F - me.Fp);
             r0 += -(Jp - c * alpha * E - Fin);
-            const double Pin = A.Itot[side] * A.S2[2 * side];
+            const double Pin = rf ? A.bmom[3 * side + 1] : A.Itot[side] * A.S2[2 * side];
             const double Ppn = l ? me.Pp : -(me.Pi - me.Pp);
             qF += -Pin;
             r1 += (c / 3.0) * sl * E - Ppn;

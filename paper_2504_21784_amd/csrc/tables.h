@@ -29,6 +29,12 @@ void run_side_inflow(hipStream_t s, int nsides, int G, const double *nu, double 
                      const double *Tb, const double *explicit_g, double *val);
 template <typename real>
 void run_fill_inflow(hipStream_t s, int dim, int nx, int ny, int G, int nang, const double *val, real *inflow);
+// reflective sides (bit s of refl): inflow [d][g][NB] from the mirrored
+// directions of psi (2D internal layout, 1D [d][g][node]) and the incoming
+// moments bmom [NB][3] of the result (nothing when refl == 0)
+template <typename real>
+void run_reflect(hipStream_t s, int dim, int nx, int ny, int G, int nang, int refl, const int *mirror, const double *om,
+                 const double *w, const int *dir_quad, const real *psi, real *inflow, double *bmom);
 template <typename real>
 void run_copy_to(hipStream_t s, int64_t n, const double *src, real *dst);
 template <typename real>

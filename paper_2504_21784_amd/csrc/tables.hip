@@ -429,6 +429,90 @@ __global__ void k_psi_convert(int nx, int ny, int G, int nang, const int *dir_qu
 }
 
 // ---------------------------------------------------------------------------
+// Reflective sides (specular reflection: the symmetry planes of Sec. 6).
+// A boundary node b of the general inflow table [d][g][NB] lies on side
+// `side` at cell (ci, cj), local node l.  For a direction d entering through
+// a reflective side, the inflow is the intensity of its mirror image e
+// (mu -> -mu on the x sides, eta -> -eta on the y sides) at the same node,
+// read from the sweep's angular flux (2D: internal layout; 1D: [d][g][node]).
+// refl has bit s set for a reflective side s; mirror[ax * nang + d] = e.
+// ---------------------------------------------------------------------------
+__device__ inline void boundary_node(int dim, int nx, int ny, int b, int &side, int &ci, int &cj, int &l) {
+    if (dim == 1) { side = b; ci = b ? nx - 1 : 0; cj = 0; l = b; return; }
+    if (b < 2 * ny) { side = 0; ci = 0; cj = b >> 1; l = (b & 1) << 1; return; }
+    b -= 2 * ny;
+    if (b < 2 * ny) { side = 1; ci = nx - 1; cj = b >> 1; l = 1 | ((b & 1) << 1); return; }
+    b -= 2 * ny;
+    if (b < 2 * nx) { side = 2; ci = b >> 1; cj = 0; l = b & 1; return; }
+    b -= 2 * nx;
+    side = 3; ci = b >> 1; cj = ny - 1; l = 2 | (b & 1);
+}
+
+// one thread per (d, g, boundary node); entries of other sides and of
+// directions leaving through the side are left as they are
+template <typename real>
+__global__ void k_reflect(int dim, int nx, int ny, int G, int nang, int refl, const int *mirror, const double *om,
+                          const int *dir_quad, const real *psi, real *inflow) {
+    const int NB = dim == 1 ? 2 : 4 * (nx + ny);
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nang * G * NB) return;
+    const int b = (int)(i % NB);
+    const int g = (int)((i / NB) % G);
+    const int d = (int)(i / ((int64_t)NB * G));
+    int side, ci, cj, l;
+    boundary_node(dim, nx, ny, b, side, ci, cj, l);
+    if (!((refl >> side) & 1)) return;
+    const int ax = side >> 1;
+    if ((side & 1 ? 1.0 : -1.0) * om[3 * d + ax] >= 0.0) return;
+    const int e = mirror[ax * nang + d];
+    const int64_t pair = (int64_t)e * G + g;
+    if (dim == 1) inflow[i] = psi[pair * 2 * nx + 2 * ci + l];
+    else inflow[i] = psi[internal_index(nx, ny, dir_quad[e], ci, cj, l, pair * psi_slab(nx, ny))];
+}
+
+// Incoming moments of the inflow at each boundary node of a reflective side,
+//   bmom[b] = (sum_{Omega.n<0} sum_g w (Omega.n) I_b, the same weighted by
+//   mu, by eta),
+// the closures' boundary terms F_in and P_in for an inflow that is neither
+// isotropic nor uniform along the side.  One 64-thread block per node: the
+// (d, g) pairs are strided over the lanes, summed in FP64 and reduced over
+// the wave.
+template <typename real>
+__global__ void __launch_bounds__(64) k_inflow_moments(int dim, int nx, int ny, int G, int nang, int refl,
+                                                       const double *om, const double *w, const real *inflow,
+                                                       double *bmom) {
+    const int NB = dim == 1 ? 2 : 4 * (nx + ny);
+    const int b = blockIdx.x;
+    int side, ci, cj, l;
+    boundary_node(dim, nx, ny, b, side, ci, cj, l);
+    if (!((refl >> side) & 1)) return;     // uniform over the block
+    const int ax = side >> 1;
+    const double sgn = side & 1 ? 1.0 : -1.0;
+    double f = 0.0, p0 = 0.0, p1 = 0.0;
+    for (int k = threadIdx.x; k < nang * G; k += 64) {
+        const int d = k / G, g = k - d * G;
+        const double on = sgn * om[3 * d + ax];
+        if (on < 0.0) {
+            const double v = w[d] * on * (double)inflow[((int64_t)d * G + g) * NB + b];
+            f += v;
+            p0 += om[3 * d] * v;
+            p1 += (dim == 2 ? om[3 * d + 1] : 0.0) * v;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        f += __shfl_xor(f, off, 64);
+        p0 += __shfl_xor(p0, off, 64);
+        p1 += __shfl_xor(p1, off, 64);
+    }
+    if (threadIdx.x == 0) {
+        bmom[3 * b] = f;
+        bmom[3 * b + 1] = p0;
+        bmom[3 * b + 2] = p1;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint helpers: direction permutation (out[d] = in[map[d]]) of [d][per]
 // arrays, and the opacity sensitivity of a sweep,
 //   dsig[c][g] = sum_d sum_{l in c} w_l lambda_{d,g,l} (emis_{l,g} - I_{d,g,l}),
@@ -910,6 +994,16 @@ void run_fill_inflow(hipStream_t s, int dim, int nx, int ny, int G, int nang, co
                        nang, val, inflow);
 }
 template <typename real>
+void run_reflect(hipStream_t s, int dim, int nx, int ny, int G, int nang, int refl, const int *mirror, const double *om,
+                 const double *w, const int *dir_quad, const real *psi, real *inflow, double *bmom) {
+    if (!refl) return;
+    const int NB = dim == 1 ? 2 : 4 * (nx + ny);
+    hipLaunchKernelGGL(k_reflect<real>, dim3(nblk((int64_t)nang * G * NB, 256)), dim3(256), 0, s, dim, nx, ny, G, nang,
+                       refl, mirror, om, dir_quad, psi, inflow);
+    hipLaunchKernelGGL(k_inflow_moments<real>, dim3(NB), dim3(64), 0, s, dim, nx, ny, G, nang, refl, om, w,
+                       (const real *)inflow, bmom);
+}
+template <typename real>
 void run_copy_to(hipStream_t s, int64_t n, const double *src, real *dst) {
     hipLaunchKernelGGL(k_copy_to<real>, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
 }
@@ -1041,6 +1135,8 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
     template void run_source<real>(hipStream_t, int, int, int, const double *, const double *, double, double,      \
                                    const double *, real *, real *, double *, double *);                             \
     template void run_fill_inflow<real>(hipStream_t, int, int, int, int, int, const double *, real *);              \
+    template void run_reflect<real>(hipStream_t, int, int, int, int, int, int, const int *, const double *,         \
+                                    const double *, const int *, const real *, real *, double *);                   \
     template void run_stab2d<real>(hipStream_t, int, int, int, const double *, const double *, double, real *);     \
     template void run_opacity_tab2d<real>(hipStream_t, int, int, int, const double *, const int *, int,            \
                                           const double *, double, double, const double *, double, double *, real *); \

@@ -1,0 +1,188 @@
+"""GPU parity of reflective sides (specular reflection, the symmetry planes
+of Sec. 6) against the FP64 oracle, through the C ABI.
+
+* Each side reflective on its own, on a ragged non-uniform 2D mesh with
+  several bands (every quadrant's internal layout is read at every side),
+  and all four together; 1D with a reflective right side.
+* The all-reflective multigroup box against the spatially uniform
+  backward-Euler recursion (no oracle involved), and its energy.
+* The 2D symmetry plane: half domain on the GPU against the full symmetric
+  domain in the oracle.
+* FP32 sweep on a reflective problem within the FP32 budget.
+* A raw sweep after smrt_set_state mirrors the given intensity; batches of
+  reflective problems match their problems stepped alone.
+* Errors: a reflective side without mirror images in the quadrature; the
+  adjoint with a reflective side.
+"""
+import numpy as np
+import pytest
+
+from paper_2504_21784_amd import workloads as W
+from test_oracle_reflect import (TIGHT, infinite_medium_2d, planck_fractions, symmetric_1d, symmetric_2d,
+                                 uniform_recursion)
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _steps(smrt_mod, oracle_mod, p, n_steps, prec=0, opts=TIGHT, T_start=None):
+    o = oracle_mod.Oracle(p)
+    st = o.initial_state()
+    if T_start is not None:
+        st["T"] = T_start.copy()
+    ctx = smrt_mod.Context(p, precision=prec, **opts)
+    ctx.set_state(st["T"], st["psi"])
+    out = []
+    for k in range(n_steps):
+        print(f"{p.name} bc={p.bc_kind} step {k}", flush=True)
+        r, st, ost = o.step(st, oracle_mod.default_opts(**opts))
+        assert r == 0
+        gst = ctx.step()
+        out.append((st, ost, ctx.get_state(), gst))
+    ctx.close()
+    return out
+
+
+def ragged_2d(bc):
+    p = W.multigroup_2d(n=37, G=2, sn=4, region=8, seed=6)
+    p.ny = 29
+    rng = np.random.default_rng(6)
+    xe = np.cumsum(np.r_[0.0, rng.uniform(0.5, 1.5, 37)])
+    ye = np.cumsum(np.r_[0.0, rng.uniform(0.5, 1.5, 29)])
+    p.x_edges, p.y_edges = xe / xe[-1], 0.8 * ye / ye[-1]
+    p.region_of_cell = p.region_of_cell[:37 * 29].copy()
+    p.bc_kind = list(bc)
+    p.T_bdr = [1.0 if k == W.BC_PLANCK else 0.0 for k in bc]
+    p.T0 = 0.05
+    p.dt = 0.01
+    return p
+
+
+R, P, V = W.BC_REFLECT, W.BC_PLANCK, W.BC_VACUUM
+
+
+@pytest.mark.parametrize("bc", [(R, V, P, V), (P, R, V, V), (V, P, R, V), (P, V, V, R), (R, R, R, R)])
+def test_reflective_sides_2d_match_oracle(smrt_mod, oracle_mod, bc):
+    p = ragged_2d(bc)
+    T0 = None
+    if bc == (R, R, R, R):
+        T0 = np.where((np.arange(p.n_nodes) // 4) % 37 < 9, 0.4, p.T0)   # something to move
+    for ref, ost, got, gst in _steps(smrt_mod, oracle_mod, p, 2, T_start=T0):
+        assert _rel(got["T"], ref["T"]) < 1e-10
+        assert _rel(got["E"], ref["E"]) < 1e-10
+        assert _rel(got["psi"], ref["psi"]) < 1e-10
+        assert abs(gst["outer"] - ost["outer"]) <= 1
+
+
+def test_reflective_1d_matches_oracle(smrt_mod, oracle_mod):
+    p = symmetric_1d(20, True)
+    for ref, ost, got, gst in _steps(smrt_mod, oracle_mod, p, 4):
+        assert _rel(got["T"], ref["T"]) < 1e-10
+        assert _rel(got["psi"], ref["psi"]) < 1e-10
+        assert abs(gst["outer"] - ost["outer"]) <= 1
+
+
+def test_reflective_box_matches_uniform_recursion(smrt_mod):
+    """Radiation in equilibrium at T0, material at 2 T0, every side reflective."""
+    p = infinite_medium_2d()
+    I0 = p.a * p.c * p.T0 ** 4 * planck_fractions(p.nu_edges, p.T0) / (4 * np.pi)
+    psi0 = np.broadcast_to(I0[None, :, None], (p.n_angles, p.G, p.n_nodes)).copy()
+    ctx = smrt_mod.Context(p, precision=0, **TIGHT)
+    ctx.set_state(2.0 * p.initial_T_nodes(), psi0)
+    for k, (T_ref, I_ref) in enumerate(uniform_recursion(p, 2.0 * p.T0, 3)):
+        ctx.step()
+        s = ctx.get_state()
+        assert np.ptp(s["T"]) <= 1e-10 * T_ref
+        assert abs(s["T"].mean() - T_ref) <= 1e-10 * T_ref, k
+        assert np.abs(s["psi"] - I_ref[None, :, None]).max() <= 1e-9 * I_ref.max(), k
+    ctx.close()
+
+
+def test_reflective_symmetry_plane_matches_full_domain(smrt_mod, oracle_mod):
+    pf, ph = symmetric_2d(12, False), symmetric_2d(6, True)
+    of = oracle_mod.Oracle(pf)
+    sf = of.initial_state()
+    ctx = smrt_mod.Context(ph, precision=0, **TIGHT)
+    ctx.set_state(ph.initial_T_nodes())
+    for k in range(2):
+        r, sf, _ = of.step(sf, oracle_mod.default_opts(**TIGHT))
+        assert r == 0
+        ctx.step()
+        Tf = sf["T"].reshape(12, 12, 4)[:6].reshape(-1)
+        assert _rel(ctx.get_state()["T"], Tf) < 1e-10, k
+    ctx.close()
+
+
+def test_reflective_fp32_within_budget(smrt_mod, oracle_mod):
+    p = ragged_2d((P, V, V, R))
+    for ref, ost, got, gst in _steps(smrt_mod, oracle_mod, p, 2, prec=1):
+        phi_ref = np.einsum("d,dgn->n", p.w, ref["psi"])
+        phi = np.einsum("d,dgn->n", p.w, got["psi"])
+        assert np.linalg.norm(phi - phi_ref) / np.linalg.norm(phi_ref) < 1e-5
+        assert np.linalg.norm(got["T"] - ref["T"]) / np.linalg.norm(ref["T"]) < 1e-6
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5)])
+def test_raw_sweep_mirrors_the_state(smrt_mod, oracle_mod, prec, tol):
+    p = ragged_2d((R, P, R, V))
+    rng = np.random.default_rng(4)
+    psi0 = rng.uniform(0.5, 1.0, (p.n_angles, p.G, p.n_nodes))
+    sigt, q, pp, _ = W.random_sweep_inputs(p, seed=8)
+    o = oracle_mod.Oracle(p)
+    ref = o.sweep(sigt, q, pp, 0.4, o.inflow(psi0))
+    ctx = smrt_mod.Context(p, precision=prec)
+    ctx.set_state(p.initial_T_nodes(), psi0)
+    psi, _ = ctx.sweep(sigt, 0.5 * sigt, q, pp, 0.4, None)
+    ctx.close()
+    assert _rel(psi, ref) < tol
+
+
+def test_batch_of_reflective_problems_matches_single_steps(smrt_mod):
+    ps = [ragged_2d((R, V, P, V)), ragged_2d((P, V, V, R)), ragged_2d((R, R, R, R))]
+    single, batched = [], []
+    for p in ps:
+        for lst in (single, batched):
+            c = smrt_mod.Context(p, precision=0, **TIGHT)
+            c.set_state(p.initial_T_nodes())
+            lst.append(c)
+    b = smrt_mod.Batch(batched)
+    info = b.info()
+    for c in single:
+        c.set_launch(info["waves_per_group"], info["pairs_per_lane"])
+    for k in range(2):
+        print(f"batched reflective step {k}", flush=True)
+        b.step(ps[0].dt)
+        for c in single:
+            c.step()
+        for c1, c2 in zip(single, batched):
+            assert _rel(c2.get_state()["T"], c1.get_state()["T"]) < 1e-12
+    b.close()
+    for c in single + batched:
+        c.close()
+
+
+def test_reflective_needs_mirror_images(smrt_mod):
+    p = W.gray_2d(n=4, sn=4, block=4, seed=2)
+    # two opposite directions only: no (-mu, eta) image
+    v = np.array([1.0, 2.0, 0.5])
+    v /= np.linalg.norm(v)
+    p.omega = np.array([v, -v])
+    p.w = np.array([2 * np.pi, 2 * np.pi])
+    p.bc_kind = [R, V, V, V]
+    with pytest.raises(smrt_mod.SmrtError) as e:
+        smrt_mod.Context(p, precision=0)
+    assert e.value.status == smrt_mod.SMRT_E_INVALID_ARG
+
+
+def test_adjoint_rejects_reflective_side(smrt_mod):
+    p = W.adjoint_2d(n=16, G=2)
+    p.bc_kind = [P, V, V, R]
+    ctx = smrt_mod.Context(p, precision=0)
+    ctx.set_state(p.initial_T_nodes())
+    with pytest.raises(smrt_mod.SmrtError) as e:
+        ctx.adjoint(1, p.dt)
+    assert e.value.status == smrt_mod.SMRT_E_INVALID_ARG
+    ctx.close()

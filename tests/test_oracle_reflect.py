@@ -171,3 +171,33 @@ def test_reflective_inflow_mirrors_the_boundary_intensity(oracle_mod):
         mask = np.ones(inf.shape[2], bool)
         mask[4 * ny + 2 * nx:] = eta >= 0
         assert np.array_equal(inf[d, 0, mask], base[d, 0, mask])
+
+
+def test_reflective_box_conserves_energy(oracle_mod):
+    """Every side reflective, blocky random opacities, a hot spot in the
+    material: nothing enters or leaves, so the total energy
+    sum_n w_n (E_n + c_v T_n) of each step equals that of the step before
+    (the time-edge E being the high-order energy density of the previous
+    intensity), to the iteration tolerances."""
+    p = W.multigroup_2d(n=10, G=3, sn=4, region=5, seed=8)
+    p.ny = 8
+    p.y_edges = np.linspace(0.0, 0.8, 9)
+    p.region_of_cell = p.region_of_cell[:80].copy()
+    p.bc_kind = [W.BC_REFLECT] * 4
+    p.T0 = 0.1
+    p.dt = 0.02
+    o = oracle_mod.Oracle(p)
+    st = o.initial_state()
+    hot = (np.arange(p.n_nodes) // 4) % 10 < 3
+    st["T"] = np.where(hot, 0.5, st["T"])
+    wv = 0.1 * 0.1 / 4
+    cvn = p.cv[p.region_of_cell][np.arange(p.n_nodes) // 4]
+    for k in range(3):
+        Estar = np.einsum("d,dgn->n", p.w, st["psi"]) / p.c
+        r, new, _ = o.step(st, oracle_mod.default_opts(**TIGHT))
+        assert r == 0
+        before = wv * (Estar + cvn * st["T"]).sum()
+        after = wv * (new["E"] + cvn * new["T"]).sum()
+        assert abs(after - before) <= 1e-10 * before, k
+        assert np.ptp(new["T"]) > 1e-3                # not trivially uniform
+        st = new

@@ -73,3 +73,29 @@ def test_workload_shapes():
     assert all(64 <= x.nx <= 384 and x.G in (4, 8, 16, 32) and x.n_angles in (12, 40, 84) for x in b)
     a = W.adjoint_2d()
     assert a.n_regions == 64 and 0.5 <= a.cv.min() and a.cv.max() <= 2.0
+
+
+def test_marshak_units_and_first_steps(oracle_mod):
+    """The Marshak wave's constants (a from 7.5657e-15 erg cm^-3 K^-4 and
+    11604.518 K/eV), its opacity at 1 eV and 1 keV through the library's
+    power-law model, and 40 oracle steps with the fixup and the floor: the
+    temperature stays below 1 keV and near or above 1 eV, and the 500 eV
+    front only moves right."""
+    p = W.marshak_1d(32, 8e-3)
+    assert abs(p.a - 137.2) < 0.01 and p.n_steps == 312
+    o = oracle_mod.Oracle(p)
+    assert abs(o.opacity(np.full(p.n_nodes, 1.0))[0, 0] - 1e12) < 1e-3
+    assert abs(o.opacity(np.full(p.n_nodes, 1000.0))[0, 0] - 1e3) < 1e-12
+    st = o.initial_state()
+    opts = oracle_mod.default_opts(eps_outer=1e-8, eps_inner=1e-10, cg_rtol=1e-12, elim_rtol=1e-12, max_outer=200,
+                                   max_inner=60, max_cg=2000, fixup=1, T_floor=1e-8)
+    last = 0
+    for k in range(40):
+        r, st, _ = o.step(st, opts)
+        assert r == 0
+        T = st["T"]
+        assert T.max() <= 1000.0 and T.min() >= 0.999      # the cold end radiates through the vacuum face
+        front = int(np.argmax(T < 500.0))
+        assert front >= last
+        last = front
+    assert last > 4
