@@ -146,6 +146,11 @@ typedef struct {
                            max(root, T_floor), and T_floor where it has no positive root, instead
                            of failing with SMRT_E_NONPHYSICAL.  0 (default): no floor.  In the
                            problem's temperature units. */
+    int lo_precond;     /* preconditioner of the LO conjugate gradients (Sec. 5 solves them with an
+                           algebraic-multigrid preconditioner): 0 (default) Jacobi; 1 aggregation
+                           multigrid (cells, then 2x2 blocks of cells, Galerkin coarse operators,
+                           damped-Jacobi smoothing, one V-cycle per iteration), rebuilt for every
+                           Newton linearisation.  Changes the iteration count, not the solution. */
 } smrt_options;
 
 /* Per-step statistics (the columns of the paper's summary tables). */

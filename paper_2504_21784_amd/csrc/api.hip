@@ -361,6 +361,7 @@ static LoInputs lo_inputs(smrt_ctx *x, double dt, const double *clos) {
     in.dt = dt; in.eps_inner = x->opt.eps_inner; in.cg_rtol = x->opt.cg_rtol; in.elim_rtol = x->opt.elim_rtol;
     in.max_inner = x->opt.max_inner; in.max_cg = x->opt.max_cg; in.max_elim = x->opt.max_elim;
     in.T_floor = x->opt.T_floor;
+    in.precond = x->opt.lo_precond;
     const int64_t nn = x->nn;
     in.sigE = clos; in.sigF = clos + nn; in.sigP = clos + 2 * nn; in.qE = clos + 3 * nn; in.qF = clos + 4 * nn;
     in.cvn = x->d_cvn.p;
@@ -418,6 +419,7 @@ static void validate_options(const smrt_options *o) {
     require(o->lo_graphs == 0 || o->lo_graphs == 1, "lo_graphs must be 0 or 1");
     require(o->fixup == 0 || o->fixup == 1, "fixup must be 0 or 1");
     require(std::isfinite(o->T_floor) && o->T_floor >= 0.0, "T_floor must be finite and >= 0");
+    require(o->lo_precond == 0 || o->lo_precond == 1, "lo_precond must be 0 (Jacobi) or 1 (multigrid)");
 }
 
 extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_desc *quad, const smrt_groups_desc *groups,

@@ -1,6 +1,7 @@
 // FP64 closure post-pass and low-order solver (lo.hip).
 #pragma once
 #include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -93,13 +94,22 @@ struct LoInputs {
     double dt, eps_inner, cg_rtol, elim_rtol;
     double T_floor;                               // > 0: temperature floor of the elimination
     int max_inner, max_cg, max_elim;
+    int precond;                                  // 0: Jacobi; 1: aggregation multigrid V-cycle
     const double *sigE, *sigF, *sigP, *qE, *qF;   // closure rows (qF: [dim][nn])
     const double *cvn, *Tstar;
 };
 
+struct MgHierarchy;   // aggregation multigrid levels (built on first use)
+
 struct LoSolver {
     int dim = 0, nn = 0;
     double c = 1, a = 1;
+    // mesh, kept to re-assemble the geometric operators for the multigrid set-up
+    int gnx = 0, gny = 0;
+    std::vector<double> gxe, gye;
+    double galpha[2] = {0, 0};
+    std::unique_ptr<MgHierarchy> mg;
+    int precond = 0;               // preconditioner of the current solve
     DevCsr dD, dDT, dP;
     DevBuf<double> wn, MFinv, DqF, jbase, diagE, rhs, Minv, r, z, p, Ap, Eold, Told, tmpF, part, sc, bpart, apart;
     DevBuf<int> flags;
@@ -108,8 +118,15 @@ struct LoSolver {
     hipGraphExec_t cg_exec = nullptr;
     hipStream_t cg_stream = nullptr;
     const double *cg_x = nullptr;
+    int cg_precond = -1;
     bool use_graphs = true, graph_failed = false;
+    LoSolver();
     ~LoSolver();
+    void init_mg();
+    void setup_mg(hipStream_t s);
+    void vcycle(hipStream_t s, const double *r, double *z);
+    void mg_cg_init(hipStream_t s);
+    void mg_cg_iteration(hipStream_t s, double *x);
     void drop_graph();
     void cg_block(hipStream_t s, double *x, int iters);
     void init(int dim, int nx, int ny, const std::vector<double> &xe, const std::vector<double> &ye,

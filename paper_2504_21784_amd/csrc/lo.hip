@@ -621,6 +621,12 @@ void LoSolver::init(int dim_, int nx, int ny, const std::vector<double> &xe, con
     dim = dim_;
     c = c_;
     a = a_;
+    gnx = nx;
+    gny = ny;
+    gxe = xe;
+    gye = ye;
+    galpha[0] = alpha[0];
+    galpha[1] = alpha[1];
     Csr D, DT, P;
     std::vector<double> wv;
     assemble_lo_operators(dim, nx, ny, xe, ye, alpha, c, D, DT, P, wv);
@@ -662,6 +668,7 @@ void LoSolver::schur(hipStream_t s, const double *x, double *y) {
 int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
     schur(s, x, Ap.p);
     hipLaunchKernelGGL(k_cg_init, dim3(nb(nn)), dim3(256), 0, s, nn, rhs.p, Ap.p, r.p, Minv.p, z.p, p.p);
+    if (precond == 1) mg_cg_init(s);               // z = M^-1 r, p = z by a V-cycle
     dot(s, rhs.p, nullptr, nullptr, 4, false);     // |b|^2
     dot(s, r.p, z.p, nullptr, 0, false);           // rz
     dot(s, r.p, nullptr, nullptr, 2, false);       // rr
@@ -669,7 +676,7 @@ int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
     // solve that starts converged runs one frozen block and reports 0 iterations
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1), 0, s, sc.p, rtol, maxit);
     constexpr int CHECK = 4;   // iterations queued between host checks
-    if (use_graphs && !graph_failed && (cg_exec == nullptr || cg_stream != s || cg_x != x)) {
+    if (use_graphs && !graph_failed && (cg_exec == nullptr || cg_stream != s || cg_x != x || cg_precond != precond)) {
         // record CHECK iterations once (kernels only) and replay them; streams
         // that cannot capture fall back to direct launches
         drop_graph();
@@ -681,6 +688,7 @@ int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
                 cg_graph = g;
                 cg_stream = s;
                 cg_x = x;
+                cg_precond = precond;
             } else {
                 if (g) (void)hipGraphDestroy(g);
                 cg_exec = nullptr;
@@ -706,6 +714,10 @@ int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
 // partials; the new direction (each block sums r.z); the scalars and the stop test.
 void LoSolver::cg_block(hipStream_t s, double *x, int iters) {
     const int nbk = nb(nn);
+    if (precond == 1) {
+        for (int k = 0; k < iters; ++k) mg_cg_iteration(s, x);
+        return;
+    }
     for (int k = 0; k < iters; ++k) {
         hipLaunchKernelGGL(k_dt_scaled, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn * dim, dim, c / 3.0, dDT.rp,
                            dDT.col, dDT.val, p.p, MFinv.p, tmpF.p);
@@ -725,9 +737,9 @@ void LoSolver::drop_graph() {
     cg_graph = nullptr;
     cg_stream = nullptr;
     cg_x = nullptr;
+    cg_precond = -1;
 }
 
-LoSolver::~LoSolver() { drop_graph(); }
 
 smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double *F, double *T, smrt_step_stats *st,
                             std::string &err) {
@@ -741,6 +753,11 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
     for (int m = 1; m <= in.max_inner; ++m) {
         hipLaunchKernelGGL(k_newton_prep, dim3(nb(nn)), dim3(256), 0, s, nn, a, c, in.dt, wn.p, in.cvn, T, in.Tstar,
                            in.sigE, in.sigP, in.qE, DqF.p, jbase.p, diagE.p, rhs.p, Minv.p, E, Eold.p, Told.p);
+        precond = in.precond;
+        if (precond == 1) {
+            init_mg();                              // once per context
+            setup_mg(s);                            // coarse operators of this linearisation
+        }
         st->cg_total += pcg(s, E, in.cg_rtol, in.max_cg);
         hipLaunchKernelGGL(k_backsub, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn, dim, c / 3.0, dDT.rp, dDT.col,
                            dDT.val, E, in.qF, MFinv.p, F);
@@ -772,3 +789,5 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
 }
 
 }  // namespace smrt
+
+#include "mg_precond.inc"

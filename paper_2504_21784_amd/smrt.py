@@ -53,7 +53,7 @@ class Options(C.Structure):
                 ("elim_rtol", C.c_double), ("max_outer", C.c_int), ("max_inner", C.c_int), ("max_cg", C.c_int),
                 ("max_elim", C.c_int), ("precision", C.c_int), ("scheme", C.c_int), ("strict", C.c_int),
                 ("fixed_outer", C.c_int), ("lo_time_edge", C.c_int), ("lo_graphs", C.c_int),
-                ("fixup", C.c_int), ("T_floor", C.c_double)]
+                ("fixup", C.c_int), ("T_floor", C.c_double), ("lo_precond", C.c_int)]
 
 
 class StepStats(C.Structure):
