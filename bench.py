@@ -16,7 +16,8 @@ HBM roofline (algorithmic bytes: read I* + write I; measured bytes from the
 committed counters; the measured device-to-device copy rate as a practical
 ceiling), the FP64 sweep for the FP32-vs-FP64 ratio and errors (one sweep
 and one full step from the same state), the sweep with the negative-flux
-fixup switched on (its cost), full time steps, the batched and
+fixup switched on (its cost), full time steps, the LO preconditioners
+(Jacobi, multigrid) on a diffusion-dominated step, the batched and
 adjoint workloads, and the FP64 CPU oracle timed on a bounded sample of the
 same workload.
 """
@@ -30,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LO_GRAPHS = 1   # --lo-graphs: 1 replays the LO conjugate-gradient blocks as HIP graphs (the library default)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep2d_fp32_256x256_S8_G16_hbm_bytes.md")
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2504_21784_amd", "csrc", f) for f in ("sweep2d.hip", "smrt_internal.h")]
 
@@ -96,7 +98,7 @@ def batched(args):
     ps = W.batch_2d()
     ctxs = []
     for q in ps:
-        c = smrt.Context(q, precision=smrt.SMRT_FP32)
+        c = smrt.Context(q, precision=smrt.SMRT_FP32, lo_graphs=LO_GRAPHS)
         c.set_state(q.initial_T_nodes())
         ctxs.append(c)
     b = smrt.Batch(ctxs)
@@ -129,7 +131,7 @@ def time_steps(p, T0, n=3):
     import numpy as np
     from paper_2504_21784_amd import smrt
 
-    ctx = smrt.Context(p, precision=smrt.SMRT_FP32)
+    ctx = smrt.Context(p, precision=smrt.SMRT_FP32, lo_graphs=LO_GRAPHS)
     ctx.set_state(T0)
     ctx.step(p.dt)   # warm-up step
     t0 = _t.perf_counter()
@@ -142,6 +144,37 @@ def time_steps(p, T0, n=3):
             "inner_per_step": float(np.mean([s["inner_total"] for s in stats])),
             "cg_per_step": float(np.mean([s["cg_total"] for s in stats])),
             "sweep_ms_per_step": float(np.mean([s["t_sweep_ms"] for s in stats]))}
+
+
+def lo_multigrid():
+    """The LO preconditioners on a diffusion-dominated step: gray 256x256,
+    level-symmetric S8, per-8x8-block opacity log-uniform [0.1, 1000] (seed 2),
+    T0 = 0.3, dt = 1 (cells thin enough that the diffusion term outweighs the
+    diagonal), consistent SM with the fixup and the floor, FP32 sweep, CG to
+    1e-12.  One warm-up step (it includes the one-time multigrid set-up), then
+    the second step timed, with Jacobi and with the multigrid V-cycle."""
+    import time as _t
+    from paper_2504_21784_amd import smrt, workloads as W
+
+    p = W.gray_2d(n=256, sn=8, block=8, seed=2)
+    p.dt = 1.0
+    p.T0 = 0.3
+    out = {"workload": "gray 256x256, S8, sigma per 8x8 block log-uniform [0.1, 1000] (seed 2), T0 = 0.3, dt = 1, "
+                       "fixup + floor, FP32 sweep, CG rtol 1e-12, outer/inner 1e-6/1e-8; second step timed"}
+    for pc, name in ((0, "jacobi"), (1, "multigrid")):
+        ctx = smrt.Context(p, precision=smrt.SMRT_FP32, lo_precond=pc, lo_graphs=LO_GRAPHS, cg_rtol=1e-12, max_cg=4000,
+                           eps_inner=1e-8, eps_outer=1e-6, fixup=1, T_floor=1e-6)
+        ctx.set_state(p.initial_T_nodes())
+        ctx.step()
+        t0 = _t.perf_counter()
+        st = ctx.step()
+        wall = _t.perf_counter() - t0
+        ctx.close()
+        out[name] = {"ms_per_step": 1e3 * wall, "lo_ms": st["t_lo_ms"], "outer": st["outer"],
+                     "newton": st["inner_total"], "cg": st["cg_total"],
+                     "us_per_cg_iteration": 1e3 * st["t_lo_ms"] / max(st["cg_total"], 1)}
+    out["step_speedup"] = out["jacobi"]["ms_per_step"] / out["multigrid"]["ms_per_step"]
+    return out
 
 
 def adjoint():
@@ -157,7 +190,7 @@ def adjoint():
     p = W.adjoint_2d()
     tight = dict(eps_outer=1e-10, eps_inner=1e-11, cg_rtol=1e-13, elim_rtol=1e-15, max_outer=200, max_inner=60,
                  max_cg=500, max_elim=100)
-    ctx = smrt.Context(p, precision=smrt.SMRT_FP64, **tight)
+    ctx = smrt.Context(p, precision=smrt.SMRT_FP64, lo_graphs=LO_GRAPHS, **tight)
     T0 = p.initial_T_nodes()
     ctx.set_state(T0)
     t0 = _t.perf_counter()
@@ -197,9 +230,14 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-problem batched-sweep measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient measurement")
     ap.add_argument("--no-step", action="store_true", help="skip the full time-step measurement")
+    ap.add_argument("--no-multigrid", action="store_true", help="skip the LO preconditioner comparison")
+    ap.add_argument("--lo-graphs", type=int, default=1, choices=(0, 1),
+                    help="0: launch the LO conjugate-gradient kernels directly instead of replaying graphs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference point for HBM byte counters)")
     args = ap.parse_args()
+    global LO_GRAPHS
+    LO_GRAPHS = args.lo_graphs
     if args.gpus != 1:
         print("bench.py measures one MI355X: this build runs on a single GPU (the multi-GPU sharding "
               "of the sweep is described in DESIGN.md); use --gpus 1", file=sys.stderr)
@@ -216,7 +254,7 @@ def main():
     T0 = p.initial_T_nodes()
 
     def make(prec, T=T0, psi=None):
-        ctx = smrt.Context(p, precision=prec, stream=stream)
+        ctx = smrt.Context(p, precision=prec, stream=stream, lo_graphs=LO_GRAPHS)
         if args.waves or args.pairs:
             ctx.set_launch(args.waves, args.pairs if prec == smrt.SMRT_FP32 else min(args.pairs, 1))
         ctx.set_state(T, psi)
@@ -350,6 +388,8 @@ def main():
         out["batched"] = batched(args)
     if not args.no_adjoint:
         out["adjoint"] = adjoint()
+    if not args.no_multigrid:
+        out["lo_multigrid"] = lo_multigrid()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
