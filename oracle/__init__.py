@@ -64,6 +64,11 @@ class Opts(C.Structure):
                 ("fixup", C.c_int), ("T_floor", C.c_double)]
 
 
+class QGeom(C.Structure):
+    _fields_ = [("nv", C.c_int), ("nc", C.c_int), ("xy", _dp), ("cv", _ip), ("nang", C.c_int), ("om", _dp),
+                ("w", _dp), ("G", C.c_int)]
+
+
 class Stats(C.Structure):
     _fields_ = [("outer", C.c_int), ("inner_total", C.c_int), ("cg_total", C.c_int),
                 ("elim_max", C.c_int), ("hit_max", C.c_int), ("energy_residual", C.c_double)]
@@ -100,6 +105,10 @@ def _declare(L):
     L.orc_step.argtypes = [gp, mp, bp, op, C.c_double, _dp, _dp, _dp, _dp, sp]
     L.orc_step.restype = C.c_int
     L.orc_equilibrium_psi.argtypes = [gp, _dp, _dp]
+    L.orc_qmesh_nbnodes.argtypes = [C.POINTER(QGeom)]
+    L.orc_qmesh_nbnodes.restype = C.c_int
+    L.orc_qsweep.argtypes = [C.POINTER(QGeom), _dp, _dp, _dp, C.c_double, _dp, _dp]
+    L.orc_qsweep.restype = C.c_int
 
 
 def _p(a):
@@ -300,3 +309,31 @@ class Oracle:
                             float(dt if dt is not None else p.dt), _p(s["psi"]), _p(s["T"]), _p(s["E"]),
                             _p(s["F"]), C.byref(st))
         return r, s, st.as_dict()
+
+
+class QuadMesh:
+    """The lumped bilinear DG sweep on an unstructured quadrilateral mesh
+    (vertices xy[v][2], cells[c][4] counter-clockwise) with the quadrature
+    omega[d][3], w[d] and G groups."""
+
+    def __init__(self, xy, cells, omega, w, G):
+        self.L = lib()
+        self.xy = _f64(xy).reshape(-1, 2)
+        self.cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, 4)
+        self.om = _f64(omega).reshape(-1, 3)
+        self.w = _f64(w)
+        self.G = int(G)
+        self.geom = QGeom(len(self.xy), len(self.cells), _p(self.xy), self.cells.ctypes.data_as(_ip),
+                          len(self.w), _p(self.om), _p(self.w), self.G)
+        self.nb = self.L.orc_qmesh_nbnodes(C.byref(self.geom))
+        assert self.nb >= 0, "non-manifold mesh"
+
+    def sweep(self, sig_t, q_iso, psi_prev, inv_c_dt, inflow):
+        nn = 4 * len(self.cells)
+        out = np.zeros((len(self.w), self.G, nn))
+        pp = _f64(psi_prev) if psi_prev is not None else None
+        inf = _f64(inflow) if inflow is not None else None
+        r = self.L.orc_qsweep(C.byref(self.geom), _p(_f64(sig_t)), _p(_f64(q_iso)), _p(pp), float(inv_c_dt),
+                              _p(inf), _p(out))
+        assert r == 0, f"orc_qsweep returned {r}"
+        return out

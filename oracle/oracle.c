@@ -1442,3 +1442,190 @@ int orc_objective(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const 
     free(psi); free(T); free(E); free(F);
     return rc;
 }
+
+/* ======================================================================== */
+/* Unstructured quadrilateral meshes: the lumped bilinear DG sweep of       */
+/* Eq. dgsn_transport on general convex quadrilaterals (the paper's refined */
+/* meshes use trapezoidal corner cells), cells taken in a dependency order  */
+/* per direction.                                                           */
+/*                                                                          */
+/* Mesh: nv vertices xy[v][2]; nc cells cv[c][4] listed counter-clockwise.  */
+/* Node n = 4 c + l is the cell's l-th vertex.  The bilinear map from the   */
+/* reference square (vertices (0,0), (1,0), (1,1), (0,1)) gives at vertex m */
+/* the Jacobian J_m; the trapezoid (vertex) quadrature gives the lumped     */
+/* weight w_m = det J_m / 4 and grad phi_l(x_m) = J_m^-T grad_ref phi_l.    */
+/* Edge e joins local vertices e and e+1 (mod 4) with outward normal times  */
+/* length nL_e; each endpoint gets half of it (trapezoid).  Local system    */
+/*   A_lm = sigt w_l delta_lm - w_m Omega.grad(phi_l)(x_m)                 */
+/*        + delta_lm sum_{edges e of l, Omega.nL_e > 0} Omega.nL_e / 2      */
+/*   b_l  = w_l q_l - sum_{edges e of l, Omega.nL_e < 0} Omega.nL_e/2 I_up  */
+/* I_up the neighbour's node at the same vertex, or the inflow of the       */
+/* boundary node.  Boundary edges are numbered in (cell, edge) order; the   */
+/* boundary node 2 k + j is the j-th endpoint of boundary edge k.           */
+/* ======================================================================== */
+
+typedef struct {
+    int nv, nc;
+    const double *xy;   /* [nv][2] */
+    const int *cv;      /* [nc][4] counter-clockwise */
+    int nang;
+    const double *om;   /* [nang][3] */
+    const double *w;
+    int G;
+} orc_qgeom;
+
+typedef struct { int a, b, c, e; } orc_qedge;
+
+static int qedge_cmp(const void *x, const void *y)
+{
+    const orc_qedge *p = x, *q = y;
+    if (p->a != q->a) return p->a < q->a ? -1 : 1;
+    if (p->b != q->b) return p->b < q->b ? -1 : 1;
+    if (p->c != q->c) return p->c < q->c ? -1 : 1;
+    return p->e - q->e;
+}
+
+/* nb[4c+e] = neighbour cell across edge e (-1 on the boundary); bedge[4c+e] = boundary edge index or -1 */
+static int qmesh_connect(const orc_qgeom *q, int *nb, int *bedge)
+{
+    int ne = 4 * q->nc, nbnd = 0;
+    orc_qedge *E = malloc(sizeof(orc_qedge) * ne);
+    for (int c = 0; c < q->nc; ++c)
+        for (int e = 0; e < 4; ++e) {
+            int v0 = q->cv[4 * c + e], v1 = q->cv[4 * c + (e + 1) % 4];
+            E[4 * c + e] = (orc_qedge){v0 < v1 ? v0 : v1, v0 < v1 ? v1 : v0, c, e};
+            nb[4 * c + e] = -1;
+        }
+    qsort(E, ne, sizeof(orc_qedge), qedge_cmp);
+    for (int k = 0; k < ne; ++k) {
+        if (k + 1 < ne && E[k].a == E[k + 1].a && E[k].b == E[k + 1].b) {
+            if (k + 2 < ne && E[k + 2].a == E[k].a && E[k + 2].b == E[k].b) { free(E); return -1; }  /* non-manifold */
+            nb[4 * E[k].c + E[k].e] = E[k + 1].c;
+            nb[4 * E[k + 1].c + E[k + 1].e] = E[k].c;
+            ++k;
+        }
+    }
+    free(E);
+    for (int c = 0; c < q->nc; ++c)
+        for (int e = 0; e < 4; ++e) bedge[4 * c + e] = nb[4 * c + e] < 0 ? nbnd++ : -1;
+    return nbnd;
+}
+
+int orc_qmesh_nbnodes(const orc_qgeom *q)
+{
+    int *nb = malloc(sizeof(int) * 4 * q->nc), *be = malloc(sizeof(int) * 4 * q->nc);
+    int n = qmesh_connect(q, nb, be);
+    free(nb); free(be);
+    return n < 0 ? n : 2 * n;
+}
+
+/* reference gradient of phi_l at reference vertex m (vertices (0,0),(1,0),(1,1),(0,1)) */
+static void qref_grad(int l, int m, double g[2])
+{
+    static const double V[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+    double xi = V[m][0], eta = V[m][1];
+    switch (l) {
+        case 0: g[0] = -(1 - eta); g[1] = -(1 - xi); break;
+        case 1: g[0] = 1 - eta; g[1] = -xi; break;
+        case 2: g[0] = eta; g[1] = xi; break;
+        default: g[0] = -eta; g[1] = 1 - xi; break;
+    }
+}
+
+/* per cell: w[m], G[l][m][2] = grad phi_l(x_m), nL[e][2]; returns -1 if not positively oriented */
+static int qcell_terms(const orc_qgeom *q, int c, double w[4], double G[4][4][2], double nL[4][2])
+{
+    double X[4][2];
+    for (int l = 0; l < 4; ++l) { X[l][0] = q->xy[2 * q->cv[4 * c + l]]; X[l][1] = q->xy[2 * q->cv[4 * c + l] + 1]; }
+    for (int m = 0; m < 4; ++m) {
+        double J[2][2] = {{0, 0}, {0, 0}};   /* J[i][k] = d x_i / d ref_k */
+        for (int l = 0; l < 4; ++l) {
+            double g[2];
+            qref_grad(l, m, g);
+            for (int i = 0; i < 2; ++i) for (int k = 0; k < 2; ++k) J[i][k] += X[l][i] * g[k];
+        }
+        double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        if (!(det > 0.0)) return -1;
+        w[m] = det / 4.0;
+        for (int l = 0; l < 4; ++l) {
+            double g[2];
+            qref_grad(l, m, g);
+            /* solve J^T y = g */
+            G[l][m][0] = (J[1][1] * g[0] - J[1][0] * g[1]) / det;
+            G[l][m][1] = (-J[0][1] * g[0] + J[0][0] * g[1]) / det;
+        }
+    }
+    for (int e = 0; e < 4; ++e) {
+        int b = (e + 1) % 4;
+        nL[e][0] = X[b][1] - X[e][1];
+        nL[e][1] = -(X[b][0] - X[e][0]);
+    }
+    return 0;
+}
+
+int orc_qsweep(const orc_qgeom *q, const double *sig_t, const double *q_iso, const double *psi_prev,
+               double inv_c_dt, const double *inflow, double *psi)
+{
+    int nc = q->nc, G = q->G, nn = 4 * nc;
+    int *nb = malloc(sizeof(int) * 4 * nc), *be = malloc(sizeof(int) * 4 * nc);
+    int nbe = qmesh_connect(q, nb, be), NB = 2 * nbe;
+    int *indeg = malloc(sizeof(int) * nc), *order = malloc(sizeof(int) * nc);
+    int status = nbe < 0 ? -1 : ORC_OK;
+    for (int d = 0; d < q->nang && status == ORC_OK; ++d) {
+        double mu = q->om[3 * d], eta = q->om[3 * d + 1];
+        /* dependency order (Kahn): a cell waits for the neighbours across its inflow edges */
+        for (int c = 0; c < nc; ++c) indeg[c] = 0;
+        for (int c = 0; c < nc && status == ORC_OK; ++c) {
+            double w[4], Gr[4][4][2], nL[4][2];
+            if (qcell_terms(q, c, w, Gr, nL)) { status = -2; break; }
+            for (int e = 0; e < 4; ++e)
+                if (nb[4 * c + e] >= 0 && mu * nL[e][0] + eta * nL[e][1] < 0.0) indeg[c]++;
+        }
+        int head = 0, tail = 0;
+        for (int c = 0; c < nc; ++c) if (indeg[c] == 0) order[tail++] = c;
+        while (head < tail && status == ORC_OK) {
+            int c = order[head++];
+            double w[4], Gr[4][4][2], nL[4][2];
+            qcell_terms(q, c, w, Gr, nL);
+            for (int k = 0; k < G; ++k) {
+                const double *pp = psi_prev ? psi_prev + ((size_t)d * G + k) * nn : NULL;
+                double *out = psi + ((size_t)d * G + k) * nn;
+                const double *inf = inflow ? inflow + ((size_t)d * G + k) * NB : NULL;
+                double A[16], b[4], x[4], st = sig_t[(size_t)c * G + k];
+                for (int l = 0; l < 4; ++l) {
+                    double ql = q_iso[(size_t)(4 * c + l) * G + k];
+                    if (pp) ql += inv_c_dt * pp[4 * c + l];
+                    b[l] = w[l] * ql;
+                    for (int m = 0; m < 4; ++m)
+                        A[4 * l + m] = (l == m ? st * w[l] : 0.0) - w[m] * (mu * Gr[l][m][0] + eta * Gr[l][m][1]);
+                }
+                for (int e = 0; e < 4; ++e) {
+                    double on = 0.5 * (mu * nL[e][0] + eta * nL[e][1]);
+                    for (int j = 0; j < 2; ++j) {
+                        int l = (e + j) % 4;
+                        if (on > 0.0) { A[4 * l + l] += on; continue; }
+                        double up = 0.0;
+                        int n2 = nb[4 * c + e];
+                        if (n2 >= 0) {
+                            int v = q->cv[4 * c + l], l2 = 0;
+                            while (l2 < 4 && q->cv[4 * n2 + l2] != v) ++l2;
+                            up = out[4 * n2 + l2];
+                        } else if (inf) {
+                            up = inf[2 * be[4 * c + e] + j];
+                        }
+                        b[l] -= on * up;
+                    }
+                }
+                if (lu_solve(4, A, b, x)) { status = -1; break; }
+                for (int l = 0; l < 4; ++l) out[4 * c + l] = x[l];
+            }
+            for (int e = 0; e < 4; ++e) {
+                int n2 = nb[4 * c + e];
+                if (n2 >= 0 && mu * nL[e][0] + eta * nL[e][1] > 0.0 && --indeg[n2] == 0) order[tail++] = n2;
+            }
+        }
+        if (status == ORC_OK && tail != nc) status = -3;   /* a dependency cycle */
+    }
+    free(nb); free(be); free(indeg); free(order);
+    return status;
+}

@@ -304,3 +304,76 @@ def boundary_node_count(p: Problem) -> int:
     x- side (2*ny), x+ side (2*ny), y- side (2*nx), y+ side (2*nx); along a
     side, cell index then local face node in increasing coordinate."""
     return 2 if p.dim == 1 else 4 * (p.nx + p.ny)
+
+
+# ----------------------------------------------------------------------------
+# Unstructured quadrilateral meshes (vertices xy[v][2], cells [c][4]
+# counter-clockwise), seeded
+# ----------------------------------------------------------------------------
+
+def quad_mesh_jittered(nx: int, ny: int, jitter: float = 0.25, seed: int = 0, x_edges=None, y_edges=None):
+    """Logically structured quadrilaterals: the vertices of a rectilinear grid
+    (uniform on [0,1]^2 unless edges are given), interior ones moved by up to
+    jitter x the local spacing in each coordinate (jitter < 0.3 keeps every
+    cell convex).  Returns (xy, cells)."""
+    xs = np.linspace(0.0, 1.0, nx + 1) if x_edges is None else np.asarray(x_edges, float)
+    ys = np.linspace(0.0, 1.0, ny + 1) if y_edges is None else np.asarray(y_edges, float)
+    X, Y = np.meshgrid(xs, ys)
+    if jitter > 0 and nx > 1 and ny > 1:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        hx = np.minimum(np.diff(xs)[:-1], np.diff(xs)[1:])[None, :]
+        hy = np.minimum(np.diff(ys)[:-1], np.diff(ys)[1:])[:, None]
+        X[1:-1, 1:-1] += jitter * hx * rng.uniform(-1, 1, (ny - 1, nx - 1))
+        Y[1:-1, 1:-1] += jitter * hy * rng.uniform(-1, 1, (ny - 1, nx - 1))
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    v = lambda i, j: j * (nx + 1) + i
+    cells = np.array([[v(i, j), v(i + 1, j), v(i + 1, j + 1), v(i, j + 1)] for j in range(ny) for i in range(nx)],
+                     dtype=np.int32)
+    return xy, cells
+
+
+def quad_mesh_split_triangles(n: int, jitter: float = 0.2, seed: int = 0):
+    """An unstructured quadrilateral mesh of [0,1]^2: an n x n grid of squares
+    (interior vertices jittered), each cut into two triangles along a
+    diagonal chosen at random, each triangle cut into three quadrilaterals by
+    its centroid and edge midpoints (vertices of valence 3 at the centroids,
+    up to 8 at the grid vertices).  Returns (xy, cells)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gx, gy = np.meshgrid(np.linspace(0, 1, n + 1), np.linspace(0, 1, n + 1))
+    if jitter > 0 and n > 1:
+        gx[1:-1, 1:-1] += jitter / n * rng.uniform(-1, 1, (n - 1, n - 1))
+        gy[1:-1, 1:-1] += jitter / n * rng.uniform(-1, 1, (n - 1, n - 1))
+    pts = [tuple(p) for p in np.stack([gx.ravel(), gy.ravel()], axis=1)]
+    mid = {}
+
+    def midpoint(a, b):
+        k = (min(a, b), max(a, b))
+        if k not in mid:
+            pts.append(((pts[a][0] + pts[b][0]) / 2, (pts[a][1] + pts[b][1]) / 2))
+            mid[k] = len(pts) - 1
+        return mid[k]
+
+    cells = []
+    g = lambda i, j: j * (n + 1) + i
+    for j in range(n):
+        for i in range(n):
+            a, b, c, d = g(i, j), g(i + 1, j), g(i + 1, j + 1), g(i, j + 1)
+            tris = [(a, b, c), (a, c, d)] if rng.uniform() < 0.5 else [(a, b, d), (b, c, d)]
+            for (p, q, r) in tris:                                   # counter-clockwise
+                pts.append(tuple(np.mean([pts[p], pts[q], pts[r]], axis=0)))
+                ctr = len(pts) - 1
+                mpq, mqr, mrp = midpoint(p, q), midpoint(q, r), midpoint(r, p)
+                cells += [[p, mpq, ctr, mrp], [q, mqr, ctr, mpq], [r, mrp, ctr, mqr]]
+    return np.array(pts, dtype=np.float64), np.array(cells, dtype=np.int32)
+
+
+def quad_sweep_inputs(n_cells: int, n_angles: int, G: int, n_bnodes: int, seed: int = 0):
+    """Seeded sweep inputs on a quadrilateral mesh: sig_t[c][G] log-uniform
+    [0.5, 200], q_iso[node][G], psi_prev[d][g][node] and inflow[d][g][b]
+    uniform [0, 1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sigt = _log_uniform(rng, 0.5, 200.0, (n_cells, G))
+    q = rng.uniform(0, 1, (4 * n_cells, G))
+    pp = rng.uniform(0, 1, (n_angles, G, 4 * n_cells))
+    inf = rng.uniform(0, 1, (n_angles, G, n_bnodes))
+    return sigt, q, pp, inf

@@ -1,0 +1,175 @@
+"""Pins of the oracle's sweep on unstructured quadrilateral meshes (the
+lumped bilinear DG of Eq. dgsn_transport on general convex quadrilaterals,
+cells taken in a dependency order per direction):
+
+* on a rectilinear mesh given as quadrilaterals it equals the rectilinear
+  oracle (itself pinned by closed forms, manufactured solutions and balance);
+* a uniform medium with the matching isotropic inflow gives the uniform
+  intensity q/sigma exactly on skewed and on unstructured meshes (the
+  trapezoid-lumped volume term integrates constants by parts exactly);
+* every cell's particle balance, recomputed here from the vertex Jacobians
+  and face fluxes, holds;
+* numbering the cells differently, or starting each cell's vertex list at
+  another vertex, changes nothing.
+"""
+import numpy as np
+import pytest
+
+from paper_2504_21784_amd import workloads as W
+
+
+def _quad(oracle_mod, xy, cells, sn=4, G=2):
+    om, w = W.level_symmetric_2d(sn)
+    return oracle_mod.QuadMesh(xy, cells, om, w, G), om, w
+
+
+def test_rectilinear_mesh_as_quads_equals_rectilinear_oracle(oracle_mod):
+    nx, ny, G = 7, 5, 2
+    rng = np.random.default_rng(4)
+    xe = np.cumsum(np.r_[0.0, rng.uniform(0.5, 1.5, nx)])
+    ye = np.cumsum(np.r_[0.0, rng.uniform(0.5, 1.5, ny)])
+    xe, ye = xe / xe[-1], ye / ye[-1]
+    p = W.gray_2d(n=4, sn=4)
+    p.nx, p.ny, p.x_edges, p.y_edges, p.G = nx, ny, xe, ye, G
+    p.nu_edges = np.logspace(-2, 1, G + 1)
+    p.region_of_cell = np.zeros(nx * ny, np.int32)
+    p.sigma0 = np.ones((1, G))
+    sigt, q, pp, inf = W.random_sweep_inputs(p, seed=9)
+    ref = oracle_mod.Oracle(p).sweep(sigt, q, pp, 0.6, inf)
+    xy, cells = W.quad_mesh_jittered(nx, ny, jitter=0.0, x_edges=xe, y_edges=ye)
+    m, om, w = _quad(oracle_mod, xy, cells, 4, G)
+    # rectilinear local node l = lx + 2 ly; quadrilateral local vertices (0,0), (1,0), (1,1), (0,1)
+    perm = [0, 1, 3, 2]
+    qq = np.zeros_like(q)
+    for c in range(nx * ny):
+        for lq in range(4):
+            qq[4 * c + lq] = q[4 * c + perm[lq]]
+    ppq = pp.reshape(p.n_angles, G, nx * ny, 4)[:, :, :, perm].reshape(p.n_angles, G, -1)
+    # boundary edges in (cell, edge) order; edge e runs from vertex e to e+1
+    infq = np.zeros((p.n_angles, G, m.nb))
+    k = 0
+    for c in range(nx * ny):
+        i, j = c % nx, c // nx
+        for e in range(4):
+            onb = (e == 0 and j == 0) or (e == 1 and i == nx - 1) or (e == 2 and j == ny - 1) or (e == 3 and i == 0)
+            if not onb:
+                continue
+            for t in range(2):
+                lq = (e + t) % 4
+                lx, ly = perm[lq] & 1, perm[lq] >> 1
+                if e == 0:
+                    b = 4 * ny + 2 * i + lx
+                elif e == 1:
+                    b = 2 * ny + 2 * j + ly
+                elif e == 2:
+                    b = 4 * ny + 2 * nx + 2 * i + lx
+                else:
+                    b = 2 * j + ly
+                infq[:, :, 2 * k + t] = inf[:, :, b]
+            k += 1
+    assert k == m.nb // 2
+    got = m.sweep(sigt, qq, ppq, 0.6, infq)
+    want = ref.reshape(p.n_angles, G, nx * ny, 4)[:, :, :, perm].reshape(p.n_angles, G, -1)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("kind", ["jittered", "split"])
+def test_uniform_medium_reproduced(oracle_mod, kind):
+    xy, cells = (W.quad_mesh_jittered(9, 7, jitter=0.28, seed=2) if kind == "jittered"
+                 else W.quad_mesh_split_triangles(5, seed=3))
+    m, om, w = _quad(oracle_mod, xy, cells, 8, 1)
+    nc = len(cells)
+    sig = np.full((nc, 1), 4.0)
+    q = np.full((4 * nc, 1), 6.0)
+    psi = m.sweep(sig, q, None, 0.0, np.full((len(w), 1, m.nb), 1.5))
+    assert np.abs(psi - 1.5).max() <= 1e-13
+
+
+def _cell_terms(X):
+    """w_m = det J_m / 4 and nL_e for one cell (vertices X[4][2], counter-clockwise)."""
+    ref = [(0, 0), (1, 0), (1, 1), (0, 1)]
+    w = np.zeros(4)
+    for m, (xi, eta) in enumerate(ref):
+        dxi = (1 - eta) * (X[1] - X[0]) + eta * (X[2] - X[3])
+        deta = (1 - xi) * (X[3] - X[0]) + xi * (X[2] - X[1])
+        w[m] = (dxi[0] * deta[1] - dxi[1] * deta[0]) / 4
+    nL = np.array([[X[(e + 1) % 4][1] - X[e][1], -(X[(e + 1) % 4][0] - X[e][0])] for e in range(4)])
+    return w, nL
+
+
+def test_cell_balance_on_unstructured_mesh(oracle_mod):
+    xy, cells = W.quad_mesh_split_triangles(5, seed=5)
+    m, om, w = _quad(oracle_mod, xy, cells, 4, 2)
+    nc = len(cells)
+    sigt, q, pp, inf = W.quad_sweep_inputs(nc, len(w), 2, m.nb, seed=6)
+    psi = m.sweep(sigt, q, pp, 0.3, inf)
+    # edges: neighbour across each (cell, edge); boundary edges numbered in (cell, edge) order
+    owner = {}
+    for c in range(nc):
+        for e in range(4):
+            owner.setdefault(frozenset((cells[c][e], cells[c][(e + 1) % 4])), []).append((c, e))
+    bidx, k = {}, 0
+    for c in range(nc):
+        for e in range(4):
+            if len(owner[frozenset((cells[c][e], cells[c][(e + 1) % 4]))]) == 1:
+                bidx[(c, e)] = k
+                k += 1
+    worst = 0.0
+    for d in range(len(w)):
+        Om = om[d, :2]
+        for g in range(2):
+            I = psi[d, g]
+            for c in range(nc):
+                X = xy[cells[c]]
+                wl, nL = _cell_terms(X)
+                src = wl @ (q[4 * c:4 * c + 4, g] + 0.3 * pp[d, g, 4 * c:4 * c + 4])
+                bal = sigt[c, g] * (wl @ I[4 * c:4 * c + 4]) - src
+                for e in range(4):
+                    on = 0.5 * (Om @ nL[e])
+                    for t in range(2):
+                        l = (e + t) % 4
+                        if on > 0:
+                            bal += on * I[4 * c + l]
+                        else:
+                            sh = [x for x in owner[frozenset((cells[c][e], cells[c][(e + 1) % 4]))] if x[0] != c]
+                            if sh:
+                                c2 = sh[0][0]
+                                l2 = list(cells[c2]).index(cells[c][l])
+                                bal += on * I[4 * c2 + l2]
+                            else:
+                                bal += on * inf[d, g, 2 * bidx[(c, e)] + t]
+                worst = max(worst, abs(bal) / (abs(src) + 1e-300))
+    assert worst < 1e-12
+
+
+def test_numbering_does_not_matter(oracle_mod):
+    xy, cells = W.quad_mesh_split_triangles(4, seed=7)
+    nc = len(cells)
+    m, om, w = _quad(oracle_mod, xy, cells, 4, 1)
+    sigt, q, pp, _ = W.quad_sweep_inputs(nc, len(w), 1, m.nb, seed=8)
+    # a smooth inflow that depends only on the boundary position, so it can follow the renumbering
+    def inflow_for(cells_):
+        vals, k = [], 0
+        edges = {}
+        for c in range(len(cells_)):
+            for e in range(4):
+                edges.setdefault(frozenset((cells_[c][e], cells_[c][(e + 1) % 4])), []).append(c)
+        out = []
+        for c in range(len(cells_)):
+            for e in range(4):
+                if len(edges[frozenset((cells_[c][e], cells_[c][(e + 1) % 4]))]) == 1:
+                    for t in range(2):
+                        x = xy[cells_[c][(e + t) % 4]]
+                        out.append(1.0 + np.sin(3 * x[0]) * np.cos(2 * x[1]))
+        return np.broadcast_to(np.array(out)[None, None, :], (len(w), 1, len(out))).copy()
+    # a node value field that depends on the physical vertex and the cell
+    base = m.sweep(sigt, q, None, 0.0, inflow_for(cells))
+    rng = np.random.default_rng(9)
+    perm = rng.permutation(nc)
+    rot = rng.integers(0, 4, nc)
+    cells2 = np.array([np.roll(cells[perm[k]], -rot[k]) for k in range(nc)], dtype=np.int32)
+    # node 4k + l of the new mesh is node 4 perm[k] + (l + rot[k]) % 4 of the old
+    src = np.array([4 * perm[k] + (l + rot[k]) % 4 for k in range(nc) for l in range(4)])
+    m2, _, _ = _quad(oracle_mod, xy, cells2, 4, 1)
+    got = m2.sweep(sigt[perm], q[src], None, 0.0, inflow_for(cells2))
+    assert np.abs(got - base[:, :, src]).max() <= 1e-13 * np.abs(base).max()
