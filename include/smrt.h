@@ -386,6 +386,43 @@ smrt_status smrt_batch_sweep_resident(smrt_batch *batch, double dt, int n_times,
  * the first problem's failure status (message in smrt_batch_last_error). */
 smrt_status smrt_batch_step(smrt_batch *batch, const double *dt, smrt_step_stats *stats);
 
+/* ------------------------------------------------------------------------
+ * Unstructured quadrilateral meshes (the paper's refined meshes have
+ * trapezoidal corner cells; Sec. 6).  The lumped bilinear DG sweep of
+ * Eq. dgsn_transport on general convex quadrilaterals: at vertex m of a
+ * cell the bilinear map's Jacobian J_m gives the lumped weight det(J_m)/4
+ * and the basis gradients; each edge's normal times length is split evenly
+ * between its two vertices.  Cells are swept per direction in dependency
+ * levels (all directions' pairs of a level in one launch).
+ * ------------------------------------------------------------------------ */
+typedef struct smrt_qmesh smrt_qmesh;
+
+/* n_vertices points xy[v][2]; n_cells cells[c][4] vertex indices listed
+ * counter-clockwise (node n = 4c + l is vertex l of cell c); the quadrature
+ * (weights > 0 summing to 4 pi; omega[d][0..1] used); G groups; precision of
+ * the sweep.  Boundary edges are numbered in (cell, edge) order, edge e
+ * joining vertices e and e+1 (mod 4); boundary node 2k + j is the j-th
+ * endpoint of boundary edge k.  Errors: SMRT_E_INVALID_ARG (NULL or empty
+ * mesh, index out of range, a cell that is not convex and counter-clockwise,
+ * an edge shared by more than two cells, a direction whose upwind
+ * dependencies form a cycle), SMRT_E_OUT_OF_MEMORY, SMRT_E_DEVICE.
+ * hip_stream: a hipStream_t, or NULL for one owned by the mesh.  Copies
+ * everything it needs. */
+smrt_status smrt_qmesh_create(int n_vertices, const double *xy, int n_cells, const int32_t *cells,
+                              const smrt_quad_desc *quad, int G, smrt_precision precision, void *hip_stream,
+                              smrt_qmesh **out);
+void smrt_qmesh_destroy(smrt_qmesh *mesh);
+const char *smrt_qmesh_last_error(const smrt_qmesh *mesh);
+/* Number of boundary nodes and of dependency levels (launches per sweep). */
+smrt_status smrt_qmesh_info(const smrt_qmesh *mesh, int *n_boundary_nodes, int *n_levels);
+/* One sweep of every (d, g): sig_t[cell][G] (> 0, incl. time absorption),
+ * q_iso[node][G], psi_prev[d][g][node] or NULL (zero), inv_c_dt >= 0,
+ * inflow[d][g][boundary node] or NULL (vacuum), all host FP64; psi_out
+ * [d][g][node] FP64 host; ms_kernel (may be NULL) receives the time of the
+ * sweep launches.  Errors: SMRT_E_INVALID_ARG, SMRT_E_DEVICE. */
+smrt_status smrt_qmesh_sweep(smrt_qmesh *mesh, const double *sig_t, const double *q_iso, const double *psi_prev,
+                             double inv_c_dt, const double *inflow, double *psi_out, double *ms_kernel);
+
 #ifdef __cplusplus
 }
 #endif

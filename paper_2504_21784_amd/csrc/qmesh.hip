@@ -1,0 +1,420 @@
+// Lumped bilinear DG S_N sweep on unstructured quadrilateral meshes.
+//
+// What is computed (Eq. dgsn_transport on general convex quadrilaterals,
+// every form lumped by the vertex (trapezoid) rule): for every (direction
+// d, group g) and cell K, the 4x4 local system
+//   A_lm = sigt w_l delta_lm - w_m Omega.grad(phi_l)(x_m)
+//        + delta_lm sum_{edges e of l, Omega.nL_e > 0} Omega.nL_e / 2
+//   b_l  = w_l (q_l + inv_c_dt I*_l) - sum_{edges e of l, Omega.nL_e < 0} Omega.nL_e / 2 I_up
+// with, at vertex m of the bilinear map from the reference square,
+// w_m = det J_m / 4 and w_m grad(phi_l)(x_m) = w_m J_m^-T grad_ref(phi_l)(m);
+// nL_e is edge e's outward normal times its length; I_up is the upwind
+// neighbour's value at the same vertex, or the boundary inflow.
+//
+// Schedule.  The paper's refined meshes (trapezoidal corner cells) break the
+// diagonal wavefront of the rectilinear kernel, so cells are ordered per
+// direction by their upwind dependencies: the host assigns every (direction,
+// cell) pair a level (one more than the deepest upwind neighbour, Kahn's
+// algorithm; a cycle is an error), and one launch sweeps all pairs of a
+// level, of every direction at once, one thread per (pair, group).  The
+// host also classifies each edge of each pair as inflow or outflow, so the
+// device never disagrees with the schedule about an edge nearly parallel to
+// the direction.  The local system is solved in registers by Gaussian
+// elimination with partial pivoting.  Angular flux layout [d][g][node],
+// node = 4 cell + local vertex (counter-clockwise), as the ABI's.
+#include <cmath>
+#include <memory>
+#include <numeric>
+
+#include "lo.h"
+
+namespace smrt {
+
+struct QGeomCell {
+    double K[4][2][2];   // K_m = w_m J_m^-T (w_m grad phi_l(x_m) = K_m grad_ref phi_l(m))
+    double w[4];         // lumped weights
+    double nL[4][2];     // edge e (vertex e -> e+1): outward normal x length
+};
+
+struct QArgs {
+    int nc, G, nang, NB;
+    const QGeomCell *geo;
+    const int2 *sched;            // (d, cell) by level
+    const unsigned char *flags;   // [d][cell]: bit e inflow edge, bit 4+e outflow edge
+    const int *upw;               // [cell][edge][2]: upwind node (>= 0) or -(1 + boundary node)
+    const double *om;             // [nang][3]
+    const double *sig_t;          // [cell][G]
+    const double *q;              // [node][G]
+    const double *psi_prev;       // [d][g][node] or null
+    const double *inflow;         // [d][g][NB]
+    double inv_c_dt;
+    void *psi;                    // [d][g][node], sweep precision
+};
+
+// reference gradient of phi_l at reference vertex m ((0,0), (1,0), (1,1), (0,1))
+__host__ __device__ inline void qref_grad(int l, int m, double &gx, double &gy) {
+    const double xi = (m == 1 || m == 2) ? 1.0 : 0.0, eta = (m >= 2) ? 1.0 : 0.0;
+    switch (l) {
+        case 0: gx = -(1 - eta); gy = -(1 - xi); break;
+        case 1: gx = 1 - eta; gy = -xi; break;
+        case 2: gx = eta; gy = xi; break;
+        default: gx = -eta; gy = 1 - xi; break;
+    }
+}
+
+template <typename real>
+__global__ void k_qsweep_level(QArgs A, int p0, int p1) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t pair = p0 + t / A.G;
+    if (pair >= p1) return;
+    const int g = (int)(t % A.G);
+    const int2 dc = A.sched[pair];
+    const int d = dc.x, c = dc.y;
+    const int nn = 4 * A.nc;
+    const real mu = (real)A.om[3 * d], eta = (real)A.om[3 * d + 1];
+    const QGeomCell &K = A.geo[c];
+    const unsigned fl = A.flags[(int64_t)d * A.nc + c];
+    real *psi = static_cast<real *>(A.psi);
+    const int64_t slab = ((int64_t)d * A.G + g) * nn;
+    const real st = (real)A.sig_t[(int64_t)c * A.G + g];
+    real M[4][4], b[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        double ql = A.q[(int64_t)(4 * c + l) * A.G + g];
+        if (A.psi_prev) ql += A.inv_c_dt * A.psi_prev[slab + 4 * c + l];
+        b[l] = (real)K.w[l] * (real)ql;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double gx, gy;
+            qref_grad(l, m, gx, gy);
+            // w_m grad phi_l(x_m) = K_m grad_ref phi_l(m)
+            const real ax = (real)(K.K[m][0][0] * gx + K.K[m][0][1] * gy);
+            const real ay = (real)(K.K[m][1][0] * gx + K.K[m][1][1] * gy);
+            M[l][m] = (l == m ? st * (real)K.w[l] : real(0)) - (mu * ax + eta * ay);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const real on = real(0.5) * (mu * (real)K.nL[e][0] + eta * (real)K.nL[e][1]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int l = (e + j) & 3;
+            if ((fl >> (4 + e)) & 1) {
+                M[l][l] += on;
+            } else if ((fl >> e) & 1) {
+                const int u = A.upw[(4 * c + e) * 2 + j];
+                const real up = u >= 0 ? psi[slab + u]
+                                       : (real)A.inflow[((int64_t)d * A.G + g) * A.NB + (-u - 1)];
+                b[l] -= on * up;
+            }
+        }
+    }
+    // Gaussian elimination with partial pivoting (4x4, in registers)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int p = k;
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r)
+            if (fabs(M[r][k]) > fabs(M[p][k])) p = r;
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            if (r != p) continue;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) { const real tmp = M[k][cc]; M[k][cc] = M[r][cc]; M[r][cc] = tmp; }
+            const real tmp = b[k]; b[k] = b[r]; b[r] = tmp;
+        }
+#pragma unroll
+        for (int r = k + 1; r < 4; ++r) {
+            const real f = M[r][k] / M[k][k];
+#pragma unroll
+            for (int cc = k; cc < 4; ++cc) M[r][cc] -= f * M[k][cc];
+            b[r] -= f * b[k];
+        }
+    }
+    real x[4];
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+        real s = b[k];
+#pragma unroll
+        for (int cc = k + 1; cc < 4; ++cc) s -= M[k][cc] * x[cc];
+        x[k] = s / M[k][k];
+    }
+#pragma unroll
+    for (int l = 0; l < 4; ++l) psi[slab + 4 * c + l] = x[l];
+}
+
+template <typename real>
+__global__ void k_qcopy_out(int64_t n, const real *in, double *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (double)in[i];
+}
+
+}  // namespace smrt
+
+using namespace smrt;
+
+struct smrt_qmesh {
+    std::string err;
+    int nv = 0, nc = 0, nang = 0, G = 0, NB = 0, nlev = 0;
+    bool fp32 = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<int> lev_off;   // [nlev + 1] into sched
+    DevBuf<QGeomCell> geo;
+    DevBuf<int2> sched;
+    DevBuf<unsigned char> flags, psi;
+    DevBuf<int> upw;
+    DevBuf<double> om, sig_t, q, psi_prev, inflow, out;
+    ~smrt_qmesh() {
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+static thread_local std::string g_qmesh_error;
+
+template <typename F>
+static smrt_status qguard(smrt_qmesh *m, F &&f) {
+    try {
+        f();
+        return SMRT_OK;
+    } catch (const smrt::Error &e) {
+        if (m) m->err = e.msg;
+        g_qmesh_error = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        if (m) m->err = "host allocation failed";
+        g_qmesh_error = "host allocation failed";
+        return SMRT_E_OUT_OF_MEMORY;
+    } catch (...) {
+        if (m) m->err = "unexpected exception";
+        g_qmesh_error = "unexpected exception";
+        return SMRT_E_DEVICE;
+    }
+}
+
+static void qrequire(bool ok, const std::string &msg) {
+    if (!ok) throw smrt::Error(SMRT_E_INVALID_ARG, msg);
+}
+
+extern "C" smrt_status smrt_qmesh_create(int n_vertices, const double *xy, int n_cells, const int32_t *cells,
+                                         const smrt_quad_desc *quad, int G, smrt_precision precision, void *hip_stream,
+                                         smrt_qmesh **out) {
+    if (!out) { g_qmesh_error = "out is NULL"; return SMRT_E_INVALID_ARG; }
+    *out = nullptr;
+    std::unique_ptr<smrt_qmesh> h(new (std::nothrow) smrt_qmesh());
+    if (!h) { g_qmesh_error = "host allocation failed"; return SMRT_E_OUT_OF_MEMORY; }
+    smrt_qmesh *m = h.get();
+    const smrt_status st = qguard(m, [&] {
+        qrequire(n_vertices > 0 && n_cells > 0 && xy && cells && quad && quad->omega && quad->w, "NULL or empty mesh");
+        qrequire(G >= 1, "G must be >= 1");
+        qrequire(precision == SMRT_FP64 || precision == SMRT_FP32, "unknown precision");
+        qrequire((int64_t)n_cells * 4 < (1ll << 30), "mesh too large");
+        const int nang = quad->n_angles;
+        qrequire(nang > 0, "no directions");
+        double ws = 0.0;
+        for (int d = 0; d < nang; ++d) {
+            qrequire(quad->w[d] > 0.0, "quadrature weights must be > 0");
+            ws += quad->w[d];
+        }
+        qrequire(std::fabs(ws - 4.0 * M_PI) <= 1e-12 * 4.0 * M_PI, "quadrature weights must sum to 4 pi");
+        m->nv = n_vertices; m->nc = n_cells; m->nang = nang; m->G = G; m->fp32 = precision == SMRT_FP32;
+        const int nc = n_cells;
+        for (int k = 0; k < 4 * nc; ++k) qrequire(cells[k] >= 0 && cells[k] < n_vertices, "vertex index out of range");
+        // geometry
+        std::vector<QGeomCell> geo(nc);
+        for (int c = 0; c < nc; ++c) {
+            double X[4][2];
+            for (int l = 0; l < 4; ++l) { X[l][0] = xy[2 * cells[4 * c + l]]; X[l][1] = xy[2 * cells[4 * c + l] + 1]; }
+            for (int mv = 0; mv < 4; ++mv) {
+                double J[2][2] = {{0, 0}, {0, 0}};
+                for (int l = 0; l < 4; ++l) {
+                    double gx, gy;
+                    qref_grad(l, mv, gx, gy);
+                    for (int i = 0; i < 2; ++i) { J[i][0] += X[l][i] * gx; J[i][1] += X[l][i] * gy; }
+                }
+                const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+                qrequire(det > 0.0, "cells must be convex quadrilaterals listed counter-clockwise");
+                const double w = det / 4.0;
+                geo[c].w[mv] = w;
+                // w J^-T = (1/4) [[J11, -J10], [-J01, J00]]
+                geo[c].K[mv][0][0] = J[1][1] / 4.0;
+                geo[c].K[mv][0][1] = -J[1][0] / 4.0;
+                geo[c].K[mv][1][0] = -J[0][1] / 4.0;
+                geo[c].K[mv][1][1] = J[0][0] / 4.0;
+            }
+            for (int e = 0; e < 4; ++e) {
+                const int b = (e + 1) & 3;
+                geo[c].nL[e][0] = X[b][1] - X[e][1];
+                geo[c].nL[e][1] = -(X[b][0] - X[e][0]);
+            }
+        }
+        // connectivity: pair edges by their sorted vertex pair
+        struct E { int a, b, c, e; };
+        std::vector<E> es(4 * (size_t)nc);
+        for (int c = 0; c < nc; ++c)
+            for (int e = 0; e < 4; ++e) {
+                const int v0 = cells[4 * c + e], v1 = cells[4 * c + ((e + 1) & 3)];
+                es[4 * c + e] = {std::min(v0, v1), std::max(v0, v1), c, e};
+            }
+        std::sort(es.begin(), es.end(), [](const E &x, const E &y) {
+            return x.a != y.a ? x.a < y.a : x.b != y.b ? x.b < y.b : x.c != y.c ? x.c < y.c : x.e < y.e;
+        });
+        std::vector<int> nb(4 * (size_t)nc, -1);
+        for (size_t k = 0; k < es.size(); ++k) {
+            if (k + 1 < es.size() && es[k].a == es[k + 1].a && es[k].b == es[k + 1].b) {
+                qrequire(!(k + 2 < es.size() && es[k + 2].a == es[k].a && es[k + 2].b == es[k].b),
+                         "an edge is shared by more than two cells");
+                nb[4 * es[k].c + es[k].e] = es[k + 1].c;
+                nb[4 * es[k + 1].c + es[k + 1].e] = es[k].c;
+                ++k;
+            }
+        }
+        std::vector<int> upw(8 * (size_t)nc);
+        int nbe = 0;
+        for (int c = 0; c < nc; ++c)
+            for (int e = 0; e < 4; ++e) {
+                const int n2 = nb[4 * c + e];
+                for (int j = 0; j < 2; ++j) {
+                    const int l = (e + j) & 3;
+                    if (n2 >= 0) {
+                        int l2 = 0;
+                        while (l2 < 4 && cells[4 * n2 + l2] != cells[4 * c + l]) ++l2;
+                        upw[(4 * c + e) * 2 + j] = 4 * n2 + l2;
+                    } else {
+                        upw[(4 * c + e) * 2 + j] = -(1 + 2 * nbe + j);
+                    }
+                }
+                if (n2 < 0) ++nbe;
+            }
+        m->NB = 2 * nbe;
+        // per direction: edge classes and levels (Kahn); then the (d, cell) pairs by level
+        std::vector<unsigned char> flags((size_t)nang * nc, 0);
+        std::vector<int> level((size_t)nang * nc, 0), indeg(nc), queue(nc);
+        int maxlev = 0;
+        for (int d = 0; d < nang; ++d) {
+            const double mu = quad->omega[3 * d], eta = quad->omega[3 * d + 1];
+            for (int c = 0; c < nc; ++c) {
+                unsigned f = 0;
+                int deg = 0;
+                for (int e = 0; e < 4; ++e) {
+                    const double on = mu * geo[c].nL[e][0] + eta * geo[c].nL[e][1];
+                    if (on < 0.0) {
+                        f |= 1u << e;
+                        if (nb[4 * c + e] >= 0) ++deg;
+                    } else if (on > 0.0) {
+                        f |= 1u << (4 + e);
+                    }
+                }
+                flags[(size_t)d * nc + c] = (unsigned char)f;
+                indeg[c] = deg;
+            }
+            int head = 0, tail = 0;
+            for (int c = 0; c < nc; ++c) if (indeg[c] == 0) { queue[tail++] = c; level[(size_t)d * nc + c] = 0; }
+            while (head < tail) {
+                const int c = queue[head++];
+                const int lv = level[(size_t)d * nc + c];
+                maxlev = std::max(maxlev, lv);
+                for (int e = 0; e < 4; ++e) {
+                    const int n2 = nb[4 * c + e];
+                    if (n2 < 0 || !((flags[(size_t)d * nc + c] >> (4 + e)) & 1)) continue;
+                    int &ln = level[(size_t)d * nc + n2];
+                    ln = std::max(ln, lv + 1);
+                    if (--indeg[n2] == 0) queue[tail++] = n2;
+                }
+            }
+            qrequire(tail == nc, "the upwind dependencies of a direction form a cycle");
+        }
+        m->nlev = maxlev + 1;
+        std::vector<int> count(m->nlev + 1, 0);
+        for (size_t k = 0; k < level.size(); ++k) count[level[k] + 1]++;
+        std::partial_sum(count.begin(), count.end(), count.begin());
+        m->lev_off = count;
+        std::vector<int2> sched(level.size());
+        std::vector<int> fill(count.begin(), count.end() - 1);
+        for (int d = 0; d < nang; ++d)
+            for (int c = 0; c < nc; ++c) sched[fill[level[(size_t)d * nc + c]]++] = make_int2(d, c);
+        // device
+        if (hip_stream) m->stream = static_cast<hipStream_t>(hip_stream);
+        else { SMRT_HIP(hipStreamCreate(&m->stream)); m->own_stream = true; }
+        const int64_t nn = 4 * (int64_t)nc, npsi = (int64_t)nang * G * nn;
+        m->geo.alloc(nc);
+        m->sched.alloc((int64_t)sched.size());
+        m->flags.alloc((int64_t)flags.size());
+        m->upw.alloc((int64_t)upw.size());
+        m->om.alloc(3 * (int64_t)nang);
+        SMRT_HIP(hipMemcpy(m->geo.p, geo.data(), sizeof(QGeomCell) * nc, hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->sched.p, sched.data(), sizeof(int2) * sched.size(), hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->flags.p, flags.data(), flags.size(), hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->upw.p, upw.data(), sizeof(int) * upw.size(), hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->om.p, quad->omega, sizeof(double) * 3 * nang, hipMemcpyHostToDevice));
+        m->sig_t.alloc((int64_t)nc * G);
+        m->q.alloc(nn * G);
+        m->psi_prev.alloc(npsi);
+        m->inflow.alloc(std::max<int64_t>((int64_t)nang * G * m->NB, 1));
+        m->out.alloc(npsi);
+        m->psi.alloc(npsi * (m->fp32 ? 4 : 8));
+    });
+    if (st != SMRT_OK) return st;
+    *out = h.release();
+    return SMRT_OK;
+}
+
+extern "C" void smrt_qmesh_destroy(smrt_qmesh *m) { delete m; }
+
+extern "C" const char *smrt_qmesh_last_error(const smrt_qmesh *m) { return m ? m->err.c_str() : g_qmesh_error.c_str(); }
+
+extern "C" smrt_status smrt_qmesh_info(const smrt_qmesh *m, int *n_boundary_nodes, int *n_levels) {
+    if (!m) { g_qmesh_error = "mesh is NULL"; return SMRT_E_INVALID_ARG; }
+    if (n_boundary_nodes) *n_boundary_nodes = m->NB;
+    if (n_levels) *n_levels = m->nlev;
+    return SMRT_OK;
+}
+
+extern "C" smrt_status smrt_qmesh_sweep(smrt_qmesh *m, const double *sig_t, const double *q_iso, const double *psi_prev,
+                                        double inv_c_dt, const double *inflow, double *psi_out, double *ms_kernel) {
+    if (!m) { g_qmesh_error = "mesh is NULL"; return SMRT_E_INVALID_ARG; }
+    return qguard(m, [&] {
+        qrequire(sig_t && q_iso && psi_out, "NULL input or output");
+        qrequire(std::isfinite(inv_c_dt) && inv_c_dt >= 0.0, "inv_c_dt must be finite and >= 0");
+        const int64_t nn = 4 * (int64_t)m->nc, npsi = (int64_t)m->nang * m->G * nn;
+        for (int64_t k = 0; k < (int64_t)m->nc * m->G; ++k)
+            qrequire(std::isfinite(sig_t[k]) && sig_t[k] > 0.0, "sig_t must be finite and > 0");
+        hipStream_t s = m->stream;
+        SMRT_HIP(hipMemcpyAsync(m->sig_t.p, sig_t, sizeof(double) * m->nc * m->G, hipMemcpyHostToDevice, s));
+        SMRT_HIP(hipMemcpyAsync(m->q.p, q_iso, sizeof(double) * nn * m->G, hipMemcpyHostToDevice, s));
+        if (psi_prev) SMRT_HIP(hipMemcpyAsync(m->psi_prev.p, psi_prev, sizeof(double) * npsi, hipMemcpyHostToDevice, s));
+        if (inflow) SMRT_HIP(hipMemcpyAsync(m->inflow.p, inflow, sizeof(double) * m->nang * m->G * m->NB,
+                                            hipMemcpyHostToDevice, s));
+        else if (m->NB) SMRT_HIP(hipMemsetAsync(m->inflow.p, 0, sizeof(double) * m->nang * m->G * m->NB, s));
+        QArgs A{};
+        A.nc = m->nc; A.G = m->G; A.nang = m->nang; A.NB = m->NB;
+        A.geo = m->geo.p; A.sched = m->sched.p; A.flags = m->flags.p; A.upw = m->upw.p; A.om = m->om.p;
+        A.sig_t = m->sig_t.p; A.q = m->q.p; A.psi_prev = psi_prev ? m->psi_prev.p : nullptr; A.inflow = m->inflow.p;
+        A.inv_c_dt = inv_c_dt; A.psi = m->psi.p;
+        hipEvent_t e0, e1;
+        SMRT_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); throw Error(SMRT_E_DEVICE, "hipEventCreate failed"); }
+        SMRT_HIP(hipEventRecord(e0, s));
+        for (int L = 0; L < m->nlev; ++L) {
+            const int p0 = m->lev_off[L], p1 = m->lev_off[L + 1];
+            const int64_t nt = (int64_t)(p1 - p0) * m->G;
+            if (nt == 0) continue;
+            const dim3 grid((unsigned)((nt + 255) / 256));
+            if (m->fp32) hipLaunchKernelGGL(k_qsweep_level<float>, grid, dim3(256), 0, s, A, p0, p1);
+            else hipLaunchKernelGGL(k_qsweep_level<double>, grid, dim3(256), 0, s, A, p0, p1);
+        }
+        SMRT_HIP(hipGetLastError());
+        SMRT_HIP(hipEventRecord(e1, s));
+        if (m->fp32) hipLaunchKernelGGL(k_qcopy_out<float>, dim3((unsigned)((npsi + 255) / 256)), dim3(256), 0, s, npsi,
+                                        (const float *)m->psi.p, m->out.p);
+        else hipLaunchKernelGGL(k_qcopy_out<double>, dim3((unsigned)((npsi + 255) / 256)), dim3(256), 0, s, npsi,
+                                (const double *)m->psi.p, m->out.p);
+        SMRT_HIP(hipMemcpyAsync(psi_out, m->out.p, sizeof(double) * npsi, hipMemcpyDeviceToHost, s));
+        SMRT_HIP(hipStreamSynchronize(s));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (ms_kernel) *ms_kernel = ms;
+    });
+}

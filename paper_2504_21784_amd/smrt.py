@@ -113,6 +113,12 @@ _SIGS = {
     "smrt_batch_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _dp], C.c_int),
     "smrt_batch_sweep_resident": ([C.c_void_p, C.c_double, C.c_int, C.c_int, _dp, _dp], C.c_int),
     "smrt_batch_step": ([C.c_void_p, _dp, C.POINTER(StepStats)], C.c_int),
+    "smrt_qmesh_create": ([C.c_int, _dp, C.c_int, C.POINTER(C.c_int32), C.POINTER(QuadDesc), C.c_int, C.c_int,
+                           C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "smrt_qmesh_destroy": ([C.c_void_p], None),
+    "smrt_qmesh_last_error": ([C.c_void_p], C.c_char_p),
+    "smrt_qmesh_info": ([C.c_void_p, _ip, _ip], C.c_int),
+    "smrt_qmesh_sweep": ([C.c_void_p, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp], C.c_int),
 }
 
 
@@ -409,3 +415,50 @@ class Batch:
         st = (StepStats * n)()
         self._check(self.L.smrt_batch_step(self.h, _p(d), st))
         return [s.as_dict() for s in st]
+
+
+class QuadMeshSweep:
+    """The sweep on an unstructured quadrilateral mesh (vertices xy[v][2],
+    cells[c][4] counter-clockwise) with the quadrature omega[d][3], w[d] and
+    G groups, on the GPU."""
+
+    def __init__(self, xy, cells, omega, w, G, precision=SMRT_FP64, stream=None):
+        self.L = load()
+        self._xy = _f64(np.asarray(xy).reshape(-1, 2))
+        self._cells = np.ascontiguousarray(np.asarray(cells).reshape(-1, 4), dtype=np.int32)
+        self._om, self._w = _f64(np.asarray(omega).reshape(-1, 3)), _f64(w)
+        self.G = int(G)
+        self.quad = QuadDesc(len(self._w), _p(self._om), _p(self._w))
+        h = C.c_void_p()
+        st = self.L.smrt_qmesh_create(len(self._xy), _p(self._xy), len(self._cells),
+                                      self._cells.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(self.quad), self.G,
+                                      int(precision), stream, C.byref(h))
+        if st != 0:
+            raise SmrtError(st, self.L.smrt_qmesh_last_error(None).decode())
+        self.h = h
+        nb, nl = C.c_int(0), C.c_int(0)
+        self.L.smrt_qmesh_info(self.h, C.byref(nb), C.byref(nl))
+        self.nb, self.n_levels = nb.value, nl.value
+
+    def sweep(self, sig_t, q_iso, psi_prev, inv_c_dt, inflow=None):
+        """Returns (psi [d][g][node], milliseconds of the sweep launches)."""
+        out = np.zeros((len(self._w), self.G, 4 * len(self._cells)))
+        ms = C.c_double(0.0)
+        pp = _f64(psi_prev) if psi_prev is not None else None
+        inf = _f64(inflow) if inflow is not None else None
+        st = self.L.smrt_qmesh_sweep(self.h, _p(_f64(sig_t)), _p(_f64(q_iso)), _p(pp), float(inv_c_dt), _p(inf),
+                                     _p(out), C.byref(ms))
+        if st != 0:
+            raise SmrtError(st, self.L.smrt_qmesh_last_error(self.h).decode())
+        return out, ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.smrt_qmesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

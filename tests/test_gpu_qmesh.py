@@ -1,0 +1,110 @@
+"""GPU sweep on unstructured quadrilateral meshes against the FP64 oracle,
+through the C ABI: jittered logically structured meshes (ragged sizes, one
+cell) and unstructured ones (triangles cut into three quadrilaterals), FP64
+to 1e-10 and FP32 to 1e-5 of the field's maximum; a rectilinear mesh given
+as quadrilaterals against the rectilinear sweep kernel (two GPU paths that
+share nothing but the problem); the error cases; and the throughput at the
+benchmark's scale (printed).
+"""
+import numpy as np
+import pytest
+
+from paper_2504_21784_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+MESHES = [("jittered", 13, 11, 4, 3), ("jittered", 1, 1, 4, 2), ("jittered", 30, 2, 8, 1), ("split", 6, 6, 8, 2),
+          ("split", 20, 20, 4, 2)]
+
+
+@pytest.mark.parametrize("kind,nx,ny,sn,G", MESHES)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5)])
+def test_qmesh_sweep_matches_oracle(smrt_mod, oracle_mod, kind, nx, ny, sn, G, prec, tol):
+    xy, cells = (W.quad_mesh_jittered(nx, ny, jitter=0.28, seed=nx + ny) if kind == "jittered"
+                 else W.quad_mesh_split_triangles(nx, seed=nx))
+    print(f"{kind} {nx}x{ny}: {len(cells)} cells, S{sn}, G={G}, precision {prec}", flush=True)
+    om, w = W.level_symmetric_2d(sn)
+    ref_mesh = oracle_mod.QuadMesh(xy, cells, om, w, G)
+    sigt, q, pp, inf = W.quad_sweep_inputs(len(cells), len(w), G, ref_mesh.nb, seed=len(cells))
+    ref = ref_mesh.sweep(sigt, q, pp, 0.7, inf)
+    m = smrt_mod.QuadMeshSweep(xy, cells, om, w, G, precision=prec)
+    assert m.nb == ref_mesh.nb
+    psi, ms = m.sweep(sigt, q, pp, 0.7, inf)
+    m.close()
+    assert _rel(psi, ref) < tol
+
+
+def test_qmesh_rectilinear_matches_rectilinear_kernel(smrt_mod):
+    """A non-uniform 64x48 rectilinear mesh given as quadrilaterals, swept by
+    the unstructured path, equals the rectilinear kernel's sweep (FP64)."""
+    nx, ny, G = 64, 48, 2
+    rng = np.random.default_rng(3)
+    xe = np.cumsum(np.r_[0.0, rng.uniform(0.5, 1.5, nx)])
+    ye = np.cumsum(np.r_[0.0, rng.uniform(0.5, 1.5, ny)])
+    xe, ye = xe / xe[-1], ye / ye[-1]
+    p = W.gray_2d(n=4, sn=8)
+    p.nx, p.ny, p.x_edges, p.y_edges, p.G = nx, ny, xe, ye, G
+    p.nu_edges = np.logspace(-2, 1, G + 1)
+    p.region_of_cell = np.zeros(nx * ny, np.int32)
+    p.sigma0 = np.ones((1, G))
+    sigt, q, pp, inf = W.random_sweep_inputs(p, seed=5)
+    ctx = smrt_mod.Context(p, precision=0)
+    ref, _ = ctx.sweep(sigt, 0.5 * sigt, q, pp, 0.4, inf)
+    ctx.close()
+    xy, cells = W.quad_mesh_jittered(nx, ny, jitter=0.0, x_edges=xe, y_edges=ye)
+    perm = [0, 1, 3, 2]       # quadrilateral vertex -> rectilinear local node lx + 2 ly
+    nc = nx * ny
+    src = np.array([4 * c + perm[l] for c in range(nc) for l in range(4)])
+    infq = []
+    for c in range(nc):
+        i, j = c % nx, c // nx
+        for e in range(4):
+            if not ((e == 0 and j == 0) or (e == 1 and i == nx - 1) or (e == 2 and j == ny - 1) or (e == 3 and i == 0)):
+                continue
+            for t in range(2):
+                lx, ly = perm[(e + t) % 4] & 1, perm[(e + t) % 4] >> 1
+                infq.append([4 * ny + 2 * i + lx, 2 * ny + 2 * j + ly, 4 * ny + 2 * nx + 2 * i + lx, 2 * j + ly][e])
+    m = smrt_mod.QuadMeshSweep(xy, cells, p.omega, p.w, G, precision=0)
+    psi, _ = m.sweep(sigt, q[src], pp[:, :, src], 0.4, inf[:, :, infq])
+    m.close()
+    assert _rel(psi, ref[:, :, src]) < 1e-10
+
+
+def test_qmesh_rejects_bad_meshes(smrt_mod):
+    om, w = W.level_symmetric_2d(4)
+    xy, cells = W.quad_mesh_jittered(3, 3, jitter=0.1, seed=1)
+    bad = [cells[:, ::-1].copy(),                                  # clockwise
+           np.vstack([cells, cells[:1]]),                           # an edge shared by three cells
+           np.where(cells == cells.max(), len(xy), cells)]          # a vertex out of range
+    for c in bad:
+        with pytest.raises(smrt_mod.SmrtError) as e:
+            smrt_mod.QuadMeshSweep(xy, c, om, w, 1)
+        assert e.value.status == smrt_mod.SMRT_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("kind", ["rectilinear", "split"])
+def test_qmesh_throughput_at_benchmark_scale(smrt_mod, kind):
+    """S8, 16 groups, FP32: 256x256 cells given as quadrilaterals, and an
+    unstructured mesh of 64,896 cells (triangles cut into quadrilaterals);
+    prints the sweep launches' time and cell*angle*group units per second."""
+    xy, cells = (W.quad_mesh_jittered(256, 256, jitter=0.0) if kind == "rectilinear"
+                 else W.quad_mesh_split_triangles(104, seed=2))
+    om, w = W.level_symmetric_2d(8)
+    G = 16
+    m = smrt_mod.QuadMeshSweep(xy, cells, om, w, G, precision=1)
+    rng = np.random.default_rng(1)
+    nc = len(cells)
+    sigt = 10.0 ** rng.uniform(-1, 2, (nc, G))
+    q = rng.uniform(0, 1, (4 * nc, G))
+    m.sweep(sigt, q, None, 0.0)
+    _, ms = m.sweep(sigt, q, None, 0.0)
+    units = nc * len(w) * G
+    print(f"{kind}: {nc} cells, {m.n_levels} levels, {ms:.2f} ms, {units / (ms * 1e-3) / 1e9:.2f} G units/s",
+          flush=True)
+    m.close()
+    assert ms > 0
