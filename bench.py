@@ -17,7 +17,8 @@ committed counters; the measured device-to-device copy rate as a practical
 ceiling), the FP64 sweep for the FP32-vs-FP64 ratio and errors (one sweep
 and one full step from the same state), the sweep with the negative-flux
 fixup switched on (its cost), full time steps, the LO preconditioners
-(Jacobi, multigrid) on a diffusion-dominated step, the batched and
+(Jacobi, multigrid) on a diffusion-dominated step, the sweep on
+unstructured quadrilateral meshes, the batched and
 adjoint workloads, and the FP64 CPU oracle timed on a bounded sample of the
 same workload.
 """
@@ -177,6 +178,34 @@ def lo_multigrid():
     return out
 
 
+def qmesh_sweep():
+    """The sweep on unstructured quadrilateral meshes (dependency levels per
+    direction), S8, 16 groups, FP32, sigma_t log-uniform [0.1, 100], no
+    time-edge source: the 256x256 mesh given as quadrilaterals (the
+    rectilinear kernel's workload) and an unstructured mesh of 64,896 cells
+    (104x104 squares, jittered, each cut into two triangles and each triangle
+    into three quadrilaterals; seed 2).  Second sweep timed."""
+    import numpy as np
+    from paper_2504_21784_amd import smrt, workloads as W
+
+    out = {}
+    om, w = W.level_symmetric_2d(8)
+    G = 16
+    for name, (xy, cells) in (("rectilinear_256x256_as_quads", W.quad_mesh_jittered(256, 256, jitter=0.0)),
+                              ("unstructured_64896_cells", W.quad_mesh_split_triangles(104, seed=2))):
+        m = smrt.QuadMeshSweep(xy, cells, om, w, G, precision=smrt.SMRT_FP32)
+        rng = np.random.default_rng(1)
+        nc = len(cells)
+        sigt = 10.0 ** rng.uniform(-1, 2, (nc, G))
+        q = rng.uniform(0, 1, (4 * nc, G))
+        m.sweep(sigt, q, None, 0.0)
+        _, ms = m.sweep(sigt, q, None, 0.0)
+        units = nc * len(w) * G
+        out[name] = {"cells": nc, "levels": m.n_levels, "sweep_ms": ms, "units_per_s": units / (ms * 1e-3)}
+        m.close()
+    return out
+
+
 def adjoint():
     """Adjoint workload: 128x128, S8, 8 groups, 64 regions (seed 4), 10 steps of
     dt = 1e-3, FP64: time of the gradient of the time-integrated x+ outflow
@@ -231,6 +260,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient measurement")
     ap.add_argument("--no-step", action="store_true", help="skip the full time-step measurement")
     ap.add_argument("--no-multigrid", action="store_true", help="skip the LO preconditioner comparison")
+    ap.add_argument("--no-qmesh", action="store_true", help="skip the unstructured-mesh sweep")
     ap.add_argument("--lo-graphs", type=int, default=1, choices=(0, 1),
                     help="0: launch the LO conjugate-gradient kernels directly instead of replaying graphs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -390,6 +420,8 @@ def main():
         out["adjoint"] = adjoint()
     if not args.no_multigrid:
         out["lo_multigrid"] = lo_multigrid()
+    if not args.no_qmesh:
+        out["qmesh_sweep"] = qmesh_sweep()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

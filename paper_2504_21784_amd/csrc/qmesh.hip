@@ -45,9 +45,9 @@ struct QArgs {
     const double *om;             // [nang][3]
     const double *sig_t;          // [cell][G]
     const double *q;              // [node][G]
-    const double *psi_prev;       // [d][g][node] or null
+    const double *psi_prev;       // [d][g][node]
     const double *inflow;         // [d][g][NB]
-    double inv_c_dt;
+    const double *par;            // [0] inv_c_dt, [1] 1 if psi_prev holds I*, else 0 (set per sweep)
     void *psi;                    // [d][g][node], sweep precision
 };
 
@@ -78,10 +78,12 @@ __global__ void k_qsweep_level(QArgs A, int p0, int p1) {
     const int64_t slab = ((int64_t)d * A.G + g) * nn;
     const real st = (real)A.sig_t[(int64_t)c * A.G + g];
     real M[4][4], b[4];
+    const double icdt = A.par[0];
+    const bool has_prev = A.par[1] != 0.0;
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
         double ql = A.q[(int64_t)(4 * c + l) * A.G + g];
-        if (A.psi_prev) ql += A.inv_c_dt * A.psi_prev[slab + 4 * c + l];
+        if (has_prev) ql += icdt * A.psi_prev[slab + 4 * c + l];
         b[l] = (real)K.w[l] * (real)ql;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -164,11 +166,33 @@ struct smrt_qmesh {
     DevBuf<int2> sched;
     DevBuf<unsigned char> flags, psi;
     DevBuf<int> upw;
-    DevBuf<double> om, sig_t, q, psi_prev, inflow, out;
+    DevBuf<double> om, sig_t, q, psi_prev, inflow, out, par;
+    // the level launches of a sweep, captured once (their arguments are fixed per mesh)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool graph_failed = false;
     ~smrt_qmesh() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
+    void launch_levels(hipStream_t s);
 };
+
+void smrt_qmesh::launch_levels(hipStream_t s) {
+    QArgs A{};
+    A.nc = nc; A.G = G; A.nang = nang; A.NB = NB;
+    A.geo = geo.p; A.sched = sched.p; A.flags = flags.p; A.upw = upw.p; A.om = om.p;
+    A.sig_t = sig_t.p; A.q = q.p; A.psi_prev = psi_prev.p; A.inflow = inflow.p; A.par = par.p; A.psi = psi.p;
+    for (int L = 0; L < nlev; ++L) {
+        const int p0 = lev_off[L], p1 = lev_off[L + 1];
+        const int64_t nt = (int64_t)(p1 - p0) * G;
+        if (nt == 0) continue;
+        const dim3 grid((unsigned)((nt + 255) / 256));
+        if (fp32) hipLaunchKernelGGL(k_qsweep_level<float>, grid, dim3(256), 0, s, A, p0, p1);
+        else hipLaunchKernelGGL(k_qsweep_level<double>, grid, dim3(256), 0, s, A, p0, p1);
+    }
+}
 
 static thread_local std::string g_qmesh_error;
 
@@ -352,6 +376,7 @@ extern "C" smrt_status smrt_qmesh_create(int n_vertices, const double *xy, int n
         m->psi_prev.alloc(npsi);
         m->inflow.alloc(std::max<int64_t>((int64_t)nang * G * m->NB, 1));
         m->out.alloc(npsi);
+        m->par.alloc(2);
         m->psi.alloc(npsi * (m->fp32 ? 4 : 8));
     });
     if (st != SMRT_OK) return st;
@@ -386,23 +411,32 @@ extern "C" smrt_status smrt_qmesh_sweep(smrt_qmesh *m, const double *sig_t, cons
         if (inflow) SMRT_HIP(hipMemcpyAsync(m->inflow.p, inflow, sizeof(double) * m->nang * m->G * m->NB,
                                             hipMemcpyHostToDevice, s));
         else if (m->NB) SMRT_HIP(hipMemsetAsync(m->inflow.p, 0, sizeof(double) * m->nang * m->G * m->NB, s));
-        QArgs A{};
-        A.nc = m->nc; A.G = m->G; A.nang = m->nang; A.NB = m->NB;
-        A.geo = m->geo.p; A.sched = m->sched.p; A.flags = m->flags.p; A.upw = m->upw.p; A.om = m->om.p;
-        A.sig_t = m->sig_t.p; A.q = m->q.p; A.psi_prev = psi_prev ? m->psi_prev.p : nullptr; A.inflow = m->inflow.p;
-        A.inv_c_dt = inv_c_dt; A.psi = m->psi.p;
+        const double par[2] = {inv_c_dt, psi_prev ? 1.0 : 0.0};
+        SMRT_HIP(hipMemcpyAsync(m->par.p, par, sizeof(par), hipMemcpyHostToDevice, s));
+        if (!m->exec && !m->graph_failed) {
+            // capture the level launches once; a stream that cannot capture launches them directly
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                m->launch_levels(s);
+                hipGraph_t g = nullptr;
+                if (hipStreamEndCapture(s, &g) == hipSuccess && g &&
+                    hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0) == hipSuccess) {
+                    m->graph = g;
+                } else {
+                    if (g) (void)hipGraphDestroy(g);
+                    m->exec = nullptr;
+                    m->graph_failed = true;
+                }
+            } else {
+                (void)hipGetLastError();
+                m->graph_failed = true;
+            }
+        }
         hipEvent_t e0, e1;
         SMRT_HIP(hipEventCreate(&e0));
         if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); throw Error(SMRT_E_DEVICE, "hipEventCreate failed"); }
         SMRT_HIP(hipEventRecord(e0, s));
-        for (int L = 0; L < m->nlev; ++L) {
-            const int p0 = m->lev_off[L], p1 = m->lev_off[L + 1];
-            const int64_t nt = (int64_t)(p1 - p0) * m->G;
-            if (nt == 0) continue;
-            const dim3 grid((unsigned)((nt + 255) / 256));
-            if (m->fp32) hipLaunchKernelGGL(k_qsweep_level<float>, grid, dim3(256), 0, s, A, p0, p1);
-            else hipLaunchKernelGGL(k_qsweep_level<double>, grid, dim3(256), 0, s, A, p0, p1);
-        }
+        if (m->exec) SMRT_HIP(hipGraphLaunch(m->exec, s));
+        else m->launch_levels(s);
         SMRT_HIP(hipGetLastError());
         SMRT_HIP(hipEventRecord(e1, s));
         if (m->fp32) hipLaunchKernelGGL(k_qcopy_out<float>, dim3((unsigned)((npsi + 255) / 256)), dim3(256), 0, s, npsi,
