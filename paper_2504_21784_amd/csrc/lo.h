@@ -110,6 +110,7 @@ struct LoSolver {
     double galpha[2] = {0, 0};
     std::unique_ptr<MgHierarchy> mg;
     int precond = 0;               // preconditioner of the current solve
+    DevBuf<double> dhx, dhy;       // cell sizes (the stencil form of S)
     DevCsr dD, dDT, dP;
     DevBuf<double> wn, MFinv, DqF, jbase, diagE, rhs, Minv, r, z, p, Ap, Eold, Told, tmpF, part, sc, bpart, apart;
     DevBuf<int> flags;
@@ -134,6 +135,7 @@ struct LoSolver {
     double dot(hipStream_t s, const double *x, const double *y, const double *cdiff, int slot, bool accumulate);
     double fetch(hipStream_t s, int slot);
     void schur(hipStream_t s, const double *x, double *y);
+    struct LoGeom geom() const;
     int pcg(hipStream_t s, double *x, double rtol, int maxit);
     smrt_status solve(hipStream_t s, const LoInputs &in, double *E, double *F, double *T, smrt_step_stats *st,
                       std::string &err);

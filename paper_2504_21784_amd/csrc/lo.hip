@@ -378,6 +378,106 @@ __global__ void k_schur_rows(int nn, const int *drp, const int *dcol, const doub
     y[n] = s + diagE[n] * x[n];
 }
 
+// The same two products as k_dt_scaled and k_schur_rows(_dot), computed from
+// the mesh instead of the CSR arrays (the operators of assemble_lo_operators
+// written as stencils: every entry follows from hx, hy, the local node and
+// whether the face is interior), so an application reads only the vectors.
+//   (D^T x)(m, a) = -(w/h_a) s_a(m) (x_m - x_{partner_a(m)})
+//                   + [m on the cell's upper a-face, face interior] fw_a (x_m - x_{coincident node above})
+//   (D f)_n = -(w/h_x) s_x (f(n,x) + f(n^1,x)) - (w/h_y) s_y (f(n,y) + f(n^2,y))
+//             + sum over n's faces a: interior: fw_a jmp f(lower, a)
+//   (P x)_n = sum over n's faces a: interior 0.5 fw_a c alpha_a (x_n - x_nb), boundary fw_a c alpha_a x_n
+struct LoGeom {
+    int dim, nx, ny;
+    const double *hx, *hy;
+    double c, alpha[2];
+};
+
+__device__ inline void lo_node(const LoGeom &g, int n, int &cell, int &l, int &i, int &j, double &hx, double &hy,
+                               double &w) {
+    const int npc = g.dim == 2 ? 4 : 2;
+    cell = n / npc;
+    l = n - npc * cell;
+    i = cell % g.nx;
+    j = cell / g.nx;
+    hx = g.hx[i];
+    hy = g.dim == 2 ? g.hy[j] : 1.0;
+    w = hx * hy / npc;
+}
+
+__global__ void k_dt_stencil(int nn, LoGeom g, double c3, const double *x, const double *MFinv, double *tmpF) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nn) return;
+    int cell, l, i, j;
+    double hx, hy, w;
+    lo_node(g, m, cell, l, i, j, hx, hy, w);
+    const int npc = g.dim == 2 ? 4 : 2;
+    const double xm = x[m], sc = c3 * MFinv[m];
+    {
+        const int lx = l & 1;
+        double v = -(w / hx) * (lx ? 1.0 : -1.0) * (xm - x[m ^ 1]);
+        if (lx && i + 1 < g.nx) v += (g.dim == 2 ? 0.5 * hy : 1.0) * (xm - x[npc * (cell + 1) + (l ^ 1)]);
+        tmpF[(int64_t)m * g.dim] = sc * v;
+    }
+    if (g.dim == 2) {
+        const int ly = l >> 1;
+        double v = -(w / hy) * (ly ? 1.0 : -1.0) * (xm - x[m ^ 2]);
+        if (ly && j + 1 < g.ny) v += 0.5 * hx * (xm - x[npc * (cell + g.nx) + (l ^ 2)]);
+        tmpF[(int64_t)m * 2 + 1] = sc * v;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_schur_stencil_dot(int nn, LoGeom g, const double *tmpF, const double *x,
+                                                           const double *diagE, double *y, double *part) {
+    __shared__ double sh[256];
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (n < nn) {
+        int cell, l, i, j;
+        double hx, hy, w;
+        lo_node(g, n, cell, l, i, j, hx, hy, w);
+        const int npc = g.dim == 2 ? 4 : 2, dim = g.dim;
+        const double xn = x[n];
+        const int lx = l & 1;
+        double s = -(w / hx) * (lx ? 1.0 : -1.0) * (tmpF[(int64_t)n * dim] + tmpF[(int64_t)(n ^ 1) * dim]);
+        double pp = 0.0;
+        {
+            const double fw = dim == 2 ? 0.5 * hy : 1.0, cal = g.c * g.alpha[0];
+            const int ii = i + (lx ? 1 : -1);
+            if (ii >= 0 && ii < g.nx) {
+                const int nbn = npc * (cell + (lx ? 1 : -1)) + (l ^ 1);
+                s += fw * (lx ? tmpF[(int64_t)n * dim] : -tmpF[(int64_t)nbn * dim]);
+                pp += 0.5 * fw * cal * (xn - x[nbn]);
+            } else {
+                pp += fw * cal * xn;
+            }
+        }
+        if (dim == 2) {
+            const int ly = l >> 1;
+            s += -(w / hy) * (ly ? 1.0 : -1.0) * (tmpF[(int64_t)n * 2 + 1] + tmpF[(int64_t)(n ^ 2) * 2 + 1]);
+            const double fw = 0.5 * hx, cal = g.c * g.alpha[1];
+            const int jj = j + (ly ? 1 : -1);
+            if (jj >= 0 && jj < g.ny) {
+                const int nbn = npc * (cell + (ly ? g.nx : -g.nx)) + (l ^ 2);
+                s += fw * (ly ? tmpF[(int64_t)n * 2 + 1] : -tmpF[(int64_t)nbn * 2 + 1]);
+                pp += 0.5 * fw * cal * (xn - x[nbn]);
+            } else {
+                pp += fw * cal * xn;
+            }
+        }
+        const double yn = s + pp + diagE[n] * xn;
+        y[n] = yn;
+        v = xn * yn;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && part) part[blockIdx.x] = sh[0];
+}
+
 // S x fused with the block partials of x . (S x) (one partial per 256-row block)
 __global__ void __launch_bounds__(256) k_schur_rows_dot(int nn, const int *drp, const int *dcol, const double *dval,
                                                         const int *prp, const int *pcol, const double *pval,
@@ -631,6 +731,16 @@ void LoSolver::init(int dim_, int nx, int ny, const std::vector<double> &xe, con
     std::vector<double> wv;
     assemble_lo_operators(dim, nx, ny, xe, ye, alpha, c, D, DT, P, wv);
     nn = D.nrows;
+    {
+        std::vector<double> hx(nx), hy(dim == 2 ? ny : 1, 1.0);
+        for (int i = 0; i < nx; ++i) hx[i] = xe[i + 1] - xe[i];
+        if (dim == 2)
+            for (int j = 0; j < ny; ++j) hy[j] = ye[j + 1] - ye[j];
+        dhx.alloc(nx);
+        dhy.alloc((int64_t)hy.size());
+        SMRT_HIP(hipMemcpy(dhx.p, hx.data(), sizeof(double) * nx, hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(dhy.p, hy.data(), sizeof(double) * hy.size(), hipMemcpyHostToDevice));
+    }
     dD.upload(D);
     dDT.upload(DT);
     dP.upload(P);
@@ -658,11 +768,19 @@ double LoSolver::fetch(hipStream_t s, int slot) {
     return v;
 }
 
+LoGeom LoSolver::geom() const {
+    LoGeom g{};
+    g.dim = dim; g.nx = gnx; g.ny = dim == 2 ? gny : 1;
+    g.hx = dhx.p; g.hy = dhy.p;
+    g.c = c; g.alpha[0] = galpha[0]; g.alpha[1] = galpha[1];
+    return g;
+}
+
 void LoSolver::schur(hipStream_t s, const double *x, double *y) {
-    hipLaunchKernelGGL(k_dt_scaled, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn * dim, dim, c / 3.0, dDT.rp, dDT.col,
-                       dDT.val, x, MFinv.p, tmpF.p);
-    hipLaunchKernelGGL(k_schur_rows, dim3(nb(nn)), dim3(256), 0, s, nn, dD.rp, dD.col, dD.val, dP.rp, dP.col, dP.val,
-                       tmpF.p, x, diagE.p, y);
+    const LoGeom g = geom();
+    hipLaunchKernelGGL(k_dt_stencil, dim3(nb(nn)), dim3(256), 0, s, nn, g, c / 3.0, x, MFinv.p, tmpF.p);
+    hipLaunchKernelGGL(k_schur_stencil_dot, dim3(nb(nn)), dim3(256), 0, s, nn, g, tmpF.p, x, diagE.p, y,
+                       (double *)nullptr);
 }
 
 int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
@@ -709,7 +827,8 @@ int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
     }
 }
 
-// One CG iteration = 5 launches: D^T p; S p with the p.Sp block partials; the
+// One CG iteration = 5 launches: D^T p; S p with the p.Sp block partials (both
+// in stencil form); the
 // x/r/z update (each block sums the p.Sp partials itself) with the r.z and r.r
 // partials; the new direction (each block sums r.z); the scalars and the stop test.
 void LoSolver::cg_block(hipStream_t s, double *x, int iters) {
@@ -718,11 +837,11 @@ void LoSolver::cg_block(hipStream_t s, double *x, int iters) {
         for (int k = 0; k < iters; ++k) mg_cg_iteration(s, x);
         return;
     }
+    const LoGeom g = geom();
     for (int k = 0; k < iters; ++k) {
-        hipLaunchKernelGGL(k_dt_scaled, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn * dim, dim, c / 3.0, dDT.rp,
-                           dDT.col, dDT.val, p.p, MFinv.p, tmpF.p);
-        hipLaunchKernelGGL(k_schur_rows_dot, dim3(nbk), dim3(256), 0, s, nn, dD.rp, dD.col, dD.val, dP.rp, dP.col,
-                           dP.val, tmpF.p, p.p, diagE.p, Ap.p, apart.p);
+        hipLaunchKernelGGL(k_dt_stencil, dim3(nbk), dim3(256), 0, s, nn, g, c / 3.0, p.p, MFinv.p, tmpF.p);
+        hipLaunchKernelGGL(k_schur_stencil_dot, dim3(nbk), dim3(256), 0, s, nn, g, tmpF.p, p.p, diagE.p, Ap.p,
+                           apart.p);
         hipLaunchKernelGGL(k_cg_xr_dot, dim3(nbk), dim3(256), 0, s, nn, nbk, sc.p, apart.p, p.p, Ap.p, x, r.p, Minv.p,
                            z.p, bpart.p);
         hipLaunchKernelGGL(k_cg_p, dim3(nbk), dim3(256), 0, s, nn, nbk, sc.p, bpart.p, z.p, p.p);
