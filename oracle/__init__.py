@@ -337,3 +337,26 @@ class QuadMesh:
                               _p(inf), _p(out))
         assert r == 0, f"orc_qsweep returned {r}"
         return out
+
+    def moments(self, sig, psi):
+        """Gray angular moments per node of an intensity psi[d][g][node]: the
+        moment sums of Sec. 2 over directions and groups, split by the
+        quadrant of the direction as on the rectilinear mesh (for quadrant q,
+        row 6q + m sums w_d f_m I with f = 1, mu, eta, mu^2, mu eta, eta^2;
+        q = 0 for mu, eta > 0, 1 for mu < 0 < eta, 2 for both < 0, 3 for the
+        rest), and rows 24-26 sum sig_g w_d (1, mu, eta) I with sig[cell][g].
+        Written out one direction at a time."""
+        nn = 4 * len(self.cells)
+        psi = _f64(psi).reshape(len(self.w), self.G, nn)
+        sg = np.repeat(_f64(sig).reshape(-1, self.G), 4, axis=0).T      # [g][node]
+        mom = np.zeros((27, nn))
+        for d in range(len(self.w)):
+            mu, eta, w = self.om[d, 0], self.om[d, 1], self.w[d]
+            q = 0 if (mu > 0 and eta > 0) else 1 if (mu < 0 and eta > 0) else 2 if (mu < 0 and eta < 0) else 3
+            tot = psi[d].sum(axis=0)
+            for m, f in enumerate((1.0, mu, eta, mu * mu, mu * eta, eta * eta)):
+                mom[6 * q + m] += w * f * tot
+            absorbed = (sg * psi[d]).sum(axis=0)
+            for m, f in enumerate((1.0, mu, eta)):
+                mom[24 + m] += w * f * absorbed
+        return mom

@@ -248,6 +248,35 @@ def multigroup_2d(n: int = 256, G: int = 16, sn: int = 8, region: int = 16, seed
         n_steps=n_steps, seed=seed)
 
 
+def chebyshev_block_edges(n_blocks: int, per_block: int, block: float = 1.0) -> np.ndarray:
+    """Cell edges along one axis of ``n_blocks`` blocks of width ``block``,
+    each cut into ``per_block`` cells at the Chebyshev points of the second
+    kind (x_k = (1 - cos(pi k / n)) / 2 inside a block), so that cells cluster
+    at every block boundary: the refined meshes of the multigroup test of
+    Sec. 6 (30 cells per 1 cm block there)."""
+    k = np.arange(per_block + 1)
+    local = 0.5 * (1.0 - np.cos(np.pi * k / per_block))
+    local[0], local[-1] = 0.0, 1.0
+    edges = [0.0]
+    for b in range(n_blocks):
+        edges.extend(((b + local[1:]) * block).tolist())
+    return np.array(edges)
+
+
+def multigroup_2d_clustered(blocks: int = 2, per_block: int = 30, G: int = 16, sn: int = 8, seed: int = 3,
+                            n_steps: int = 10) -> Problem:
+    """The multigroup problem on a Chebyshev-clustered rectilinear mesh:
+    ``blocks`` x ``blocks`` unit blocks of ``per_block``^2 cells each
+    (``chebyshev_block_edges``), one opacity region per block, otherwise as
+    ``multigroup_2d`` (left side incident at T = 1, others vacuum)."""
+    n = blocks * per_block
+    p = multigroup_2d(n=n, G=G, sn=sn, region=per_block, seed=seed, n_steps=n_steps, domain=float(blocks))
+    p.x_edges = chebyshev_block_edges(blocks, per_block)
+    p.y_edges = chebyshev_block_edges(blocks, per_block)
+    p.name = f"multigroup_2d_clustered_{blocks}x{per_block}_g{G}_s{sn}"
+    return p
+
+
 def adjoint_2d(n: int = 128, G: int = 8, seed: int = 4, n_steps: int = 10) -> Problem:
     """Adjoint workload: 128^2, S8, 8 groups, 8x8 regions of 16x16 cells with
     per-region sigma0 (log-uniform [1,100]) and c_v (log-uniform [0.5, 2])."""

@@ -173,3 +173,50 @@ def test_numbering_does_not_matter(oracle_mod):
     m2, _, _ = _quad(oracle_mod, xy, cells2, 4, 1)
     got = m2.sweep(sigt[perm], q[src], None, 0.0, inflow_for(cells2))
     assert np.abs(got - base[:, :, src]).max() <= 1e-13 * np.abs(base).max()
+
+
+def test_moments_on_rectilinear_quads_equal_rectilinear_oracle(oracle_mod):
+    """The unstructured mesh's gray moments (a plain numpy sum) equal the
+    rectilinear oracle's C moments of the same intensity, node for node."""
+    nx, ny, G = 6, 5, 3
+    p = W.gray_2d(n=4, sn=8)
+    p.nx, p.ny, p.G = nx, ny, G
+    p.x_edges, p.y_edges = np.linspace(0, 1, nx + 1), np.linspace(0, 0.7, ny + 1)
+    p.nu_edges = np.logspace(-2, 1, G + 1)
+    p.region_of_cell = np.zeros(nx * ny, np.int32)
+    p.sigma0 = np.ones((1, G))
+    sigt, q, pp, inf = W.random_sweep_inputs(p, seed=12)
+    o = oracle_mod.Oracle(p)
+    psi = o.sweep(sigt, q, pp, 0.6, inf)
+    sig = 0.4 * sigt
+    want = o.moments(sig, psi)
+    xy, cells = W.quad_mesh_jittered(nx, ny, jitter=0.0, x_edges=p.x_edges, y_edges=p.y_edges)
+    m, _, _ = _quad(oracle_mod, xy, cells, 8, G)
+    perm = [0, 1, 3, 2]
+    psiq = psi.reshape(p.n_angles, G, nx * ny, 4)[:, :, :, perm].reshape(p.n_angles, G, -1)
+    got = m.moments(sig, psiq)
+    want_q = want.reshape(27, nx * ny, 4)[:, :, perm].reshape(27, -1)
+    assert np.abs(got - want_q).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_moments_of_uniform_intensity(oracle_mod):
+    """An isotropic uniform intensity I on a skewed mesh: each quadrant holds
+    a quarter of the 4 pi weight, the level-symmetric set integrates the
+    second moments exactly (mu^2 and eta^2 sum to 4 pi / 3, mu eta to 0),
+    the currents vanish, and the opacity-weighted rows are the group
+    opacities times 4 pi I."""
+    xy, cells = W.quad_mesh_jittered(5, 4, jitter=0.25, seed=3)
+    G, I = 3, 1.5
+    m, om, w = _quad(oracle_mod, xy, cells, 8, G)
+    nc = len(cells)
+    sig = np.tile([0.5, 2.0, 7.0], (nc, 1))
+    mom = m.moments(sig, np.full((len(w), G, 4 * nc), I))
+    total = lambda k: sum(mom[6 * qd + k] for qd in range(4))
+    for qd in range(4):
+        assert np.allclose(mom[6 * qd], np.pi * G * I, rtol=1e-13, atol=0)
+    assert np.allclose(total(3), 4 * np.pi / 3 * G * I, rtol=1e-13, atol=0)
+    assert np.allclose(total(5), 4 * np.pi / 3 * G * I, rtol=1e-13, atol=0)
+    for k in (1, 2, 4):
+        assert np.abs(total(k)).max() <= 1e-13
+    assert np.allclose(mom[24], 9.5 * 4 * np.pi * I, rtol=1e-13, atol=0)
+    assert np.abs(mom[25]).max() <= 1e-12 and np.abs(mom[26]).max() <= 1e-12

@@ -99,3 +99,36 @@ def test_marshak_units_and_first_steps(oracle_mod):
         assert front >= last
         last = front
     assert last > 4
+
+
+def _refined_gold():
+    vals = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "refined_block_mesh.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        vals[k] = float(v)
+    return vals
+
+
+def test_chebyshev_block_mesh_matches_printed_lengths():
+    """The refined mesh of the multigroup test (30 cells per 1 cm block at the
+    Chebyshev points of the second kind) has the smallest and largest mesh
+    lengths the paper prints, to their 4 digits, and 9x the elements of the
+    10-per-block uniform mesh; cells are mirror-symmetric inside a block and
+    block boundaries are mesh lines."""
+    g = _refined_gold()
+    n = int(g["per_block"])
+    e = W.chebyshev_block_edges(3, n)
+    h = np.diff(e)
+    assert len(h) == 3 * n and np.all(h > 0)
+    assert abs(h.min() - g["h_min_cm"]) < 0.5e-6
+    assert abs(h.max() - g["h_max_cm"]) < 0.5e-5
+    assert (n / g["coarse_per_block"]) ** 2 * g["coarse_elements"] == g["fine_elements"]
+    for b in range(3):
+        hb = h[b * n:(b + 1) * n]
+        assert np.allclose(hb, hb[::-1], rtol=0, atol=1e-15)
+        assert e[b * n] == b and abs(hb.sum() - 1.0) < 1e-14
+    p = W.multigroup_2d_clustered(blocks=2, per_block=6, G=3, sn=4)
+    assert p.nx == p.ny == 12 and p.x_edges[-1] == 2.0 and len(np.unique(p.region_of_cell)) == 4
+    assert np.array_equal(p.region_of_cell.reshape(12, 12)[:6, :6], np.zeros((6, 6), p.region_of_cell.dtype))
