@@ -184,7 +184,8 @@ def qmesh_sweep():
     time-edge source: the 256x256 mesh given as quadrilaterals (the
     rectilinear kernel's workload) and an unstructured mesh of 64,896 cells
     (104x104 squares, jittered, each cut into two triangles and each triangle
-    into three quadrilaterals; seed 2).  Second sweep timed."""
+    into three quadrilaterals; seed 2).  Second sweep timed, then the gray
+    moments of its intensity (a separate kernel on this path)."""
     import numpy as np
     from paper_2504_21784_amd import smrt, workloads as W
 
@@ -200,8 +201,10 @@ def qmesh_sweep():
         q = rng.uniform(0, 1, (4 * nc, G))
         m.sweep(sigt, q, None, 0.0)
         _, ms = m.sweep(sigt, q, None, 0.0)
+        _, ms_mom = m.moments(0.5 * sigt)
         units = nc * len(w) * G
-        out[name] = {"cells": nc, "levels": m.n_levels, "sweep_ms": ms, "units_per_s": units / (ms * 1e-3)}
+        out[name] = {"cells": nc, "levels": m.n_levels, "sweep_ms": ms, "units_per_s": units / (ms * 1e-3),
+                     "moments_ms": ms_mom}
         m.close()
     return out
 

@@ -422,6 +422,18 @@ smrt_status smrt_qmesh_info(const smrt_qmesh *mesh, int *n_boundary_nodes, int *
  * sweep launches.  Errors: SMRT_E_INVALID_ARG, SMRT_E_DEVICE. */
 smrt_status smrt_qmesh_sweep(smrt_qmesh *mesh, const double *sig_t, const double *q_iso, const double *psi_prev,
                              double inv_c_dt, const double *inflow, double *psi_out, double *ms_kernel);
+/* Gray angular moments (the moment sums of Sec. 2 over directions and
+ * groups) of the intensity left on the device by the last successful
+ * smrt_qmesh_sweep on this mesh, in the rectilinear path's 27-row layout:
+ * mom_out[27][4 * n_cells] FP64 host, rows 6q..6q+5 = sum over the
+ * directions of quadrant q (0: mu > 0 and eta > 0; 1: mu < 0 < eta; 2: both
+ * < 0; 3: the rest) and all groups of w f I with f = 1, mu, eta, mu^2,
+ * mu eta, eta^2; rows 24..26 = sum of sig w (1, mu, eta) I.  sig[cell][G]
+ * (finite, >= 0) host FP64 is the opacity weighting the last three rows.
+ * Summed in FP64 on the GPU; ms_kernel (may be NULL) receives the kernel's
+ * time.  Errors: SMRT_E_INVALID_ARG (NULL, bad sig, or no sweep yet),
+ * SMRT_E_OUT_OF_MEMORY, SMRT_E_DEVICE. */
+smrt_status smrt_qmesh_moments(smrt_qmesh *mesh, const double *sig, double *mom_out, double *ms_kernel);
 
 #ifdef __cplusplus
 }

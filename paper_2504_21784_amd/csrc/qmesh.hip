@@ -151,6 +151,56 @@ __global__ void k_qcopy_out(int64_t n, const real *in, double *out) {
     if (i < n) out[i] = (double)in[i];
 }
 
+// Gray angular moments of a swept intensity per node (Sec. 2's moment sums
+// with the quadrature weights, over all groups), split by the quadrant of the
+// direction as on the rectilinear path: rows 6q..6q+5 hold the sums of
+// w f I with f = 1, mu, eta, mu^2, mu eta, eta^2 over the directions of
+// quadrant q (0: mu, eta > 0; 1: mu < 0 < eta; 2: both < 0; 3: the rest),
+// rows 24..26 the sums of sigma w (1, mu, eta) I with sigma the cell's
+// group opacity.  One thread per node; the directions and groups are summed
+// in index order in FP64, every intensity value read once (coalesced along
+// the nodes).  A dependency-level sweep cannot fuse these sums: the
+// directions of one node are solved in different launches.
+template <typename real>
+__global__ void k_qmoments(int nang, int G, int nn, const double *om, const double *wq, const double *sig,
+                           const real *psi, double *mom) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double acc[27];
+#pragma unroll
+    for (int m = 0; m < 27; ++m) acc[m] = 0.0;
+    const double *sg = sig + (int64_t)(n >> 2) * G;
+    for (int d = 0; d < nang; ++d) {
+        const double mu = om[3 * d], eta = om[3 * d + 1], w = wq[d];
+        const int q = (mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3;
+        const double f[6] = {1.0, mu, eta, mu * mu, mu * eta, eta * eta};
+        double s0[6] = {0, 0, 0, 0, 0, 0}, s1[3] = {0, 0, 0};
+        const real *I = psi + (int64_t)d * G * nn + n;
+        for (int g = 0; g < G; ++g) {
+            const double v = (double)I[(int64_t)g * nn];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) s0[m] += w * f[m] * v;
+            const double sv = sg[g] * w * v;
+            s1[0] += sv;
+            s1[1] += sv * mu;
+            s1[2] += sv * eta;
+        }
+        // the quadrant index is uniform over the wave (one direction at a time)
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            acc[m] += q == 0 ? s0[m] : 0.0;
+            acc[6 + m] += q == 1 ? s0[m] : 0.0;
+            acc[12 + m] += q == 2 ? s0[m] : 0.0;
+            acc[18 + m] += q == 3 ? s0[m] : 0.0;
+        }
+        acc[24] += s1[0];
+        acc[25] += s1[1];
+        acc[26] += s1[2];
+    }
+#pragma unroll
+    for (int m = 0; m < 27; ++m) mom[(int64_t)m * nn + n] = acc[m];
+}
+
 }  // namespace smrt
 
 using namespace smrt;
@@ -166,7 +216,8 @@ struct smrt_qmesh {
     DevBuf<int2> sched;
     DevBuf<unsigned char> flags, psi;
     DevBuf<int> upw;
-    DevBuf<double> om, sig_t, q, psi_prev, inflow, out, par;
+    DevBuf<double> om, sig_t, q, psi_prev, inflow, out, par, wq, sig_m, mom;
+    bool swept = false;       // psi holds the intensity of a finished sweep
     // the level launches of a sweep, captured once (their arguments are fixed per mesh)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -371,6 +422,8 @@ extern "C" smrt_status smrt_qmesh_create(int n_vertices, const double *xy, int n
         SMRT_HIP(hipMemcpy(m->flags.p, flags.data(), flags.size(), hipMemcpyHostToDevice));
         SMRT_HIP(hipMemcpy(m->upw.p, upw.data(), sizeof(int) * upw.size(), hipMemcpyHostToDevice));
         SMRT_HIP(hipMemcpy(m->om.p, quad->omega, sizeof(double) * 3 * nang, hipMemcpyHostToDevice));
+        m->wq.alloc(nang);
+        SMRT_HIP(hipMemcpy(m->wq.p, quad->w, sizeof(double) * nang, hipMemcpyHostToDevice));
         m->sig_t.alloc((int64_t)nc * G);
         m->q.alloc(nn * G);
         m->psi_prev.alloc(npsi);
@@ -405,6 +458,7 @@ extern "C" smrt_status smrt_qmesh_sweep(smrt_qmesh *m, const double *sig_t, cons
         for (int64_t k = 0; k < (int64_t)m->nc * m->G; ++k)
             qrequire(std::isfinite(sig_t[k]) && sig_t[k] > 0.0, "sig_t must be finite and > 0");
         hipStream_t s = m->stream;
+        m->swept = false;
         SMRT_HIP(hipMemcpyAsync(m->sig_t.p, sig_t, sizeof(double) * m->nc * m->G, hipMemcpyHostToDevice, s));
         SMRT_HIP(hipMemcpyAsync(m->q.p, q_iso, sizeof(double) * nn * m->G, hipMemcpyHostToDevice, s));
         if (psi_prev) SMRT_HIP(hipMemcpyAsync(m->psi_prev.p, psi_prev, sizeof(double) * npsi, hipMemcpyHostToDevice, s));
@@ -444,6 +498,42 @@ extern "C" smrt_status smrt_qmesh_sweep(smrt_qmesh *m, const double *sig_t, cons
         else hipLaunchKernelGGL(k_qcopy_out<double>, dim3((unsigned)((npsi + 255) / 256)), dim3(256), 0, s, npsi,
                                 (const double *)m->psi.p, m->out.p);
         SMRT_HIP(hipMemcpyAsync(psi_out, m->out.p, sizeof(double) * npsi, hipMemcpyDeviceToHost, s));
+        SMRT_HIP(hipStreamSynchronize(s));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (ms_kernel) *ms_kernel = ms;
+        m->swept = true;
+    });
+}
+
+extern "C" smrt_status smrt_qmesh_moments(smrt_qmesh *m, const double *sig, double *mom_out, double *ms_kernel) {
+    if (!m) { g_qmesh_error = "mesh is NULL"; return SMRT_E_INVALID_ARG; }
+    return qguard(m, [&] {
+        qrequire(sig && mom_out, "NULL input or output");
+        qrequire(m->swept, "no sweep has run on this mesh");
+        for (int64_t k = 0; k < (int64_t)m->nc * m->G; ++k)
+            qrequire(std::isfinite(sig[k]) && sig[k] >= 0.0, "sig must be finite and >= 0");
+        const int nn = 4 * m->nc;
+        if (!m->mom.p) {
+            m->sig_m.alloc((int64_t)m->nc * m->G);
+            m->mom.alloc(27 * (int64_t)nn);
+        }
+        hipStream_t s = m->stream;
+        SMRT_HIP(hipMemcpyAsync(m->sig_m.p, sig, sizeof(double) * m->nc * m->G, hipMemcpyHostToDevice, s));
+        hipEvent_t e0, e1;
+        SMRT_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); throw Error(SMRT_E_DEVICE, "hipEventCreate failed"); }
+        SMRT_HIP(hipEventRecord(e0, s));
+        const dim3 grid((unsigned)((nn + 255) / 256));
+        if (m->fp32) hipLaunchKernelGGL(k_qmoments<float>, grid, dim3(256), 0, s, m->nang, m->G, nn, m->om.p, m->wq.p,
+                                        m->sig_m.p, (const float *)m->psi.p, m->mom.p);
+        else hipLaunchKernelGGL(k_qmoments<double>, grid, dim3(256), 0, s, m->nang, m->G, nn, m->om.p, m->wq.p,
+                                m->sig_m.p, (const double *)m->psi.p, m->mom.p);
+        SMRT_HIP(hipGetLastError());
+        SMRT_HIP(hipEventRecord(e1, s));
+        SMRT_HIP(hipMemcpyAsync(mom_out, m->mom.p, sizeof(double) * 27 * nn, hipMemcpyDeviceToHost, s));
         SMRT_HIP(hipStreamSynchronize(s));
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);

@@ -119,6 +119,7 @@ _SIGS = {
     "smrt_qmesh_last_error": ([C.c_void_p], C.c_char_p),
     "smrt_qmesh_info": ([C.c_void_p, _ip, _ip], C.c_int),
     "smrt_qmesh_sweep": ([C.c_void_p, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp], C.c_int),
+    "smrt_qmesh_moments": ([C.c_void_p, _dp, _dp, _dp], C.c_int),
 }
 
 
@@ -448,6 +449,18 @@ class QuadMeshSweep:
         inf = _f64(inflow) if inflow is not None else None
         st = self.L.smrt_qmesh_sweep(self.h, _p(_f64(sig_t)), _p(_f64(q_iso)), _p(pp), float(inv_c_dt), _p(inf),
                                      _p(out), C.byref(ms))
+        if st != 0:
+            raise SmrtError(st, self.L.smrt_qmesh_last_error(self.h).decode())
+        return out, ms.value
+
+    def moments(self, sig):
+        """Gray moments of the last sweep's intensity, [27][node] in the
+        rectilinear path's layout (quadrant-split 1, mu, eta, mu^2, mu eta,
+        eta^2 sums, then the sig-weighted 1, mu, eta sums), with sig[cell][g];
+        returns (moments, milliseconds of the kernel)."""
+        out = np.zeros((27, 4 * len(self._cells)))
+        ms = C.c_double(0.0)
+        st = self.L.smrt_qmesh_moments(self.h, _p(_f64(sig)), _p(out), C.byref(ms))
         if st != 0:
             raise SmrtError(st, self.L.smrt_qmesh_last_error(self.h).decode())
         return out, ms.value

@@ -3,8 +3,8 @@ through the C ABI: jittered logically structured meshes (ragged sizes, one
 cell) and unstructured ones (triangles cut into three quadrilaterals), FP64
 to 1e-10 and FP32 to 1e-5 of the field's maximum; a rectilinear mesh given
 as quadrilaterals against the rectilinear sweep kernel (two GPU paths that
-share nothing but the problem); the error cases; and the throughput at the
-benchmark's scale (printed).
+share nothing but the problem); the gray moments of the swept intensity;
+the error cases; and the throughput at the benchmark's scale (printed).
 """
 import numpy as np
 import pytest
@@ -37,6 +37,33 @@ def test_qmesh_sweep_matches_oracle(smrt_mod, oracle_mod, kind, nx, ny, sn, G, p
     psi, ms = m.sweep(sigt, q, pp, 0.7, inf)
     m.close()
     assert _rel(psi, ref) < tol
+
+
+@pytest.mark.parametrize("kind,nx,ny,sn,G", [("jittered", 13, 11, 8, 3), ("split", 9, 9, 4, 2), ("jittered", 1, 1, 4, 1)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-5)])
+def test_qmesh_moments_match_oracle(smrt_mod, oracle_mod, kind, nx, ny, sn, G, prec, tol):
+    """The GPU's gray moments of its own sweep against the oracle's moments of
+    the oracle's sweep; each quadrant's rows are measured against that
+    quadrant's scalar-flux row and the opacity-weighted rows against theirs
+    (|f| <= 1 bounds every row by those)."""
+    xy, cells = (W.quad_mesh_jittered(nx, ny, jitter=0.28, seed=nx + ny) if kind == "jittered"
+                 else W.quad_mesh_split_triangles(nx, seed=nx))
+    print(f"moments {kind} {nx}x{ny}: {len(cells)} cells, S{sn}, G={G}, precision {prec}", flush=True)
+    om, w = W.level_symmetric_2d(sn)
+    ref_mesh = oracle_mod.QuadMesh(xy, cells, om, w, G)
+    sigt, q, pp, inf = W.quad_sweep_inputs(len(cells), len(w), G, ref_mesh.nb, seed=len(cells) + 1)
+    sig = 0.7 * sigt
+    ref = ref_mesh.moments(sig, ref_mesh.sweep(sigt, q, pp, 0.7, inf))
+    m = smrt_mod.QuadMeshSweep(xy, cells, om, w, G, precision=prec)
+    with pytest.raises(smrt_mod.SmrtError) as e:
+        m.moments(sig)                                   # no sweep yet
+    assert e.value.status == smrt_mod.SMRT_E_INVALID_ARG
+    m.sweep(sigt, q, pp, 0.7, inf)
+    got, ms = m.moments(sig)
+    m.close()
+    for r in range(27):
+        scale = np.abs(ref[24 if r >= 24 else 6 * (r // 6)]).max()
+        assert np.abs(got[r] - ref[r]).max() <= tol * scale, r
 
 
 def test_qmesh_rectilinear_matches_rectilinear_kernel(smrt_mod):
@@ -91,7 +118,8 @@ def test_qmesh_rejects_bad_meshes(smrt_mod):
 def test_qmesh_throughput_at_benchmark_scale(smrt_mod, kind):
     """S8, 16 groups, FP32: 256x256 cells given as quadrilaterals, and an
     unstructured mesh of 64,896 cells (triangles cut into quadrilaterals);
-    prints the sweep launches' time and cell*angle*group units per second."""
+    prints the sweep launches' time and cell*angle*group units per second, and the
+    moment kernel's time."""
     xy, cells = (W.quad_mesh_jittered(256, 256, jitter=0.0) if kind == "rectilinear"
                  else W.quad_mesh_split_triangles(104, seed=2))
     om, w = W.level_symmetric_2d(8)
@@ -103,8 +131,9 @@ def test_qmesh_throughput_at_benchmark_scale(smrt_mod, kind):
     q = rng.uniform(0, 1, (4 * nc, G))
     m.sweep(sigt, q, None, 0.0)
     _, ms = m.sweep(sigt, q, None, 0.0)
+    _, ms_mom = m.moments(0.5 * sigt)
     units = nc * len(w) * G
-    print(f"{kind}: {nc} cells, {m.n_levels} levels, {ms:.2f} ms, {units / (ms * 1e-3) / 1e9:.2f} G units/s",
-          flush=True)
+    print(f"{kind}: {nc} cells, {m.n_levels} levels, {ms:.2f} ms, {units / (ms * 1e-3) / 1e9:.2f} G units/s; "
+          f"moments {ms_mom:.3f} ms", flush=True)
     m.close()
     assert ms > 0
