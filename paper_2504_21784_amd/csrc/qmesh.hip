@@ -157,48 +157,58 @@ __global__ void k_qcopy_out(int64_t n, const real *in, double *out) {
 // w f I with f = 1, mu, eta, mu^2, mu eta, eta^2 over the directions of
 // quadrant q (0: mu, eta > 0; 1: mu < 0 < eta; 2: both < 0; 3: the rest),
 // rows 24..26 the sums of sigma w (1, mu, eta) I with sigma the cell's
-// group opacity.  One thread per node; the directions and groups are summed
-// in index order in FP64, every intensity value read once (coalesced along
-// the nodes).  A dependency-level sweep cannot fuse these sums: the
+// group opacity.  A dependency-level sweep cannot fuse these sums: the
 // directions of one node are solved in different launches.
+//
+// A workgroup is 4 waves over the same 64 nodes, wave q taking the
+// directions of quadrant q (so every wave streams a quarter of the
+// intensity, 4x the waves of one thread per node).  Each wave writes its
+// quadrant's six rows; the opacity-weighted sums of the four quadrants meet
+// in LDS and are added in quadrant order.  Directions, then groups, are
+// summed in index order in FP64, every intensity value read once (coalesced
+// along the nodes).
 template <typename real>
-__global__ void k_qmoments(int nang, int G, int nn, const double *om, const double *wq, const double *sig,
-                           const real *psi, double *mom) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
-    double acc[27];
-#pragma unroll
-    for (int m = 0; m < 27; ++m) acc[m] = 0.0;
-    const double *sg = sig + (int64_t)(n >> 2) * G;
+__global__ void __launch_bounds__(256) k_qmoments(int nang, int G, int nn, const double *om, const double *wq,
+                                                  const double *sig, const real *psi, double *mom) {
+    __shared__ double part[4][3][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + lane;
+    const bool live = n < nn;
+    const int nc = live ? n : nn - 1;       // a clamped node keeps the loads in range; its sums are not stored
+    double s0[6] = {0, 0, 0, 0, 0, 0}, s1[3] = {0, 0, 0};
+    const double *sg = sig + (int64_t)(nc >> 2) * G;
     for (int d = 0; d < nang; ++d) {
-        const double mu = om[3 * d], eta = om[3 * d + 1], w = wq[d];
-        const int q = (mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3;
+        const double mu = om[3 * d], eta = om[3 * d + 1];
+        const int qd = (mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3;
+        if (qd != q) continue;              // uniform over the wave
+        const double w = wq[d];
         const double f[6] = {1.0, mu, eta, mu * mu, mu * eta, eta * eta};
-        double s0[6] = {0, 0, 0, 0, 0, 0}, s1[3] = {0, 0, 0};
-        const real *I = psi + (int64_t)d * G * nn + n;
+        const real *I = psi + (int64_t)d * G * nn + nc;
+        double t = 0.0, a = 0.0;
+#pragma unroll 4
         for (int g = 0; g < G; ++g) {
             const double v = (double)I[(int64_t)g * nn];
-#pragma unroll
-            for (int m = 0; m < 6; ++m) s0[m] += w * f[m] * v;
-            const double sv = sg[g] * w * v;
-            s1[0] += sv;
-            s1[1] += sv * mu;
-            s1[2] += sv * eta;
+            t += v;
+            a += sg[g] * v;
         }
-        // the quadrant index is uniform over the wave (one direction at a time)
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            acc[m] += q == 0 ? s0[m] : 0.0;
-            acc[6 + m] += q == 1 ? s0[m] : 0.0;
-            acc[12 + m] += q == 2 ? s0[m] : 0.0;
-            acc[18 + m] += q == 3 ? s0[m] : 0.0;
-        }
-        acc[24] += s1[0];
-        acc[25] += s1[1];
-        acc[26] += s1[2];
+        for (int m = 0; m < 6; ++m) s0[m] += w * f[m] * t;
+        s1[0] += w * a;
+        s1[1] += w * mu * a;
+        s1[2] += w * eta * a;
+    }
+    if (live) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) mom[(int64_t)(6 * q + m) * nn + n] = s0[m];
     }
 #pragma unroll
-    for (int m = 0; m < 27; ++m) mom[(int64_t)m * nn + n] = acc[m];
+    for (int m = 0; m < 3; ++m) part[q][m][lane] = s1[m];
+    __syncthreads();
+    if (q == 0 && live) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            mom[(int64_t)(24 + m) * nn + n] = ((part[0][m][lane] + part[1][m][lane]) + part[2][m][lane]) + part[3][m][lane];
+    }
 }
 
 }  // namespace smrt
@@ -526,7 +536,7 @@ extern "C" smrt_status smrt_qmesh_moments(smrt_qmesh *m, const double *sig, doub
         SMRT_HIP(hipEventCreate(&e0));
         if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); throw Error(SMRT_E_DEVICE, "hipEventCreate failed"); }
         SMRT_HIP(hipEventRecord(e0, s));
-        const dim3 grid((unsigned)((nn + 255) / 256));
+        const dim3 grid((unsigned)((nn + 63) / 64));     // 64 nodes per workgroup of 4 quadrant waves
         if (m->fp32) hipLaunchKernelGGL(k_qmoments<float>, grid, dim3(256), 0, s, m->nang, m->G, nn, m->om.p, m->wq.p,
                                         m->sig_m.p, (const float *)m->psi.p, m->mom.p);
         else hipLaunchKernelGGL(k_qmoments<double>, grid, dim3(256), 0, s, m->nang, m->G, nn, m->om.p, m->wq.p,
