@@ -136,7 +136,11 @@ struct LoSolver {
     double fetch(hipStream_t s, int slot);
     void schur(hipStream_t s, const double *x, double *y);
     struct LoGeom geom() const;
-    int pcg(hipStream_t s, double *x, double rtol, int maxit);
+    static constexpr int CG_CHECK = 4;   // CG iterations queued between host checks
+    double *hbuf = nullptr;              // pinned: CG stop flag and count, elimination flags, iterate change
+    void pcg_begin(hipStream_t s, double *x, double rtol, int maxit);
+    void pcg_block(hipStream_t s, double *x);
+    void pcg_status_async(hipStream_t s);
     smrt_status solve(hipStream_t s, const LoInputs &in, double *E, double *F, double *T, smrt_step_stats *st,
                       std::string &err);
 };

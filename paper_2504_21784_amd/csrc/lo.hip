@@ -23,9 +23,13 @@
 //   S E = qE + B(T0) - D M_F^-1 qF + dB dBt^-1 (qT - Bt(T0)),
 //   F = M_F^-1 (qF + (c/3) D^T E),
 //   cv T/dt + sigma_P a c T^4 = c sigma_E E + cv T*/dt at every node,
-// with Jacobi-preconditioned CG on S in CSR form; D (divergence) and P
-// (penalty, kappa = alpha/2) are geometric and assembled once on the host.
+// with preconditioned CG on S (Jacobi, or the aggregation multigrid of
+// mg_precond.inc); D (divergence) and P (penalty, kappa = alpha/2) are
+// geometric and assembled once on the host in CSR form, and the CG applies S
+// in stencil form.  One host wait per Newton iteration when a block of CG
+// iterations suffices.
 #include <cmath>
+#include <cstring>
 
 #include "lo.h"
 
@@ -783,23 +787,25 @@ void LoSolver::schur(hipStream_t s, const double *x, double *y) {
                        (double *)nullptr);
 }
 
-int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
+// Queues the start of a PCG solve of S x = rhs (x holds the initial guess):
+// the residual, the preconditioned residual, the scalars, the threshold and
+// the initial convergence test (all on the device; a solve that starts
+// converged runs frozen blocks and reports 0 iterations), then its first
+// block of CG_CHECK iterations.  Nothing is waited for.
+void LoSolver::pcg_begin(hipStream_t s, double *x, double rtol, int maxit) {
     schur(s, x, Ap.p);
     hipLaunchKernelGGL(k_cg_init, dim3(nb(nn)), dim3(256), 0, s, nn, rhs.p, Ap.p, r.p, Minv.p, z.p, p.p);
     if (precond == 1) mg_cg_init(s);               // z = M^-1 r, p = z by a V-cycle
     dot(s, rhs.p, nullptr, nullptr, 4, false);     // |b|^2
     dot(s, r.p, z.p, nullptr, 0, false);           // rz
     dot(s, r.p, nullptr, nullptr, 2, false);       // rr
-    // the threshold and the initial convergence test stay on the device: a
-    // solve that starts converged runs one frozen block and reports 0 iterations
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1), 0, s, sc.p, rtol, maxit);
-    constexpr int CHECK = 4;   // iterations queued between host checks
     if (use_graphs && !graph_failed && (cg_exec == nullptr || cg_stream != s || cg_x != x || cg_precond != precond)) {
-        // record CHECK iterations once (kernels only) and replay them; streams
-        // that cannot capture fall back to direct launches
+        // record CG_CHECK iterations once (kernels only) and replay them;
+        // streams that cannot capture fall back to direct launches
         drop_graph();
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-            cg_block(s, x, CHECK);
+            cg_block(s, x, CG_CHECK);
             hipGraph_t g = nullptr;
             if (hipStreamEndCapture(s, &g) == hipSuccess && g &&
                 hipGraphInstantiate(&cg_exec, g, nullptr, nullptr, 0) == hipSuccess) {
@@ -817,14 +823,18 @@ int LoSolver::pcg(hipStream_t s, double *x, double rtol, int maxit) {
             graph_failed = true;
         }
     }
-    for (;;) {
-        if (use_graphs && cg_exec) SMRT_HIP(hipGraphLaunch(cg_exec, s));
-        else cg_block(s, x, CHECK);
-        double st[2];
-        SMRT_HIP(hipMemcpyAsync(st, sc.p + 8, sizeof(st), hipMemcpyDeviceToHost, s));
-        SMRT_HIP(hipStreamSynchronize(s));
-        if (st[0] != 0.0) return (int)st[1];
-    }
+    pcg_block(s, x);
+}
+
+// Queues one more block of CG_CHECK iterations (frozen once converged).
+void LoSolver::pcg_block(hipStream_t s, double *x) {
+    if (use_graphs && cg_exec) SMRT_HIP(hipGraphLaunch(cg_exec, s));
+    else cg_block(s, x, CG_CHECK);
+}
+
+// Queues the copy of the CG stop flag and iteration count to the host.
+void LoSolver::pcg_status_async(hipStream_t s) {
+    SMRT_HIP(hipMemcpyAsync(hbuf, sc.p + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
 }
 
 // One CG iteration = 5 launches: D^T p; S p with the p.Sp block partials (both
@@ -867,6 +877,27 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
     hipLaunchKernelGGL(k_spmv, dim3(nb(nn)), dim3(256), 0, s, nn, dD.rp, dD.col, dD.val, tmpF.p, DqF.p);
     hipLaunchKernelGGL(k_jacobi_base, dim3(nb(nn)), dim3(256), 0, s, nn, dim, c / 3.0, dD.rp, dD.col, dD.val, dP.rp,
                        dP.col, dP.val, MFinv.p, jbase.p);
+    if (!hbuf) {
+        SMRT_HIP(hipHostMalloc((void **)&hbuf, 8 * sizeof(double), hipHostMallocDefault));
+    }
+    // F from E, then the pointwise temperature from the energy balance
+    // (starting from T as it was at the linearisation), then the iterate
+    // change |T - T_old|^2 + |E - E_old|^2 into scalar slot 5; the stop flag
+    // and count of the CG, the elimination flags and the change are copied
+    // to the host together
+    auto tail = [&]() {
+        hipLaunchKernelGGL(k_backsub, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn, dim, c / 3.0, dDT.rp, dDT.col,
+                           dDT.val, E, in.qF, MFinv.p, F);
+        hipLaunchKernelGGL(k_zero4, dim3(1), dim3(4), 0, s, flags.p);
+        hipLaunchKernelGGL(k_eliminate, dim3(nb(nn)), dim3(256), 0, s, nn, a, c, in.dt, in.elim_rtol, in.max_elim,
+                           in.T_floor, in.cvn, in.sigE, in.sigP, E, in.Tstar, T, flags.p);
+        dot(s, T, nullptr, Told.p, 5, false);
+        dot(s, E, nullptr, Eold.p, 5, true);
+        pcg_status_async(s);
+        SMRT_HIP(hipMemcpyAsync(hbuf + 2, flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+        SMRT_HIP(hipMemcpyAsync(hbuf + 4, sc.p + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+        SMRT_HIP(hipStreamSynchronize(s));
+    };
     double first = -1.0;
     smrt_status status = SMRT_OK;
     for (int m = 1; m <= in.max_inner; ++m) {
@@ -877,17 +908,24 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
             init_mg();                              // once per context
             setup_mg(s);                            // coarse operators of this linearisation
         }
-        st->cg_total += pcg(s, E, in.cg_rtol, in.max_cg);
-        hipLaunchKernelGGL(k_backsub, dim3(nb((int64_t)nn * dim)), dim3(256), 0, s, nn, dim, c / 3.0, dDT.rp, dDT.col,
-                           dDT.val, E, in.qF, MFinv.p, F);
-        hipLaunchKernelGGL(k_zero4, dim3(1), dim3(4), 0, s, flags.p);
-        hipLaunchKernelGGL(k_eliminate, dim3(nb(nn)), dim3(256), 0, s, nn, a, c, in.dt, in.elim_rtol, in.max_elim,
-                           in.T_floor, in.cvn, in.sigE, in.sigP, E, in.Tstar, T, flags.p);
+        // one block of CG iterations and the rest of the Newton iteration are
+        // queued before the first wait; a CG that needs more than one block
+        // runs on and the rest is redone from the saved temperature
+        pcg_begin(s, E, in.cg_rtol, in.max_cg);
+        tail();
+        if (hbuf[0] == 0.0) {
+            do {
+                pcg_block(s, E);
+                pcg_status_async(s);
+                SMRT_HIP(hipStreamSynchronize(s));
+            } while (hbuf[0] == 0.0);
+            SMRT_HIP(hipMemcpyAsync(T, Told.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+            tail();
+        }
+        st->cg_total += (int)hbuf[1];
         int fl[4];
-        SMRT_HIP(hipMemcpyAsync(fl, flags.p, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
-        dot(s, T, nullptr, Told.p, 5, false);
-        dot(s, E, nullptr, Eold.p, 5, true);
-        const double diff = std::sqrt(fetch(s, 5));
+        std::memcpy(fl, hbuf + 2, sizeof(fl));
+        const double diff = std::sqrt(hbuf[4]);
         st->inner_total++;
         if (fl[1] > st->elim_max) st->elim_max = fl[1];
         if (fl[0]) {
