@@ -62,6 +62,14 @@ struct smrt_ctx {
     double alpha[2] = {0, 0}, S1[4] = {0, 0, 0, 0}, S2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool have_state = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int *h_ctr = nullptr;          // pinned copy of the sweep's protocol counters
+    ~smrt_ctx() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (h_ctr) (void)hipHostFree(h_ctr);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -290,18 +298,28 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
     }
 }
 
+// The sweep's error flag (counter 3) is set when a band-trace wait exceeded
+// its bound.  fetch_sweep_flag queues its copy to pinned host memory;
+// raise_sweep_flag reads it after the caller's wait, resets the protocol
+// state so the context stays usable, and reports.
+static void fetch_sweep_flag(smrt_ctx *x) {
+    if (x->dim == 2) SMRT_HIP(hipMemcpyAsync(x->h_ctr, x->d_ctr.p, 4 * sizeof(int), hipMemcpyDeviceToHost, x->stream));
+}
+
+static void raise_sweep_flag(smrt_ctx *x) {
+    if (x->dim != 2 || !x->h_ctr[3]) return;
+    hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, x->stream, x->d_ctr.p);
+    SMRT_HIP(hipMemsetAsync(x->d_trace.p, 0, sizeof(uint64_t) * x->d_trace.n, x->stream));
+    SMRT_HIP(hipStreamSynchronize(x->stream));
+    x->h_ctr[3] = 0;
+    throw smrt::Error(SMRT_E_DEVICE, "sweep band-trace wait exceeded its bound");
+}
+
 static void check_sweep_flag(smrt_ctx *x) {
     if (x->dim != 2) return;
-    int ctr[4];
-    SMRT_HIP(hipMemcpyAsync(ctr, x->d_ctr.p, sizeof(ctr), hipMemcpyDeviceToHost, x->stream));
+    fetch_sweep_flag(x);
     SMRT_HIP(hipStreamSynchronize(x->stream));
-    if (ctr[3]) {
-        // reset the protocol state so the context stays usable, then report
-        hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, x->stream, x->d_ctr.p);
-        SMRT_HIP(hipMemsetAsync(x->d_trace.p, 0, sizeof(uint64_t) * x->d_trace.n, x->stream));
-        SMRT_HIP(hipStreamSynchronize(x->stream));
-        throw smrt::Error(SMRT_E_DEVICE, "sweep band-trace wait exceeded its bound");
-    }
+    raise_sweep_flag(x);
 }
 
 // rebuild the per-side inflow tables from the boundary description
@@ -501,6 +519,7 @@ extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_d
         else { SMRT_HIP(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking)); p->own_stream = true; }
         SMRT_HIP(hipEventCreate(&p->ev0));
         SMRT_HIP(hipEventCreate(&p->ev1));
+        SMRT_HIP(hipHostMalloc((void **)&p->h_ctr, 4 * sizeof(int), hipHostMallocDefault));
         upload_series_coefficients();
         // quadrature sums used by the closures
         for (int ax = 0; ax < p->dim; ++ax) {
@@ -636,14 +655,7 @@ extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_d
     return SMRT_OK;
 }
 
-extern "C" void smrt_destroy(smrt_ctx *ctx) {
-    if (!ctx) return;
-    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
-    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
-    delete ctx;
-}
+extern "C" void smrt_destroy(smrt_ctx *ctx) { delete ctx; }
 
 extern "C" smrt_status smrt_set_options(smrt_ctx *x, const smrt_options *o) {
     if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
@@ -1180,7 +1192,8 @@ extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, 
                                                  x->d_sigP.p, x->d_sigF.p, x->d_Eho.p, x->d_Fho.p, x->d_clos.p));
         }
         SMRT_HIP(hipEventRecord(x->ev1, x->stream));
-        SMRT_HIP(hipEventSynchronize(x->ev1));
+        fetch_sweep_flag(x);                       // one wait for the passes and the flag
+        SMRT_HIP(hipStreamSynchronize(x->stream));
         float ms = 0.f, ks = 0.f;
         SMRT_HIP(hipEventElapsedTime(&ms, x->ev0, x->ev1));
         for (int k = 0; k < n_times; ++k) {
@@ -1190,7 +1203,7 @@ extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, 
         }
         *ms_per_pass = ms / n_times;
         *ms_sweep_kernel = ks / n_times;
-        check_sweep_flag(x);
+        raise_sweep_flag(x);
     });
 }
 
