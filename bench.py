@@ -272,8 +272,8 @@ def main():
     global LO_GRAPHS
     LO_GRAPHS = args.lo_graphs
     if args.gpus != 1:
-        print("bench.py measures one MI355X: this build runs on a single GPU (the multi-GPU sharding "
-              "of the sweep is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one MI355X: the library runs on a single GPU (sharding the sweep "
+              "over several GPUs is not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
