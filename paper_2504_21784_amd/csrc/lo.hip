@@ -604,6 +604,62 @@ __global__ void k_dot_finish(const double *part, double *out, int slot, int accu
     if (threadIdx.x == 0) out[slot] = accumulate ? out[slot] + sh[0] : sh[0];
 }
 
+// Several sums in one pass over the vectors (the CG start: b.b, r.z, r.r;
+// the Newton iterate change: |T - T_old|^2 + |E - E_old|^2), as block
+// partials part[j][block], then k_dot_finish_n adds each row in a fixed
+// order into its scalar slot.
+__global__ void k_dot3_partial(int n, const double *b, const double *r, const double *z, double *part) {
+    __shared__ double sh[3][RED_THREADS];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
+        const double ri = r[i];
+        s0 += b[i] * b[i];
+        s1 += ri * z[i];
+        s2 += ri * ri;
+    }
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    sh[2][threadIdx.x] = s2;
+    __syncthreads();
+    for (int k = RED_THREADS / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k)
+            for (int j = 0; j < 3; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 3; ++j) part[j * RED_BLOCKS + blockIdx.x] = sh[j][0];
+}
+__global__ void k_diff2_partial(int n, const double *T, const double *To, const double *E, const double *Eo,
+                                double *part) {
+    __shared__ double sh[RED_THREADS];
+    double s = 0.0;
+    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
+        const double dT = T[i] - To[i], dE = E[i] - Eo[i];
+        s += dT * dT + dE * dE;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = RED_THREADS / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_dot_finish_n(const double *part, double *out, int m, int slot0, int slot1, int slot2) {
+    __shared__ double sh[RED_BLOCKS];
+    const int slots[3] = {slot0, slot1, slot2};
+    for (int j = 0; j < m; ++j) {
+        sh[threadIdx.x] = part[j * RED_BLOCKS + threadIdx.x];
+        __syncthreads();
+        for (int k = RED_BLOCKS / 2; k > 0; k >>= 1) {
+            if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[slots[j]] = sh[0];
+        __syncthreads();
+    }
+}
+
 // CG vector updates with device-side scalars: sc[0]=rz, sc[1]=pAp, sc[2]=rr, sc[3]=rz_new
 // p = z + (rz_new / rz) p, rz_new summed here from the r.z block partials
 __global__ void __launch_bounds__(256) k_cg_p(int n, int nbk, const double *sc, const double *part, const double *z,
@@ -752,7 +808,7 @@ void LoSolver::init(int dim_, int nx, int ny, const std::vector<double> &xe, con
     SMRT_HIP(hipMemcpy(wn.p, wv.data(), sizeof(double) * nn, hipMemcpyHostToDevice));
     for (auto *v : {&MFinv, &DqF, &jbase, &diagE, &rhs, &Minv, &r, &z, &p, &Ap, &Eold, &Told}) v->alloc(nn);
     tmpF.alloc((int64_t)nn * dim);
-    part.alloc(RED_BLOCKS);
+    part.alloc(3 * RED_BLOCKS);
     sc.alloc(12);
     bpart.alloc(2 * (int64_t)((nn + 255) / 256));
     apart.alloc((int64_t)((nn + 255) / 256));
@@ -796,9 +852,9 @@ void LoSolver::pcg_begin(hipStream_t s, double *x, double rtol, int maxit) {
     schur(s, x, Ap.p);
     hipLaunchKernelGGL(k_cg_init, dim3(nb(nn)), dim3(256), 0, s, nn, rhs.p, Ap.p, r.p, Minv.p, z.p, p.p);
     if (precond == 1) mg_cg_init(s);               // z = M^-1 r, p = z by a V-cycle
-    dot(s, rhs.p, nullptr, nullptr, 4, false);     // |b|^2
-    dot(s, r.p, z.p, nullptr, 0, false);           // rz
-    dot(s, r.p, nullptr, nullptr, 2, false);       // rr
+    // |b|^2, rz, rr into slots 4, 0, 2
+    hipLaunchKernelGGL(k_dot3_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, nn, rhs.p, r.p, z.p, part.p);
+    hipLaunchKernelGGL(k_dot_finish_n, dim3(1), dim3(RED_BLOCKS), 0, s, part.p, sc.p, 3, 4, 0, 2);
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1), 0, s, sc.p, rtol, maxit);
     if (use_graphs && !graph_failed && (cg_exec == nullptr || cg_stream != s || cg_x != x || cg_precond != precond)) {
         // record CG_CHECK iterations once (kernels only) and replay them;
@@ -891,8 +947,9 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
         hipLaunchKernelGGL(k_zero4, dim3(1), dim3(4), 0, s, flags.p);
         hipLaunchKernelGGL(k_eliminate, dim3(nb(nn)), dim3(256), 0, s, nn, a, c, in.dt, in.elim_rtol, in.max_elim,
                            in.T_floor, in.cvn, in.sigE, in.sigP, E, in.Tstar, T, flags.p);
-        dot(s, T, nullptr, Told.p, 5, false);
-        dot(s, E, nullptr, Eold.p, 5, true);
+        hipLaunchKernelGGL(k_diff2_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, nn, T, Told.p, E, Eold.p,
+                           part.p);
+        hipLaunchKernelGGL(k_dot_finish_n, dim3(1), dim3(RED_BLOCKS), 0, s, part.p, sc.p, 1, 5, 5, 5);
         pcg_status_async(s);
         SMRT_HIP(hipMemcpyAsync(hbuf + 2, flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         SMRT_HIP(hipMemcpyAsync(hbuf + 4, sc.p + 5, sizeof(double), hipMemcpyDeviceToHost, s));
