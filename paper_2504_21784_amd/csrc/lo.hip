@@ -721,7 +721,7 @@ __global__ void k_backsub(int nn, int dim, double c3, const int *rp, const int *
 // as it is and flags a node without one.
 // flags: [0] a node without a positive root (no floor), [1] the largest
 // iteration count, [2] a node that hit maxit; the count is reduced over the
-// wave first, so the flags see one atomic per wave.
+// wave first, and a wave whose count is already stored skips its atomic.
 __global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, int maxit, double T_floor,
                             const double *cvn, const double *sigE, const double *sigP, const double *E,
                             const double *Tstar, double *T, int *flags) {
@@ -757,7 +757,9 @@ __global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, 
     const bool any_capped = __builtin_amdgcn_ballot_w64(capped) != 0;
     if ((threadIdx.x & 63) == 0) {
         if (any_bad) atomicOr(&flags[0], 1);
-        if (m > 0) atomicMax(&flags[1], m);
+        // a count at or below the one already stored needs no atomic (most
+        // waves, once a few have stored theirs): one address, thousands of waves
+        if (m > __hip_atomic_load(&flags[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&flags[1], m);
         if (any_capped) atomicOr(&flags[2], 1);
     }
 }
