@@ -4,7 +4,8 @@ cell) and unstructured ones (triangles cut into three quadrilaterals), FP64
 to 1e-10 and FP32 to 1e-5 of the field's maximum; a rectilinear mesh given
 as quadrilaterals against the rectilinear sweep kernel (two GPU paths that
 share nothing but the problem); the gray moments of the swept intensity;
-the error cases; and the throughput at the benchmark's scale (printed).
+the error cases; sampled parity and the throughput at the benchmark's scale
+(printed).
 """
 import numpy as np
 import pytest
@@ -112,6 +113,33 @@ def test_qmesh_rejects_bad_meshes(smrt_mod):
         with pytest.raises(smrt_mod.SmrtError) as e:
             smrt_mod.QuadMeshSweep(xy, c, om, w, 1)
         assert e.value.status == smrt_mod.SMRT_E_INVALID_ARG
+
+
+def test_qmesh_full_size_sampled(smrt_mod, oracle_mod):
+    """The benchmark's scale and launch (256x256 given as quadrilaterals, S8,
+    16 groups, FP32, vacuum, no time-edge source): the oracle sweeps groups 0
+    and 15 alone (groups are independent) and the GPU's intensity matches
+    them to 1e-5; the GPU's gray moments match the oracle's moment sums of
+    the GPU's own intensity (the moment kernel's parity at full size)."""
+    xy, cells = W.quad_mesh_jittered(256, 256, jitter=0.0)
+    om, w = W.level_symmetric_2d(8)
+    G, nc = 16, len(cells)
+    rng = np.random.default_rng(1)
+    sigt = 10.0 ** rng.uniform(-1, 2, (nc, G))
+    q = rng.uniform(0, 1, (4 * nc, G))
+    print("full-size unstructured sweep: 65536 cells, S8, G=16, FP32", flush=True)
+    m = smrt_mod.QuadMeshSweep(xy, cells, om, w, G, precision=1)
+    psi, _ = m.sweep(sigt, q, None, 0.0)
+    mom, _ = m.moments(0.5 * sigt)
+    m.close()
+    sample = [0, G - 1]
+    ref_mesh = oracle_mod.QuadMesh(xy, cells, om, w, len(sample))
+    ref = ref_mesh.sweep(sigt[:, sample], q[:, sample], None, 0.0, None)
+    assert _rel(psi[:, sample], ref) < 1e-5
+    full = oracle_mod.QuadMesh(xy, cells, om, w, G)
+    want = full.moments(0.5 * sigt, psi)
+    for r in range(27):
+        assert np.abs(mom[r] - want[r]).max() <= 1e-12 * np.abs(want[24 if r >= 24 else 6 * (r // 6)]).max(), r
 
 
 @pytest.mark.parametrize("kind", ["rectilinear", "split"])
