@@ -1080,8 +1080,9 @@ struct StepRun {
             s.hit_max |= ls.hit_max;
             if (r != SMRT_OK) result = r;
         }
-        check_sweep_flag(x);
+        fetch_sweep_flag(x);                       // read after the change norm's own wait
         const double diff = diff_norm(x, x->d_Tn.p, x->d_Tl.p, x->d_En.p, x->d_El.p);
+        raise_sweep_flag(x);
         SMRT_HIP(hipMemcpyAsync(x->d_Tl.p, x->d_Tn.p, 8 * nn, hipMemcpyDeviceToDevice, S));
         SMRT_HIP(hipMemcpyAsync(x->d_El.p, x->d_En.p, 8 * nn, hipMemcpyDeviceToDevice, S));
         if (result != SMRT_OK) return done = true;
