@@ -28,6 +28,24 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def build_variant(path: str, edits) -> C.CDLL:
+    """Compile a copy of ``oracle.c`` with textual ``edits`` [(old, new)]
+    applied (each must match exactly once) into ``path`` and load it.  Used
+    only by the pins, to plant a known mistake and check that a pin fails."""
+    src = open(_SRC).read()
+    for old, new in edits:
+        if src.count(old) != 1:
+            raise ValueError(f"edit does not match exactly once: {old!r}")
+        src = src.replace(old, new)
+    csrc = path + ".c"
+    with open(csrc, "w") as f:
+        f.write(src)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-w", "-fPIC", "-shared", "-o", path, csrc, "-lm"])
+    L = C.CDLL(path)
+    _declare(L)
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -131,9 +149,12 @@ def default_opts(**kw) -> dict:
 class Oracle:
     """Holds ctypes descriptors (and keeps the numpy arrays alive) for one Problem."""
 
-    def __init__(self, p):
+    def __init__(self, p, L=None):
+        """``L``: an already loaded oracle library (default: the built one);
+        the pins load deliberately broken copies this way to show that they
+        catch the mistake."""
         self.p = p
-        self.L = lib()
+        self.L = L if L is not None else lib()
         self._keep = []
         k = self._keep.append
         xe = _f64(p.x_edges); k(xe)
