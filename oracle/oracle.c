@@ -901,7 +901,11 @@ static void schur_apply(const orc_schur *S, const double *x, double *y)
     for (int n = 0; n < nn; ++n) y[n] = S->c3 * y[n] + S->tmpE[n] + S->diagE[n] * x[n];
 }
 
-static int pcg(const orc_schur *S, const double *b, double *x, const double *Minv, double rtol, int maxit)
+/* Returns the iteration count; *capped = 1 when maxit iterations ran and the
+ * residual still exceeds the threshold (the paper's tables mark such capped
+ * counts). */
+static int pcg(const orc_schur *S, const double *b, double *x, const double *Minv, double rtol, int maxit,
+               int *capped)
 {
     int n = S->ops->nn;
     double *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
@@ -923,6 +927,7 @@ static int pcg(const orc_schur *S, const double *b, double *x, const double *Min
         rz = rzn;
         ++it;
     }
+    *capped = it >= maxit && sqrt(dot(n, r, r)) > rtol * bn;
     free(r); free(z); free(p); free(Ap);
     return it;
 }
@@ -970,7 +975,9 @@ static int lo_solve_ops(const orc_geom *g, const orc_lo_ops *ops, const orc_opts
             for (int k = 0; k < ops->P[n].n; ++k) if (ops->P[n].col[k] == n) pp += ops->P[n].val[k];
             Minv[n] = 1.0 / ((c / 3.0) * dd + pp + diagE[n]);
         }
-        st->cg_total += pcg(&S, rhs, E, Minv, op->cg_rtol, op->max_cg);
+        int cg_capped = 0;
+        st->cg_total += pcg(&S, rhs, E, Minv, op->cg_rtol, op->max_cg, &cg_capped);
+        if (cg_capped) st->hit_max = 1;
         /* back substitution for F */
         apply_DT(ops, E, tF);
         for (int k = 0; k < nn * dim; ++k) F[k] = (qF[k] + (c / 3.0) * tF[k]) / MF[k];
@@ -980,6 +987,7 @@ static int lo_solve_ops(const orc_geom *g, const orc_lo_ops *ops, const orc_opts
             int it = orc_energy_solve(cvn[n] / dt, sigP[n] * a * c, r, T[n], op->elim_rtol, op->max_elim, &T[n]);
             if (floor_temperature(op->T_floor, it, &T[n])) { status = ORC_E_NONPHYSICAL; break; }
             if (it > st->elim_max) st->elim_max = it;
+            if (it >= op->max_elim) st->hit_max = 1;   /* this node's Newton ran to its cap */
         }
         st->inner_total++;
         if (status) break;
@@ -1143,6 +1151,7 @@ int orc_step(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_o
                 int it = orc_energy_solve(cvn[n] / dt, (sbs / sb) * a * c, r, Tl[n], op->elim_rtol, op->max_elim, &Tn[n]);
                 if (floor_temperature(op->T_floor, it, &Tn[n])) { status = ORC_E_NONPHYSICAL; break; }
                 if (it > st->elim_max) st->elim_max = it;
+                if (it >= op->max_elim) st->hit_max = 1;
             }
             memcpy(E_lo, En, sizeof(double) * nn);
         } else {

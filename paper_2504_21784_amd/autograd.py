@@ -24,13 +24,16 @@ class ObjectiveFunction(torch.autograd.Function):
         ctx.set_materials(s0, cv)
         ctx.set_state(T0)
         J, gs, gc, _ = ctx.adjoint(n_steps, dt, objective=kind)
-        fctx.save_for_backward(torch.from_numpy(gs).to(log_sigma0.dtype), torch.from_numpy(gc).to(log_cv.dtype))
-        return torch.tensor(J, dtype=torch.float64)
+        # gradients live where the parameters live (CPU or GPU tensors alike)
+        fctx.save_for_backward(torch.from_numpy(gs).to(device=log_sigma0.device, dtype=log_sigma0.dtype),
+                               torch.from_numpy(gc).to(device=log_cv.device, dtype=log_cv.dtype))
+        return torch.tensor(J, dtype=torch.float64, device=log_sigma0.device)
 
     @staticmethod
     def backward(fctx, gJ):
         gs, gc = fctx.saved_tensors
-        return gJ * gs, gJ * gc, None, None, None, None, None
+        return (gJ.to(device=gs.device, dtype=gs.dtype) * gs, gJ.to(device=gc.device, dtype=gc.dtype) * gc,
+                None, None, None, None, None)
 
 
 def objective(log_sigma0, log_cv, ctx, T0, n_steps, dt, kind=0):

@@ -63,9 +63,11 @@ struct smrt_ctx {
     bool have_state = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int *h_ctr = nullptr;          // pinned copy of the sweep's protocol counters
+    double *h_small = nullptr;     // pinned staging for small device-to-host reads (32 doubles)
     ~smrt_ctx() {
         if (stream) (void)hipStreamSynchronize(stream);
         if (h_ctr) (void)hipHostFree(h_ctr);
+        if (h_small) (void)hipHostFree(h_small);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -302,6 +304,16 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
 // its bound.  fetch_sweep_flag queues its copy to pinned host memory;
 // raise_sweep_flag reads it after the caller's wait, resets the protocol
 // state so the context stays usable, and reports.
+// A small device-to-host read (at most 32 doubles) that waits for the
+// context stream: staged through the context's pinned buffer, never copied
+// asynchronously into pageable (stack) memory.
+static void read_small(smrt_ctx *x, void *dst, const void *src, size_t bytes) {
+    if (bytes > 32 * sizeof(double)) throw smrt::Error(SMRT_E_INVALID_ARG, "read_small: more than 32 doubles");
+    SMRT_HIP(hipMemcpyAsync(x->h_small, src, bytes, hipMemcpyDeviceToHost, x->stream));
+    SMRT_HIP(hipStreamSynchronize(x->stream));
+    std::memcpy(dst, x->h_small, bytes);
+}
+
 static void fetch_sweep_flag(smrt_ctx *x) {
     if (x->dim == 2) SMRT_HIP(hipMemcpyAsync(x->h_ctr, x->d_ctr.p, 4 * sizeof(int), hipMemcpyDeviceToHost, x->stream));
 }
@@ -520,6 +532,7 @@ extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_d
         SMRT_HIP(hipEventCreate(&p->ev0));
         SMRT_HIP(hipEventCreate(&p->ev1));
         SMRT_HIP(hipHostMalloc((void **)&p->h_ctr, 4 * sizeof(int), hipHostMallocDefault));
+        SMRT_HIP(hipHostMalloc((void **)&p->h_small, 32 * sizeof(double), hipHostMallocDefault));
         upload_series_coefficients();
         // quadrature sums used by the closures
         for (int ax = 0; ax < p->dim; ++ax) {
@@ -880,8 +893,7 @@ extern "C" smrt_status smrt_sweep_dev(smrt_ctx *x, const double *sig_t, const do
         hipLaunchKernelGGL(k_check_opacities, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, x->stream, ng, sig_t,
                            sig, bad.p);
         int hb = 0;
-        d2h(&hb, bad.p, sizeof(int), x->stream);
-        SMRT_HIP(hipStreamSynchronize(x->stream));
+        read_small(x, &hb, bad.p, sizeof(int));
         require(hb == 0, "sig_t must be > 0 and sig >= 0");
         raw_sweep(x, sig_t, sig, q_iso, psi_prev, inv_c_dt, psi_inflow, psi_out, moments_out);
     });
@@ -1062,9 +1074,9 @@ struct StepRun {
                           x->d_sigEho.p,
                           x->d_sigP.p, x->d_En.p, x->d_Tstar.p, x->d_Tn.p, L.flags.p);
             int fl[4];
-            d2h(fl, L.flags.p, sizeof fl, S);
-            SMRT_HIP(hipStreamSynchronize(S));
+            L.fetch_flags(S, fl);
             if (fl[1] > s.elim_max) s.elim_max = fl[1];
+            if (fl[2]) s.hit_max = 1;             // a node's pointwise Newton ran to its cap
             if (fl[0]) { x->err = "no positive temperature root in the energy balance"; result = SMRT_E_NONPHYSICAL; }
         } else {
             SMRT_HIP(hipMemcpyAsync(x->d_En.p, x->d_El.p, 8 * nn, hipMemcpyDeviceToDevice, S));
@@ -1752,16 +1764,14 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
             if (objective == 0) {
                 run_dot(S, npsi, dJdI.p, ck_psi.p + npsi * k, part.p, scal.p);
                 double jk = 0.0;
-                d2h(&jk, scal.p, 8, S);
-                SMRT_HIP(hipStreamSynchronize(S));
+                read_small(x, &jk, scal.p, 8);
                 J += jk;
             }
         }
         const double *TN = ck_T.p + (int64_t)nn * N;
         if (objective == 1) {
             run_dot(S, nn, wc.p, TN, part.p, scal.p);
-            d2h(&J, scal.p, 8, S);
-            SMRT_HIP(hipStreamSynchronize(S));
+            read_small(x, &J, scal.p, 8);
         }
         // reverse
         DevBuf<double> lam, lam_next, src, prev_tmp, out_tmp, zq, zinf, sigt, tau, tau_new, ST, ST_prev, emis, dE, phi, D,
@@ -1803,8 +1813,7 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
                 run_adj_tau(S, x->dim, x->nx, ny1, G, x->nang, x->d_hx64.p, hy, sig, dE.p, ST.p, D.p, lam.p, tau.p,
                             tau_new.p, part.p, scal.p);
                 double nd[2];
-                d2h(nd, scal.p, 16, S);
-                SMRT_HIP(hipStreamSynchronize(S));
+                read_small(x, nd, scal.p, 16);
                 ++iters;
                 if (!(nd[0] > 1e-30 * nd[1]) || nd[1] == 0.0) {   // |g - tau| small: keep g
                     std::swap(tau.p, tau_new.p);
@@ -1827,8 +1836,7 @@ extern "C" smrt_status smrt_adjoint(smrt_ctx *x, int objective, int n_steps, dou
                 for (int c = 0; c < nwin; ++c) sl.s[c] = win[c];
                 run_aa_dots(S, nn, nwin, sl, dFr.p, dFr.p + (int64_t)slot * nn, fprev.p, aapart.p, aaout.p);
                 double dots[2 * AA_M];
-                d2h(dots, aaout.p, sizeof(double) * 2 * nwin, S);
-                SMRT_HIP(hipStreamSynchronize(S));
+                read_small(x, dots, aaout.p, sizeof(double) * 2 * nwin);
                 double b[AA_M], A[AA_M][AA_M], L[AA_M][AA_M] = {};
                 for (int c = 0; c < nwin; ++c) {
                     Mg[win[c]][slot] = Mg[slot][win[c]] = dots[2 * c];

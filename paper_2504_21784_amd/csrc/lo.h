@@ -134,6 +134,8 @@ struct LoSolver {
               const double alpha[2], double c, double a);
     double dot(hipStream_t s, const double *x, const double *y, const double *cdiff, int slot, bool accumulate);
     double fetch(hipStream_t s, int slot);
+    void fetch_flags(hipStream_t s, int fl[4]);   // the elimination flags, through pinned memory
+    void ensure_hbuf();
     void schur(hipStream_t s, const double *x, double *y);
     struct LoGeom geom() const;
     static constexpr int CG_CHECK = 4;   // CG iterations queued between host checks

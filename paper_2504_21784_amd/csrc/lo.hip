@@ -823,11 +823,26 @@ double LoSolver::dot(hipStream_t s, const double *x, const double *y, const doub
     return 0.0;
 }
 
+// Every small device-to-host read of the LO goes through the pinned buffer
+// hbuf (slots 0-1 CG status, 2-3 elimination flags, 4 iterate change, 5 a
+// fetched scalar, 6-7 the flags of a caller's elimination), never through
+// pageable stack memory.
+void LoSolver::ensure_hbuf() {
+    if (!hbuf) SMRT_HIP(hipHostMalloc((void **)&hbuf, 8 * sizeof(double), hipHostMallocDefault));
+}
+
 double LoSolver::fetch(hipStream_t s, int slot) {
-    double v;
-    SMRT_HIP(hipMemcpyAsync(&v, sc.p + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+    ensure_hbuf();
+    SMRT_HIP(hipMemcpyAsync(hbuf + 5, sc.p + slot, sizeof(double), hipMemcpyDeviceToHost, s));
     SMRT_HIP(hipStreamSynchronize(s));
-    return v;
+    return hbuf[5];
+}
+
+void LoSolver::fetch_flags(hipStream_t s, int fl[4]) {
+    ensure_hbuf();
+    SMRT_HIP(hipMemcpyAsync(hbuf + 6, flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    SMRT_HIP(hipStreamSynchronize(s));
+    std::memcpy(fl, hbuf + 6, 4 * sizeof(int));
 }
 
 LoGeom LoSolver::geom() const {
@@ -918,6 +933,8 @@ void LoSolver::cg_block(hipStream_t s, double *x, int iters) {
 }
 
 void LoSolver::drop_graph() {
+    // the last replay may still be queued on its stream: let it finish first
+    if (cg_exec && cg_stream) (void)hipStreamSynchronize(cg_stream);
     if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
     if (cg_graph) (void)hipGraphDestroy(cg_graph);
     cg_exec = nullptr;
@@ -935,9 +952,7 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
     hipLaunchKernelGGL(k_spmv, dim3(nb(nn)), dim3(256), 0, s, nn, dD.rp, dD.col, dD.val, tmpF.p, DqF.p);
     hipLaunchKernelGGL(k_jacobi_base, dim3(nb(nn)), dim3(256), 0, s, nn, dim, c / 3.0, dD.rp, dD.col, dD.val, dP.rp,
                        dP.col, dP.val, MFinv.p, jbase.p);
-    if (!hbuf) {
-        SMRT_HIP(hipHostMalloc((void **)&hbuf, 8 * sizeof(double), hipHostMallocDefault));
-    }
+    ensure_hbuf();
     // F from E, then the pointwise temperature from the energy balance
     // (starting from T as it was at the linearisation), then the iterate
     // change |T - T_old|^2 + |E - E_old|^2 into scalar slot 5; the stop flag
@@ -982,11 +997,16 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
             tail();
         }
         st->cg_total += (int)hbuf[1];
+        // a CG stopped by its iteration cap (stop flag 2), or a node whose
+        // pointwise Newton ran to its cap (elimination flag 2), is a capped
+        // iteration of this step
+        if (hbuf[0] == 2.0) st->hit_max = 1;
         int fl[4];
         std::memcpy(fl, hbuf + 2, sizeof(fl));
         const double diff = std::sqrt(hbuf[4]);
         st->inner_total++;
         if (fl[1] > st->elim_max) st->elim_max = fl[1];
+        if (fl[2]) st->hit_max = 1;
         if (fl[0]) {
             err = "no positive temperature root in the energy balance";
             status = SMRT_E_NONPHYSICAL;

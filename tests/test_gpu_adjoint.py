@@ -192,3 +192,26 @@ def test_adjoint_full_size_finite_differences(smrt_mod, objective):
                 fd = (J_at(p.sigma0, p.cv * np.exp(e)) - J_at(p.sigma0, p.cv * np.exp(-e))) / (2 * h)
             assert abs(g[r] - fd) <= 1e-4 * abs(fd), (which, r, g[r], fd)
     ctx.close()
+
+
+def test_autograd_function_on_gpu_tensors(smrt_mod):
+    """Parameters held on the GPU: the objective and both gradients come back
+    on that device, equal to the CPU-tensor call."""
+    import torch
+    from paper_2504_21784_amd.autograd import outflow
+    p = _adjoint_problem()
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **TIGHT)
+    T0 = p.initial_T_nodes()
+    dev = torch.device("cuda:0")
+    ls = torch.tensor(np.log(p.sigma0), dtype=torch.float64, device=dev, requires_grad=True)
+    lc = torch.tensor(np.log(p.cv), dtype=torch.float64, device=dev, requires_grad=True)
+    J = outflow(ls, lc, ctx, T0, 2, p.dt)
+    assert J.device == dev
+    (2.0 * J).backward()
+    assert ls.grad.device == dev and lc.grad.device == dev
+    ls_c = torch.tensor(np.log(p.sigma0), dtype=torch.float64, requires_grad=True)
+    lc_c = torch.tensor(np.log(p.cv), dtype=torch.float64, requires_grad=True)
+    (2.0 * outflow(ls_c, lc_c, ctx, T0, 2, p.dt)).backward()
+    np.testing.assert_array_equal(ls.grad.cpu().numpy(), ls_c.grad.numpy())
+    np.testing.assert_array_equal(lc.grad.cpu().numpy(), lc_c.grad.numpy())
+    ctx.close()

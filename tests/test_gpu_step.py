@@ -236,3 +236,34 @@ def test_lo_nonphysical_energy_balance(smrt_mod):
         ctx.lo_solve(rows, T, p.dt, p.a * T ** 4, T)
     assert e.value.status == smrt_mod.SMRT_E_NONPHYSICAL
     ctx.close()
+
+
+@pytest.mark.parametrize("scheme,caps", [
+    (0, dict(max_cg=500, max_elim=100)),
+    (0, dict(max_cg=1, max_elim=100)),
+    (0, dict(max_cg=500, max_elim=1)),
+    (2, dict(max_elim=100)),
+    (2, dict(max_elim=1)),
+])
+def test_lo_and_elimination_caps_are_reported(smrt_mod, oracle_mod, scheme, caps):
+    """A CG stopped by its cap, or a pointwise Newton run to its cap, is a
+    capped iteration: hit_max as the oracle reports it; strict = 1 turns it
+    into SMRT_E_NOT_CONVERGED (generous caps: OK either way)."""
+    p = W.gray_2d(n=8, sn=4, block=4, seed=2)
+    o = oracle_mod.Oracle(p)
+    opts = dict(eps_outer=1e-6, eps_inner=1e-8, cg_rtol=1e-12, elim_rtol=1e-13, max_outer=500, max_inner=60, **caps)
+    _, _, ref = o.step(o.initial_state(), oracle_mod.default_opts(scheme=scheme, **opts))
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, scheme=scheme, **opts)
+    ctx.set_state(p.initial_T_nodes())
+    st = ctx.step()
+    assert st["hit_max"] == ref["hit_max"], (st, ref)
+    ctx.close()
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, scheme=scheme, strict=1, **opts)
+    ctx.set_state(p.initial_T_nodes())
+    if ref["hit_max"]:
+        with pytest.raises(smrt_mod.SmrtError) as e:
+            ctx.step()
+        assert e.value.status == smrt_mod.SMRT_E_NOT_CONVERGED
+    else:
+        ctx.step()
+    ctx.close()

@@ -615,3 +615,25 @@ def test_P11_adjoint_gradient_matches_finite_differences(oracle_mod, objective):
     assert scale > 0
     assert np.abs(gs - fd_s).max() <= 1e-5 * scale, (gs, fd_s)
     assert np.abs(gc - fd_c).max() <= 1e-5 * scale, (gc, fd_c)
+
+
+# ---------------------------------------------------------------------------
+# Iteration caps (Sec. 6 tables mark capped counts): a CG that stops at its
+# cap with the residual above the threshold, or a node whose pointwise Newton
+# runs to its cap, sets hit_max; generous caps leave it clear.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,caps,capped", [
+    (0, dict(max_cg=500, max_elim=100), 0),
+    (0, dict(max_cg=1, max_elim=100), 1),
+    (0, dict(max_cg=500, max_elim=1), 1),
+    (2, dict(max_elim=100), 0),
+    (2, dict(max_elim=1), 1),
+])
+def test_iteration_caps_are_reported(oracle_mod, scheme, caps, capped):
+    p = W.gray_2d(n=8, sn=4, block=4, seed=2)
+    o = oracle_mod.Oracle(p)
+    opts = oracle_mod.default_opts(eps_outer=1e-6, eps_inner=1e-8, cg_rtol=1e-12, elim_rtol=1e-13, max_outer=500,
+                                   max_inner=60, scheme=scheme, **caps)
+    r, _, stats = o.step(o.initial_state(), opts)
+    assert r == 0
+    assert stats["hit_max"] == capped, stats
