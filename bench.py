@@ -289,7 +289,7 @@ def main():
     def make(prec, T=T0, psi=None):
         ctx = smrt.Context(p, precision=prec, stream=stream, lo_graphs=LO_GRAPHS)
         if args.waves or args.pairs:
-            ctx.set_launch(args.waves, args.pairs if prec == smrt.SMRT_FP32 else min(args.pairs, 1))
+            ctx.set_launch(args.waves, args.pairs if prec == smrt.SMRT_FP32 else min(args.pairs, 2))
         ctx.set_state(T, psi)
         return ctx
 
@@ -330,7 +330,8 @@ def main():
     step32 = (ctx.get_moments(), ctx.get_state(with_psi=False)["T"])
     alg_bytes = info["algorithmic_bytes_per_sweep"]
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    sweep_kernel = f"sweep2d_kernel<float, {info['pairs_per_lane']}, {4 if info['pairs_per_lane'] == 1 else 2}, " \
+    prefetch = {1: 4, 2: 3, 4: 1}[info['pairs_per_lane']]   # the kernel's prefetch depth per groups-per-lane
+    sweep_kernel = f"sweep2d_kernel<float, {info['pairs_per_lane']}, {prefetch}, " \
                    f"{info['waves_per_group']}, false, false>"
     ctx.close()
 

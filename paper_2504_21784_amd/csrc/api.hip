@@ -48,7 +48,9 @@ struct smrt_ctx {
     std::vector<int> qc_quad;
     std::vector<int> slot_pair;   // pairs (d, g)
     ChunkRanges chunks{};         // chunk range of each quadrant
-    DevBuf<int> d_qc_quad, d_slot_pair, d_ctr, d_lctr;
+    DevBuf<int> d_qc_quad, d_qc_dir, d_slot_pair, d_ctr, d_lctr;
+    DevBuf<double> d_dirs64;      // per direction, FP64: mu, eta, w, w mu, w eta, w mu^2, w mu eta, w eta^2
+    std::vector<int> qc_dir;      // direction of each chunk
     DevBuf<int2> d_tasks;         // single-problem task list (0, band * NQC + chunk)
     DevBuf<unsigned char> d_psi[2], d_part, d_qiso, d_sig2, d_inflow;
     DevBuf<uint64_t> d_trace;
@@ -173,21 +175,17 @@ static void plan_sweep(smrt_ctx *x) {
         const int q = (mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3;
         qdirs[q].push_back(d);
     }
-    // A chunk = (quadrant, block of NW directions, block of 4K groups): wave w
-    // of a workgroup sweeps direction w of the block, its channel c the groups
-    // 4k + c of the group block.  Slots past the quadrant's directions or past
-    // G are inactive (-1, -1).
-    int maxD = 0;
-    for (int q = 0; q < 4; ++q) maxD = std::max(maxD, (int)qdirs[q].size());
-    int K = x->user_K ? x->user_K : 1;
-    if (x->fp32 == false) K = 1;
-    int NW = x->user_NW;
+    // A chunk = (quadrant, direction, block of 4 K NW groups): wave w of a
+    // workgroup sweeps groups 4K w .. 4K w + 4K - 1 of the block, its channel
+    // c the groups 4k + c of that range.  Slots past G are inactive (-1, -1).
+    int K = x->user_K, NW = x->user_NW;
+    if (!K) K = (x->fp32 && x->G >= 8) ? 2 : 1;
+    if (!x->fp32) K = std::min(K, 2);
     if (!NW) {
-        // fewest direction blocks of at most 8 waves, balanced (more waves per
-        // workgroup share its CU's SIMDs and slow every step of the band)
-        const int cap = 8;
-        const int nblk = (maxD + cap - 1) / cap;
-        NW = std::max(1, (maxD + nblk - 1) / nblk);
+        // the fewest waves (at most 8) that cover every group of a direction
+        const int need = (x->G + 4 * K - 1) / (4 * K);
+        NW = 1;
+        while (NW < need && NW < 8) NW *= 2;
     }
     x->NW = NW;
     x->K = K;
@@ -199,20 +197,21 @@ static void plan_sweep(smrt_ctx *x) {
     require((int64_t)CHANNELS * K * x->nbands * x->NT * BAND_ROWS * 4 * x->rs < (int64_t(1) << 31),
             "mesh too large for the sweep's 31-bit per-wave offsets");
     x->qc_quad.clear();
+    x->qc_dir.clear();
     x->slot_pair.clear();
-    const int GB = 4 * K;
+    const int GB = 4 * K * NW;
     const int ngb = (x->G + GB - 1) / GB;
     for (int q = 0; q < 4; ++q) {
         const int nd = (int)qdirs[q].size();
-        const int ndb = (nd + NW - 1) / NW;
-        for (int db = 0; db < ndb; ++db)
+        for (int dq = 0; dq < nd; ++dq)
             for (int gb = 0; gb < ngb; ++gb) {
                 x->qc_quad.push_back(q);
+                x->qc_dir.push_back(qdirs[q][dq]);
                 for (int w = 0; w < NW; ++w)
                     for (int c = 0; c < CHANNELS; ++c)
                         for (int k = 0; k < K; ++k) {
-                            const int dq = db * NW + w, g = gb * GB + CHANNELS * k + c;
-                            const bool on = dq < nd && g < x->G;
+                            const int g = gb * GB + w * CHANNELS * K + CHANNELS * k + c;
+                            const bool on = g < x->G;
                             x->slot_pair.push_back(on ? qdirs[q][dq] : -1);
                             x->slot_pair.push_back(on ? g : -1);
                         }
@@ -224,6 +223,8 @@ static void plan_sweep(smrt_ctx *x) {
     for (int q = 1; q <= 4; ++q) x->chunks.start[q] = std::max(x->chunks.start[q], x->chunks.start[q - 1]);
     x->n_wg = x->NQC * x->nbands;
     x->d_qc_quad.alloc(x->NQC);
+    x->d_qc_dir.alloc(x->NQC);
+    SMRT_HIP(hipMemcpy(x->d_qc_dir.p, x->qc_dir.data(), sizeof(int) * x->NQC, hipMemcpyHostToDevice));
     x->d_slot_pair.alloc((int64_t)x->slot_pair.size());
     SMRT_HIP(hipMemcpy(x->d_qc_quad.p, x->qc_quad.data(), sizeof(int) * x->NQC, hipMemcpyHostToDevice));
     SMRT_HIP(hipMemcpy(x->d_slot_pair.p, x->slot_pair.data(), sizeof(int) * x->slot_pair.size(), hipMemcpyHostToDevice));
@@ -233,6 +234,7 @@ static void plan_sweep(smrt_ctx *x) {
     SMRT_HIP(hipMemset(x->d_trace.p, 0, sizeof(uint64_t) * x->d_trace.n));
     x->d_ctr.alloc(4);
     hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, x->stream, x->d_ctr.p);
+    // band-major task list: a band is claimed only after every band below it
     std::vector<int2> tasks(x->n_wg);
     for (int t = 0; t < x->n_wg; ++t) tasks[t] = make_int2(0, t);
     x->d_tasks.alloc(x->n_wg);
@@ -264,8 +266,8 @@ static Sweep2DArgs sweep_args(const smrt_ctx *x, const void *psi_prev, void *psi
 }
 
 static void finalize_moments(smrt_ctx *x, double *mom) {
-    if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, x->d_sigq.p, mom);
-    else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, x->d_sigq.p, mom);
+    if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const float *)x->d_part.p, x->d_sigq.p, mom);
+    else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const double *)x->d_part.p, x->d_sigq.p, mom);
 }
 
 static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const void *sig2, const void *qiso,
@@ -323,8 +325,13 @@ static void raise_sweep_flag(smrt_ctx *x) {
     hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, x->stream, x->d_ctr.p);
     SMRT_HIP(hipMemsetAsync(x->d_trace.p, 0, sizeof(uint64_t) * x->d_trace.n, x->stream));
     SMRT_HIP(hipStreamSynchronize(x->stream));
+    const int bits = x->h_ctr[3];
     x->h_ctr[3] = 0;
-    throw smrt::Error(SMRT_E_DEVICE, "sweep band-trace wait exceeded its bound");
+    std::string which;
+    if (bits & WAIT_START_GATE) which += " (band start)";
+    if (bits & WAIT_TRACE) which += " (band trace)";
+    if (bits & WAIT_RING) which += " (workgroup ring)";
+    throw smrt::Error(SMRT_E_DEVICE, "sweep band-trace wait exceeded its bound" + which);
 }
 
 static void check_sweep_flag(smrt_ctx *x) {
@@ -585,6 +592,8 @@ extern "C" smrt_status smrt_create(const smrt_mesh_desc *mesh, const smrt_quad_d
         to_real(hx, p->d_hx);
         to_real(hy, p->d_hy);
         to_real(dirs, p->d_dirs);
+        p->d_dirs64.alloc((int64_t)dirs.size());
+        SMRT_HIP(hipMemcpy(p->d_dirs64.p, dirs.data(), 8 * dirs.size(), hipMemcpyHostToDevice));
         to_real(mw, p->d_mu_w);
         p->d_dir_quad.alloc(p->nang);
         SMRT_HIP(hipMemcpy(p->d_dir_quad.p, dq.data(), sizeof(int) * p->nang, hipMemcpyHostToDevice));
@@ -691,10 +700,11 @@ extern "C" smrt_status smrt_set_boundary(smrt_ctx *x, const smrt_boundary_desc *
 extern "C" smrt_status smrt_set_launch(smrt_ctx *x, int waves_per_group, int pairs_per_lane) {
     if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
     return guard(x, [&] {
-        require(waves_per_group >= 0 && waves_per_group <= MAX_SWEEP_WAVES, "waves per group must be in [0, 12]");
-        require(pairs_per_lane == 0 || pairs_per_lane == 1 || (pairs_per_lane == 2 && x->fp32),
-                "pairs per lane must be 0 (auto), 1, or 2 (FP32 only)");
-        require(!(pairs_per_lane == 2 && waves_per_group > 8), "2 groups per lane allow at most 8 waves per group");
+        require(waves_per_group == 0 || waves_per_group == 1 || waves_per_group == 2 || waves_per_group == 4 ||
+                    waves_per_group == 8,
+                "waves per group must be 0 (auto), 1, 2, 4 or 8");
+        require(pairs_per_lane == 0 || pairs_per_lane == 1 || pairs_per_lane == 2 || (pairs_per_lane == 4 && x->fp32),
+                "pairs per lane must be 0 (auto), 1, 2, or 4 (FP32 only)");
         SMRT_HIP(hipStreamSynchronize(x->stream));
         x->user_NW = waves_per_group;
         x->user_K = pairs_per_lane;
@@ -1194,8 +1204,7 @@ extern "C" smrt_status smrt_sweep_resident(smrt_ctx *x, double dt, int n_times, 
             run_sweep(x, pin, pout, x->d_sig2.p, x->d_qiso.p, x->d_inflow.p, icdt, x->d_sig.p, x->d_mom.p, false);
             SMRT_HIP(hipEventRecord(evp[k].e1, x->stream));
             if (x->dim == 2) {
-                if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, (const float *)x->d_part.p, x->d_sigq.p, x->d_mom.p);
-                else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, (const double *)x->d_part.p, x->d_sigq.p, x->d_mom.p);
+                finalize_moments(x, x->d_mom.p);
             } else {
                 if (x->fp32) run_moments1d<float>(x->stream, x->nx, x->G, x->nang, (const float *)x->d_mu_w.p, x->d_sig.p, (const float *)pout, x->d_mom.p);
                 else run_moments1d<double>(x->stream, x->nx, x->G, x->nang, (const double *)x->d_mu_w.p, x->d_sig.p, (const double *)pout, x->d_mom.p);
@@ -1234,25 +1243,20 @@ extern "C" smrt_status smrt_get_moments(smrt_ctx *x, double *moments) {
 // (waves per workgroup, groups per lane) on the context's current state and
 // keep the fastest.
 // ---------------------------------------------------------------------------
-static std::vector<std::pair<int, int>> launch_candidates(bool fp32, int max_dirs_per_quadrant) {
+static std::vector<std::pair<int, int>> launch_candidates(bool fp32, int G) {
+    // (waves per workgroup, groups per lane): every shape whose workgroup
+    // covers at most twice the groups a direction has (beyond that only idle
+    // waves are added)
     std::vector<std::pair<int, int>> c;
-    for (int k = 1; k <= (fp32 ? 2 : 1); ++k)
-        for (int nw = 1; nw <= (k == 1 ? MAX_SWEEP_WAVES : 8); ++nw) {
-            if (nw > max_dirs_per_quadrant) break;          // only idle waves beyond this
-            const int blocks = (max_dirs_per_quadrant + nw - 1) / nw;
-            if (blocks * nw - max_dirs_per_quadrant >= blocks) continue;   // an idle wave in every block
+    for (int k : {1, 2, 4}) {
+        if (k == 4 && !fp32) break;
+        for (int nw : {1, 2, 4, 8}) {
+            const int gb = 4 * k * nw;
+            if (gb > 4 && gb >= 2 * std::max(G, 4)) break;
             c.emplace_back(nw, k);
         }
-    return c;
-}
-
-static int max_dirs_per_quadrant(const smrt_ctx *x) {
-    int cnt[4] = {0, 0, 0, 0};
-    for (int d = 0; d < x->nang; ++d) {
-        const double mu = x->om[3 * d], eta = x->om[3 * d + 1];
-        cnt[(mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3]++;
     }
-    return *std::max_element(cnt, cnt + 4);
+    return c;
 }
 
 extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_group, int *pairs_per_lane, double *ms_best) {
@@ -1267,7 +1271,7 @@ extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_grou
         float best = 1e30f;
         int bnw = 0, bk = 0;
         int bo = 0;
-        for (auto [nw, k] : launch_candidates(x->fp32, max_dirs_per_quadrant(x))) {
+        for (auto [nw, k] : launch_candidates(x->fp32, x->G)) {
             SMRT_HIP(hipStreamSynchronize(x->stream));
             x->user_NW = nw;
             x->user_K = k;
@@ -1479,9 +1483,10 @@ extern "C" smrt_status smrt_batch_set_launch(smrt_batch *b, int waves_per_group,
     if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
     return bguard(b, [&] {
         BatchStreams on(b);
-        require(waves_per_group >= 1 && waves_per_group <= MAX_SWEEP_WAVES, "waves per group must be in [1, 12]");
-        require(pairs_per_lane == 1 || (pairs_per_lane == 2 && b->fp32 && waves_per_group <= 8),
-                "pairs per lane must be 1, or 2 (FP32, at most 8 waves)");
+        require(waves_per_group == 1 || waves_per_group == 2 || waves_per_group == 4 || waves_per_group == 8,
+                "waves per group must be 1, 2, 4 or 8");
+        require(pairs_per_lane == 1 || pairs_per_lane == 2 || (pairs_per_lane == 4 && b->fp32),
+                "pairs per lane must be 1, 2, or 4 (FP32 only)");
         batch_plan(b, waves_per_group, pairs_per_lane);
     });
 }
@@ -1588,13 +1593,13 @@ extern "C" smrt_status smrt_batch_autotune(smrt_batch *b, double dt, int *waves_
     return bguard(b, [&] {
         BatchStreams on(b);
         require(dt > 0.0, "dt must be > 0");
-        int maxd = 0;
-        for (const smrt_ctx *x : b->P) maxd = std::max(maxd, max_dirs_per_quadrant(x));
+        int maxg = 0;
+        for (const smrt_ctx *x : b->P) maxg = std::max(maxg, x->G);
         float best = 1e30f;
         int bnw = b->NW, bk = b->K;
         const std::vector<int> all = all_problems(b);
         int bo = 0;
-        for (auto [nw, k] : launch_candidates(b->fp32, maxd)) {
+        for (auto [nw, k] : launch_candidates(b->fp32, maxg)) {
             batch_plan(b, nw, k);
             std::vector<double> icdt;
             batch_tables(b, dt, icdt);

@@ -14,11 +14,14 @@ namespace smrt {
 constexpr int BAND_ROWS = 16;       // rows of cells per band (lanes per channel)
 constexpr int CHANNELS = 4;         // (angle, group) channels per wave (64 / BAND_ROWS)
 constexpr int NMOM2D = 9;           // per node per quadrant: 6 quadrant sums + 3 sigma-weighted
-constexpr int PART_PER_CELL = 4 * NMOM2D;   // partial moments per cell per chunk
+constexpr int PART_PER_CELL = 4 * 2;         // per cell per chunk: sum_g I and sum_g sigma_g I of 4 nodes
 constexpr int SPIN_LIMIT = 1 << 20;          // bounded wait on a band trace
+// bits of a sweep's error flag: which bounded wait ran out
+constexpr int WAIT_START_GATE = 1;           // a band waiting for the band below to start
+constexpr int WAIT_TRACE = 2;                // a row-0 lane waiting for the band below's trace
+constexpr int WAIT_RING = 4;                 // a wave waiting for its workgroup's ring slot
 constexpr int TRACE_LAG = 8;                 // columns a band stays behind the band below
 constexpr int LDS_PER_CU = 160 * 1024;       // gfx950 LDS per compute unit (bytes)
-constexpr int MAX_SWEEP_WAVES = 12;         // sweep workgroups: at most 12 waves (one direction each)
 
 #define SMRT_HIP(call)                                                                   \
     do {                                                                                 \
@@ -41,7 +44,7 @@ struct ChunkRanges {
 // Device-side description of one 2D sweep (one problem).
 struct Sweep2DArgs {
     int nx, ny, G, nbands, NT;       // NT = nx + BAND_ROWS - 1 steps per band
-    int NW, K, R, NQC;               // waves/WG, pairs/lane, pairs/chunk, (quadrant,chunk) count
+    int NW, K, R, NQC;               // waves/WG (group blocks of one direction), pairs/lane, pairs/chunk, chunk count
     int n_wg;                        // workgroups of this launch (NQC * nbands)
     int NB;                          // boundary face nodes
     const int *qc_quad;              // [NQC] quadrant of each chunk
@@ -54,15 +57,16 @@ struct Sweep2DArgs {
     void *psi_out;                   // internal layout
     const void *inflow;              // real [d][G][NB]
     double inv_c_dt;
-    void *part;                      // real [NQC][nbands][NT][16][36]
-    uint64_t *trace;                 // [NQC][nbands][R][nx][2 * words]
+    void *part;                      // real2 [NQC][nbands][NT][4 nodes][16 rows]: (sum_g I, sum_g sigma_g I)
+    uint64_t *trace;                 // [NQC][nbands][slot = (wave, k, channel)][nx][2 values][words]
     int *ctr;                        // [4]: (unused), workgroups done, epoch, error flag
 };
 
 // One sweep launch: one problem (args by value) or a batch of problems
 // (device array), and the launch's task list.  A task is (problem, band *
-// NQC + chunk); the list is ordered so that every band comes after the band
-// below it of the same problem and chunk (deadlock-free at any residency).
+// NQC + chunk); the list is band-major, so a workgroup that claims a ticket
+// only ever waits on tasks claimed before it by running workgroups:
+// deadlock-free at any residency.
 struct SweepLaunch {
     Sweep2DArgs single;              // used when probs == nullptr
     const Sweep2DArgs *probs;        // [n_probs] device array (batch) or nullptr
@@ -70,7 +74,7 @@ struct SweepLaunch {
     int n_tasks;
     int NW, K;                       // launch shape shared by every problem
     int wg_per_cu;                   // 0: as many as fit; n: pad LDS so at most n workgroups share a CU
-    int *lctr;                       // [2]: ticket, tasks done (reset by the last workgroup)
+    int *lctr;                       // [2]: ticket, workgroups done (both reset by the last workgroup)
     int fixup;                       // 1: zero-and-scale negative-flux fixup in every cell
 };
 

@@ -189,12 +189,6 @@ __device__ __forceinline__ Sweep2DArgs load_uniform_args(const Sweep2DArgs *p) {
     return a;
 }
 
-// entries per node block of the moment-reduction buffer (9 moments x NW waves
-// x 16 rows, padded to 16 mod 64)
-constexpr int red_node_block(int nw) {
-    return NMOM2D * nw * BAND_ROWS + (((BAND_ROWS - NMOM2D * nw * BAND_ROWS) % 64) + 64) % 64;
-}
-
 template <typename real, int K>
 struct StepIn {
     // raw loaded values only: any reordering happens at use, so the loads of
@@ -273,17 +267,36 @@ __device__ __forceinline__ void zero_and_scale(real &I0, real &I1, real &I2, rea
     }
 }
 
+__device__ __forceinline__ void bstore_pair(float a, float b, rsrc_t r, uint32_t vo, uint32_t so) {
+    using u2 = __attribute__((ext_vector_type(2))) unsigned int;
+    u2 w;
+    w[0] = __float_as_uint(a); w[1] = __float_as_uint(b);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, vo, so, 0);
+}
+__device__ __forceinline__ void bstore_pair(double a, double b, rsrc_t r, uint32_t vo, uint32_t so) {
+    using u4 = __attribute__((ext_vector_type(4))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, make_double2(a, b)), r, vo, so, 0);
+}
+
+// LDS ring through which the NW waves of a workgroup (the group blocks of one
+// direction) combine their per-node group sums: RING steps deep, one slot
+// per step holding every wave's two sums per lane, an arrival count and a
+// consumed count per slot.
+constexpr int RING = 8;
+template <typename real, int NW>
+constexpr size_t ring_bytes() {
+    return NW > 1 ? (size_t)RING * NW * 64 * 2 * sizeof(real) + 2 * RING * sizeof(unsigned) : 0;
+}
+
+// One workgroup = one task (problem, band, chunk): a chunk is one direction
+// of a quadrant and a block of 4*K*NW groups; wave w sweeps groups
+// 4K w .. 4K w + 4K - 1 of the block (channel c, pair k -> group 4k + c).
 template <typename real, int K, int PF, int NW, bool BATCH, bool FIX>
 __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     using r2 = typename vec2<real>::type;
     using r4 = typename vec4<real>::type;
     constexpr int TW = trace_words<real>::n;
-    // LDS reduction buffer: [buffer][node c][moment j][wave][row]; node blocks
-    // padded to 16 (mod 64) entries so the 4 channels of a wave hit disjoint banks
-    constexpr int CB = red_node_block(NW);
-    constexpr int BUF = 4 * CB;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    real *red = reinterpret_cast<real *>(smem_raw);
     __shared__ int s_prob, s_task, s_epoch;
 
     const int lane = threadIdx.x & 63;
@@ -298,6 +311,13 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
         s_task = tk.y;
         int *pc = BATCH ? L.probs[tk.x].ctr : L.single.ctr;
         s_epoch = __hip_atomic_load(&pc[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the ring's counters start at zero
+    r2 *ring = reinterpret_cast<r2 *>(smem_raw);
+    unsigned *arrived = reinterpret_cast<unsigned *>(smem_raw + (size_t)RING * NW * 64 * sizeof(r2));
+    unsigned *consumed = arrived + RING;
+    if constexpr (NW > 1) {
+        if (threadIdx.x < 2 * RING) arrived[threadIdx.x] = 0;
     }
     __syncthreads();
     const int prob = __builtin_amdgcn_readfirstlane(s_prob);
@@ -325,20 +345,16 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     r4 *pout = static_cast<r4 *>(A.psi_out);
     const real *inflow = static_cast<const real *>(A.inflow);
 
-    // the wave's direction (uniform); slot (wv, ch, k) -> group
+    // the chunk's direction (slot 0 of wave 0 is always active); this wave's
+    // first group, or -1 when the block has no group for it
+    const int d = __builtin_amdgcn_readfirstlane(A.slot_pair[qc * A.R].x);
     const int2 pg0 = A.slot_pair[qc * A.R + wv * CHANNELS * K];
-    const int dw = __builtin_amdgcn_readfirstlane(pg0.x);
-    const bool wave_on = dw >= 0;
-    const int d = wave_on ? dw : 0;
+    const bool wave_on = __builtin_amdgcn_readfirstlane(pg0.x) >= 0;
     const real *dr = dirs + 8 * d;
     const real am = fabs(dr[0]), bm = fabs(dr[1]);
-    real cw[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) cw[m] = wave_on ? dr[2 + m] : real(0);   // an idle wave adds zeros
-    // the workgroup's group block starts at gb0; lane group = gb0 + gl[k]
     const int gb0 = wave_on ? __builtin_amdgcn_readfirstlane(pg0.y) : 0;
     bool act[K];
-    int gl[K];                    // group within the block (0 for an inactive slot)
+    int gl[K];                    // group within the wave's block (0 for an inactive slot)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int slot = (wv * CHANNELS + ch) * K + k;
@@ -353,7 +369,8 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     // boundary side bases in the general inflow array [d][g][NB]
     const int xside = fx ? 2 * ny : 0;                 // canonical x- side
     const int yside = 4 * ny + (fy ? 2 * nx : 0);      // canonical y- side
-    const int traces_per_band = A.R * nx * 2 * TW;
+    // band trace words of a (chunk, band): [slot (wave, k, channel)][column][2 values][TW]
+    const int64_t traces_per_band = (int64_t)A.R * nx * 2 * TW;
     uint64_t *trace_in = A.trace + ((int64_t)qc * nbands + (band > 0 ? band - 1 : 0)) * traces_per_band;
     uint64_t *trace_out = A.trace + ((int64_t)qc * nbands + band) * traces_per_band;
     const bool produce = (r == BAND_ROWS - 1) && (band + 1 < nbands);
@@ -370,22 +387,27 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     const rsrc_t rs_sig = make_rsrc(sig2 + tbase, span * sizeof(r2));
     const rsrc_t rs_q = make_rsrc(qiso + tbase, span * sizeof(r4));
     const rsrc_t rs_inf = make_rsrc(inflow + ((int64_t)d * G + gb0) * A.NB, (uint64_t)CHANNELS * K * A.NB * sizeof(real));
-    const uint64_t wave_trace_bytes = (uint64_t)CHANNELS * K * nx * 2 * TW * sizeof(uint64_t);
-    const rsrc_t rs_tr = make_rsrc(trace_in + (int64_t)wvu * CHANNELS * K * nx * 2 * TW, wave_trace_bytes);
-    const rsrc_t rs_tw = make_rsrc(trace_out + (int64_t)wvu * CHANNELS * K * nx * 2 * TW, wave_trace_bytes);
+    const uint64_t band_trace_bytes = (uint64_t)traces_per_band * sizeof(uint64_t);
+    const rsrc_t rs_tr = make_rsrc(trace_in, band_trace_bytes);
+    const rsrc_t rs_tw = make_rsrc(trace_out, band_trace_bytes);
+    // moment partials of the (chunk, band): [t][channel = node][row][2]
+    r2 *part_band = static_cast<r2 *>(A.part) + ((int64_t)qc * nbands + band) * NT * 64;
+    const rsrc_t rs_part = make_rsrc(part_band, (uint64_t)NT * 64 * sizeof(r2));
+    const uint32_t vo_part = (uint32_t)(lane * sizeof(r2));
     // lane byte offsets, OOB for a lane with no work (see make_rsrc)
     uint32_t vo4[K], vo2[K];   // cell gl * gslab + r in the 4-value and 2-value slabs
     uint32_t vo_inf[K], vo_tr[K], vo_tw[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const uint32_t cell = (uint32_t)(gl[k] * gslab + r);
-        const uint32_t slot_words = (uint32_t)((ch * K + k) * nx * 2 * TW * sizeof(uint64_t));
+        const uint32_t slot_bytes = (uint32_t)((((wv * K + k) * CHANNELS + ch) * nx * 2 * TW) * sizeof(uint64_t));
         vo4[k] = act[k] ? cell * (uint32_t)sizeof(r4) : OOB;
         vo2[k] = act[k] ? cell * (uint32_t)sizeof(r2) : OOB;
         vo_inf[k] = act[k] ? (uint32_t)((gl[k] * A.NB + yside) * sizeof(real)) : OOB;
-        vo_tr[k] = act[k] ? slot_words : OOB;
-        vo_tw[k] = act[k] && produce ? slot_words : OOB;
+        vo_tr[k] = act[k] ? slot_bytes : OOB;
+        vo_tw[k] = act[k] && produce ? slot_bytes : OOB;
     }
+    const uint32_t col_bytes = (uint32_t)(2 * TW * sizeof(uint64_t));   // one column of one slot
 
     // All prefetch loads are issued unconditionally (in bounds, or at the
     // out-of-range offset of a lane with no work, which reads zeros) into raw
@@ -401,7 +423,7 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
         // band trace words first (band > 0, row 0): every lane of a channel reads
         // the words its row-0 lane needs, so a wave touches one address per channel
 #pragma unroll
-        for (int k = 0; k < K; ++k) bload_words(S.tw[k], 2 * TW, rs_tr, vo_tr[k], (uint32_t)(c0 * 2 * TW * sizeof(uint64_t)));
+        for (int k = 0; k < K; ++k) bload_words(S.tw[k], 2 * TW, rs_tr, vo_tr[k], (uint32_t)c0 * col_bytes);
         S.hx0 = hxa[in0];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -440,6 +462,11 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     __builtin_amdgcn_s_waitcnt(0);
     int err = 0;
 
+    // word index of (column, this lane's slot k) in a band's trace block
+    auto trace_word = [&](int column, int k) -> int64_t {
+        return ((int64_t)((wv * K + k) * CHANNELS + ch) * nx + column) * 2 * TW;
+    };
+
     // Start gate: a band begins only once the band below has published the
     // trace of column TRACE_LAG, so that in steady state each prefetched
     // trace word was written several steps before it is needed.
@@ -447,7 +474,7 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
         const int gcol = TRACE_LAG < nx - 1 ? TRACE_LAG : nx - 1;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const uint64_t *g = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + gcol) * 2 * TW;
+            const uint64_t *g = trace_in + trace_word(gcol, k);
             bool waiting = (r == 0) && act[k];
             int spins = 0;
             while (waiting) {
@@ -455,10 +482,13 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
 #pragma unroll
                 for (int u2 = 0; u2 < 2 * TW; ++u2) rd &= (uint32_t)(poll_word(g + u2) >> 32) == epoch;
                 if (rd) break;
-                if (++spins > SPIN_LIMIT ||
-                    __hip_atomic_load(&A.ctr[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                if (++spins > SPIN_LIMIT) {
                     err = 1;
-                    atomicOr(&A.ctr[3], 1);
+                    atomicOr(&A.ctr[3], WAIT_START_GATE);
+                    break;
+                }
+                if (__hip_atomic_load(&A.ctr[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    err = 1;   // another wave timed out: give up at once
                     break;
                 }
                 __builtin_amdgcn_s_sleep(2);
@@ -466,7 +496,6 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
         }
     }
 
-    real *part_base = static_cast<real *>(A.part) + ((int64_t)qc * nbands + band) * NT * (BAND_ROWS * PART_PER_CELL);
     // rows 0 of active slots: the lanes that read the band below's trace
     uint64_t row0_mask[K];
 #pragma unroll
@@ -474,7 +503,7 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     // The step loop runs in whole groups of PF+1 steps with no per-step
     // condition (a conditional step or prefetch would merge register values
     // and force a wait on every outstanding load); padding steps t >= NT have
-    // no valid column, so they store nothing and write no partial.
+    // no valid column, so they store nothing.
     for (int t0 = 0; t0 < NT; t0 += PF + 1) {
 #pragma unroll
         for (int u = 0; u <= PF; ++u) {
@@ -500,16 +529,19 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                         for (int u2 = 0; u2 < 2 * TW; ++u2) ready &= (uint32_t)(tw[u2] >> 32) == epoch;
                         const uint64_t need = __builtin_amdgcn_ballot_w64(!ready) & row0_mask[k];
                         if (need != 0) {
-                            const uint64_t *src = trace_in + (((int64_t)(wv * CHANNELS + ch) * K + k) * nx + t) * 2 * TW;
+                            const uint64_t *src = trace_in + trace_word(t, k);
                             int spins = 0;
                             bool waiting = ((need >> lane) & 1) && !err;
                             while (waiting) {
                                 // bounded wait; a timed-out wave raises ctr[3] and every other
                                 // waiter gives up at once
-                                if (++spins > SPIN_LIMIT ||
-                                    __hip_atomic_load(&A.ctr[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                                if (++spins > SPIN_LIMIT) {
                                     err = 1;
-                                    atomicOr(&A.ctr[3], 1);
+                                    atomicOr(&A.ctr[3], WAIT_TRACE);
+                                    break;
+                                }
+                                if (__hip_atomic_load(&A.ctr[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                                    err = 1;
                                     break;
                                 }
                                 __builtin_amdgcn_s_sleep(1);
@@ -553,7 +585,7 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                     if constexpr (FIX) zero_and_scale(I0, I1, I2, I3, S.st[k] * wgt, a, b, (rh0 + rh1) + (rh2 + rh3));
                     // A cell outside the mesh (ic < 0 or ic >= nx, or a row past ny)
                     // is a padding slot of the skewed layout: its store lands
-                    // there and its moments are never read, so neither needs a
+                    // there and its sums are never read, so neither needs a
                     // per-lane test.  Padding steps (t >= NT) store nothing.
                     if (t < NT) {
                         r4 o;
@@ -562,18 +594,17 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                     }
                     // the top row publishes its column ic = t - 15 while it lies in the mesh
                     if (t >= BAND_ROWS - 1 && t < NT) {
-                        const uint32_t so = (uint32_t)((t - (BAND_ROWS - 1)) * 2 * TW * sizeof(uint64_t));
+                        const uint32_t so = (uint32_t)(t - (BAND_ROWS - 1)) * col_bytes;
                         put_trace_words(I2, epoch, rs_tw, vo_tw[k], so);
                         put_trace_words(I3, epoch, rs_tw, vo_tw[k], so + TW * (uint32_t)sizeof(uint64_t));
                     }
-                    const real i0 = I0, i1 = I1, i2 = I2, i3 = I3;
                     const real sg = S.sg[k];
                     if (k == 0) {
-                        sumI[0] = i0; sumI[1] = i1; sumI[2] = i2; sumI[3] = i3;
-                        sumS[0] = sg * i0; sumS[1] = sg * i1; sumS[2] = sg * i2; sumS[3] = sg * i3;
+                        sumI[0] = I0; sumI[1] = I1; sumI[2] = I2; sumI[3] = I3;
+                        sumS[0] = sg * I0; sumS[1] = sg * I1; sumS[2] = sg * I2; sumS[3] = sg * I3;
                     } else {
-                        sumI[0] += i0; sumI[1] += i1; sumI[2] += i2; sumI[3] += i3;
-                        sumS[0] += sg * i0; sumS[1] += sg * i1; sumS[2] += sg * i2; sumS[3] += sg * i3;
+                        sumI[0] += I0; sumI[1] += I1; sumI[2] += I2; sumI[3] += I3;
+                        sumS[0] += sg * I0; sumS[1] += sg * I1; sumS[2] += sg * I2; sumS[3] += sg * I3;
                     }
                     xl[k][0] = I1;
                     xl[k][1] = I3;
@@ -584,32 +615,57 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
                 // prefetch the step PF+1 ahead into the slot just consumed
                 load_step(t + PF + 1, buf[u]);
 
-                // channel sums; channel c then forms the 9 moments of canonical node c
+                // channel sums: channel c gets node c's sums over the wave's groups
                 const real nI = channel_scatter_sum<real>(sumI);
                 const real nS = channel_scatter_sum<real>(sumS);
-                real *rb = red + (t & 1) * BUF + ch * CB + wv * BAND_ROWS + r;
+                if (t < NT) {
+                    if constexpr (NW == 1) {
+                        bstore_pair(nI, nS, rs_part, vo_part, (uint32_t)(t * 64 * sizeof(r2)));
+                    } else {
+                        // Combine the workgroup's waves through the LDS ring: each
+                        // wave deposits its sums; the last to arrive at this step
+                        // adds them in wave order and stores the partial.
+                        const int slot = t & (RING - 1);
+                        const unsigned round = (unsigned)(t / RING);
+                        if (round > 0 && !err) {
+                            // the slot's previous step must have been consumed
+                            int spins = 0;
+                            while (__hip_atomic_load(&consumed[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) <
+                                   round) {
+                                if (++spins > SPIN_LIMIT) {
+                                    err = 1;
+                                    atomicOr(&A.ctr[3], WAIT_RING);
+                                    break;
+                                }
+                                if (__hip_atomic_load(&A.ctr[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                                    err = 1;
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(1);
+                            }
+                        }
+                        r2 mine;
+                        mine.x = nI;
+                        mine.y = nS;
+                        ring[(slot * NW + wvu) * 64 + lane] = mine;
+                        unsigned prev = 0;
+                        if (lane == 0)
+                            prev = __hip_atomic_fetch_add(&arrived[slot], 1u, __ATOMIC_ACQ_REL,
+                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                        prev = __builtin_amdgcn_readfirstlane(prev);
+                        if (prev == round * NW + (NW - 1)) {
+                            real sI = 0, sS = 0;   // fixed order over the waves
 #pragma unroll
-                for (int j = 0; j < 6; ++j) rb[j * NW * BAND_ROWS] = cw[j] * nI;
-#pragma unroll
-                for (int j = 0; j < 3; ++j) rb[(6 + j) * NW * BAND_ROWS] = cw[j] * nS;
-                __syncthreads();
-                // one partial per cell of this step: [t][node*9 + moment][row]
-                const real *rr_base = red + (t & 1) * BUF;
-                real *part = part_base + (int64_t)t * (BAND_ROWS * PART_PER_CELL);
-#pragma unroll
-                for (int o0 = 0; o0 < BAND_ROWS * PART_PER_CELL; o0 += NW * 64) {
-                    const int o = o0 + threadIdx.x;
-                    // 576 outputs = 9 whole waves: the test is uniform per wave
-                    if (o0 + wvu * 64 < BAND_ROWS * PART_PER_CELL) {
-                        const int rr = o & (BAND_ROWS - 1);
-                        const int lm = o >> 4;                  // node*9 + moment
-                        const int l = lm / NMOM2D, j = lm - l * NMOM2D;
-                        const real *src = rr_base + l * CB + j * NW * BAND_ROWS + rr;
-                        real s = 0;   // fixed order over the waves
-#pragma unroll
-                        for (int w2 = 0; w2 < NW; ++w2) s += src[w2 * BAND_ROWS];
-                        // cells outside the mesh reduce to exact zeros: no per-lane test
-                        if (t < NT) part[o] = s;
+                            for (int w2 = 0; w2 < NW; ++w2) {
+                                const r2 v = ring[(slot * NW + w2) * 64 + lane];
+                                sI += v.x;
+                                sS += v.y;
+                            }
+                            bstore_pair(sI, sS, rs_part, vo_part, (uint32_t)(t * 64 * sizeof(r2)));
+                            if (lane == 0)
+                                __hip_atomic_fetch_add(&consumed[slot], 1u, __ATOMIC_RELEASE,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
                     }
                 }
             }
@@ -635,13 +691,19 @@ __global__ void __launch_bounds__(NW * 64) sweep2d_kernel(SweepLaunch L) {
     }
 }
 
+// prefetch depth: PF + 1 steps of loads in flight (fewer when K pairs per
+// lane make a step's loads larger)
+template <typename real, int K>
+constexpr int prefetch_depth() {
+    return sizeof(real) == 4 ? (K == 1 ? 4 : K == 2 ? 3 : 1) : (K == 1 ? 2 : 1);
+}
+
 template <typename real, int K, int NW, bool BATCH, bool FIX>
 static void launch_knwbf(const SweepLaunch &L, hipStream_t s) {
-    constexpr int PF = sizeof(real) == 4 ? (K == 1 ? 4 : 2) : 1;
-    constexpr int CB = red_node_block(NW);
-    // LDS: the reduction buffer, or more when the launch asks for fewer
-    // workgroups per CU (a workgroup alone on a CU runs each step faster)
-    size_t lds = (size_t)2 * 4 * CB * sizeof(real);
+    constexpr int PF = prefetch_depth<real, K>();
+    // LDS: the wave ring, or more when the launch asks for fewer workgroups
+    // per CU (a workgroup alone on a CU runs each step faster)
+    size_t lds = ring_bytes<real, NW>();
     if (L.wg_per_cu > 0) lds = std::max(lds, (size_t)(LDS_PER_CU / L.wg_per_cu - 1024));
     static bool lds_attr_set = false;   // once per instantiation (so a launch can be graph-captured)
     if (!lds_attr_set) {
@@ -665,26 +727,11 @@ static void launch_knw(const SweepLaunch &L, hipStream_t s) {
 template <typename real, int K>
 static void launch_k(const SweepLaunch &L, hipStream_t s) {
     switch (L.NW) {
-        case 1: launch_knw<real, K, 1>(L, s); break;
-        case 2: launch_knw<real, K, 2>(L, s); break;
-        case 3: launch_knw<real, K, 3>(L, s); break;
-        case 4: launch_knw<real, K, 4>(L, s); break;
-        case 5: launch_knw<real, K, 5>(L, s); break;
-        case 6: launch_knw<real, K, 6>(L, s); break;
-        case 7: launch_knw<real, K, 7>(L, s); break;
-        case 8: launch_knw<real, K, 8>(L, s); break;
-        default:
-            // more than 8 waves only with one group per lane (two would spill)
-            if constexpr (K == 1) {
-                switch (L.NW) {
-                    case 9: launch_knw<real, K, 9>(L, s); return;
-                    case 10: launch_knw<real, K, 10>(L, s); return;
-                    case 11: launch_knw<real, K, 11>(L, s); return;
-                    case 12: launch_knw<real, K, 12>(L, s); return;
-                    default: break;
-                }
-            }
-            throw Error(SMRT_E_INVALID_ARG, "waves per workgroup must be in [1, 12] (in [1, 8] with 2 groups per lane)");
+        case 1: launch_knw<real, K, 1>(L, s); return;
+        case 2: launch_knw<real, K, 2>(L, s); return;
+        case 4: launch_knw<real, K, 4>(L, s); return;
+        case 8: launch_knw<real, K, 8>(L, s); return;
+        default: throw Error(SMRT_E_INVALID_ARG, "waves per workgroup must be 1, 2, 4 or 8");
     }
 }
 
@@ -692,10 +739,11 @@ template <typename real>
 void launch_sweep2d(const SweepLaunch &L, hipStream_t s) {
     if (L.n_tasks <= 0) return;
     if (L.K == 1) { launch_k<real, 1>(L, s); SMRT_HIP(hipGetLastError()); return; }
+    if (L.K == 2) { launch_k<real, 2>(L, s); SMRT_HIP(hipGetLastError()); return; }
     if constexpr (sizeof(real) == 4) {
-        if (L.K == 2) { launch_k<real, 2>(L, s); SMRT_HIP(hipGetLastError()); return; }
+        if (L.K == 4) { launch_k<real, 4>(L, s); SMRT_HIP(hipGetLastError()); return; }
     }
-    throw Error(SMRT_E_INVALID_ARG, "pairs per lane must be 1 (FP64) or 1, 2 (FP32)");
+    throw Error(SMRT_E_INVALID_ARG, "pairs per lane must be 1, 2 (FP64) or 1, 2, 4 (FP32)");
 }
 
 template void launch_sweep2d<float>(const SweepLaunch &, hipStream_t);

@@ -89,8 +89,9 @@ template <typename real>
 void run_psi_from_internal(hipStream_t s, int nx, int ny, int G, int nang, const int *dq, const real *in, double *abi);
 template <typename real>
 // sigq: scratch of 12 * n_nodes doubles (per-quadrant sigma-weighted moments)
-void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const real *part, double *sigq,
-                          double *mom);
+// qc_dir: direction of each chunk; dirs: FP64 per-direction table (mu, eta, w, w mu, w eta, w mu^2, w mu eta, w eta^2)
+void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const int *qc_dir, const double *dirs,
+                          const real *part, double *sigq, double *mom);
 template <typename real>
 void run_moments1d(hipStream_t s, int nx, int G, int nang, const real *mw, const double *sig, const real *psi, double *mom);
 void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *om, const double *w, double c,

@@ -791,17 +791,23 @@ __global__ void k_add_scalar(int64_t n, const double *a, double v, double *out) 
 
 // ---------------------------------------------------------------------------
 // Moment finalisation (2D), deterministic (fixed summation order).
-// Partials: [chunk][band][step t][canonical node lc * 9 + moment][row], the
-// cell of (t, row) being canonical column t - row; chunks are grouped by
-// quadrant.  Pass 1 works in each quadrant's own skewed coordinates (thread =
-// (quadrant, band, step, canonical node, row), so the 16 rows of a wave read
-// contiguous partials), sums the quadrant's chunks in FP64 and writes the 6
-// angular moments of that quadrant into mom and the 3 sigma-weighted ones into
-// a per-quadrant buffer; pass 2 sums those over the 4 quadrants.
+// Partials: [chunk][band][step t][canonical node lc][row] pairs (sum_g I,
+// sum_g sigma_g I) over the chunk's groups, the cell of (t, row) being
+// canonical column t - row; a chunk is one direction and chunks are grouped by
+// quadrant.  The angular weights enter here, in FP64:
+//   quadrant moments  sum_{d in q} w_d {1, mu, eta, mu^2, mu eta, eta^2}_d S_I,
+//   sigma-weighted    sum_d w_d {1, mu, eta}_d S_sigma.
+// Pass 1 works in each quadrant's own skewed coordinates (thread = (quadrant,
+// band, step, canonical node, row), so the 16 rows of a wave read contiguous
+// partials), sums the quadrant's chunks in FP64 in chunk order and writes the
+// 6 angular moments of that quadrant into mom and its 3 sigma-weighted ones
+// into a per-quadrant buffer; pass 2 sums those over the 4 quadrants.
 // ---------------------------------------------------------------------------
 template <typename real>
-__global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkRanges cr, const real *part,
-                                                          double *mom, double *sigq) {
+__global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkRanges cr, const int *qc_dir,
+                                                          const double *dirs, const real *part, double *mom,
+                                                          double *sigq) {
+    using r2 = typename std::conditional<sizeof(real) == 4, float2, double2>::type;
     const int nb = (ny + BAND_ROWS - 1) / BAND_ROWS, NT = nx + BAND_ROWS - 1;
     const int ntb = (NT + 3) / 4;
     int b = blockIdx.x;
@@ -812,14 +818,18 @@ __global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkR
     const int t = tb * 4 + (threadIdx.x >> 6);
     const int ic = t - rc, jc = band * BAND_ROWS + rc;
     if (t >= NT || ic < 0 || ic >= nx || jc >= ny) return;
-    constexpr int PB = BAND_ROWS * PART_PER_CELL;   // partial entries per step
     double acc[NMOM2D];
 #pragma unroll
     for (int k = 0; k < NMOM2D; ++k) acc[k] = 0.0;
+    const r2 *pp = reinterpret_cast<const r2 *>(part);
     for (int qc = cr.start[q]; qc < cr.start[q + 1]; ++qc) {
-        const real *p = part + (((int64_t)qc * nb + band) * NT + t) * PB + lc * NMOM2D * BAND_ROWS + rc;
+        const r2 v = pp[(((int64_t)qc * nb + band) * NT + t) * 64 + lc * BAND_ROWS + rc];
+        const double *cw = dirs + 8 * qc_dir[qc] + 2;   // w, w mu, w eta, w mu^2, w mu eta, w eta^2
+        const double sI = (double)v.x, sS = (double)v.y;
 #pragma unroll
-        for (int k = 0; k < NMOM2D; ++k) acc[k] += (double)p[k * BAND_ROWS];
+        for (int k = 0; k < 6; ++k) acc[k] += cw[k] * sI;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[6 + k] += cw[k] * sS;
     }
     const bool fx = (q == 1 || q == 2), fy = (q == 2 || q == 3);
     const int i = fx ? nx - 1 - ic : ic, j = fy ? ny - 1 - jc : jc;
@@ -1107,11 +1117,11 @@ void run_copy_from(hipStream_t s, int64_t n, const real *src, double *dst) {
     hipLaunchKernelGGL(k_copy_from<real>, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
 }
 template <typename real>
-void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const real *part, double *sigq,
-                          double *mom) {
+void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const int *qc_dir, const double *dirs,
+                          const real *part, double *sigq, double *mom) {
     const int nb = (ny + BAND_ROWS - 1) / BAND_ROWS, NT = nx + BAND_ROWS - 1;
-    hipLaunchKernelGGL(k_moments_quadrant<real>, dim3(4 * nb * ((NT + 3) / 4)), dim3(256), 0, s, nx, ny, cr, part, mom,
-                       sigq);
+    hipLaunchKernelGGL(k_moments_quadrant<real>, dim3(4 * nb * ((NT + 3) / 4)), dim3(256), 0, s, nx, ny, cr, qc_dir,
+                       dirs, part, mom, sigq);
     const int64_t nn = (int64_t)nx * ny * 4;
     hipLaunchKernelGGL(k_moments_sigma, dim3(nblk(nn, 256)), dim3(256), 0, s, nn, (const double *)sigq, mom);
 }
@@ -1147,8 +1157,8 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
     template void run_sig_to_internal<real>(hipStream_t, int, int, const double *, const double *, real *);         \
     template void run_psi_to_internal<real>(hipStream_t, int, int, int, int, const int *, const double *, real *);  \
     template void run_psi_from_internal<real>(hipStream_t, int, int, int, int, const int *, const real *, double *); \
-    template void run_moments_finalize<real>(hipStream_t, int, int, const ChunkRanges &, const real *, double *,   \
-                                              double *);                                                        \
+    template void run_moments_finalize<real>(hipStream_t, int, int, const ChunkRanges &, const int *,              \
+                                              const double *, const real *, double *, double *);                                                        \
     template void launch_sweep1d<real>(const Sweep1DArgs &, hipStream_t);                                           \
     template void run_moments1d<real>(hipStream_t, int, int, int, const real *, const double *, const real *, double *);
 INST(float)

@@ -172,7 +172,7 @@ def test_full_batch_matches_single_problem_launches(smrt_mod):
     print("full batch:", len(ps), "problems", flush=True)
     cs = _contexts(smrt_mod, ps, 1)
     b = smrt_mod.Batch(cs)
-    b.set_launch(4, 2)
+    b.set_launch(2, 2)
     b.sweep_resident(ps[0].dt, n_times=1)
     sizes = [p.nx * p.ny * p.n_angles * p.G for p in ps]
     picks = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), len(ps) // 2})
@@ -180,7 +180,7 @@ def test_full_batch_matches_single_problem_launches(smrt_mod):
         print("problem", ps[i].name, flush=True)
         single = smrt_mod.Context(ps[i], precision=1)
         single.set_state(ps[i].initial_T_nodes())
-        single.set_launch(4, 2)
+        single.set_launch(2, 2)
         single.sweep_resident(ps[i].dt, n_times=1)
         assert _rel(cs[i].get_moments(), single.get_moments()) < 1e-6, ps[i].name
         single.close()

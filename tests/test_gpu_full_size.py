@@ -38,12 +38,11 @@ def _quadrant(mu, eta):
 def test_full_size_sweep_sampled_groups_and_moments(smrt_mod, oracle_mod, prec, tol, mtol):
     p = W.multigroup_2d()
     assert (p.nx, p.ny, p.n_angles, p.G) == (256, 256, 40, 16)
-    print(f"full size: 256x256 S8 G16, precision {prec}, launch (5 waves, 1 group per lane)", flush=True)
+    print(f"full size: 256x256 S8 G16, precision {prec}, the benchmark's launch", flush=True)
     sigt, q, pp, inf = W.random_sweep_inputs(p, seed=2024)
     sig = 0.8 * sigt
     icdt = 1.0 / (p.c * p.dt)
     ctx = smrt_mod.Context(p, precision=prec)
-    ctx.set_launch(5, 1)
     psi, mom = ctx.sweep(sigt, sig, q, pp, icdt, inf)
     ctx.close()
 

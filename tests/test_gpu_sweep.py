@@ -58,7 +58,7 @@ def test_sweep2d_fp64_matches_oracle(smrt_mod, oracle_mod, nx, ny, sn, G):
 
 
 @pytest.mark.parametrize("nx,ny,sn,G", [(37, 35, 4, 3), (20, 33, 8, 4), (64, 48, 8, 2)])
-@pytest.mark.parametrize("launch", [(0, 1), (0, 2), (2, 1), (8, 2), (10, 1), (12, 1)])
+@pytest.mark.parametrize("launch", [(0, 0), (1, 1), (2, 1), (1, 2), (2, 2), (1, 4), (8, 1), (4, 4)])
 def test_sweep2d_fp32_matches_oracle(smrt_mod, oracle_mod, nx, ny, sn, G, launch):
     p = _prob2d(nx, ny, sn, G, seed=3)
     print(f"shape nx={nx} ny={ny} S{sn} G={G} launch={launch}", flush=True)
@@ -81,8 +81,8 @@ def test_sweep2d_fp32_matches_oracle(smrt_mod, oracle_mod, nx, ny, sn, G, launch
 
 def test_sweep2d_inactive_slots_large(smrt_mod, oracle_mod):
     """Regression: chunks with inactive (angle, group) slots (8 waves x 2 pairs
-    = 64 slots for 40 pairs per quadrant) at a size where a negative slot
-    index would leave the inflow buffer."""
+    = 64 group slots for 4 groups) at a size where a negative slot index would
+    leave the inflow buffer."""
     p = _prob2d(96, 80, 8, 4, seed=8)
     sigt, q, pp, inf = W.random_sweep_inputs(p, seed=21)
     ref = oracle_mod.Oracle(p).sweep(sigt, q, pp, 0.5, inf)
@@ -116,9 +116,9 @@ def test_sweep2d_launch_shapes_agree_fp64(smrt_mod, oracle_mod):
     sigt, q, pp, inf = W.random_sweep_inputs(p, seed=9)
     ref = oracle_mod.Oracle(p).sweep(sigt, q, pp, 0.3, inf)
     ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64)
-    for nw in (1, 3, 8, 12):
-        print(f"waves per group {nw}", flush=True)
-        ctx.set_launch(nw, 1)
+    for nw, k in ((1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (2, 2)):
+        print(f"waves per group {nw}, groups per lane {k}", flush=True)
+        ctx.set_launch(nw, k)
         psi, _ = ctx.sweep(sigt, sigt * 0.5, q, pp, 0.3, inf)
         assert _rel(psi, ref) < 1e-10
     ctx.close()

@@ -1,0 +1,196 @@
+"""CPU check of the 2D sweep kernel's indexing (no GPU).
+
+The sweep kernel addresses its arrays through wave-uniform bases plus per-lane
+and per-step byte offsets; a lane with no work gets an offset at or past 2^31,
+which the hardware turns into a dropped access.  This module restates the
+planner's chunk and slot layout and the kernel's index arithmetic (task ->
+chunk, band; wave -> direction, groups; lane -> channel, row; step -> column)
+and checks, for every launch shape (waves per workgroup 1, 2, 4, 8; groups
+per lane 1, 2, 4; FP32 and FP64), on regular, ragged and degenerate meshes:
+
+* every access of a lane with work lies inside its allocation and inside
+  the buffer resource it goes through, with a byte offset below 2^31;
+* every lane without work is marked out of range;
+* the trace words a band publishes are exactly the words the band above
+  reads, and each (column, slot) word is written once;
+* each moment partial of a (chunk, band, step) is stored by one lane, and the
+  finalisation reads only partials of cells inside the mesh.
+
+It is run before kernel changes go to a GPU.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2504_21784_amd import workloads as W
+
+BAND_ROWS, CHANNELS, OOB = 16, 4, 1 << 31
+TRACE_LAG = 8
+
+
+def quadrant_dirs(omega):
+    q = []
+    for d, (mu, eta, _) in enumerate(omega):
+        q.append(0 if (mu > 0 and eta > 0) else 1 if (mu < 0 and eta > 0) else 2 if (mu < 0 and eta < 0) else 3)
+    return [[d for d in range(len(q)) if q[d] == k] for k in range(4)]
+
+
+def plan(nx, ny, G, omega, NW, K):
+    """Chunks (quadrant, direction, block of 4 K NW groups) and their slots
+    (wave w, channel c, pair k) -> (direction, group) or (-1, -1)."""
+    qd = quadrant_dirs(omega)
+    GB = 4 * K * NW
+    ngb = (G + GB - 1) // GB
+    qc_quad, qc_dir, slots = [], [], []
+    for q in range(4):
+        for d in qd[q]:
+            for gb in range(ngb):
+                qc_quad.append(q)
+                qc_dir.append(d)
+                s = []
+                for w in range(NW):
+                    for c in range(CHANNELS):
+                        for k in range(K):
+                            g = gb * GB + w * CHANNELS * K + CHANNELS * k + c
+                            s.append((d, g) if g < G else (-1, -1))
+                slots.append(s)
+    nbands = (ny + BAND_ROWS - 1) // BAND_ROWS
+    return dict(qc_quad=qc_quad, qc_dir=qc_dir, slots=slots, NQC=len(qc_quad), R=4 * NW * K, nbands=nbands,
+                NT=nx + BAND_ROWS - 1)
+
+
+def check_shape(nx, ny, G, sn, NW, K, rs):
+    omega, _ = W.level_symmetric_2d(sn)
+    nang = len(omega)
+    P = plan(nx, ny, G, omega, NW, K)
+    NQC, R, nb, NT = P["NQC"], P["R"], P["nbands"], P["NT"]
+    TW = rs // 4
+    NB = 4 * (nx + ny)
+    gslab = nb * NT * BAND_ROWS
+    # allocations (elements of the unit each array is addressed in)
+    n_psi = nang * G * gslab            # r4 records
+    n_tab = 4 * G * gslab               # r2 / r4 records of the per-quadrant tables
+    n_inf = nang * G * NB               # reals
+    slot_words = nx * 2 * TW            # one slot's words in a band's trace block
+    n_trace = NQC * nb * R * slot_words
+    n_part = NQC * nb * NT * 64         # r2 records
+    assert CHANNELS * K * nb * NT * BAND_ROWS * 4 * rs < OOB, "planner would reject this mesh"
+    written = np.zeros(n_trace, np.int32)
+    read_words = np.zeros(n_trace, np.int32)
+    part_owner = np.zeros(n_part, np.int32)
+    lane = np.arange(64)
+    ch, r = lane >> 4, lane & 15
+    t = np.arange(NT)
+    for qc in range(NQC):
+        quad = P["qc_quad"][qc]
+        fx, fy = quad in (1, 2), quad in (2, 3)
+        slots = P["slots"][qc]
+        d = slots[0][0]
+        assert d >= 0, "slot 0 of a chunk must be active"
+        assert 0 <= 8 * d and 8 * d + 7 < 8 * nang
+        for band in range(nb):
+            jc = band * BAND_ROWS + r
+            row_ok = jc < ny
+            jn = np.where(fy, ny - 1 - jc, jc)
+            assert np.all(jn[row_ok] >= 0) and np.all(jn[row_ok] < ny)
+            produce = (r == BAND_ROWS - 1) & (band + 1 < nb)
+            tin_base = (qc * nb + (band - 1 if band > 0 else 0)) * R * slot_words
+            tout_base = (qc * nb + band) * R * slot_words
+            part_base = (qc * nb + band) * NT * 64
+            for w in range(NW):
+                pg0 = slots[w * CHANNELS * K]
+                wave_on = pg0[0] >= 0
+                gb0 = pg0[1] if wave_on else 0
+                pbase = ((d * G + gb0) * nb + band) * NT * BAND_ROWS
+                tbase = (quad * G + gb0) * gslab + band * NT * BAND_ROWS
+                span = CHANNELS * K * gslab
+                for k in range(K):
+                    slot_idx = (w * CHANNELS + ch) * K + k
+                    assert np.all(slot_idx < R)
+                    pg = [slots[i] for i in slot_idx]
+                    act = np.array([p[0] >= 0 for p in pg]) & row_ok
+                    gl = np.array([p[1] - gb0 if p[1] >= 0 else 0 for p in pg])
+                    g = gb0 + gl
+                    assert np.all(g[act] < G) and np.all(gl[act] < CHANNELS * K) and np.all(gl[act] >= 0)
+                    cell = gl * gslab + r
+                    vo4 = np.where(act, cell * 4 * rs, OOB)
+                    assert np.all(vo4[act] < OOB) and np.all(vo4[~act] >= OOB)
+                    # intensity and tables over every step (loads clamp t to NT-1)
+                    so = t * BAND_ROWS * 4 * rs
+                    off = vo4[act][:, None] + so[None, :]
+                    assert off.size == 0 or (off.max() < OOB and off.max() + 4 * rs <= span * 4 * rs)
+                    el = pbase + (off // (4 * rs))
+                    assert el.size == 0 or (el.min() >= 0 and el.max() < n_psi)
+                    el = tbase + (off // (4 * rs))
+                    assert el.size == 0 or (el.min() >= 0 and el.max() < n_tab)
+                    # boundary inflow (y- side at row 0's column, x- side per row)
+                    yside = 4 * ny + (2 * nx if fy else 0)
+                    xside = 2 * ny if fx else 0
+                    c0 = np.minimum(t, nx - 1)
+                    in0 = np.where(fx, nx - 1 - c0, c0)
+                    inf_off = (gl[act][:, None] * NB + yside + 2 * in0[None, :])
+                    el = (d * G + gb0) * NB + inf_off
+                    assert el.size == 0 or (el.max() + 1 < n_inf and inf_off.max() + 1 < CHANNELS * K * NB)
+                    jv = np.where(row_ok, jn, 0)
+                    ib = (d * G + gb0 + gl) * NB
+                    el = ib[act] + xside + 2 * jv[act] + 1
+                    assert el.size == 0 or el.max() < n_inf
+                    # trace words: this lane's slot row of a band's block
+                    slot = ((w * K + k) * CHANNELS + ch)
+                    assert np.all(slot < R)
+                    if band > 0:
+                        rd = act & (r == 0)
+                        for c in range(nx):
+                            for sl in slot[rd]:
+                                o = tin_base + (sl * nx + c) * 2 * TW
+                                read_words[o: o + 2 * TW] += 1
+                        gcol = min(TRACE_LAG, nx - 1)
+                        assert tin_base + ((R - 1) * nx + gcol) * 2 * TW + 2 * TW <= n_trace
+                    pr = act & produce
+                    for tt in range(BAND_ROWS - 1, NT):
+                        col = tt - (BAND_ROWS - 1)
+                        assert 0 <= col < nx
+                        for sl in slot[pr]:
+                            o = tout_base + (sl * nx + col) * 2 * TW
+                            written[o: o + 2 * TW] += 1
+                # moment partial: one store per lane and step (NW = 1: this wave;
+                # NW > 1: the last wave to reach the step, once per step)
+                if w == 0:
+                    idx = part_base + t[:, None] * 64 + lane[None, :]
+                    assert idx.max() < n_part
+                    part_owner[idx.ravel()] += 1
+    # every word the band above reads was published by the band below, once;
+    # words nobody reads are those of the top band's chunks (never written)
+    assert np.all(written <= 1), "a trace word is written twice"
+    assert np.all(written[read_words > 0] == 1), "a band reads a trace word nobody writes"
+    assert np.all(part_owner == 1), "each moment partial has one owner"
+    # the finalisation reads (chunk, band, t, node, row) for cells inside the mesh
+    for band in range(nb):
+        for tt in range(NT):
+            rc = np.arange(16)
+            ic, jc = tt - rc, band * BAND_ROWS + rc
+            ok = (ic >= 0) & (ic < nx) & (jc < ny)
+            assert np.all(((NQC - 1) * nb + band) * NT * 64 + tt * 64 + 3 * 16 + rc[ok] < n_part)
+
+
+SHAPES = [(1, 1), (9, 1), (1, 20), (37, 35), (16, 16), (17, 33), (64, 48)]
+LAUNCH = [(nw, k) for nw, k in itertools.product((1, 2, 4, 8), (1, 2, 4))]
+
+
+@pytest.mark.parametrize("nx,ny", SHAPES)
+@pytest.mark.parametrize("nw,k", LAUNCH)
+@pytest.mark.parametrize("rs", [4, 8])
+def test_sweep_indexing_in_bounds(nx, ny, nw, k, rs):
+    if rs == 8 and k == 4:
+        pytest.skip("four groups per lane is an FP32 shape only")
+    for G, sn in ((1, 4), (5, 4), (16, 8), (33, 4)):
+        if 4 * k * nw > 2 * max(G, 4) and (nw, k) != (1, 1):
+            continue
+        check_shape(nx, ny, G, sn, nw, k, rs)
+
+
+def test_sweep_indexing_benchmark_size():
+    """The benchmark's 256^2, S8, 16-group sweep in its default FP32 shapes."""
+    for nw, k in ((2, 2), (1, 4), (4, 1)):
+        check_shape(256, 256, 16, 8, nw, k, 4)
