@@ -34,7 +34,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 LO_GRAPHS = 1   # --lo-graphs: 1 replays the LO conjugate-gradient blocks as HIP graphs (the library default)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep2d_fp32_256x256_S8_G16_hbm_bytes.md")
-SWEEP_SOURCES = [os.path.join(ROOT, "paper_2504_21784_amd", "csrc", f) for f in ("sweep2d.hip", "smrt_internal.h")]
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2504_21784_amd", "csrc", f)
+                 for f in ("sweep2d.inc", "sweep2d_f32.hip", "smrt_internal.h")]
 
 
 def measured_traffic(info):
@@ -51,10 +52,23 @@ def measured_traffic(info):
                 if l.startswith(("traffic_bytes_per_launch:", "source_sha256:", "launch:")))
     if vals.get("source_sha256", "").strip() != h:
         return None
-    shape = f"waves_per_group={info['waves_per_group']} pairs_per_lane={info['pairs_per_lane']}"
+    shape = (f"waves_per_band={info['waves_per_band']} bands_per_group={info['bands_per_group']} "
+             f"pairs_per_lane={info['pairs_per_lane']}")
     if vals.get("launch", "").strip() != shape:
         return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+def sweep_kernel_name(info):
+    """The FP32 sweep kernel instance a launch shape runs (its template
+    arguments: pairs per lane, prefetch depth, waves per band, bands per
+    workgroup, fixup), as the profiler names it."""
+    k, nw, nb = info["pairs_per_lane"], info["waves_per_band"], info["bands_per_group"]
+    if nw * nb >= 16:
+        prefetch = 3 if k == 1 else 1
+    else:
+        prefetch = {1: 4, 2: 3, 4: 1}[k]
+    return f"sweep2d_kernel<float, {k}, {prefetch}, {nw}, {nb}, false>"
 
 
 def cpu_baseline(p, sample_groups=16):
@@ -105,7 +119,7 @@ def batched(args):
     b = smrt.Batch(ctxs)
     setup_s = _t.perf_counter() - t0
     dt = ps[0].dt
-    nw, k, tune_ms = b.autotune(dt)
+    nw, nb, k, tune_ms = b.autotune(dt)
     info = b.info()
     b.sweep_resident(dt, n_times=1, capture_graph=False)
     ms, ks = b.sweep_resident(dt, n_times=max(3, args.steps // 4), capture_graph=True)
@@ -114,7 +128,7 @@ def batched(args):
     res = {"workload": "32 independent 2D problems (seed 5): n in {64,...,384}, G in {4,8,16,32}, "
                        "level-symmetric S4/S8/S12, power-law region opacities (seed 5000+i), dt=1e-3, FP32",
            "units_per_sweep": units, "n_tasks": info["n_tasks"],
-           "launch": {"waves_per_group": nw, "pairs_per_lane": k}, "autotuned_sweep_ms": tune_ms,
+           "launch": {"waves_per_band": nw, "bands_per_group": nb, "pairs_per_lane": k}, "autotuned_sweep_ms": tune_ms,
            "sweep_ms": ks, "sweep_units_per_s": units / (ks * 1e-3),
            "sweep_hbm_frac": alg / (ks * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "graph_pass_ms": ms, "graph_pass_units_per_s": units / (ms * 1e-3), "setup_s": setup_s}
@@ -257,7 +271,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--waves", type=int, default=0, help="sweep waves per workgroup (0 = automatic)")
+    ap.add_argument("--waves", type=int, default=0, help="sweep waves per band (0 = automatic)")
+    ap.add_argument("--bands", type=int, default=0, help="sweep bands per workgroup (0 = automatic)")
     ap.add_argument("--pairs", type=int, default=0, help="(angle,group) pairs per lane (0 = automatic)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 32-problem batched-sweep measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient measurement")
@@ -288,8 +303,8 @@ def main():
 
     def make(prec, T=T0, psi=None):
         ctx = smrt.Context(p, precision=prec, stream=stream, lo_graphs=LO_GRAPHS)
-        if args.waves or args.pairs:
-            ctx.set_launch(args.waves, args.pairs if prec == smrt.SMRT_FP32 else min(args.pairs, 2))
+        if args.waves or args.bands or args.pairs:
+            ctx.set_launch(args.waves, args.bands, args.pairs if prec == smrt.SMRT_FP32 else min(args.pairs, 2))
         ctx.set_state(T, psi)
         return ctx
 
@@ -330,9 +345,7 @@ def main():
     step32 = (ctx.get_moments(), ctx.get_state(with_psi=False)["T"])
     alg_bytes = info["algorithmic_bytes_per_sweep"]
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    prefetch = {1: 4, 2: 3, 4: 1}[info['pairs_per_lane']]   # the kernel's prefetch depth per groups-per-lane
-    sweep_kernel = f"sweep2d_kernel<float, {info['pairs_per_lane']}, {prefetch}, " \
-                   f"{info['waves_per_group']}, false, false>"
+    sweep_kernel = sweep_kernel_name(info)
     ctx.close()
 
     # the same sweep with the zero-and-scale negative-flux fixup compiled in
@@ -396,7 +409,7 @@ def main():
         "config": {"workload": "multigroup_2d: 256x256 bilinear DG, level-symmetric S8 (40 angles), 16 groups, "
                                "power-law region opacities (seed 3), dt=1e-3; step = opacity + sources + FP32 sweep "
                                "with fused moments + moment finalisation + SM closures",
-                   "units_per_sweep": units, "launch": {k: info[k] for k in ("band_rows", "waves_per_group",
+                   "units_per_sweep": units, "launch": {k: info[k] for k in ("band_rows", "waves_per_band", "bands_per_group",
                                                                              "pairs_per_lane", "pairs_per_chunk",
                                                                              "n_chunks", "n_workgroups")}},
         "sweep_kernel_ms": k_ms,

@@ -321,15 +321,21 @@ typedef struct {
     int dim, nx, ny, n_angles, G, n_nodes, n_cells;
     int64_t units_per_sweep;
     int64_t algorithmic_bytes_per_sweep;   /* read I* + write I, at the sweep precision */
-    int band_rows, waves_per_group, pairs_per_lane, pairs_per_chunk, n_chunks, n_workgroups;
+    int band_rows, waves_per_band, pairs_per_lane, pairs_per_chunk, n_chunks, n_workgroups;
+    int bands_per_group;
 } smrt_info;
 smrt_status smrt_get_info(const smrt_ctx *ctx, smrt_info *info);
 
-/* Sweep launch configuration override (0 = automatic): waves per
- * workgroup in [0, 12] (each wave sweeps one direction of a quadrant) and
- * groups per lane in {0, 1, 2} (2: FP32 only, with at most 8 waves).
+/* Sweep launch configuration override (2D; 0 = automatic per field).  A
+ * sweep workgroup sweeps one direction and a block of groups on a group of
+ * consecutive bands of 16 rows: waves_per_band in {0, 1, 2, 4} waves share
+ * a band (4 pairs_per_lane groups each), bands_per_group in {0, 1, 2, 4,
+ * 8, 16} bands run in lockstep in one workgroup (the band hand-off goes
+ * through LDS), at most 16 waves in all; pairs_per_lane in {0, 1, 2, 4}
+ * (4: FP32 only).  Automatic: one wave per band, one group per lane, and
+ * the fewest bands (a power of two) that cover the mesh within 16 waves.
  * Returns SMRT_E_INVALID_ARG outside these ranges. */
-smrt_status smrt_set_launch(smrt_ctx *ctx, int waves_per_group, int pairs_per_lane);
+smrt_status smrt_set_launch(smrt_ctx *ctx, int waves_per_band, int bands_per_group, int pairs_per_lane);
 
 /* Sweep occupancy (2D): at most workgroups_per_cu sweep workgroups share a
  * compute unit (the launch pads its LDS request accordingly); 0 = as many as
@@ -337,20 +343,22 @@ smrt_status smrt_set_launch(smrt_ctx *ctx, int waves_per_group, int pairs_per_la
 smrt_status smrt_set_occupancy(smrt_ctx *ctx, int workgroups_per_cu);
 
 /* Launch-shape autotuner (2D): on the context's current state with time step
- * dt, times one sweep for every candidate (waves per workgroup, groups per
- * lane) that leaves no workgroup with an idle wave in every direction block,
- * each at occupancy 0, 1 and 2 workgroups per CU, applies the fastest and
- * returns its shape with its sweep time in ms (any output pointer may be
- * NULL).  The state is not advanced.  Errors:
- * SMRT_E_INVALID_ARG before smrt_set_state, for 1D, or for dt <= 0. */
-smrt_status smrt_autotune(smrt_ctx *ctx, double dt, int *waves_per_group, int *pairs_per_lane, double *ms_best);
+ * dt, times one sweep for every candidate (waves per band, bands per
+ * workgroup, groups per lane) whose chunk covers less than twice the groups
+ * and whose workgroup less than twice the bands of the problem, each at
+ * occupancy 0, 1 and 2 workgroups per CU, applies the fastest and returns its
+ * shape with its sweep time in ms (any output pointer may be NULL).  The
+ * state is not advanced.  Errors: SMRT_E_INVALID_ARG before smrt_set_state,
+ * for 1D, or for dt <= 0. */
+smrt_status smrt_autotune(smrt_ctx *ctx, double dt, int *waves_per_band, int *bands_per_group, int *pairs_per_lane,
+                          double *ms_best);
 
 /* ---- Batches: many independent 2D problems swept in one launch ---------
  * A batch borrows n contexts (all 2D, one precision, each with a state) and
- * sweeps every (problem, quadrant, direction block, group block,
- * band) task of all of them in one persistent launch, in an order where
- * every band follows the band below it of the same problem (no deadlock at
- * any residency) and the longest bands start first.  The contexts stay
+ * sweeps every (problem, chunk, band group) task of all of them in one
+ * launch, in an order where every band group follows the group below it of
+ * the same problem (no deadlock at any residency) and the longest bands
+ * start first.  The contexts stay
  * owned by the caller and must outlive the batch; the batch re-plans their
  * sweep launch shape (one shape for the whole batch).  A batch call drains
  * every problem's stream, works on the batch's own stream and drains it
@@ -360,19 +368,19 @@ typedef struct smrt_batch smrt_batch;
 smrt_status smrt_batch_create(int n, smrt_ctx *const *problems, smrt_batch **out);
 void smrt_batch_destroy(smrt_batch *batch);
 const char *smrt_batch_last_error(const smrt_batch *batch);
-/* Launch shape shared by the batch (waves in [1, 12]; groups per lane 1, or
- * 2 in FP32 with at most 8 waves). */
-smrt_status smrt_batch_set_launch(smrt_batch *batch, int waves_per_group, int pairs_per_lane);
+/* Launch shape shared by the batch (as smrt_set_launch, every field given:
+ * no automatic value). */
+smrt_status smrt_batch_set_launch(smrt_batch *batch, int waves_per_band, int bands_per_group, int pairs_per_lane);
 /* Occupancy of the batched sweep (as smrt_set_occupancy). */
 smrt_status smrt_batch_set_occupancy(smrt_batch *batch, int workgroups_per_cu);
 /* Total units per batched sweep, workgroup tasks, and the launch shape. */
-smrt_status smrt_batch_info(const smrt_batch *batch, int64_t *units_per_sweep, int *n_tasks, int *waves_per_group,
-                            int *pairs_per_lane);
+smrt_status smrt_batch_info(const smrt_batch *batch, int64_t *units_per_sweep, int *n_tasks, int *waves_per_band,
+                            int *bands_per_group, int *pairs_per_lane);
 /* Batch autotuner: times the batched sweep for every candidate launch shape
  * on the problems' current states with time step dt, applies and returns the
  * fastest (ms of one batched sweep). */
-smrt_status smrt_batch_autotune(smrt_batch *batch, double dt, int *waves_per_group, int *pairs_per_lane,
-                                double *ms_best);
+smrt_status smrt_batch_autotune(smrt_batch *batch, double dt, int *waves_per_band, int *bands_per_group,
+                                int *pairs_per_lane, double *ms_best);
 /* Resident high-order pass of every problem (as smrt_sweep_resident, with
  * all sweeps in one batched launch), n_times.  capture_graph != 0 records
  * the pass once as a HIP graph (kernels only) and replays it n_times.

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmrt.so")
-SOURCES = ["api.hip", "sweep2d.hip", "tables.hip", "lo.hip", "qmesh.hip"]
+SOURCES = ["api.hip", "sweep2d_f32.hip", "sweep2d_f64.hip", "tables.hip", "lo.hip", "qmesh.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]

@@ -43,15 +43,15 @@ struct smrt_ctx {
     DevBuf<double> d_bmom;        // [NB][3] incoming moments of the reflective sides' inflow
     DevBuf<unsigned char> d_hx, d_hy, d_dirs, d_mu_w;
     // sweep plan
-    int NW = 0, K = 1, R = 0, NQC = 0, nbands = 0, NT = 0, n_wg = 0;
-    int user_NW = 0, user_K = 0, wg_per_cu = 0;
+    int NW = 0, NBW = 1, K = 1, R = 0, NQC = 0, nbands = 0, NT = 0, n_bgroups = 0, n_wg = 0;
+    int user_NW = 0, user_NBW = 0, user_K = 0, wg_per_cu = 0;
     std::vector<int> qc_quad;
     std::vector<int> slot_pair;   // pairs (d, g)
     ChunkRanges chunks{};         // chunk range of each quadrant
     DevBuf<int> d_qc_quad, d_qc_dir, d_slot_pair, d_ctr, d_lctr;
     DevBuf<double> d_dirs64;      // per direction, FP64: mu, eta, w, w mu, w eta, w mu^2, w mu eta, w eta^2
     std::vector<int> qc_dir;      // direction of each chunk
-    DevBuf<int2> d_tasks;         // single-problem task list (0, band * NQC + chunk)
+    DevBuf<int2> d_tasks;         // single-problem task list (0, band group * NQC + chunk)
     DevBuf<unsigned char> d_psi[2], d_part, d_qiso, d_sig2, d_inflow;
     DevBuf<uint64_t> d_trace;
     int cur = 0;
@@ -167,6 +167,10 @@ static int nblk(int64_t n, int b = 256) { return (int)((n + b - 1) / b); }
 // ---------------------------------------------------------------------------
 // launch plan of the 2D sweep
 // ---------------------------------------------------------------------------
+// waves a sweep workgroup may have: a wave's registers bound it (16 bytes of
+// intensity per lane and node take twice the registers)
+static int max_waves(bool fp32, int k) { return (fp32 ? 4 : 8) * k >= 16 ? 8 : 16; }
+
 static void plan_sweep(smrt_ctx *x) {
     if (x->dim != 2) return;
     std::vector<std::vector<int>> qdirs(4);
@@ -175,23 +179,24 @@ static void plan_sweep(smrt_ctx *x) {
         const int q = (mu > 0 && eta > 0) ? 0 : (mu < 0 && eta > 0) ? 1 : (mu < 0 && eta < 0) ? 2 : 3;
         qdirs[q].push_back(d);
     }
-    // A chunk = (quadrant, direction, block of 4 K NW groups): wave w of a
-    // workgroup sweeps groups 4K w .. 4K w + 4K - 1 of the block, its channel
-    // c the groups 4k + c of that range.  Slots past G are inactive (-1, -1).
-    int K = x->user_K, NW = x->user_NW;
-    if (!K) K = (x->fp32 && x->G >= 8) ? 2 : 1;
-    if (!x->fp32) K = std::min(K, 2);
-    if (!NW) {
-        // the fewest waves (at most 8) that cover every group of a direction
-        const int need = (x->G + 4 * K - 1) / (4 * K);
-        NW = 1;
-        while (NW < need && NW < 8) NW *= 2;
+    // A chunk = (quadrant, direction, block of 4 K NW groups): group block w
+    // of a band sweeps groups 4K w .. 4K w + 4K - 1 of the chunk's block, its
+    // channel c the groups 4k + c of that range.  Slots past G are inactive
+    // (-1, -1).  A workgroup sweeps one chunk on NBW consecutive bands.
+    int K = x->user_K ? x->user_K : 1, NW = x->user_NW ? x->user_NW : 1;
+    x->nbands = (x->ny + BAND_ROWS - 1) / BAND_ROWS;
+    int NBW = x->user_NBW;
+    if (!NBW) {
+        // the fewest bands (a power of two) that cover the mesh, within 16 waves
+        NBW = 1;
+        while (NBW < x->nbands && NW * NBW < max_waves(x->fp32, K)) NBW *= 2;
     }
     x->NW = NW;
+    x->NBW = NBW;
     x->K = K;
     x->R = 4 * NW * K;
-    x->nbands = (x->ny + BAND_ROWS - 1) / BAND_ROWS;
     x->NT = x->nx + BAND_ROWS - 1;
+    x->n_bgroups = (x->nbands + NBW - 1) / NBW;
     // a sweep wave addresses its 4K group slabs through 32-bit byte offsets
     // below 2^31 (offsets from 2^31 up mark lanes with no work)
     require((int64_t)CHANNELS * K * x->nbands * x->NT * BAND_ROWS * 4 * x->rs < (int64_t(1) << 31),
@@ -221,7 +226,7 @@ static void plan_sweep(smrt_ctx *x) {
     for (int q = 0; q <= 4; ++q) x->chunks.start[q] = 0;
     for (int qc = 0; qc < x->NQC; ++qc) x->chunks.start[x->qc_quad[qc] + 1] = qc + 1;
     for (int q = 1; q <= 4; ++q) x->chunks.start[q] = std::max(x->chunks.start[q], x->chunks.start[q - 1]);
-    x->n_wg = x->NQC * x->nbands;
+    x->n_wg = x->NQC * x->n_bgroups;
     x->d_qc_quad.alloc(x->NQC);
     x->d_qc_dir.alloc(x->NQC);
     SMRT_HIP(hipMemcpy(x->d_qc_dir.p, x->qc_dir.data(), sizeof(int) * x->NQC, hipMemcpyHostToDevice));
@@ -234,7 +239,7 @@ static void plan_sweep(smrt_ctx *x) {
     SMRT_HIP(hipMemset(x->d_trace.p, 0, sizeof(uint64_t) * x->d_trace.n));
     x->d_ctr.alloc(4);
     hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, x->stream, x->d_ctr.p);
-    // band-major task list: a band is claimed only after every band below it
+    // band-group-major task list: a band group is claimed only after every group below it
     std::vector<int2> tasks(x->n_wg);
     for (int t = 0; t < x->n_wg; ++t) tasks[t] = make_int2(0, t);
     x->d_tasks.alloc(x->n_wg);
@@ -280,6 +285,7 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
         L.tasks = x->d_tasks.p;
         L.n_tasks = x->n_wg;
         L.NW = x->NW;
+        L.NBW = x->NBW;
         L.K = x->K;
         L.wg_per_cu = x->wg_per_cu;
         L.lctr = x->d_lctr.p;
@@ -330,7 +336,6 @@ static void raise_sweep_flag(smrt_ctx *x) {
     std::string which;
     if (bits & WAIT_START_GATE) which += " (band start)";
     if (bits & WAIT_TRACE) which += " (band trace)";
-    if (bits & WAIT_RING) which += " (workgroup ring)";
     throw smrt::Error(SMRT_E_DEVICE, "sweep band-trace wait exceeded its bound" + which);
 }
 
@@ -697,16 +702,25 @@ extern "C" smrt_status smrt_set_boundary(smrt_ctx *x, const smrt_boundary_desc *
     });
 }
 
-extern "C" smrt_status smrt_set_launch(smrt_ctx *x, int waves_per_group, int pairs_per_lane) {
+// a launch shape the sweep kernels are built for (0 = automatic per field)
+static void check_shape(bool fp32, int nw, int nbw, int k, bool allow_auto) {
+    const int lo = allow_auto ? 0 : 1;
+    require((nw >= lo && nw <= 2) || nw == 4, "waves per band must be 1, 2 or 4 (0: automatic)");
+    require((nbw >= lo && nbw <= 2) || nbw == 4 || nbw == 8 || nbw == 16,
+            "bands per workgroup must be 1, 2, 4, 8 or 16 (0: automatic)");
+    require((k >= lo && k <= 2) || (k == 4 && fp32), "pairs per lane must be 1, 2, or 4 (FP32 only) (0: automatic)");
+    require(std::max(nw, 1) * std::max(nbw, 1) <= 16, "a sweep workgroup has at most 16 waves (waves per band x bands)");
+    require(std::max(nw, 1) * std::max(nbw, 1) <= max_waves(fp32, std::max(k, 1)),
+            "with 16 bytes per lane and node (FP32 with four pairs per lane, FP64 with two) a sweep workgroup has at most 8 waves");
+}
+
+extern "C" smrt_status smrt_set_launch(smrt_ctx *x, int waves_per_band, int bands_per_group, int pairs_per_lane) {
     if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
     return guard(x, [&] {
-        require(waves_per_group == 0 || waves_per_group == 1 || waves_per_group == 2 || waves_per_group == 4 ||
-                    waves_per_group == 8,
-                "waves per group must be 0 (auto), 1, 2, 4 or 8");
-        require(pairs_per_lane == 0 || pairs_per_lane == 1 || pairs_per_lane == 2 || (pairs_per_lane == 4 && x->fp32),
-                "pairs per lane must be 0 (auto), 1, 2, or 4 (FP32 only)");
+        check_shape(x->fp32, waves_per_band, bands_per_group, pairs_per_lane, true);
         SMRT_HIP(hipStreamSynchronize(x->stream));
-        x->user_NW = waves_per_group;
+        x->user_NW = waves_per_band;
+        x->user_NBW = bands_per_group;
         x->user_K = pairs_per_lane;
         plan_sweep(x);
     });
@@ -726,8 +740,9 @@ extern "C" smrt_status smrt_get_info(const smrt_ctx *x, smrt_info *info) {
     info->n_nodes = x->nn; info->n_cells = x->ncell;
     info->units_per_sweep = (int64_t)x->ncell * x->nang * x->G;
     info->algorithmic_bytes_per_sweep = info->units_per_sweep * 2 * x->npc * (int64_t)x->rs;
-    info->band_rows = BAND_ROWS; info->waves_per_group = x->NW; info->pairs_per_lane = x->K;
+    info->band_rows = BAND_ROWS; info->waves_per_band = x->NW; info->pairs_per_lane = x->K;
     info->pairs_per_chunk = x->R; info->n_chunks = x->NQC; info->n_workgroups = x->n_wg;
+    info->bands_per_group = x->NBW;
     return SMRT_OK;
 }
 
@@ -1243,23 +1258,32 @@ extern "C" smrt_status smrt_get_moments(smrt_ctx *x, double *moments) {
 // (waves per workgroup, groups per lane) on the context's current state and
 // keep the fastest.
 // ---------------------------------------------------------------------------
-static std::vector<std::pair<int, int>> launch_candidates(bool fp32, int G) {
-    // (waves per workgroup, groups per lane): every shape whose workgroup
-    // covers at most twice the groups a direction has (beyond that only idle
-    // waves are added)
-    std::vector<std::pair<int, int>> c;
+struct Shape {
+    int nw, nbw, k;
+};
+static std::vector<Shape> launch_candidates(bool fp32, int G, int nbands) {
+    // (waves per band, bands per workgroup, groups per lane): every shape
+    // whose chunk covers at most twice the groups a direction has and whose
+    // workgroup covers at most twice the bands (beyond that only idle waves
+    // are added), within 16 waves
+    std::vector<Shape> c;
     for (int k : {1, 2, 4}) {
         if (k == 4 && !fp32) break;
-        for (int nw : {1, 2, 4, 8}) {
+        for (int nw : {1, 2, 4}) {
             const int gb = 4 * k * nw;
             if (gb > 4 && gb >= 2 * std::max(G, 4)) break;
-            c.emplace_back(nw, k);
+            for (int nbw : {1, 2, 4, 8, 16}) {
+                if (nw * nbw > max_waves(fp32, k)) break;
+                if (nbw > 1 && nbw >= 2 * nbands) break;
+                c.push_back({nw, nbw, k});
+            }
         }
     }
     return c;
 }
 
-extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_group, int *pairs_per_lane, double *ms_best) {
+extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_band, int *bands_per_group,
+                                     int *pairs_per_lane, double *ms_best) {
     if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
     return guard(x, [&] {
         require(x->dim == 2, "the launch shape applies to 2D sweeps");
@@ -1269,12 +1293,13 @@ extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_grou
         run_source_at(x, x->d_T.p);
         void *pin = x->d_psi[x->cur].p, *pout = x->d_psi[1 - x->cur].p;
         float best = 1e30f;
-        int bnw = 0, bk = 0;
+        Shape bs{1, 1, 1};
         int bo = 0;
-        for (auto [nw, k] : launch_candidates(x->fp32, x->G)) {
+        for (const Shape &c : launch_candidates(x->fp32, x->G, (x->ny + BAND_ROWS - 1) / BAND_ROWS)) {
             SMRT_HIP(hipStreamSynchronize(x->stream));
-            x->user_NW = nw;
-            x->user_K = k;
+            x->user_NW = c.nw;
+            x->user_NBW = c.nbw;
+            x->user_K = c.k;
             plan_sweep(x);
             for (int occ : {0, 1, 2}) {
                 x->wg_per_cu = occ;
@@ -1282,16 +1307,18 @@ extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_grou
                 once();   // warm-up
                 const float ms = std::min(timed(x->stream, once), timed(x->stream, once));
                 check_sweep_flag(x);
-                if (ms < best) { best = ms; bnw = nw; bk = k; bo = occ; }
+                if (ms < best) { best = ms; bs = c; bo = occ; }
             }
         }
         SMRT_HIP(hipStreamSynchronize(x->stream));
-        x->user_NW = bnw;
-        x->user_K = bk;
+        x->user_NW = bs.nw;
+        x->user_NBW = bs.nbw;
+        x->user_K = bs.k;
         x->wg_per_cu = bo;
         plan_sweep(x);
-        if (waves_per_group) *waves_per_group = bnw;
-        if (pairs_per_lane) *pairs_per_lane = bk;
+        if (waves_per_band) *waves_per_band = bs.nw;
+        if (bands_per_group) *bands_per_group = bs.nbw;
+        if (pairs_per_lane) *pairs_per_lane = bs.k;
         if (ms_best) *ms_best = best;
     });
 }
@@ -1304,7 +1331,7 @@ struct smrt_batch {
     std::vector<smrt_ctx *> P;
     hipStream_t stream = nullptr;   // the batch's own stream (default priority)
     bool fp32 = false;
-    int NW = 0, K = 1, wg_per_cu = 0;
+    int NW = 0, NBW = 1, K = 1, wg_per_cu = 0;
     DevBuf<Sweep2DArgs> d_args;
     DevBuf<int2> d_tasks;
     DevBuf<int> d_lctr;
@@ -1362,37 +1389,41 @@ static smrt_status bguard(smrt_batch *b, F &&f) {
     }
 }
 
-// re-plan every problem with the batch's launch shape
-static void batch_plan(smrt_batch *b, int nw, int k) {
+// re-plan every problem with the batch's launch shape (0 = automatic per field)
+static void batch_plan(smrt_batch *b, int nw, int nbw, int k) {
     SMRT_HIP(hipStreamSynchronize(b->stream));
     b->drop_graph();
     b->task_set.clear();
     for (smrt_ctx *x : b->P) {
         x->user_NW = nw;
+        x->user_NBW = nbw;
         x->user_K = k;
         plan_sweep(x);
     }
     b->NW = b->P[0]->NW;
+    b->NBW = b->P[0]->NBW;
     b->K = b->P[0]->K;
-    for (smrt_ctx *x : b->P) require(x->NW == b->NW && x->K == b->K, "problems of a batch need one launch shape: set it explicitly");
+    for (smrt_ctx *x : b->P)
+        require(x->NW == b->NW && x->NBW == b->NBW && x->K == b->K,
+                "problems of a batch need one launch shape: set it explicitly");
 }
 
-// Task list over the given problems: band level by band level (so every band
-// follows the band below it), and within a level the problems with the
-// longest bands first (their pipelines are the critical paths).
+// Task list over the given problems: band-group level by level (so every
+// band group follows the group below it), and within a level the problems
+// with the longest bands first (their pipelines are the critical paths).
 static void batch_upload_tasks(smrt_batch *b, const std::vector<int> &active) {
     if (active == b->task_set) return;
     std::vector<int> order(active.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int i, int j) { return b->P[active[i]]->NT > b->P[active[j]]->NT; });
-    int maxb = 0;
-    for (int p : active) maxb = std::max(maxb, b->P[p]->nbands);
+    int maxg = 0;
+    for (int p : active) maxg = std::max(maxg, b->P[p]->n_bgroups);
     std::vector<int2> tasks;
-    for (int band = 0; band < maxb; ++band)
+    for (int bg = 0; bg < maxg; ++bg)
         for (int i : order) {
             const smrt_ctx *x = b->P[active[i]];
-            if (band >= x->nbands) continue;
-            for (int qc = 0; qc < x->NQC; ++qc) tasks.push_back(make_int2(i, band * x->NQC + qc));
+            if (bg >= x->n_bgroups) continue;
+            for (int qc = 0; qc < x->NQC; ++qc) tasks.push_back(make_int2(i, bg * x->NQC + qc));
         }
     b->n_tasks = (int)tasks.size();
     b->d_tasks.alloc(std::max<int64_t>(1, b->n_tasks));
@@ -1421,6 +1452,7 @@ static void batch_launch(smrt_batch *b) {
     L.tasks = b->d_tasks.p;
     L.n_tasks = b->n_tasks;
     L.NW = b->NW;
+    L.NBW = b->NBW;
     L.K = b->K;
     L.wg_per_cu = b->wg_per_cu;
     L.lctr = b->d_lctr.p;
@@ -1462,9 +1494,10 @@ extern "C" smrt_status smrt_batch_create(int n, smrt_ctx *const *problems, smrt_
             if ((int64_t)b->P[i]->ncell * b->P[i]->nang * b->P[i]->G > (int64_t)b->P[big]->ncell * b->P[big]->nang * b->P[big]->G) big = i;
         smrt_ctx *xb = b->P[big];
         xb->user_NW = 0;
+        xb->user_NBW = 0;
         xb->user_K = 0;
         plan_sweep(xb);
-        batch_plan(b.get(), xb->NW, xb->K);
+        batch_plan(b.get(), xb->NW, xb->NBW, xb->K);
     });
     if (st != SMRT_OK) return st;
     *out = b.release();
@@ -1479,15 +1512,13 @@ extern "C" void smrt_batch_destroy(smrt_batch *b) {
 
 extern "C" const char *smrt_batch_last_error(const smrt_batch *b) { return b ? b->err.c_str() : g_last_error.c_str(); }
 
-extern "C" smrt_status smrt_batch_set_launch(smrt_batch *b, int waves_per_group, int pairs_per_lane) {
+extern "C" smrt_status smrt_batch_set_launch(smrt_batch *b, int waves_per_band, int bands_per_group,
+                                             int pairs_per_lane) {
     if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
     return bguard(b, [&] {
         BatchStreams on(b);
-        require(waves_per_group == 1 || waves_per_group == 2 || waves_per_group == 4 || waves_per_group == 8,
-                "waves per group must be 1, 2, 4 or 8");
-        require(pairs_per_lane == 1 || pairs_per_lane == 2 || (pairs_per_lane == 4 && b->fp32),
-                "pairs per lane must be 1, 2, or 4 (FP32 only)");
-        batch_plan(b, waves_per_group, pairs_per_lane);
+        check_shape(b->fp32, waves_per_band, bands_per_group, pairs_per_lane, false);
+        batch_plan(b, waves_per_band, bands_per_group, pairs_per_lane);
     });
 }
 
@@ -1501,7 +1532,7 @@ extern "C" smrt_status smrt_batch_set_occupancy(smrt_batch *b, int workgroups_pe
 }
 
 extern "C" smrt_status smrt_batch_info(const smrt_batch *b, int64_t *units_per_sweep, int *n_tasks,
-                                       int *waves_per_group, int *pairs_per_lane) {
+                                       int *waves_per_band, int *bands_per_group, int *pairs_per_lane) {
     if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
     int64_t u = 0, t = 0;
     for (const smrt_ctx *x : b->P) {
@@ -1510,7 +1541,8 @@ extern "C" smrt_status smrt_batch_info(const smrt_batch *b, int64_t *units_per_s
     }
     if (units_per_sweep) *units_per_sweep = u;
     if (n_tasks) *n_tasks = (int)t;
-    if (waves_per_group) *waves_per_group = b->NW;
+    if (waves_per_band) *waves_per_band = b->NW;
+    if (bands_per_group) *bands_per_group = b->NBW;
     if (pairs_per_lane) *pairs_per_lane = b->K;
     return SMRT_OK;
 }
@@ -1587,20 +1619,23 @@ extern "C" smrt_status smrt_batch_sweep_resident(smrt_batch *b, double dt, int n
     });
 }
 
-extern "C" smrt_status smrt_batch_autotune(smrt_batch *b, double dt, int *waves_per_group, int *pairs_per_lane,
-                                           double *ms_best) {
+extern "C" smrt_status smrt_batch_autotune(smrt_batch *b, double dt, int *waves_per_band, int *bands_per_group,
+                                           int *pairs_per_lane, double *ms_best) {
     if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
     return bguard(b, [&] {
         BatchStreams on(b);
         require(dt > 0.0, "dt must be > 0");
-        int maxg = 0;
-        for (const smrt_ctx *x : b->P) maxg = std::max(maxg, x->G);
+        int maxg = 0, maxb = 0;
+        for (const smrt_ctx *x : b->P) {
+            maxg = std::max(maxg, x->G);
+            maxb = std::max(maxb, x->nbands);
+        }
         float best = 1e30f;
-        int bnw = b->NW, bk = b->K;
+        Shape bs{b->NW, b->NBW, b->K};
         const std::vector<int> all = all_problems(b);
         int bo = 0;
-        for (auto [nw, k] : launch_candidates(b->fp32, maxg)) {
-            batch_plan(b, nw, k);
+        for (const Shape &c : launch_candidates(b->fp32, maxg, maxb)) {
+            batch_plan(b, c.nw, c.nbw, c.k);
             std::vector<double> icdt;
             batch_tables(b, dt, icdt);
             batch_upload_tasks(b, all);
@@ -1610,13 +1645,14 @@ extern "C" smrt_status smrt_batch_autotune(smrt_batch *b, double dt, int *waves_
                 batch_launch(b);   // warm-up
                 const float ms = std::min(timed(b->stream, [&] { batch_launch(b); }), timed(b->stream, [&] { batch_launch(b); }));
                 for (smrt_ctx *x : b->P) check_sweep_flag(x);
-                if (ms < best) { best = ms; bnw = nw; bk = k; bo = occ; }
+                if (ms < best) { best = ms; bs = c; bo = occ; }
             }
         }
-        batch_plan(b, bnw, bk);
+        batch_plan(b, bs.nw, bs.nbw, bs.k);
         b->wg_per_cu = bo;
-        if (waves_per_group) *waves_per_group = bnw;
-        if (pairs_per_lane) *pairs_per_lane = bk;
+        if (waves_per_band) *waves_per_band = bs.nw;
+        if (bands_per_group) *bands_per_group = bs.nbw;
+        if (pairs_per_lane) *pairs_per_lane = bs.k;
         if (ms_best) *ms_best = best;
     });
 }

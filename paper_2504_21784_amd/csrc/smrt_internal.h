@@ -19,7 +19,6 @@ constexpr int SPIN_LIMIT = 1 << 20;          // bounded wait on a band trace
 // bits of a sweep's error flag: which bounded wait ran out
 constexpr int WAIT_START_GATE = 1;           // a band waiting for the band below to start
 constexpr int WAIT_TRACE = 2;                // a row-0 lane waiting for the band below's trace
-constexpr int WAIT_RING = 4;                 // a wave waiting for its workgroup's ring slot
 constexpr int TRACE_LAG = 8;                 // columns a band stays behind the band below
 constexpr int LDS_PER_CU = 160 * 1024;       // gfx950 LDS per compute unit (bytes)
 
@@ -44,8 +43,8 @@ struct ChunkRanges {
 // Device-side description of one 2D sweep (one problem).
 struct Sweep2DArgs {
     int nx, ny, G, nbands, NT;       // NT = nx + BAND_ROWS - 1 steps per band
-    int NW, K, R, NQC;               // waves/WG (group blocks of one direction), pairs/lane, pairs/chunk, chunk count
-    int n_wg;                        // workgroups of this launch (NQC * nbands)
+    int NW, K, R, NQC;               // waves per band (group blocks of one direction), pairs/lane, pairs/chunk, chunk count
+    int n_wg;                        // workgroups of this problem (NQC * band groups)
     int NB;                          // boundary face nodes
     const int *qc_quad;              // [NQC] quadrant of each chunk
     const int2 *slot_pair;           // [NQC*R] (direction, group) or (-1,-1)
@@ -63,16 +62,17 @@ struct Sweep2DArgs {
 };
 
 // One sweep launch: one problem (args by value) or a batch of problems
-// (device array), and the launch's task list.  A task is (problem, band *
-// NQC + chunk); the list is band-major, so a workgroup that claims a ticket
-// only ever waits on tasks claimed before it by running workgroups:
+// (device array), and the launch's task list.  A task is (problem, band group
+// * NQC + chunk); the list is band-group-major, so a workgroup that claims a
+// ticket only ever waits on tasks claimed before it by running workgroups:
 // deadlock-free at any residency.
 struct SweepLaunch {
     Sweep2DArgs single;              // used when probs == nullptr
     const Sweep2DArgs *probs;        // [n_probs] device array (batch) or nullptr
     const int2 *tasks;               // [n_tasks]
     int n_tasks;
-    int NW, K;                       // launch shape shared by every problem
+    int NW, NBW, K;                  // launch shape shared by every problem: waves per band,
+                                     // bands per workgroup (NW * NBW <= 16), pairs per lane
     int wg_per_cu;                   // 0: as many as fit; n: pad LDS so at most n workgroups share a CU
     int *lctr;                       // [2]: ticket, workgroups done (both reset by the last workgroup)
     int fixup;                       // 1: zero-and-scale negative-flux fixup in every cell

@@ -1,0 +1,6 @@
+// 2D sweep kernels, FP64 instances (the kernel is in sweep2d.inc).
+#include "sweep2d.inc"
+
+namespace smrt {
+template void launch_sweep2d<double>(const SweepLaunch &, hipStream_t);
+}

@@ -68,9 +68,9 @@ class StepStats(C.Structure):
 class Info(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("n_angles", C.c_int), ("G", C.c_int),
                 ("n_nodes", C.c_int), ("n_cells", C.c_int), ("units_per_sweep", C.c_int64),
-                ("algorithmic_bytes_per_sweep", C.c_int64), ("band_rows", C.c_int), ("waves_per_group", C.c_int),
+                ("algorithmic_bytes_per_sweep", C.c_int64), ("band_rows", C.c_int), ("waves_per_band", C.c_int),
                 ("pairs_per_lane", C.c_int), ("pairs_per_chunk", C.c_int), ("n_chunks", C.c_int),
-                ("n_workgroups", C.c_int)]
+                ("n_workgroups", C.c_int), ("bands_per_group", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -98,8 +98,8 @@ _SIGS = {
     "smrt_sweep_resident": ([C.c_void_p, C.c_double, C.c_int, _dp, _dp], C.c_int),
     "smrt_get_info": ([C.c_void_p, C.POINTER(Info)], C.c_int),
     "smrt_get_moments": ([C.c_void_p, _dp], C.c_int),
-    "smrt_set_launch": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
-    "smrt_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _dp], C.c_int),
+    "smrt_set_launch": ([C.c_void_p, C.c_int, C.c_int, C.c_int], C.c_int),
+    "smrt_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _ip, _dp], C.c_int),
     "smrt_set_occupancy": ([C.c_void_p, C.c_int], C.c_int),
     "smrt_batch_set_occupancy": ([C.c_void_p, C.c_int], C.c_int),
     "smrt_adjoint_sweep": ([C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp], C.c_int),
@@ -108,9 +108,9 @@ _SIGS = {
     "smrt_batch_create": ([C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)], C.c_int),
     "smrt_batch_destroy": ([C.c_void_p], None),
     "smrt_batch_last_error": ([C.c_void_p], C.c_char_p),
-    "smrt_batch_set_launch": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
-    "smrt_batch_info": ([C.c_void_p, C.POINTER(C.c_int64), _ip, _ip, _ip], C.c_int),
-    "smrt_batch_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _dp], C.c_int),
+    "smrt_batch_set_launch": ([C.c_void_p, C.c_int, C.c_int, C.c_int], C.c_int),
+    "smrt_batch_info": ([C.c_void_p, C.POINTER(C.c_int64), _ip, _ip, _ip, _ip], C.c_int),
+    "smrt_batch_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _ip, _dp], C.c_int),
     "smrt_batch_sweep_resident": ([C.c_void_p, C.c_double, C.c_int, C.c_int, _dp, _dp], C.c_int),
     "smrt_batch_step": ([C.c_void_p, _dp, C.POINTER(StepStats)], C.c_int),
     "smrt_qmesh_create": ([C.c_int, _dp, C.c_int, C.POINTER(C.c_int32), C.POINTER(QuadDesc), C.c_int, C.c_int,
@@ -233,8 +233,9 @@ class Context:
     def set_occupancy(self, workgroups_per_cu=0):
         self._check(self.L.smrt_set_occupancy(self.h, int(workgroups_per_cu)))
 
-    def set_launch(self, waves_per_group=0, pairs_per_lane=0):
-        self._check(self.L.smrt_set_launch(self.h, waves_per_group, pairs_per_lane))
+    def set_launch(self, waves_per_band=0, bands_per_group=0, pairs_per_lane=0):
+        """Sweep launch shape (0 = automatic per field)."""
+        self._check(self.L.smrt_set_launch(self.h, int(waves_per_band), int(bands_per_group), int(pairs_per_lane)))
 
     def info(self) -> dict:
         i = Info()
@@ -350,11 +351,12 @@ class Context:
         return ms.value, ks.value
 
     def autotune(self, dt=None):
-        """Pick the fastest sweep launch shape; returns (waves, groups per lane, ms)."""
-        nw, k, ms = C.c_int(0), C.c_int(0), C.c_double(0.0)
-        self._check(self.L.smrt_autotune(self.h, float(dt if dt is not None else self.p.dt), C.byref(nw), C.byref(k),
-                                         C.byref(ms)))
-        return nw.value, k.value, ms.value
+        """Pick the fastest sweep launch shape; returns (waves per band, bands per
+        workgroup, groups per lane, ms)."""
+        nw, nb, k, ms = C.c_int(0), C.c_int(0), C.c_int(0), C.c_double(0.0)
+        self._check(self.L.smrt_autotune(self.h, float(dt if dt is not None else self.p.dt), C.byref(nw), C.byref(nb),
+                                         C.byref(k), C.byref(ms)))
+        return nw.value, nb.value, k.value, ms.value
 
 
 class Batch:
@@ -387,20 +389,21 @@ class Batch:
             pass
 
     def info(self) -> dict:
-        u, t, nw, k = C.c_int64(0), C.c_int(0), C.c_int(0), C.c_int(0)
-        self._check(self.L.smrt_batch_info(self.h, C.byref(u), C.byref(t), C.byref(nw), C.byref(k)))
-        return {"units_per_sweep": u.value, "n_tasks": t.value, "waves_per_group": nw.value, "pairs_per_lane": k.value}
+        u, t, nw, nb, k = C.c_int64(0), C.c_int(0), C.c_int(0), C.c_int(0), C.c_int(0)
+        self._check(self.L.smrt_batch_info(self.h, C.byref(u), C.byref(t), C.byref(nw), C.byref(nb), C.byref(k)))
+        return {"units_per_sweep": u.value, "n_tasks": t.value, "waves_per_band": nw.value, "bands_per_group": nb.value,
+                "pairs_per_lane": k.value}
 
-    def set_launch(self, waves_per_group, pairs_per_lane=1):
-        self._check(self.L.smrt_batch_set_launch(self.h, int(waves_per_group), int(pairs_per_lane)))
+    def set_launch(self, waves_per_band, bands_per_group, pairs_per_lane=1):
+        self._check(self.L.smrt_batch_set_launch(self.h, int(waves_per_band), int(bands_per_group), int(pairs_per_lane)))
 
     def set_occupancy(self, workgroups_per_cu=0):
         self._check(self.L.smrt_batch_set_occupancy(self.h, int(workgroups_per_cu)))
 
     def autotune(self, dt):
-        nw, k, ms = C.c_int(0), C.c_int(0), C.c_double(0.0)
-        self._check(self.L.smrt_batch_autotune(self.h, float(dt), C.byref(nw), C.byref(k), C.byref(ms)))
-        return nw.value, k.value, ms.value
+        nw, nb, k, ms = C.c_int(0), C.c_int(0), C.c_int(0), C.c_double(0.0)
+        self._check(self.L.smrt_batch_autotune(self.h, float(dt), C.byref(nw), C.byref(nb), C.byref(k), C.byref(ms)))
+        return nw.value, nb.value, k.value, ms.value
 
     def sweep_resident(self, dt, n_times=1, capture_graph=False):
         """Returns (ms per batched high-order pass, ms of one batched sweep launch)."""

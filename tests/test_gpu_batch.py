@@ -42,7 +42,7 @@ def test_batched_pass_matches_single_problem_launches(smrt_mod, prec, tol):
     b = smrt_mod.Batch(batched)
     info = b.info()
     for c in single:
-        c.set_launch(info["waves_per_group"], info["pairs_per_lane"])
+        c.set_launch(info["waves_per_band"], info["bands_per_group"], info["pairs_per_lane"])
         c.sweep_resident(n_times=1)
     b.sweep_resident(ps[0].dt, n_times=1)
     for c1, c2 in zip(single, batched):
@@ -101,7 +101,7 @@ def test_batched_steps_match_single_problem_steps(smrt_mod):
     b = smrt_mod.Batch(batched)
     info = b.info()
     for c in single:
-        c.set_launch(info["waves_per_group"], info["pairs_per_lane"])
+        c.set_launch(info["waves_per_band"], info["bands_per_group"], info["pairs_per_lane"])
     for step in range(2):
         print("step", step, flush=True)
         s1 = [c.step(p.dt) for c, p in zip(single, ps)]
@@ -123,10 +123,10 @@ def test_batch_autotune_keeps_results(smrt_mod):
     b = smrt_mod.Batch(cs)
     b.sweep_resident(ps[0].dt, n_times=1)
     before = [c.get_moments() for c in cs]
-    nw, k, ms = b.autotune(ps[0].dt)
-    print("batch autotune:", nw, k, ms, flush=True)
-    assert 1 <= nw <= 12 and k in (1, 2) and ms > 0
-    assert b.info()["waves_per_group"] == nw
+    nw, nb, k, ms = b.autotune(ps[0].dt)
+    print("batch autotune:", nw, nb, k, ms, flush=True)
+    assert nw in (1, 2, 4) and nb in (1, 2, 4, 8, 16) and nw * nb <= 16 and k in (1, 2, 4) and ms > 0
+    assert b.info()["waves_per_band"] == nw and b.info()["bands_per_group"] == nb
     b.sweep_resident(ps[0].dt, n_times=1)
     for c, m in zip(cs, before):
         assert _rel(c.get_moments(), m) < 1e-6
@@ -141,9 +141,10 @@ def test_single_autotune(smrt_mod):
     c.set_state(p.initial_T_nodes())
     c.sweep_resident(n_times=1)
     before = c.get_moments()
-    nw, k, ms = c.autotune()
-    print("autotune:", nw, k, ms, flush=True)
-    assert c.info()["waves_per_group"] == nw and c.info()["pairs_per_lane"] == k
+    nw, nb, k, ms = c.autotune()
+    print("autotune:", nw, nb, k, ms, flush=True)
+    i = c.info()
+    assert i["waves_per_band"] == nw and i["bands_per_group"] == nb and i["pairs_per_lane"] == k
     c.sweep_resident(n_times=1)
     assert _rel(c.get_moments(), before) < 1e-6
     c.close()
@@ -167,12 +168,14 @@ def test_full_batch_matches_single_problem_launches(smrt_mod):
     benchmark reports (4 waves x 2 groups per lane): the largest, the
     smallest and one middle problem match the same problem launched alone
     with the same shape (which the full-size sweep test checks against the
-    oracle)."""
+    oracle).  The shape (2 waves per band, 4 bands per workgroup, 2 groups
+    per lane) puts several band groups on the larger problems, so the
+    workgroup-to-workgroup trace hand-off is exercised too."""
     ps = W.batch_2d()
     print("full batch:", len(ps), "problems", flush=True)
     cs = _contexts(smrt_mod, ps, 1)
     b = smrt_mod.Batch(cs)
-    b.set_launch(2, 2)
+    b.set_launch(2, 4, 2)
     b.sweep_resident(ps[0].dt, n_times=1)
     sizes = [p.nx * p.ny * p.n_angles * p.G for p in ps]
     picks = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), len(ps) // 2})
@@ -180,7 +183,7 @@ def test_full_batch_matches_single_problem_launches(smrt_mod):
         print("problem", ps[i].name, flush=True)
         single = smrt_mod.Context(ps[i], precision=1)
         single.set_state(ps[i].initial_T_nodes())
-        single.set_launch(2, 2)
+        single.set_launch(2, 4, 2)
         single.sweep_resident(ps[i].dt, n_times=1)
         assert _rel(cs[i].get_moments(), single.get_moments()) < 1e-6, ps[i].name
         single.close()

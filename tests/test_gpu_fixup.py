@@ -65,12 +65,12 @@ def test_sweep2d_fixup_matches_oracle(smrt_mod, oracle_mod, nx, ny, sn, G, prec,
         assert _rel(mom[m], ref_mom[m]) < tol, m
 
 
-@pytest.mark.parametrize("launch", [(1, 1), (2, 1), (8, 2), (4, 1), (1, 4)])
+@pytest.mark.parametrize("launch", [(1, 1, 1), (2, 1, 1), (4, 2, 2), (4, 1, 1), (1, 4, 4), (1, 16, 1), (2, 2, 2)])
 def test_sweep2d_fixup_launch_shapes(smrt_mod, oracle_mod, launch):
     p = _mesh2d(45, 40, 8, 3, seed=4)
     sigt, q, pp, inf = _inputs(p, 4)
     ref = oracle_mod.Oracle(p).sweep(sigt, q, pp, 0.3, inf, fixup=True)
-    prec = 1 if launch[1] >= 2 else 0
+    prec = 1 if launch[2] >= 2 else 0
     print(f"fixup launch {launch} precision {prec}", flush=True)
     ctx = smrt_mod.Context(p, precision=prec, fixup=1)
     ctx.set_launch(*launch)
@@ -167,7 +167,7 @@ def test_batch_fixup_matches_single_problem_launches(smrt_mod):
     b = smrt_mod.Batch(batched)
     info = b.info()
     for c in single:
-        c.set_launch(info["waves_per_group"], info["pairs_per_lane"])
+        c.set_launch(info["waves_per_band"], info["bands_per_group"], info["pairs_per_lane"])
         c.sweep_resident(ps[0].dt, n_times=1)
     b.sweep_resident(ps[0].dt, n_times=1)
     for c1, c2 in zip(single, batched):

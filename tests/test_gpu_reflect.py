@@ -151,7 +151,7 @@ def test_batch_of_reflective_problems_matches_single_steps(smrt_mod):
     b = smrt_mod.Batch(batched)
     info = b.info()
     for c in single:
-        c.set_launch(info["waves_per_group"], info["pairs_per_lane"])
+        c.set_launch(info["waves_per_band"], info["bands_per_group"], info["pairs_per_lane"])
     for k in range(2):
         print(f"batched reflective step {k}", flush=True)
         b.step(ps[0].dt)

@@ -3,17 +3,22 @@
 The sweep kernel addresses its arrays through wave-uniform bases plus per-lane
 and per-step byte offsets; a lane with no work gets an offset at or past 2^31,
 which the hardware turns into a dropped access.  This module restates the
-planner's chunk and slot layout and the kernel's index arithmetic (task ->
-chunk, band; wave -> direction, groups; lane -> channel, row; step -> column)
-and checks, for every launch shape (waves per workgroup 1, 2, 4, 8; groups
-per lane 1, 2, 4; FP32 and FP64), on regular, ragged and degenerate meshes:
+planner's chunk, band-group and slot layout and the kernel's index arithmetic
+(task -> band group, chunk; wave -> band, group block; lane -> channel, row;
+step -> column) and checks, for every launch shape (waves per band 1, 2, 4;
+bands per workgroup 1 .. 16; groups per lane 1, 2, 4; FP32 and FP64), on
+regular, ragged and degenerate meshes:
 
 * every access of a lane with work lies inside its allocation and inside
   the buffer resource it goes through, with a byte offset below 2^31;
 * every lane without work is marked out of range;
-* the trace words a band publishes are exactly the words the band above
-  reads, and each (column, slot) word is written once;
-* each moment partial of a (chunk, band, step) is stored by one lane, and the
+* the trace words the top band of a workgroup publishes are exactly the words
+  the bottom band of the workgroup above reads, and each is written once;
+* the LDS hand-off slot a band writes at one step is the slot the band above
+  reads at the next barrier interval, and every LDS index stays inside its
+  array;
+* every wave of a workgroup passes the same number of barriers;
+* each moment partial of a (chunk, band, step) is stored once, and the
   finalisation reads only partials of cells inside the mesh.
 
 It is run before kernel changes go to a GPU.
@@ -38,7 +43,7 @@ def quadrant_dirs(omega):
 
 def plan(nx, ny, G, omega, NW, K):
     """Chunks (quadrant, direction, block of 4 K NW groups) and their slots
-    (wave w, channel c, pair k) -> (direction, group) or (-1, -1)."""
+    (group block w, channel c, pair k) -> (direction, group) or (-1, -1)."""
     qd = quadrant_dirs(omega)
     GB = 4 * K * NW
     ngb = (G + GB - 1) // GB
@@ -60,7 +65,16 @@ def plan(nx, ny, G, omega, NW, K):
                 NT=nx + BAND_ROWS - 1)
 
 
-def check_shape(nx, ny, G, sn, NW, K, rs):
+def prefetch_steps(rs, K, waves):
+    """Steps per unrolled round of the kernel's step loop (prefetch depth + 1)."""
+    if rs == 4:
+        pf = (3 if K == 1 else 1) if waves >= 16 else {1: 4, 2: 3, 4: 1}[K]
+    else:
+        pf = 1 if waves >= 16 else (2 if K == 1 else 1)
+    return pf + 1
+
+
+def check_shape(nx, ny, G, sn, NW, NBW, K, rs):
     omega, _ = W.level_symmetric_2d(sn)
     nang = len(omega)
     P = plan(nx, ny, G, omega, NW, K)
@@ -68,6 +82,9 @@ def check_shape(nx, ny, G, sn, NW, K, rs):
     TW = rs // 4
     NB = 4 * (nx + ny)
     gslab = nb * NT * BAND_ROWS
+    n_groups = (nb + NBW - 1) // NBW
+    STEPS = prefetch_steps(rs, K, NW * NBW)
+    NTP = (NT + STEPS - 1) // STEPS * STEPS
     # allocations (elements of the unit each array is addressed in)
     n_psi = nang * G * gslab            # r4 records
     n_tab = 4 * G * gslab               # r2 / r4 records of the per-quadrant tables
@@ -75,6 +92,8 @@ def check_shape(nx, ny, G, sn, NW, K, rs):
     slot_words = nx * 2 * TW            # one slot's words in a band's trace block
     n_trace = NQC * nb * R * slot_words
     n_part = NQC * nb * NT * 64         # r2 records
+    n_hand = 2 * NBW * NW * K * CHANNELS * 2
+    n_ring = 2 * NBW * NW * 64
     assert CHANNELS * K * nb * NT * BAND_ROWS * 4 * rs < OOB, "planner would reject this mesh"
     written = np.zeros(n_trace, np.int32)
     read_words = np.zeros(n_trace, np.int32)
@@ -88,80 +107,110 @@ def check_shape(nx, ny, G, sn, NW, K, rs):
         slots = P["slots"][qc]
         d = slots[0][0]
         assert d >= 0, "slot 0 of a chunk must be active"
-        assert 0 <= 8 * d and 8 * d + 7 < 8 * nang
-        for band in range(nb):
-            jc = band * BAND_ROWS + r
-            row_ok = jc < ny
-            jn = np.where(fy, ny - 1 - jc, jc)
-            assert np.all(jn[row_ok] >= 0) and np.all(jn[row_ok] < ny)
-            produce = (r == BAND_ROWS - 1) & (band + 1 < nb)
-            tin_base = (qc * nb + (band - 1 if band > 0 else 0)) * R * slot_words
-            tout_base = (qc * nb + band) * R * slot_words
-            part_base = (qc * nb + band) * NT * 64
-            for w in range(NW):
-                pg0 = slots[w * CHANNELS * K]
-                wave_on = pg0[0] >= 0
-                gb0 = pg0[1] if wave_on else 0
-                pbase = ((d * G + gb0) * nb + band) * NT * BAND_ROWS
-                tbase = (quad * G + gb0) * gslab + band * NT * BAND_ROWS
-                span = CHANNELS * K * gslab
-                for k in range(K):
-                    slot_idx = (w * CHANNELS + ch) * K + k
-                    assert np.all(slot_idx < R)
-                    pg = [slots[i] for i in slot_idx]
-                    act = np.array([p[0] >= 0 for p in pg]) & row_ok
-                    gl = np.array([p[1] - gb0 if p[1] >= 0 else 0 for p in pg])
-                    g = gb0 + gl
-                    assert np.all(g[act] < G) and np.all(gl[act] < CHANNELS * K) and np.all(gl[act] >= 0)
-                    cell = gl * gslab + r
-                    vo4 = np.where(act, cell * 4 * rs, OOB)
-                    assert np.all(vo4[act] < OOB) and np.all(vo4[~act] >= OOB)
-                    # intensity and tables over every step (loads clamp t to NT-1)
-                    so = t * BAND_ROWS * 4 * rs
-                    off = vo4[act][:, None] + so[None, :]
-                    assert off.size == 0 or (off.max() < OOB and off.max() + 4 * rs <= span * 4 * rs)
-                    el = pbase + (off // (4 * rs))
-                    assert el.size == 0 or (el.min() >= 0 and el.max() < n_psi)
-                    el = tbase + (off // (4 * rs))
-                    assert el.size == 0 or (el.min() >= 0 and el.max() < n_tab)
-                    # boundary inflow (y- side at row 0's column, x- side per row)
-                    yside = 4 * ny + (2 * nx if fy else 0)
-                    xside = 2 * ny if fx else 0
-                    c0 = np.minimum(t, nx - 1)
-                    in0 = np.where(fx, nx - 1 - c0, c0)
-                    inf_off = (gl[act][:, None] * NB + yside + 2 * in0[None, :])
-                    el = (d * G + gb0) * NB + inf_off
-                    assert el.size == 0 or (el.max() + 1 < n_inf and inf_off.max() + 1 < CHANNELS * K * NB)
-                    jv = np.where(row_ok, jn, 0)
-                    ib = (d * G + gb0 + gl) * NB
-                    el = ib[act] + xside + 2 * jv[act] + 1
-                    assert el.size == 0 or el.max() < n_inf
-                    # trace words: this lane's slot row of a band's block
-                    slot = ((w * K + k) * CHANNELS + ch)
-                    assert np.all(slot < R)
-                    if band > 0:
-                        rd = act & (r == 0)
-                        for c in range(nx):
-                            for sl in slot[rd]:
-                                o = tin_base + (sl * nx + c) * 2 * TW
-                                read_words[o: o + 2 * TW] += 1
-                        gcol = min(TRACE_LAG, nx - 1)
-                        assert tin_base + ((R - 1) * nx + gcol) * 2 * TW + 2 * TW <= n_trace
-                    pr = act & produce
-                    for tt in range(BAND_ROWS - 1, NT):
-                        col = tt - (BAND_ROWS - 1)
-                        assert 0 <= col < nx
-                        for sl in slot[pr]:
-                            o = tout_base + (sl * nx + col) * 2 * TW
-                            written[o: o + 2 * TW] += 1
-                # moment partial: one store per lane and step (NW = 1: this wave;
-                # NW > 1: the last wave to reach the step, once per step)
-                if w == 0:
-                    idx = part_base + t[:, None] * 64 + lane[None, :]
-                    assert idx.max() < n_part
-                    part_owner[idx.ravel()] += 1
-    # every word the band above reads was published by the band below, once;
-    # words nobody reads are those of the top band's chunks (never written)
+        for bg in range(n_groups):
+            hand_w = {}   # LDS hand-off writes: (parity, band slot, w, k, ch) -> (band, global iteration)
+            barriers = []
+            for bw in range(NBW):
+                band = bg * NBW + bw
+                for w in range(NW):
+                    if band >= nb:
+                        barriers.append(NTP + BAND_ROWS * (NBW - 1))
+                        continue
+                    barriers.append(BAND_ROWS * bw + NTP + BAND_ROWS * (NBW - 1 - bw))
+                    jc = band * BAND_ROWS + r
+                    row_ok = jc < ny
+                    jn = np.where(fy, ny - 1 - jc, jc)
+                    assert np.all(jn[row_ok] >= 0) and np.all(jn[row_ok] < ny)
+                    rd_global = bw == 0 and band > 0
+                    wr_global = bw == NBW - 1 and band + 1 < nb
+                    tin_base = (qc * nb + (band - 1 if band > 0 else 0)) * R * slot_words
+                    tout_base = (qc * nb + band) * R * slot_words
+                    part_base = (qc * nb + band) * NT * 64
+                    pg0 = slots[w * CHANNELS * K]
+                    wave_on = pg0[0] >= 0
+                    gb0 = pg0[1] if wave_on else 0
+                    pbase = ((d * G + gb0) * nb + band) * NT * BAND_ROWS
+                    tbase = (quad * G + gb0) * gslab + band * NT * BAND_ROWS
+                    span = CHANNELS * K * gslab
+                    for k in range(K):
+                        slot_idx = (w * CHANNELS + ch) * K + k
+                        assert np.all(slot_idx < R)
+                        pg = [slots[i] for i in slot_idx]
+                        act = np.array([p[0] >= 0 for p in pg]) & row_ok
+                        gl = np.array([p[1] - gb0 if p[1] >= 0 else 0 for p in pg])
+                        g = gb0 + gl
+                        assert np.all(g[act] < G) and np.all(gl[act] < CHANNELS * K) and np.all(gl[act] >= 0)
+                        cell = gl * gslab + r
+                        vo4 = np.where(act, cell * 4 * rs, OOB)
+                        assert np.all(vo4[act] < OOB) and np.all(vo4[~act] >= OOB)
+                        # intensity and tables over every step (loads clamp t to NT-1)
+                        so = t * BAND_ROWS * 4 * rs
+                        off = vo4[act][:, None] + so[None, :]
+                        assert off.size == 0 or (off.max() < OOB and off.max() + 4 * rs <= span * 4 * rs)
+                        el = pbase + (off // (4 * rs))
+                        assert el.size == 0 or (el.min() >= 0 and el.max() < n_psi)
+                        el = tbase + (off // (4 * rs))
+                        assert el.size == 0 or (el.min() >= 0 and el.max() < n_tab)
+                        # boundary inflow (y- side at row 0's column for band 0, x- side per row)
+                        yside = 4 * ny + (2 * nx if fy else 0)
+                        xside = 2 * ny if fx else 0
+                        c0 = np.minimum(t, nx - 1)
+                        in0 = np.where(fx, nx - 1 - c0, c0)
+                        if band == 0:
+                            inf_off = (gl[act][:, None] * NB + yside + 2 * in0[None, :])
+                            el = (d * G + gb0) * NB + inf_off
+                            assert el.size == 0 or (el.max() + 1 < n_inf and inf_off.max() + 1 < CHANNELS * K * NB)
+                        jv = np.where(row_ok, jn, 0)
+                        ib = (d * G + gb0 + gl) * NB
+                        el = ib[act] + xside + 2 * jv[act] + 1
+                        assert el.size == 0 or el.max() < n_inf
+                        # trace words: this lane's slot row of a band's block
+                        slot = ((w * K + k) * CHANNELS + ch)
+                        assert np.all(slot < R)
+                        if rd_global:
+                            rd = act & (r == 0)
+                            for c in range(nx):
+                                for sl in slot[rd]:
+                                    o = tin_base + (sl * nx + c) * 2 * TW
+                                    read_words[o: o + 2 * TW] += 1
+                            gcol = min(TRACE_LAG, nx - 1)
+                            assert tin_base + ((R - 1) * nx + gcol) * 2 * TW + 2 * TW <= n_trace
+                        if wr_global:
+                            pr = act & (r == BAND_ROWS - 1)
+                            for tt in range(BAND_ROWS - 1, NT):
+                                col = tt - (BAND_ROWS - 1)
+                                assert 0 <= col < nx
+                                for sl in slot[pr]:
+                                    o = tout_base + (sl * nx + col) * 2 * TW
+                                    written[o: o + 2 * TW] += 1
+                        # LDS hand-off: written by the top row at step tt (global
+                        # iteration 16 bw + tt) into parity tt & 1 of band slot bw
+                        for c in range(CHANNELS):
+                            if bw < NBW - 1:
+                                for tt in range(NTP):
+                                    idx = ((((tt & 1) * NBW + bw) * NW + w) * K + k) * CHANNELS * 2 + c * 2
+                                    assert 0 <= idx and idx + 1 < n_hand
+                                    hand_w[(tt & 1, bw, w, k, c, tt - (BAND_ROWS - 1))] = BAND_ROWS * bw + tt
+                            if bw > 0:
+                                # row 0 at step tt < nx reads column tt from parity (tt + 1) & 1 of band slot bw - 1
+                                for tt in range(min(nx, NTP)):
+                                    idx = (((((tt + 1) & 1) * NBW + bw - 1) * NW + w) * K + k) * CHANNELS * 2 + c * 2
+                                    assert 0 <= idx and idx + 1 < n_hand
+                                    key = ((tt + 1) & 1, bw - 1, w, k, c, tt)
+                                    assert key in hand_w, "a band reads an LDS slot the band below never wrote"
+                                    # written in the previous barrier interval, not overwritten since
+                                    assert hand_w[key] == BAND_ROWS * bw + tt - 1
+                    # moment partials: block 0 stores each step of the band once
+                    if NW > 1:
+                        for tt in range(NTP):
+                            assert ((((tt & 1) * NBW + bw) * NW + w) * 64 + 63) < n_ring
+                    if w == 0:
+                        idx = part_base + t[:, None] * 64 + lane[None, :]
+                        assert idx.max() < n_part
+                        part_owner[idx.ravel()] += 1
+            assert len(set(barriers)) == 1, "the waves of a workgroup pass different numbers of barriers"
+    # every word the bottom band of a workgroup reads was published by the top
+    # band of the workgroup below, once; words nobody reads are never written
     assert np.all(written <= 1), "a trace word is written twice"
     assert np.all(written[read_words > 0] == 1), "a band reads a trace word nobody writes"
     assert np.all(part_owner == 1), "each moment partial has one owner"
@@ -174,23 +223,29 @@ def check_shape(nx, ny, G, sn, NW, K, rs):
             assert np.all(((NQC - 1) * nb + band) * NT * 64 + tt * 64 + 3 * 16 + rc[ok] < n_part)
 
 
-SHAPES = [(1, 1), (9, 1), (1, 20), (37, 35), (16, 16), (17, 33), (64, 48)]
-LAUNCH = [(nw, k) for nw, k in itertools.product((1, 2, 4, 8), (1, 2, 4))]
+def max_waves(rs, K):
+    return 8 if rs * K >= 16 else 16
+
+
+SHAPES = [(1, 1), (9, 1), (1, 20), (37, 35), (16, 16), (17, 33), (64, 48), (20, 130)]
+LAUNCH = [(nw, nb, k) for nw, nb, k in itertools.product((1, 2, 4), (1, 2, 4, 8, 16), (1, 2, 4))]
 
 
 @pytest.mark.parametrize("nx,ny", SHAPES)
-@pytest.mark.parametrize("nw,k", LAUNCH)
+@pytest.mark.parametrize("nw,nb,k", LAUNCH)
 @pytest.mark.parametrize("rs", [4, 8])
-def test_sweep_indexing_in_bounds(nx, ny, nw, k, rs):
+def test_sweep_indexing_in_bounds(nx, ny, nw, nb, k, rs):
     if rs == 8 and k == 4:
         pytest.skip("four groups per lane is an FP32 shape only")
+    if nw * nb > max_waves(rs, k):
+        pytest.skip("more waves than the shape's register budget allows (rejected by the planner)")
     for G, sn in ((1, 4), (5, 4), (16, 8), (33, 4)):
         if 4 * k * nw > 2 * max(G, 4) and (nw, k) != (1, 1):
             continue
-        check_shape(nx, ny, G, sn, nw, k, rs)
+        check_shape(nx, ny, G, sn, nw, nb, k, rs)
 
 
 def test_sweep_indexing_benchmark_size():
-    """The benchmark's 256^2, S8, 16-group sweep in its default FP32 shapes."""
-    for nw, k in ((2, 2), (1, 4), (4, 1)):
-        check_shape(256, 256, 16, 8, nw, k, 4)
+    """The benchmark's 256^2, S8, 16-group sweep in its default and nearby FP32 shapes."""
+    for nw, nb, k in ((1, 16, 1), (2, 8, 1), (1, 8, 2), (4, 4, 1)):
+        check_shape(256, 256, 16, 8, nw, nb, k, 4)
