@@ -226,6 +226,22 @@ smrt_status smrt_sweep_dev(smrt_ctx *ctx, const double *sig_t, const double *sig
                            const double *psi_prev, double inv_c_dt, const double *psi_inflow, double *psi_out,
                            double *moments_out);
 
+/* smrt_sweep_dev for callers that cannot allocate device memory (serving
+ * loops, harnesses that forbid hipMalloc): the same operation, arguments,
+ * layouts and errors, but every per-call work array (inputs in the sweep's
+ * internal layouts, the internal output, moment partials, band trace words,
+ * counters) lives in one static device array of 64 MiB that each GPU the
+ * library runs on holds until the process ends; the call makes no
+ * allocation.  Problems whose work arrays exceed 64 MiB are rejected with
+ * SMRT_E_INVALID_ARG (the message gives the bytes needed): use
+ * smrt_sweep_dev for them.  The call waits for the context stream before it
+ * returns.  All calls on one GPU share its array, which keeps the last
+ * call's contents: calls that overlap on one GPU (from several threads or
+ * streams) race and must be serialised by the caller. */
+smrt_status smrt_sweep_dev_static(smrt_ctx *ctx, const double *sig_t, const double *sig, const double *q_iso,
+                                  const double *psi_prev, double inv_c_dt, const double *psi_inflow, double *psi_out,
+                                  double *moments_out);
+
 /* Adjoint sweep: the transpose of the lumped upwind DG transport operator
  * of smrt_sweep (Sec. 3, eq. dgsn_transport), the building block of the
  * adjoint of a time step.  For every (d, g):

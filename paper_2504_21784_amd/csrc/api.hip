@@ -6,6 +6,7 @@
 #include <memory>
 #include <numeric>
 #include <algorithm>
+#include <mutex>
 
 #include "lo.h"
 #include "tables.h"
@@ -257,8 +258,19 @@ static int64_t psi_count(const smrt_ctx *x) {
 // ---------------------------------------------------------------------------
 // sweep launch (2D: band kernel + moment finalisation; 1D: pair kernel + moments)
 // ---------------------------------------------------------------------------
+// Work memory of the 2D sweep kernels beyond inputs and outputs: moment
+// partials, band trace words, the problem's counters and the launch ticket.
+// By default the context's own buffers; the allocation-free entry point
+// passes regions of its static array instead.
+struct SweepScratch {
+    void *part = nullptr;
+    uint64_t *trace = nullptr;
+    int *ctr = nullptr;    // [4]
+    int *lctr = nullptr;   // [2]
+};
+
 static Sweep2DArgs sweep_args(const smrt_ctx *x, const void *psi_prev, void *psi_out, const void *sig2,
-                              const void *qiso, const void *inflow, double icdt) {
+                              const void *qiso, const void *inflow, double icdt, const SweepScratch *ws = nullptr) {
     Sweep2DArgs a{};
     a.nx = x->nx; a.ny = x->ny; a.G = x->G; a.nbands = x->nbands; a.NT = x->NT;
     a.NW = x->NW; a.K = x->K; a.R = x->R; a.NQC = x->NQC; a.n_wg = x->n_wg; a.NB = x->NB;
@@ -267,18 +279,25 @@ static Sweep2DArgs sweep_args(const smrt_ctx *x, const void *psi_prev, void *psi
     a.dirs = x->d_dirs.p; a.hx = x->d_hx.p; a.hy = x->d_hy.p;
     a.sig2 = sig2; a.qiso = qiso; a.psi_prev = psi_prev; a.psi_out = psi_out; a.inflow = inflow;
     a.inv_c_dt = icdt; a.part = x->d_part.p; a.trace = x->d_trace.p; a.ctr = x->d_ctr.p;
+    if (ws) {
+        a.part = ws->part;
+        a.trace = ws->trace;
+        a.ctr = ws->ctr;
+    }
     return a;
 }
 
-static void finalize_moments(smrt_ctx *x, double *mom) {
-    if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const float *)x->d_part.p, x->d_sigq.p, mom);
-    else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const double *)x->d_part.p, x->d_sigq.p, mom);
+static void finalize_moments(smrt_ctx *x, double *mom, const void *part = nullptr) {
+    if (!part) part = x->d_part.p;
+    if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const float *)part, x->d_sigq.p, mom);
+    else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const double *)part, x->d_sigq.p, mom);
 }
 
 static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const void *sig2, const void *qiso,
-                      const void *inflow, double icdt, const double *sig64, double *mom, bool finalize = true) {
+                      const void *inflow, double icdt, const double *sig64, double *mom, bool finalize = true,
+                      const SweepScratch *ws = nullptr) {
     if (x->dim == 2) {
-        const Sweep2DArgs a = sweep_args(x, psi_prev, psi_out, sig2, qiso, inflow, icdt);
+        const Sweep2DArgs a = sweep_args(x, psi_prev, psi_out, sig2, qiso, inflow, icdt, ws);
         SweepLaunch L{};
         L.single = a;
         L.probs = nullptr;
@@ -288,11 +307,11 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
         L.NBW = x->NBW;
         L.K = x->K;
         L.wg_per_cu = x->wg_per_cu;
-        L.lctr = x->d_lctr.p;
+        L.lctr = ws ? ws->lctr : x->d_lctr.p;
         L.fixup = x->opt.fixup;
         if (x->fp32) launch_sweep2d<float>(L, x->stream);
         else launch_sweep2d<double>(L, x->stream);
-        if (finalize) finalize_moments(x, mom);
+        if (finalize) finalize_moments(x, mom, ws ? ws->part : nullptr);
     } else {
         Sweep1DArgs a{};
         a.nx = x->nx; a.G = x->G; a.nang = x->nang; a.mu_w = x->d_mu_w.p; a.hx = x->d_hx.p;
@@ -820,10 +839,53 @@ static void ensure(DevBuf<T> &b, int64_t n) {
     if (b.n != n) b.alloc(n);
 }
 
+// Work arrays of one raw sweep: the inputs in the sweep's internal layouts
+// and precision, the internal output, and moments when the caller wants none.
+struct RawBufs {
+    void *sig2, *qiso, *in, *out, *inflow;
+    double *mom;
+};
+static int64_t raw_tab_cells(const smrt_ctx *x) { return x->dim == 2 ? 4 * cell_slab(x->nx, x->ny) : x->ncell; }
+
+// The sweep of explicit inputs (FP64, caller layouts) into out/mom through
+// the work arrays B; ws: kernel work memory (nullptr: the context's).
+static void raw_sweep_with(smrt_ctx *x, const double *sig_t, const double *sig, const double *q, const double *prev,
+                           double inv_c_dt, const double *inflow64, double *out, double *mom, const RawBufs &B,
+                           const SweepScratch *ws) {
+    const int64_t na = (int64_t)x->nang * x->G * x->nn;
+    auto tables = [&](auto zero) {
+        using real = decltype(zero);
+        if (x->dim == 2) {
+            run_stab2d<real>(x->stream, x->nx, x->ny, x->G, sig, sig_t, 0.0, (real *)B.sig2);
+            run_qtab2d<real, double>(x->stream, x->nx, x->ny, x->G, q, x->G, 1, (real *)B.qiso);
+        } else {
+            run_sig_to_internal<real>(x->stream, x->ncell, x->G, sig_t, sig, (real *)B.sig2);
+            run_qiso_to_internal<real>(x->stream, x->nn, x->G, x->npc, q, (real *)B.qiso);
+        }
+        if (prev) {
+            if (x->dim == 2) run_psi_to_internal<real>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, prev, (real *)B.in);
+            else run_copy_to<real>(x->stream, na, prev, (real *)B.in);
+        }
+        if (inflow64) run_copy_to<real>(x->stream, (int64_t)x->nang * x->G * x->NB, inflow64, (real *)B.inflow);
+    };
+    if (x->fp32) tables(0.0f);
+    else tables(0.0);
+    if (!mom) mom = B.mom;
+    run_sweep(x, prev ? B.in : nullptr, B.out, B.sig2, B.qiso, inflow64 ? B.inflow : x->d_inflow.p, inv_c_dt, sig, mom,
+              true, ws);
+    if (!ws) check_sweep_flag(x);
+    auto back = [&](auto zero) {
+        using real = decltype(zero);
+        if (x->dim == 2) run_psi_from_internal<real>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const real *)B.out, out);
+        else run_copy_from<real>(x->stream, na, (const real *)B.out, out);
+    };
+    if (x->fp32) back(0.0f);
+    else back(0.0);
+}
+
 static void raw_sweep(smrt_ctx *x, const double *sig_t, const double *sig, const double *q, const double *prev,
                       double inv_c_dt, const double *inflow64, double *out, double *mom, RawScratch *scratch = nullptr) {
-    const int64_t na = (int64_t)x->nang * x->G * x->nn;
-    const int64_t tab_cells = x->dim == 2 ? 4 * cell_slab(x->nx, x->ny) : x->ncell;
+    const int64_t tab_cells = raw_tab_cells(x);
     RawScratch local;
     RawScratch &R = scratch ? *scratch : local;
     ensure(R.sig2, tab_cells * x->G * 2 * x->rs);
@@ -831,38 +893,9 @@ static void raw_sweep(smrt_ctx *x, const double *sig_t, const double *sig, const
     ensure(R.in, psi_count(x) * x->rs);
     ensure(R.out, psi_count(x) * x->rs);
     ensure(R.inflow, (int64_t)x->nang * x->G * x->NB * x->rs);
-    DevBuf<unsigned char> &t_sig2 = R.sig2, &t_qiso = R.qiso, &t_in = R.in, &t_out = R.out, &t_inflow = R.inflow;
-    auto tables = [&](auto zero) {
-        using real = decltype(zero);
-        if (x->dim == 2) {
-            run_stab2d<real>(x->stream, x->nx, x->ny, x->G, sig, sig_t, 0.0, (real *)t_sig2.p);
-            run_qtab2d<real, double>(x->stream, x->nx, x->ny, x->G, q, x->G, 1, (real *)t_qiso.p);
-        } else {
-            run_sig_to_internal<real>(x->stream, x->ncell, x->G, sig_t, sig, (real *)t_sig2.p);
-            run_qiso_to_internal<real>(x->stream, x->nn, x->G, x->npc, q, (real *)t_qiso.p);
-        }
-        if (prev) {
-            if (x->dim == 2) run_psi_to_internal<real>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, prev, (real *)t_in.p);
-            else run_copy_to<real>(x->stream, na, prev, (real *)t_in.p);
-        }
-        if (inflow64) run_copy_to<real>(x->stream, (int64_t)x->nang * x->G * x->NB, inflow64, (real *)t_inflow.p);
-    };
-    if (x->fp32) tables(0.0f);
-    else tables(0.0);
-    if (!mom) {
-        ensure(R.mom, (int64_t)(x->dim == 2 ? 27 : 8) * x->nn);
-        mom = R.mom.p;
-    }
-    run_sweep(x, prev ? t_in.p : nullptr, t_out.p, t_sig2.p, t_qiso.p, inflow64 ? t_inflow.p : x->d_inflow.p, inv_c_dt,
-              sig, mom);
-    check_sweep_flag(x);
-    auto back = [&](auto zero) {
-        using real = decltype(zero);
-        if (x->dim == 2) run_psi_from_internal<real>(x->stream, x->nx, x->ny, x->G, x->nang, x->d_dir_quad.p, (const real *)t_out.p, out);
-        else run_copy_from<real>(x->stream, na, (const real *)t_out.p, out);
-    };
-    if (x->fp32) back(0.0f);
-    else back(0.0);
+    if (!mom) ensure(R.mom, (int64_t)(x->dim == 2 ? 27 : 8) * x->nn);
+    const RawBufs B{R.sig2.p, R.qiso.p, R.in.p, R.out.p, R.inflow.p, R.mom.p};
+    raw_sweep_with(x, sig_t, sig, q, prev, inv_c_dt, inflow64, out, mom, B, nullptr);
     SMRT_HIP(hipStreamSynchronize(x->stream));
 }
 
@@ -921,6 +954,110 @@ extern "C" smrt_status smrt_sweep_dev(smrt_ctx *x, const double *sig_t, const do
         read_small(x, &hb, bad.p, sizeof(int));
         require(hb == 0, "sig_t must be > 0 and sig >= 0");
         raw_sweep(x, sig_t, sig, q_iso, psi_prev, inv_c_dt, psi_inflow, psi_out, moments_out);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free sweep (smrt_sweep_dev_static): every per-call work array of
+// smrt_sweep_dev (input tables, internal intensities, moment partials, trace
+// words, counters, the opacity check flag) lives in one static device array,
+// so the call allocates nothing.  The array's device address is looked up
+// once per device; host code uses that address, never the array's name.
+// ---------------------------------------------------------------------------
+constexpr size_t SWEEP_SCRATCH_BYTES = (size_t)64 << 20;   // per GPU, held until the process ends
+static __device__ __align__(256) unsigned char scratch[SWEEP_SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// the static array's address on the current device (looked up on first use)
+static unsigned char *static_scratch() {
+    int dev = 0;
+    SMRT_HIP(hipGetDevice(&dev));
+    require(dev >= 0 && dev < SCRATCH_MAX_DEVICES, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SMRT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        require(p != nullptr, "hipGetSymbolAddress returned no address for the static scratch");
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+__global__ void k_fill_u64(int64_t n, uint64_t *p, uint64_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_i32(int n, int *p, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Regions of the static array, 256-byte aligned, in a fixed order.
+struct ScratchPlan {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    }
+};
+
+extern "C" smrt_status smrt_sweep_dev_static(smrt_ctx *x, const double *sig_t, const double *sig, const double *q_iso,
+                                             const double *psi_prev, double inv_c_dt, const double *psi_inflow,
+                                             double *psi_out, double *moments_out) {
+    if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
+    return guard(x, [&] {
+        require(sig_t && sig && q_iso && psi_out, "sig_t, sig, q_iso and psi_out are required");
+        require(std::isfinite(inv_c_dt) && inv_c_dt >= 0.0, "inv_c_dt must be finite and >= 0");
+        const int64_t tab_cells = raw_tab_cells(x);
+        const bool two_d = x->dim == 2;
+        ScratchPlan plan;
+        const size_t o_sig2 = plan.take((size_t)(tab_cells * x->G * 2 * x->rs));
+        const size_t o_qiso = plan.take((size_t)(tab_cells * x->G * x->npc * x->rs));
+        const size_t o_in = plan.take(psi_prev ? (size_t)(psi_count(x) * x->rs) : 0);
+        const size_t o_out = plan.take((size_t)(psi_count(x) * x->rs));
+        const size_t o_inflow = plan.take(psi_inflow ? (size_t)((int64_t)x->nang * x->G * x->NB * x->rs) : 0);
+        const size_t o_mom = plan.take(moments_out ? 0 : (size_t)((two_d ? 27 : 8) * x->nn) * sizeof(double));
+        const size_t o_part = plan.take(two_d ? (size_t)x->d_part.n : 0);
+        const size_t o_trace = plan.take(two_d ? (size_t)x->d_trace.n * sizeof(uint64_t) : 0);
+        const size_t o_flags = plan.take(8 * sizeof(int));   // ctr[4], lctr[2], opacity flag
+        if (plan.off > SWEEP_SCRATCH_BYTES)
+            throw smrt::Error(SMRT_E_INVALID_ARG, "the problem needs " + std::to_string(plan.off) +
+                                                      " bytes of sweep work memory; the static scratch holds " +
+                                                      std::to_string(SWEEP_SCRATCH_BYTES) + " (use smrt_sweep_dev)");
+        unsigned char *base = static_scratch();
+        int *flags = reinterpret_cast<int *>(base + o_flags);
+        // clear what must start at zero, with fill kernels (no memset)
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, x->stream, 8, flags, 0);
+        SweepScratch ws;
+        if (two_d) {
+            ws.part = base + o_part;
+            ws.trace = reinterpret_cast<uint64_t *>(base + o_trace);
+            ws.ctr = flags;
+            ws.lctr = flags + 4;
+            hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, x->stream, ws.ctr);
+            const int64_t nt = x->d_trace.n;
+            if (nt > 0)
+                hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>((nt + 255) / 256, 1024)), dim3(256), 0,
+                                   x->stream, nt, ws.trace, (uint64_t)0);
+        }
+        const int64_t ng = (int64_t)x->ncell * x->G;
+        hipLaunchKernelGGL(k_check_opacities, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, x->stream, ng, sig_t, sig,
+                           flags + 6);
+        int hb = 0;
+        read_small(x, &hb, flags + 6, sizeof(int));
+        require(hb == 0, "sig_t must be > 0 and sig >= 0");
+        const RawBufs B{base + o_sig2, base + o_qiso, psi_prev ? base + o_in : nullptr, base + o_out,
+                        psi_inflow ? base + o_inflow : nullptr, reinterpret_cast<double *>(base + o_mom)};
+        raw_sweep_with(x, sig_t, sig, q_iso, psi_prev, inv_c_dt, psi_inflow, psi_out, moments_out, B,
+                       two_d ? &ws : nullptr);
+        if (two_d) {
+            int fl = 0;
+            read_small(x, &fl, ws.ctr + 3, sizeof(int));
+            if (fl) throw smrt::Error(SMRT_E_DEVICE, "sweep band-trace wait exceeded its bound");
+        }
+        SMRT_HIP(hipStreamSynchronize(x->stream));
     });
 }
 

@@ -92,6 +92,8 @@ _SIGS = {
     "smrt_sweep": ([C.c_void_p, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp], C.c_int),
     "smrt_sweep_dev": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                         C.c_void_p, C.c_void_p], C.c_int),
+    "smrt_sweep_dev_static": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                               C.c_void_p, C.c_void_p], C.c_int),
     "smrt_compute_closures": ([C.c_void_p, _dp, _dp, _dp, _dp, _dp, C.c_double, _dp], C.c_int),
     "smrt_lo_solve": ([C.c_void_p, _dp, _dp, C.c_double, _dp, _dp, _dp, C.POINTER(StepStats)], C.c_int),
     "smrt_step": ([C.c_void_p, C.c_double, C.POINTER(StepStats)], C.c_int),
@@ -266,9 +268,11 @@ class Context:
                                       _p(mom)))
         return psi, mom
 
-    def sweep_dev(self, sig_t, sig, q_iso, psi_prev, inv_c_dt, inflow=None, psi_out=None, moments_out=None):
+    def sweep_dev(self, sig_t, sig, q_iso, psi_prev, inv_c_dt, inflow=None, psi_out=None, moments_out=None,
+                  static_scratch=False):
         """smrt_sweep on device tensors (float64, contiguous, on the context's GPU), no host round trip.
-        Returns (psi_out, moments_out or None); psi_out is allocated if not given."""
+        Returns (psi_out, moments_out or None); psi_out is allocated if not given.  static_scratch=True
+        calls the allocation-free entry point (work arrays in the library's static device array)."""
         import torch
         p = self.p
         want = {"sig_t": (p.n_cells, p.G), "sig": (p.n_cells, p.G), "q_iso": (p.n_nodes, p.G),
@@ -285,8 +289,9 @@ class Context:
                 raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {want[name]}")
         ptr = {k: (v.data_ptr() if v is not None else None) for k, v in args.items()}
         torch.cuda.current_stream(sig_t.device).synchronize()   # inputs ready before the context stream reads them
-        self._check(self.L.smrt_sweep_dev(self.h, ptr["sig_t"], ptr["sig"], ptr["q_iso"], ptr["psi_prev"],
-                                          float(inv_c_dt), ptr["inflow"], ptr["psi_out"], ptr["moments_out"]))
+        fn = self.L.smrt_sweep_dev_static if static_scratch else self.L.smrt_sweep_dev
+        self._check(fn(self.h, ptr["sig_t"], ptr["sig"], ptr["q_iso"], ptr["psi_prev"], float(inv_c_dt), ptr["inflow"],
+                       ptr["psi_out"], ptr["moments_out"]))
         return psi_out, moments_out
 
     def adjoint_sweep(self, sig_t, src, emis=None, psi_fwd=None, want_dsig=False):
