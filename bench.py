@@ -71,35 +71,133 @@ def sweep_kernel_name(info):
     return f"sweep2d_kernel<float, {k}, {prefetch}, {nw}, {nb}, false>"
 
 
-def cpu_baseline(p, sample_groups=16):
-    """FP64 oracle sweep + moments on the same mesh, angles and opacities
-    (the first `sample_groups` groups; all 16 by default: one full sweep),
-    single thread."""
+def planck_group_fractions(nu_edges, T):
+    """Fractions b_g(T) of a c T^4 in the groups [nu_g, nu_g+1) (the first from
+    0, the last to infinity) for an array of temperatures, from the standard
+    series for the Planck integral: below x = nu/T < 1 its Taylor series
+    (Bernoulli coefficients), above it the exponential series.  Input preparation of the CPU baseline
+    only (the oracle's own spectra integrate numerically)."""
+    import numpy as np
+
+    def below(x):
+        x = np.asarray(x, dtype=np.float64)
+        out = np.empty_like(x)
+        small = x < 1.0
+        xs = x[small]
+        # sum_n B_n x^(n+3) / (n! (n+3)) through x^17
+        out[small] = (xs ** 3 / 3 - xs ** 4 / 8 + xs ** 5 / 60 - xs ** 7 / 5040 + xs ** 9 / 272160
+                      - xs ** 11 / 13305600 + xs ** 13 / 622702080 - 691 * xs ** 15 / 19615115520000
+                      + 7 * xs ** 17 / 8892185702400) * 15 / np.pi ** 4
+        xl = x[~small]
+        above = np.zeros_like(xl)
+        for k in range(1, 60):
+            above += np.exp(-k * xl) * (xl ** 3 / k + 3 * xl ** 2 / k ** 2 + 6 * xl / k ** 3 + 6 / k ** 4)
+        out[~small] = 1.0 - above * 15 / np.pi ** 4
+        return out
+
+    nu = np.asarray(nu_edges, dtype=np.float64)
+    G = len(nu) - 1
+    Fb = np.stack([below(nu[g] / T) if g > 0 else np.zeros_like(T) for g in range(G)] + [np.ones_like(T)], axis=1)
+    return np.diff(Fb, axis=1)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, mid, reps=5):
+    """The FP64 oracle's sweep + moments on the inputs of the timed GPU sweep
+    (the mid-run state: opacities from its T, emission source sigma a c T^4
+    b_g(T) / 4 pi, its intensity as the time-edge source, the boundary
+    inflow), median of `reps` sweeps: all 16 groups on every host thread the
+    oracle's OpenMP sweep uses, and group 1 alone on one thread."""
+    import copy
     import numpy as np
     import oracle
-    from paper_2504_21784_amd import workloads as W
 
-    T = p.initial_T_nodes()
-    sig = oracle.Oracle(p).opacity(T)
-    q = W.multigroup_2d()
-    q.G = sample_groups
-    q.nu_edges = p.nu_edges[:sample_groups + 1]
-    o = oracle.Oracle(q)
-    sigt = sig[:, :sample_groups] + 1.0 / (p.c * p.dt)
+    T, psi = mid["T"], mid["psi"]
     full = oracle.Oracle(p)
-    b = np.array([full.spectra(t)[0][:sample_groups] for t in T[:1]])[0]
-    B = p.a * p.c * T ** 4 / (4 * np.pi)
-    qiso = sig[np.arange(p.n_nodes) // 4, :sample_groups] * (B[:, None] * b[None, :])
-    psi0 = np.broadcast_to((B[None, None, :] * b[None, :, None]), (p.n_angles, sample_groups, p.n_nodes)).copy()
-    inflow = full.inflow()[:, :sample_groups, :]
-    t0 = time.perf_counter()
-    psi = o.sweep(sigt, qiso, psi0, 1.0 / (p.c * p.dt), inflow)
-    o.moments(sig[:, :sample_groups], psi)
-    dt = time.perf_counter() - t0
-    units = p.n_cells * p.n_angles * sample_groups
-    return {"value": units / dt, "unit": "units/s", "cores": 1, "kind": "oracle",
-            "sample": f"same 256x256 S8 workload, groups 1-{sample_groups} of {p.G} "
-                      f"({units / 1e6:.2f} M units): FP64 sweep + moments, 1 thread, {dt:.1f} s"}
+    sig = full.opacity(T)
+    sigt = sig + 1.0 / (p.c * p.dt)
+    b = planck_group_fractions(p.nu_edges, T)
+    q = sig[np.arange(p.n_nodes) // 4] * (p.a * p.c * T ** 4 / (4 * np.pi))[:, None] * b
+    inflow = full.inflow()
+    icdt = 1.0 / (p.c * p.dt)
+
+    def run(G, threads):
+        n_thr = oracle.set_threads(threads)
+        sub = copy.copy(p)
+        sub.G = G
+        sub.nu_edges = p.nu_edges[:G + 1]
+        o = oracle.Oracle(sub) if G != p.G else full
+        args = [np.ascontiguousarray(a) for a in (sigt[:, :G], q[:, :G], psi[:, :G, :], inflow[:, :G, :])]
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = o.sweep(args[0], args[1], args[2], icdt, args[3])
+            o.moments(np.ascontiguousarray(sig[:, :G]), out)
+            ts.append(time.perf_counter() - t0)
+        units = p.n_cells * p.n_angles * G
+        return units / float(np.median(ts)), n_thr, float(np.median(ts)), units
+
+    v_all, n_all, t_all, u_all = run(p.G, 0)
+    v_one, _, t_one, u_one = run(1, 1)
+    oracle.set_threads(0)
+    return {"value": v_all, "unit": "units/s", "cores": n_all, "kind": "oracle",
+            "sample": f"mid-run 256x256 S8 G16 inputs: FP64 sweep + moments of all {u_all / 1e6:.1f} M units on "
+                      f"{n_all} threads (OpenMP over (angle, group) pairs), median of {reps}: {t_all:.2f} s",
+            "one_thread": {"value": v_one, "unit": "units/s", "cores": 1,
+                           "sample": f"group 1 only ({u_one / 1e6:.2f} M units), 1 thread, median of {reps}: "
+                                     f"{t_one:.2f} s"},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def c3_oracle_errors():
+    """One step of the 256x256 S8 G16 workload from its initial state, FP32
+    sweep + FP64 low order and all-FP64, both iterated to the tight
+    tolerances of the stored FP64 oracle step (tests/golden/c3_step1_oracle.npz,
+    written by tests/golden/make_c3_step.py): relative L2 and pointwise
+    (floor 1e-12 of the max) errors of phi, T and E at its 4096 stored
+    nodes, and the relative error of the total energy."""
+    import numpy as np
+    from paper_2504_21784_amd import smrt, workloads as W
+
+    path = os.path.join(ROOT, "tests", "golden", "c3_step1_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path, allow_pickle=False)
+    opts = {str(k): float(v) for k, v in zip(g["opt_names"], g["opts"])}
+    for k in ("max_outer", "max_inner", "max_cg"):
+        opts[k] = int(opts[k])
+    p = W.multigroup_2d()
+    hx, hy = np.diff(p.x_edges), np.diff(p.y_edges)
+    V = np.repeat((hx[None, :] * hy[:, None]).ravel() / 4.0, 4)
+    cv = np.repeat(np.asarray(p.cv)[np.asarray(p.region_of_cell)], 4)
+    res = {"workload": "one step of multigroup_2d (256x256 S8 G16) from its initial state, outer 1e-11, "
+                       "inner 1e-12, CG 1e-13; errors at 4096 sampled nodes against the stored FP64 oracle step",
+           "oracle_outer": int(g["outer"])}
+    for name, prec in (("fp32_sweep", smrt.SMRT_FP32), ("fp64", smrt.SMRT_FP64)):
+        ctx = smrt.Context(p, precision=prec, lo_graphs=LO_GRAPHS, **opts)
+        ctx.set_state(p.initial_T_nodes())
+        st = ctx.step()
+        s = ctx.get_state()
+        ctx.close()
+        phi = np.einsum("d,dgn->n", p.w, s["psi"])
+        e = {"outer": int(st["outer"])}
+        for f, field in (("phi", phi), ("T", s["T"]), ("E", s["E"])):
+            ref, got = g[f], field[g["nodes"]]
+            e[f + "_rel_l2"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            e[f + "_pointwise"] = float((np.abs(got - ref) / np.maximum(np.abs(ref), 1e-12 * float(g[f + "_max"]))).max())
+        energy = float(np.sum(V * (s["E"] + cv * s["T"])))
+        e["energy_rel"] = abs(energy - float(g["energy"])) / abs(float(g["energy"]))
+        res[name] = e
+    return res
 
 
 def batched(args):
@@ -279,6 +377,8 @@ def main():
     ap.add_argument("--no-step", action="store_true", help="skip the full time-step measurement")
     ap.add_argument("--no-multigrid", action="store_true", help="skip the LO preconditioner comparison")
     ap.add_argument("--no-qmesh", action="store_true", help="skip the unstructured-mesh sweep")
+    ap.add_argument("--no-oracle-error", action="store_true",
+                    help="skip the full-size step against the stored oracle step")
     ap.add_argument("--lo-graphs", type=int, default=1, choices=(0, 1),
                     help="0: launch the LO conjugate-gradient kernels directly instead of replaying graphs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -431,6 +531,8 @@ def main():
     }
     if not args.no_step:
         out["time_step"] = time_steps(p, T0)
+    if not args.no_oracle_error:
+        out["error_vs_oracle_c3_step"] = c3_oracle_errors()
     if not args.no_batch:
         out["batched"] = batched(args)
     if not args.no_adjoint:
@@ -440,7 +542,7 @@ def main():
     if not args.no_qmesh:
         out["qmesh_sweep"] = qmesh_sweep()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
+        out["cpu_baseline"] = cpu_baseline(p, mid)
     print(json.dumps(out), flush=True)
 
 

@@ -19,9 +19,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C11, -O2, single threaded)."""
+    """Compile the oracle with gcc (plain C11, -O2; OpenMP only spreads the
+    sweep's independent (direction, group) pairs over threads)."""
     if force or not os.path.exists(_LIB):
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fopenmp", "-fPIC", "-shared", "-o", _LIB, _SRC,
+                               "-lm"])
     return _LIB
 
 
@@ -40,7 +42,7 @@ def build_variant(path: str, edits) -> C.CDLL:
     csrc = path + ".c"
     with open(csrc, "w") as f:
         f.write(src)
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-w", "-fPIC", "-shared", "-o", path, csrc, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-w", "-fopenmp", "-fPIC", "-shared", "-o", path, csrc, "-lm"])
     L = C.CDLL(path)
     _declare(L)
     return L
@@ -54,6 +56,12 @@ def lib():
         _lib = C.CDLL(_LIB)
         _declare(_lib)
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's sweep (0: the OpenMP default); returns the
+    count its next sweep uses.  Results do not depend on it."""
+    return lib().orc_set_threads(int(n))
 
 
 _dp = C.POINTER(C.c_double)
@@ -101,6 +109,8 @@ def _declare(L):
     L.orc_opacity.argtypes = [gp, mp, _dp, _dp]
     L.orc_sweep.argtypes = [gp, _dp, _dp, _dp, C.c_double, _dp, C.c_int, _dp]
     L.orc_sweep.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = C.c_int
     L.orc_adjoint_sweep.argtypes = [gp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_adjoint_sweep.restype = C.c_int
     L.orc_adjoint_gradient.argtypes = [gp, mp, bp, C.POINTER(Opts), C.c_double, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp,

@@ -14,7 +14,9 @@
  * the trapezoid (2-point Gauss-Lobatto) lumping, solved by Gaussian
  * elimination with partial pivoting; moments and closures summed
  * direction by direction; the low-order operator applied from an
- * explicitly assembled sparse divergence matrix.  Single threaded.
+ * explicitly assembled sparse divergence matrix.  Single threaded, except
+ * that the sweep may run its independent (direction, group) pairs on
+ * several OpenMP threads (the results do not depend on the thread count).
  *
  * Conventions.
  *   cell c = i + nx*j; local node l = lx + 2*ly (1D: l = lx);
@@ -28,6 +30,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846264338327950288
@@ -311,63 +316,86 @@ static void zero_and_scale(int np, const double *colsum, double src, double *x)
 /*   q_l = q_iso[l][g] + inv_c_dt * psi_prev[d][g][l]                       */
 /* ------------------------------------------------------------------------ */
 
-int orc_sweep(const orc_geom *g, const double *sig_t, const double *q_iso, const double *psi_prev,
-              double inv_c_dt, const double *inflow, int fixup, double *psi)
+/* one (direction d, group k) pair of orc_sweep */
+static int sweep_pair(const orc_geom *g, int d, int k, const double *sig_t, const double *q_iso,
+                      const double *psi_prev, double inv_c_dt, const double *inflow, int fixup, double *psi)
 {
     int nx = g->nx, ny = g->dim == 2 ? g->ny : 1, np = npc(g), G = g->G, nn = nnode(g), NB = nbnode(g);
-    for (int d = 0; d < g->nang; ++d) {
-        int fwdx = om_ax(g, d, 0) > 0.0, fwdy = g->dim == 2 ? om_ax(g, d, 1) > 0.0 : 1;
-        for (int k = 0; k < G; ++k) {
-            const double *pp = psi_prev ? psi_prev + ((size_t)d * G + k) * nn : NULL;
-            double *out = psi + ((size_t)d * G + k) * nn;
-            const double *inf = inflow ? inflow + ((size_t)d * G + k) * NB : NULL;
-            for (int jj = 0; jj < ny; ++jj) {
-                int j = fwdy ? jj : ny - 1 - jj;
-                for (int ii = 0; ii < nx; ++ii) {
-                    int i = fwdx ? ii : nx - 1 - ii;
-                    int c = i + nx * j;
-                    double A[16], b[4], x[4];
-                    double wv = vol_weight(g, i, j), st = sig_t[(size_t)c * G + k];
-                    for (int l = 0; l < np; ++l) {
-                        double q = q_iso[(size_t)(np * c + l) * G + k];
-                        if (pp) q += inv_c_dt * pp[np * c + l];
-                        b[l] = wv * q;
-                        for (int m = 0; m < np; ++m) {
-                            double og = 0.0;
-                            for (int ax = 0; ax < g->dim; ++ax) og += om_ax(g, d, ax) * dbasis(g, i, j, l, m, ax);
-                            A[l * np + m] = (l == m ? st * wv : 0.0) - wv * og;
-                        }
-                        for (int ax = 0; ax < g->dim; ++ax) {
-                            for (int sd = 0; sd < 2; ++sd) {
-                                if (!node_on_face(l, ax, sd)) continue;
-                                double on = om_ax(g, d, ax) * (sd ? 1.0 : -1.0);
-                                double fw = face_weight(g, i, j, ax);
-                                if (on > 0.0) {
-                                    A[l * np + l] += on * fw;
-                                } else {
-                                    int nb = neighbour(g, i, j, ax, sd);
-                                    double up;
-                                    if (nb >= 0) up = out[np * nb + mirror(l, ax)];
-                                    else up = inf ? inf[bnode_index(g, i, j, ax, sd, l)] : 0.0;
-                                    b[l] -= on * fw * up;
-                                }
-                            }
+    int fwdx = om_ax(g, d, 0) > 0.0, fwdy = g->dim == 2 ? om_ax(g, d, 1) > 0.0 : 1;
+    const double *pp = psi_prev ? psi_prev + ((size_t)d * G + k) * nn : NULL;
+    double *out = psi + ((size_t)d * G + k) * nn;
+    const double *inf = inflow ? inflow + ((size_t)d * G + k) * NB : NULL;
+    for (int jj = 0; jj < ny; ++jj) {
+        int j = fwdy ? jj : ny - 1 - jj;
+        for (int ii = 0; ii < nx; ++ii) {
+            int i = fwdx ? ii : nx - 1 - ii;
+            int c = i + nx * j;
+            double A[16], b[4], x[4];
+            double wv = vol_weight(g, i, j), st = sig_t[(size_t)c * G + k];
+            for (int l = 0; l < np; ++l) {
+                double q = q_iso[(size_t)(np * c + l) * G + k];
+                if (pp) q += inv_c_dt * pp[np * c + l];
+                b[l] = wv * q;
+                for (int m = 0; m < np; ++m) {
+                    double og = 0.0;
+                    for (int ax = 0; ax < g->dim; ++ax) og += om_ax(g, d, ax) * dbasis(g, i, j, l, m, ax);
+                    A[l * np + m] = (l == m ? st * wv : 0.0) - wv * og;
+                }
+                for (int ax = 0; ax < g->dim; ++ax) {
+                    for (int sd = 0; sd < 2; ++sd) {
+                        if (!node_on_face(l, ax, sd)) continue;
+                        double on = om_ax(g, d, ax) * (sd ? 1.0 : -1.0);
+                        double fw = face_weight(g, i, j, ax);
+                        if (on > 0.0) {
+                            A[l * np + l] += on * fw;
+                        } else {
+                            int nb = neighbour(g, i, j, ax, sd);
+                            double up;
+                            if (nb >= 0) up = out[np * nb + mirror(l, ax)];
+                            else up = inf ? inf[bnode_index(g, i, j, ax, sd, l)] : 0.0;
+                            b[l] -= on * fw * up;
                         }
                     }
-                    double colsum[4], src = 0.0;
-                    for (int m = 0; m < np; ++m) {
-                        colsum[m] = 0.0;
-                        for (int l = 0; l < np; ++l) colsum[m] += A[l * np + m];
-                        src += b[m];
-                    }
-                    if (lu_solve(np, A, b, x)) return -1;
-                    if (fixup) zero_and_scale(np, colsum, src, x);
-                    for (int l = 0; l < np; ++l) out[np * c + l] = x[l];
                 }
             }
+            double colsum[4], src = 0.0;
+            for (int m = 0; m < np; ++m) {
+                colsum[m] = 0.0;
+                for (int l = 0; l < np; ++l) colsum[m] += A[l * np + m];
+                src += b[m];
+            }
+            if (lu_solve(np, A, b, x)) return -1;
+            if (fixup) zero_and_scale(np, colsum, src, x);
+            for (int l = 0; l < np; ++l) out[np * c + l] = x[l];
         }
     }
     return ORC_OK;
+}
+
+/* The (d, g) pairs are independent (each writes only its own psi[d][g]),
+ * so they may run on several threads (OpenMP, when compiled with it):
+ * every result is the same whatever the thread count. */
+int orc_sweep(const orc_geom *g, const double *sig_t, const double *q_iso, const double *psi_prev,
+              double inv_c_dt, const double *inflow, int fixup, double *psi)
+{
+    int npairs = g->nang * g->G, fail = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : fail)
+    for (int pk = 0; pk < npairs; ++pk)
+        fail |= sweep_pair(g, pk / g->G, pk % g->G, sig_t, q_iso, psi_prev, inv_c_dt, inflow, fixup, psi) != ORC_OK;
+    return fail ? -1 : ORC_OK;
+}
+
+/* threads of the parallel sweep (OpenMP builds; 0 = the runtime default);
+ * returns the count the next sweep uses (1 without OpenMP) */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */
@@ -717,9 +745,12 @@ int orc_closures(const orc_geom *g, const orc_bc *bc, int scheme, double dt, con
             }
         }
     for (int n = 0; n < nn; ++n) E[n] = phi[n] / c;
-    /* gray opacities (Eqs. sigmaE, sigmaF and the Planck collapse) */
+    /* gray opacities (Eqs. sigmaE, sigmaF and the Planck collapse); nodes are
+       independent (OpenMP threads, when built with it) */
+#pragma omp parallel for schedule(static)
     for (int n = 0; n < nn; ++n) {
         int cc = n / np;
+        double bg[G], rg[G];
         orc_spectra(G, g->nu, T_l[n], bg, rg);
         double sb = 0, sr = 0, sbs = 0, srs = 0;
         for (int k = 0; k < G; ++k) {
@@ -1120,8 +1151,11 @@ int orc_step(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_o
     int status = refl_bad ? -2 : ORC_OK;
     int maxo = refl_bad ? 0 : op->max_outer;
     for (int l = 1; l <= maxo; ++l) {
-        /* emission source at the current temperature iterate */
+        /* emission source at the current temperature iterate (nodes are
+           independent: OpenMP threads, when built with it) */
+#pragma omp parallel for schedule(static)
         for (int n = 0; n < nn; ++n) {
+            double bg[G], rg[G];
             orc_spectra(G, g->nu, Tl[n], bg, rg);
             double B = a * c * pow(Tl[n], 4);
             for (int k = 0; k < G; ++k) q[(size_t)n * G + k] = sig[(size_t)(n / np) * G + k] * B * bg[k] / (4.0 * M_PI);
@@ -1193,14 +1227,14 @@ int orc_step(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_o
 void orc_equilibrium_psi(const orc_geom *g, const double *T, double *psi)
 {
     int nn = nnode(g), G = g->G;
-    double *b = malloc(sizeof(double) * G), *r = malloc(sizeof(double) * G);
+#pragma omp parallel for schedule(static)
     for (int n = 0; n < nn; ++n) {
+        double b[G], r[G];
         orc_spectra(G, g->nu, T[n], b, r);
         double B = g->a * g->c * pow(T[n], 4);
         for (int d = 0; d < g->nang; ++d)
             for (int k = 0; k < G; ++k) psi[((size_t)d * G + k) * nn + n] = B * b[k] / (4.0 * M_PI);
     }
-    free(b); free(r);
 }
 
 /* ------------------------------------------------------------------------ */

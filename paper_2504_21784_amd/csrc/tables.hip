@@ -822,14 +822,28 @@ __global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkR
 #pragma unroll
     for (int k = 0; k < NMOM2D; ++k) acc[k] = 0.0;
     const r2 *pp = reinterpret_cast<const r2 *>(part);
-    for (int qc = cr.start[q]; qc < cr.start[q + 1]; ++qc) {
-        const r2 v = pp[(((int64_t)qc * nb + band) * NT + t) * 64 + lc * BAND_ROWS + rc];
-        const double *cw = dirs + 8 * qc_dir[qc] + 2;   // w, w mu, w eta, w mu^2, w mu eta, w eta^2
-        const double sI = (double)v.x, sS = (double)v.y;
+    // the quadrant's chunks in order, loads issued 8 chunks at a time so that
+    // several are in flight (the sum keeps the chunk order)
+    constexpr int U = 8;
+    const int64_t stride = (int64_t)nb * NT * 64;
+    const r2 *base = pp + ((int64_t)band * NT + t) * 64 + lc * BAND_ROWS + rc;
+    for (int qc0 = cr.start[q]; qc0 < cr.start[q + 1]; qc0 += U) {
+        r2 v[U];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) acc[k] += cw[k] * sI;
+        for (int u = 0; u < U; ++u) {
+            const int qc = qc0 + u < cr.start[q + 1] ? qc0 + u : qc0;
+            v[u] = base[qc * stride];
+        }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) acc[6 + k] += cw[k] * sS;
+        for (int u = 0; u < U; ++u) {
+            if (qc0 + u >= cr.start[q + 1]) break;
+            const double *cw = dirs + 8 * qc_dir[qc0 + u] + 2;   // w, w mu, w eta, w mu^2, w mu eta, w eta^2
+            const double sI = (double)v[u].x, sS = (double)v[u].y;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[k] += cw[k] * sI;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[6 + k] += cw[k] * sS;
+        }
     }
     const bool fx = (q == 1 || q == 2), fy = (q == 2 || q == 3);
     const int i = fx ? nx - 1 - ic : ic, j = fy ? ny - 1 - jc : jc;

@@ -1,11 +1,14 @@
 """GPU parity at the benchmark's full size and launch: the 256x256 bilinear-DG
-mesh, level-symmetric S8 (40 angles), 16 groups, with the 5-wave,
-1-group-per-lane launch that bench.py times (FP32, the timed form, and FP64),
-on seeded random inputs of the workload's shapes.
+mesh, level-symmetric S8 (40 angles), 16 groups, with the automatic launch
+that bench.py times (16 bands per workgroup, one group per lane; FP32, the
+timed form, and FP64), on seeded random inputs of the workload's shapes.
 
 * Sampled outputs: three whole groups (every angle and node) are swept by the
   FP64 oracle and compared element by element (1e-5 of the field's maximum
-  in FP32, 1e-10 in FP64).
+  in FP32, 1e-10 in FP64), and pointwise (relative to each value, floored at
+  1e-12 of the max: 5e-2 in FP32, where these random inputs make the
+  intensity change sign and values near a sign change keep only absolute
+  accuracy, 1e-9 in FP64).
 * A property at any size: the fused moments the sweep returns equal the
   moments recomputed in FP64 from the sweep's own angular flux (quadrant
   phi, F, Pi and the sigma-weighted full-range phi, F), so the partial
@@ -15,6 +18,7 @@ import copy
 
 import numpy as np
 import pytest
+from parity import rel_pointwise
 
 from paper_2504_21784_amd import workloads as W
 
@@ -34,8 +38,8 @@ def _quadrant(mu, eta):
     return 1 if eta > 0 else 2
 
 
-@pytest.mark.parametrize("prec,tol,mtol", [(1, 1e-5, 1e-5), (0, 1e-10, 1e-12)])
-def test_full_size_sweep_sampled_groups_and_moments(smrt_mod, oracle_mod, prec, tol, mtol):
+@pytest.mark.parametrize("prec,tol,mtol,pw", [(1, 1e-5, 1e-5, 5e-2), (0, 1e-10, 1e-12, 1e-9)])
+def test_full_size_sweep_sampled_groups_and_moments(smrt_mod, oracle_mod, prec, tol, mtol, pw):
     p = W.multigroup_2d()
     assert (p.nx, p.ny, p.n_angles, p.G) == (256, 256, 40, 16)
     print(f"full size: 256x256 S8 G16, precision {prec}, the benchmark's launch", flush=True)
@@ -55,7 +59,10 @@ def test_full_size_sweep_sampled_groups_and_moments(smrt_mod, oracle_mod, prec, 
     ref = o.sweep(np.ascontiguousarray(sigt[:, S]), np.ascontiguousarray(q[:, S]),
                   np.ascontiguousarray(pp[:, S, :]), icdt, np.ascontiguousarray(inf[:, S, :]))
     for i, g in enumerate(S):
+        e_pw = rel_pointwise(psi[:, g, :], ref[:, i, :])
+        print(f"  group {g}: max-normalised {_rel(psi[:, g, :], ref[:, i, :]):.3e}, pointwise {e_pw:.3e}", flush=True)
         assert _rel(psi[:, g, :], ref[:, i, :]) < tol, g
+        assert e_pw < pw, g
 
     # fused moments against moments recomputed from the returned flux
     nn = p.n_nodes

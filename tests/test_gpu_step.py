@@ -4,10 +4,14 @@ backward-Euler SM steps against the FP64 oracle (through the C ABI).
 FP64 results agree to 1e-10 relative when both sides iterate to tight
 tolerances; with the paper's tolerances the outer iteration count matches
 within +-1.  The FP32 sweep keeps flux within 1e-5 and temperature within
-1e-6 of the FP64 oracle over several steps.
+1e-6 of the FP64 oracle over several steps.  Next to the max-normalised
+errors the pointwise relative error (floored at 1e-12 of the max) is
+asserted: the state fields of a step stay positive, so the same bounds hold
+pointwise (FP64 1e-10; FP32 1e-5 for phi, E and I, 1e-6 for T).
 """
 import numpy as np
 import pytest
+from parity import rel_pointwise
 
 from paper_2504_21784_amd import workloads as W
 
@@ -119,9 +123,9 @@ def test_step_fp64_matches_oracle_2d(smrt_mod, oracle_mod, scheme):
     if scheme == 2:
         opts["max_outer"] = 2000
     for ref, ost, got, gst in _run_steps(smrt_mod, oracle_mod, p, 2, scheme, 0, opts):
-        assert _rel(got["T"], ref["T"]) < 1e-10
-        assert _rel(got["E"], ref["E"]) < 1e-10
-        assert _rel(got["psi"], ref["psi"]) < 1e-10
+        for k in ("T", "E", "psi"):
+            assert _rel(got[k], ref[k]) < 1e-10, k
+            assert rel_pointwise(got[k], ref[k]) < 1e-10, k
         assert abs(gst["outer"] - ost["outer"]) <= 1
 
 
@@ -137,6 +141,34 @@ def test_step_fp64_slab_paper_tolerances(smrt_mod, oracle_mod):
         assert _rel(got["T"], ref["T"]) < 1e-7
 
 
+def test_step_fp64_slab_replayed_outer_counts(smrt_mod, oracle_mod):
+    """The 1D gray slab (64 cells, S8, sigma = 10, c_v = 1, T0 = 0.01, left
+    inflow at T = 1, dt = 0.01, 10 steps), SM outer iteration to the paper's
+    1e-8, run on the GPU with exactly the oracle's per-step outer counts
+    (fixed_outer) and tight inner, CG and elimination tolerances on both
+    sides: T, E and I agree to 1e-10 relative (max-normalised and
+    pointwise), step by step."""
+    p = W.slab_1d(n_cells=64, n_angles=8)
+    opts = dict(eps_outer=1e-8, eps_inner=1e-12, cg_rtol=1e-13, elim_rtol=1e-15, max_outer=100, max_inner=60,
+                max_cg=3000)
+    o = oracle_mod.Oracle(p)
+    st = o.initial_state()
+    ctx = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP64, **opts)
+    ctx.set_state(st["T"])
+    for k in range(10):
+        r, st, ost = o.step(st, oracle_mod.default_opts(**opts))
+        assert r == 0 and ost["outer"] >= 1
+        ctx.set_options(fixed_outer=ost["outer"])
+        gst = ctx.step()
+        assert gst["outer"] == ost["outer"]
+        got = ctx.get_state()
+        print(f"step {k}: {ost['outer']} outer iterations; T error {_rel(got['T'], st['T']):.2e}", flush=True)
+        for key in ("T", "E", "psi"):
+            assert _rel(got[key], st[key]) < 1e-10, (k, key)
+            assert rel_pointwise(got[key], st[key]) < 1e-10, (k, key)
+    ctx.close()
+
+
 def test_step_fp32_error_budget(smrt_mod, oracle_mod):
     """FP32 sweep, FP64 low-order: phi within 1e-5 and T within 1e-6 (relative
     L2) of the FP64 oracle over several steps."""
@@ -147,6 +179,10 @@ def test_step_fp32_error_budget(smrt_mod, oracle_mod):
         phi = np.einsum("d,dgn->n", p.w, got["psi"])
         assert np.linalg.norm(phi - phi_ref) / np.linalg.norm(phi_ref) < 1e-5
         assert np.linalg.norm(got["T"] - ref["T"]) / np.linalg.norm(ref["T"]) < 1e-6
+        assert rel_pointwise(phi, phi_ref) < 1e-5
+        assert rel_pointwise(got["T"], ref["T"]) < 1e-6
+        assert rel_pointwise(got["E"], ref["E"]) < 1e-5
+        assert rel_pointwise(got["psi"], ref["psi"]) < 1e-5
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -159,15 +195,17 @@ def test_gray_2d_full_size_steps(smrt_mod, oracle_mod, prec):
     print(f"gray 2D 128x128 S8, precision {prec}", flush=True)
     for ref, ost, got, gst in _run_steps(smrt_mod, oracle_mod, p, 3, 0, prec, dict(TIGHT)):
         if prec == 0:
-            assert _rel(got["T"], ref["T"]) < 1e-10
-            assert _rel(got["E"], ref["E"]) < 1e-10
-            assert _rel(got["psi"], ref["psi"]) < 1e-10
+            for k in ("T", "E", "psi"):
+                assert _rel(got[k], ref[k]) < 1e-10, k
+                assert rel_pointwise(got[k], ref[k]) < 1e-10, k
             assert abs(gst["outer"] - ost["outer"]) <= 1
         else:
             phi_ref = np.einsum("d,dgn->n", p.w, ref["psi"])
             phi = np.einsum("d,dgn->n", p.w, got["psi"])
             assert np.linalg.norm(phi - phi_ref) / np.linalg.norm(phi_ref) < 1e-5
             assert np.linalg.norm(got["T"] - ref["T"]) / np.linalg.norm(ref["T"]) < 1e-6
+            assert rel_pointwise(phi, phi_ref) < 1e-5
+            assert rel_pointwise(got["T"], ref["T"]) < 1e-6
 
 
 def test_step_rejects_bad_dt(smrt_mod):

@@ -2,7 +2,11 @@
 oracle on identical seeded inputs (element by element), through the C ABI.
 
 FP64: <= 1e-10 relative (to the field's max); FP32: <= 1e-5 relative.  The
-pointwise relative error (floor 1e-12 of the field's max) is asserted too.
+pointwise relative error (relative to each value, floored at 1e-12 of the
+field's max) is asserted too: for the scalar flux (positive) 1e-13 in FP64
+and 1e-6 in FP32; for the angular flux, which these random inputs drive
+through sign changes (values near a sign change keep only absolute accuracy,
+about the rounding of the terms that cancel), 1e-9 in FP64 and 5e-2 in FP32.
 Shapes span several 16-row bands with ragged tails, several (angle, group)
 chunks, and the degenerate cases (one cell, one row, one band exactly).
 """
@@ -57,13 +61,17 @@ def test_sweep2d_fp64_matches_oracle(smrt_mod, oracle_mod, nx, ny, sn, G):
     print(f"  psi: max-normalised {_rel(psi, ref):.3e}, pointwise {pw:.3e}", flush=True)
     assert _rel(psi, ref) < 1e-10
     assert pw < PW64
+    phi = sum(mom[6 * k] for k in range(4))
+    phi_ref = sum(ref_mom[6 * k] for k in range(4))
+    assert rel_pointwise(phi, phi_ref) < PW64_PHI
     for m in range(27):
         assert _rel(mom[m], ref_mom[m]) < 1e-10, m
     ctx.close()
 
 
-# pointwise relative error bounds (floor 1e-12 of the max)
-PW64, PW32 = 1e-8, 1e-2
+# pointwise relative error bounds (floor 1e-12 of the max): angular flux, scalar flux
+PW64, PW32 = 1e-9, 5e-2
+PW64_PHI, PW32_PHI = 1e-13, 1e-6
 
 # (waves per band, bands per workgroup, groups per lane); (0, 0, 0) = automatic
 FP32_LAUNCHES = [(0, 0, 0), (1, 1, 1), (1, 2, 1), (1, 4, 1), (2, 2, 1), (4, 4, 1), (1, 16, 1), (2, 8, 1), (1, 4, 2),
@@ -90,6 +98,7 @@ def test_sweep2d_fp32_matches_oracle(smrt_mod, oracle_mod, nx, ny, sn, G, launch
     phi = sum(mom[6 * k] for k in range(4))
     phi_ref = sum(ref_mom[6 * k] for k in range(4))
     assert np.linalg.norm(phi - phi_ref) / np.linalg.norm(phi_ref) < 1e-5
+    assert rel_pointwise(phi, phi_ref) < PW32_PHI
     for m in range(27):
         assert _rel(mom[m], ref_mom[m]) < 1e-5, m
     ctx.close()
