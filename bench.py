@@ -464,7 +464,8 @@ def main():
     c64.step()
     step64 = (c64.get_moments(), c64.get_state(with_psi=False)["T"])
     c64.close()
-    del mid
+    if args.no_cpu_baseline:
+        del mid   # the CPU baseline sweeps the same mid-run inputs
 
     def rel_l2(a, b):
         return float(np.linalg.norm(a - b) / np.linalg.norm(b))
