@@ -156,7 +156,6 @@ typedef struct {
 /* Per-step statistics (the columns of the paper's summary tables). */
 typedef struct {
     int outer, inner_total, cg_total, elim_max, hit_max;
-    double energy_residual;
     double t_sweep_ms, t_lo_ms, t_total_ms;
 } smrt_step_stats;
 

@@ -97,7 +97,7 @@ class QGeom(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("outer", C.c_int), ("inner_total", C.c_int), ("cg_total", C.c_int),
-                ("elim_max", C.c_int), ("hit_max", C.c_int), ("energy_residual", C.c_double)]
+                ("elim_max", C.c_int), ("hit_max", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

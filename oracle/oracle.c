@@ -78,7 +78,6 @@ typedef struct {
 
 typedef struct {
     int outer, inner_total, cg_total, elim_max, hit_max;
-    double energy_residual;
 } orc_stats;
 
 /* ------------------------------------------------------------------------ */
@@ -1213,9 +1212,6 @@ int orc_step(const orc_geom *g, const orc_mat *mt, const orc_bc *bc, const orc_o
     }
     memcpy(T, Tl, sizeof(double) * nn);
     if (op->scheme != 2) memcpy(E_lo, El, sizeof(double) * nn);
-    /* total energy balance residual: sum w (E + cv T) change + dt * net LO boundary outflow
-       is reported by the tests from the returned state; here only a placeholder */
-    st->energy_residual = 0.0;
     lo_ops_free(&ops);
     free(sig); free(sigt); free(psi_prev); free(q); free(inflow); free(Tstar); free(Estar); free(Fstar);
     free(cvn); free(sigE); free(sigF); free(sigP); free(qE); free(qF); free(Tl); free(El); free(bg); free(rg);

@@ -58,7 +58,7 @@ class Options(C.Structure):
 
 class StepStats(C.Structure):
     _fields_ = [("outer", C.c_int), ("inner_total", C.c_int), ("cg_total", C.c_int), ("elim_max", C.c_int),
-                ("hit_max", C.c_int), ("energy_residual", C.c_double), ("t_sweep_ms", C.c_double),
+                ("hit_max", C.c_int), ("t_sweep_ms", C.c_double),
                 ("t_lo_ms", C.c_double), ("t_total_ms", C.c_double)]
 
     def as_dict(self):
