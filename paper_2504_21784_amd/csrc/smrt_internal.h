@@ -76,6 +76,8 @@ struct SweepLaunch {
     int wg_per_cu;                   // 0: as many as fit; n: pad LDS so at most n workgroups share a CU
     int *lctr;                       // [2]: ticket, workgroups done (both reset by the last workgroup)
     int fixup;                       // 1: zero-and-scale negative-flux fixup in every cell
+    int xw;                          // 1: some chunk spans several band groups (publishing and
+                                     //    receiving waves in every workgroup)
 };
 
 // Internal angular-flux layout (both precisions): [d][g][band][t][r][4 canonical nodes].

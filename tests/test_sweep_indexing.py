@@ -12,10 +12,13 @@ regular, ragged and degenerate meshes:
 * every access of a lane with work lies inside its allocation and inside
   the buffer resource it goes through, with a byte offset below 2^31;
 * every lane without work is marked out of range;
-* the trace words the top band of a workgroup publishes are exactly the words
-  the bottom band of the workgroup above reads, and each is written once;
+* the trace words the publishing wave of a workgroup writes (its top band's
+  outflow) are exactly the words the receiving wave of the workgroup above
+  reads, and each is written once;
 * the LDS hand-off slot a band writes at one step is the slot the band above
-  reads at the next barrier interval, and every LDS index stays inside its
+  (or the publishing wave) reads at the next barrier interval, the receiving
+  wave's slot for column c is written in the interval before the bottom band
+  reads it and not overwritten before, and every LDS index stays inside its
   array;
 * every wave of a workgroup passes the same number of barriers;
 * each moment partial of a (chunk, band, step) is stored once, and the
@@ -83,6 +86,8 @@ def check_shape(nx, ny, G, sn, NW, NBW, K, rs):
     NB = 4 * (nx + ny)
     gslab = nb * NT * BAND_ROWS
     n_groups = (nb + NBW - 1) // NBW
+    if n_groups > 1 and NW * NBW > 8:
+        return   # the planner rejects it: stacked band groups take at most 8 compute waves
     STEPS = prefetch_steps(rs, K, NW * NBW)
     NTP = (NT + STEPS - 1) // STEPS * STEPS
     # allocations (elements of the unit each array is addressed in)
@@ -94,6 +99,7 @@ def check_shape(nx, ny, G, sn, NW, NBW, K, rs):
     n_part = NQC * nb * NT * 64         # r2 records
     n_hand = 2 * NBW * NW * K * CHANNELS * 2
     n_ring = 2 * NBW * NW * 64
+    n_recv = 2 * NW * K * CHANNELS * 2
     assert CHANNELS * K * nb * NT * BAND_ROWS * 4 * rs < OOB, "planner would reject this mesh"
     written = np.zeros(n_trace, np.int32)
     read_words = np.zeros(n_trace, np.int32)
@@ -108,23 +114,38 @@ def check_shape(nx, ny, G, sn, NW, NBW, K, rs):
         d = slots[0][0]
         assert d >= 0, "slot 0 of a chunk must be active"
         for bg in range(n_groups):
-            hand_w = {}   # LDS hand-off writes: (parity, band slot, w, k, ch) -> (band, global iteration)
+            hand_w = {}   # LDS hand-off writes: (parity, band slot, w, k, ch, column) -> barrier interval
             barriers = []
+            XW = n_groups > 1
+            NSLOT = CHANNELS * K * NW
+            total = NTP + BAND_ROWS * (NBW - 1)   # barrier intervals after the first barrier
+            RP = 4                                # the receiving wave's columns in flight
+            active_iv = (nx - 1 + RP - 1) // RP * RP
+            # the receiving wave's LDS writes: column c < nx into slot c & 1 in
+            # interval c - 1 (column 0 before the first barrier); it writes
+            # columns up to active_iv, whose slots nobody reads past nx - 1
+            recv_w = {}
+            if XW and bg * NBW > 0:
+                assert active_iv <= total
+                for sl in range(NSLOT):
+                    sc, sk, sw = sl % CHANNELS, (sl // CHANNELS) % K, sl // (CHANNELS * K)
+                    for c in range(0, active_iv + 1):
+                        idx = ((((c & 1) * NW + sw) * K + sk) * CHANNELS + sc) * 2
+                        assert 0 <= idx and idx + 1 < n_recv
+                        recv_w[(c & 1, sw, sk, sc, c)] = c - 1
             for bw in range(NBW):
                 band = bg * NBW + bw
                 for w in range(NW):
                     if band >= nb:
-                        barriers.append(NTP + BAND_ROWS * (NBW - 1))
+                        barriers.append(1 + NTP + BAND_ROWS * (NBW - 1))
                         continue
-                    barriers.append(BAND_ROWS * bw + NTP + BAND_ROWS * (NBW - 1 - bw))
+                    barriers.append(1 + BAND_ROWS * bw + NTP + BAND_ROWS * (NBW - 1 - bw))
                     jc = band * BAND_ROWS + r
                     row_ok = jc < ny
                     jn = np.where(fy, ny - 1 - jc, jc)
                     assert np.all(jn[row_ok] >= 0) and np.all(jn[row_ok] < ny)
-                    rd_global = bw == 0 and band > 0
-                    wr_global = bw == NBW - 1 and band + 1 < nb
-                    tin_base = (qc * nb + (band - 1 if band > 0 else 0)) * R * slot_words
-                    tout_base = (qc * nb + band) * R * slot_words
+                    rd_recv = bw == 0 and band > 0
+                    assert not rd_recv or XW, "a band reads the group below without a receiving wave"
                     part_base = (qc * nb + band) * NT * 64
                     pg0 = slots[w * CHANNELS * K]
                     wave_on = pg0[0] >= 0
@@ -164,29 +185,19 @@ def check_shape(nx, ny, G, sn, NW, NBW, K, rs):
                         ib = (d * G + gb0 + gl) * NB
                         el = ib[act] + xside + 2 * jv[act] + 1
                         assert el.size == 0 or el.max() < n_inf
-                        # trace words: this lane's slot row of a band's block
-                        slot = ((w * K + k) * CHANNELS + ch)
-                        assert np.all(slot < R)
-                        if rd_global:
-                            rd = act & (r == 0)
-                            for c in range(nx):
-                                for sl in slot[rd]:
-                                    o = tin_base + (sl * nx + c) * 2 * TW
-                                    read_words[o: o + 2 * TW] += 1
-                            gcol = min(TRACE_LAG, nx - 1)
-                            assert tin_base + ((R - 1) * nx + gcol) * 2 * TW + 2 * TW <= n_trace
-                        if wr_global:
-                            pr = act & (r == BAND_ROWS - 1)
-                            for tt in range(BAND_ROWS - 1, NT):
-                                col = tt - (BAND_ROWS - 1)
-                                assert 0 <= col < nx
-                                for sl in slot[pr]:
-                                    o = tout_base + (sl * nx + col) * 2 * TW
-                                    written[o: o + 2 * TW] += 1
+                        if rd_recv:
+                            # row 0 at step tt < nx reads column tt from the receiving wave's
+                            # slot (tt & 1), written in interval tt - 1 (column 0: before the
+                            # first barrier, interval -1)
+                            for c in range(CHANNELS):
+                                for tt in range(min(nx, NTP)):
+                                    idx = ((((tt & 1) * NW + w) * K + k) * CHANNELS + c) * 2
+                                    assert 0 <= idx and idx + 1 < n_recv
+                                    assert recv_w[(tt & 1, w, k, c, tt)] == tt - 1
                         # LDS hand-off: written by the top row at step tt (global
                         # iteration 16 bw + tt) into parity tt & 1 of band slot bw
                         for c in range(CHANNELS):
-                            if bw < NBW - 1:
+                            if True:   # every band, the top one for the publishing wave
                                 for tt in range(NTP):
                                     idx = ((((tt & 1) * NBW + bw) * NW + w) * K + k) * CHANNELS * 2 + c * 2
                                     assert 0 <= idx and idx + 1 < n_hand
@@ -208,6 +219,40 @@ def check_shape(nx, ny, G, sn, NW, NBW, K, rs):
                         idx = part_base + t[:, None] * 64 + lane[None, :]
                         assert idx.max() < n_part
                         part_owner[idx.ravel()] += 1
+            if XW:
+                # publishing wave: after interval i - 1 it reads the top band's step
+                # ts = i - 1 - 16 (NBW - 1) and stores column ts - 15 of the top band
+                top = bg * NBW + NBW - 1
+                barriers.append(1 + total)
+                if top + 1 < nb:
+                    tout_base = (qc * nb + top) * R * slot_words
+                    for i in range(total + 1):
+                        ts = i - 1 - BAND_ROWS * (NBW - 1)
+                        col = ts - (BAND_ROWS - 1)
+                        if not (0 <= col < nx):
+                            continue
+                        for sl in range(NSLOT):
+                            sc, sk, sw = sl % CHANNELS, (sl // CHANNELS) % K, sl // (CHANNELS * K)
+                            assert hand_w[(ts & 1, NBW - 1, sw, sk, sc, col)] == i - 1
+                            o = tout_base + (sl * nx + col) * 2 * TW
+                            assert o + 2 * TW <= n_trace
+                            written[o: o + 2 * TW] += 1
+                # receiving wave: column c < nx into slot c & 1 in interval c - 1, from
+                # the trace words of band bg NBW - 1 (active slots only); loads of
+                # columns past nx - 1 are clamped to it
+                barriers.append(1 + total)
+                bottom = bg * NBW
+                if bottom > 0:
+                    tin_base = (qc * nb + bottom - 1) * R * slot_words
+                    for sl in range(NSLOT):
+                        sc, sk, sw = sl % CHANNELS, (sl // CHANNELS) % K, sl // (CHANNELS * K)
+                        if slots[(sw * CHANNELS + sc) * K + sk][0] < 0:
+                            continue
+                        cols = [min(TRACE_LAG, nx - 1)] + [min(c, nx - 1) for c in range(0, active_iv + 1 + RP)]
+                        for c in cols:
+                            o = tin_base + (sl * nx + c) * 2 * TW
+                            assert o + 2 * TW <= n_trace
+                            read_words[o: o + 2 * TW] += 1
             assert len(set(barriers)) == 1, "the waves of a workgroup pass different numbers of barriers"
     # every word the bottom band of a workgroup reads was published by the top
     # band of the workgroup below, once; words nobody reads are never written
