@@ -62,13 +62,17 @@ def measured_traffic(info):
 def sweep_kernel_name(info):
     """The FP32 sweep kernel instance a launch shape runs (its template
     arguments: pairs per lane, prefetch depth, waves per band, bands per
-    workgroup, fixup), as the profiler names it."""
+    workgroup, fixup, and whether a publisher and a receiver wave carry the
+    outflow between stacked band groups), as the profiler names it."""
     k, nw, nb = info["pairs_per_lane"], info["waves_per_band"], info["bands_per_group"]
-    if nw * nb >= 16:
+    n_bands = -(-info["ny"] // info["band_rows"])
+    xw = n_bands > nb
+    waves = nw * nb + (2 if xw else 0)
+    if waves >= 16:
         prefetch = 3 if k == 1 else 1
     else:
         prefetch = {1: 4, 2: 3, 4: 1}[k]
-    return f"sweep2d_kernel<float, {k}, {prefetch}, {nw}, {nb}, false>"
+    return f"sweep2d_kernel<float, {k}, {prefetch}, {nw}, {nb}, false, {str(xw).lower()}>"
 
 
 def planck_group_fractions(nu_edges, T):
