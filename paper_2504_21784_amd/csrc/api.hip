@@ -252,6 +252,24 @@ static void plan_sweep(smrt_ctx *x) {
     // band-group-major task list: a band group is claimed only after every group below it
     std::vector<int2> tasks(x->n_wg);
     for (int t = 0; t < x->n_wg; ++t) tasks[t] = make_int2(0, t);
+    if (x->n_bgroups == 1) {
+        // No workgroup waits on another, so workgroup b sweeps tasks[b].  The
+        // hardware hands workgroup b to XCD b mod 8; give each XCD a run of
+        // chunks that read the same opacity and source tables (one quadrant
+        // and group block, successive directions), so those tables are
+        // fetched into each XCD's L2 once and shared by its workgroups.
+        std::vector<int> by_table;
+        for (int q = 0; q < 4; ++q)
+            for (int gb = 0; gb < ngb; ++gb)
+                for (int qc = x->chunks.start[q]; qc < x->chunks.start[q + 1]; ++qc)
+                    if ((qc - x->chunks.start[q]) % ngb == gb) by_table.push_back(qc);
+        const int n = x->n_wg, per = n / N_XCD, extra = n % N_XCD;
+        for (int b = 0; b < n; ++b) {
+            const int xcd = b % N_XCD, local = b / N_XCD;
+            const int first = xcd < extra ? xcd * (per + 1) : extra * (per + 1) + (xcd - extra) * per;
+            tasks[b] = make_int2(0, by_table[first + local]);
+        }
+    }
     x->d_tasks.alloc(x->n_wg);
     SMRT_HIP(hipMemcpy(x->d_tasks.p, tasks.data(), sizeof(int2) * x->n_wg, hipMemcpyHostToDevice));
     x->d_lctr.alloc(2);
@@ -319,6 +337,7 @@ static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const vo
         L.lctr = ws ? ws->lctr : x->d_lctr.p;
         L.fixup = x->opt.fixup;
         L.xw = x->n_bgroups > 1 ? 1 : 0;
+        L.static_order = x->n_bgroups == 1 ? 1 : 0;
         if (x->fp32) launch_sweep2d<float>(L, x->stream);
         else launch_sweep2d<double>(L, x->stream);
         if (finalize) finalize_moments(x, mom, ws ? ws->part : nullptr);

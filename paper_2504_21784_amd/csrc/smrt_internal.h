@@ -13,6 +13,7 @@ namespace smrt {
 
 constexpr int BAND_ROWS = 16;       // rows of cells per band (lanes per channel)
 constexpr int CHANNELS = 4;         // (angle, group) channels per wave (64 / BAND_ROWS)
+constexpr int N_XCD = 8;            // accelerator dies (XCDs), each with its own L2; workgroup b runs on XCD b mod 8
 constexpr int NMOM2D = 9;           // per node per quadrant: 6 quadrant sums + 3 sigma-weighted
 constexpr int PART_PER_CELL = 4 * 2;         // per cell per chunk: sum_g I and sum_g sigma_g I of 4 nodes
 constexpr int SPIN_LIMIT = 1 << 20;          // bounded wait on a band trace
@@ -78,6 +79,8 @@ struct SweepLaunch {
     int fixup;                       // 1: zero-and-scale negative-flux fixup in every cell
     int xw;                          // 1: some chunk spans several band groups (publishing and
                                      //    receiving waves in every workgroup)
+    int static_order;                // 1: workgroup b sweeps tasks[b] (no workgroup waits on
+                                     //    another); 0: tasks are claimed through the ticket lctr[0]
 };
 
 // Internal angular-flux layout (both precisions): [d][g][band][t][r][4 canonical nodes].
