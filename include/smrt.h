@@ -408,6 +408,28 @@ smrt_status smrt_batch_sweep_resident(smrt_batch *batch, double dt, int n_times,
  * the problems still iterating; stats[n] (may be NULL) per problem.  Returns
  * the first problem's failure status (message in smrt_batch_last_error). */
 smrt_status smrt_batch_step(smrt_batch *batch, const double *dt, smrt_step_stats *stats);
+/* n_steps backward-Euler steps (Algorithm 1) of every problem with the
+ * convergence decisions on the device: each problem's outer iteration is
+ * stopped by its own test (Algorithm 1: eps_outer, fixed_outer, max_outer)
+ * in a control block in device memory, and its LO solve (Sec. 5: Newton
+ * with nonlinear elimination, Jacobi-preconditioned CG, their tests and
+ * caps) runs for all problems in one persistent launch whose workgroups
+ * meet at grid barriers.  The host queues blocks of 4 outer iterations of
+ * the whole batch (one batched sweep each; a converged problem is not swept
+ * again and its LO is skipped) and waits once per block, and once per step;
+ * capture_graph != 0 records the block once as a HIP graph and replays it.
+ * dt[n_steps * n]: step s of problem p at dt[s * n + p]; stats (may be NULL)
+ * [n_steps * n] likewise (t_total_ms: the whole batch's step; t_sweep_ms and
+ * t_lo_ms are not separated: 0).  Each problem's result equals n_steps calls
+ * of smrt_step on it alone with the batch's launch shape, bit for bit.
+ * Requires an SM scheme, lo_precond = 0 and no reflective side on every
+ * problem, and at most 64 problems (else SMRT_E_INVALID_ARG).  Stops after
+ * the first step in which a problem fails and returns that status (message
+ * in smrt_batch_last_error; strict turns a capped iteration into
+ * SMRT_E_NOT_CONVERGED); SMRT_E_DEVICE if a grid-barrier wait of the LO
+ * launch exceeds its bound (workgroups not all resident). */
+smrt_status smrt_batch_run(smrt_batch *batch, int n_steps, const double *dt, smrt_step_stats *stats,
+                           int capture_graph);
 
 /* ------------------------------------------------------------------------
  * Unstructured quadrilateral meshes (the paper's refined meshes have

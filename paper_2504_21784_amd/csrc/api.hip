@@ -1503,6 +1503,38 @@ extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_band
 // ---------------------------------------------------------------------------
 // Batches: every sweep task of many 2D problems in one persistent launch.
 // ---------------------------------------------------------------------------
+// Device state of smrt_batch_run (its control blocks, LO descriptors and
+// barrier, the captured block of outer iterations, per-step events).
+struct BatchRunState {
+    DevBuf<RunCtl> ctl;      // [n] this step's control blocks
+    DevBuf<RunCtl> hist;     // [n_steps][n] control blocks at the end of every step
+    DevBuf<LoProb> lo;       // [n]
+    DevBuf<unsigned> bar;    // [2] the batched LO kernel's grid barrier
+    DevBuf<int> flags;       // [0] a batched-LO barrier wait past its bound, [1] problems still iterating
+    int *h_flags = nullptr;  // pinned: the two flags
+    RunCtl *h_ctl = nullptr; // pinned: the control blocks at the end of a step
+    std::vector<LoProb> h_lo;
+    LoBatch lb{};
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<double> graph_dt;   // time steps the captured block of outer iterations was recorded with
+    std::vector<hipEvent_t> ev;
+    ~BatchRunState() {
+        drop();
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        if (h_flags) (void)hipHostFree(h_flags);
+        if (h_ctl) (void)hipHostFree(h_ctl);
+    }
+    void drop() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        graph_dt.clear();
+    }
+};
+
 struct smrt_batch {
     std::string err;
     std::vector<smrt_ctx *> P;
@@ -1517,6 +1549,7 @@ struct smrt_batch {
     int n_tasks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    std::unique_ptr<BatchRunState> run;   // device state of smrt_batch_run (made on first use)
     ~smrt_batch() {
         drop_graph();
         if (stream) (void)hipStreamDestroy(stream);
@@ -1610,12 +1643,14 @@ static void batch_upload_tasks(smrt_batch *b, const std::vector<int> &active) {
 }
 
 // argument blocks of the active problems (position i in the launch = active[i])
-static void batch_upload_args(smrt_batch *b, const std::vector<int> &active, const std::vector<double> &icdt) {
+static void batch_upload_args(smrt_batch *b, const std::vector<int> &active, const std::vector<double> &icdt,
+                              const int *const *gates = nullptr) {
     b->h_args.resize(active.size());
     for (size_t i = 0; i < active.size(); ++i) {
         smrt_ctx *x = b->P[active[i]];
         b->h_args[i] = sweep_args(x, x->d_psi[x->cur].p, x->d_psi[1 - x->cur].p, x->d_sig2.p, x->d_qiso.p,
                                   x->d_inflow.p, icdt[active[i]]);
+        if (gates) b->h_args[i].gate = gates[active[i]];
     }
     if (b->d_args.n < (int64_t)active.size()) b->d_args.alloc((int64_t)b->P.size());
     SMRT_HIP(hipMemcpyAsync(b->d_args.p, b->h_args.data(), sizeof(Sweep2DArgs) * active.size(), hipMemcpyHostToDevice,
@@ -1872,6 +1907,306 @@ extern "C" smrt_status smrt_batch_step(smrt_batch *b, const double *dt, smrt_ste
                 b->err = "problem " + std::to_string(i) + ": " + b->P[i]->err;
             }
         }
+    });
+    if (st == SMRT_OK && result != SMRT_OK) g_last_error = b->err;
+    return st != SMRT_OK ? st : result;
+}
+
+// ---------------------------------------------------------------------------
+// Multi-step batched run with device-side convergence control
+// ---------------------------------------------------------------------------
+// Each problem's outer iteration (Algorithm 1) is decided on the device from
+// its control block, and its LO solve (Newton and CG, Sec. 5) runs inside the
+// batched LO kernel, so the host queues blocks of RUN_BLOCK outer iterations
+// and waits once per block to learn whether any problem still iterates.  A
+// problem whose step has converged is not swept again, and its LO is
+// skipped; the small per-problem kernels of an outer iteration (emission
+// tables at the outer temperature, moment finalisation, closures, the
+// iterate change) run on for it but only reproduce the values it already
+// holds, since its temperature, intensity and moment partials no longer
+// change.
+constexpr int RUN_BLOCK = 4;
+
+__global__ void k_run_begin(RunCtl *ctl, int n) {
+    const int p = threadIdx.x;
+    if (p >= n) return;
+    RunCtl c{};
+    c.active = 1;
+    c.first = -1.0;
+    c.first_in = -1.0;
+    ctl[p] = c;
+}
+
+// The end of one outer iteration of one problem: the checks StepRun::post_sweep
+// makes on the host, on the iterate change |T - T_l|^2 + |E - E_l|^2 in sc[6].
+__global__ void k_outer_decide(RunCtl *ctl, const double *sc, const int *sweep_ctr, int fixed_outer, int maxo,
+                               double eps_outer) {
+    RunCtl &c = *ctl;
+    if (!c.active) return;
+    c.l += 1;
+    c.outer += 1;
+    const double diff = sqrt(sc[6]);
+    bool done = false;
+    if (c.status != SMRT_OK) {
+        done = true;                                   // its LO solve failed
+    } else if (sweep_ctr[3]) {
+        c.status = SMRT_E_DEVICE;
+        c.reason = RUN_SWEEP_WAIT;
+        done = true;
+    } else if (!isfinite(diff)) {
+        c.status = SMRT_E_NONPHYSICAL;
+        c.reason = RUN_OUTER_NONFINITE;
+        done = true;
+    } else if (fixed_outer > 0) {
+        done = c.l >= maxo;
+    } else {
+        if (c.l == 1) c.first = diff;
+        if (diff == 0.0 || (c.l > 1 && diff < eps_outer * c.first)) done = true;
+        else if (c.l == maxo) {
+            c.hit_max = 1;
+            done = true;
+        }
+    }
+    if (done) c.active = 0;
+}
+
+// flags[1] = problems still iterating (one thread)
+__global__ void k_run_count(const RunCtl *ctl, int n, int *flags) {
+    int a = 0;
+    for (int p = 0; p < n; ++p) a += ctl[p].active;
+    flags[1] = a;
+}
+
+// one outer iteration of every problem (the converged ones skip the sweep and the LO)
+static void run_outer_iteration(smrt_batch *b, BatchRunState &R, const std::vector<double> &dt) {
+    hipStream_t S = b->stream;
+    const size_t n = b->P.size();
+    for (smrt_ctx *x : b->P) run_source_at(x, x->d_Tl.p);
+    batch_launch(b);
+    for (size_t i = 0; i < n; ++i) {
+        smrt_ctx *x = b->P[i];
+        finalize_moments(x, x->d_mom.p);
+        SMRT_HIP(hipMemcpyAsync(x->d_Tn.p, x->d_Tl.p, 8 * x->nn, hipMemcpyDeviceToDevice, S));
+        SMRT_HIP(hipMemcpyAsync(x->d_En.p, x->d_El.p, 8 * x->nn, hipMemcpyDeviceToDevice, S));
+        run_closures(S, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt[i], x->d_mom.p, x->d_sigP.p,
+                                     x->d_sigF.p, x->d_Estar.p, x->d_Fstar.p, x->d_clos.p));
+    }
+    run_lo_batch(S, R.lb, R.grid);
+    for (size_t i = 0; i < n; ++i) {
+        smrt_ctx *x = b->P[i];
+        x->lo.dot(S, x->d_Tn.p, nullptr, x->d_Tl.p, 6, false);
+        x->lo.dot(S, x->d_En.p, nullptr, x->d_El.p, 6, true);
+        const int maxo = x->opt.fixed_outer > 0 ? x->opt.fixed_outer : x->opt.max_outer;
+        hipLaunchKernelGGL(k_outer_decide, dim3(1), dim3(1), 0, S, R.ctl.p + i, (const double *)x->lo.sc.p,
+                           (const int *)x->d_ctr.p, x->opt.fixed_outer, maxo, x->opt.eps_outer);
+        SMRT_HIP(hipMemcpyAsync(x->d_Tl.p, x->d_Tn.p, 8 * x->nn, hipMemcpyDeviceToDevice, S));
+        SMRT_HIP(hipMemcpyAsync(x->d_El.p, x->d_En.p, 8 * x->nn, hipMemcpyDeviceToDevice, S));
+    }
+}
+
+static LoProb lo_prob(smrt_ctx *x, double dt, RunCtl *ctl) {
+    LoSolver &L = x->lo;
+    const LoInputs in = lo_inputs(x, dt, x->d_clos.p);
+    LoProb q{};
+    q.nn = L.nn;
+    q.dim = L.dim;
+    q.nbk = (L.nn + 255) / 256;
+    q.nbkd = (L.nn * L.dim + 255) / 256;
+    q.g = L.geom();
+    q.a = L.a;
+    q.c = L.c;
+    q.dt = dt;
+    q.eps_inner = in.eps_inner;
+    q.cg_rtol = in.cg_rtol;
+    q.elim_rtol = in.elim_rtol;
+    q.T_floor = in.T_floor;
+    q.max_inner = in.max_inner;
+    q.max_cg = in.max_cg;
+    q.max_elim = in.max_elim;
+    q.drp = L.dD.rp; q.dcol = L.dD.col; q.dval = L.dD.val;
+    q.dtrp = L.dDT.rp; q.dtcol = L.dDT.col; q.dtval = L.dDT.val;
+    q.prp = L.dP.rp; q.pcol = L.dP.col; q.pval = L.dP.val;
+    q.wn = L.wn.p;
+    q.MFinv = L.MFinv.p; q.DqF = L.DqF.p; q.jbase = L.jbase.p; q.diagE = L.diagE.p; q.rhs = L.rhs.p;
+    q.Minv = L.Minv.p; q.r = L.r.p; q.z = L.z.p; q.p = L.p.p; q.Ap = L.Ap.p; q.Eold = L.Eold.p; q.Told = L.Told.p;
+    q.tmpF = L.tmpF.p; q.part = L.part.p; q.sc = L.sc.p; q.bpart = L.bpart.p; q.apart = L.apart.p;
+    q.flags = L.flags.p;
+    q.sigE = in.sigE; q.sigF = in.sigF; q.sigP = in.sigP; q.qE = in.qE; q.qF = in.qF; q.cvn = in.cvn;
+    q.Tstar = x->d_Tstar.p;
+    q.E = x->d_En.p;
+    q.F = x->d_F.p;
+    q.T = x->d_Tn.p;
+    q.ctl = ctl;
+    return q;
+}
+
+static const char *run_reason(int r) {
+    switch (r) {
+    case RUN_NO_ROOT: return "no positive temperature root in the energy balance";
+    case RUN_LO_NONFINITE: return "non-finite low-order iterate";
+    case RUN_OUTER_NONFINITE: return "non-finite outer iterate";
+    case RUN_SWEEP_WAIT: return "sweep band-trace wait exceeded its bound";
+    default: return "step failed";
+    }
+}
+
+extern "C" smrt_status smrt_batch_run(smrt_batch *b, int n_steps, const double *dt, smrt_step_stats *stats,
+                                      int capture_graph) {
+    if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
+    const size_t n = b->P.size();
+    smrt_status result = SMRT_OK;
+    smrt_status st = bguard(b, [&] {
+        require(n_steps >= 1 && dt != nullptr, "n_steps must be >= 1 and dt non-NULL");
+        require(n <= (size_t)LO_BATCH_MAX, "a batched run takes at most 64 problems");
+        for (int64_t k = 0; k < (int64_t)n_steps * (int64_t)n; ++k)
+            require(dt[k] > 0.0 && std::isfinite(dt[k]), "dt must be finite and > 0");
+        for (const smrt_ctx *x : b->P) {
+            require(x->opt.scheme != SMRT_UNACCELERATED, "a batched run needs an SM scheme (the LO solve)");
+            require(x->opt.lo_precond == 0, "a batched run uses the Jacobi-preconditioned LO (lo_precond = 0)");
+            require(!x->refl, "a batched run has no reflective sides");
+        }
+        BatchStreams on(b);
+        hipStream_t S = b->stream;
+        if (!b->run) b->run = std::make_unique<BatchRunState>();
+        BatchRunState &R = *b->run;
+        R.drop();
+        if (R.ctl.n != (int64_t)n) {
+            R.ctl.alloc((int64_t)n);
+            R.lo.alloc((int64_t)n);
+        }
+        if (R.hist.n < (int64_t)n_steps * (int64_t)n) R.hist.alloc((int64_t)n_steps * (int64_t)n);
+        if (!R.bar.p) R.bar.alloc(2);
+        if (!R.flags.p) R.flags.alloc(2);
+        if (!R.h_flags) SMRT_HIP(hipHostMalloc((void **)&R.h_flags, 2 * sizeof(int), hipHostMallocDefault));
+        if (!R.h_ctl) SMRT_HIP(hipHostMalloc((void **)&R.h_ctl, LO_BATCH_MAX * sizeof(RunCtl), hipHostMallocDefault));
+        if (!R.grid) R.grid = lo_batch_grid();
+        while ((int)R.ev.size() < n_steps + 1) {
+            hipEvent_t e;
+            SMRT_HIP(hipEventCreate(&e));
+            R.ev.push_back(e);
+        }
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, S, (int *)R.bar.p, 2);
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, S, R.flags.p, 2);
+        R.lb = LoBatch{};
+        R.lb.P = R.lo.p;
+        R.lb.np = (int)n;
+        R.lb.bar = R.bar.p;
+        R.lb.abort = R.flags.p;
+        R.h_lo.resize(n);
+        for (size_t i = 0; i < n; ++i) R.lb.vb_n[i + 1] = R.lb.vb_n[i] + (b->P[i]->lo.nn + 255) / 256;
+        std::vector<const int *> gates(n);
+        for (size_t i = 0; i < n; ++i) gates[i] = &R.ctl.p[i].active;
+        const std::vector<int> all = all_problems(b);
+        batch_upload_tasks(b, all);
+        SMRT_HIP(hipEventRecord(R.ev[0], S));
+        int steps_done = 0;
+        for (int s = 0; s < n_steps; ++s) {
+            const std::vector<double> dts(dt + (int64_t)s * n, dt + (int64_t)(s + 1) * n);
+            std::vector<StepRun> runs(n);
+            std::vector<double> icdt(n);
+            for (size_t i = 0; i < n; ++i) {
+                runs[i].begin(b->P[i], dts[i]);
+                icdt[i] = runs[i].icdt;
+                R.h_lo[i] = lo_prob(b->P[i], dts[i], R.ctl.p + i);
+            }
+            hipLaunchKernelGGL(k_run_begin, dim3(1), dim3(LO_BATCH_MAX), 0, S, R.ctl.p, (int)n);
+            SMRT_HIP(hipMemcpyAsync(R.lo.p, R.h_lo.data(), sizeof(LoProb) * n, hipMemcpyHostToDevice, S));
+            batch_upload_args(b, all, icdt, gates.data());   // waits for the uploads
+            // blocks of outer iterations until no problem iterates
+            int max_blocks = 0;
+            for (const smrt_ctx *x : b->P) {
+                const int maxo = x->opt.fixed_outer > 0 ? x->opt.fixed_outer : x->opt.max_outer;
+                max_blocks = std::max(max_blocks, (maxo + RUN_BLOCK - 1) / RUN_BLOCK);
+            }
+            for (int blk = 0;; ++blk) {
+                require(blk < max_blocks, "batched run: outer iterations past every problem's cap");
+                if (capture_graph) {
+                    if (!R.exec || R.graph_dt != dts) {
+                        R.drop();
+                        SMRT_HIP(hipStreamBeginCapture(S, hipStreamCaptureModeThreadLocal));
+                        try {
+                            for (int k = 0; k < RUN_BLOCK; ++k) run_outer_iteration(b, R, dts);
+                        } catch (...) {
+                            hipGraph_t g = nullptr;
+                            (void)hipStreamEndCapture(S, &g);
+                            if (g) (void)hipGraphDestroy(g);
+                            throw;
+                        }
+                        SMRT_HIP(hipStreamEndCapture(S, &R.graph));
+                        SMRT_HIP(hipGraphInstantiate(&R.exec, R.graph, nullptr, nullptr, 0));
+                        R.graph_dt = dts;
+                    }
+                    SMRT_HIP(hipGraphLaunch(R.exec, S));
+                } else {
+                    for (int k = 0; k < RUN_BLOCK; ++k) run_outer_iteration(b, R, dts);
+                }
+                hipLaunchKernelGGL(k_run_count, dim3(1), dim3(1), 0, S, R.ctl.p, (int)n, R.flags.p);
+                SMRT_HIP(hipMemcpyAsync(R.h_flags, R.flags.p, 2 * sizeof(int), hipMemcpyDeviceToHost, S));
+                SMRT_HIP(hipStreamSynchronize(S));
+                if (R.h_flags[0]) throw smrt::Error(SMRT_E_DEVICE, "batched LO: a grid-barrier wait exceeded its bound");
+                if (R.h_flags[1] == 0) break;
+            }
+            // the new state of every problem (StepRun::end, without its wait)
+            for (size_t i = 0; i < n; ++i) {
+                smrt_ctx *x = b->P[i];
+                const int64_t nn = x->nn;
+                SMRT_HIP(hipMemcpyAsync(x->d_T.p, x->d_Tl.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+                SMRT_HIP(hipMemcpyAsync(x->d_E.p, x->d_El.p, 8 * nn, hipMemcpyDeviceToDevice, S));
+                hipLaunchKernelGGL(k_ho_from_mom, dim3(nblk(nn)), dim3(256), 0, S, (int)nn, x->dim, x->c, x->d_mom.p,
+                                   x->d_sigP.p, x->d_Eho.p, x->d_Fho.p, (double *)nullptr);
+                x->cur = 1 - x->cur;
+            }
+            SMRT_HIP(hipMemcpyAsync(R.hist.p + (int64_t)s * n, R.ctl.p, sizeof(RunCtl) * n, hipMemcpyDeviceToDevice, S));
+            SMRT_HIP(hipMemcpyAsync(R.h_ctl, R.ctl.p, sizeof(RunCtl) * n, hipMemcpyDeviceToHost, S));
+            SMRT_HIP(hipEventRecord(R.ev[s + 1], S));
+            SMRT_HIP(hipStreamSynchronize(S));
+            steps_done = s + 1;
+            bool failed = false;
+            for (size_t i = 0; i < n; ++i) {
+                const RunCtl &c = R.h_ctl[i];
+                smrt_ctx *x = b->P[i];
+                if (c.reason == RUN_SWEEP_WAIT) {
+                    // clear the sweep's wait flag and trace words, as a single step does
+                    hipLaunchKernelGGL(k_init_ctr, dim3(1), dim3(1), 0, S, x->d_ctr.p);
+                    SMRT_HIP(hipMemsetAsync(x->d_trace.p, 0, sizeof(uint64_t) * x->d_trace.n, S));
+                }
+                smrt_status ps = (smrt_status)c.status;
+                std::string why = ps != SMRT_OK ? run_reason(c.reason) : "";
+                if (ps == SMRT_OK && x->opt.strict && c.hit_max) {
+                    ps = SMRT_E_NOT_CONVERGED;
+                    why = "iteration cap reached";
+                }
+                if (ps != SMRT_OK && result == SMRT_OK) {
+                    result = ps;
+                    b->err = "step " + std::to_string(s) + ", problem " + std::to_string(i) + ": " + why;
+                }
+                if (ps != SMRT_OK) failed = true;
+            }
+            SMRT_HIP(hipStreamSynchronize(S));
+            if (failed) break;
+        }
+        if (stats) {
+            std::vector<RunCtl> h((size_t)steps_done * n);
+            if (!h.empty())
+                SMRT_HIP(hipMemcpy(h.data(), R.hist.p, sizeof(RunCtl) * h.size(), hipMemcpyDeviceToHost));
+            for (int s = 0; s < n_steps; ++s) {
+                float ms = 0.f;
+                if (s < steps_done) SMRT_HIP(hipEventElapsedTime(&ms, R.ev[s], R.ev[s + 1]));
+                for (size_t i = 0; i < n; ++i) {
+                    smrt_step_stats &o = stats[(int64_t)s * n + i];
+                    o = smrt_step_stats{};
+                    if (s >= steps_done) continue;
+                    const RunCtl &c = h[(size_t)s * n + i];
+                    o.outer = c.outer;
+                    o.inner_total = c.inner_total;
+                    o.cg_total = c.cg_total;
+                    o.elim_max = c.elim_max;
+                    o.hit_max = c.hit_max;
+                    o.t_total_ms = ms;
+                }
+            }
+        }
+        R.drop();
     });
     if (st == SMRT_OK && result != SMRT_OK) g_last_error = b->err;
     return st != SMRT_OK ? st : result;

@@ -101,6 +101,64 @@ struct LoInputs {
 
 struct MgHierarchy;   // aggregation multigrid levels (built on first use)
 
+// mesh of the stencil form of the LO operators
+struct LoGeom {
+    int dim, nx, ny;
+    const double *hx, *hy;
+    double c, alpha[2];
+};
+
+// Device-side control of one problem in a multi-step batched run: the outer
+// iteration of the step (Algorithm 1) and the Newton and CG iterations of its
+// LO solve (Sec. 5) are decided on the device from these fields.
+struct RunCtl {
+    int active;          // 1 while the step's outer iteration runs
+    int l;               // outer iterations done in this step
+    int status;          // SMRT_OK, or the failure that ended this step
+    int reason;          // RUN_* code of a failure (its message on the host)
+    int m;               // Newton iteration of the current LO solve
+    int nt_on;           // 1 while the LO's Newton iteration runs
+    int cg_on;           // 1 while the current CG runs
+    int outer, inner_total, cg_total, elim_max, hit_max;   // statistics of the step
+    double first;        // first outer change of the step
+    double first_in;     // first Newton change of the current LO solve
+};
+enum { RUN_NO_ROOT = 1, RUN_LO_NONFINITE = 2, RUN_OUTER_NONFINITE = 3, RUN_SWEEP_WAIT = 4 };
+
+// One problem of the batched LO kernel: its operators, the work vectors of its
+// LoSolver, the closure inputs, the iterate and its control block.
+struct LoProb {
+    int nn, dim, nbk, nbkd;                  // nodes, 256-node blocks of nodes and of F rows
+    LoGeom g;
+    double a, c, dt, eps_inner, cg_rtol, elim_rtol, T_floor;
+    int max_inner, max_cg, max_elim;
+    const int *drp, *dcol, *dtrp, *dtcol, *prp, *pcol;   // D, D^T and P (CSR)
+    const double *dval, *dtval, *pval, *wn;
+    double *MFinv, *DqF, *jbase, *diagE, *rhs, *Minv, *r, *z, *p, *Ap, *Eold, *Told, *tmpF, *part, *sc, *bpart,
+        *apart;
+    int *flags;
+    const double *sigE, *sigF, *sigP, *qE, *qF, *cvn, *Tstar;
+    double *E, *F, *T;
+    RunCtl *ctl;
+};
+
+constexpr int LO_BATCH_MAX = 64;   // problems of one batched LO launch
+// Launch arguments of the batched LO kernel: the problems and where each
+// problem's node blocks start in the launch's sequence of node blocks.
+struct LoBatch {
+    const LoProb *P;
+    int np;
+    int vb_n[LO_BATCH_MAX + 1];    // prefix sums of nbk
+    unsigned *bar;                 // [2] grid barrier: arrivals, generation
+    int *abort;                    // set when a barrier wait exceeds its bound
+};
+// One LO solve (Newton with nonlinear elimination, Jacobi-PCG) of every
+// problem whose control block is active, in one persistent launch whose
+// workgroups meet at grid barriers; the same arithmetic, block by block, as
+// LoSolver::solve.  grid: workgroups that are all resident at once.
+void run_lo_batch(hipStream_t s, const LoBatch &b, int grid);
+int lo_batch_grid();
+
 struct LoSolver {
     int dim = 0, nn = 0;
     double c = 1, a = 1;

@@ -308,28 +308,31 @@ void assemble_lo_operators(int dim, int nx, int ny, const std::vector<double> &x
 // ---------------------------------------------------------------------------
 // LO kernels
 // ---------------------------------------------------------------------------
-__global__ void k_lo_outer_setup(int nn, int dim, double icdt, const double *wn, const double *sigF, const double *qF,
+__device__ __forceinline__ void d_lo_outer_setup(int bid, int nn, int dim, double icdt, const double *wn, const double *sigF, const double *qF,
                                  double *MFinv, double *tmpF) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = bid * 256 + threadIdx.x;
     if (n >= nn) return;
     const double mi = 1.0 / (wn[n] * (sigF[n] + icdt));
     MFinv[n] = mi;
     for (int a = 0; a < dim; ++a) tmpF[dim * n + a] = qF[(int64_t)a * nn + n] * mi;
 }
+__global__ void k_lo_outer_setup(int nn, int dim, double icdt, const double *wn, const double *sigF, const double *qF,
+                                 double *MFinv, double *tmpF) { d_lo_outer_setup(blockIdx.x, nn, dim, icdt, wn, sigF, qF, MFinv, tmpF); }
 
 // y = A x (CSR), optionally y = alpha A x + beta y
-__global__ void k_spmv(int nrows, const int *rp, const int *col, const double *val, const double *x, double *y) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void d_spmv(int bid, int nrows, const int *rp, const int *col, const double *val, const double *x, double *y) {
+    const int r = bid * 256 + threadIdx.x;
     if (r >= nrows) return;
     double s = 0.0;
     for (int k = rp[r]; k < rp[r + 1]; ++k) s += val[k] * x[col[k]];
     y[r] = s;
 }
+__global__ void k_spmv(int nrows, const int *rp, const int *col, const double *val, const double *x, double *y) { d_spmv(blockIdx.x, nrows, rp, col, val, x, y); }
 
 // dDD_n = (c/3) sum_k D_nk^2 MFinv(col node) + P_nn
-__global__ void k_jacobi_base(int nn, int dim, double c3, const int *drp, const int *dcol, const double *dval,
+__device__ __forceinline__ void d_jacobi_base(int bid, int nn, int dim, double c3, const int *drp, const int *dcol, const double *dval,
                               const int *prp, const int *pcol, const double *pval, const double *MFinv, double *base) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = bid * 256 + threadIdx.x;
     if (n >= nn) return;
     double s = 0.0;
     for (int k = drp[n]; k < drp[n + 1]; ++k) s += dval[k] * dval[k] * MFinv[dcol[k] / dim];
@@ -338,13 +341,15 @@ __global__ void k_jacobi_base(int nn, int dim, double c3, const int *drp, const 
         if (pcol[k] == n) p += pval[k];
     base[n] = c3 * s + p;
 }
+__global__ void k_jacobi_base(int nn, int dim, double c3, const int *drp, const int *dcol, const double *dval,
+                              const int *prp, const int *pcol, const double *pval, const double *MFinv, double *base) { d_jacobi_base(blockIdx.x, nn, dim, c3, drp, dcol, dval, prp, pcol, pval, MFinv, base); }
 
 // Newton linearisation at T0: diagE, rhs, Jacobi inverse
-__global__ void k_newton_prep(int nn, double a, double c, double dt, const double *wn, const double *cvn,
+__device__ __forceinline__ void d_newton_prep(int bid, int nn, double a, double c, double dt, const double *wn, const double *cvn,
                               const double *T0, const double *Tstar, const double *sigE, const double *sigP,
                               const double *qE, const double *DqF, const double *jbase, double *diagE, double *rhs,
                               double *Minv, const double *E, double *Eold, double *Told) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = bid * 256 + threadIdx.x;
     if (n >= nn) return;
     const double w = wn[n], t = T0[n];
     Told[n] = t;      // the iterate this Newton step starts from (for the stopping test)
@@ -360,6 +365,10 @@ __global__ void k_newton_prep(int nn, double a, double c, double dt, const doubl
     rhs[n] = qE[n] + B0 - DqF[n] + dB / dBt * (qT - Bt0);
     Minv[n] = 1.0 / (jbase[n] + de);
 }
+__global__ void k_newton_prep(int nn, double a, double c, double dt, const double *wn, const double *cvn,
+                              const double *T0, const double *Tstar, const double *sigE, const double *sigP,
+                              const double *qE, const double *DqF, const double *jbase, double *diagE, double *rhs,
+                              double *Minv, const double *E, double *Eold, double *Told) { d_newton_prep(blockIdx.x, nn, a, c, dt, wn, cvn, T0, Tstar, sigE, sigP, qE, DqF, jbase, diagE, rhs, Minv, E, Eold, Told); }
 
 // tmpF = (c/3) MFinv * (D^T x)  (D^T rows are F dofs)
 __global__ void k_dt_scaled(int nrows, int dim, double c3, const int *rp, const int *col, const double *val,
@@ -391,11 +400,6 @@ __global__ void k_schur_rows(int nn, const int *drp, const int *dcol, const doub
 //   (D f)_n = -(w/h_x) s_x (f(n,x) + f(n^1,x)) - (w/h_y) s_y (f(n,y) + f(n^2,y))
 //             + sum over n's faces a: interior: fw_a jmp f(lower, a)
 //   (P x)_n = sum over n's faces a: interior 0.5 fw_a c alpha_a (x_n - x_nb), boundary fw_a c alpha_a x_n
-struct LoGeom {
-    int dim, nx, ny;
-    const double *hx, *hy;
-    double c, alpha[2];
-};
 
 __device__ inline void lo_node(const LoGeom &g, int n, int &cell, int &l, int &i, int &j, double &hx, double &hy,
                                double &w) {
@@ -409,8 +413,8 @@ __device__ inline void lo_node(const LoGeom &g, int n, int &cell, int &l, int &i
     w = hx * hy / npc;
 }
 
-__global__ void k_dt_stencil(int nn, LoGeom g, double c3, const double *x, const double *MFinv, double *tmpF) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void d_dt_stencil(int bid, int nn, LoGeom g, double c3, const double *x, const double *MFinv, double *tmpF) {
+    const int m = bid * 256 + threadIdx.x;
     if (m >= nn) return;
     int cell, l, i, j;
     double hx, hy, w;
@@ -430,11 +434,12 @@ __global__ void k_dt_stencil(int nn, LoGeom g, double c3, const double *x, const
         tmpF[(int64_t)m * 2 + 1] = sc * v;
     }
 }
+__global__ void k_dt_stencil(int nn, LoGeom g, double c3, const double *x, const double *MFinv, double *tmpF) { d_dt_stencil(blockIdx.x, nn, g, c3, x, MFinv, tmpF); }
 
-__global__ void __launch_bounds__(256) k_schur_stencil_dot(int nn, LoGeom g, const double *tmpF, const double *x,
+__device__ __forceinline__ void d_schur_stencil_dot(int bid, int nn, LoGeom g, const double *tmpF, const double *x,
                                                            const double *diagE, double *y, double *part) {
     __shared__ double sh[256];
-    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int n = bid * 256 + threadIdx.x;
     double v = 0.0;
     if (n < nn) {
         int cell, l, i, j;
@@ -479,8 +484,10 @@ __global__ void __launch_bounds__(256) k_schur_stencil_dot(int nn, LoGeom g, con
         if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && part) part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0 && part) part[bid] = sh[0];
 }
+__global__ void __launch_bounds__(256) k_schur_stencil_dot(int nn, LoGeom g, const double *tmpF, const double *x,
+                                                           const double *diagE, double *y, double *part) { d_schur_stencil_dot(blockIdx.x, nn, g, tmpF, x, diagE, y, part); }
 
 // S x fused with the block partials of x . (S x) (one partial per 256-row block)
 __global__ void __launch_bounds__(256) k_schur_rows_dot(int nn, const int *drp, const int *dcol, const double *dval,
@@ -539,11 +546,11 @@ __device__ void block_sum_partials(int nb, int stride, bool two, const double *p
 // the host checks convergence only every few iterations.
 // CG update x += al p, r -= al Ap, z = M^-1 r (al = rz / pAp, pAp summed here from
 // the block partials apart of p.Ap) fused with the block partials of r.z and r.r
-__global__ void __launch_bounds__(256) k_cg_xr_dot(int n, int nbk, const double *sc, const double *apart,
+__device__ __forceinline__ void d_cg_xr_dot(int bid, int n, int nbk, const double *sc, const double *apart,
                                                    const double *p, const double *Ap, double *x, double *r,
                                                    const double *Minv, double *z, double *part) {
     __shared__ double sh[2][256];
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = bid * 256 + threadIdx.x;
     const bool frozen = sc[8] != 0.0;
     double pAp = 0.0, unused;
     block_sum_partials(nbk, 1, false, apart, sh, pAp, unused);
@@ -571,17 +578,20 @@ __global__ void __launch_bounds__(256) k_cg_xr_dot(int n, int nbk, const double 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = sh[0][0];
-        part[2 * blockIdx.x + 1] = sh[1][0];
+        part[2 * bid] = sh[0][0];
+        part[2 * bid + 1] = sh[1][0];
     }
 }
+__global__ void __launch_bounds__(256) k_cg_xr_dot(int n, int nbk, const double *sc, const double *apart,
+                                                   const double *p, const double *Ap, double *x, double *r,
+                                                   const double *Minv, double *z, double *part) { d_cg_xr_dot(blockIdx.x, n, nbk, sc, apart, p, Ap, x, r, Minv, z, part); }
 
 // deterministic block reduction of sum_i a_i b_i (b == nullptr: sum a_i^2 of (a - c))
 constexpr int RED_BLOCKS = 256, RED_THREADS = 256;
-__global__ void k_dot_partial(int n, const double *a, const double *b, const double *cdiff, double *part) {
+__device__ __forceinline__ void d_dot_partial(int bid, int n, const double *a, const double *b, const double *cdiff, double *part) {
     __shared__ double sh[RED_THREADS];
     double s = 0.0;
-    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
+    for (int i = bid * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
         if (cdiff) { const double d = a[i] - cdiff[i]; s += d * d; }
         else s += a[i] * (b ? b[i] : a[i]);
     }
@@ -591,9 +601,10 @@ __global__ void k_dot_partial(int n, const double *a, const double *b, const dou
         if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) part[bid] = sh[0];
 }
-__global__ void k_dot_finish(const double *part, double *out, int slot, int accumulate) {
+__global__ void k_dot_partial(int n, const double *a, const double *b, const double *cdiff, double *part) { d_dot_partial(blockIdx.x, n, a, b, cdiff, part); }
+__device__ __forceinline__ void d_dot_finish(int bid, const double *part, double *out, int slot, int accumulate) {
     __shared__ double sh[RED_BLOCKS];
     sh[threadIdx.x] = part[threadIdx.x];
     __syncthreads();
@@ -603,15 +614,16 @@ __global__ void k_dot_finish(const double *part, double *out, int slot, int accu
     }
     if (threadIdx.x == 0) out[slot] = accumulate ? out[slot] + sh[0] : sh[0];
 }
+__global__ void k_dot_finish(const double *part, double *out, int slot, int accumulate) { d_dot_finish(blockIdx.x, part, out, slot, accumulate); }
 
 // Several sums in one pass over the vectors (the CG start: b.b, r.z, r.r;
 // the Newton iterate change: |T - T_old|^2 + |E - E_old|^2), as block
 // partials part[j][block], then k_dot_finish_n adds each row in a fixed
 // order into its scalar slot.
-__global__ void k_dot3_partial(int n, const double *b, const double *r, const double *z, double *part) {
+__device__ __forceinline__ void d_dot3_partial(int bid, int n, const double *b, const double *r, const double *z, double *part) {
     __shared__ double sh[3][RED_THREADS];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
+    for (int i = bid * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
         const double ri = r[i];
         s0 += b[i] * b[i];
         s1 += ri * z[i];
@@ -627,13 +639,14 @@ __global__ void k_dot3_partial(int n, const double *b, const double *r, const do
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int j = 0; j < 3; ++j) part[j * RED_BLOCKS + blockIdx.x] = sh[j][0];
+        for (int j = 0; j < 3; ++j) part[j * RED_BLOCKS + bid] = sh[j][0];
 }
-__global__ void k_diff2_partial(int n, const double *T, const double *To, const double *E, const double *Eo,
+__global__ void k_dot3_partial(int n, const double *b, const double *r, const double *z, double *part) { d_dot3_partial(blockIdx.x, n, b, r, z, part); }
+__device__ __forceinline__ void d_diff2_partial(int bid, int n, const double *T, const double *To, const double *E, const double *Eo,
                                 double *part) {
     __shared__ double sh[RED_THREADS];
     double s = 0.0;
-    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
+    for (int i = bid * RED_THREADS + threadIdx.x; i < n; i += RED_BLOCKS * RED_THREADS) {
         const double dT = T[i] - To[i], dE = E[i] - Eo[i];
         s += dT * dT + dE * dE;
     }
@@ -643,9 +656,11 @@ __global__ void k_diff2_partial(int n, const double *T, const double *To, const 
         if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) part[bid] = sh[0];
 }
-__global__ void k_dot_finish_n(const double *part, double *out, int m, int slot0, int slot1, int slot2) {
+__global__ void k_diff2_partial(int n, const double *T, const double *To, const double *E, const double *Eo,
+                                double *part) { d_diff2_partial(blockIdx.x, n, T, To, E, Eo, part); }
+__device__ __forceinline__ void d_dot_finish_n(int bid, const double *part, double *out, int m, int slot0, int slot1, int slot2) {
     __shared__ double sh[RED_BLOCKS];
     const int slots[3] = {slot0, slot1, slot2};
     for (int j = 0; j < m; ++j) {
@@ -659,27 +674,31 @@ __global__ void k_dot_finish_n(const double *part, double *out, int m, int slot0
         __syncthreads();
     }
 }
+__global__ void k_dot_finish_n(const double *part, double *out, int m, int slot0, int slot1, int slot2) { d_dot_finish_n(blockIdx.x, part, out, m, slot0, slot1, slot2); }
 
 // CG vector updates with device-side scalars: sc[0]=rz, sc[1]=pAp, sc[2]=rr, sc[3]=rz_new
 // p = z + (rz_new / rz) p, rz_new summed here from the r.z block partials
-__global__ void __launch_bounds__(256) k_cg_p(int n, int nbk, const double *sc, const double *part, const double *z,
+__device__ __forceinline__ void d_cg_p(int bid, int n, int nbk, const double *sc, const double *part, const double *z,
                                               double *p) {
     __shared__ double sh[2][256];
     if (sc[8] != 0.0) return;   // uniform over the grid
     double rzn, unused;
     block_sum_partials(nbk, 2, false, part, sh, rzn, unused);
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = bid * 256 + threadIdx.x;
     if (i < n) p[i] = z[i] + (rzn / sc[0]) * p[i];
 }
-__global__ void k_cg_init(int n, const double *b, const double *Ax, double *r, const double *Minv, double *z, double *p) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_cg_p(int n, int nbk, const double *sc, const double *part, const double *z,
+                                              double *p) { d_cg_p(blockIdx.x, n, nbk, sc, part, z, p); }
+__device__ __forceinline__ void d_cg_init(int bid, int n, const double *b, const double *Ax, double *r, const double *Minv, double *z, double *p) {
+    const int i = bid * 256 + threadIdx.x;
     if (i >= n) return;
     r[i] = b[i] - Ax[i];
     z[i] = Minv[i] * r[i];
     p[i] = z[i];
 }
+__global__ void k_cg_init(int n, const double *b, const double *Ax, double *r, const double *Minv, double *z, double *p) { d_cg_init(blockIdx.x, n, b, Ax, r, Minv, z, p); }
 // one 256-thread block: (rz_new, rr) from the block partials, then the scalars
-__global__ void __launch_bounds__(256) k_cg_step_end(int nbk, const double *part, double *sc) {
+__device__ __forceinline__ void d_cg_step_end(int bid, int nbk, const double *part, double *sc) {
     __shared__ double sh[2][256];
     if (sc[8] != 0.0) return;   // uniform over the block
     double rzn, rr;
@@ -692,9 +711,10 @@ __global__ void __launch_bounds__(256) k_cg_step_end(int nbk, const double *part
     if (sc[2] <= sc[10]) sc[8] = 1.0;
     else if (sc[9] >= sc[11]) sc[8] = 2.0;
 }
+__global__ void __launch_bounds__(256) k_cg_step_end(int nbk, const double *part, double *sc) { d_cg_step_end(blockIdx.x, nbk, part, sc); }
 // stopping threshold rtol^2 |b|^2 (|b|^2 in sc[4], 1 if b = 0) and the stop
 // flag before the first iteration (already converged, or no iterations allowed)
-__global__ void k_cg_start(double *sc, double rtol, int maxit) {
+__device__ __forceinline__ void d_cg_start(int bid, double *sc, double rtol, int maxit) {
     const double bb = sc[4];
     const double tol2 = rtol * rtol * (bb > 0 ? bb : 1.0);
     sc[8] = (!(sc[2] > tol2) || maxit <= 0) ? 3.0 : 0.0;
@@ -702,17 +722,20 @@ __global__ void k_cg_start(double *sc, double rtol, int maxit) {
     sc[10] = tol2;
     sc[11] = (double)maxit;
 }
+__global__ void k_cg_start(double *sc, double rtol, int maxit) { d_cg_start(blockIdx.x, sc, rtol, maxit); }
 
 // F = MFinv (qF + (c/3) D^T E)  (qF rows [a][n], F node-major [n][a])
-__global__ void k_backsub(int nn, int dim, double c3, const int *rp, const int *col, const double *val, const double *E,
+__device__ __forceinline__ void d_backsub(int bid, int nn, int dim, double c3, const int *rp, const int *col, const double *val, const double *E,
                           const double *qF, const double *MFinv, double *F) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = bid * 256 + threadIdx.x;
     if (r >= nn * dim) return;
     double s = 0.0;
     for (int k = rp[r]; k < rp[r + 1]; ++k) s += val[k] * E[col[k]];
     const int n = r / dim, a = r % dim;
     F[r] = MFinv[n] * (qF[(int64_t)a * nn + n] + c3 * s);
 }
+__global__ void k_backsub(int nn, int dim, double c3, const int *rp, const int *col, const double *val, const double *E,
+                          const double *qF, const double *MFinv, double *F) { d_backsub(blockIdx.x, nn, dim, c3, rp, col, val, E, qF, MFinv, F); }
 
 // pointwise energy balance: cv T/dt + sigP a c T^4 = c sigE E + cv T*/dt
 // (Newton safeguarded by bisection on [0, rhs dt/cv]; stop at |f| <= rtol |rhs|).
@@ -722,10 +745,10 @@ __global__ void k_backsub(int nn, int dim, double c3, const int *rp, const int *
 // flags: [0] a node without a positive root (no floor), [1] the largest
 // iteration count, [2] a node that hit maxit; the count is reduced over the
 // wave first, and a wave whose count is already stored skips its atomic.
-__global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, int maxit, double T_floor,
+__device__ __forceinline__ void d_eliminate(int bid, int nn, double a, double c, double dt, double rtol, int maxit, double T_floor,
                             const double *cvn, const double *sigE, const double *sigP, const double *E,
                             const double *Tstar, double *T, int *flags) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = bid * 256 + threadIdx.x;
     int it = 0;
     bool bad = false, capped = false;
     if (n < nn) {
@@ -763,6 +786,9 @@ __global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, 
         if (any_capped) atomicOr(&flags[2], 1);
     }
 }
+__global__ void k_eliminate(int nn, double a, double c, double dt, double rtol, int maxit, double T_floor,
+                            const double *cvn, const double *sigE, const double *sigP, const double *E,
+                            const double *Tstar, double *T, int *flags) { d_eliminate(blockIdx.x, nn, a, c, dt, rtol, maxit, T_floor, cvn, sigE, sigP, E, Tstar, T, flags); }
 
 __global__ void k_zero4(int *p) { p[threadIdx.x] = 0; }
 
@@ -1027,3 +1053,4 @@ smrt_status LoSolver::solve(hipStream_t s, const LoInputs &in, double *E, double
 }  // namespace smrt
 
 #include "mg_precond.inc"
+#include "lo_batch.inc"

@@ -60,6 +60,7 @@ struct Sweep2DArgs {
     void *part;                      // real2 [NQC][nbands][NT][4 nodes][16 rows]: (sum_g I, sum_g sigma_g I)
     uint64_t *trace;                 // [NQC][nbands][slot = (wave, k, channel)][nx][2 values][words]
     int *ctr;                        // [4]: (unused), workgroups done, epoch, error flag
+    const int *gate;                 // nullptr, or a flag: the problem is swept only while it is nonzero
 };
 
 // One sweep launch: one problem (args by value) or a batch of problems

@@ -115,6 +115,7 @@ _SIGS = {
     "smrt_batch_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _ip, _dp], C.c_int),
     "smrt_batch_sweep_resident": ([C.c_void_p, C.c_double, C.c_int, C.c_int, _dp, _dp], C.c_int),
     "smrt_batch_step": ([C.c_void_p, _dp, C.POINTER(StepStats)], C.c_int),
+    "smrt_batch_run": ([C.c_void_p, C.c_int, _dp, C.POINTER(StepStats), C.c_int], C.c_int),
     "smrt_qmesh_create": ([C.c_int, _dp, C.c_int, C.POINTER(C.c_int32), C.POINTER(QuadDesc), C.c_int, C.c_int,
                            C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "smrt_qmesh_destroy": ([C.c_void_p], None),
@@ -424,6 +425,19 @@ class Batch:
         st = (StepStats * n)()
         self._check(self.L.smrt_batch_step(self.h, _p(d), st))
         return [s.as_dict() for s in st]
+
+    def run(self, n_steps, dt, capture_graph=False):
+        """n_steps time steps of every problem with device-side convergence
+        control; dt scalar, per problem [n] or per step and problem [n_steps][n].
+        Returns the stats as a list of n_steps lists of per-problem dicts."""
+        n, ns = len(self.contexts), int(n_steps)
+        d = np.asarray(dt, dtype=np.float64)
+        if d.ndim == 1:
+            d = d[None, :]
+        d = _f64(np.broadcast_to(d, (ns, n)).ravel())
+        st = (StepStats * (ns * n))()
+        self._check(self.L.smrt_batch_run(self.h, ns, _p(d), st, int(bool(capture_graph))))
+        return [[st[s * n + i].as_dict() for i in range(n)] for s in range(ns)]
 
 
 class QuadMeshSweep:
