@@ -234,6 +234,37 @@ def batched(args):
            "sweep_ms": ks, "sweep_units_per_s": units / (ks * 1e-3),
            "sweep_hbm_frac": alg / (ks * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "graph_pass_ms": ms, "graph_pass_units_per_s": units / (ms * 1e-3), "setup_s": setup_s}
+    # five backward-Euler steps of every problem (FP32 sweep, FP64 LO), from
+    # the initial states: the host-driven lock-stepped step, then the run with
+    # device-side convergence control replayed from one captured HIP graph
+    n_steps = 5
+    pu = [q.nx * q.ny * q.n_angles * q.G for q in ps]
+
+    def swept(stats):
+        return sum(st[i]["outer"] * pu[i] for st in stats for i in range(len(ps)))
+
+    for c, q in zip(ctxs, ps):
+        c.set_state(q.initial_T_nodes())
+    t0 = _t.perf_counter()
+    host = [b.step(dt) for _ in range(n_steps)]
+    t_host = _t.perf_counter() - t0
+    for c, q in zip(ctxs, ps):
+        c.set_state(q.initial_T_nodes())
+    t0 = _t.perf_counter()
+    dev = b.run(n_steps, dt, capture_graph=True)
+    t_dev = _t.perf_counter() - t0
+    res["five_steps"] = {
+        "workload": "5 steps of every problem from its initial state, dt=1e-3, consistent SM, eps 1e-3, FP32 sweep + "
+                    "FP64 LO (Jacobi CG)",
+        "device_control": {"wall_s": t_dev, "ms_per_step": t_dev / n_steps * 1e3,
+                           "swept_units_per_s": swept(dev) / t_dev,
+                           "outer_per_step": [max(st[i]["outer"] for i in range(len(ps))) for st in dev],
+                           "outer_total": sum(st[i]["outer"] for st in dev for i in range(len(ps))),
+                           "cg_total": sum(st[i]["cg_total"] for st in dev for i in range(len(ps)))},
+        "host_lockstep": {"wall_s": t_host, "ms_per_step": t_host / n_steps * 1e3,
+                          "swept_units_per_s": swept(host) / t_host,
+                          "outer_total": sum(st[i]["outer"] for st in host for i in range(len(ps)))},
+        "speedup": t_host / t_dev}
     b.close()
     for c in ctxs:
         c.close()

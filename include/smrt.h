@@ -415,8 +415,8 @@ smrt_status smrt_batch_step(smrt_batch *batch, const double *dt, smrt_step_stats
  * with nonlinear elimination, Jacobi-preconditioned CG, their tests and
  * caps) runs for all problems in one persistent launch whose workgroups
  * meet at grid barriers.  The host queues blocks of 4 outer iterations of
- * the whole batch (one batched sweep each; a converged problem is not swept
- * again and its LO is skipped) and waits once per block, and once per step;
+ * the whole batch (one batched sweep each; a converged problem skips the
+ * rest of them) and waits once per block, and once per step;
  * capture_graph != 0 records the block once as a HIP graph and replays it.
  * dt[n_steps * n]: step s of problem p at dt[s * n + p]; stats (may be NULL)
  * [n_steps * n] likewise (t_total_ms: the whole batch's step; t_sweep_ms and

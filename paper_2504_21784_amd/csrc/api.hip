@@ -314,10 +314,10 @@ static Sweep2DArgs sweep_args(const smrt_ctx *x, const void *psi_prev, void *psi
     return a;
 }
 
-static void finalize_moments(smrt_ctx *x, double *mom, const void *part = nullptr) {
+static void finalize_moments(smrt_ctx *x, double *mom, const void *part = nullptr, const int *gate = nullptr) {
     if (!part) part = x->d_part.p;
-    if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const float *)part, x->d_sigq.p, mom);
-    else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const double *)part, x->d_sigq.p, mom);
+    if (x->fp32) run_moments_finalize<float>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const float *)part, x->d_sigq.p, mom, gate);
+    else run_moments_finalize<double>(x->stream, x->nx, x->ny, x->chunks, x->d_qc_dir.p, x->d_dirs64.p, (const double *)part, x->d_sigq.p, mom, gate);
 }
 
 static void run_sweep(smrt_ctx *x, const void *psi_prev, void *psi_out, const void *sig2, const void *qiso,
@@ -1204,14 +1204,14 @@ static double prepare_step_tables(smrt_ctx *x, double dt) {
     return icdt;
 }
 
-static void run_source_at(smrt_ctx *x, const double *T) {
+static void run_source_at(smrt_ctx *x, const double *T, const int *gate = nullptr) {
     const bool d2 = x->dim == 2;
     if (x->fp32) {
-        run_source<float>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (float *)x->d_qiso.p, d2 ? (float *)x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p);
-        if (d2) run_qtab2d<float, float>(x->stream, x->nx, x->ny, x->G, (const float *)x->d_qnat.p, 1, x->nn, (float *)x->d_qiso.p);
+        run_source<float>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (float *)x->d_qiso.p, d2 ? (float *)x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p, gate);
+        if (d2) run_qtab2d<float, float>(x->stream, x->nx, x->ny, x->G, (const float *)x->d_qnat.p, 1, x->nn, (float *)x->d_qiso.p, gate);
     } else {
-        run_source<double>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (double *)x->d_qiso.p, d2 ? x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p);
-        if (d2) run_qtab2d<double, double>(x->stream, x->nx, x->ny, x->G, x->d_qnat.p, 1, x->nn, (double *)x->d_qiso.p);
+        run_source<double>(x->stream, x->nn, x->npc, x->G, T, x->d_nu.p, x->a, x->c, x->d_sig.p, d2 ? nullptr : (double *)x->d_qiso.p, d2 ? x->d_qnat.p : nullptr, x->d_sigP.p, x->d_sigF.p, gate);
+        if (d2) run_qtab2d<double, double>(x->stream, x->nx, x->ny, x->G, x->d_qnat.p, 1, x->nn, (double *)x->d_qiso.p, gate);
     }
 }
 
@@ -1509,7 +1509,7 @@ struct BatchRunState {
     DevBuf<RunCtl> ctl;      // [n] this step's control blocks
     DevBuf<RunCtl> hist;     // [n_steps][n] control blocks at the end of every step
     DevBuf<LoProb> lo;       // [n]
-    DevBuf<unsigned> bar;    // [2] the batched LO kernel's grid barrier
+    DevBuf<unsigned> bar;    // [LO_BAR_WORDS] the batched LO kernel's grid barrier
     DevBuf<int> flags;       // [0] a batched-LO barrier wait past its bound, [1] problems still iterating
     int *h_flags = nullptr;  // pinned: the two flags
     RunCtl *h_ctl = nullptr; // pinned: the control blocks at the end of a step
@@ -1919,12 +1919,10 @@ extern "C" smrt_status smrt_batch_step(smrt_batch *b, const double *dt, smrt_ste
 // its control block, and its LO solve (Newton and CG, Sec. 5) runs inside the
 // batched LO kernel, so the host queues blocks of RUN_BLOCK outer iterations
 // and waits once per block to learn whether any problem still iterates.  A
-// problem whose step has converged is not swept again, and its LO is
-// skipped; the small per-problem kernels of an outer iteration (emission
-// tables at the outer temperature, moment finalisation, closures, the
-// iterate change) run on for it but only reproduce the values it already
-// holds, since its temperature, intensity and moment partials no longer
-// change.
+// problem whose step has converged skips every kernel of the remaining
+// outer iterations of the block: each takes the problem's control-block flag
+// as a gate (the batched sweep and LO per problem, the per-problem kernels
+// as a whole).
 constexpr int RUN_BLOCK = 4;
 
 __global__ void k_run_begin(RunCtl *ctl, int n) {
@@ -1970,6 +1968,14 @@ __global__ void k_outer_decide(RunCtl *ctl, const double *sc, const int *sweep_c
     if (done) c.active = 0;
 }
 
+// a = b and c = d (n doubles each), skipped while *gate is 0
+__global__ void k_copy2_gated(const int *gate, int64_t n, double *a, const double *b, double *c, const double *d) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n || !*gate) return;
+    a[i] = b[i];
+    c[i] = d[i];
+}
+
 // flags[1] = problems still iterating (one thread)
 __global__ void k_run_count(const RunCtl *ctl, int n, int *flags) {
     int a = 0;
@@ -1977,30 +1983,36 @@ __global__ void k_run_count(const RunCtl *ctl, int n, int *flags) {
     flags[1] = a;
 }
 
-// one outer iteration of every problem (the converged ones skip the sweep and the LO)
+// One outer iteration of every problem; a converged problem (its control
+// block no longer active) skips every kernel of it.
 static void run_outer_iteration(smrt_batch *b, BatchRunState &R, const std::vector<double> &dt) {
     hipStream_t S = b->stream;
     const size_t n = b->P.size();
-    for (smrt_ctx *x : b->P) run_source_at(x, x->d_Tl.p);
+    for (size_t i = 0; i < n; ++i) run_source_at(b->P[i], b->P[i]->d_Tl.p, &R.ctl.p[i].active);
     batch_launch(b);
     for (size_t i = 0; i < n; ++i) {
         smrt_ctx *x = b->P[i];
-        finalize_moments(x, x->d_mom.p);
-        SMRT_HIP(hipMemcpyAsync(x->d_Tn.p, x->d_Tl.p, 8 * x->nn, hipMemcpyDeviceToDevice, S));
-        SMRT_HIP(hipMemcpyAsync(x->d_En.p, x->d_El.p, 8 * x->nn, hipMemcpyDeviceToDevice, S));
-        run_closures(S, closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt[i], x->d_mom.p, x->d_sigP.p,
-                                     x->d_sigF.p, x->d_Estar.p, x->d_Fstar.p, x->d_clos.p));
+        const int *on = &R.ctl.p[i].active;
+        finalize_moments(x, x->d_mom.p, nullptr, on);
+        hipLaunchKernelGGL(k_copy2_gated, dim3(nblk(x->nn)), dim3(256), 0, S, on, (int64_t)x->nn, x->d_Tn.p,
+                           (const double *)x->d_Tl.p, x->d_En.p, (const double *)x->d_El.p);
+        ClosureArgs ca = closure_args(x, x->opt.scheme == SMRT_SM_INDEPENDENT ? 1 : 0, dt[i], x->d_mom.p, x->d_sigP.p,
+                                      x->d_sigF.p, x->d_Estar.p, x->d_Fstar.p, x->d_clos.p);
+        ca.gate = on;
+        run_closures(S, ca);
     }
     run_lo_batch(S, R.lb, R.grid);
     for (size_t i = 0; i < n; ++i) {
         smrt_ctx *x = b->P[i];
-        x->lo.dot(S, x->d_Tn.p, nullptr, x->d_Tl.p, 6, false);
-        x->lo.dot(S, x->d_En.p, nullptr, x->d_El.p, 6, true);
+        const int *on = &R.ctl.p[i].active;
+        x->lo.dot_gated(S, on, x->d_Tn.p, nullptr, x->d_Tl.p, 6, false);
+        x->lo.dot_gated(S, on, x->d_En.p, nullptr, x->d_El.p, 6, true);
+        // the copies precede the decision, which may clear the flag that gates them
+        hipLaunchKernelGGL(k_copy2_gated, dim3(nblk(x->nn)), dim3(256), 0, S, on, (int64_t)x->nn, x->d_Tl.p,
+                           (const double *)x->d_Tn.p, x->d_El.p, (const double *)x->d_En.p);
         const int maxo = x->opt.fixed_outer > 0 ? x->opt.fixed_outer : x->opt.max_outer;
         hipLaunchKernelGGL(k_outer_decide, dim3(1), dim3(1), 0, S, R.ctl.p + i, (const double *)x->lo.sc.p,
                            (const int *)x->d_ctr.p, x->opt.fixed_outer, maxo, x->opt.eps_outer);
-        SMRT_HIP(hipMemcpyAsync(x->d_Tl.p, x->d_Tn.p, 8 * x->nn, hipMemcpyDeviceToDevice, S));
-        SMRT_HIP(hipMemcpyAsync(x->d_El.p, x->d_En.p, 8 * x->nn, hipMemcpyDeviceToDevice, S));
     }
 }
 
@@ -2075,7 +2087,7 @@ extern "C" smrt_status smrt_batch_run(smrt_batch *b, int n_steps, const double *
             R.lo.alloc((int64_t)n);
         }
         if (R.hist.n < (int64_t)n_steps * (int64_t)n) R.hist.alloc((int64_t)n_steps * (int64_t)n);
-        if (!R.bar.p) R.bar.alloc(2);
+        if (!R.bar.p) R.bar.alloc(LO_BAR_WORDS);
         if (!R.flags.p) R.flags.alloc(2);
         if (!R.h_flags) SMRT_HIP(hipHostMalloc((void **)&R.h_flags, 2 * sizeof(int), hipHostMallocDefault));
         if (!R.h_ctl) SMRT_HIP(hipHostMalloc((void **)&R.h_ctl, LO_BATCH_MAX * sizeof(RunCtl), hipHostMallocDefault));
@@ -2085,7 +2097,7 @@ extern "C" smrt_status smrt_batch_run(smrt_batch *b, int n_steps, const double *
             SMRT_HIP(hipEventCreate(&e));
             R.ev.push_back(e);
         }
-        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, S, (int *)R.bar.p, 2);
+        hipLaunchKernelGGL(k_zero_int, dim3(nblk(LO_BAR_WORDS)), dim3(256), 0, S, (int *)R.bar.p, LO_BAR_WORDS);
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, S, R.flags.p, 2);
         R.lb = LoBatch{};
         R.lb.P = R.lo.p;

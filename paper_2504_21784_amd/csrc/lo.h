@@ -81,6 +81,7 @@ struct ClosureArgs {
     const double *sigP, *sigF;    // [nn] at the outer iterate's T
     const double *Estar, *Fstar;  // [nn], [nn][dim]
     double *out;                  // [3+1+dim][nn]
+    const int *gate;              // nullptr, or a device flag: no work while it is 0
 };
 void run_closures(hipStream_t s, const ClosureArgs &a);
 void run_eliminate(hipStream_t s, int nn, double a, double c, double dt, double rtol, int maxit, double T_floor,
@@ -143,13 +144,14 @@ struct LoProb {
 };
 
 constexpr int LO_BATCH_MAX = 64;   // problems of one batched LO launch
+constexpr int LO_BAR_WORDS = 512;  // words of the batched LO's grid barrier
 // Launch arguments of the batched LO kernel: the problems and where each
 // problem's node blocks start in the launch's sequence of node blocks.
 struct LoBatch {
     const LoProb *P;
     int np;
     int vb_n[LO_BATCH_MAX + 1];    // prefix sums of nbk
-    unsigned *bar;                 // [2] grid barrier: arrivals, generation
+    unsigned *bar;                 // [LO_BAR_WORDS] grid barrier: generation, top and group counters
     int *abort;                    // set when a barrier wait exceeds its bound
 };
 // One LO solve (Newton with nonlinear elimination, Jacobi-PCG) of every
@@ -191,6 +193,9 @@ struct LoSolver {
     void init(int dim, int nx, int ny, const std::vector<double> &xe, const std::vector<double> &ye,
               const double alpha[2], double c, double a);
     double dot(hipStream_t s, const double *x, const double *y, const double *cdiff, int slot, bool accumulate);
+    // dot(), skipped while the device flag *gate is 0
+    void dot_gated(hipStream_t s, const int *gate, const double *x, const double *y, const double *cdiff, int slot,
+                   bool accumulate);
     double fetch(hipStream_t s, int slot);
     void fetch_flags(hipStream_t s, int fl[4]);   // the elimination flags, through pinned memory
     void ensure_hbuf();

@@ -76,7 +76,7 @@ __device__ inline double Tten(const NodeMom2D &m, int a, int b) { return m.Pi[a]
 __global__ void k_closures2d(ClosureArgs A) {
     const int nn = 4 * A.nx * A.ny;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
+    if (n >= nn || (A.gate && !*A.gate)) return;
     const int cell = n >> 2, l = n & 3, lx = l & 1, ly = l >> 1;
     const int i = cell % A.nx, j = cell / A.nx;
     const double hx = A.hx[i], hy = A.hy[j], w = 0.25 * hx * hy, c = A.c;
@@ -841,6 +841,23 @@ void LoSolver::init(int dim_, int nx, int ny, const std::vector<double> &xe, con
     bpart.alloc(2 * (int64_t)((nn + 255) / 256));
     apart.alloc((int64_t)((nn + 255) / 256));
     flags.alloc(4);
+}
+
+// the same sum, skipped while *gate is 0
+__global__ void k_dot_partial_g(const int *gate, int n, const double *a, const double *b, const double *cdiff,
+                                double *part) {
+    if (!*gate) return;
+    d_dot_partial(blockIdx.x, n, a, b, cdiff, part);
+}
+__global__ void k_dot_finish_g(const int *gate, const double *part, double *out, int slot, int accumulate) {
+    if (!*gate) return;
+    d_dot_finish(blockIdx.x, part, out, slot, accumulate);
+}
+void LoSolver::dot_gated(hipStream_t s, const int *gate, const double *x, const double *y, const double *cdiff,
+                         int slot, bool accumulate) {
+    hipLaunchKernelGGL(k_dot_partial_g, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, gate, nn, x, y, cdiff, part.p);
+    hipLaunchKernelGGL(k_dot_finish_g, dim3(1), dim3(RED_BLOCKS), 0, s, gate, (const double *)part.p, sc.p, slot,
+                       accumulate ? 1 : 0);
 }
 
 double LoSolver::dot(hipStream_t s, const double *x, const double *y, const double *cdiff, int slot, bool accumulate) {

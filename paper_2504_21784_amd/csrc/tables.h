@@ -4,6 +4,9 @@
 
 namespace smrt {
 
+// A launcher's gate (nullptr: always) is a device flag: while it is 0 the
+// kernels return at once (a converged problem of a multi-step batched run).
+
 constexpr int NBERN = 24;   // Bernoulli terms of the small-argument Planck series
 constexpr int MAXG = 64;    // largest group count
 
@@ -13,7 +16,8 @@ void run_opacity(hipStream_t s, int ncell, int npc, int G, const double *T, cons
                  const double *sigma0, double lo, double hi, const double *nu, double icdt, double *sig, real *sig2);
 template <typename real>
 void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const double *nu, double a, double c,
-                const double *sig, real *qiso, real *qnat, double *sigP, double *sigF);
+                const double *sig, real *qiso, real *qnat, double *sigP, double *sigF,
+                const int *gate = nullptr);
 template <typename real>
 void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const double *sigt, double icdt, real *stab);
 // 2D: opacity sigma[cell][G] and its skewed per-quadrant (sigma_t, sigma) tables in one pass
@@ -22,7 +26,8 @@ void run_opacity_tab2d(hipStream_t s, int nx, int ny, int G, const double *T, co
                        const double *sigma0, double lo, double hi, const double *nu, double icdt, double *sig,
                        real *stab);
 template <typename real, typename src_t>
-void run_qtab2d(hipStream_t s, int nx, int ny, int G, const src_t *q, int64_t sn, int64_t sg, real *qtab);
+void run_qtab2d(hipStream_t s, int nx, int ny, int G, const src_t *q, int64_t sn, int64_t sg, real *qtab,
+                const int *gate = nullptr);
 void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
                      double *psi);
 void run_side_inflow(hipStream_t s, int nsides, int G, const double *nu, double a, double c, const int *kind,
@@ -91,7 +96,8 @@ template <typename real>
 // sigq: scratch of 12 * n_nodes doubles (per-quadrant sigma-weighted moments)
 // qc_dir: direction of each chunk; dirs: FP64 per-direction table (mu, eta, w, w mu, w eta, w mu^2, w mu eta, w eta^2)
 void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const int *qc_dir, const double *dirs,
-                          const real *part, double *sigq, double *mom);
+                          const real *part, double *sigq, double *mom,
+                          const int *gate = nullptr);
 template <typename real>
 void run_moments1d(hipStream_t s, int nx, int G, int nang, const real *mw, const double *sig, const real *psi, double *mom);
 void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *om, const double *w, double c,

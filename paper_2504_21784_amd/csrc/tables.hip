@@ -148,9 +148,9 @@ __global__ void k_opacity(int ncell, int npc, int G, const double *T, const int 
 // ---------------------------------------------------------------------------
 template <typename real>
 __global__ void k_source(int nn, int npc, int G, const double *T, const double *nu, double a, double c,
-                         const double *sig, real *qiso, real *qnat, double *sigP, double *sigF) {
+                         const double *sig, real *qiso, real *qnat, double *sigP, double *sigF, const int *gate) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
+    if (n >= nn || (gate && !*gate)) return;
     const double Tn = T[n];
     GroupFractions fr(G, nu, Tn);
     const int cell = n / npc, l = n - cell * npc;
@@ -279,10 +279,10 @@ __global__ void k_opacity_tab2d(int nx, int ny, int G, const double *__restrict_
 // blocks of TAB_GB (gathers first, then stores).  A padding slot stores zeros.
 template <typename real, typename src_t>
 __global__ void k_qtab2d(int nx, int ny, int G, const src_t *__restrict__ q, int64_t sn, int64_t sg,
-                         real *__restrict__ qtab) {
+                         real *__restrict__ qtab, const int *gate) {
     const int64_t cs = cell_slab(nx, ny);
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= 4 * cs) return;
+    if (i >= 4 * cs || (gate && !*gate)) return;
     const int64_t slot = i % cs;
     const int qd = (int)(i / cs);
     int cell = 0, flip = 0;
@@ -806,8 +806,9 @@ __global__ void k_add_scalar(int64_t n, const double *a, double v, double *out) 
 template <typename real>
 __global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkRanges cr, const int *qc_dir,
                                                           const double *dirs, const real *part, double *mom,
-                                                          double *sigq) {
+                                                          double *sigq, const int *gate) {
     using r2 = typename std::conditional<sizeof(real) == 4, float2, double2>::type;
+    if (gate && !*gate) return;   // uniform over the grid
     const int nb = (ny + BAND_ROWS - 1) / BAND_ROWS, NT = nx + BAND_ROWS - 1;
     const int ntb = (NT + 3) / 4;
     int b = blockIdx.x;
@@ -856,9 +857,9 @@ __global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkR
     for (int k = 0; k < 3; ++k) sigq[(3 * q + k) * nn + n] = acc[6 + k];
 }
 
-__global__ void k_moments_sigma(int64_t nn, const double *sigq, double *mom) {
+__global__ void k_moments_sigma(int64_t nn, const double *sigq, double *mom, const int *gate) {
     const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (n >= nn) return;
+    if (n >= nn || (gate && !*gate)) return;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         mom[(24 + k) * nn + n] = ((sigq[k * nn + n] + sigq[(3 + k) * nn + n]) + sigq[(6 + k) * nn + n]) +
@@ -982,8 +983,8 @@ void run_opacity(hipStream_t s, int ncell, int npc, int G, const double *T, cons
 }
 template <typename real>
 void run_source(hipStream_t s, int nn, int npc, int G, const double *T, const double *nu, double a, double c,
-                const double *sig, real *qiso, real *qnat, double *sigP, double *sigF) {
-    hipLaunchKernelGGL(k_source<real>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, npc, G, T, nu, a, c, sig, qiso, qnat, sigP, sigF);
+                const double *sig, real *qiso, real *qnat, double *sigP, double *sigF, const int *gate) {
+    hipLaunchKernelGGL(k_source<real>, dim3(nblk(nn, 128)), dim3(128), 0, s, nn, npc, G, T, nu, a, c, sig, qiso, qnat, sigP, sigF, gate);
 }
 template <typename real>
 void run_opacity_tab2d(hipStream_t s, int nx, int ny, int G, const double *T, const int *region, int model,
@@ -999,9 +1000,10 @@ void run_stab2d(hipStream_t s, int nx, int ny, int G, const double *sig, const d
     hipLaunchKernelGGL(k_stab2d<real>, dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, sig, sigt, icdt, stab);
 }
 template <typename real, typename src_t>
-void run_qtab2d(hipStream_t s, int nx, int ny, int G, const src_t *q, int64_t sn, int64_t sg, real *qtab) {
+void run_qtab2d(hipStream_t s, int nx, int ny, int G, const src_t *q, int64_t sn, int64_t sg, real *qtab,
+                const int *gate) {
     const int64_t n = 4 * cell_slab(nx, ny);
-    hipLaunchKernelGGL((k_qtab2d<real, src_t>), dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, q, sn, sg, qtab);
+    hipLaunchKernelGGL((k_qtab2d<real, src_t>), dim3(nblk(n, 256)), dim3(256), 0, s, nx, ny, G, q, sn, sg, qtab, gate);
 }
 void run_equilibrium(hipStream_t s, int nn, int G, int nang, const double *T, const double *nu, double a, double c,
                      double *psi) {
@@ -1132,12 +1134,12 @@ void run_copy_from(hipStream_t s, int64_t n, const real *src, double *dst) {
 }
 template <typename real>
 void run_moments_finalize(hipStream_t s, int nx, int ny, const ChunkRanges &cr, const int *qc_dir, const double *dirs,
-                          const real *part, double *sigq, double *mom) {
+                          const real *part, double *sigq, double *mom, const int *gate) {
     const int nb = (ny + BAND_ROWS - 1) / BAND_ROWS, NT = nx + BAND_ROWS - 1;
     hipLaunchKernelGGL(k_moments_quadrant<real>, dim3(4 * nb * ((NT + 3) / 4)), dim3(256), 0, s, nx, ny, cr, qc_dir,
-                       dirs, part, mom, sigq);
+                       dirs, part, mom, sigq, gate);
     const int64_t nn = (int64_t)nx * ny * 4;
-    hipLaunchKernelGGL(k_moments_sigma, dim3(nblk(nn, 256)), dim3(256), 0, s, nn, (const double *)sigq, mom);
+    hipLaunchKernelGGL(k_moments_sigma, dim3(nblk(nn, 256)), dim3(256), 0, s, nn, (const double *)sigq, mom, gate);
 }
 template <typename real>
 void launch_sweep1d(const Sweep1DArgs &a, hipStream_t s) {
@@ -1157,14 +1159,15 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
     template void run_opacity<real>(hipStream_t, int, int, int, const double *, const int *, int, const double *,  \
                                     double, double, const double *, double, double *, real *);                      \
     template void run_source<real>(hipStream_t, int, int, int, const double *, const double *, double, double,      \
-                                   const double *, real *, real *, double *, double *);                             \
+                                   const double *, real *, real *, double *, double *, const int *);                \
     template void run_fill_inflow<real>(hipStream_t, int, int, int, int, int, const double *, real *);              \
     template void run_reflect<real>(hipStream_t, int, int, int, int, int, int, const int *, const double *,         \
                                     const double *, const int *, const real *, real *, double *);                   \
     template void run_stab2d<real>(hipStream_t, int, int, int, const double *, const double *, double, real *);     \
     template void run_opacity_tab2d<real>(hipStream_t, int, int, int, const double *, const int *, int,            \
                                           const double *, double, double, const double *, double, double *, real *); \
-    template void run_qtab2d<real, double>(hipStream_t, int, int, int, const double *, int64_t, int64_t, real *);  \
+    template void run_qtab2d<real, double>(hipStream_t, int, int, int, const double *, int64_t, int64_t, real *,   \
+                                           const int *);                                                          \
     template void run_copy_to<real>(hipStream_t, int64_t, const double *, real *);                                  \
     template void run_copy_from<real>(hipStream_t, int64_t, const real *, double *);                                \
     template void run_qiso_to_internal<real>(hipStream_t, int, int, int, const double *, real *);                   \
@@ -1172,11 +1175,12 @@ void run_psi_EF(hipStream_t s, int nn, int dim, int G, int nang, const double *o
     template void run_psi_to_internal<real>(hipStream_t, int, int, int, int, const int *, const double *, real *);  \
     template void run_psi_from_internal<real>(hipStream_t, int, int, int, int, const int *, const real *, double *); \
     template void run_moments_finalize<real>(hipStream_t, int, int, const ChunkRanges &, const int *,              \
-                                              const double *, const real *, double *, double *);                                                        \
+                                              const double *, const real *, double *, double *, const int *);                                                        \
     template void launch_sweep1d<real>(const Sweep1DArgs &, hipStream_t);                                           \
     template void run_moments1d<real>(hipStream_t, int, int, int, const real *, const double *, const real *, double *);
 INST(float)
-template void run_qtab2d<float, float>(hipStream_t, int, int, int, const float *, int64_t, int64_t, float *);
+template void run_qtab2d<float, float>(hipStream_t, int, int, int, const float *, int64_t, int64_t, float *,
+                                       const int *);
 INST(double)
 
 }  // namespace smrt
