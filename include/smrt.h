@@ -438,7 +438,8 @@ smrt_status smrt_batch_run(smrt_batch *batch, int n_steps, const double *dt, smr
  * cell the bilinear map's Jacobian J_m gives the lumped weight det(J_m)/4
  * and the basis gradients; each edge's normal times length is split evenly
  * between its two vertices.  Cells are swept per direction in dependency
- * levels (all directions' pairs of a level in one launch).
+ * levels, in one launch: a workgroup per (direction, block of 4 groups)
+ * walks its direction's levels with a workgroup barrier between them.
  * ------------------------------------------------------------------------ */
 typedef struct smrt_qmesh smrt_qmesh;
 
@@ -458,7 +459,7 @@ smrt_status smrt_qmesh_create(int n_vertices, const double *xy, int n_cells, con
                               smrt_qmesh **out);
 void smrt_qmesh_destroy(smrt_qmesh *mesh);
 const char *smrt_qmesh_last_error(const smrt_qmesh *mesh);
-/* Number of boundary nodes and of dependency levels (launches per sweep). */
+/* Number of boundary nodes and of dependency levels (the most of any direction). */
 smrt_status smrt_qmesh_info(const smrt_qmesh *mesh, int *n_boundary_nodes, int *n_levels);
 /* One sweep of every (d, g): sig_t[cell][G] (> 0, incl. time absorption),
  * q_iso[node][G], psi_prev[d][g][node] or NULL (zero), inv_c_dt >= 0,

@@ -15,8 +15,12 @@
 // diagonal wavefront of the rectilinear kernel, so cells are ordered per
 // direction by their upwind dependencies: the host assigns every (direction,
 // cell) pair a level (one more than the deepest upwind neighbour, Kahn's
-// algorithm; a cycle is an error), and one launch sweeps all pairs of a
-// level, of every direction at once, one thread per (pair, group).  The
+// algorithm; a cycle is an error) and lists each direction's cells level
+// by level.  One launch sweeps everything: a workgroup of 1024 threads takes
+// one direction and a block of 4 groups and walks that direction's levels,
+// 256 cells x 4 groups at a time, with a workgroup barrier between levels
+// (the upwind values a level reads were written by the same workgroup), so
+// a level costs a barrier and one round of loads instead of a launch.  The
 // host also classifies each edge of each pair as inflow or outflow, so the
 // device never disagrees with the schedule about an edge nearly parallel to
 // the direction.  The local system is solved in registers by Gaussian
@@ -39,7 +43,9 @@ struct QGeomCell {
 struct QArgs {
     int nc, G, nang, NB;
     const QGeomCell *geo;
-    const int2 *sched;            // (d, cell) by level
+    const int *dcell;             // [d][nc]: direction d's cells, level by level
+    const int *dlev;              // level offsets into a direction's cells, direction d's at dlev_base[d]
+    const int *dlev_base;         // [nang + 1]: direction d has levels dlev_base[d+1] - dlev_base[d] - 1
     const unsigned char *flags;   // [d][cell]: bit e inflow edge, bit 4+e outflow edge
     const int *upw;               // [cell][edge][2]: upwind node (>= 0) or -(1 + boundary node)
     const double *om;             // [nang][3]
@@ -62,14 +68,9 @@ __host__ __device__ inline void qref_grad(int l, int m, double &gx, double &gy) 
     }
 }
 
+// the unit (direction d, group g, cell c): local system, elimination, store
 template <typename real>
-__global__ void k_qsweep_level(QArgs A, int p0, int p1) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t pair = p0 + t / A.G;
-    if (pair >= p1) return;
-    const int g = (int)(t % A.G);
-    const int2 dc = A.sched[pair];
-    const int d = dc.x, c = dc.y;
+__device__ __forceinline__ void qsolve_unit(const QArgs &A, int d, int g, int c) {
     const int nn = 4 * A.nc;
     const real mu = (real)A.om[3 * d], eta = (real)A.om[3 * d + 1];
     const QGeomCell &K = A.geo[c];
@@ -143,6 +144,25 @@ __global__ void k_qsweep_level(QArgs A, int p0, int p1) {
     }
 #pragma unroll
     for (int l = 0; l < 4; ++l) psi[slab + 4 * c + l] = x[l];
+}
+
+
+// One workgroup per (direction, block of QGB groups): the direction's levels
+// in order, a workgroup barrier between levels.
+constexpr int QGB = 4, QSWEEP_THREADS = 1024, QCELLS = QSWEEP_THREADS / QGB;
+template <typename real>
+__global__ void __launch_bounds__(QSWEEP_THREADS) k_qsweep_dir(QArgs A) {
+    const int ngb = (A.G + QGB - 1) / QGB;
+    const int d = blockIdx.x / ngb, g = (blockIdx.x % ngb) * QGB + (int)(threadIdx.x % QGB);
+    const int slot = threadIdx.x / QGB;
+    const int *cells = A.dcell + (int64_t)d * A.nc;
+    const int l0 = A.dlev_base[d], l1 = A.dlev_base[d + 1];
+    for (int L = l0; L + 1 < l1; ++L) {
+        const int c0 = A.dlev[L], c1 = A.dlev[L + 1];
+        for (int k = c0 + slot; k < c1; k += QCELLS)
+            if (g < A.G) qsolve_unit<real>(A, d, g, cells[k]);
+        __syncthreads();   // this level's outflow before the next level reads it
+    }
 }
 
 template <typename real>
@@ -221,38 +241,27 @@ struct smrt_qmesh {
     bool fp32 = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    std::vector<int> lev_off;   // [nlev + 1] into sched
     DevBuf<QGeomCell> geo;
-    DevBuf<int2> sched;
+    DevBuf<int> dcell, dlev, dlev_base;   // per direction: cells by level, level offsets
     DevBuf<unsigned char> flags, psi;
     DevBuf<int> upw;
     DevBuf<double> om, sig_t, q, psi_prev, inflow, out, par, wq, sig_m, mom;
     bool swept = false;       // psi holds the intensity of a finished sweep
-    // the level launches of a sweep, captured once (their arguments are fixed per mesh)
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    bool graph_failed = false;
     ~smrt_qmesh() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
-    void launch_levels(hipStream_t s);
+    void launch_sweep(hipStream_t s);
 };
 
-void smrt_qmesh::launch_levels(hipStream_t s) {
+void smrt_qmesh::launch_sweep(hipStream_t s) {
     QArgs A{};
     A.nc = nc; A.G = G; A.nang = nang; A.NB = NB;
-    A.geo = geo.p; A.sched = sched.p; A.flags = flags.p; A.upw = upw.p; A.om = om.p;
+    A.geo = geo.p; A.dcell = dcell.p; A.dlev = dlev.p; A.dlev_base = dlev_base.p; A.flags = flags.p; A.upw = upw.p;
+    A.om = om.p;
     A.sig_t = sig_t.p; A.q = q.p; A.psi_prev = psi_prev.p; A.inflow = inflow.p; A.par = par.p; A.psi = psi.p;
-    for (int L = 0; L < nlev; ++L) {
-        const int p0 = lev_off[L], p1 = lev_off[L + 1];
-        const int64_t nt = (int64_t)(p1 - p0) * G;
-        if (nt == 0) continue;
-        const dim3 grid((unsigned)((nt + 255) / 256));
-        if (fp32) hipLaunchKernelGGL(k_qsweep_level<float>, grid, dim3(256), 0, s, A, p0, p1);
-        else hipLaunchKernelGGL(k_qsweep_level<double>, grid, dim3(256), 0, s, A, p0, p1);
-    }
+    const dim3 grid((unsigned)(nang * ((G + QGB - 1) / QGB)));
+    if (fp32) hipLaunchKernelGGL(k_qsweep_dir<float>, grid, dim3(QSWEEP_THREADS), 0, s, A);
+    else hipLaunchKernelGGL(k_qsweep_dir<double>, grid, dim3(QSWEEP_THREADS), 0, s, A);
 }
 
 static thread_local std::string g_qmesh_error;
@@ -410,25 +419,34 @@ extern "C" smrt_status smrt_qmesh_create(int n_vertices, const double *xy, int n
             qrequire(tail == nc, "the upwind dependencies of a direction form a cycle");
         }
         m->nlev = maxlev + 1;
-        std::vector<int> count(m->nlev + 1, 0);
-        for (size_t k = 0; k < level.size(); ++k) count[level[k] + 1]++;
-        std::partial_sum(count.begin(), count.end(), count.begin());
-        m->lev_off = count;
-        std::vector<int2> sched(level.size());
-        std::vector<int> fill(count.begin(), count.end() - 1);
-        for (int d = 0; d < nang; ++d)
-            for (int c = 0; c < nc; ++c) sched[fill[level[(size_t)d * nc + c]]++] = make_int2(d, c);
+        // per direction: its cells sorted by level and the level offsets
+        std::vector<int> dcell((size_t)nang * nc), dlev, dlev_base(nang + 1, 0);
+        for (int d = 0; d < nang; ++d) {
+            int nl = 0;
+            for (int c = 0; c < nc; ++c) nl = std::max(nl, level[(size_t)d * nc + c] + 1);
+            std::vector<int> count(nl + 1, 0);
+            for (int c = 0; c < nc; ++c) count[level[(size_t)d * nc + c] + 1]++;
+            std::partial_sum(count.begin(), count.end(), count.begin());
+            std::vector<int> fill(count.begin(), count.end() - 1);
+            for (int c = 0; c < nc; ++c) dcell[(size_t)d * nc + fill[level[(size_t)d * nc + c]]++] = c;
+            dlev.insert(dlev.end(), count.begin(), count.end());
+            dlev_base[d + 1] = (int)dlev.size();
+        }
         // device
         if (hip_stream) m->stream = static_cast<hipStream_t>(hip_stream);
         else { SMRT_HIP(hipStreamCreate(&m->stream)); m->own_stream = true; }
         const int64_t nn = 4 * (int64_t)nc, npsi = (int64_t)nang * G * nn;
         m->geo.alloc(nc);
-        m->sched.alloc((int64_t)sched.size());
+        m->dcell.alloc((int64_t)dcell.size());
+        m->dlev.alloc((int64_t)dlev.size());
+        m->dlev_base.alloc(nang + 1);
         m->flags.alloc((int64_t)flags.size());
         m->upw.alloc((int64_t)upw.size());
         m->om.alloc(3 * (int64_t)nang);
         SMRT_HIP(hipMemcpy(m->geo.p, geo.data(), sizeof(QGeomCell) * nc, hipMemcpyHostToDevice));
-        SMRT_HIP(hipMemcpy(m->sched.p, sched.data(), sizeof(int2) * sched.size(), hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->dcell.p, dcell.data(), sizeof(int) * dcell.size(), hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->dlev.p, dlev.data(), sizeof(int) * dlev.size(), hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->dlev_base.p, dlev_base.data(), sizeof(int) * (nang + 1), hipMemcpyHostToDevice));
         SMRT_HIP(hipMemcpy(m->flags.p, flags.data(), flags.size(), hipMemcpyHostToDevice));
         SMRT_HIP(hipMemcpy(m->upw.p, upw.data(), sizeof(int) * upw.size(), hipMemcpyHostToDevice));
         SMRT_HIP(hipMemcpy(m->om.p, quad->omega, sizeof(double) * 3 * nang, hipMemcpyHostToDevice));
@@ -477,30 +495,11 @@ extern "C" smrt_status smrt_qmesh_sweep(smrt_qmesh *m, const double *sig_t, cons
         else if (m->NB) SMRT_HIP(hipMemsetAsync(m->inflow.p, 0, sizeof(double) * m->nang * m->G * m->NB, s));
         const double par[2] = {inv_c_dt, psi_prev ? 1.0 : 0.0};
         SMRT_HIP(hipMemcpyAsync(m->par.p, par, sizeof(par), hipMemcpyHostToDevice, s));
-        if (!m->exec && !m->graph_failed) {
-            // capture the level launches once; a stream that cannot capture launches them directly
-            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-                m->launch_levels(s);
-                hipGraph_t g = nullptr;
-                if (hipStreamEndCapture(s, &g) == hipSuccess && g &&
-                    hipGraphInstantiate(&m->exec, g, nullptr, nullptr, 0) == hipSuccess) {
-                    m->graph = g;
-                } else {
-                    if (g) (void)hipGraphDestroy(g);
-                    m->exec = nullptr;
-                    m->graph_failed = true;
-                }
-            } else {
-                (void)hipGetLastError();
-                m->graph_failed = true;
-            }
-        }
         hipEvent_t e0, e1;
         SMRT_HIP(hipEventCreate(&e0));
         if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); throw Error(SMRT_E_DEVICE, "hipEventCreate failed"); }
         SMRT_HIP(hipEventRecord(e0, s));
-        if (m->exec) SMRT_HIP(hipGraphLaunch(m->exec, s));
-        else m->launch_levels(s);
+        m->launch_sweep(s);
         SMRT_HIP(hipGetLastError());
         SMRT_HIP(hipEventRecord(e1, s));
         if (m->fp32) hipLaunchKernelGGL(k_qcopy_out<float>, dim3((unsigned)((npsi + 255) / 256)), dim3(256), 0, s, npsi,
