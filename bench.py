@@ -552,6 +552,8 @@ def main():
         "sweep_units_per_s": units / (k_ms * 1e-3),
         "fp64_sweep_kernel_ms": k64,
         "fp64_sweep_units_per_s": units / (k64 * 1e-3),
+        # the FP64 sweep moves twice the bytes per unit (64 B: read I*, write I)
+        "fp64_sweep_hbm_frac": 2 * alg_bytes / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "fp32_vs_fp64_sweep_speedup": k64 / k_ms,
         "fixup_sweep_kernel_ms": k_fix,
         "fixup_sweep_cost": k_fix / k_ms - 1.0,

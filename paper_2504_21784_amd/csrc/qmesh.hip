@@ -49,10 +49,10 @@ struct QArgs {
     const unsigned char *flags;   // [d][cell]: bit e inflow edge, bit 4+e outflow edge
     const int *upw;               // [cell][edge][2]: upwind node (>= 0) or -(1 + boundary node)
     const double *om;             // [nang][3]
-    const double *sig_t;          // [cell][G]
-    const double *q;              // [node][G]
-    const double *psi_prev;       // [d][g][node]
-    const double *inflow;         // [d][g][NB]
+    const void *sig_t;            // [cell][G], sweep precision
+    const void *q;                // [node][G], sweep precision
+    const void *psi_prev;         // [d][g][node], sweep precision
+    const void *inflow;           // [d][g][NB], sweep precision
     const double *par;            // [0] inv_c_dt, [1] 1 if psi_prev holds I*, else 0 (set per sweep)
     void *psi;                    // [d][g][node], sweep precision
 };
@@ -77,15 +77,17 @@ __device__ __forceinline__ void qsolve_unit(const QArgs &A, int d, int g, int c)
     const unsigned fl = A.flags[(int64_t)d * A.nc + c];
     real *psi = static_cast<real *>(A.psi);
     const int64_t slab = ((int64_t)d * A.G + g) * nn;
-    const real st = (real)A.sig_t[(int64_t)c * A.G + g];
+    const real *sig_t = static_cast<const real *>(A.sig_t), *q = static_cast<const real *>(A.q);
+    const real *psi_prev = static_cast<const real *>(A.psi_prev), *inflow = static_cast<const real *>(A.inflow);
+    const real st = sig_t[(int64_t)c * A.G + g];
     real M[4][4], b[4];
-    const double icdt = A.par[0];
+    const real icdt = (real)A.par[0];
     const bool has_prev = A.par[1] != 0.0;
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-        double ql = A.q[(int64_t)(4 * c + l) * A.G + g];
-        if (has_prev) ql += icdt * A.psi_prev[slab + 4 * c + l];
-        b[l] = (real)K.w[l] * (real)ql;
+        real ql = q[(int64_t)(4 * c + l) * A.G + g];
+        if (has_prev) ql += icdt * psi_prev[slab + 4 * c + l];
+        b[l] = (real)K.w[l] * ql;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             double gx, gy;
@@ -106,8 +108,7 @@ __device__ __forceinline__ void qsolve_unit(const QArgs &A, int d, int g, int c)
                 M[l][l] += on;
             } else if ((fl >> e) & 1) {
                 const int u = A.upw[(4 * c + e) * 2 + j];
-                const real up = u >= 0 ? psi[slab + u]
-                                       : (real)A.inflow[((int64_t)d * A.G + g) * A.NB + (-u - 1)];
+                const real up = u >= 0 ? psi[slab + u] : inflow[((int64_t)d * A.G + g) * A.NB + (-u - 1)];
                 b[l] -= on * up;
             }
         }
@@ -163,6 +164,12 @@ __global__ void __launch_bounds__(QSWEEP_THREADS) k_qsweep_dir(QArgs A) {
             if (g < A.G) qsolve_unit<real>(A, d, g, cells[k]);
         __syncthreads();   // this level's outflow before the next level reads it
     }
+}
+
+// double inputs to the sweep's precision
+__global__ void k_qto_f32(int64_t n, const double *in, float *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
 }
 
 template <typename real>
@@ -246,6 +253,7 @@ struct smrt_qmesh {
     DevBuf<unsigned char> flags, psi;
     DevBuf<int> upw;
     DevBuf<double> om, sig_t, q, psi_prev, inflow, out, par, wq, sig_m, mom;
+    DevBuf<float> sig_t32, q32, psi_prev32, inflow32;   // FP32 sweeps read their inputs in FP32
     bool swept = false;       // psi holds the intensity of a finished sweep
     ~smrt_qmesh() {
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -258,7 +266,12 @@ void smrt_qmesh::launch_sweep(hipStream_t s) {
     A.nc = nc; A.G = G; A.nang = nang; A.NB = NB;
     A.geo = geo.p; A.dcell = dcell.p; A.dlev = dlev.p; A.dlev_base = dlev_base.p; A.flags = flags.p; A.upw = upw.p;
     A.om = om.p;
-    A.sig_t = sig_t.p; A.q = q.p; A.psi_prev = psi_prev.p; A.inflow = inflow.p; A.par = par.p; A.psi = psi.p;
+    if (fp32) {
+        A.sig_t = sig_t32.p; A.q = q32.p; A.psi_prev = psi_prev32.p; A.inflow = inflow32.p;
+    } else {
+        A.sig_t = sig_t.p; A.q = q.p; A.psi_prev = psi_prev.p; A.inflow = inflow.p;
+    }
+    A.par = par.p; A.psi = psi.p;
     const dim3 grid((unsigned)(nang * ((G + QGB - 1) / QGB)));
     if (fp32) hipLaunchKernelGGL(k_qsweep_dir<float>, grid, dim3(QSWEEP_THREADS), 0, s, A);
     else hipLaunchKernelGGL(k_qsweep_dir<double>, grid, dim3(QSWEEP_THREADS), 0, s, A);
@@ -459,6 +472,12 @@ extern "C" smrt_status smrt_qmesh_create(int n_vertices, const double *xy, int n
         m->out.alloc(npsi);
         m->par.alloc(2);
         m->psi.alloc(npsi * (m->fp32 ? 4 : 8));
+        if (m->fp32) {
+            m->sig_t32.alloc((int64_t)nc * G);
+            m->q32.alloc(nn * G);
+            m->psi_prev32.alloc(npsi);
+            m->inflow32.alloc(std::max<int64_t>((int64_t)nang * G * m->NB, 1));
+        }
     });
     if (st != SMRT_OK) return st;
     *out = h.release();
@@ -493,6 +512,15 @@ extern "C" smrt_status smrt_qmesh_sweep(smrt_qmesh *m, const double *sig_t, cons
         if (inflow) SMRT_HIP(hipMemcpyAsync(m->inflow.p, inflow, sizeof(double) * m->nang * m->G * m->NB,
                                             hipMemcpyHostToDevice, s));
         else if (m->NB) SMRT_HIP(hipMemsetAsync(m->inflow.p, 0, sizeof(double) * m->nang * m->G * m->NB, s));
+        if (m->fp32) {
+            auto to32 = [&](int64_t n, const double *in, float *out) {
+                if (n > 0) hipLaunchKernelGGL(k_qto_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in, out);
+            };
+            to32((int64_t)m->nc * m->G, m->sig_t.p, m->sig_t32.p);
+            to32(nn * m->G, m->q.p, m->q32.p);
+            if (psi_prev) to32(npsi, m->psi_prev.p, m->psi_prev32.p);
+            to32((int64_t)m->nang * m->G * m->NB, m->inflow.p, m->inflow32.p);
+        }
         const double par[2] = {inv_c_dt, psi_prev ? 1.0 : 0.0};
         SMRT_HIP(hipMemcpyAsync(m->par.p, par, sizeof(par), hipMemcpyHostToDevice, s));
         hipEvent_t e0, e1;
