@@ -352,6 +352,12 @@ smrt_status smrt_get_info(const smrt_ctx *ctx, smrt_info *info);
  * Returns SMRT_E_INVALID_ARG outside these ranges. */
 smrt_status smrt_set_launch(smrt_ctx *ctx, int waves_per_band, int bands_per_group, int pairs_per_lane);
 
+/* Name of the current HIP device and its architecture ("<name> <gcnArch>",
+ * truncated to len - 1 characters and NUL-terminated) and its compute-unit
+ * count: the key under which tuned launch shapes are cached.  Errors:
+ * SMRT_E_INVALID_ARG for a NULL buffer or len < 1, SMRT_E_DEVICE. */
+smrt_status smrt_device_name(char *buf, int len, int *n_compute_units);
+
 /* Sweep occupancy (2D): at most workgroups_per_cu sweep workgroups share a
  * compute unit (the launch pads its LDS request accordingly); 0 = as many as
  * the registers allow (default).  Errors: SMRT_E_INVALID_ARG outside [0, 8]. */
@@ -362,11 +368,11 @@ smrt_status smrt_set_occupancy(smrt_ctx *ctx, int workgroups_per_cu);
  * workgroup, groups per lane) whose chunk covers less than twice the groups
  * and whose workgroup less than twice the bands of the problem, each at
  * occupancy 0, 1 and 2 workgroups per CU, applies the fastest and returns its
- * shape with its sweep time in ms (any output pointer may be NULL).  The
- * state is not advanced.  Errors: SMRT_E_INVALID_ARG before smrt_set_state,
- * for 1D, or for dt <= 0. */
+ * shape, its occupancy (as smrt_set_occupancy takes it) and its sweep time in
+ * ms (any output pointer may be NULL).  The state is not advanced.  Errors:
+ * SMRT_E_INVALID_ARG before smrt_set_state, for 1D, or for dt <= 0. */
 smrt_status smrt_autotune(smrt_ctx *ctx, double dt, int *waves_per_band, int *bands_per_group, int *pairs_per_lane,
-                          double *ms_best);
+                          int *workgroups_per_cu, double *ms_best);
 
 /* ---- Batches: many independent 2D problems swept in one launch ---------
  * A batch borrows n contexts (all 2D, one precision, each with a state) and
@@ -392,10 +398,10 @@ smrt_status smrt_batch_set_occupancy(smrt_batch *batch, int workgroups_per_cu);
 smrt_status smrt_batch_info(const smrt_batch *batch, int64_t *units_per_sweep, int *n_tasks, int *waves_per_band,
                             int *bands_per_group, int *pairs_per_lane);
 /* Batch autotuner: times the batched sweep for every candidate launch shape
- * on the problems' current states with time step dt, applies and returns the
- * fastest (ms of one batched sweep). */
+ * and occupancy on the problems' current states with time step dt, applies
+ * and returns the fastest (shape, occupancy, ms of one batched sweep). */
 smrt_status smrt_batch_autotune(smrt_batch *batch, double dt, int *waves_per_band, int *bands_per_group,
-                                int *pairs_per_lane, double *ms_best);
+                                int *pairs_per_lane, int *workgroups_per_cu, double *ms_best);
 /* Resident high-order pass of every problem (as smrt_sweep_resident, with
  * all sweeps in one batched launch), n_times.  capture_graph != 0 records
  * the pass once as a HIP graph (kernels only) and replays it n_times.

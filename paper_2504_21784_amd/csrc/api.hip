@@ -6,6 +6,7 @@
 #include <memory>
 #include <numeric>
 #include <algorithm>
+#include <cstdio>
 #include <mutex>
 
 #include "lo.h"
@@ -1460,7 +1461,7 @@ static std::vector<Shape> launch_candidates(bool fp32, int G, int nbands) {
 }
 
 extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_band, int *bands_per_group,
-                                     int *pairs_per_lane, double *ms_best) {
+                                     int *pairs_per_lane, int *workgroups_per_cu, double *ms_best) {
     if (!x) { g_last_error = "ctx is NULL"; return SMRT_E_INVALID_ARG; }
     return guard(x, [&] {
         require(x->dim == 2, "the launch shape applies to 2D sweeps");
@@ -1496,8 +1497,22 @@ extern "C" smrt_status smrt_autotune(smrt_ctx *x, double dt, int *waves_per_band
         if (waves_per_band) *waves_per_band = bs.nw;
         if (bands_per_group) *bands_per_group = bs.nbw;
         if (pairs_per_lane) *pairs_per_lane = bs.k;
+        if (workgroups_per_cu) *workgroups_per_cu = bo;
         if (ms_best) *ms_best = best;
     });
+}
+
+extern "C" smrt_status smrt_device_name(char *buf, int len, int *n_compute_units) {
+    if (!buf || len < 1) { g_last_error = "invalid argument"; return SMRT_E_INVALID_ARG; }
+    int dev = 0;
+    hipDeviceProp_t pr{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess) {
+        g_last_error = "no HIP device";
+        return SMRT_E_DEVICE;
+    }
+    std::snprintf(buf, (size_t)len, "%s %s", pr.name, pr.gcnArchName);
+    if (n_compute_units) *n_compute_units = pr.multiProcessorCount;
+    return SMRT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1834,7 +1849,7 @@ extern "C" smrt_status smrt_batch_sweep_resident(smrt_batch *b, double dt, int n
 }
 
 extern "C" smrt_status smrt_batch_autotune(smrt_batch *b, double dt, int *waves_per_band, int *bands_per_group,
-                                           int *pairs_per_lane, double *ms_best) {
+                                           int *pairs_per_lane, int *workgroups_per_cu, double *ms_best) {
     if (!b) { g_last_error = "batch is NULL"; return SMRT_E_INVALID_ARG; }
     return bguard(b, [&] {
         BatchStreams on(b);
@@ -1867,6 +1882,7 @@ extern "C" smrt_status smrt_batch_autotune(smrt_batch *b, double dt, int *waves_
         if (waves_per_band) *waves_per_band = bs.nw;
         if (bands_per_group) *bands_per_group = bs.nbw;
         if (pairs_per_lane) *pairs_per_lane = bs.k;
+        if (workgroups_per_cu) *workgroups_per_cu = bo;
         if (ms_best) *ms_best = best;
     });
 }

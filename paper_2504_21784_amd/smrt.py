@@ -13,6 +13,8 @@ from typing import Optional
 
 import numpy as np
 
+from .tune_cache import TuneCache, problem_key
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsmrt.so")
 
@@ -78,6 +80,21 @@ class Info(C.Structure):
 
 _lib = None
 
+
+def device_name() -> str:
+    """The current HIP device as "<name> <arch> <n> CUs" (the tuning cache key)."""
+    L = load()
+    buf = C.create_string_buffer(256)
+    n = C.c_int(0)
+    st = L.smrt_device_name(buf, 256, C.byref(n))
+    if st != 0:
+        raise SmrtError(st, L.smrt_last_error(None).decode())
+    return f"{buf.value.decode()} {n.value} CUs"
+
+
+def _cache(cache):
+    return TuneCache() if cache is True else cache
+
 # exported names and ctypes signatures (argtypes, restype)
 _SIGS = {
     "smrt_default_options": ([C.POINTER(Options)], None),
@@ -101,7 +118,8 @@ _SIGS = {
     "smrt_get_info": ([C.c_void_p, C.POINTER(Info)], C.c_int),
     "smrt_get_moments": ([C.c_void_p, _dp], C.c_int),
     "smrt_set_launch": ([C.c_void_p, C.c_int, C.c_int, C.c_int], C.c_int),
-    "smrt_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _ip, _dp], C.c_int),
+    "smrt_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _ip, _ip, _dp], C.c_int),
+    "smrt_device_name": ([C.c_char_p, C.c_int, _ip], C.c_int),
     "smrt_set_occupancy": ([C.c_void_p, C.c_int], C.c_int),
     "smrt_batch_set_occupancy": ([C.c_void_p, C.c_int], C.c_int),
     "smrt_adjoint_sweep": ([C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp], C.c_int),
@@ -112,7 +130,7 @@ _SIGS = {
     "smrt_batch_last_error": ([C.c_void_p], C.c_char_p),
     "smrt_batch_set_launch": ([C.c_void_p, C.c_int, C.c_int, C.c_int], C.c_int),
     "smrt_batch_info": ([C.c_void_p, C.POINTER(C.c_int64), _ip, _ip, _ip, _ip], C.c_int),
-    "smrt_batch_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _ip, _dp], C.c_int),
+    "smrt_batch_autotune": ([C.c_void_p, C.c_double, _ip, _ip, _ip, _ip, _dp], C.c_int),
     "smrt_batch_sweep_resident": ([C.c_void_p, C.c_double, C.c_int, C.c_int, _dp, _dp], C.c_int),
     "smrt_batch_step": ([C.c_void_p, _dp, C.POINTER(StepStats)], C.c_int),
     "smrt_batch_run": ([C.c_void_p, C.c_int, _dp, C.POINTER(StepStats), C.c_int], C.c_int),
@@ -356,12 +374,31 @@ class Context:
                                                C.byref(ms), C.byref(ks)))
         return ms.value, ks.value
 
-    def autotune(self, dt=None):
+    def autotune(self, dt=None, cache=None):
         """Pick the fastest sweep launch shape; returns (waves per band, bands per
-        workgroup, groups per lane, ms)."""
-        nw, nb, k, ms = C.c_int(0), C.c_int(0), C.c_int(0), C.c_double(0.0)
+        workgroup, groups per lane, ms).  cache: a tune_cache.TuneCache (or
+        True for the default file): a shape stored for the same device and
+        sweep shape is applied without timing (self.last_tune_cached says
+        which happened), and a new one is stored."""
+        key = None
+        self.last_tune_cached = False
+        if cache:
+            cache = _cache(cache)
+            p = self.p
+            key = problem_key("single", device_name(), self.opts.precision,
+                              [(p.nx, p.ny if p.dim == 2 else 1, p.G, p.n_angles)], self.opts.fixup)
+            e = cache.get(key)
+            if e is not None:
+                self.set_launch(e["waves_per_band"], e["bands_per_group"], e["pairs_per_lane"])
+                self.set_occupancy(e["workgroups_per_cu"])
+                self.last_tune_cached = True
+                return e["waves_per_band"], e["bands_per_group"], e["pairs_per_lane"], e["ms"]
+        nw, nb, k, occ, ms = C.c_int(0), C.c_int(0), C.c_int(0), C.c_int(0), C.c_double(0.0)
         self._check(self.L.smrt_autotune(self.h, float(dt if dt is not None else self.p.dt), C.byref(nw), C.byref(nb),
-                                         C.byref(k), C.byref(ms)))
+                                         C.byref(k), C.byref(occ), C.byref(ms)))
+        if key is not None:
+            cache.put(key, {"waves_per_band": nw.value, "bands_per_group": nb.value, "pairs_per_lane": k.value,
+                            "workgroups_per_cu": occ.value, "ms": ms.value})
         return nw.value, nb.value, k.value, ms.value
 
 
@@ -406,9 +443,27 @@ class Batch:
     def set_occupancy(self, workgroups_per_cu=0):
         self._check(self.L.smrt_batch_set_occupancy(self.h, int(workgroups_per_cu)))
 
-    def autotune(self, dt):
-        nw, nb, k, ms = C.c_int(0), C.c_int(0), C.c_int(0), C.c_double(0.0)
-        self._check(self.L.smrt_batch_autotune(self.h, float(dt), C.byref(nw), C.byref(nb), C.byref(k), C.byref(ms)))
+    def autotune(self, dt, cache=None):
+        """Fastest batched launch shape (as Context.autotune, cache likewise)."""
+        key = None
+        self.last_tune_cached = False
+        if cache:
+            cache = _cache(cache)
+            c0 = self.contexts[0]
+            key = problem_key("batch", device_name(), c0.opts.precision,
+                              [(c.p.nx, c.p.ny, c.p.G, c.p.n_angles) for c in self.contexts], c0.opts.fixup)
+            e = cache.get(key)
+            if e is not None:
+                self.set_launch(e["waves_per_band"], e["bands_per_group"], e["pairs_per_lane"])
+                self.set_occupancy(e["workgroups_per_cu"])
+                self.last_tune_cached = True
+                return e["waves_per_band"], e["bands_per_group"], e["pairs_per_lane"], e["ms"]
+        nw, nb, k, occ, ms = C.c_int(0), C.c_int(0), C.c_int(0), C.c_int(0), C.c_double(0.0)
+        self._check(self.L.smrt_batch_autotune(self.h, float(dt), C.byref(nw), C.byref(nb), C.byref(k), C.byref(occ),
+                                               C.byref(ms)))
+        if key is not None:
+            cache.put(key, {"waves_per_band": nw.value, "bands_per_group": nb.value, "pairs_per_lane": k.value,
+                            "workgroups_per_cu": occ.value, "ms": ms.value})
         return nw.value, nb.value, k.value, ms.value
 
     def sweep_resident(self, dt, n_times=1, capture_graph=False):

@@ -150,6 +150,41 @@ def test_single_autotune(smrt_mod):
     c.close()
 
 
+def test_autotune_cache_reuses_shape(smrt_mod, tmp_path):
+    """A tuned shape is stored on disk under the device and sweep shape and
+    applied without timing on the next call (single context and batch)."""
+    from paper_2504_21784_amd.tune_cache import TuneCache
+    cache = TuneCache(str(tmp_path / "shapes.json"))
+    print("device:", smrt_mod.device_name(), flush=True)
+    p = W.multigroup_2d(n=48, G=8)
+    c = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP32)
+    c.set_state(p.initial_T_nodes())
+    first = c.autotune(cache=cache)
+    assert not c.last_tune_cached
+    c2 = smrt_mod.Context(p, precision=smrt_mod.SMRT_FP32)
+    c2.set_state(p.initial_T_nodes())
+    again = c2.autotune(cache=cache)
+    assert c2.last_tune_cached and again[:3] == first[:3]
+    i = c2.info()
+    assert (i["waves_per_band"], i["bands_per_group"], i["pairs_per_lane"]) == first[:3]
+    c.sweep_resident(n_times=1)
+    c2.sweep_resident(n_times=1)
+    assert np.array_equal(c.get_moments(), c2.get_moments())
+    c.close()
+    c2.close()
+    ps = _problems()
+    b = smrt_mod.Batch(_contexts(smrt_mod, ps, 1))
+    bf = b.autotune(ps[0].dt, cache=cache)
+    assert not b.last_tune_cached
+    b2 = smrt_mod.Batch(_contexts(smrt_mod, ps, 1))
+    bs = b2.autotune(ps[0].dt, cache=cache)
+    assert b2.last_tune_cached and bs[:3] == bf[:3]
+    for bb in (b, b2):
+        for x in bb.contexts:
+            x.close()
+        bb.close()
+
+
 def test_batch_rejects_mixed_precision(smrt_mod):
     ps = _problems()[:2]
     a = smrt_mod.Context(ps[0], precision=0)
