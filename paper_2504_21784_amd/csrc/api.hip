@@ -2057,7 +2057,7 @@ static LoProb lo_prob(smrt_ctx *x, double dt, RunCtl *ctl) {
     q.wn = L.wn.p;
     q.MFinv = L.MFinv.p; q.DqF = L.DqF.p; q.jbase = L.jbase.p; q.diagE = L.diagE.p; q.rhs = L.rhs.p;
     q.Minv = L.Minv.p; q.r = L.r.p; q.z = L.z.p; q.p = L.p.p; q.Ap = L.Ap.p; q.Eold = L.Eold.p; q.Told = L.Told.p;
-    q.tmpF = L.tmpF.p; q.part = L.part.p; q.sc = L.sc.p; q.bpart = L.bpart.p; q.apart = L.apart.p;
+    q.tmpF = L.tmpF.p; q.part = L.part.p; q.sc = L.sc.p; q.bpart = L.bpart.p; q.apart = L.apart.p; q.sc2 = L.sc2.p;
     q.flags = L.flags.p;
     q.sigE = in.sigE; q.sigF = in.sigF; q.sigP = in.sigP; q.qE = in.qE; q.qF = in.qF; q.cvn = in.cvn;
     q.Tstar = x->d_Tstar.p;

@@ -120,6 +120,7 @@ struct RunCtl {
     int m;               // Newton iteration of the current LO solve
     int nt_on;           // 1 while the LO's Newton iteration runs
     int cg_on;           // 1 while the current CG runs
+    int cg_par;          // the current CG scalars are in sc (0) or sc2 (1)
     int outer, inner_total, cg_total, elim_max, hit_max;   // statistics of the step
     double first;        // first outer change of the step
     double first_in;     // first Newton change of the current LO solve
@@ -136,7 +137,7 @@ struct LoProb {
     const int *drp, *dcol, *dtrp, *dtcol, *prp, *pcol;   // D, D^T and P (CSR)
     const double *dval, *dtval, *pval, *wn;
     double *MFinv, *DqF, *jbase, *diagE, *rhs, *Minv, *r, *z, *p, *Ap, *Eold, *Told, *tmpF, *part, *sc, *bpart,
-        *apart;
+        *apart, *sc2;
     int *flags;
     const double *sigE, *sigF, *sigP, *qE, *qF, *cvn, *Tstar;
     double *E, *F, *T;
@@ -173,6 +174,7 @@ struct LoSolver {
     DevBuf<double> dhx, dhy;       // cell sizes (the stencil form of S)
     DevCsr dD, dDT, dP;
     DevBuf<double> wn, MFinv, DqF, jbase, diagE, rhs, Minv, r, z, p, Ap, Eold, Told, tmpF, part, sc, bpart, apart;
+    DevBuf<double> sc2;            // second set of CG scalars (the batched LO alternates between sc and sc2)
     DevBuf<int> flags;
     // captured HIP graph of a block of CG iterations (kernels only), per (stream, x)
     hipGraph_t cg_graph = nullptr;

@@ -838,6 +838,7 @@ void LoSolver::init(int dim_, int nx, int ny, const std::vector<double> &xe, con
     tmpF.alloc((int64_t)nn * dim);
     part.alloc(3 * RED_BLOCKS);
     sc.alloc(12);
+    sc2.alloc(12);
     bpart.alloc(2 * (int64_t)((nn + 255) / 256));
     apart.alloc((int64_t)((nn + 255) / 256));
     flags.alloc(4);
