@@ -206,3 +206,38 @@ def test_full_batch_run_fp64_smallest_against_oracle(smrt_mod, oracle_mod):
     alone.close()
     b.close()
     _close(cs)
+
+
+def test_batch_run_captured_as_first_call_of_a_process():
+    """A fresh process whose first GPU work is a captured batched run (so the
+    sweep's one-time launch attributes are set during capture) gets the same
+    bits as an eager run in another fresh process."""
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys, hashlib, numpy as np\n"
+        f"sys.path.insert(0, {root!r})\n"
+        "from paper_2504_21784_amd import smrt, workloads as W\n"
+        "ps = W.batch_2d(n_problems=3, seed=11, sizes=[16, 24])\n"
+        "cs = []\n"
+        "for p in ps:\n"
+        "    c = smrt.Context(p, precision=smrt.SMRT_FP32)\n"
+        "    c.set_state(p.initial_T_nodes())\n"
+        "    cs.append(c)\n"
+        "b = smrt.Batch(cs)\n"
+        "b.run(2, [p.dt for p in ps], capture_graph=bool(int(sys.argv[1])))\n"
+        "h = hashlib.sha256()\n"
+        "for c in cs:\n"
+        "    s = c.get_state()\n"
+        "    for k in ('T', 'E', 'psi'):\n"
+        "        h.update(np.ascontiguousarray(s[k]).tobytes())\n"
+        "print(h.hexdigest())\n")
+    out = []
+    for cap in ("1", "0"):
+        r = subprocess.run([sys.executable, "-c", code, cap], capture_output=True, text=True, timeout=180)
+        assert r.returncode == 0, r.stderr[-2000:]
+        out.append(r.stdout.strip().splitlines()[-1])
+        print("capture", cap, out[-1][:16], flush=True)
+    assert out[0] == out[1]
