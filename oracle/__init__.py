@@ -137,6 +137,9 @@ def _declare(L):
     L.orc_qmesh_nbnodes.restype = C.c_int
     L.orc_qsweep.argtypes = [C.POINTER(QGeom), _dp, _dp, _dp, C.c_double, _dp, _dp]
     L.orc_qsweep.restype = C.c_int
+    L.orc_qstep_unacc.argtypes = [C.POINTER(QGeom), _dp, C.c_double, C.c_double, mp, _dp, op, C.c_double, _dp, _dp,
+                                  _dp, sp]
+    L.orc_qstep_unacc.restype = C.c_int
 
 
 def _p(a):
@@ -368,6 +371,24 @@ class QuadMesh:
                               _p(inf), _p(out))
         assert r == 0, f"orc_qsweep returned {r}"
         return out
+
+    def step_unaccelerated(self, T, psi, region, sigma0, cv, nu, a, c, dt, inflow=None, model=1, clip_lo=1e-2,
+                           clip_hi=1e5, **opts):
+        """One backward-Euler step of the unaccelerated scheme (Algorithm 1
+        without the low-order solve) with a fixed boundary inflow[d][g][NB]:
+        returns (status, T, E, psi, stats).  region[cell], sigma0 and cv per
+        region, nu the G + 1 group bounds; options as default_opts."""
+        o = Opts(**{k: v for k, v in default_opts(**opts).items() if k in dict(Opts._fields_)})
+        reg = np.ascontiguousarray(region, dtype=np.int32)
+        s0, cvr, nuv = _f64(sigma0), _f64(cv), _f64(nu)
+        mat = Mat(reg.ctypes.data_as(_ip), int(model), _p(s0), float(clip_lo), float(clip_hi), _p(cvr))
+        Tn, ps = _f64(T).copy(), _f64(psi).copy()
+        E = np.zeros_like(Tn)
+        st = Stats()
+        inf = _f64(inflow) if inflow is not None else None
+        r = self.L.orc_qstep_unacc(C.byref(self.geom), _p(nuv), float(a), float(c), C.byref(mat), _p(inf),
+                                   C.byref(o), float(dt), _p(ps), _p(Tn), _p(E), C.byref(st))
+        return r, Tn, E, ps, {f: getattr(st, f) for f, _ in Stats._fields_}
 
     def moments(self, sig, psi):
         """Gray angular moments per node of an intensity psi[d][g][node]: the

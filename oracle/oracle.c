@@ -1668,3 +1668,93 @@ int orc_qsweep(const orc_qgeom *q, const double *sig_t, const double *q_iso, con
     free(nb); free(be); free(indeg); free(order);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* One backward-Euler step of the unaccelerated scheme of Algorithm 1 (no   */
+/* low-order solve: every outer iteration sweeps with the emission source   */
+/* at the current temperature iterate and solves the pointwise energy       */
+/* balance cv T/dt + sigma_P a c T^4 = sum_g sigma_g phi_g + cv Tstar/dt)   */
+/* on an unstructured quadrilateral mesh, with a fixed boundary inflow.     */
+/* The opacity is taken once per step at the start-of-step temperature     */
+/* (cell mean of the nodal values, as on the rectilinear mesh); node n of   */
+/* cell n/4 has that cell's c_v.  psi: in I*, out I; T in/out; E out       */
+/* (sum_d w I / c).  Same outer test and caps as orc_step.                 */
+/* ------------------------------------------------------------------------ */
+int orc_qstep_unacc(const orc_qgeom *q, const double *nu, double a, double c, const orc_mat *m,
+                    const double *inflow, const orc_opts *op, double dt, double *psi, double *T, double *E,
+                    orc_stats *st)
+{
+    int nc = q->nc, G = q->G, nn = 4 * nc, nang = q->nang;
+    size_t npsi = (size_t)nang * G * nn;
+    orc_geom g;   /* only what orc_opacity reads: nc cells of 4 nodes, the groups */
+    memset(&g, 0, sizeof g);
+    g.dim = 2; g.nx = nc; g.ny = 1; g.G = G; g.nu = nu; g.a = a; g.c = c;
+    memset(st, 0, sizeof *st);
+    double *sig = malloc(sizeof(double) * nc * G), *sigt = malloc(sizeof(double) * nc * G);
+    double *qs = malloc(sizeof(double) * nn * G), *prev = malloc(sizeof(double) * npsi);
+    double *out = malloc(sizeof(double) * npsi), *Tstar = malloc(sizeof(double) * nn);
+    double *Tl = malloc(sizeof(double) * nn), *El = malloc(sizeof(double) * nn);
+    double *Tn = malloc(sizeof(double) * nn), *En = malloc(sizeof(double) * nn);
+    double *sphi = malloc(sizeof(double) * nn), *cvn = malloc(sizeof(double) * nn);
+    orc_opacity(&g, m, T, sig);
+    for (size_t k = 0; k < (size_t)nc * G; ++k) sigt[k] = sig[k] + 1.0 / (c * dt);
+    for (int n = 0; n < nn; ++n) cvn[n] = m->cv[m->region[n / 4]];
+    memcpy(prev, psi, sizeof(double) * npsi);
+    memcpy(Tstar, T, sizeof(double) * nn);
+    memcpy(Tl, T, sizeof(double) * nn);
+    /* first energy iterate: the intensity's own E* */
+    memset(El, 0, sizeof(double) * nn);
+    for (int d = 0; d < nang; ++d)
+        for (int k = 0; k < G; ++k)
+            for (int n = 0; n < nn; ++n) El[n] += q->w[d] * prev[((size_t)d * G + k) * nn + n] / c;
+    double first = -1.0;
+    int status = ORC_OK;
+    for (int l = 1; l <= op->max_outer; ++l) {
+#pragma omp parallel for schedule(static)
+        for (int n = 0; n < nn; ++n) {
+            double bg[G], rg[G];
+            orc_spectra(G, nu, Tl[n], bg, rg);
+            double B = a * c * pow(Tl[n], 4);
+            for (int k = 0; k < G; ++k) qs[(size_t)n * G + k] = sig[(size_t)(n / 4) * G + k] * B * bg[k] / (4.0 * M_PI);
+        }
+        int r = orc_qsweep(q, sigt, qs, prev, 1.0 / (c * dt), inflow, out);
+        if (r) { status = r; break; }
+        st->outer++;
+        memset(En, 0, sizeof(double) * nn);
+        memset(sphi, 0, sizeof(double) * nn);
+        for (int d = 0; d < nang; ++d)
+            for (int k = 0; k < G; ++k)
+                for (int n = 0; n < nn; ++n) {
+                    double wI = q->w[d] * out[((size_t)d * G + k) * nn + n];
+                    En[n] += wI / c;
+                    sphi[n] += sig[(size_t)(n / 4) * G + k] * wI;
+                }
+        for (int n = 0; n < nn && status == ORC_OK; ++n) {
+            double bg[G], rg[G];
+            orc_spectra(G, nu, Tl[n], bg, rg);
+            double sb = 0, sbs = 0;
+            for (int k = 0; k < G; ++k) { sb += bg[k]; sbs += bg[k] * sig[(size_t)(n / 4) * G + k]; }
+            double rhs = sphi[n] + cvn[n] * Tstar[n] / dt;
+            Tn[n] = Tl[n];
+            int it = orc_energy_solve(cvn[n] / dt, (sbs / sb) * a * c, rhs, Tl[n], op->elim_rtol, op->max_elim, &Tn[n]);
+            if (floor_temperature(op->T_floor, it, &Tn[n])) { status = ORC_E_NONPHYSICAL; break; }
+            if (it > st->elim_max) st->elim_max = it;
+            if (it >= op->max_elim) st->hit_max = 1;
+        }
+        double diff = 0.0;
+        for (int n = 0; n < nn; ++n) diff += (Tn[n] - Tl[n]) * (Tn[n] - Tl[n]) + (En[n] - El[n]) * (En[n] - El[n]);
+        diff = sqrt(diff);
+        memcpy(Tl, Tn, sizeof(double) * nn);
+        memcpy(El, En, sizeof(double) * nn);
+        if (status) break;
+        if (l == 1) first = diff;
+        if (diff == 0.0 || (l > 1 && diff < op->eps_outer * first)) break;
+        if (l == op->max_outer) st->hit_max = 1;
+    }
+    memcpy(T, Tl, sizeof(double) * nn);
+    memcpy(E, El, sizeof(double) * nn);
+    memcpy(psi, out, sizeof(double) * npsi);
+    free(sig); free(sigt); free(qs); free(prev); free(out); free(Tstar); free(Tl); free(El); free(Tn); free(En);
+    free(sphi); free(cvn);
+    return status;
+}

@@ -220,3 +220,91 @@ def test_moments_of_uniform_intensity(oracle_mod):
         assert np.abs(total(k)).max() <= 1e-13
     assert np.allclose(mom[24], 9.5 * 4 * np.pi * I, rtol=1e-13, atol=0)
     assert np.abs(mom[25]).max() <= 1e-12 and np.abs(mom[26]).max() <= 1e-12
+
+
+# ---- the unaccelerated time step on quadrilateral meshes ------------------
+
+PERM = [0, 1, 3, 2]   # quadrilateral vertex lq -> rectilinear local node lx + 2 ly
+
+
+def _rect_inflow_to_quads(nx, ny, inf, nb):
+    """Rectilinear boundary inflow [d][g][4(nx+ny)] in the quadrilateral
+    boundary numbering ((cell, edge) order, edge e from vertex e to e+1)."""
+    out = np.zeros(inf.shape[:2] + (nb,))
+    k = 0
+    for c in range(nx * ny):
+        i, j = c % nx, c // nx
+        for e in range(4):
+            if not ((e == 0 and j == 0) or (e == 1 and i == nx - 1) or (e == 2 and j == ny - 1) or (e == 3 and i == 0)):
+                continue
+            for t in range(2):
+                lq = (e + t) % 4
+                lx, ly = PERM[lq] & 1, PERM[lq] >> 1
+                b = (4 * ny + 2 * i + lx if e == 0 else 2 * ny + 2 * j + ly if e == 1
+                     else 4 * ny + 2 * nx + 2 * i + lx if e == 2 else 2 * j + ly)
+                out[:, :, 2 * k + t] = inf[:, :, b]
+            k += 1
+    assert 2 * k == nb
+    return out
+
+
+def _to_quads(a, n_cells):
+    """Nodal array [..., 4 n_cells] from rectilinear to quadrilateral vertex order."""
+    sh = a.shape
+    return a.reshape(sh[:-1] + (n_cells, 4))[..., PERM].reshape(sh)
+
+
+def test_unaccelerated_step_on_rectilinear_quads_equals_rectilinear_step(oracle_mod):
+    """Two steps of the unaccelerated scheme on a multigroup problem (power-law
+    region opacities, Planck inflow on the left side) given as quadrilaterals
+    equal the rectilinear oracle's steps of the same scheme: T, E and I to
+    1e-12, the same outer counts."""
+    p = W.multigroup_2d(n=6, G=3, sn=4, region=3, seed=11)
+    p.T0 = 0.2
+    opts = dict(scheme=2, eps_outer=1e-10, elim_rtol=1e-14, max_outer=300, max_elim=60)
+    o = oracle_mod.Oracle(p)
+    st = o.initial_state()
+    xy, cells = W.quad_mesh_jittered(p.nx, p.ny, jitter=0.0, x_edges=p.x_edges, y_edges=p.y_edges)
+    m = oracle_mod.QuadMesh(xy, cells, p.omega, p.w, p.G)
+    nc = p.nx * p.ny
+    inf = _rect_inflow_to_quads(p.nx, p.ny, o.inflow(), m.nb)
+    T, psi = _to_quads(st["T"], nc), _to_quads(st["psi"], nc)
+    for k in range(2):
+        r, st, ost = o.step(st, oracle_mod.default_opts(**opts))
+        assert r == 0
+        r2, T, E, psi, qst = m.step_unaccelerated(T, psi, p.region_of_cell, p.sigma0, p.cv, p.nu_edges, p.a, p.c,
+                                                  p.dt, inf, model=p.model, clip_lo=p.clip_lo, clip_hi=p.clip_hi,
+                                                  **opts)
+        assert r2 == 0 and qst["outer"] == ost["outer"], (k, qst, ost)
+        for got, want in ((T, st["T"]), (E, st["E"]), (psi, st["psi"])):
+            want = _to_quads(want, nc)
+            assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), k
+
+
+@pytest.mark.parametrize("kind", ["jittered", "split"])
+def test_unaccelerated_step_keeps_equilibrium(oracle_mod, kind):
+    """A uniform medium at T_eq with the equilibrium intensity B_g(T_eq)/4 pi
+    inside and entering through every boundary node stays there: T and I
+    unchanged to 1e-12, E = a T_eq^4 (unstructured and skewed meshes)."""
+    xy, cells = (W.quad_mesh_jittered(7, 5, jitter=0.28, seed=2) if kind == "jittered"
+                 else W.quad_mesh_split_triangles(4, seed=3))
+    G, Teq, a, c = 3, 0.5, 1.0, 1.0
+    om, w = W.level_symmetric_2d(4)
+    m = oracle_mod.QuadMesh(xy, cells, om, w, G)
+    nu = np.logspace(-2, 1, G + 1)
+    L = oracle_mod.lib()
+    b, rr = np.zeros(G), np.zeros(G)
+    L.orc_spectra(G, nu.ctypes.data_as(oracle_mod._dp), Teq, b.ctypes.data_as(oracle_mod._dp),
+                  rr.ctypes.data_as(oracle_mod._dp))
+    Ig = a * c * Teq ** 4 * b / (4 * np.pi)
+    nn = 4 * len(cells)
+    psi = np.broadcast_to(Ig[None, :, None], (len(w), G, nn)).copy()
+    inf = np.broadcast_to(Ig[None, :, None], (len(w), G, m.nb)).copy()
+    T = np.full(nn, Teq)
+    r, T1, E1, psi1, st = m.step_unaccelerated(T, psi, np.zeros(len(cells), np.int32), np.array([30.0]),
+                                                np.array([0.7]), nu, a, c, 1e-2, inf, eps_outer=1e-12,
+                                                elim_rtol=1e-15, max_elim=60)
+    assert r == 0
+    assert np.abs(T1 - Teq).max() <= 1e-12 * Teq
+    assert np.abs(psi1 - psi).max() <= 1e-12 * np.abs(psi).max()
+    assert np.abs(E1 - a * Teq ** 4).max() <= 1e-12 * a * Teq ** 4
