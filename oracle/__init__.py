@@ -362,9 +362,11 @@ class QuadMesh:
         self.nb = self.L.orc_qmesh_nbnodes(C.byref(self.geom))
         assert self.nb >= 0, "non-manifold mesh"
 
-    def sweep(self, sig_t, q_iso, psi_prev, inv_c_dt, inflow):
+    def sweep(self, sig_t, q_iso, psi_prev, inv_c_dt, inflow, fill=0.0):
+        """fill: the value the output buffer holds before the sweep (the
+        result must not depend on it)."""
         nn = 4 * len(self.cells)
-        out = np.zeros((len(self.w), self.G, nn))
+        out = np.full((len(self.w), self.G, nn), float(fill))
         pp = _f64(psi_prev) if psi_prev is not None else None
         inf = _f64(inflow) if inflow is not None else None
         r = self.L.orc_qsweep(C.byref(self.geom), _p(_f64(sig_t)), _p(_f64(q_iso)), _p(pp), float(inv_c_dt),

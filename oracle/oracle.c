@@ -1643,6 +1643,9 @@ int orc_qsweep(const orc_qgeom *q, const double *sig_t, const double *q_iso, con
                     for (int j = 0; j < 2; ++j) {
                         int l = (e + j) % 4;
                         if (on > 0.0) { A[4 * l + l] += on; continue; }
+                        /* a face parallel to the direction carries nothing (and its
+                           neighbour is not upwind, so it may not be swept yet) */
+                        if (on == 0.0) continue;
                         double up = 0.0;
                         int n2 = nb[4 * c + e];
                         if (n2 >= 0) {
@@ -1692,7 +1695,7 @@ int orc_qstep_unacc(const orc_qgeom *q, const double *nu, double a, double c, co
     memset(st, 0, sizeof *st);
     double *sig = malloc(sizeof(double) * nc * G), *sigt = malloc(sizeof(double) * nc * G);
     double *qs = malloc(sizeof(double) * nn * G), *prev = malloc(sizeof(double) * npsi);
-    double *out = malloc(sizeof(double) * npsi), *Tstar = malloc(sizeof(double) * nn);
+    double *out = calloc(npsi, sizeof(double)), *Tstar = malloc(sizeof(double) * nn);
     double *Tl = malloc(sizeof(double) * nn), *El = malloc(sizeof(double) * nn);
     double *Tn = malloc(sizeof(double) * nn), *En = malloc(sizeof(double) * nn);
     double *sphi = malloc(sizeof(double) * nn), *cvn = malloc(sizeof(double) * nn);

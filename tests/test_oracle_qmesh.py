@@ -308,3 +308,18 @@ def test_unaccelerated_step_keeps_equilibrium(oracle_mod, kind):
     assert np.abs(T1 - Teq).max() <= 1e-12 * Teq
     assert np.abs(psi1 - psi).max() <= 1e-12 * np.abs(psi).max()
     assert np.abs(E1 - a * Teq ** 4).max() <= 1e-12 * a * Teq ** 4
+
+
+def test_sweep_ignores_faces_parallel_to_the_direction(oracle_mod):
+    """The triangle-split mesh has faces parallel to some S4 directions; they
+    carry no flux and their neighbour need not be swept first, so the sweep
+    must not read it: the result is the same whatever the output buffer held
+    before (a NaN there would spread through a zero-weight term)."""
+    xy, cells = W.quad_mesh_split_triangles(4, seed=3)
+    om, w = W.level_symmetric_2d(4)
+    m = oracle_mod.QuadMesh(xy, cells, om, w, 2)
+    sigt, q, pp, inf = W.quad_sweep_inputs(len(cells), len(w), 2, m.nb, seed=9)
+    ref = m.sweep(sigt, q, pp, 0.5, inf)
+    got = m.sweep(sigt, q, pp, 0.5, inf, fill=np.nan)
+    assert np.isfinite(got).all()
+    assert np.array_equal(got, ref)
