@@ -487,6 +487,42 @@ smrt_status smrt_qmesh_sweep(smrt_qmesh *mesh, const double *sig_t, const double
  * SMRT_E_OUT_OF_MEMORY, SMRT_E_DEVICE. */
 smrt_status smrt_qmesh_moments(smrt_qmesh *mesh, const double *sig, double *mom_out, double *ms_kernel);
 
+/* ---- Time steps on the mesh: the unaccelerated scheme of Algorithm 1 ----
+ * (no low-order solve: each outer iteration sweeps with the emission at the
+ * temperature iterate and the time-edge source I^k / (c dt), then solves the
+ * pointwise energy balance c_v T/dt + sigma_P a c T^4 = sum_g sigma_g phi_g
+ * + c_v T^k / dt; the outer test and caps of smrt_step).  The SM closures are
+ * not built on unstructured meshes: their half-range sums are needed for
+ * every face normal.
+ *
+ * Materials: region[n_cells] in [0, n_regions); model 0: sigma0[r][G]
+ * tabulated, model 1: sigma_g = sigma0[r] / (nubar_g^3 T^3) clipped to
+ * [clip_lo, clip_hi] (nubar_g the geometric mean of the group bounds), T the
+ * cell mean of its 4 nodal values, taken once per step at the start-of-step
+ * temperature; c_v[r] > 0; nu_edges[G+1] increasing; a, c > 0.  Copied.
+ * Errors: SMRT_E_INVALID_ARG. */
+smrt_status smrt_qmesh_set_materials(smrt_qmesh *mesh, const int32_t *region, int n_regions, int model,
+                                     const double *sigma0, double clip_lo, double clip_hi, const double *cv,
+                                     const double *nu_edges, double a, double c);
+/* State: T[4 n_cells] > 0 at the nodes; psi[d][g][node] the intensity, or
+ * NULL for the isotropic equilibrium B_g(T)/4pi.  E = sum_d w_d sum_g I / c
+ * follows from psi.  Requires smrt_qmesh_set_materials. */
+smrt_status smrt_qmesh_set_state(smrt_qmesh *mesh, const double *T, const double *psi);
+/* One backward-Euler step of length dt with the boundary inflow
+ * inflow[d][g][NB] (NULL: vacuum) held fixed; opt: scheme must be
+ * SMRT_UNACCELERATED and fixup 0 (else SMRT_E_INVALID_ARG); eps_outer,
+ * max_outer, fixed_outer, elim_rtol, max_elim, T_floor and strict as for
+ * smrt_step.  stats (may be NULL): outer, elim_max, hit_max, t_total_ms.
+ * Errors: SMRT_E_NONPHYSICAL (no positive root without a floor, non-finite
+ * iterate; the state is left as it was before the step),
+ * SMRT_E_NOT_CONVERGED (strict and a cap reached; the state is advanced to
+ * the last iterate). */
+smrt_status smrt_qmesh_step(smrt_qmesh *mesh, double dt, const double *inflow, const smrt_options *opt,
+                            smrt_step_stats *stats);
+/* The state after the last step (any pointer may be NULL): T, E [4 n_cells],
+ * psi [d][g][node]. */
+smrt_status smrt_qmesh_get_state(smrt_qmesh *mesh, double *T, double *E, double *psi);
+
 #ifdef __cplusplus
 }
 #endif

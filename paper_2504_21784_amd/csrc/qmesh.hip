@@ -27,10 +27,12 @@
 // elimination with partial pivoting.  Angular flux layout [d][g][node],
 // node = 4 cell + local vertex (counter-clockwise), as the ABI's.
 #include <cmath>
+#include <cstring>
 #include <memory>
 #include <numeric>
 
 #include "lo.h"
+#include "tables.h"
 
 namespace smrt {
 
@@ -238,6 +240,69 @@ __global__ void __launch_bounds__(256) k_qmoments(int nang, int G, int nn, const
     }
 }
 
+// ---------------------------------------------------------------------------
+// The unaccelerated time step on the mesh (Algorithm 1 without the
+// low-order solve): small kernels around the sweep and the moments.
+// ---------------------------------------------------------------------------
+// emission q[g][node] (the source kernel's layout) to the sweep's q[node][G]
+template <typename real>
+__global__ void k_qtranspose(int nn, int G, const double *qn, real *q) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nn * G) return;
+    const int64_t n = i / G, g = i - n * G;
+    q[i] = (real)qn[g * nn + n];
+}
+// sigma_t = sigma + 1/(c dt) per (cell, group), in the sweep precision
+template <typename real>
+__global__ void k_qsigt(int64_t n, const double *sig, double icdt, real *sigt) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) sigt[i] = (real)(sig[i] + icdt);
+}
+// equilibrium intensity: every direction takes B_g(T_n)/4pi (qn[g][node])
+template <typename real>
+__global__ void k_qequilibrium(int nang, int G, int nn, const double *qn, real *psi) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nang * G * nn) return;
+    psi[i] = (real)qn[i % ((int64_t)G * nn)];
+}
+// E = phi / c and sigma_E = sum_g sigma_g phi_g / phi (sigma_P where phi = 0)
+// from the 27 nodal moments (phi: the four quadrants' rows 0, 6, 12, 18)
+__global__ void k_qho(int nn, double c, const double *mom, const double *sigP, double *E, double *sigE) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const double phi = ((mom[n] + mom[6 * (int64_t)nn + n]) + mom[12 * (int64_t)nn + n]) + mom[18 * (int64_t)nn + n];
+    E[n] = phi / c;
+    if (sigE) sigE[n] = phi > 0.0 ? mom[24 * (int64_t)nn + n] / phi : sigP[n];
+}
+// |Ta - Tb|^2 + |Ea - Eb|^2: 256 block partials, then one block sums them (fixed order)
+constexpr int QRED = 256;
+__global__ void k_qdiff2(int n, const double *Ta, const double *Tb, const double *Ea, const double *Eb, double *part) {
+    __shared__ double sh[QRED];
+    double s = 0.0;
+    for (int i = blockIdx.x * QRED + threadIdx.x; i < n; i += QRED * QRED) {
+        const double dT = Ta[i] - Tb[i], dE = Ea[i] - Eb[i];
+        s += dT * dT + dE * dE;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = QRED / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_qsum(const double *part, double *out) {
+    __shared__ double sh[QRED];
+    sh[threadIdx.x] = part[threadIdx.x];
+    __syncthreads();
+    for (int k = QRED / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+__global__ void k_qzero4(int *p) { if (threadIdx.x < 4) p[threadIdx.x] = 0; }
+
 }  // namespace smrt
 
 using namespace smrt;
@@ -255,13 +320,23 @@ struct smrt_qmesh {
     DevBuf<double> om, sig_t, q, psi_prev, inflow, out, par, wq, sig_m, mom;
     DevBuf<float> sig_t32, q32, psi_prev32, inflow32;   // FP32 sweeps read their inputs in FP32
     bool swept = false;       // psi holds the intensity of a finished sweep
+    // time step: materials, state (T, E, I at nodes; I in the sweep precision)
+    bool have_mat = false, have_state = false;
+    int nreg = 0, model = 1;
+    double clip_lo = 0.0, clip_hi = 0.0, a = 1.0, c = 1.0;
+    DevBuf<int> region, eflags;
+    DevBuf<double> sigma0, nu, cvn, T, E, Tstar, Tl, El, Tn, En, sig_step, qn, sigP, sigF, sigE, ones, red;
+    DevBuf<unsigned char> psi_state;
+    double *hbuf = nullptr;   // pinned: [0] iterate change, [1..4] elimination flags (as ints)
     ~smrt_qmesh() {
+        if (hbuf) (void)hipHostFree(hbuf);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
-    void launch_sweep(hipStream_t s);
+    // the sweep from I* = prev (nullptr: the uploaded psi_prev) into out (nullptr: psi)
+    void launch_sweep(hipStream_t s, const void *prev = nullptr, void *out = nullptr);
 };
 
-void smrt_qmesh::launch_sweep(hipStream_t s) {
+void smrt_qmesh::launch_sweep(hipStream_t s, const void *prev, void *out_psi) {
     QArgs A{};
     A.nc = nc; A.G = G; A.nang = nang; A.NB = NB;
     A.geo = geo.p; A.dcell = dcell.p; A.dlev = dlev.p; A.dlev_base = dlev_base.p; A.flags = flags.p; A.upw = upw.p;
@@ -272,6 +347,8 @@ void smrt_qmesh::launch_sweep(hipStream_t s) {
         A.sig_t = sig_t.p; A.q = q.p; A.psi_prev = psi_prev.p; A.inflow = inflow.p;
     }
     A.par = par.p; A.psi = psi.p;
+    if (prev) A.psi_prev = prev;
+    if (out_psi) A.psi = out_psi;
     const dim3 grid((unsigned)(nang * ((G + QGB - 1) / QGB)));
     if (fp32) hipLaunchKernelGGL(k_qsweep_dir<float>, grid, dim3(QSWEEP_THREADS), 0, s, A);
     else hipLaunchKernelGGL(k_qsweep_dir<double>, grid, dim3(QSWEEP_THREADS), 0, s, A);
@@ -553,10 +630,8 @@ extern "C" smrt_status smrt_qmesh_moments(smrt_qmesh *m, const double *sig, doub
         for (int64_t k = 0; k < (int64_t)m->nc * m->G; ++k)
             qrequire(std::isfinite(sig[k]) && sig[k] >= 0.0, "sig must be finite and >= 0");
         const int nn = 4 * m->nc;
-        if (!m->mom.p) {
-            m->sig_m.alloc((int64_t)m->nc * m->G);
-            m->mom.alloc(27 * (int64_t)nn);
-        }
+        if (!m->sig_m.p) m->sig_m.alloc((int64_t)m->nc * m->G);
+        if (!m->mom.p) m->mom.alloc(27 * (int64_t)nn);
         hipStream_t s = m->stream;
         SMRT_HIP(hipMemcpyAsync(m->sig_m.p, sig, sizeof(double) * m->nc * m->G, hipMemcpyHostToDevice, s));
         hipEvent_t e0, e1;
@@ -578,4 +653,239 @@ extern "C" smrt_status smrt_qmesh_moments(smrt_qmesh *m, const double *sig, doub
         (void)hipEventDestroy(e1);
         if (ms_kernel) *ms_kernel = ms;
     });
+}
+
+// ---------------------------------------------------------------------------
+// Time step on the mesh: the unaccelerated scheme of Algorithm 1
+// ---------------------------------------------------------------------------
+extern "C" smrt_status smrt_qmesh_set_materials(smrt_qmesh *m, const int32_t *region, int n_regions, int model,
+                                                const double *sigma0, double clip_lo, double clip_hi, const double *cv,
+                                                const double *nu_edges, double a, double c) {
+    if (!m) { g_qmesh_error = "mesh is NULL"; return SMRT_E_INVALID_ARG; }
+    return qguard(m, [&] {
+        qrequire(region && sigma0 && cv && nu_edges, "NULL input");
+        qrequire(n_regions >= 1, "n_regions must be >= 1");
+        qrequire(model == 0 || model == 1, "model must be 0 (tabulated) or 1 (power law)");
+        qrequire(std::isfinite(a) && a > 0.0 && std::isfinite(c) && c > 0.0, "a and c must be finite and > 0");
+        const int nc = m->nc, G = m->G, nn = 4 * nc;
+        for (int k = 0; k < nc; ++k) qrequire(region[k] >= 0 && region[k] < n_regions, "region index out of range");
+        const int ns = model == 0 ? n_regions * G : n_regions;
+        for (int k = 0; k < ns; ++k) qrequire(std::isfinite(sigma0[k]) && sigma0[k] >= 0.0, "sigma0 must be >= 0");
+        if (model == 1) qrequire(clip_lo > 0.0 && clip_hi >= clip_lo, "clip bounds must satisfy 0 < lo <= hi");
+        for (int r = 0; r < n_regions; ++r) qrequire(std::isfinite(cv[r]) && cv[r] > 0.0, "c_v must be > 0");
+        qrequire(nu_edges[0] >= 0.0, "group bounds must be >= 0");
+        for (int g = 0; g < G; ++g) qrequire(nu_edges[g + 1] > nu_edges[g], "group bounds must increase");
+        hipStream_t s = m->stream;
+        SMRT_HIP(hipStreamSynchronize(s));
+        m->nreg = n_regions; m->model = model; m->clip_lo = clip_lo; m->clip_hi = clip_hi; m->a = a; m->c = c;
+        m->region.alloc(nc);
+        m->sigma0.alloc(ns);
+        m->nu.alloc(G + 1);
+        std::vector<double> cvn(nn);
+        for (int n = 0; n < nn; ++n) cvn[n] = cv[region[n / 4]];
+        m->cvn.alloc(nn);
+        SMRT_HIP(hipMemcpy(m->region.p, region, sizeof(int) * nc, hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->sigma0.p, sigma0, sizeof(double) * ns, hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->nu.p, nu_edges, sizeof(double) * (G + 1), hipMemcpyHostToDevice));
+        SMRT_HIP(hipMemcpy(m->cvn.p, cvn.data(), sizeof(double) * nn, hipMemcpyHostToDevice));
+        if (!m->T.p) {
+            for (auto *v : {&m->T, &m->E, &m->Tstar, &m->Tl, &m->El, &m->Tn, &m->En, &m->sigP, &m->sigF, &m->sigE})
+                v->alloc(nn);
+            m->sig_step.alloc((int64_t)nc * G);
+            m->qn.alloc((int64_t)nn * G);
+            m->red.alloc(QRED + 1);
+            m->eflags.alloc(4);
+            m->psi_state.alloc((int64_t)m->nang * G * nn * (m->fp32 ? 4 : 8));
+            if (!m->mom.p) m->mom.alloc(27 * (int64_t)nn);
+            std::vector<double> ones((size_t)nc * G, 1.0);
+            m->ones.alloc((int64_t)nc * G);
+            SMRT_HIP(hipMemcpy(m->ones.p, ones.data(), sizeof(double) * ones.size(), hipMemcpyHostToDevice));
+            SMRT_HIP(hipHostMalloc((void **)&m->hbuf, 8 * sizeof(double), hipHostMallocDefault));
+        }
+        m->have_mat = true;
+        m->have_state = false;
+    });
+}
+
+extern "C" smrt_status smrt_qmesh_set_state(smrt_qmesh *m, const double *T, const double *psi) {
+    if (!m) { g_qmesh_error = "mesh is NULL"; return SMRT_E_INVALID_ARG; }
+    return qguard(m, [&] {
+        qrequire(m->have_mat, "smrt_qmesh_set_materials must come first");
+        qrequire(T != nullptr, "T is NULL");
+        const int nc = m->nc, G = m->G, nang = m->nang, nn = 4 * nc;
+        const int64_t npsi = (int64_t)nang * G * nn;
+        for (int n = 0; n < nn; ++n) qrequire(std::isfinite(T[n]) && T[n] > 0.0, "T must be finite and > 0");
+        hipStream_t s = m->stream;
+        SMRT_HIP(hipMemcpyAsync(m->T.p, T, sizeof(double) * nn, hipMemcpyHostToDevice, s));
+        if (psi) {
+            SMRT_HIP(hipMemcpyAsync(m->psi_prev.p, psi, sizeof(double) * npsi, hipMemcpyHostToDevice, s));
+            if (m->fp32) hipLaunchKernelGGL(k_qto_f32, dim3((unsigned)((npsi + 255) / 256)), dim3(256), 0, s, npsi,
+                                            (const double *)m->psi_prev.p, (float *)m->psi_state.p);
+            else SMRT_HIP(hipMemcpyAsync(m->psi_state.p, m->psi_prev.p, sizeof(double) * npsi, hipMemcpyDeviceToDevice, s));
+        } else {
+            // isotropic equilibrium B_g(T_n)/4pi: the emission of a unit opacity
+            run_source<double>(s, nn, 4, G, m->T.p, m->nu.p, m->a, m->c, m->ones.p, nullptr, m->qn.p, m->sigP.p,
+                               m->sigF.p);
+            const dim3 grid((unsigned)((npsi + 255) / 256));
+            if (m->fp32) hipLaunchKernelGGL(k_qequilibrium<float>, grid, dim3(256), 0, s, nang, G, nn,
+                                            (const double *)m->qn.p, (float *)m->psi_state.p);
+            else hipLaunchKernelGGL(k_qequilibrium<double>, grid, dim3(256), 0, s, nang, G, nn, (const double *)m->qn.p,
+                                    (double *)m->psi_state.p);
+        }
+        // E = sum_d w_d sum_g I / c of the state's intensity
+        const dim3 gm((unsigned)((nn + 63) / 64));
+        if (m->fp32) hipLaunchKernelGGL(k_qmoments<float>, gm, dim3(256), 0, s, nang, G, nn, m->om.p, m->wq.p,
+                                        m->ones.p, (const float *)m->psi_state.p, m->mom.p);
+        else hipLaunchKernelGGL(k_qmoments<double>, gm, dim3(256), 0, s, nang, G, nn, m->om.p, m->wq.p, m->ones.p,
+                                (const double *)m->psi_state.p, m->mom.p);
+        hipLaunchKernelGGL(k_qho, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, nn, m->c,
+                           (const double *)m->mom.p, (const double *)nullptr, m->E.p, (double *)nullptr);
+        SMRT_HIP(hipGetLastError());
+        SMRT_HIP(hipStreamSynchronize(s));
+        m->have_state = true;
+    });
+}
+
+extern "C" smrt_status smrt_qmesh_get_state(smrt_qmesh *m, double *T, double *E, double *psi) {
+    if (!m) { g_qmesh_error = "mesh is NULL"; return SMRT_E_INVALID_ARG; }
+    return qguard(m, [&] {
+        qrequire(m->have_state, "no state (smrt_qmesh_set_state)");
+        const int nn = 4 * m->nc;
+        const int64_t npsi = (int64_t)m->nang * m->G * nn;
+        hipStream_t s = m->stream;
+        if (T) SMRT_HIP(hipMemcpyAsync(T, m->T.p, sizeof(double) * nn, hipMemcpyDeviceToHost, s));
+        if (E) SMRT_HIP(hipMemcpyAsync(E, m->E.p, sizeof(double) * nn, hipMemcpyDeviceToHost, s));
+        if (psi) {
+            const dim3 grid((unsigned)((npsi + 255) / 256));
+            if (m->fp32) hipLaunchKernelGGL(k_qcopy_out<float>, grid, dim3(256), 0, s, npsi,
+                                            (const float *)m->psi_state.p, m->out.p);
+            else hipLaunchKernelGGL(k_qcopy_out<double>, grid, dim3(256), 0, s, npsi, (const double *)m->psi_state.p,
+                                    m->out.p);
+            SMRT_HIP(hipMemcpyAsync(psi, m->out.p, sizeof(double) * npsi, hipMemcpyDeviceToHost, s));
+        }
+        SMRT_HIP(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" smrt_status smrt_qmesh_step(smrt_qmesh *m, double dt, const double *inflow, const smrt_options *opt,
+                                       smrt_step_stats *stats) {
+    if (!m) { g_qmesh_error = "mesh is NULL"; return SMRT_E_INVALID_ARG; }
+    smrt_status result = SMRT_OK;
+    const smrt_status st0 = qguard(m, [&] {
+        qrequire(m->have_state, "no state (smrt_qmesh_set_state)");
+        qrequire(opt != nullptr, "options are NULL");
+        qrequire(std::isfinite(dt) && dt > 0.0, "dt must be finite and > 0");
+        qrequire(opt->scheme == SMRT_UNACCELERATED,
+                 "unstructured meshes step with the unaccelerated scheme only (the SM closures need half-range "
+                 "sums for every face normal)");
+        qrequire(!opt->fixup, "the unstructured sweep has no negative-flux fixup");
+        qrequire(opt->max_outer >= 1 && opt->max_elim >= 1, "iteration caps must be >= 1");
+        const int nc = m->nc, G = m->G, nang = m->nang, nn = 4 * nc;
+        const int64_t npsi = (int64_t)nang * G * nn, nin = (int64_t)nang * G * m->NB;
+        hipStream_t s = m->stream;
+        hipEvent_t e0, e1;
+        SMRT_HIP(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); throw Error(SMRT_E_DEVICE, "hipEventCreate failed"); }
+        struct Ev { hipEvent_t a, b; ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } ev{e0, e1};
+        SMRT_HIP(hipEventRecord(e0, s));
+        const double icdt = 1.0 / (m->c * dt);
+        // fixed inflow of the step (vacuum when NULL), in the sweep precision
+        if (inflow) SMRT_HIP(hipMemcpyAsync(m->inflow.p, inflow, sizeof(double) * nin, hipMemcpyHostToDevice, s));
+        else if (nin) SMRT_HIP(hipMemsetAsync(m->inflow.p, 0, sizeof(double) * nin, s));
+        if (m->fp32 && nin)
+            hipLaunchKernelGGL(k_qto_f32, dim3((unsigned)((nin + 255) / 256)), dim3(256), 0, s, nin,
+                               (const double *)m->inflow.p, m->inflow32.p);
+        const double par[2] = {icdt, 1.0};
+        SMRT_HIP(hipMemcpyAsync(m->par.p, par, sizeof(par), hipMemcpyHostToDevice, s));
+        // opacity at the start-of-step temperature, sigma_t in the sweep precision
+        run_opacity<double>(s, nc, 4, G, m->T.p, m->region.p, m->model, m->sigma0.p, m->clip_lo, m->clip_hi, m->nu.p,
+                            0.0, m->sig_step.p, (double *)nullptr);
+        const int64_t ncg = (int64_t)nc * G;
+        const dim3 gcg((unsigned)((ncg + 255) / 256));
+        if (m->fp32) hipLaunchKernelGGL(k_qsigt<float>, gcg, dim3(256), 0, s, ncg, (const double *)m->sig_step.p, icdt,
+                                        m->sig_t32.p);
+        else hipLaunchKernelGGL(k_qsigt<double>, gcg, dim3(256), 0, s, ncg, (const double *)m->sig_step.p, icdt,
+                                m->sig_t.p);
+        SMRT_HIP(hipMemcpyAsync(m->Tstar.p, m->T.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+        SMRT_HIP(hipMemcpyAsync(m->Tl.p, m->T.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+        SMRT_HIP(hipMemcpyAsync(m->El.p, m->E.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+        smrt_step_stats st{};
+        const dim3 gn((unsigned)((nn + 255) / 256)), gm((unsigned)((nn + 63) / 64));
+        const dim3 gq((unsigned)(((int64_t)nn * G + 255) / 256));
+        double first = -1.0;
+        for (int l = 1; l <= opt->max_outer; ++l) {
+            run_source<double>(s, nn, 4, G, m->Tl.p, m->nu.p, m->a, m->c, m->sig_step.p, nullptr, m->qn.p, m->sigP.p,
+                               m->sigF.p);
+            if (m->fp32) {
+                hipLaunchKernelGGL(k_qtranspose<float>, gq, dim3(256), 0, s, nn, G, (const double *)m->qn.p, m->q32.p);
+                m->launch_sweep(s, m->psi_state.p, m->psi.p);
+                hipLaunchKernelGGL(k_qmoments<float>, gm, dim3(256), 0, s, nang, G, nn, m->om.p, m->wq.p,
+                                   (const double *)m->sig_step.p, (const float *)m->psi.p, m->mom.p);
+            } else {
+                hipLaunchKernelGGL(k_qtranspose<double>, gq, dim3(256), 0, s, nn, G, (const double *)m->qn.p, m->q.p);
+                m->launch_sweep(s, m->psi_state.p, m->psi.p);
+                hipLaunchKernelGGL(k_qmoments<double>, gm, dim3(256), 0, s, nang, G, nn, m->om.p, m->wq.p,
+                                   (const double *)m->sig_step.p, (const double *)m->psi.p, m->mom.p);
+            }
+            hipLaunchKernelGGL(k_qho, gn, dim3(256), 0, s, nn, m->c, (const double *)m->mom.p,
+                               (const double *)m->sigP.p, m->En.p, m->sigE.p);
+            SMRT_HIP(hipMemcpyAsync(m->Tn.p, m->Tl.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_qzero4, dim3(1), dim3(64), 0, s, m->eflags.p);
+            run_eliminate(s, nn, m->a, m->c, dt, opt->elim_rtol, opt->max_elim, opt->T_floor, m->cvn.p, m->sigE.p,
+                          m->sigP.p, m->En.p, m->Tstar.p, m->Tn.p, m->eflags.p);
+            hipLaunchKernelGGL(k_qdiff2, dim3(QRED), dim3(QRED), 0, s, nn, (const double *)m->Tn.p,
+                               (const double *)m->Tl.p, (const double *)m->En.p, (const double *)m->El.p, m->red.p);
+            hipLaunchKernelGGL(k_qsum, dim3(1), dim3(QRED), 0, s, (const double *)m->red.p, m->red.p + QRED);
+            SMRT_HIP(hipGetLastError());
+            SMRT_HIP(hipMemcpyAsync(m->hbuf, m->red.p + QRED, sizeof(double), hipMemcpyDeviceToHost, s));
+            SMRT_HIP(hipMemcpyAsync(m->hbuf + 1, m->eflags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+            SMRT_HIP(hipMemcpyAsync(m->Tl.p, m->Tn.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+            SMRT_HIP(hipMemcpyAsync(m->El.p, m->En.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+            SMRT_HIP(hipStreamSynchronize(s));
+            st.outer++;
+            int fl[4];
+            std::memcpy(fl, m->hbuf + 1, sizeof(fl));
+            const double diff = std::sqrt(m->hbuf[0]);
+            if (fl[1] > st.elim_max) st.elim_max = fl[1];
+            if (fl[2]) st.hit_max = 1;
+            if (fl[0]) {
+                m->err = "no positive temperature root in the energy balance";
+                result = SMRT_E_NONPHYSICAL;
+                break;
+            }
+            if (!std::isfinite(diff)) {
+                m->err = "non-finite outer iterate";
+                result = SMRT_E_NONPHYSICAL;
+                break;
+            }
+            if (opt->fixed_outer > 0) {
+                if (l >= opt->fixed_outer) break;
+                continue;
+            }
+            if (l == 1) first = diff;
+            if (diff == 0.0 || (l > 1 && diff < opt->eps_outer * first)) break;
+            if (l == opt->max_outer) st.hit_max = 1;
+        }
+        // the new state: the last iterate and the last sweep's intensity (a
+        // non-physical iterate leaves the state as it was before the step)
+        if (result == SMRT_OK) {
+            SMRT_HIP(hipMemcpyAsync(m->T.p, m->Tl.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+            SMRT_HIP(hipMemcpyAsync(m->E.p, m->El.p, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+            SMRT_HIP(hipMemcpyAsync(m->psi_state.p, m->psi.p, npsi * (m->fp32 ? 4 : 8), hipMemcpyDeviceToDevice, s));
+        }
+        SMRT_HIP(hipEventRecord(e1, s));
+        SMRT_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        st.t_total_ms = ms;
+        m->swept = true;
+        if (stats) *stats = st;
+        if (result == SMRT_OK && opt->strict && st.hit_max) {
+            result = SMRT_E_NOT_CONVERGED;
+            m->err = "iteration cap reached";
+        }
+    });
+    if (st0 != SMRT_OK) return st0;
+    if (result != SMRT_OK) g_qmesh_error = m->err;
+    return result;
 }

@@ -141,6 +141,11 @@ _SIGS = {
     "smrt_qmesh_info": ([C.c_void_p, _ip, _ip], C.c_int),
     "smrt_qmesh_sweep": ([C.c_void_p, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp], C.c_int),
     "smrt_qmesh_moments": ([C.c_void_p, _dp, _dp, _dp], C.c_int),
+    "smrt_qmesh_set_materials": ([C.c_void_p, C.POINTER(C.c_int32), C.c_int, C.c_int, _dp, C.c_double, C.c_double,
+                                  _dp, _dp, C.c_double, C.c_double], C.c_int),
+    "smrt_qmesh_set_state": ([C.c_void_p, _dp, _dp], C.c_int),
+    "smrt_qmesh_step": ([C.c_void_p, C.c_double, _dp, C.POINTER(Options), C.POINTER(StepStats)], C.c_int),
+    "smrt_qmesh_get_state": ([C.c_void_p, _dp, _dp, _dp], C.c_int),
 }
 
 
@@ -541,6 +546,43 @@ class QuadMeshSweep:
         if st != 0:
             raise SmrtError(st, self.L.smrt_qmesh_last_error(self.h).decode())
         return out, ms.value
+
+    def _qcheck(self, st):
+        if st != 0:
+            raise SmrtError(st, self.L.smrt_qmesh_last_error(self.h).decode())
+
+    def set_materials(self, region, sigma0, cv, nu_edges, a=1.0, c=1.0, model=1, clip_lo=1e-2, clip_hi=1e5):
+        """Materials of the time step: region[cell], sigma0 (per region, or
+        [region][G] for model 0), c_v per region, the G + 1 group bounds."""
+        self._reg = np.ascontiguousarray(region, dtype=np.int32)
+        self._s0, self._cv, self._nu = _f64(sigma0).ravel(), _f64(cv), _f64(nu_edges)
+        self._qcheck(self.L.smrt_qmesh_set_materials(self.h, self._reg.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                     len(self._cv), int(model), _p(self._s0), float(clip_lo),
+                                                     float(clip_hi), _p(self._cv), _p(self._nu), float(a), float(c)))
+
+    def set_state(self, T, psi=None):
+        """Nodal temperature T[4 n_cells] and intensity psi[d][g][node]
+        (None: the isotropic equilibrium at T)."""
+        self._qcheck(self.L.smrt_qmesh_set_state(self.h, _p(_f64(T)), _p(_f64(psi) if psi is not None else None)))
+
+    def step(self, dt, inflow=None, **opts):
+        """One unaccelerated backward-Euler step with the fixed boundary
+        inflow[d][g][NB] (None: vacuum); options as for Context (scheme is
+        the unaccelerated one).  Returns the step's stats."""
+        kw = dict(scheme=SMRT_UNACCELERATED)
+        kw.update(opts)
+        o = default_options(**kw)
+        st = StepStats()
+        inf = _f64(inflow) if inflow is not None else None
+        self._qcheck(self.L.smrt_qmesh_step(self.h, float(dt), _p(inf), C.byref(o), C.byref(st)))
+        return st.as_dict()
+
+    def get_state(self):
+        nn = 4 * len(self._cells)
+        T, E = np.zeros(nn), np.zeros(nn)
+        psi = np.zeros((len(self._w), self.G, nn))
+        self._qcheck(self.L.smrt_qmesh_get_state(self.h, _p(T), _p(E), _p(psi)))
+        return {"T": T, "E": E, "psi": psi}
 
     def close(self):
         if getattr(self, "h", None):

@@ -165,3 +165,98 @@ def test_qmesh_throughput_at_benchmark_scale(smrt_mod, kind):
           f"moments {ms_mom:.3f} ms", flush=True)
     m.close()
     assert ms > 0
+
+
+# ---- time steps on the mesh (the unaccelerated scheme) ----------------------
+
+STEP_OPTS = dict(eps_outer=1e-10, elim_rtol=1e-14, max_outer=300, max_elim=60)
+
+
+def _planck(oracle_mod, nu, T):
+    G = len(nu) - 1
+    b, r = np.zeros(G), np.zeros(G)
+    oracle_mod.lib().orc_spectra(G, np.ascontiguousarray(nu).ctypes.data_as(oracle_mod._dp), float(T),
+                                 b.ctypes.data_as(oracle_mod._dp), r.ctypes.data_as(oracle_mod._dp))
+    return b
+
+
+def _step_problem(kind, oracle_mod, seed=5):
+    """A 3-group, S4 problem on the mesh: two regions with tabulated
+    opacities (0.5, 2, 8 and 2, 8, 30 per group) and c_v 0.5 and 1, T0 = 0.2
+    with its equilibrium intensity, an isotropic Planck inflow at T = 1
+    through every boundary node (with dt = 0.01 the unaccelerated iteration
+    converges in a few tens of sweeps)."""
+    xy, cells = (W.quad_mesh_jittered(9, 7, jitter=0.28, seed=seed) if kind == "jittered"
+                 else W.quad_mesh_split_triangles(5, seed=seed))
+    om, w = W.level_symmetric_2d(4)
+    G, nu = 3, np.logspace(-2, 1, 4)
+    nc = len(cells)
+    region = (np.arange(nc) % 2).astype(np.int32)
+    s0, cv = np.array([[0.5, 2.0, 8.0], [2.0, 8.0, 30.0]]), np.array([0.5, 1.0])
+    nn = 4 * nc
+    T0 = np.full(nn, 0.2)
+    psi0 = np.broadcast_to((0.2 ** 4 * _planck(oracle_mod, nu, 0.2) / (4 * np.pi))[None, :, None],
+                           (len(w), G, nn)).copy()
+    return xy, cells, om, w, G, nu, region, s0, cv, T0, psi0
+
+
+@pytest.mark.parametrize("kind", ["jittered", "split"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_qmesh_step_matches_oracle(smrt_mod, oracle_mod, kind, prec):
+    """Two unaccelerated steps (dt = 0.01) on a skewed and on an unstructured
+    mesh against the oracle's: FP64 T, E and I to 1e-10 (max-normalised;
+    T and E pointwise too) with outer counts within one; FP32 sweep T to 1e-6
+    and I to 1e-5."""
+    from parity import rel_pointwise
+    xy, cells, om, w, G, nu, region, s0, cv, T0, psi0 = _step_problem(kind, oracle_mod)
+    ref = oracle_mod.QuadMesh(xy, cells, om, w, G)
+    inf = np.broadcast_to((_planck(oracle_mod, nu, 1.0) / (4 * np.pi))[None, :, None], (len(w), G, ref.nb)).copy()
+    m = smrt_mod.QuadMeshSweep(xy, cells, om, w, G, precision=prec)
+    m.set_materials(region, s0, cv, nu, model=0)
+    m.set_state(T0)
+    T, psi = T0, psi0
+    for k in range(2):
+        r, T, E, psi, ost = ref.step_unaccelerated(T, psi, region, s0, cv, nu, 1.0, 1.0, 0.01, inf, model=0,
+                                                   **STEP_OPTS)
+        assert r == 0
+        gst = m.step(0.01, inf, **STEP_OPTS)
+        got = m.get_state()
+        print(f"{kind} prec {prec} step {k}: outer {gst['outer']} (oracle {ost['outer']}), "
+              f"T {_rel(got['T'], T):.2e}, psi {_rel(got['psi'], psi):.2e}", flush=True)
+        if prec == 0:
+            assert abs(gst["outer"] - ost["outer"]) <= 1
+            for key, want in (("T", T), ("E", E), ("psi", psi)):
+                assert _rel(got[key], want) < 1e-10, (k, key)
+            assert rel_pointwise(got["T"], T) < 1e-10 and rel_pointwise(got["E"], E) < 1e-10
+        else:
+            assert _rel(got["T"], T) < 1e-6 and _rel(got["psi"], psi) < 1e-5
+    m.close()
+
+
+def test_qmesh_step_error_paths(smrt_mod, oracle_mod):
+    xy, cells, om, w, G, nu, region, s0, cv, T0, psi0 = _step_problem("split", oracle_mod)
+    m = smrt_mod.QuadMeshSweep(xy, cells, om, w, G)
+    with pytest.raises(smrt_mod.SmrtError):
+        m.set_state(T0)                        # before the materials
+    m.set_materials(region, s0, cv, nu, model=0)
+    with pytest.raises(smrt_mod.SmrtError):
+        m.step(0.02)                           # before the state
+    m.set_state(T0, psi0)
+    with pytest.raises(smrt_mod.SmrtError) as e:
+        m.step(0.02, scheme=0)                 # the SM closures are not built here
+    assert e.value.status == smrt_mod.SMRT_E_INVALID_ARG
+    with pytest.raises(smrt_mod.SmrtError) as e:
+        m.step(0.02, fixup=1)
+    assert e.value.status == smrt_mod.SMRT_E_INVALID_ARG
+    with pytest.raises(smrt_mod.SmrtError) as e:
+        m.step(-1.0)
+    assert e.value.status == smrt_mod.SMRT_E_INVALID_ARG
+    before = m.get_state()
+    with pytest.raises(smrt_mod.SmrtError) as e:
+        m.step(0.02, strict=1, max_outer=1)    # cap reached under strict
+    assert e.value.status == smrt_mod.SMRT_E_NOT_CONVERGED
+    after = m.get_state()
+    assert not np.array_equal(after["T"], before["T"])   # the capped iterate is kept
+    st = m.step(0.02)                          # vacuum sides
+    assert st["outer"] >= 1
+    m.close()
