@@ -353,7 +353,35 @@ def qmesh_sweep():
         out[name] = {"cells": nc, "levels": m.n_levels, "sweep_ms": ms, "units_per_s": units / (ms * 1e-3),
                      "moments_ms": ms_mom}
         m.close()
+    out["unaccelerated_step"] = qmesh_step()
     return out
+
+
+def qmesh_step():
+    """The unaccelerated time step on the 64,896-cell unstructured mesh (S8,
+    16 groups, FP32): 4 regions (cell index mod 4) with tabulated opacities
+    log-uniform in [0.1, 100] per (region, group) (seed 3), c_v = 1, group
+    bounds logspace(-2, 1.5), T0 = 0.5 with its equilibrium intensity,
+    vacuum sides, dt = 1e-3.  Each step runs a fixed 5 outer iterations
+    (emission, sweep, gray moments, energy balance, outer test), so the time
+    per outer iteration is the path's cost; the second step is timed."""
+    import numpy as np
+    from paper_2504_21784_amd import smrt, workloads as W
+
+    xy, cells = W.quad_mesh_split_triangles(104, seed=2)
+    om, w = W.level_symmetric_2d(8)
+    G, nc, n_outer = 16, len(cells), 5
+    rng = np.random.default_rng(3)
+    s0 = 10.0 ** rng.uniform(-1, 2, (4, G))
+    m = smrt.QuadMeshSweep(xy, cells, om, w, G, precision=smrt.SMRT_FP32)
+    m.set_materials((np.arange(nc) % 4).astype(np.int32), s0, np.ones(4), np.logspace(-2, 1.5, G + 1), model=0)
+    m.set_state(np.full(4 * nc, 0.5))
+    m.step(1e-3, fixed_outer=n_outer)
+    st = m.step(1e-3, fixed_outer=n_outer)
+    m.close()
+    ms = st["t_total_ms"]
+    return {"cells": nc, "outer": st["outer"], "ms_per_step": ms, "ms_per_outer": ms / max(st["outer"], 1),
+            "sweep_units_per_s": st["outer"] * nc * len(w) * G / (ms * 1e-3)}
 
 
 def adjoint():
