@@ -112,24 +112,6 @@ static void d2h(void *dst, const void *src, size_t bytes, hipStream_t s) {
     if (bytes) SMRT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
 }
 
-// Bernoulli coefficients B_2k / ((2k)! (2k+3)) = (-1)^(k+1) 2 zeta(2k) / ((2 pi)^(2k) (2k+3))
-static void upload_series_coefficients() {
-    double coef[NBERN];
-    for (int k = 1; k <= NBERN; ++k) {
-        double z;
-        if (k == 1) z = M_PI * M_PI / 6.0;
-        else {
-            z = 0.0;
-            const int N = 20000;
-            for (int n = N; n >= 1; --n) z += std::pow((double)n, -2.0 * k);
-            z += std::pow((double)N, 1.0 - 2.0 * k) / (2.0 * k - 1.0) - 0.5 * std::pow((double)N, -2.0 * k);
-        }
-        const double sign = (k % 2 == 1) ? 1.0 : -1.0;
-        coef[k - 1] = sign * 2.0 * z / (std::pow(2.0 * M_PI, 2.0 * k) * (2.0 * k + 3.0));
-    }
-    upload_bernoulli(coef);
-}
-
 __global__ void k_zero_int(int *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;

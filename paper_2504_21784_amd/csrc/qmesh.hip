@@ -664,6 +664,7 @@ extern "C" smrt_status smrt_qmesh_set_materials(smrt_qmesh *m, const int32_t *re
     if (!m) { g_qmesh_error = "mesh is NULL"; return SMRT_E_INVALID_ARG; }
     return qguard(m, [&] {
         qrequire(region && sigma0 && cv && nu_edges, "NULL input");
+        upload_series_coefficients();   // the emission's Planck series, as at context creation
         qrequire(n_regions >= 1, "n_regions must be >= 1");
         qrequire(model == 0 || model == 1, "model must be 0 (tabulated) or 1 (power law)");
         qrequire(std::isfinite(a) && a > 0.0 && std::isfinite(c) && c > 0.0, "a and c must be finite and > 0");

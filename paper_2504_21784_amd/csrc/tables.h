@@ -10,7 +10,9 @@ namespace smrt {
 constexpr int NBERN = 24;   // Bernoulli terms of the small-argument Planck series
 constexpr int MAXG = 64;    // largest group count
 
-void upload_bernoulli(const double *coef);
+// computes the small-argument Planck series coefficients and uploads them to
+// the current device (every entry point that creates device state calls it)
+void upload_series_coefficients();
 template <typename real>
 void run_opacity(hipStream_t s, int ncell, int npc, int G, const double *T, const int *region, int model,
                  const double *sigma0, double lo, double hi, const double *nu, double icdt, double *sig, real *sig2);

@@ -17,6 +17,7 @@
 // cumulative R(x) = P(x) - 15/(4 pi^4) x^4/(e^x - 1) (integration by parts
 // of x^4 e^x/(e^x-1)^2).  b_g = P(x_{g+1}) - P(x_g), r_g likewise, with the
 // first lower bound at 0 and the last upper bound at infinity.
+#include <cmath>
 #include <type_traits>
 
 #include "smrt_internal.h"
@@ -39,17 +40,20 @@ __constant__ InvTable c_inv = InvTable();
 // evaluation of the Planck integral:
 //   P(x) = 15/pi^4 int_0^x t^3/(e^t-1) dt,
 //   R(x) = 15/(4 pi^4) int_0^x t^4 e^t/(e^t-1)^2 dt = P(x) - 15/(4 pi^4) x^4 e^{-x}/(1-e^{-x})
-// (integration by parts).  P by the Bernoulli series for x < 2 and by the
-// exponential series sum_k e^{-kx} (x^3/k + 3x^2/k^2 + 6x/k^3 + 6/k^4) above.
+// (integration by parts).  P by the Bernoulli series for x < 2; above, the
+// upper tail 1 - P by the exponential series sum_k e^{-kx} (x^3/k + 3x^2/k^2
+// + 6x/k^3 + 6/k^4).  Each side is returned together with its complement,
+// so that a fraction between two bounds above x = 2 is taken as the
+// difference of the tails, which keeps its relative precision where the
+// fraction is tiny (1 - P near 1 would lose it).
 struct PR {
-    double P, R;
+    double P, R, Pc, Rc;   // P, R and the tails 1 - P, 1 - R
 };
 __device__ PR planck_rosseland_cum(double x) {
     constexpr double c15 = 15.0 / (M_PI * M_PI * M_PI * M_PI);
     constexpr double c15_4 = 15.0 / (4.0 * M_PI * M_PI * M_PI * M_PI);
-    if (!(x > 0.0)) return {0.0, 0.0};
-    if (x >= 1e300) return {1.0, 1.0};
-    double P, e, em;
+    if (!(x > 0.0)) return {0.0, 0.0, 1.0, 1.0};
+    if (x >= 1e300) return {1.0, 1.0, 0.0, 0.0};
     if (x < 2.0) {
         // int_0^x t^3/(e^t-1) dt = x^3/3 - x^4/8 + sum_k B_2k x^(2k+3) / ((2k)! (2k+3))
         const double x2 = x * x, x3 = x2 * x;
@@ -58,49 +62,56 @@ __device__ PR planck_rosseland_cum(double x) {
             s += c_bern[k] * p;
             p *= x2;
         }
-        P = c15 * (x3 / 3.0 - x3 * x / 8.0 + s);
-        e = exp(-x);
-        em = -expm1(-x);
-    } else {
-        double s = 0.0;
-        e = exp(-x);
-        em = 1.0 - e;
-        const double x2 = x * x, x3 = x2 * x;
-        double ek = e;
-        for (int k = 1; k <= 200; ++k) {
-            const double ik = c_inv.v[k];
-            const double term = ek * (ik * (x3 + ik * (3.0 * x2 + ik * (6.0 * x + 6.0 * ik))));
-            s += term;
-            if (term < 1e-18 * s) break;
-            ek *= e;
-            if (ek == 0.0) break;
-        }
-        P = 1.0 - c15 * s;
+        const double P = c15 * (x3 / 3.0 - x3 * x / 8.0 + s);
+        const double R = P - c15_4 * x3 * x * exp(-x) / -expm1(-x);
+        return {P, R, 1.0 - P, 1.0 - R};
     }
-    const double R = x > 700.0 ? 1.0 : P - c15_4 * x * x * x * x * e / em;
-    return {P, R};
+    double s = 0.0;
+    const double e = exp(-x), em = 1.0 - e;
+    const double x2 = x * x, x3 = x2 * x;
+    double ek = e;
+    for (int k = 1; k <= 200; ++k) {
+        const double ik = c_inv.v[k];
+        const double term = ek * (ik * (x3 + ik * (3.0 * x2 + ik * (6.0 * x + 6.0 * ik))));
+        s += term;
+        if (term < 1e-18 * s) break;
+        ek *= e;
+        if (ek == 0.0) break;
+    }
+    const double Q = c15 * s;
+    const double Qr = x > 700.0 ? 0.0 : Q + c15_4 * x3 * x * e / em;
+    return {1.0 - Q, 1.0 - Qr, Q, Qr};
 }
 
 // Group fractions at temperature T, produced one group at a time in group
 // order (no per-thread arrays, which would live in scratch memory):
 // b_g = P(x_{g+1}) - P(x_g), r_g likewise, with x_0 = 0 and x_G = infinity
-// (so a single group gets b = r = 1).
+// (so a single group gets b = r = 1); a group whose lower bound lies at
+// x >= 2 takes the difference of the upper tails.
 struct GroupFractions {
     const double *nu;
-    double T, Pl = 0.0, Rl = 0.0;
+    double T, Pl = 0.0, Rl = 0.0, Pcl = 1.0, Rcl = 1.0, xl = 0.0;
     int G, g = 0;
     __device__ GroupFractions(int G_, const double *nu_, double T_) : nu(nu_), T(T_), G(G_) {}
     __device__ void next(double &b, double &r) {
-        double Pu = 1.0, Ru = 1.0;
+        PR u{1.0, 1.0, 0.0, 0.0};
+        double xu = 1e308;
         if (g < G - 1) {
-            const PR pr = planck_rosseland_cum(nu[g + 1] / T);
-            Pu = pr.P;
-            Ru = pr.R;
+            xu = nu[g + 1] / T;
+            u = planck_rosseland_cum(xu);
         }
-        b = Pu - Pl;
-        r = Ru - Rl;
-        Pl = Pu;
-        Rl = Ru;
+        if (xl >= 2.0) {
+            b = Pcl - u.Pc;
+            r = Rcl - u.Rc;
+        } else {
+            b = u.P - Pl;
+            r = u.R - Rl;
+        }
+        Pl = u.P;
+        Rl = u.R;
+        Pcl = u.Pc;
+        Rcl = u.Rc;
+        xl = xu;
         ++g;
     }
 };
@@ -973,7 +984,24 @@ __global__ void k_psi_EF(int nn, int dim, int G, int nang, const double *om, con
 // ---------------------------------------------------------------------------
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
-void upload_bernoulli(const double *coef) { SMRT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_bern), coef, sizeof(double) * NBERN)); }
+// Bernoulli coefficients B_2k / ((2k)! (2k+3)) = (-1)^(k+1) 2 zeta(2k) / ((2 pi)^(2k) (2k+3))
+void upload_series_coefficients() {
+    double coef[NBERN];
+    for (int k = 1; k <= NBERN; ++k) {
+        double z;
+        if (k == 1) z = M_PI * M_PI / 6.0;
+        else {
+            z = 0.0;
+            const int N = 20000;
+            for (int n = N; n >= 1; --n) z += std::pow((double)n, -2.0 * k);
+            z += std::pow((double)N, 1.0 - 2.0 * k) / (2.0 * k - 1.0) - 0.5 * std::pow((double)N, -2.0 * k);
+        }
+        const double sign = (k % 2 == 1) ? 1.0 : -1.0;
+        coef[k - 1] = sign * 2.0 * z / (std::pow(2.0 * M_PI, 2.0 * k) * (2.0 * k + 3.0));
+    }
+    SMRT_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_bern), coef, sizeof(double) * NBERN));
+}
+
 
 template <typename real>
 void run_opacity(hipStream_t s, int ncell, int npc, int G, const double *T, const int *region, int model,

@@ -166,7 +166,12 @@ def test_adjoint_rejects_unknown_objective(smrt_mod):
 def test_adjoint_full_size_finite_differences(smrt_mod, objective):
     """The adjoint configuration at full size (128x128, S8, 8 groups, 64 regions
     of sigma0 and c_v, 10 steps of dt = 1e-3, FP64): the two largest gradient
-    components of each kind against central finite differences (h = 1e-4)."""
+    components of each kind against central finite differences (h = 1e-4).
+    A component below what the difference can resolve (1e-7 |J|: J's
+    rounding over 2h) must have a difference below that too; the outflow's
+    sigma0-gradients are such (the medium is cold, so every group but the
+    highest has a clipped opacity, and the highest group's emission carries
+    Planck fractions near e^-300)."""
     p = W.adjoint_2d()
     print(f"adjoint 128x128 S8 G8, 10 steps, objective {objective}", flush=True)
     tight = dict(eps_outer=1e-10, eps_inner=1e-11, cg_rtol=1e-13, elim_rtol=1e-15, max_outer=200, max_inner=60,
@@ -182,6 +187,7 @@ def test_adjoint_full_size_finite_differences(smrt_mod, objective):
         return ctx.adjoint(p.n_steps, objective=objective)[0]
 
     h = 1e-4
+    floor = 1e-7 * abs(J)
     for g, which in ((gs, 0), (gc, 1)):
         for r in np.argsort(-np.abs(g))[:2]:
             e = np.zeros(p.n_regions)
@@ -190,6 +196,9 @@ def test_adjoint_full_size_finite_differences(smrt_mod, objective):
                 fd = (J_at(p.sigma0 * np.exp(e), p.cv) - J_at(p.sigma0 * np.exp(-e), p.cv)) / (2 * h)
             else:
                 fd = (J_at(p.sigma0, p.cv * np.exp(e)) - J_at(p.sigma0, p.cv * np.exp(-e))) / (2 * h)
+            print(f"kind {which} region {r}: adjoint {g[r]:.6e} difference {fd:.6e} (J {J:.3e})", flush=True)
+            if abs(g[r]) < floor and abs(fd) < floor:
+                continue
             assert abs(g[r] - fd) <= 1e-4 * abs(fd), (which, r, g[r], fd)
     ctx.close()
 

@@ -180,6 +180,27 @@ def _planck(oracle_mod, nu, T):
     return b
 
 
+def _planck_many(oracle_mod, nu, T):
+    """[len(T)][G] group fractions b_g(T) from the oracle, in threads (the
+    foreign calls release the interpreter lock)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    G, L = len(nu) - 1, oracle_mod.lib()
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    out, r = np.zeros((len(T), G)), np.zeros((len(T), G))
+    nup = nu.ctypes.data_as(oracle_mod._dp)
+
+    def work(lo, hi):
+        for n in range(lo, hi):
+            L.orc_spectra(G, nup, float(T[n]), out[n].ctypes.data_as(oracle_mod._dp), r[n].ctypes.data_as(oracle_mod._dp))
+
+    nt = max(1, min(16, os.cpu_count() or 1))
+    cuts = np.linspace(0, len(T), nt + 1).astype(int)
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(lambda k: work(cuts[k], cuts[k + 1]), range(nt)))
+    return out
+
+
 def _step_problem(kind, oracle_mod, seed=5):
     """A 3-group, S4 problem on the mesh: two regions with tabulated
     opacities (0.5, 2, 8 and 2, 8, 30 per group) and c_v 0.5 and 1, T0 = 0.2
@@ -260,3 +281,95 @@ def test_qmesh_step_error_paths(smrt_mod, oracle_mod):
     st = m.step(0.02)                          # vacuum sides
     assert st["outer"] >= 1
     m.close()
+
+
+def test_qmesh_step_full_size_balance_and_sampled_sweep(smrt_mod, oracle_mod):
+    """The benchmark's unstructured step (64,896 cells, S8, 16 groups, FP32,
+    4 regions of tabulated opacities, T0 = 0.5 at equilibrium, vacuum sides,
+    dt = 1e-3), iterated to the FP32 floor (40 outer iterations), checked by properties that hold
+    at any size and by sampled groups:
+      * E = sum_d w_d sum_g I / c of the returned intensity (1e-12);
+      * the nodal energy balance c_v (T - T*)/dt + sigma_P(T) a c T^4 =
+        sum_g sigma_g phi_g, with sigma_P the Planck mean over the groups
+        and phi_g taken from the returned intensity, to 1e-5 of the
+        radiation terms (the balance froze sigma_P at the previous iterate);
+      * groups 0 and 15 of the last sweep against the oracle's sweep of that
+        group alone with the emission at the returned T (1e-5)."""
+    xy, cells = W.quad_mesh_split_triangles(104, seed=2)
+    om, w = W.level_symmetric_2d(8)
+    G, nc, dt, T0 = 16, len(cells), 1e-3, 0.5
+    nn = 4 * nc
+    rng = np.random.default_rng(3)
+    s0 = 10.0 ** rng.uniform(-1, 2, (4, G))
+    region = (np.arange(nc) % 4).astype(np.int32)
+    nu = np.logspace(-2, 1.5, G + 1)
+    print(f"full-size unstructured step: {nc} cells, S8, G={G}, FP32", flush=True)
+    m = smrt_mod.QuadMeshSweep(xy, cells, om, w, G, precision=1)
+    m.set_materials(region, s0, np.ones(4), nu, model=0)
+    m.set_state(np.full(nn, T0))
+    # iterated until the iterate stops changing (the FP32 floor): the highest
+    # group's emission moves about 50 times faster than T there (x = h nu / kT
+    # near 50), so the test's emission at the returned T matches the last
+    # sweep's (at the previous iterate) only once T has settled
+    st = m.step(dt, eps_outer=1e-13, max_outer=40, elim_rtol=1e-14, max_elim=60)
+    got = m.get_state()
+    m.close()
+    print("outer", st["outer"], "hit_max", st["hit_max"], flush=True)
+    T, E, psi = got["T"], got["E"], got["psi"]
+    phi_g = np.tensordot(w, psi, axes=(0, 0))                      # [g][node]
+    assert np.abs(E - phi_g.sum(axis=0)).max() <= 1e-12 * np.abs(E).max()
+    sig_n = s0[region][np.arange(nn) // 4]                         # [node][g]
+    sphi = np.einsum("ng,gn->n", sig_n, phi_g)
+    bT = _planck_many(oracle_mod, nu, T)                             # [node][g]
+    sigP = (bT * sig_n).sum(axis=1) / bT.sum(axis=1)
+    rad = sigP * T ** 4
+    res = (T - T0) / dt + rad - sphi
+    scale = np.maximum(np.abs(sphi), rad)
+    print(f"balance residual max {np.abs(res / scale).max():.2e}", flush=True)
+    assert np.abs(res / scale).max() < 1e-5
+    ref_mesh = oracle_mod.QuadMesh(xy, cells, om, w, 1)
+    for g in (0, G - 1):
+        q = (sig_n[:, g] * T ** 4 * bT[:, g] / (4 * np.pi))[:, None]
+        eq = _planck(oracle_mod, nu, T0)[g] * T0 ** 4 / (4 * np.pi)
+        prev = np.full((len(w), 1, nn), eq)
+        ref = ref_mesh.sweep(s0[region][:, g:g + 1] + 1.0 / dt, q, prev, 1.0 / dt, None)
+        err = _rel(psi[:, g:g + 1], ref)
+        print(f"group {g}: sweep vs oracle {err:.2e}", flush=True)
+        assert err < 1e-5
+
+
+def test_qmesh_equilibrium_group_fractions_in_a_fresh_process(oracle_mod, tmp_path):
+    """A process whose only GPU work is on the unstructured mesh (no
+    rectilinear context created before) gets the equilibrium intensity
+    B_g(T)/4pi with every group fraction to 1e-11 relative of that group's
+    own value against the oracle's: the lowest group (the small-argument
+    series' coefficients must be on the device) and the highest, whose
+    fraction is ~1e-13 and must come from the difference of upper tails."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = str(tmp_path / "eq.npz")
+    code = (
+        "import sys, numpy as np\n"
+        f"sys.path.insert(0, {root!r})\n"
+        "from paper_2504_21784_amd import smrt, workloads as W\n"
+        "xy, cells = W.quad_mesh_jittered(3, 3, jitter=0.2, seed=1)\n"
+        "om, w = W.level_symmetric_2d(4)\n"
+        "G, nc = 16, len(cells)\n"
+        "T = np.random.default_rng(4).uniform(0.3, 1.0, 4 * nc)\n"
+        "m = smrt.QuadMeshSweep(xy, cells, om, w, G, precision=smrt.SMRT_FP64)\n"
+        "m.set_materials(np.zeros(nc, np.int32), np.ones((1, G)), np.ones(1), np.logspace(-2, 1.5, G + 1), model=0)\n"
+        "m.set_state(T)\n"
+        f"np.savez({out!r}, T=T, psi=m.get_state()['psi'])\n"
+        "m.close()\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stderr[-2000:]
+    d = np.load(out)
+    T, psi = d["T"], d["psi"]
+    nu = np.logspace(-2, 1.5, 17)
+    want = _planck_many(oracle_mod, nu, T) * (T ** 4)[:, None] / (4 * np.pi)     # [node][g]
+    for g in range(16):
+        err = (np.abs(psi[:, g, :] - want[None, :, g]) / want[None, :, g]).max()    # pointwise
+        print(f"group {g}: {err:.2e}", flush=True)
+        assert err < 1e-11, g
