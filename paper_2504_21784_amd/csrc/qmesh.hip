@@ -27,6 +27,7 @@
 // elimination with partial pivoting.  Angular flux layout [d][g][node],
 // node = 4 cell + local vertex (counter-clockwise), as the ABI's.
 #include <cmath>
+#include <type_traits>
 #include <cstring>
 #include <memory>
 #include <numeric>
@@ -52,7 +53,7 @@ struct QArgs {
     const int *upw;               // [cell][edge][2]: upwind node (>= 0) or -(1 + boundary node)
     const double *om;             // [nang][3]
     const void *sig_t;            // [cell][G], sweep precision
-    const void *q;                // [node][G], sweep precision
+    const void *q;                // [g][node], sweep precision
     const void *psi_prev;         // [d][g][node], sweep precision
     const void *inflow;           // [d][g][NB], sweep precision
     const double *par;            // [0] inv_c_dt, [1] 1 if psi_prev holds I*, else 0 (set per sweep)
@@ -85,10 +86,22 @@ __device__ __forceinline__ void qsolve_unit(const QArgs &A, int d, int g, int c)
     real M[4][4], b[4];
     const real icdt = (real)A.par[0];
     const bool has_prev = A.par[1] != 0.0;
+    // the cell's 4 nodes are contiguous and 4-value aligned in every [d][g][node] slab
+    using r4 = typename std::conditional<sizeof(real) == 4, float4, double4>::type;
+    r4 pv{};
+    if (has_prev) pv = *reinterpret_cast<const r4 *>(psi_prev + slab + 4 * c);
+    // the cell's 8 upwind entries, loaded with its flags rather than after them
+    // (one dependent round trip fewer before the upwind values)
+    const int4 ua = *reinterpret_cast<const int4 *>(A.upw + 8 * (int64_t)c);
+    const int4 ub = *reinterpret_cast<const int4 *>(A.upw + 8 * (int64_t)c + 4);
+    const int upw8[8] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w};
+    const real pp[4] = {pv.x, pv.y, pv.z, pv.w};
+    const r4 qv = *reinterpret_cast<const r4 *>(q + (int64_t)g * nn + 4 * c);
+    const real qa[4] = {qv.x, qv.y, qv.z, qv.w};
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
-        real ql = q[(int64_t)(4 * c + l) * A.G + g];
-        if (has_prev) ql += icdt * psi_prev[slab + 4 * c + l];
+        real ql = qa[l];
+        if (has_prev) ql += icdt * pp[l];
         b[l] = (real)K.w[l] * ql;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -109,7 +122,7 @@ __device__ __forceinline__ void qsolve_unit(const QArgs &A, int d, int g, int c)
             if ((fl >> (4 + e)) & 1) {
                 M[l][l] += on;
             } else if ((fl >> e) & 1) {
-                const int u = A.upw[(4 * c + e) * 2 + j];
+                const int u = upw8[2 * e + j];
                 const real up = u >= 0 ? psi[slab + u] : inflow[((int64_t)d * A.G + g) * A.NB + (-u - 1)];
                 b[l] -= on * up;
             }
@@ -145,8 +158,9 @@ __device__ __forceinline__ void qsolve_unit(const QArgs &A, int d, int g, int c)
         for (int cc = k + 1; cc < 4; ++cc) s -= M[k][cc] * x[cc];
         x[k] = s / M[k][k];
     }
-#pragma unroll
-    for (int l = 0; l < 4; ++l) psi[slab + 4 * c + l] = x[l];
+    r4 xv;
+    xv.x = x[0]; xv.y = x[1]; xv.z = x[2]; xv.w = x[3];
+    *reinterpret_cast<r4 *>(psi + slab + 4 * c) = xv;
 }
 
 
@@ -244,13 +258,14 @@ __global__ void __launch_bounds__(256) k_qmoments(int nang, int G, int nn, const
 // The unaccelerated time step on the mesh (Algorithm 1 without the
 // low-order solve): small kernels around the sweep and the moments.
 // ---------------------------------------------------------------------------
-// emission q[g][node] (the source kernel's layout) to the sweep's q[node][G]
+// the ABI's emission q[node][G] to the sweep's q[g][node] (a cell's 4 nodes
+// contiguous, one vector load per unit), in the sweep precision
 template <typename real>
-__global__ void k_qtranspose(int nn, int G, const double *qn, real *q) {
+__global__ void k_qtranspose(int nn, int G, const double *q_ng, real *q) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= (int64_t)nn * G) return;
-    const int64_t n = i / G, g = i - n * G;
-    q[i] = (real)qn[g * nn + n];
+    const int64_t g = i / nn, n = i - g * nn;
+    q[i] = (real)q_ng[n * G + g];
 }
 // sigma_t = sigma + 1/(c dt) per (cell, group), in the sweep precision
 template <typename real>
@@ -584,7 +599,16 @@ extern "C" smrt_status smrt_qmesh_sweep(smrt_qmesh *m, const double *sig_t, cons
         hipStream_t s = m->stream;
         m->swept = false;
         SMRT_HIP(hipMemcpyAsync(m->sig_t.p, sig_t, sizeof(double) * m->nc * m->G, hipMemcpyHostToDevice, s));
-        SMRT_HIP(hipMemcpyAsync(m->q.p, q_iso, sizeof(double) * nn * m->G, hipMemcpyHostToDevice, s));
+        // q_iso is staged in the output buffer (free until the sweep's copy-out) and
+        // transposed to the sweep's [g][node] layout below
+        SMRT_HIP(hipMemcpyAsync(m->out.p, q_iso, sizeof(double) * nn * m->G, hipMemcpyHostToDevice, s));
+        {
+            const dim3 gq((unsigned)((nn * m->G + 255) / 256));
+            if (m->fp32) hipLaunchKernelGGL(k_qtranspose<float>, gq, dim3(256), 0, s, (int)nn, m->G,
+                                            (const double *)m->out.p, m->q32.p);
+            else hipLaunchKernelGGL(k_qtranspose<double>, gq, dim3(256), 0, s, (int)nn, m->G, (const double *)m->out.p,
+                                    m->q.p);
+        }
         if (psi_prev) SMRT_HIP(hipMemcpyAsync(m->psi_prev.p, psi_prev, sizeof(double) * npsi, hipMemcpyHostToDevice, s));
         if (inflow) SMRT_HIP(hipMemcpyAsync(m->inflow.p, inflow, sizeof(double) * m->nang * m->G * m->NB,
                                             hipMemcpyHostToDevice, s));
@@ -594,7 +618,6 @@ extern "C" smrt_status smrt_qmesh_sweep(smrt_qmesh *m, const double *sig_t, cons
                 if (n > 0) hipLaunchKernelGGL(k_qto_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in, out);
             };
             to32((int64_t)m->nc * m->G, m->sig_t.p, m->sig_t32.p);
-            to32(nn * m->G, m->q.p, m->q32.p);
             if (psi_prev) to32(npsi, m->psi_prev.p, m->psi_prev32.p);
             to32((int64_t)m->nang * m->G * m->NB, m->inflow.p, m->inflow32.p);
         }
@@ -818,12 +841,12 @@ extern "C" smrt_status smrt_qmesh_step(smrt_qmesh *m, double dt, const double *i
             run_source<double>(s, nn, 4, G, m->Tl.p, m->nu.p, m->a, m->c, m->sig_step.p, nullptr, m->qn.p, m->sigP.p,
                                m->sigF.p);
             if (m->fp32) {
-                hipLaunchKernelGGL(k_qtranspose<float>, gq, dim3(256), 0, s, nn, G, (const double *)m->qn.p, m->q32.p);
+                hipLaunchKernelGGL(k_qto_f32, gq, dim3(256), 0, s, (int64_t)nn * G, (const double *)m->qn.p, m->q32.p);
                 m->launch_sweep(s, m->psi_state.p, m->psi.p);
                 hipLaunchKernelGGL(k_qmoments<float>, gm, dim3(256), 0, s, nang, G, nn, m->om.p, m->wq.p,
                                    (const double *)m->sig_step.p, (const float *)m->psi.p, m->mom.p);
             } else {
-                hipLaunchKernelGGL(k_qtranspose<double>, gq, dim3(256), 0, s, nn, G, (const double *)m->qn.p, m->q.p);
+                SMRT_HIP(hipMemcpyAsync(m->q.p, m->qn.p, sizeof(double) * nn * G, hipMemcpyDeviceToDevice, s));
                 m->launch_sweep(s, m->psi_state.p, m->psi.p);
                 hipLaunchKernelGGL(k_qmoments<double>, gm, dim3(256), 0, s, nang, G, nn, m->om.p, m->wq.p,
                                    (const double *)m->sig_step.p, (const double *)m->psi.p, m->mom.p);
