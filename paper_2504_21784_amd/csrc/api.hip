@@ -2089,7 +2089,6 @@ extern "C" smrt_status smrt_batch_run(smrt_batch *b, int n_steps, const double *
         if (!R.flags.p) R.flags.alloc(2);
         if (!R.h_flags) SMRT_HIP(hipHostMalloc((void **)&R.h_flags, 2 * sizeof(int), hipHostMallocDefault));
         if (!R.h_ctl) SMRT_HIP(hipHostMalloc((void **)&R.h_ctl, LO_BATCH_MAX * sizeof(RunCtl), hipHostMallocDefault));
-        if (!R.grid) R.grid = lo_batch_grid();
         while ((int)R.ev.size() < n_steps + 1) {
             hipEvent_t e;
             SMRT_HIP(hipEventCreate(&e));
@@ -2104,6 +2103,7 @@ extern "C" smrt_status smrt_batch_run(smrt_batch *b, int n_steps, const double *
         R.lb.abort = R.flags.p;
         R.h_lo.resize(n);
         for (size_t i = 0; i < n; ++i) R.lb.vb_n[i + 1] = R.lb.vb_n[i] + (b->P[i]->lo.nn + 255) / 256;
+        if (!R.grid) R.grid = lo_batch_grid(R.lb.vb_n[n]);
         std::vector<const int *> gates(n);
         for (size_t i = 0; i < n; ++i) gates[i] = &R.ctl.p[i].active;
         const std::vector<int> all = all_problems(b);

@@ -160,7 +160,7 @@ struct LoBatch {
 // workgroups meet at grid barriers; the same arithmetic, block by block, as
 // LoSolver::solve.  grid: workgroups that are all resident at once.
 void run_lo_batch(hipStream_t s, const LoBatch &b, int grid);
-int lo_batch_grid();
+int lo_batch_grid(int total_blocks);   // persistent grid for a batch of that many node blocks
 
 struct LoSolver {
     int dim = 0, nn = 0;
