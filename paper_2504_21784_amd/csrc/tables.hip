@@ -274,13 +274,21 @@ __global__ void k_opacity_tab2d(int nx, int ny, int G, const double *__restrict_
     }
     const double Tc = cell_mean_T(4, T, cell);
     const int r = region[cell];
+    // a cell's G opacities are contiguous in sig: with G even they go out in
+    // 16-byte pairs (half the store instructions of the scattered cells)
+    const bool pairs = (G & 1) == 0;
+    double s_even = 0.0;
     for (int g = 0; g < G; ++g) {
         const double s = group_opacity(model, G, r, g, sigma0, nu, Tc, clip_lo, clip_hi);
         r2 v;
         v.x = (real)(s + icdt);
         v.y = (real)s;
         out[((int64_t)q * G + g) * cs + slot] = v;
-        if (q == 0) sig[(int64_t)cell * G + g] = s;
+        if (q == 0) {
+            if (!pairs) sig[(int64_t)cell * G + g] = s;
+            else if (g & 1) *reinterpret_cast<double2 *>(sig + (int64_t)cell * G + g - 1) = make_double2(s_even, s);
+            else s_even = s;
+        }
     }
 }
 
