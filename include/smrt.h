@@ -500,7 +500,8 @@ smrt_status smrt_qmesh_moments(smrt_qmesh *mesh, const double *sig, double *mom_
  * [clip_lo, clip_hi] (nubar_g the geometric mean of the group bounds), T the
  * cell mean of its 4 nodal values, taken once per step at the start-of-step
  * temperature; c_v[r] > 0; nu_edges[G+1] increasing; a, c > 0.  Copied.
- * Errors: SMRT_E_INVALID_ARG. */
+ * Setting the materials again discards the state (set it again before a
+ * step).  Errors: SMRT_E_INVALID_ARG. */
 smrt_status smrt_qmesh_set_materials(smrt_qmesh *mesh, const int32_t *region, int n_regions, int model,
                                      const double *sigma0, double clip_lo, double clip_hi, const double *cv,
                                      const double *nu_edges, double a, double c);
