@@ -827,6 +827,7 @@ __global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkR
                                                           const double *dirs, const real *part, double *mom,
                                                           double *sigq, const int *gate) {
     using r2 = typename std::conditional<sizeof(real) == 4, float2, double2>::type;
+    using e2 = __attribute__((ext_vector_type(2))) real;
     if (gate && !*gate) return;   // uniform over the grid
     const int nb = (ny + BAND_ROWS - 1) / BAND_ROWS, NT = nx + BAND_ROWS - 1;
     const int ntb = (NT + 3) / 4;
@@ -852,7 +853,10 @@ __global__ void __launch_bounds__(256) k_moments_quadrant(int nx, int ny, ChunkR
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int qc = qc0 + u < cr.start[q + 1] ? qc0 + u : qc0;
-            v[u] = base[qc * stride];
+            // each partial is read once: a streaming load (not kept in the caches)
+            const e2 t = __builtin_nontemporal_load(reinterpret_cast<const e2 *>(base + qc * stride));
+            v[u].x = t[0];
+            v[u].y = t[1];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
